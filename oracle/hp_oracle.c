@@ -1,0 +1,292 @@
+/*
+ * Plain CPU oracle for sparse-matrix permutation, extraction and assignment.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * loads this file.  Only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg use it.  It shares no code, header or table with the GPU
+ * library.
+ *
+ * Every routine writes out the definition given in the paper's problem
+ * formulation (Section 2, "Problem Formulation"), in the slowest obvious way:
+ *
+ *   permute   (Sec. 2.1):  A'[i,j] = A[pvec[i], qvec[j]]   for all i < m, j < n
+ *   extract   (Sec. 2.2):  B[i,j]  = A[pvec[i], qvec[j]]   for all (i,j) in pvec x qvec
+ *   assign    (Sec. 2.3, and the Add step of Sec. 4.7):
+ *                          B'[pvec[i], qvec[j]] = B[i,j]   for stored entries of B
+ *                          A_new = A (+) B'   with a user-chosen addition
+ *
+ * Conventions (each is a reading of the paper; the design notes list them):
+ *   - 0-based indices (the paper counts from 1);
+ *   - CSR with columns strictly ascending inside each row;
+ *   - values are moved as raw bytes (4 or 8 per value), never re-rounded;
+ *   - PLUS adds in the value's own type with round-to-nearest-even.  For
+ *     4-byte values the sum is formed in double and rounded once to float:
+ *     double has 53 >= 2*24+2 significand bits, so this equals a single
+ *     correctly rounded float addition (double rounding is innocuous for +).
+ *
+ * Output rows may be restricted to a list `rows` (the sampled-row mode used
+ * at full benchmark sizes); rows == NULL means every output row.  Outputs use
+ * the two-call protocol: with cap smaller than the needed count nothing is
+ * written beyond out_ptr and *need receives the count.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "hp_oracle.h"
+
+/* ---- small helpers --------------------------------------------------- */
+
+/* Position of column c in row r of a canonical CSR, or -1. */
+static int64_t find_in_row(const int64_t *rowptr, const int32_t *col, int64_t r, int32_t c)
+{
+    int64_t lo = rowptr[r], hi = rowptr[r + 1];
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (col[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < rowptr[r + 1] && col[lo] == c) return lo;
+    return -1;
+}
+
+static void copy_val(void *dst, int64_t di, const void *src, int64_t si, int vsize)
+{
+    memcpy((char *)dst + di * vsize, (const char *)src + si * vsize, (size_t)vsize);
+}
+
+int orc_check_csr(int64_t m, int64_t n, const int64_t *rowptr, const int32_t *col)
+{
+    if (m < 0 || n < 0 || !rowptr) return ORC_INVALID_ARG;
+    if (rowptr[0] != 0) return ORC_NOT_CANONICAL;
+    for (int64_t r = 0; r < m; r++) {
+        if (rowptr[r + 1] < rowptr[r]) return ORC_NOT_CANONICAL;
+        for (int64_t k = rowptr[r]; k < rowptr[r + 1]; k++) {
+            if (col[k] < 0 || col[k] >= n) return ORC_INDEX_RANGE;
+            if (k > rowptr[r] && col[k] <= col[k - 1]) return ORC_NOT_CANONICAL;
+        }
+    }
+    return ORC_OK;
+}
+
+/* v is a permutation of [0, len): every value in range, none repeated. */
+static int check_permutation(const int32_t *v, int64_t len)
+{
+    unsigned char *seen = (unsigned char *)calloc((size_t)(len > 0 ? len : 1), 1);
+    if (!seen) return ORC_INVALID_ARG;
+    int st = ORC_OK;
+    for (int64_t i = 0; i < len; i++) {
+        if (v[i] < 0 || v[i] >= len) { st = ORC_INDEX_RANGE; break; }
+        if (seen[v[i]]) { st = ORC_NOT_PERMUTATION; break; }
+        seen[v[i]] = 1;
+    }
+    free(seen);
+    return st;
+}
+
+static int check_range(const int32_t *v, int64_t len, int64_t hi)
+{
+    for (int64_t i = 0; i < len; i++)
+        if (v[i] < 0 || v[i] >= hi) return ORC_INDEX_RANGE;
+    return ORC_OK;
+}
+
+/* Values in range and pairwise distinct (assignment vectors, Sec. 2.3). */
+static int check_distinct(const int32_t *v, int64_t len, int64_t hi)
+{
+    int st = check_range(v, len, hi);
+    if (st != ORC_OK) return st;
+    unsigned char *seen = (unsigned char *)calloc((size_t)(hi > 0 ? hi : 1), 1);
+    if (!seen) return ORC_INVALID_ARG;
+    for (int64_t i = 0; i < len; i++) {
+        if (seen[v[i]]) { st = ORC_DUPLICATE_INDEX; break; }
+        seen[v[i]] = 1;
+    }
+    free(seen);
+    return st;
+}
+
+/* ---- permutation, Sec. 2.1 -------------------------------------------- */
+
+int orc_permute(int64_t m, int64_t n, const int64_t *rowptr, const int32_t *col,
+                const void *val, int vsize, const int32_t *p, const int32_t *q,
+                const int64_t *rows, int64_t ns,
+                int64_t *out_ptr, int32_t *out_col, void *out_val, int64_t cap, int64_t *need)
+{
+    if (vsize != 4 && vsize != 8) return ORC_INVALID_ARG;
+    if (!q) {                       /* symmetric form P A P^T */
+        if (m != n) return ORC_SHAPE;
+        q = p;
+    }
+    int st = check_permutation(p, m);
+    if (st != ORC_OK) return st;
+    st = check_permutation(q, n);
+    if (st != ORC_OK) return st;
+    if (!rows) ns = m;
+    int64_t cnt = 0;
+    out_ptr[0] = 0;
+    for (int64_t s = 0; s < ns; s++) {
+        int64_t i = rows ? rows[s] : s;
+        if (i < 0 || i >= m) return ORC_INDEX_RANGE;
+        int64_t src = p[i];
+        /* A'[i, j] = A[p[i], q[j]] for every j, in increasing j. */
+        for (int64_t j = 0; j < n; j++) {
+            int64_t k = find_in_row(rowptr, col, src, q[j]);
+            if (k < 0) continue;
+            if (cnt < cap) {
+                out_col[cnt] = (int32_t)j;
+                copy_val(out_val, cnt, val, k, vsize);
+            }
+            cnt++;
+        }
+        out_ptr[s + 1] = cnt;
+    }
+    *need = cnt;
+    return ORC_OK;
+}
+
+/* ---- extraction, Sec. 2.2 --------------------------------------------- */
+
+int orc_spref(int64_t m, int64_t n, const int64_t *rowptr, const int32_t *col,
+              const void *val, int vsize, const int32_t *I, int64_t nI,
+              const int32_t *J, int64_t nJ, const int64_t *rows, int64_t ns,
+              int64_t *out_ptr, int32_t *out_col, void *out_val, int64_t cap, int64_t *need)
+{
+    if (vsize != 4 && vsize != 8) return ORC_INVALID_ARG;
+    if (nI < 0 || nJ < 0) return ORC_INVALID_ARG;
+    int st = check_range(I, nI, m);
+    if (st != ORC_OK) return st;
+    st = check_range(J, nJ, n);
+    if (st != ORC_OK) return st;
+    if (!rows) ns = nI;
+    int64_t cnt = 0;
+    out_ptr[0] = 0;
+    for (int64_t s = 0; s < ns; s++) {
+        int64_t i = rows ? rows[s] : s;
+        if (i < 0 || i >= nI) return ORC_INDEX_RANGE;
+        /* C[i, j] = A[I[i], J[j]] over the whole Cartesian product row i x J. */
+        for (int64_t j = 0; j < nJ; j++) {
+            int64_t k = find_in_row(rowptr, col, I[i], J[j]);
+            if (k < 0) continue;
+            if (cnt < cap) {
+                out_col[cnt] = (int32_t)j;
+                copy_val(out_val, cnt, val, k, vsize);
+            }
+            cnt++;
+        }
+        out_ptr[s + 1] = cnt;
+    }
+    *need = cnt;
+    return ORC_OK;
+}
+
+/* ---- assignment, Sec. 2.3 / Sec. 4.7 ---------------------------------- */
+
+typedef struct { int32_t c; int64_t k; } bent_t;   /* B' entry: column, index into B */
+
+static int cmp_bent(const void *a, const void *b)
+{
+    const bent_t *x = (const bent_t *)a, *y = (const bent_t *)b;
+    return (x->c > y->c) - (x->c < y->c);
+}
+
+static void add_vals(void *dst, int64_t di, const void *a, int64_t ai,
+                     const void *b, int64_t bi, int vsize)
+{
+    if (vsize == 8) {
+        double x, y, z;
+        memcpy(&x, (const char *)a + ai * 8, 8);
+        memcpy(&y, (const char *)b + bi * 8, 8);
+        z = x + y;
+        memcpy((char *)dst + di * 8, &z, 8);
+    } else {
+        float x, y, z;
+        memcpy(&x, (const char *)a + ai * 4, 4);
+        memcpy(&y, (const char *)b + bi * 4, 4);
+        z = (float)((double)x + (double)y);
+        memcpy((char *)dst + di * 4, &z, 4);
+    }
+}
+
+int orc_spasgn(int64_t m, int64_t n, const int64_t *rowptr, const int32_t *col, const void *val,
+               int vsize, int64_t bm, int64_t bn, const int64_t *browptr, const int32_t *bcol,
+               const void *bval, const int32_t *I, int64_t nI, const int32_t *J, int64_t nJ,
+               int op, const int64_t *rows, int64_t ns,
+               int64_t *out_ptr, int32_t *out_col, void *out_val, int64_t cap, int64_t *need)
+{
+    if (vsize != 4 && vsize != 8) return ORC_INVALID_ARG;
+    if (op != ORC_OP_SECOND && op != ORC_OP_PLUS && op != ORC_OP_REPLACE) return ORC_INVALID_ARG;
+    if (bm != nI || bn != nJ) return ORC_SHAPE;
+    int st = check_distinct(I, nI, m);
+    if (st != ORC_OK) return st;
+    st = check_distinct(J, nJ, n);
+    if (st != ORC_OK) return st;
+    /* Position of each row / column of A inside pvec / qvec (or -1). */
+    int64_t *rowpos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    int64_t *colpos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t maxb = 0;
+    for (int64_t i = 0; i < bm; i++)
+        if (browptr[i + 1] - browptr[i] > maxb) maxb = browptr[i + 1] - browptr[i];
+    bent_t *bp = (bent_t *)malloc(sizeof(bent_t) * (size_t)(maxb > 0 ? maxb : 1));
+    if (!rowpos || !colpos || !bp) { free(rowpos); free(colpos); free(bp); return ORC_INVALID_ARG; }
+    for (int64_t r = 0; r < m; r++) rowpos[r] = -1;
+    for (int64_t c = 0; c < n; c++) colpos[c] = -1;
+    for (int64_t i = 0; i < nI; i++) rowpos[I[i]] = i;
+    for (int64_t j = 0; j < nJ; j++) colpos[J[j]] = j;
+
+    if (!rows) ns = m;
+    int64_t cnt = 0;
+    out_ptr[0] = 0;
+    for (int64_t s = 0; s < ns; s++) {
+        int64_t r = rows ? rows[s] : s;
+        if (r < 0 || r >= m) { st = ORC_INDEX_RANGE; break; }
+        int64_t i = rowpos[r];
+        int64_t nb = 0;
+        if (i >= 0) {
+            /* Row r of B' = row i of B with each column cb moved to J[cb]. */
+            for (int64_t k = browptr[i]; k < browptr[i + 1]; k++) {
+                bp[nb].c = J[bcol[k]];
+                bp[nb].k = k;
+                nb++;
+            }
+            qsort(bp, (size_t)nb, sizeof(bent_t), cmp_bent);
+        }
+        /* Entry-wise union of row r of A and row r of B'. */
+        int64_t ka = rowptr[r], ea = rowptr[r + 1], kb = 0;
+        while (ka < ea || kb < nb) {
+            if (ka < ea && i >= 0 && op == ORC_OP_REPLACE && colpos[col[ka]] >= 0) {
+                ka++;               /* block replace: A entries inside I x J are removed */
+                continue;
+            }
+            int take_a = 0, take_b = 0;
+            if (ka < ea && kb < nb) {
+                if (col[ka] < bp[kb].c) take_a = 1;
+                else if (col[ka] > bp[kb].c) take_b = 1;
+                else take_a = take_b = 1;
+            } else if (ka < ea) take_a = 1;
+            else take_b = 1;
+            if (cnt < cap) {
+                if (take_a && take_b) {
+                    out_col[cnt] = col[ka];
+                    if (op == ORC_OP_PLUS) add_vals(out_val, cnt, val, ka, bval, bp[kb].k, vsize);
+                    else copy_val(out_val, cnt, bval, bp[kb].k, vsize);   /* select-second */
+                } else if (take_a) {
+                    out_col[cnt] = col[ka];
+                    copy_val(out_val, cnt, val, ka, vsize);
+                } else {
+                    out_col[cnt] = bp[kb].c;
+                    copy_val(out_val, cnt, bval, bp[kb].k, vsize);
+                }
+            }
+            cnt++;
+            if (take_a) ka++;
+            if (take_b) kb++;
+        }
+        out_ptr[s + 1] = cnt;
+    }
+    free(rowpos);
+    free(colpos);
+    free(bp);
+    *need = cnt;
+    return st;
+}

@@ -1,0 +1,52 @@
+"""Runs the oracle pins against an oracle library given on the command line.
+
+Exit status 0: every pin held (a planted mistake survived); 1: some pin failed.
+Used by test_oracle_mutants.py, always in a child process."""
+import os
+import sys
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import oracle  # noqa: E402
+from tests import test_oracle_pins as T  # noqa: E402
+from tests._util import assert_csr_equal, rand_csr  # noqa: E402
+
+
+def battery(lib):
+    rng = np.random.default_rng(99)
+    for (m, n) in [(7, 7), (12, 9), (16, 16)]:
+        for vd in (np.float64, np.float32):
+            A = rand_csr(rng, m, n, 0.35, vd)
+            p, q = rng.permutation(m), rng.permutation(n)
+            assert_csr_equal(oracle.permute(A, p, q, lib=lib), T._brute_permute(A, p, q), "perm")
+            I = rng.integers(0, m, 2 * m)
+            J = rng.integers(0, n, 2 * n)
+            assert_csr_equal(oracle.spref(A, I, J, lib=lib), T._brute_spref(A, I, J), "spref")
+            for op in ("second", "plus", "replace"):
+                for _ in range(3):
+                    A2, B, I2, J2 = T._rand_assign(rng, m, n, vd)
+                    assert_csr_equal(oracle.spasgn(A2, B, I2, J2, op, lib=lib),
+                                     T._brute_spasgn(A2, B, I2, J2, op), op)
+    A = rand_csr(rng, 6, 5, 0.4)
+    try:
+        oracle.permute(A, np.array([0, 1, 2, 3, 4, 4]), np.arange(5), lib=lib)
+        raise AssertionError("duplicate p accepted")
+    except oracle.OracleError as e:
+        assert e.name == "NOT_PERMUTATION"
+    B = rand_csr(rng, 2, 2, 0.5)
+    try:
+        oracle.spasgn(A, B, np.array([1, 1]), np.array([0, 2]), lib=lib)
+        raise AssertionError("duplicate I accepted")
+    except oracle.OracleError as e:
+        assert e.name == "DUPLICATE_INDEX"
+
+
+if __name__ == "__main__":
+    lib = oracle._load(sys.argv[1])
+    try:
+        battery(lib)
+    except AssertionError as e:
+        print("pin failed:", str(e).splitlines()[0])
+        sys.exit(1)
+    sys.exit(0)

@@ -1,0 +1,312 @@
+"""Pins for the CPU oracle: it must agree with computations that do not share
+its code -- dense brute force, SciPy fancy indexing, the selection-matrix
+products of the paper's problem formulation (Sec. 2.1-2.3), hand-worked
+examples, closed-form counts and invariants."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from tests._util import (assert_csr_equal, dense, floats, from_dense, from_scipy, ints,
+                         rand_csr, read_golden, selection, to_scipy)
+
+SHAPES = [(1, 1), (2, 3), (5, 5), (7, 4), (9, 13), (16, 16), (33, 20)]
+
+
+def _brute_permute(A, p, q):
+    D, M = dense(A)
+    return from_dense(D[np.ix_(p, q)], M[np.ix_(p, q)])
+
+
+def _brute_spref(A, I, J):
+    D, M = dense(A)
+    return from_dense(D[np.ix_(I, J)], M[np.ix_(I, J)])
+
+
+def _brute_spasgn(A, B, I, J, op):
+    D, M = dense(A)
+    m, n = D.shape
+    bm, bn, brp, bc, bv = B
+    if op == "replace":
+        M[np.ix_(I, J)] = False
+        D[np.ix_(I, J)] = 0
+    for i in range(bm):
+        for k in range(brp[i], brp[i + 1]):
+            r, c = I[i], J[bc[k]]
+            if op == "plus" and M[r, c]:
+                D[r, c] = D[r, c] + bv[k]          # numpy: one add in the value dtype
+            else:
+                D[r, c] = bv[k]
+            M[r, c] = True
+    return from_dense(D, M)
+
+
+# ---------------------------------------------------------------- golden ---
+
+def test_golden_permute():
+    g = read_golden("permute_3x4.txt")
+    m, n = ints(g["shape"])
+    A = (int(m), int(n), ints(g["rowptr"]), ints(g["col"]).astype(np.int32), floats(g["val"]))
+    got = oracle.permute(A, ints(g["p"]), ints(g["q"]))
+    assert_csr_equal(got, (ints(g["expect_rowptr"]), ints(g["expect_col"]), floats(g["expect_val"])),
+                     "golden permute")
+
+
+def test_golden_spref():
+    g = read_golden("spref_dup_3x4.txt")
+    m, n = ints(g["shape"])
+    A = (int(m), int(n), ints(g["rowptr"]), ints(g["col"]).astype(np.int32), floats(g["val"]))
+    got = oracle.spref(A, ints(g["I"]), ints(g["J"]))
+    assert_csr_equal(got, (ints(g["expect_rowptr"]), ints(g["expect_col"]), floats(g["expect_val"])),
+                     "golden spref")
+
+
+@pytest.mark.parametrize("op", ["second", "plus", "replace"])
+def test_golden_spasgn(op):
+    g = read_golden("spasgn_3x4.txt")
+    m, n = ints(g["shape"])
+    A = (int(m), int(n), ints(g["rowptr"]), ints(g["col"]).astype(np.int32), floats(g["val"]))
+    bm, bn = ints(g["Bshape"])
+    B = (int(bm), int(bn), ints(g["Browptr"]), ints(g["Bcol"]).astype(np.int32), floats(g["Bval"]))
+    got = oracle.spasgn(A, B, ints(g["I"]), ints(g["J"]), op)
+    exp = (ints(g[f"{op}_rowptr"]), ints(g[f"{op}_col"]), floats(g[f"{op}_val"]))
+    assert_csr_equal(got, exp, f"golden spasgn {op}")
+
+
+# --------------------------------------------------------------- permute ---
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("vdtype", [np.float64, np.float32])
+def test_permute_brute_scipy_selection(shape, vdtype):
+    rng = np.random.default_rng(hash(shape) % 1000)
+    m, n = shape
+    A = rand_csr(rng, m, n, 0.3, vdtype)
+    p = rng.permutation(m)
+    q = rng.permutation(n)
+    got = oracle.permute(A, p, q)
+    assert_csr_equal(got, _brute_permute(A, p, q), "brute")
+    S = to_scipy(A)
+    assert_csr_equal(got, from_scipy(S[p][:, q]), "scipy fancy indexing")
+    Pm = selection(p, m, vdtype)
+    Qm = selection(q, n, vdtype)
+    assert_csr_equal(got, from_scipy(Pm @ S @ Qm.T), "P A Q^T")
+
+
+def test_permute_symmetric_equals_general():
+    rng = np.random.default_rng(1)
+    A = rand_csr(rng, 12, 12, 0.25)
+    p = rng.permutation(12)
+    assert_csr_equal(oracle.permute(A, p), oracle.permute(A, p, p), "symmetric")
+    assert_csr_equal(oracle.permute(A, p), _brute_permute(A, p, p), "symmetric brute")
+
+
+def test_permute_invariants():
+    rng = np.random.default_rng(2)
+    m, n = 40, 30
+    A = rand_csr(rng, m, n, 0.2)
+    p1, q1 = rng.permutation(m), rng.permutation(n)
+    p2, q2 = rng.permutation(m), rng.permutation(n)
+    A1 = oracle.permute(A, p1, q1)
+    assert A1[0][-1] == A[2][-1]                       # nnz preserved
+    lens = np.diff(A[2])
+    assert sorted(np.diff(A1[0])) == sorted(lens)       # row-length multiset preserved
+    # inverse permutations restore A byte for byte
+    back = oracle.permute((m, n) + A1, np.argsort(p1), np.argsort(q1))
+    assert_csr_equal(back, A[2:], "inverse")
+    # identity
+    assert_csr_equal(oracle.permute(A, np.arange(m), np.arange(n)), A[2:], "identity")
+    # composition: A''[i,j] = A[p1[p2[i]], q1[q2[j]]]
+    A2 = oracle.permute((m, n) + A1, p2, q2)
+    assert_csr_equal(A2, oracle.permute(A, p1[p2], q1[q2]), "composition")
+
+
+def test_permute_sampled_rows_match_full():
+    rng = np.random.default_rng(3)
+    A = rand_csr(rng, 50, 60, 0.1)
+    p, q = rng.permutation(50), rng.permutation(60)
+    full = oracle.permute(A, p, q)
+    rows = np.array([49, 0, 7, 7, 23])
+    part = oracle.permute(A, p, q, rows=rows)
+    for s, i in enumerate(rows):
+        a, b = full[0][i], full[0][i + 1]
+        c, d = part[0][s], part[0][s + 1]
+        np.testing.assert_array_equal(full[1][a:b], part[1][c:d])
+        np.testing.assert_array_equal(full[2][a:b], part[2][c:d])
+
+
+# ----------------------------------------------------------------- spref ---
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("vdtype", [np.float64, np.float32])
+def test_spref_brute_scipy_selection(shape, vdtype):
+    rng = np.random.default_rng(7 + hash(shape) % 1000)
+    m, n = shape
+    A = rand_csr(rng, m, n, 0.35, vdtype)
+    for trial in range(4):
+        nI = int(rng.integers(0, 2 * m + 1))
+        nJ = int(rng.integers(0, 2 * n + 1))
+        I = rng.integers(0, m, nI)          # duplicates and any order
+        J = rng.integers(0, n, nJ)
+        got = oracle.spref(A, I, J)
+        assert_csr_equal(got, _brute_spref(A, I, J), "brute")
+        if nI and nJ:
+            S = to_scipy(A)
+            assert_csr_equal(got, from_scipy(S[I][:, J]), "scipy")
+            R = selection(I, m, vdtype)
+            Q = selection(J, n, vdtype)
+            assert_csr_equal(got, from_scipy(R @ S @ Q.T), "R A Q^T")
+        # closed-form count: sum over selected rows of the multiplicity of each column in J
+        mult = np.bincount(J, minlength=n)
+        rp, c = A[2], A[3]
+        expect = sum(int(mult[c[k]]) for i in I for k in range(rp[i], rp[i + 1]))
+        assert got[0][-1] == expect
+
+
+def test_spref_special_cases():
+    rng = np.random.default_rng(11)
+    m, n = 25, 19
+    A = rand_csr(rng, m, n, 0.3)
+    # whole index sets in order reproduce A
+    assert_csr_equal(oracle.spref(A, np.arange(m), np.arange(n)), A[2:], "identity")
+    # full permutations make extraction a permutation (Sec. 2.2)
+    p, q = rng.permutation(m), rng.permutation(n)
+    assert_csr_equal(oracle.spref(A, p, q), oracle.permute(A, p, q), "perm special case")
+    # sorted unique subsets keep the original order
+    I = np.sort(rng.choice(m, 9, replace=False))
+    J = np.sort(rng.choice(n, 7, replace=False))
+    got = oracle.spref(A, I, J)
+    D, M = dense(A)
+    assert_csr_equal(got, from_dense(D[I][:, J], M[I][:, J]), "ordered submatrix")
+    # empty index sets give an empty, correctly shaped result
+    e = oracle.spref(A, np.zeros(0, np.int64), J)
+    assert e[0].tolist() == [0] and e[1].size == 0
+    e = oracle.spref(A, I, np.zeros(0, np.int64))
+    assert e[0].tolist() == [0] * (len(I) + 1)
+
+
+def test_spref_exhaustive_tiny():
+    """Every index vector of length <= 2 over a 3 x 3 matrix, against brute force."""
+    rng = np.random.default_rng(5)
+    A = rand_csr(rng, 3, 3, 0.5)
+    vecs = [()] + [(a,) for a in range(3)] + list(itertools.product(range(3), repeat=2))
+    for I in vecs:
+        for J in vecs:
+            I_ = np.array(I, dtype=np.int64)
+            J_ = np.array(J, dtype=np.int64)
+            assert_csr_equal(oracle.spref(A, I_, J_), _brute_spref(A, I_, J_), f"{I} {J}")
+
+
+# ---------------------------------------------------------------- spasgn ---
+
+def _rand_assign(rng, m, n, vdtype=np.float64):
+    A = rand_csr(rng, m, n, 0.3, vdtype)
+    nI = int(rng.integers(0, m + 1))
+    nJ = int(rng.integers(0, n + 1))
+    I = rng.choice(m, nI, replace=False)
+    J = rng.choice(n, nJ, replace=False)
+    B = rand_csr(rng, nI, nJ, 0.4, vdtype)
+    return A, B, I, J
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("vdtype", [np.float64, np.float32])
+@pytest.mark.parametrize("op", ["second", "plus", "replace"])
+def test_spasgn_brute(shape, vdtype, op):
+    rng = np.random.default_rng(17 + hash((shape, op)) % 1000)
+    for trial in range(3):
+        A, B, I, J = _rand_assign(rng, *shape, vdtype)
+        got = oracle.spasgn(A, B, I, J, op)
+        assert_csr_equal(got, _brute_spasgn(A, B, I, J, op), f"brute {op}")
+
+
+@pytest.mark.parametrize("vdtype", [np.float64, np.float32])
+def test_spasgn_plus_is_selection_product(vdtype):
+    """PLUS is A + P B Q^T with the Boolean P, Q of Sec. 2.3."""
+    rng = np.random.default_rng(23)
+    for trial in range(6):
+        m, n = 20 + trial, 15 + 2 * trial
+        A, B, I, J = _rand_assign(rng, m, n, vdtype)
+        if len(I) == 0 or len(J) == 0:
+            continue
+        S = to_scipy(A)
+        P = selection(I, m, vdtype).T.tocsr()      # m x |I|, P[r,i]=1 iff r = I[i]
+        Q = selection(J, n, vdtype).T.tocsr()
+        exp = from_scipy(S + P @ to_scipy(B) @ Q.T)
+        assert_csr_equal(oracle.spasgn(A, B, I, J, "plus"), exp, "A + P B Q^T")
+
+
+def test_spasgn_invariants():
+    rng = np.random.default_rng(29)
+    m, n = 30, 26
+    A, B, I, J = _rand_assign(rng, m, n)
+    Da, Ma = dense(A)
+    inside = np.zeros((m, n), bool)
+    inside[np.ix_(I, J)] = True
+    for op in ("second", "plus", "replace"):
+        got = oracle.spasgn(A, B, I, J, op)
+        Dg, Mg = dense((m, n) + got)
+        # outside I x J nothing changes
+        assert np.array_equal(Mg & ~inside, Ma & ~inside)
+        assert np.array_equal(np.where(~inside, Dg, 0), np.where(~inside, Da, 0))
+    # block replace then extract gives B back exactly
+    rep = oracle.spasgn(A, B, I, J, "replace")
+    assert_csr_equal(oracle.spref((m, n) + rep, I, J), B[2:], "extract after replace")
+    # select-second: entries outside pattern(B') keep A's value
+    sec = oracle.spasgn(A, B, I, J, "second")
+    Dg, Mg = dense((m, n) + sec)
+    Bp = np.zeros((m, n), bool)
+    bm, bn, brp, bc, bv = B
+    for i in range(bm):
+        for k in range(brp[i], brp[i + 1]):
+            Bp[I[i], J[bc[k]]] = True
+    assert np.array_equal(Mg, Ma | Bp)
+    assert np.array_equal(np.where(~Bp, Dg, 0), np.where(~Bp, Da, 0))
+
+
+def test_spasgn_round_trip_streaming():
+    """Split A's edges into 80% + 4 x 5%, assign the parts back one by one
+    (the streaming-update experiment of the assignment results): A returns."""
+    rng = np.random.default_rng(31)
+    m, n = 60, 60
+    A = rand_csr(rng, m, n, 0.15)
+    D, M = dense(A)
+    label = rng.choice(5, size=(m, n), p=[0.8, 0.05, 0.05, 0.05, 0.05])
+    cur = from_dense(np.where(label == 0, D, 0), M & (label == 0))
+    for part in range(1, 5):
+        Mp = M & (label == part)
+        I = np.nonzero(Mp.any(1))[0]
+        J = np.nonzero(Mp.any(0))[0]
+        Bd, Bm = D[np.ix_(I, J)], Mp[np.ix_(I, J)]
+        B = (len(I), len(J)) + from_dense(np.where(Bm, Bd, 0), Bm)
+        cur = oracle.spasgn((m, n) + cur, B, I, J, "second")
+    assert_csr_equal(cur, A[2:], "round trip")
+
+
+# ---------------------------------------------------------------- errors ---
+
+def test_error_statuses():
+    rng = np.random.default_rng(37)
+    A = rand_csr(rng, 6, 5, 0.4)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.permute(A, np.array([0, 1, 2, 3, 4, 4]), np.arange(5))
+    assert e.value.name == "NOT_PERMUTATION"
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.permute(A, np.arange(6), np.array([0, 1, 2, 3, 5]))
+    assert e.value.name == "INDEX_RANGE"
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.permute(A, np.arange(6))                 # symmetric needs square
+    assert e.value.name == "SHAPE"
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.spref(A, np.array([0, 6]), np.arange(5))
+    assert e.value.name == "INDEX_RANGE"
+    B = rand_csr(rng, 2, 2, 0.5)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.spasgn(A, B, np.array([1, 1]), np.array([0, 2]))
+    assert e.value.name == "DUPLICATE_INDEX"
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.spasgn(A, B, np.array([1, 2, 3]), np.array([0, 2]))
+    assert e.value.name == "SHAPE"
+    assert oracle.check_csr(A) == "OK"
+    bad = (6, 5, A[2], A[3][::-1].copy(), A[4])
+    assert oracle.check_csr(bad) != "OK"
