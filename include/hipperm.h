@@ -1,0 +1,172 @@
+/*
+ * hipperm.h -- C ABI of an MI355X (gfx950) library for sparse-matrix
+ * permutation, submatrix extraction and submatrix assignment on CSR
+ * matrices held in one GPU's HBM.
+ *
+ * Operations (definitions from the problem formulation of the paper
+ * "Distributed-memory Algorithms for Sparse Matrix Permutation, Extraction,
+ * and Assignment", Sec. 2):
+ *   permute : C[i,j] = A[p[i], q[j]]          (Sec. 2.1; C = P A Q^T)
+ *   spref   : C[i,j] = A[I[i], J[j]]  for (i,j) in I x J   (Sec. 2.2; C = R A Q^T)
+ *   spasgn  : C = A (+) B', B'[I[i], J[j]] = B[i,j] for stored B entries
+ *             (Sec. 2.3 and the Add step of Sec. 4.7; user-chosen addition)
+ *
+ * Conventions for every call:
+ *   - All matrix and index arrays are DEVICE pointers on the handle's
+ *     device.  The caller owns every buffer: inputs, outputs, workspaces.
+ *     The library never allocates or frees caller memory; it owns only the
+ *     handle (a stream, events and one pinned host scalar block).
+ *   - Indices are 0-based (the paper counts from 1).
+ *   - CSR is canonical: rowptr[0] = 0, non-decreasing; columns strictly
+ *     ascending inside a row.  rowptr is int32 or int64 (hp_idx_t); columns
+ *     are int32; values are fp32 or fp64 (hp_val_t) and are moved as raw
+ *     bits, never re-rounded (except the one addition of HP_OP_PLUS).
+ *   - Outputs are out-of-place: output arrays must not overlap inputs
+ *     (HP_ERR_ALIAS when they share an address).
+ *   - Work is enqueued on the handle's stream in order.  The plan calls end
+ *     with one blocking readback of a few scalars (output size, error
+ *     flags, bin statistics); exec calls never block.
+ *   - Errors are returned as hp_status_t; no exception crosses the ABI.
+ *     hp_last_error() gives a message for the last failing call.
+ *
+ * Each operation is split in two:
+ *   plan : validates indices, builds the inverse index tables, counts the
+ *          nonzeros of every output row and scans them into C->rowptr;
+ *          sets C->nnz and fills *info (blocking: one scalar readback).
+ *   exec : writes C->col and C->val (sized C->nnz by the caller after plan).
+ *          It must get the same arguments, the same plan workspace (untouched
+ *          in between) and the info struct of a plan call that returned
+ *          HP_OK, plus an exec workspace of at least info->exec_ws_bytes
+ *          (may be NULL when that is 0).
+ */
+#ifndef HIPPERM_H
+#define HIPPERM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HP_OK = 0,
+    HP_ERR_INVALID_ARG = 1,      /* NULL pointer, negative size, bad enum          */
+    HP_ERR_INDEX_RANGE = 2,      /* an index outside [0, nrows) or [0, ncols)      */
+    HP_ERR_NOT_PERMUTATION = 3,  /* permute: p or q repeats a value                */
+    HP_ERR_DUPLICATE_INDEX = 4,  /* spasgn: I or J repeats a value (Sec. 2.3)      */
+    HP_ERR_NOT_CANONICAL = 5,    /* hp_validate_csr: unsorted/duplicate columns    */
+    HP_ERR_SHAPE = 6,            /* B is not |I| x |J|; symmetric permute on m != n */
+    HP_ERR_OVERFLOW = 7,         /* output nnz does not fit an int32 rowptr        */
+    HP_ERR_WORKSPACE = 8,        /* workspace smaller than the queried size        */
+    HP_ERR_CAPACITY = 9,         /* batched: an output exceeded its arena slot     */
+    HP_ERR_HIP = 10,             /* a HIP runtime call failed                      */
+    HP_ERR_ALIAS = 11,           /* an output array overlaps an input array        */
+    HP_ERR_TIMEOUT = 12,         /* a device-side bounded wait gave up             */
+    HP_ERR_REJECTED = 13         /* served form: request can never fit the budget  */
+} hp_status_t;
+
+typedef enum { HP_IDX_I32 = 0, HP_IDX_I64 = 1 } hp_idx_t;
+typedef enum { HP_VAL_F32 = 0, HP_VAL_F64 = 1 } hp_val_t;
+
+/* Addition used by spasgn where A and B' both hold an entry (Sec. 2.3):
+ *   SECOND  : B's value overwrites A's (select-second, the common variant);
+ *   PLUS    : A + B in the value type, IEEE-754 round-to-nearest-even;
+ *   REPLACE : block replace -- every A entry inside I x J is removed first,
+ *             then B' is inserted (so A(I,J) == B afterwards). */
+typedef enum { HP_OP_SECOND = 0, HP_OP_PLUS = 1, HP_OP_REPLACE = 2 } hp_asgn_op_t;
+
+typedef struct {
+    int64_t nrows, ncols, nnz;
+    int32_t ptr_type;   /* hp_idx_t */
+    int32_t val_type;   /* hp_val_t */
+    void *rowptr;       /* device, nrows+1 entries of ptr_type   */
+    int32_t *col;       /* device, nnz entries                   */
+    void *val;          /* device, nnz entries of val_type       */
+} hp_csr_t;
+
+/* Filled by every plan call and passed unchanged to the matching exec call
+ * (exec needs the class sizes to size its launches without a readback). */
+typedef struct {
+    int64_t nnz_out;          /* nonzeros of C (also stored in C->nnz)              */
+    size_t exec_ws_bytes;     /* exec workspace the following exec call needs       */
+    int32_t map_monotone;     /* 1 when the column map keeps order (no row sort)    */
+    int32_t op;               /* which operation produced it (internal check)       */
+    int64_t rows_sorted[4];   /* output rows per sort class: <=16, <=64, <=4096, >  */
+    int64_t class_elems[4];   /* entries per sort class                             */
+    int64_t aux[4];           /* operation-specific counts                          */
+} hp_plan_info_t;
+
+typedef struct hp_handle_s *hp_handle_t;
+
+/* ---- handle ------------------------------------------------------------ */
+
+/* Create a handle bound to HIP device `device`, using the default (null)
+ * stream.  *h is set only on success. */
+hp_status_t hp_create(hp_handle_t *h, int device);
+hp_status_t hp_destroy(hp_handle_t h);
+/* Enqueue all later work of this handle on `stream` (a hipStream_t). */
+hp_status_t hp_set_stream(hp_handle_t h, void *stream);
+const char *hp_status_string(hp_status_t s);
+/* Message for the last failing call on h (static storage in the handle). */
+const char *hp_last_error(hp_handle_t h);
+
+/* Per-stage device timing: when enabled, every plan/exec records HIP events
+ * around each kernel stage; hp_stage_times copies up to `cap` stage
+ * durations (ms) and their names of the last plan+exec pair. */
+hp_status_t hp_enable_timing(hp_handle_t h, int enable);
+int hp_stage_times(hp_handle_t h, float *ms, const char **names, int cap);
+
+/* Canonical-CSR check (rowptr monotone, columns in range, strictly
+ * ascending in each row).  Returns HP_OK, HP_ERR_NOT_CANONICAL or
+ * HP_ERR_INDEX_RANGE.  ws must hold hp_validate_workspace() bytes. */
+hp_status_t hp_validate_workspace(hp_handle_t h, const hp_csr_t *A, size_t *bytes);
+hp_status_t hp_validate_csr(hp_handle_t h, const hp_csr_t *A, void *ws, size_t ws_bytes);
+
+/* ---- permute: C = P A Q^T, C[i,j] = A[p[i], q[j]] (Sec. 2.1) ----------- */
+/* p: m entries, a permutation of [0, m); q: n entries, a permutation of
+ * [0, n), or NULL for the symmetric form P A P^T (requires m == n).
+ * C: caller sets nrows=m, ncols=n, ptr_type/val_type equal to A's and
+ * rowptr (m+1 entries); plan writes rowptr and nnz (= nnz(A)).
+ * Errors: INDEX_RANGE, NOT_PERMUTATION, SHAPE, WORKSPACE, ALIAS. */
+hp_status_t hp_permute_workspace(hp_handle_t h, const hp_csr_t *A, size_t *bytes);
+hp_status_t hp_permute_plan(hp_handle_t h, const hp_csr_t *A, const int32_t *p, const int32_t *q,
+                            hp_csr_t *C, void *ws, size_t ws_bytes, hp_plan_info_t *info);
+hp_status_t hp_permute_exec(hp_handle_t h, const hp_csr_t *A, const int32_t *p, const int32_t *q,
+                            hp_csr_t *C, void *ws, size_t ws_bytes, const hp_plan_info_t *info,
+                            void *xws, size_t xws_bytes);
+
+/* ---- spref: C = A(I, J), C[i,j] = A[I[i], J[j]] (Sec. 2.2) -------------- */
+/* I (nI entries) and J (nJ entries) may repeat values and be in any order:
+ * a repeated row (column) is replicated, order follows I and J.
+ * C: caller sets nrows=nI, ncols=nJ, types equal to A's, rowptr (nI+1).
+ * Errors: INDEX_RANGE, OVERFLOW (int32 rowptr and nnz(C) >= 2^31),
+ * WORKSPACE, ALIAS. */
+hp_status_t hp_spref_workspace(hp_handle_t h, const hp_csr_t *A, int64_t nI, int64_t nJ,
+                               size_t *bytes);
+hp_status_t hp_spref_plan(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int64_t nI,
+                          const int32_t *J, int64_t nJ, hp_csr_t *C, void *ws, size_t ws_bytes,
+                          hp_plan_info_t *info);
+hp_status_t hp_spref_exec(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int64_t nI,
+                          const int32_t *J, int64_t nJ, hp_csr_t *C, void *ws, size_t ws_bytes,
+                          const hp_plan_info_t *info, void *xws, size_t xws_bytes);
+
+/* ---- spasgn: C = A with A(I, J) = B (Sec. 2.3, Sec. 4.7) ------------------ */
+/* I, J: distinct indices (Sec. 2.3) of lengths B->nrows and B->ncols.
+ * A and B share ptr_type and val_type.  C: caller sets nrows=m, ncols=n,
+ * types equal to A's, rowptr (m+1).
+ * Errors: INDEX_RANGE, DUPLICATE_INDEX, SHAPE, OVERFLOW, WORKSPACE, ALIAS. */
+hp_status_t hp_spasgn_workspace(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B,
+                                size_t *bytes);
+hp_status_t hp_spasgn_plan(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, const int32_t *I,
+                           const int32_t *J, hp_asgn_op_t op, hp_csr_t *C, void *ws,
+                           size_t ws_bytes, hp_plan_info_t *info);
+hp_status_t hp_spasgn_exec(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, const int32_t *I,
+                           const int32_t *J, hp_asgn_op_t op, hp_csr_t *C, void *ws,
+                           size_t ws_bytes, const hp_plan_info_t *info, void *xws,
+                           size_t xws_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HIPPERM_H */

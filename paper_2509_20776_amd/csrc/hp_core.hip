@@ -1,0 +1,381 @@
+// Handle, status, timing, and the shared kernels: status-block init, the
+// single-pass exclusive scan with row classification, and the segmented
+// sort used by every operation's Build step.
+#include "hp_internal.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+using namespace hp;
+
+// ===========================================================================
+// Status / handle
+// ===========================================================================
+extern "C" const char *hp_status_string(hp_status_t s) {
+    switch (s) {
+        case HP_OK: return "HP_OK";
+        case HP_ERR_INVALID_ARG: return "HP_ERR_INVALID_ARG";
+        case HP_ERR_INDEX_RANGE: return "HP_ERR_INDEX_RANGE";
+        case HP_ERR_NOT_PERMUTATION: return "HP_ERR_NOT_PERMUTATION";
+        case HP_ERR_DUPLICATE_INDEX: return "HP_ERR_DUPLICATE_INDEX";
+        case HP_ERR_NOT_CANONICAL: return "HP_ERR_NOT_CANONICAL";
+        case HP_ERR_SHAPE: return "HP_ERR_SHAPE";
+        case HP_ERR_OVERFLOW: return "HP_ERR_OVERFLOW";
+        case HP_ERR_WORKSPACE: return "HP_ERR_WORKSPACE";
+        case HP_ERR_CAPACITY: return "HP_ERR_CAPACITY";
+        case HP_ERR_HIP: return "HP_ERR_HIP";
+        case HP_ERR_ALIAS: return "HP_ERR_ALIAS";
+        case HP_ERR_TIMEOUT: return "HP_ERR_TIMEOUT";
+        case HP_ERR_REJECTED: return "HP_ERR_REJECTED";
+    }
+    return "HP_ERR_UNKNOWN";
+}
+
+namespace hp {
+
+hp_status_t fail(hp_handle_t h, hp_status_t s, const std::string &msg) {
+    if (h) h->last_error = std::string(hp_status_string(s)) + ": " + msg;
+    return s;
+}
+
+hp_status_t hip_check(hp_handle_t h, hipError_t e, const char *what) {
+    if (e == hipSuccess) return HP_OK;
+    return fail(h, HP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+hp_status_t status_from_err(hp_handle_t h, uint32_t err, const char *op) {
+    if (!err) return HP_OK;
+    std::string o(op);
+    if (err & E_TIMEOUT) return fail(h, HP_ERR_TIMEOUT, o + ": device wait limit reached");
+    if (err & E_RANGE) return fail(h, HP_ERR_INDEX_RANGE, o + ": index out of range");
+    if (err & E_NOTPERM) return fail(h, HP_ERR_NOT_PERMUTATION, o + ": index vector is not a permutation");
+    if (err & E_DUP) return fail(h, HP_ERR_DUPLICATE_INDEX, o + ": repeated index in an assignment vector");
+    if (err & E_NONCANON) return fail(h, HP_ERR_NOT_CANONICAL, o + ": CSR not canonical");
+    if (err & E_OVERFLOW) return fail(h, HP_ERR_OVERFLOW, o + ": output nnz exceeds int32 rowptr");
+    if (err & E_CAPACITY) return fail(h, HP_ERR_CAPACITY, o + ": output exceeds capacity");
+    return fail(h, HP_ERR_INVALID_ARG, o + ": device error");
+}
+
+bool overlaps(const void *a, size_t an, const void *b, size_t bn) {
+    if (!a || !b || an == 0 || bn == 0) return false;
+    uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bn && y < x + an;
+}
+
+size_t idx_size(int32_t t) { return t == HP_IDX_I64 ? 8 : 4; }
+size_t val_size(int32_t t) { return t == HP_VAL_F64 ? 8 : 4; }
+
+hp_status_t check_csr_args(hp_handle_t h, const hp_csr_t *A, const char *name) {
+    std::string n(name);
+    if (!A) return fail(h, HP_ERR_INVALID_ARG, n + " is NULL");
+    if (A->nrows < 0 || A->ncols < 0 || A->nnz < 0)
+        return fail(h, HP_ERR_INVALID_ARG, n + ": negative size");
+    if (A->ncols > INT32_MAX || A->nrows > INT32_MAX)
+        return fail(h, HP_ERR_INVALID_ARG, n + ": dimension exceeds int32 column/row index range");
+    if (A->ptr_type != HP_IDX_I32 && A->ptr_type != HP_IDX_I64)
+        return fail(h, HP_ERR_INVALID_ARG, n + ": bad ptr_type");
+    if (A->val_type != HP_VAL_F32 && A->val_type != HP_VAL_F64)
+        return fail(h, HP_ERR_INVALID_ARG, n + ": bad val_type");
+    if (A->ptr_type == HP_IDX_I32 && A->nnz > INT32_MAX)
+        return fail(h, HP_ERR_OVERFLOW, n + ": nnz exceeds int32 rowptr");
+    if (!A->rowptr) return fail(h, HP_ERR_INVALID_ARG, n + ": rowptr is NULL");
+    if (A->nnz > 0 && (!A->col || !A->val)) return fail(h, HP_ERR_INVALID_ARG, n + ": col/val NULL");
+    return HP_OK;
+}
+
+// ---- stage timing ---------------------------------------------------------
+void stage_begin(hp_handle_t h) {
+    if (!h->timing) return;
+    h->nstage = 0;
+    h->stage_names.clear();
+    if (h->ev.empty()) {
+        h->ev.resize(64);
+        for (auto &e : h->ev) hipEventCreate(&e);
+    }
+    hipEventRecord(h->ev[0], h->stream);
+}
+void stage_mark(hp_handle_t h, const char *name) {
+    if (!h->timing || h->nstage + 1 >= (int)h->ev.size()) return;
+    h->nstage++;
+    hipEventRecord(h->ev[h->nstage], h->stream);
+    h->stage_names.push_back(name);
+}
+void stage_end(hp_handle_t h) {
+    if (!h->timing) return;
+    hipEventSynchronize(h->ev[h->nstage]);
+    for (int k = 0; k < h->nstage && h->nstage_out < 64; k++) {
+        float ms = 0;
+        hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]);
+        h->stage_ms[h->nstage_out] = ms;
+        h->stage_name_out[h->nstage_out] = h->stage_names[k];
+        h->nstage_out++;
+    }
+}
+
+}  // namespace hp
+
+extern "C" hp_status_t hp_create(hp_handle_t *out, int device) {
+    if (!out) return HP_ERR_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HP_ERR_INVALID_ARG;
+    hp_handle_t h = new hp_handle_s();
+    h->device = device;
+    if (hipSetDevice(device) != hipSuccess ||
+        hipHostMalloc((void **)&h->host_hdr, sizeof(DevHdr), hipHostMallocDefault) != hipSuccess) {
+        delete h;
+        return HP_ERR_HIP;
+    }
+    *out = h;
+    return HP_OK;
+}
+
+extern "C" hp_status_t hp_destroy(hp_handle_t h) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    for (auto &e : h->ev) hipEventDestroy(e);
+    if (h->host_hdr) hipHostFree(h->host_hdr);
+    delete h;
+    return HP_OK;
+}
+
+extern "C" hp_status_t hp_set_stream(hp_handle_t h, void *stream) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    h->stream = (hipStream_t)stream;
+    return HP_OK;
+}
+
+extern "C" const char *hp_last_error(hp_handle_t h) { return h ? h->last_error.c_str() : "null handle"; }
+
+extern "C" hp_status_t hp_enable_timing(hp_handle_t h, int enable) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    h->timing = enable != 0;
+    h->nstage_out = 0;
+    return HP_OK;
+}
+
+extern "C" int hp_stage_times(hp_handle_t h, float *ms, const char **names, int cap) {
+    if (!h) return 0;
+    int n = std::min(cap, h->nstage_out);
+    for (int k = 0; k < n; k++) {
+        if (ms) ms[k] = h->stage_ms[k];
+        if (names) names[k] = h->stage_name_out[k];
+    }
+    h->nstage_out = 0;
+    return n;
+}
+
+// ===========================================================================
+// Small kernels
+// ===========================================================================
+__global__ void k_clear_words(uint32_t *p, size_t n) {
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    uint4 z = make_uint4(0, 0, 0, 0);
+    size_t n4 = n / 4;
+    for (size_t k = i; k < n4; k += stride) reinterpret_cast<uint4 *>(p)[k] = z;
+    for (size_t k = n4 * 4 + i; k < n; k += stride) p[k] = 0;
+}
+
+__global__ void k_init_hdr(DevHdr *h, uint64_t *tile_state, size_t ntiles) {
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    if (i < sizeof(DevHdr) / 4) reinterpret_cast<uint32_t *>(h)[i] = 0;
+    for (size_t k = i; k < ntiles; k += stride) tile_state[k] = 0;
+}
+
+namespace hp {
+
+static int grid_for(size_t n, int block, int cap = 1 << 16) {
+    size_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > (size_t)cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_clear_words(hipStream_t s, void *p, size_t nwords32) {
+    if (nwords32 == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clear_words, dim3(grid_for(nwords32 / 4 + 1, 256, 8192)), dim3(256), 0, s,
+                       (uint32_t *)p, nwords32);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_hdr(hipStream_t s, DevHdr *h, uint64_t *tile_state, size_t ntiles) {
+    size_t n = std::max(ntiles, sizeof(DevHdr) / 4);
+    hipLaunchKernelGGL(k_init_hdr, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, h, tile_state, ntiles);
+    return hipGetLastError();
+}
+
+hipError_t readback_hdr(hp_handle_t h, DevHdr *dev) {
+    hipError_t e = hipMemcpyAsync(h->host_hdr, dev, sizeof(DevHdr), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(h->stream);
+}
+
+// ===========================================================================
+// Single-pass exclusive scan (decoupled look-back) with row classification.
+//
+// Tiles are taken in launch order from an atomic ticket, so a tile only ever
+// waits on tiles that are already running: every wait ends.  The wait is
+// still bounded (SPIN_LIMIT); reaching it raises E_TIMEOUT and the kernel
+// finishes normally.
+// ===========================================================================
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+constexpr uint64_t ST_AGG = 1ull << 62, ST_PRE = 2ull << 62, ST_VAL = (1ull << 62) - 1;
+constexpr uint32_t SPIN_LIMIT = 1u << 24;
+
+size_t scan_tiles(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
+
+// Wave-aggregated append of `row` to its class list.
+__device__ __forceinline__ void classify_append(int64_t row, int64_t len, bool valid, int mode,
+                                                DevHdr *hdr, uint32_t *lists, int64_t cap,
+                                                uint64_t *goff) {
+    int bin = -1;
+    if (valid && len >= 2) {
+        if (len <= THREAD_MAX) bin = (mode == 2) ? BIN_THREAD : -1;
+        else if (len <= WAVE_MAX) bin = BIN_WAVE;
+        else if (len <= BLOCK_MAX) bin = BIN_BLOCK;
+        else bin = BIN_GLOBAL;
+    }
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int b = 0; b < NBINS; b++) {
+        uint64_t m = ballot(bin == b);
+        if (!m) continue;
+        int leader = __ffsll((long long)m) - 1;
+        uint32_t base = 0;
+        uint64_t ebase = 0;
+        uint64_t elen = (bin == b) ? (uint64_t)len : 0;
+        uint64_t esum = wave_sum(elen);
+        uint64_t epre = wave_incl_scan(elen) - elen;
+        if (lane_id() == leader) {
+            base = atomicAdd(&hdr->bin_cnt[b], (uint32_t)__popcll(m));
+            ebase = atomicAdd((unsigned long long *)&hdr->bin_elems[b], (unsigned long long)esum);
+        }
+        base = __shfl(base, leader, WAVE);
+        ebase = __shfl(ebase, leader, WAVE);
+        if (bin == b) {
+            uint32_t pos = base + (uint32_t)__popcll(m & lt);
+            if (pos < cap) {
+                lists[(int64_t)b * cap + pos] = (uint32_t)row;
+                if (b == BIN_GLOBAL) goff[pos] = ebase + epre;
+            }
+        }
+    }
+}
+
+template <typename PT>
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_counts(
+    const int32_t *__restrict__ cnt, PT *__restrict__ out, int64_t n, DevHdr *hdr, int slot,
+    uint64_t *tile_state, int classify, uint32_t *lists, int64_t cap, uint64_t *goff) {
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_wave[SCAN_BLOCK / WAVE];
+    __shared__ uint64_t s_excl;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&hdr->ticket[slot], 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t base = tile * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int32_t v[SCAN_ITEMS];
+    if (base + SCAN_ITEMS <= n) {
+        const int4 *p4 = reinterpret_cast<const int4 *>(cnt + base);
+        int4 a = p4[0], b = p4[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; k++) v[k] = (base + k < n) ? cnt[base + k] : 0;
+    }
+    uint64_t tsum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) tsum += (uint64_t)(uint32_t)v[k];
+    uint64_t tile_total;
+    uint64_t texcl = block_excl_scan<SCAN_BLOCK, uint64_t>(tsum, s_wave, tile_total);
+
+    if (threadIdx.x < WAVE) {
+        // publish this tile's aggregate, then look back for its prefix
+        if (lane_id() == 0)
+            st_agent(&tile_state[tile], (tile == 0 ? ST_PRE : ST_AGG) | (tile_total & ST_VAL));
+        uint64_t excl = 0;
+        if (tile > 0) {
+            int64_t j = tile - 1;
+            uint32_t spins = 0;
+            while (true) {
+                int64_t idx = j - lane_id();
+                uint64_t s = idx >= 0 ? ld_agent(&tile_state[idx]) : ST_PRE;
+                uint64_t flag = s & ~ST_VAL;
+                uint64_t pre = ballot(flag == ST_PRE);
+                uint64_t inval = ballot(flag == 0);
+                int fp = pre ? __ffsll((long long)pre) - 1 : 64;
+                uint64_t need = fp >= 63 ? ~0ull : ((2ull << fp) - 1);
+                if (inval & need) {
+                    if (++spins > SPIN_LIMIT) {
+                        if (lane_id() == 0) raise_err(hdr, E_TIMEOUT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                uint64_t part = (lane_id() <= fp) ? (s & ST_VAL) : 0;
+                excl += wave_sum(part);
+                if (pre) break;
+                j -= WAVE;
+            }
+            if (lane_id() == 0) st_agent(&tile_state[tile], ST_PRE | ((excl + tile_total) & ST_VAL));
+        }
+        if (lane_id() == 0) s_excl = excl;
+    }
+    __syncthreads();
+    uint64_t run = s_excl + texcl;
+    const int64_t last_base = (n - 1) / SCAN_TILE;
+    if (base + SCAN_ITEMS <= n && (sizeof(PT) == 8)) {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; k++) { out[base + k] = (PT)run; run += (uint32_t)v[k]; }
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; k++) {
+            if (base + k < n) out[base + k] = (PT)run;
+            run += (uint32_t)v[k];
+        }
+    }
+    if (tile == last_base && threadIdx.x == SCAN_BLOCK - 1) {
+        uint64_t total = s_excl + tile_total;
+        out[n] = (PT)total;
+        hdr->total[slot] = total;
+        if (sizeof(PT) == 4 && total > (uint64_t)INT32_MAX) raise_err(hdr, E_OVERFLOW);
+    }
+    if (classify) {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; k++)
+            classify_append(base + k, v[k], base + k < n, classify, hdr, lists, cap, goff);
+    }
+}
+
+template <typename PT>
+__global__ void k_scan_empty(PT *out, DevHdr *hdr, int slot) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        out[0] = 0;
+        hdr->total[slot] = 0;
+    }
+}
+
+template <typename PT>
+hipError_t launch_scan_counts(hipStream_t s, const int32_t *cnt, PT *out, int64_t n, DevHdr *hdr,
+                              int slot, uint64_t *tile_state, int classify, uint32_t *bin_lists,
+                              int64_t bin_cap) {
+    if (n == 0) {
+        hipLaunchKernelGGL(k_scan_empty<PT>, dim3(1), dim3(64), 0, s, out, hdr, slot);
+        return hipGetLastError();
+    }
+    int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    uint64_t *goff = bin_lists ? reinterpret_cast<uint64_t *>(bin_lists + NBINS * bin_cap) : nullptr;
+    hipLaunchKernelGGL(k_scan_counts<PT>, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, cnt, out, n,
+                       hdr, slot, tile_state, classify, bin_lists, bin_cap, goff);
+    return hipGetLastError();
+}
+
+template hipError_t launch_scan_counts<int32_t>(hipStream_t, const int32_t *, int32_t *, int64_t,
+                                                DevHdr *, int, uint64_t *, int, uint32_t *, int64_t);
+template hipError_t launch_scan_counts<int64_t>(hipStream_t, const int32_t *, int64_t *, int64_t,
+                                                DevHdr *, int, uint64_t *, int, uint32_t *, int64_t);
+
+}  // namespace hp

@@ -1,0 +1,304 @@
+// permute: C = P A Q^T, C[i,j] = A[p[i], q[j]] (paper Sec. 2.1).
+//
+// Identify (Sec. 4.2 Step 1): the index/value swap of p and q gives pinv
+// and qinv; the destination of source row r is output row pinv[r] and of
+// column c is qinv[c].  On one GPU the Exchange step disappears, and the
+// paper's two-pass count / prefix / scatter becomes count -> single-pass
+// scan -> fill, with the Build-step sort folded into the fill:
+//   plan : k_perm_prepare  pinv, qinv, per-output-row counts, range check
+//          k_perm_check    every value of p and q occurs once
+//          scan            rowptr of C + row classes by length
+//   exec : k_perm_fill_short  rows of <= 16 entries, streamed in source
+//                             order (push), sorted in registers
+//          class kernels       longer rows gathered from A (pull) and sorted
+#include "hp_internal.hpp"
+#include "hp_segsort.hpp"
+
+using namespace hp;
+
+namespace {
+
+struct PermLayout {
+    DevHdr *hdr;
+    uint64_t *tiles;
+    int32_t *pinv, *qinv, *cnt;
+    uint32_t *lists;
+};
+
+PermLayout perm_layout(Carve &c, int64_t m, int64_t n, bool sym) {
+    PermLayout L;
+    L.hdr = c.take<DevHdr>(1);
+    L.tiles = c.take<uint64_t>(scan_tiles(m));
+    L.pinv = c.take<int32_t>(m);
+    L.qinv = sym ? L.pinv : c.take<int32_t>(n);
+    L.cnt = c.take<int32_t>(m);
+    L.lists = c.take<uint32_t>(seg_list_words(m));
+    return L;
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void k_perm_prepare(const PT *__restrict__ arow,
+                                                     const int32_t *__restrict__ p,
+                                                     const int32_t *__restrict__ q, int64_t m,
+                                                     int64_t n, int32_t *pinv, int32_t *qinv,
+                                                     int32_t *cnt, DevHdr *hdr) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t hi = m > n ? m : n;
+    uint32_t err = 0, flags = 0;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < hi; t += stride) {
+        if (t < m) {
+            int32_t r = p[t];
+            if (r < 0 || r >= m) {
+                err |= E_RANGE;
+                cnt[t] = 0;
+            } else {
+                pinv[r] = (int32_t)t;
+                cnt[t] = (int32_t)(arow[r + 1] - arow[r]);
+            }
+            if (!q && r != t) flags |= F_NOT_MONOTONE;
+        }
+        if (q && t < n) {
+            int32_t c = q[t];
+            if (c < 0 || c >= n) err |= E_RANGE;
+            else qinv[c] = (int32_t)t;
+            if (c != t) flags |= F_NOT_MONOTONE;
+        }
+    }
+    if (err) atomicOr(&hdr->err, err);   // error path only
+    uint64_t f = ballot(flags != 0);
+    if (f && lane_id() == __ffsll((long long)f) - 1) atomicOr(&hdr->flags, F_NOT_MONOTONE);
+}
+
+__global__ __launch_bounds__(256) void k_perm_check(const int32_t *__restrict__ p,
+                                                   const int32_t *__restrict__ q, int64_t m,
+                                                   int64_t n, const int32_t *__restrict__ pinv,
+                                                   const int32_t *__restrict__ qinv, DevHdr *hdr) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t hi = m > n ? m : n;
+    bool bad = false;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < hi; t += stride) {
+        if (t < m) {
+            int32_t i = pinv[t];
+            bad |= !(i >= 0 && i < m && p[i] == t);
+        }
+        if (q && t < n) {
+            int32_t j = qinv[t];
+            bad |= !(j >= 0 && j < n && q[j] == t);
+        }
+    }
+    uint64_t b = ballot(bad);
+    if (b && lane_id() == __ffsll((long long)b) - 1) atomicOr(&hdr->err, E_NOTPERM);
+}
+
+// Rows of at most 16 entries: one lane per SOURCE row r, streamed in order
+// (coalesced reads of A, local reads of qinv for banded matrices), written
+// to output row pinv[r] after an in-register sort of the mapped columns.
+template <typename PT, typename VT>
+__global__ __launch_bounds__(256) void k_perm_fill_short(
+    const PT *__restrict__ arow, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
+    const int32_t *__restrict__ pinv, const int32_t *__restrict__ cmap, const PT *__restrict__ crow,
+    int32_t *__restrict__ ccol, VT *__restrict__ cval, int64_t m, int64_t n, int sorted,
+    const DevHdr *hdr) {
+    if (hdr->err) return;
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const int64_t s = arow[r];
+    const int len = (int)(arow[r + 1] - s);
+    if (len == 0 || len > THREAD_MAX) return;
+    const int64_t d = crow[pinv[r]];
+    if (len <= 4) {
+        int32_t k[4];
+        VT v[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            k[i] = INT32_MAX;
+            v[i] = VT(0);
+            if (i < len) {
+                k[i] = cmap[clampc(acol[s + i], n)];
+                v[i] = aval[s + i];
+            }
+        }
+        sort_store_regs<4, VT>(k, v, len, sorted, ccol + d, cval + d);
+        return;
+    }
+    int32_t k[16];
+    VT v[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        k[i] = INT32_MAX;
+        v[i] = VT(0);
+        if (i < len) {
+            k[i] = cmap[clampc(acol[s + i], n)];
+            v[i] = aval[s + i];
+        }
+    }
+    sort_store_regs<16, VT>(k, v, len, sorted, ccol + d, cval + d);
+}
+
+// Longer rows: output row i is row p[i] of A with columns mapped (pull).
+template <typename PT, typename VT>
+struct LoadPerm {
+    const PT *arow;
+    const int32_t *acol;
+    const VT *aval;
+    const int32_t *p;
+    const int32_t *cmap;
+    int64_t n;
+    __device__ __forceinline__ int64_t base(int64_t row) const { return arow[p[row]]; }
+    __device__ __forceinline__ void get(int64_t b, int64_t k, int32_t &kk, VT &vv) const {
+        kk = cmap[clampc(acol[b + k], n)];
+        vv = aval[b + k];
+    }
+};
+
+hp_status_t perm_check_args(hp_handle_t h, const hp_csr_t *A, const int32_t *p, const int32_t *q,
+                            const hp_csr_t *C) {
+    hp_status_t st = check_csr_args(h, A, "A");
+    if (st) return st;
+    if (!C) return fail(h, HP_ERR_INVALID_ARG, "C is NULL");
+    if (!q && A->nrows != A->ncols) return fail(h, HP_ERR_SHAPE, "symmetric permute needs a square A");
+    if (C->nrows != A->nrows || C->ncols != A->ncols)
+        return fail(h, HP_ERR_SHAPE, "C must have A's shape");
+    if (C->ptr_type != A->ptr_type || C->val_type != A->val_type)
+        return fail(h, HP_ERR_INVALID_ARG, "C must have A's ptr_type and val_type");
+    if (!C->rowptr) return fail(h, HP_ERR_INVALID_ARG, "C->rowptr is NULL");
+    if (A->nrows > 0 && !p) return fail(h, HP_ERR_INVALID_ARG, "p is NULL");
+    return HP_OK;
+}
+
+template <typename PT>
+hp_status_t perm_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, const int32_t *q,
+                        hp_csr_t *C, void *ws, size_t ws_bytes, hp_plan_info_t *info) {
+    const int64_t m = A->nrows, n = A->ncols;
+    const bool sym = q == nullptr;
+    Carve need(nullptr);
+    perm_layout(need, m, n, sym);
+    if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "permute plan workspace too small");
+    const size_t ps = sizeof(PT), vs = val_size(A->val_type);
+    const void *ins[] = {A->rowptr, A->col, A->val, p, q};
+    const size_t insz[] = {(size_t)(m + 1) * ps, (size_t)A->nnz * 4, (size_t)A->nnz * vs,
+                           (size_t)m * 4, q ? (size_t)n * 4 : 0};
+    for (int k = 0; k < 5; k++)
+        if (overlaps(C->rowptr, (m + 1) * ps, ins[k], insz[k]) || overlaps(ws, ws_bytes, ins[k], insz[k]))
+            return fail(h, HP_ERR_ALIAS, "output or workspace overlaps an input");
+    if (overlaps(C->rowptr, (m + 1) * ps, ws, ws_bytes))
+        return fail(h, HP_ERR_ALIAS, "C->rowptr overlaps the workspace");
+    Carve c(ws);
+    PermLayout L = perm_layout(c, m, n, sym);
+    hipStream_t s = h->stream;
+    stage_begin(h);
+    hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, scan_tiles(m));
+    const int64_t hi = m > n ? m : n;
+    const int grid = (int)std::min<int64_t>((hi + 255) / 256 > 0 ? (hi + 255) / 256 : 1, 16384);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_perm_prepare<PT>, dim3(grid), dim3(256), 0, s, (const PT *)A->rowptr, p, q,
+                           m, n, L.pinv, L.qinv, L.cnt, L.hdr);
+        stage_mark(h, "perm.prepare");
+        hipLaunchKernelGGL(k_perm_check, dim3(grid), dim3(256), 0, s, p, q, m, n, L.pinv, L.qinv, L.hdr);
+        stage_mark(h, "perm.check");
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        e = launch_scan_counts<PT>(s, L.cnt, (PT *)C->rowptr, m, L.hdr, 0, L.tiles, 1, L.lists, m);
+        stage_mark(h, "perm.scan");
+    }
+    if (e == hipSuccess) e = readback_hdr(h, L.hdr);
+    stage_end(h);
+    if (e != hipSuccess) return hip_check(h, e, "permute plan");
+    const DevHdr &H = *h->host_hdr;
+    hp_status_t st = status_from_err(h, H.err, "permute");
+    if (st) return st;
+    C->nnz = (int64_t)H.total[0];
+    if (info) {
+        *info = hp_plan_info_t{};
+        info->nnz_out = C->nnz;
+        info->map_monotone = (H.flags & F_NOT_MONOTONE) ? 0 : 1;
+        info->op = 1;
+        for (int b = 0; b < NBINS; b++) {
+            info->rows_sorted[b] = H.bin_cnt[b];
+            info->class_elems[b] = (int64_t)H.bin_elems[b];
+        }
+        info->exec_ws_bytes = seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], vs);
+    }
+    return HP_OK;
+}
+
+template <typename PT, typename VT>
+hp_status_t perm_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, const int32_t *q,
+                        hp_csr_t *C, void *ws, size_t ws_bytes, const hp_plan_info_t *info, void *xws,
+                        size_t xws_bytes) {
+    const int64_t m = A->nrows, n = A->ncols;
+    const bool sym = q == nullptr;
+    Carve need(nullptr);
+    perm_layout(need, m, n, sym);
+    if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "permute workspace too small");
+    if (!info || info->op != 1) return fail(h, HP_ERR_INVALID_ARG, "info is not from hp_permute_plan");
+    if (xws_bytes < info->exec_ws_bytes || (info->exec_ws_bytes && !xws))
+        return fail(h, HP_ERR_WORKSPACE, "permute exec workspace too small");
+    if (C->nnz != A->nnz) return fail(h, HP_ERR_INVALID_ARG, "C->nnz must equal nnz(A) (set by plan)");
+    if (C->nnz > 0 && (!C->col || !C->val)) return fail(h, HP_ERR_INVALID_ARG, "C->col/val is NULL");
+    const size_t vs = sizeof(VT);
+    const void *ins[] = {A->rowptr, A->col, A->val, p, q, ws, xws, C->rowptr};
+    const size_t insz[] = {(size_t)(m + 1) * sizeof(PT), (size_t)A->nnz * 4, (size_t)A->nnz * vs,
+                           (size_t)m * 4, q ? (size_t)n * 4 : 0, ws_bytes, xws_bytes,
+                           (size_t)(m + 1) * sizeof(PT)};
+    for (int k = 0; k < 8; k++)
+        if (overlaps(C->col, (size_t)C->nnz * 4, ins[k], insz[k]) ||
+            overlaps(C->val, (size_t)C->nnz * vs, ins[k], insz[k]))
+            return fail(h, HP_ERR_ALIAS, "C->col/val overlaps an input or workspace");
+    Carve c(ws);
+    PermLayout L = perm_layout(c, m, n, sym);
+    hipStream_t s = h->stream;
+    const int sorted = info->map_monotone;
+    stage_begin(h);
+    if (m > 0) {
+        hipLaunchKernelGGL((k_perm_fill_short<PT, VT>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                           (const PT *)A->rowptr, A->col, (const VT *)A->val, L.pinv, L.qinv,
+                           (const PT *)C->rowptr, C->col, (VT *)C->val, m, n, sorted, L.hdr);
+        stage_mark(h, "perm.fill_short");
+    }
+    uint32_t cnt[NBINS];
+    for (int b = 0; b < NBINS; b++) cnt[b] = (uint32_t)info->rows_sorted[b];
+    LoadPerm<PT, VT> ld{(const PT *)A->rowptr, A->col, (const VT *)A->val, p, L.qinv, n};
+    hipError_t e = launch_seg_classes<PT, VT, LoadPerm<PT, VT>>(
+        s, (const PT *)C->rowptr, C->col, (VT *)C->val, L.lists, m, cnt, ld, sorted != 0,
+        key_bits(n), false, xws, (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, false);
+    stage_mark(h, "perm.fill_long");
+    stage_end(h);
+    return hip_check(h, e == hipSuccess ? hipGetLastError() : e, "permute exec");
+}
+
+}  // namespace
+
+extern "C" hp_status_t hp_permute_workspace(hp_handle_t h, const hp_csr_t *A, size_t *bytes) {
+    if (!h || !bytes) return HP_ERR_INVALID_ARG;
+    hp_status_t st = check_csr_args(h, A, "A");
+    if (st) return st;
+    Carve c(nullptr);
+    perm_layout(c, A->nrows, A->ncols, false);
+    *bytes = c.size();
+    return HP_OK;
+}
+
+extern "C" hp_status_t hp_permute_plan(hp_handle_t h, const hp_csr_t *A, const int32_t *p,
+                                       const int32_t *q, hp_csr_t *C, void *ws, size_t ws_bytes,
+                                       hp_plan_info_t *info) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    hp_status_t st = perm_check_args(h, A, p, q, C);
+    if (st) return st;
+    if (A->ptr_type == HP_IDX_I32) return perm_plan_t<int32_t>(h, A, p, q, C, ws, ws_bytes, info);
+    return perm_plan_t<int64_t>(h, A, p, q, C, ws, ws_bytes, info);
+}
+
+extern "C" hp_status_t hp_permute_exec(hp_handle_t h, const hp_csr_t *A, const int32_t *p,
+                                       const int32_t *q, hp_csr_t *C, void *ws, size_t ws_bytes,
+                                       const hp_plan_info_t *info, void *xws, size_t xws_bytes) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    hp_status_t st = perm_check_args(h, A, p, q, C);
+    if (st) return st;
+    const bool p64 = A->ptr_type == HP_IDX_I64, v64 = A->val_type == HP_VAL_F64;
+    if (!p64 && !v64) return perm_exec_t<int32_t, uint32_t>(h, A, p, q, C, ws, ws_bytes, info, xws, xws_bytes);
+    if (!p64 && v64) return perm_exec_t<int32_t, uint64_t>(h, A, p, q, C, ws, ws_bytes, info, xws, xws_bytes);
+    if (p64 && !v64) return perm_exec_t<int64_t, uint32_t>(h, A, p, q, C, ws, ws_bytes, info, xws, xws_bytes);
+    return perm_exec_t<int64_t, uint64_t>(h, A, p, q, C, ws, ws_bytes, info, xws, xws_bytes);
+}

@@ -1,0 +1,219 @@
+"""Thin ctypes binding of libhipperm.so (include/hipperm.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch provides device memory (torch.empty on the GPU) and the stream
+(torch.cuda.current_stream()).  When the built library is missing this
+module raises at import time; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhipperm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2509_20776_amd.build` "
+                      "(the library has no non-GPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+STATUS = {0: "HP_OK", 1: "HP_ERR_INVALID_ARG", 2: "HP_ERR_INDEX_RANGE", 3: "HP_ERR_NOT_PERMUTATION",
+          4: "HP_ERR_DUPLICATE_INDEX", 5: "HP_ERR_NOT_CANONICAL", 6: "HP_ERR_SHAPE",
+          7: "HP_ERR_OVERFLOW", 8: "HP_ERR_WORKSPACE", 9: "HP_ERR_CAPACITY", 10: "HP_ERR_HIP",
+          11: "HP_ERR_ALIAS", 12: "HP_ERR_TIMEOUT", 13: "HP_ERR_REJECTED"}
+OPS = {"second": 0, "plus": 1, "replace": 2}
+
+
+class HPError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+        super().__init__(f"{self.name}: {msg}")
+
+
+class hp_csr_t(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("ptr_type", ctypes.c_int32), ("val_type", ctypes.c_int32),
+                ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class hp_plan_info_t(ctypes.Structure):
+    _fields_ = [("nnz_out", ctypes.c_int64), ("exec_ws_bytes", ctypes.c_size_t),
+                ("map_monotone", ctypes.c_int32), ("op", ctypes.c_int32),
+                ("rows_sorted", ctypes.c_int64 * 4), ("class_elems", ctypes.c_int64 * 4),
+                ("aux", ctypes.c_int64 * 4)]
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+_CSRP = ctypes.POINTER(hp_csr_t)
+_INFOP = ctypes.POINTER(hp_plan_info_t)
+
+
+def _sig(name, args, res=ctypes.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+hp_create = _sig("hp_create", [ctypes.POINTER(_P), ctypes.c_int])
+hp_destroy = _sig("hp_destroy", [_P])
+hp_set_stream = _sig("hp_set_stream", [_P, _P])
+hp_status_string = _sig("hp_status_string", [ctypes.c_int], ctypes.c_char_p)
+hp_last_error = _sig("hp_last_error", [_P], ctypes.c_char_p)
+hp_enable_timing = _sig("hp_enable_timing", [_P, ctypes.c_int])
+hp_stage_times = _sig("hp_stage_times", [_P, ctypes.POINTER(ctypes.c_float),
+                                         ctypes.POINTER(ctypes.c_char_p), ctypes.c_int])
+hp_permute_workspace = _sig("hp_permute_workspace", [_P, _CSRP, ctypes.POINTER(_SZ)])
+hp_permute_plan = _sig("hp_permute_plan", [_P, _CSRP, _P, _P, _CSRP, _P, _SZ, _INFOP])
+hp_permute_exec = _sig("hp_permute_exec", [_P, _CSRP, _P, _P, _CSRP, _P, _SZ, _INFOP, _P, _SZ])
+
+@dataclass
+class CSR:
+    nrows: int
+    ncols: int
+    rowptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+
+def _ptr_type(t):
+    if t.dtype == torch.int32:
+        return 0
+    if t.dtype == torch.int64:
+        return 1
+    raise HPError(1, f"rowptr dtype {t.dtype} not int32/int64")
+
+
+def _val_type(t):
+    if t.dtype == torch.float32:
+        return 0
+    if t.dtype == torch.float64:
+        return 1
+    raise HPError(1, f"value dtype {t.dtype} not float32/float64")
+
+
+def _dptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise HPError(1, "tensor is not on the GPU")
+    if not t.is_contiguous():
+        raise HPError(1, "tensor is not contiguous")
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else ctypes.c_void_p(t.data_ptr() or 0)
+
+
+def to_csr_t(A) -> hp_csr_t:
+    return hp_csr_t(A.nrows, A.ncols, int(A.col.numel()), _ptr_type(A.rowptr), _val_type(A.val),
+                    _dptr(A.rowptr), _dptr(A.col), _dptr(A.val))
+
+
+def _idx(x: Optional[torch.Tensor]):
+    if x is None:
+        return None
+    if x.dtype != torch.int32:
+        raise HPError(1, "index vectors must be int32")
+    return _dptr(x)
+
+
+class Handle:
+    """One library handle on one device; work goes on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = _P()
+        st = hp_create(ctypes.byref(h), device)
+        if st != 0:
+            raise HPError(st, "hp_create failed")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            hp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        hp_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def check(self, st):
+        if st != 0:
+            raise HPError(st, (hp_last_error(self.h) or b"").decode())
+
+    def timing(self, on: bool):
+        self.check(hp_enable_timing(self.h, 1 if on else 0))
+
+    def stage_times(self):
+        ms = (ctypes.c_float * 64)()
+        nm = (ctypes.c_char_p * 64)()
+        k = hp_stage_times(self.h, ms, nm, 64)
+        return [(nm[i].decode(), float(ms[i])) for i in range(k)]
+
+    def _alloc(self, nbytes):
+        return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    # ---- permute -----------------------------------------------------------
+    def permute_plan(self, A, p, q=None, ws=None):
+        """Plan C = P A Q^T; returns (C with rowptr filled, ws, info)."""
+        self._stream()
+        Ac = to_csr_t(A)
+        need = _SZ(0)
+        self.check(hp_permute_workspace(self.h, ctypes.byref(Ac), ctypes.byref(need)))
+        if ws is None or ws.numel() < need.value:
+            ws = self._alloc(need.value)
+        rowptr = torch.empty(A.nrows + 1, dtype=A.rowptr.dtype, device=A.rowptr.device)
+        Cc = hp_csr_t(A.nrows, A.ncols, 0, Ac.ptr_type, Ac.val_type, _dptr(rowptr), None, None)
+        info = hp_plan_info_t()
+        self.check(hp_permute_plan(self.h, ctypes.byref(Ac), _idx(p), _idx(q), ctypes.byref(Cc),
+                                   _dptr(ws), ws.numel(), ctypes.byref(info)))
+        C = CSR(A.nrows, A.ncols, rowptr,
+                torch.empty(Cc.nnz, dtype=torch.int32, device=A.col.device),
+                torch.empty(Cc.nnz, dtype=A.val.dtype, device=A.val.device))
+        return C, ws, info
+
+    def permute_exec(self, A, p, q, C, ws, info, xws=None):
+        self._stream()
+        Ac = to_csr_t(A)
+        Cc = to_csr_t(C)
+        if info.exec_ws_bytes and (xws is None or xws.numel() < info.exec_ws_bytes):
+            xws = self._alloc(info.exec_ws_bytes)
+        self.check(hp_permute_exec(self.h, ctypes.byref(Ac), _idx(p), _idx(q), ctypes.byref(Cc),
+                                   _dptr(ws), ws.numel(), ctypes.byref(info),
+                                   _dptr(xws) if xws is not None else None,
+                                   xws.numel() if xws is not None else 0))
+        return C
+
+    def permute(self, A, p, q=None):
+        C, ws, info = self.permute_plan(A, p, q)
+        return self.permute_exec(A, p, q, C, ws, info)
+
+
+_default = {}
+
+
+def handle(device: int = 0) -> Handle:
+    if device not in _default:
+        _default[device] = Handle(device)
+    return _default[device]
+
+
+def permute(A, p, q=None, device: int = 0) -> CSR:
+    """C = P A Q^T with C[i, j] = A[p[i], q[j]]; q=None gives P A P^T."""
+    return handle(device).permute(A, p, q)
