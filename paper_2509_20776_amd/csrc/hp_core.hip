@@ -230,6 +230,7 @@ size_t scan_tiles(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) 
 __device__ __forceinline__ void classify_append(int64_t row, int64_t len, bool valid, int mode,
                                                 DevHdr *hdr, uint32_t *lists, int64_t cap,
                                                 uint64_t *goff) {
+    // mode 1: rows longer than THREAD_MAX; mode 2: every row of >= 2 entries
     int bin = -1;
     if (valid && len >= 2) {
         if (len <= THREAD_MAX) bin = (mode == 2) ? BIN_THREAD : -1;
@@ -267,7 +268,8 @@ __device__ __forceinline__ void classify_append(int64_t row, int64_t len, bool v
 template <typename PT>
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_counts(
     const int32_t *__restrict__ cnt, PT *__restrict__ out, int64_t n, DevHdr *hdr, int slot,
-    uint64_t *tile_state, int classify, uint32_t *lists, int64_t cap, uint64_t *goff) {
+    uint64_t *tile_state, int classify, uint32_t *lists, int64_t cap, uint64_t *goff,
+    const int32_t *__restrict__ force) {
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_wave[SCAN_BLOCK / WAVE];
     __shared__ uint64_t s_excl;
@@ -344,9 +346,19 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_counts(
         if (sizeof(PT) == 4 && total > (uint64_t)INT32_MAX) raise_err(hdr, E_OVERFLOW);
     }
     if (classify) {
+        // mode 3: every row when the column map is not monotone, otherwise
+        // only the rows flagged in `force` (rows assembled out of order)
+        int mode = classify;
+        bool all = true;
+        if (mode == 3) {
+            all = (ld_agent(&hdr->flags) & F_NOT_MONOTONE) != 0;
+            mode = 2;
+        }
 #pragma unroll
-        for (int k = 0; k < SCAN_ITEMS; k++)
-            classify_append(base + k, v[k], base + k < n, classify, hdr, lists, cap, goff);
+        for (int k = 0; k < SCAN_ITEMS; k++) {
+            bool want = base + k < n && (all || force[base + k] != 0);
+            classify_append(base + k, v[k], want, mode, hdr, lists, cap, goff);
+        }
     }
 }
 
@@ -361,7 +373,7 @@ __global__ void k_scan_empty(PT *out, DevHdr *hdr, int slot) {
 template <typename PT>
 hipError_t launch_scan_counts(hipStream_t s, const int32_t *cnt, PT *out, int64_t n, DevHdr *hdr,
                               int slot, uint64_t *tile_state, int classify, uint32_t *bin_lists,
-                              int64_t bin_cap) {
+                              int64_t bin_cap, const int32_t *force) {
     if (n == 0) {
         hipLaunchKernelGGL(k_scan_empty<PT>, dim3(1), dim3(64), 0, s, out, hdr, slot);
         return hipGetLastError();
@@ -369,13 +381,15 @@ hipError_t launch_scan_counts(hipStream_t s, const int32_t *cnt, PT *out, int64_
     int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     uint64_t *goff = bin_lists ? reinterpret_cast<uint64_t *>(bin_lists + NBINS * bin_cap) : nullptr;
     hipLaunchKernelGGL(k_scan_counts<PT>, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, cnt, out, n,
-                       hdr, slot, tile_state, classify, bin_lists, bin_cap, goff);
+                       hdr, slot, tile_state, classify, bin_lists, bin_cap, goff, force);
     return hipGetLastError();
 }
 
 template hipError_t launch_scan_counts<int32_t>(hipStream_t, const int32_t *, int32_t *, int64_t,
-                                                DevHdr *, int, uint64_t *, int, uint32_t *, int64_t);
+                                                DevHdr *, int, uint64_t *, int, uint32_t *, int64_t,
+                                                const int32_t *);
 template hipError_t launch_scan_counts<int64_t>(hipStream_t, const int32_t *, int64_t *, int64_t,
-                                                DevHdr *, int, uint64_t *, int, uint32_t *, int64_t);
+                                                DevHdr *, int, uint64_t *, int, uint32_t *, int64_t,
+                                                const int32_t *);
 
 }  // namespace hp

@@ -171,12 +171,15 @@ hipError_t launch_init_hdr(hipStream_t s, DevHdr *h, uint64_t *tile_state, size_
 hipError_t readback_hdr(hp_handle_t h, DevHdr *dev);
 
 // Exclusive scan of n counts (int32 in) into out (PT, n+1 entries); out[n]
-// = total; hdr->total[slot] = total.  tile_state must hold scan_tiles(n)
+// = total; hdr->total[slot] = total.  classify: 0 none, 1 rows longer than
+// THREAD_MAX, 2 all rows of >= 2 entries, 3 all rows if hdr->flags has
+// F_NOT_MONOTONE else only rows with force[i] != 0 (class lists, see
+// hp_segsort.hpp).  tile_state must hold scan_tiles(n)
 // zeroed words and hdr->ticket[slot] must be zero (launch_init_hdr does both).
 size_t scan_tiles(int64_t n);
 template <typename PT>
 hipError_t launch_scan_counts(hipStream_t s, const int32_t *cnt, PT *out, int64_t n, DevHdr *hdr,
                               int slot, uint64_t *tile_state, int classify, uint32_t *bin_lists,
-                              int64_t bin_cap);
+                              int64_t bin_cap, const int32_t *force = nullptr);
 
 }  // namespace hp

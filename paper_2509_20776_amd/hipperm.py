@@ -75,6 +75,9 @@ hp_stage_times = _sig("hp_stage_times", [_P, ctypes.POINTER(ctypes.c_float),
 hp_permute_workspace = _sig("hp_permute_workspace", [_P, _CSRP, ctypes.POINTER(_SZ)])
 hp_permute_plan = _sig("hp_permute_plan", [_P, _CSRP, _P, _P, _CSRP, _P, _SZ, _INFOP])
 hp_permute_exec = _sig("hp_permute_exec", [_P, _CSRP, _P, _P, _CSRP, _P, _SZ, _INFOP, _P, _SZ])
+hp_spref_workspace = _sig("hp_spref_workspace", [_P, _CSRP, _I64, _I64, ctypes.POINTER(_SZ)])
+hp_spref_plan = _sig("hp_spref_plan", [_P, _CSRP, _P, _I64, _P, _I64, _CSRP, _P, _SZ, _INFOP])
+hp_spref_exec = _sig("hp_spref_exec", [_P, _CSRP, _P, _I64, _P, _I64, _CSRP, _P, _SZ, _INFOP, _P, _SZ])
 
 @dataclass
 class CSR:
@@ -204,6 +207,41 @@ class Handle:
         C, ws, info = self.permute_plan(A, p, q)
         return self.permute_exec(A, p, q, C, ws, info)
 
+    # ---- spref -------------------------------------------------------------
+    def spref_plan(self, A, I, J, ws=None):
+        """Plan C = A(I, J); returns (C with rowptr filled, ws, info)."""
+        self._stream()
+        Ac = to_csr_t(A)
+        nI, nJ = int(I.numel()), int(J.numel())
+        need = _SZ(0)
+        self.check(hp_spref_workspace(self.h, ctypes.byref(Ac), nI, nJ, ctypes.byref(need)))
+        if ws is None or ws.numel() < need.value:
+            ws = self._alloc(need.value)
+        rowptr = torch.empty(nI + 1, dtype=A.rowptr.dtype, device=A.rowptr.device)
+        Cc = hp_csr_t(nI, nJ, 0, Ac.ptr_type, Ac.val_type, _dptr(rowptr), None, None)
+        info = hp_plan_info_t()
+        self.check(hp_spref_plan(self.h, ctypes.byref(Ac), _idx(I), nI, _idx(J), nJ, ctypes.byref(Cc),
+                                 _dptr(ws), ws.numel(), ctypes.byref(info)))
+        C = CSR(nI, nJ, rowptr, torch.empty(Cc.nnz, dtype=torch.int32, device=A.col.device),
+                torch.empty(Cc.nnz, dtype=A.val.dtype, device=A.val.device))
+        return C, ws, info
+
+    def spref_exec(self, A, I, J, C, ws, info, xws=None):
+        self._stream()
+        Ac = to_csr_t(A)
+        Cc = to_csr_t(C)
+        if info.exec_ws_bytes and (xws is None or xws.numel() < info.exec_ws_bytes):
+            xws = self._alloc(info.exec_ws_bytes)
+        self.check(hp_spref_exec(self.h, ctypes.byref(Ac), _idx(I), int(I.numel()), _idx(J),
+                                 int(J.numel()), ctypes.byref(Cc), _dptr(ws), ws.numel(),
+                                 ctypes.byref(info), _dptr(xws) if xws is not None else None,
+                                 xws.numel() if xws is not None else 0))
+        return C
+
+    def spref(self, A, I, J):
+        C, ws, info = self.spref_plan(A, I, J)
+        return self.spref_exec(A, I, J, C, ws, info)
+
 
 _default = {}
 
@@ -217,3 +255,8 @@ def handle(device: int = 0) -> Handle:
 def permute(A, p, q=None, device: int = 0) -> CSR:
     """C = P A Q^T with C[i, j] = A[p[i], q[j]]; q=None gives P A P^T."""
     return handle(device).permute(A, p, q)
+
+
+def spref(A, I, J, device: int = 0) -> CSR:
+    """C = A(I, J) with C[i, j] = A[I[i], J[j]]; repeated/unordered indices allowed."""
+    return handle(device).spref(A, I, J)
