@@ -112,10 +112,13 @@ const char *hp_status_string(hp_status_t s);
 const char *hp_last_error(hp_handle_t h);
 
 /* Per-stage device timing: when enabled, every plan/exec records HIP events
- * around each kernel stage; hp_stage_times copies up to `cap` stage
- * durations (ms) and their names of the last plan+exec pair. */
+ * on the handle's stream around each kernel stage (no extra synchronisation).
+ * hp_stage_times waits for the last recorded event, then reports for up to
+ * `cap` distinct stage names the total milliseconds and the number of
+ * launches since the previous call, and clears the record.  Returns the
+ * number of stages written; names point to static strings. */
 hp_status_t hp_enable_timing(hp_handle_t h, int enable);
-int hp_stage_times(hp_handle_t h, float *ms, const char **names, int cap);
+int hp_stage_times(hp_handle_t h, float *ms_total, int *count, const char **names, int cap);
 
 /* Canonical-CSR check (rowptr monotone, columns in range, strictly
  * ascending in each row).  Returns HP_OK, HP_ERR_NOT_CANONICAL or

@@ -84,33 +84,29 @@ hp_status_t check_csr_args(hp_handle_t h, const hp_csr_t *A, const char *name) {
 }
 
 // ---- stage timing ---------------------------------------------------------
+// Events are recorded on the handle's stream between kernel stages and are
+// only resolved by hp_stage_times(), so timing adds no synchronisation.
+static hipEvent_t next_event(hp_handle_t h) {
+    if (h->ev_used == h->ev.size()) {
+        hipEvent_t e;
+        hipEventCreate(&e);
+        h->ev.push_back(e);
+    }
+    return h->ev[h->ev_used++];
+}
 void stage_begin(hp_handle_t h) {
     if (!h->timing) return;
-    h->nstage = 0;
-    h->stage_names.clear();
-    if (h->ev.empty()) {
-        h->ev.resize(64);
-        for (auto &e : h->ev) hipEventCreate(&e);
-    }
-    hipEventRecord(h->ev[0], h->stream);
+    h->ev_cur = next_event(h);
+    hipEventRecord(h->ev_cur, h->stream);
 }
 void stage_mark(hp_handle_t h, const char *name) {
-    if (!h->timing || h->nstage + 1 >= (int)h->ev.size()) return;
-    h->nstage++;
-    hipEventRecord(h->ev[h->nstage], h->stream);
-    h->stage_names.push_back(name);
-}
-void stage_end(hp_handle_t h) {
     if (!h->timing) return;
-    hipEventSynchronize(h->ev[h->nstage]);
-    for (int k = 0; k < h->nstage && h->nstage_out < 64; k++) {
-        float ms = 0;
-        hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]);
-        h->stage_ms[h->nstage_out] = ms;
-        h->stage_name_out[h->nstage_out] = h->stage_names[k];
-        h->nstage_out++;
-    }
+    hipEvent_t e = next_event(h);
+    hipEventRecord(e, h->stream);
+    h->recs.push_back({name, h->ev_cur, e});
+    h->ev_cur = e;
 }
+void stage_end(hp_handle_t h) { (void)h; }
 
 }  // namespace hp
 
@@ -148,18 +144,38 @@ extern "C" const char *hp_last_error(hp_handle_t h) { return h ? h->last_error.c
 extern "C" hp_status_t hp_enable_timing(hp_handle_t h, int enable) {
     if (!h) return HP_ERR_INVALID_ARG;
     h->timing = enable != 0;
-    h->nstage_out = 0;
+    h->recs.clear();
+    h->ev_used = 0;
     return HP_OK;
 }
 
-extern "C" int hp_stage_times(hp_handle_t h, float *ms, const char **names, int cap) {
+extern "C" int hp_stage_times(hp_handle_t h, float *ms, int *count, const char **names, int cap) {
     if (!h) return 0;
-    int n = std::min(cap, h->nstage_out);
-    for (int k = 0; k < n; k++) {
-        if (ms) ms[k] = h->stage_ms[k];
-        if (names) names[k] = h->stage_name_out[k];
+    std::vector<const char *> nm;
+    std::vector<float> tot;
+    std::vector<int> cnt;
+    if (!h->recs.empty()) hipEventSynchronize(h->recs.back().e1);
+    for (auto &r : h->recs) {
+        float t = 0;
+        hipEventElapsedTime(&t, r.e0, r.e1);
+        size_t k = 0;
+        while (k < nm.size() && std::strcmp(nm[k], r.name) != 0) k++;
+        if (k == nm.size()) {
+            nm.push_back(r.name);
+            tot.push_back(0);
+            cnt.push_back(0);
+        }
+        tot[k] += t;
+        cnt[k] += 1;
     }
-    h->nstage_out = 0;
+    h->recs.clear();
+    h->ev_used = 0;
+    int n = std::min<int>(cap, (int)nm.size());
+    for (int k = 0; k < n; k++) {
+        if (ms) ms[k] = tot[k];
+        if (count) count[k] = cnt[k];
+        if (names) names[k] = nm[k];
+    }
     return n;
 }
 
@@ -173,6 +189,15 @@ __global__ void k_clear_words(uint32_t *p, size_t n) {
     size_t n4 = n / 4;
     for (size_t k = i; k < n4; k += stride) reinterpret_cast<uint4 *>(p)[k] = z;
     for (size_t k = n4 * 4 + i; k < n; k += stride) p[k] = 0;
+}
+
+__global__ void k_fill_words(uint32_t *p, size_t n, uint32_t v) {
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    uint4 z = make_uint4(v, v, v, v);
+    size_t n4 = n / 4;
+    for (size_t k = i; k < n4; k += stride) reinterpret_cast<uint4 *>(p)[k] = z;
+    for (size_t k = n4 * 4 + i; k < n; k += stride) p[k] = v;
 }
 
 __global__ void k_init_hdr(DevHdr *h, uint64_t *tile_state, size_t ntiles) {
@@ -195,6 +220,13 @@ hipError_t launch_clear_words(hipStream_t s, void *p, size_t nwords32) {
     if (nwords32 == 0) return hipSuccess;
     hipLaunchKernelGGL(k_clear_words, dim3(grid_for(nwords32 / 4 + 1, 256, 8192)), dim3(256), 0, s,
                        (uint32_t *)p, nwords32);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_words(hipStream_t s, void *p, size_t nwords32, uint32_t v) {
+    if (nwords32 == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_words, dim3(grid_for(nwords32 / 4 + 1, 256, 8192)), dim3(256), 0, s,
+                       (uint32_t *)p, nwords32, v);
     return hipGetLastError();
 }
 
@@ -226,54 +258,49 @@ constexpr uint32_t SPIN_LIMIT = 1u << 24;
 
 size_t scan_tiles(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
 
-// Wave-aggregated append of `row` to its class list.
-__device__ __forceinline__ void classify_append(int64_t row, int64_t len, bool valid, int mode,
-                                                DevHdr *hdr, uint32_t *lists, int64_t cap,
-                                                uint64_t *goff) {
-    // mode 1: rows longer than THREAD_MAX; mode 2: every row of >= 2 entries
-    int bin = -1;
-    if (valid && len >= 2) {
-        if (len <= THREAD_MAX) bin = (mode == 2) ? BIN_THREAD : -1;
-        else if (len <= WAVE_MAX) bin = BIN_WAVE;
-        else if (len <= BLOCK_MAX) bin = BIN_BLOCK;
-        else bin = BIN_GLOBAL;
-    }
-    const uint64_t lt = lanemask_lt();
-#pragma unroll
-    for (int b = 0; b < NBINS; b++) {
-        uint64_t m = ballot(bin == b);
-        if (!m) continue;
-        int leader = __ffsll((long long)m) - 1;
-        uint32_t base = 0;
-        uint64_t ebase = 0;
-        uint64_t elen = (bin == b) ? (uint64_t)len : 0;
-        uint64_t esum = wave_sum(elen);
-        uint64_t epre = wave_incl_scan(elen) - elen;
-        if (lane_id() == leader) {
-            base = atomicAdd(&hdr->bin_cnt[b], (uint32_t)__popcll(m));
-            ebase = atomicAdd((unsigned long long *)&hdr->bin_elems[b], (unsigned long long)esum);
-        }
-        base = __shfl(base, leader, WAVE);
-        ebase = __shfl(ebase, leader, WAVE);
-        if (bin == b) {
-            uint32_t pos = base + (uint32_t)__popcll(m & lt);
-            if (pos < cap) {
-                lists[(int64_t)b * cap + pos] = (uint32_t)row;
-                if (b == BIN_GLOBAL) goff[pos] = ebase + epre;
-            }
+// Sort class of a row of `len` entries under classification `mode`:
+//   1  rows longer than 4 (shorter rows are sorted by the producer itself)
+//   2  every row of >= 2 entries
+//   3  rows longer than SMALL_MAX when `all` (shorter ones are sorted by
+//      k_sort_small), else only flagged rows
+__device__ __forceinline__ int class_of(int64_t len, int mode, bool all, bool flagged) {
+    if (len < 2) return -1;
+    if (mode == 1 && len <= 4) return -1;
+    if (mode == 3) {
+        if (all) {
+            if (len <= SMALL_MAX) return -1;
+        } else if (!flagged) {
+            return -1;
         }
     }
+    if (len <= THREAD_MAX) return BIN_THREAD;
+    if (len <= WAVE_MAX) return BIN_WAVE;
+    if (len <= BLOCK_MAX) return BIN_BLOCK;
+    return BIN_GLOBAL;
 }
 
 template <typename PT>
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_counts(
     const int32_t *__restrict__ cnt, PT *__restrict__ out, int64_t n, DevHdr *hdr, int slot,
     uint64_t *tile_state, int classify, uint32_t *lists, int64_t cap, uint64_t *goff,
-    const int32_t *__restrict__ force) {
+    const int32_t *__restrict__ force, const uint32_t *__restrict__ nmslots) {
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_wave[SCAN_BLOCK / WAVE];
     __shared__ uint64_t s_excl;
-    if (threadIdx.x == 0) s_tile = atomicAdd(&hdr->ticket[slot], 1u);
+    __shared__ uint32_t s_bc[NBINS], s_bbase[NBINS];
+    __shared__ unsigned long long s_ge, s_gbase;
+    __shared__ int s_all;
+    if (threadIdx.x == 0) {
+        s_tile = atomicAdd(&hdr->ticket[slot], 1u);
+        s_ge = 0;
+        s_all = 1;
+    }
+    if (threadIdx.x < NBINS) s_bc[threadIdx.x] = 0;
+    if (classify == 3 && threadIdx.x < WAVE) {
+        // any block of the J-table build that saw J out of order
+        uint64_t any = ballot(ld_agent(&nmslots[threadIdx.x * 32]) != 0);
+        if (threadIdx.x == 0) s_all = any != 0;
+    }
     __syncthreads();
     const int64_t tile = s_tile;
     const int64_t base = tile * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
@@ -328,36 +355,52 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_counts(
     }
     __syncthreads();
     uint64_t run = s_excl + texcl;
-    const int64_t last_base = (n - 1) / SCAN_TILE;
-    if (base + SCAN_ITEMS <= n && (sizeof(PT) == 8)) {
 #pragma unroll
-        for (int k = 0; k < SCAN_ITEMS; k++) { out[base + k] = (PT)run; run += (uint32_t)v[k]; }
-    } else {
-#pragma unroll
-        for (int k = 0; k < SCAN_ITEMS; k++) {
-            if (base + k < n) out[base + k] = (PT)run;
-            run += (uint32_t)v[k];
-        }
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        if (base + k < n) out[base + k] = (PT)run;
+        run += (uint32_t)v[k];
     }
+    const int64_t last_base = (n - 1) / SCAN_TILE;
     if (tile == last_base && threadIdx.x == SCAN_BLOCK - 1) {
         uint64_t total = s_excl + tile_total;
         out[n] = (PT)total;
         hdr->total[slot] = total;
         if (sizeof(PT) == 4 && total > (uint64_t)INT32_MAX) raise_err(hdr, E_OVERFLOW);
+        if (classify == 3 && s_all) atomicOr(&hdr->flags, F_NOT_MONOTONE);
     }
     if (classify) {
-        // mode 3: every row when the column map is not monotone, otherwise
-        // only the rows flagged in `force` (rows assembled out of order)
-        int mode = classify;
-        bool all = true;
-        if (mode == 3) {
-            all = (ld_agent(&hdr->flags) & F_NOT_MONOTONE) != 0;
-            mode = 2;
-        }
+        // block-aggregated append to the class lists: LDS offsets, then a
+        // handful of global atomics per tile
+        const bool all = s_all != 0;
+        int bin[SCAN_ITEMS];
+        uint32_t off[SCAN_ITEMS];
+        unsigned long long eoff[SCAN_ITEMS];
 #pragma unroll
         for (int k = 0; k < SCAN_ITEMS; k++) {
-            bool want = base + k < n && (all || force[base + k] != 0);
-            classify_append(base + k, v[k], want, mode, hdr, lists, cap, goff);
+            const bool valid = base + k < n;
+            const bool fl = (classify == 3 && valid && !all) ? force[base + k] != 0 : false;
+            bin[k] = valid ? class_of(v[k], classify, all, fl) : -1;
+            off[k] = 0;
+            eoff[k] = 0;
+            if (bin[k] >= 0) {
+                off[k] = atomicAdd(&s_bc[bin[k]], 1u);
+                if (bin[k] == BIN_GLOBAL) eoff[k] = atomicAdd(&s_ge, (unsigned long long)(uint32_t)v[k]);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < NBINS && s_bc[threadIdx.x])
+            s_bbase[threadIdx.x] = atomicAdd(&hdr->bin_cnt[threadIdx.x], s_bc[threadIdx.x]);
+        if (threadIdx.x == NBINS && s_ge)
+            s_gbase = atomicAdd((unsigned long long *)&hdr->bin_elems[BIN_GLOBAL], s_ge);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; k++) {
+            if (bin[k] < 0) continue;
+            const uint32_t pos = s_bbase[bin[k]] + off[k];
+            if (pos < cap) {
+                lists[(int64_t)bin[k] * cap + pos] = (uint32_t)(base + k);
+                if (bin[k] == BIN_GLOBAL) goff[pos] = s_gbase + eoff[k];
+            }
         }
     }
 }
@@ -373,7 +416,7 @@ __global__ void k_scan_empty(PT *out, DevHdr *hdr, int slot) {
 template <typename PT>
 hipError_t launch_scan_counts(hipStream_t s, const int32_t *cnt, PT *out, int64_t n, DevHdr *hdr,
                               int slot, uint64_t *tile_state, int classify, uint32_t *bin_lists,
-                              int64_t bin_cap, const int32_t *force) {
+                              int64_t bin_cap, const int32_t *force, const uint32_t *nmslots) {
     if (n == 0) {
         hipLaunchKernelGGL(k_scan_empty<PT>, dim3(1), dim3(64), 0, s, out, hdr, slot);
         return hipGetLastError();
@@ -381,15 +424,15 @@ hipError_t launch_scan_counts(hipStream_t s, const int32_t *cnt, PT *out, int64_
     int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     uint64_t *goff = bin_lists ? reinterpret_cast<uint64_t *>(bin_lists + NBINS * bin_cap) : nullptr;
     hipLaunchKernelGGL(k_scan_counts<PT>, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, cnt, out, n,
-                       hdr, slot, tile_state, classify, bin_lists, bin_cap, goff, force);
+                       hdr, slot, tile_state, classify, bin_lists, bin_cap, goff, force, nmslots);
     return hipGetLastError();
 }
 
 template hipError_t launch_scan_counts<int32_t>(hipStream_t, const int32_t *, int32_t *, int64_t,
                                                 DevHdr *, int, uint64_t *, int, uint32_t *, int64_t,
-                                                const int32_t *);
+                                                const int32_t *, const uint32_t *);
 template hipError_t launch_scan_counts<int64_t>(hipStream_t, const int32_t *, int64_t *, int64_t,
                                                 DevHdr *, int, uint64_t *, int, uint32_t *, int64_t,
-                                                const int32_t *);
+                                                const int32_t *, const uint32_t *);
 
 }  // namespace hp

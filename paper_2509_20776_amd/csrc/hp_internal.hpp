@@ -26,7 +26,8 @@ enum : uint32_t { F_NOT_MONOTONE = 1u };
 
 enum { BIN_THREAD = 0, BIN_WAVE = 1, BIN_BLOCK = 2, BIN_GLOBAL = 3, NBINS = 4 };
 constexpr int64_t THREAD_MAX = 16;     // rows sorted in registers by one lane
-constexpr int64_t WAVE_MAX = 64;       // rows sorted by one wavefront
+constexpr int64_t SMALL_MAX = 64;      // rows k_sort_small sorts with one wavefront
+constexpr int64_t WAVE_MAX = 256;      // rows sorted by one wavefront (4 keys per lane)
 constexpr int64_t BLOCK_MAX = 4096;    // rows sorted in LDS by one workgroup
 
 struct DevHdr {
@@ -67,6 +68,9 @@ __device__ __forceinline__ int64_t clampc(int32_t c, int64_t n) {
 }
 
 __device__ __forceinline__ void raise_err(DevHdr *h, uint32_t bits) { atomicOr(&h->err, bits); }
+
+// Fill n 32-bit words with v (sequential stores).
+hipError_t launch_fill_words(hipStream_t s, void *p, size_t nwords32, uint32_t v);
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -130,23 +134,24 @@ struct Carve {
     size_t size() const { return (off + 255) & ~size_t(255); }
 };
 
-struct StageTimer;
 
 }  // namespace hp
 
 // The handle (opaque to callers).
+struct hp_stage_rec {
+    const char *name;
+    hipEvent_t e0, e1;
+};
 struct hp_handle_s {
     int device = 0;
     hipStream_t stream = nullptr;
     hp::DevHdr *host_hdr = nullptr;        // pinned readback block
     std::string last_error;
     bool timing = false;
-    std::vector<hipEvent_t> ev;            // pool of events for stage timing
-    std::vector<const char *> stage_names; // names of recorded stages
-    int nstage = 0;
-    float stage_ms[64];
-    const char *stage_name_out[64];
-    int nstage_out = 0;
+    std::vector<hipEvent_t> ev;            // event pool for stage timing
+    size_t ev_used = 0;
+    hipEvent_t ev_cur = nullptr;
+    std::vector<hp_stage_rec> recs;        // recorded (stage, start, end) triples
 };
 
 namespace hp {
@@ -172,14 +177,16 @@ hipError_t readback_hdr(hp_handle_t h, DevHdr *dev);
 
 // Exclusive scan of n counts (int32 in) into out (PT, n+1 entries); out[n]
 // = total; hdr->total[slot] = total.  classify: 0 none, 1 rows longer than
-// THREAD_MAX, 2 all rows of >= 2 entries, 3 all rows if hdr->flags has
-// F_NOT_MONOTONE else only rows with force[i] != 0 (class lists, see
-// hp_segsort.hpp).  tile_state must hold scan_tiles(n)
+// THREAD_MAX, 2 all rows of >= 2 entries, 3 rows longer than WAVE_MAX when
+// any of the 64 spread flag slots nmslots[32*k] is set (the column map is
+// not monotone; F_NOT_MONOTONE is then raised), else only rows with
+// force[i] != 0 (class lists, see hp_segsort.hpp).  tile_state must hold scan_tiles(n)
 // zeroed words and hdr->ticket[slot] must be zero (launch_init_hdr does both).
 size_t scan_tiles(int64_t n);
 template <typename PT>
 hipError_t launch_scan_counts(hipStream_t s, const int32_t *cnt, PT *out, int64_t n, DevHdr *hdr,
                               int slot, uint64_t *tile_state, int classify, uint32_t *bin_lists,
-                              int64_t bin_cap, const int32_t *force = nullptr);
+                              int64_t bin_cap, const int32_t *force = nullptr,
+                              const uint32_t *nmslots = nullptr);
 
 }  // namespace hp

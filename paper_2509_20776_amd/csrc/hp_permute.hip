@@ -5,10 +5,11 @@
 // column c is qinv[c].  On one GPU the Exchange step disappears, and the
 // paper's two-pass count / prefix / scatter becomes count -> single-pass
 // scan -> fill, with the Build-step sort folded into the fill:
-//   plan : k_perm_prepare  pinv, qinv, per-output-row counts, range check
-//          k_perm_check    every value of p and q occurs once
+//   plan : fill -1      pinv, qinv
+//          k_perm_prepare  scatter pinv, qinv; per-output-row counts; range
+//          k_perm_check    no slot left at -1 (every value occurs once)
 //          scan            rowptr of C + row classes by length
-//   exec : k_perm_fill_short  rows of <= 16 entries, streamed in source
+//   exec : k_perm_fill_short  rows of <= 4 entries, streamed in source
 //                             order (push), sorted in registers
 //          class kernels       longer rows gathered from A (pull) and sorted
 #include "hp_internal.hpp"
@@ -42,89 +43,57 @@ __global__ __launch_bounds__(256) void k_perm_prepare(const PT *__restrict__ aro
                                                      const int32_t *__restrict__ q, int64_t m,
                                                      int64_t n, int32_t *pinv, int32_t *qinv,
                                                      int32_t *cnt, DevHdr *hdr) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t hi = m > n ? m : n;
-    uint32_t err = 0, flags = 0;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < hi; t += stride) {
-        if (t < m) {
-            int32_t r = p[t];
-            if (r < 0 || r >= m) {
-                err |= E_RANGE;
-                cnt[t] = 0;
-            } else {
-                pinv[r] = (int32_t)t;
-                cnt[t] = (int32_t)(arow[r + 1] - arow[r]);
-            }
-            if (!q && r != t) flags |= F_NOT_MONOTONE;
-        }
-        if (q && t < n) {
-            int32_t c = q[t];
-            if (c < 0 || c >= n) err |= E_RANGE;
-            else qinv[c] = (int32_t)t;
-            if (c != t) flags |= F_NOT_MONOTONE;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < m) {
+        const int32_t r = p[t];
+        if (r < 0 || r >= m) {
+            atomicOr(&hdr->err, E_RANGE);     // error path only
+            cnt[t] = 0;
+        } else {
+            pinv[r] = (int32_t)t;
+            cnt[t] = (int32_t)(arow[r + 1] - arow[r]);
         }
     }
-    if (err) atomicOr(&hdr->err, err);   // error path only
-    uint64_t f = ballot(flags != 0);
-    if (f && lane_id() == __ffsll((long long)f) - 1) atomicOr(&hdr->flags, F_NOT_MONOTONE);
+    if (q && t < n) {
+        const int32_t c = q[t];
+        if (c < 0 || c >= n) atomicOr(&hdr->err, E_RANGE);
+        else qinv[c] = (int32_t)t;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_perm_check(const int32_t *__restrict__ p,
-                                                   const int32_t *__restrict__ q, int64_t m,
-                                                   int64_t n, const int32_t *__restrict__ pinv,
-                                                   const int32_t *__restrict__ qinv, DevHdr *hdr) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t hi = m > n ? m : n;
+// pinv and qinv start filled with -1 and every in-range value of p (q) has
+// been scattered: a slot left at -1 means some value is missing, hence
+// (m values in m slots) another is repeated.  Sequential reads only.
+__global__ __launch_bounds__(256) void k_perm_check(int64_t m, int64_t n, const int32_t *__restrict__ pinv,
+                                                   const int32_t *__restrict__ qinv, bool general,
+                                                   DevHdr *hdr) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     bool bad = false;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < hi; t += stride) {
-        if (t < m) {
-            int32_t i = pinv[t];
-            bad |= !(i >= 0 && i < m && p[i] == t);
-        }
-        if (q && t < n) {
-            int32_t j = qinv[t];
-            bad |= !(j >= 0 && j < n && q[j] == t);
-        }
-    }
-    uint64_t b = ballot(bad);
-    if (b && lane_id() == __ffsll((long long)b) - 1) atomicOr(&hdr->err, E_NOTPERM);
+    if (t < m) bad |= pinv[t] < 0;
+    if (general && t < n) bad |= qinv[t] < 0;
+    if (bad) atomicOr(&hdr->err, E_NOTPERM);   // error path only
 }
 
-// Rows of at most 16 entries: one lane per SOURCE row r, streamed in order
+// Rows of at most 4 entries: one lane per SOURCE row r, streamed in order
 // (coalesced reads of A, local reads of qinv for banded matrices), written
 // to output row pinv[r] after an in-register sort of the mapped columns.
+// Longer rows go through the class kernels (pull from A).
 template <typename PT, typename VT>
 __global__ __launch_bounds__(256) void k_perm_fill_short(
     const PT *__restrict__ arow, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
     const int32_t *__restrict__ pinv, const int32_t *__restrict__ cmap, const PT *__restrict__ crow,
-    int32_t *__restrict__ ccol, VT *__restrict__ cval, int64_t m, int64_t n, int sorted,
-    const DevHdr *hdr) {
+    int32_t *__restrict__ ccol, VT *__restrict__ cval, int64_t m, int64_t n, const DevHdr *hdr) {
     if (hdr->err) return;
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= m) return;
     const int64_t s = arow[r];
     const int len = (int)(arow[r + 1] - s);
-    if (len == 0 || len > THREAD_MAX) return;
+    if (len == 0 || len > 4) return;
     const int64_t d = crow[pinv[r]];
-    if (len <= 4) {
-        int32_t k[4];
-        VT v[4];
+    int32_t k[4];
+    VT v[4];
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            k[i] = INT32_MAX;
-            v[i] = VT(0);
-            if (i < len) {
-                k[i] = cmap[clampc(acol[s + i], n)];
-                v[i] = aval[s + i];
-            }
-        }
-        sort_store_regs<4, VT>(k, v, len, sorted, ccol + d, cval + d);
-        return;
-    }
-    int32_t k[16];
-    VT v[16];
-#pragma unroll
-    for (int i = 0; i < 16; i++) {
+    for (int i = 0; i < 4; i++) {
         k[i] = INT32_MAX;
         v[i] = VT(0);
         if (i < len) {
@@ -132,7 +101,7 @@ __global__ __launch_bounds__(256) void k_perm_fill_short(
             v[i] = aval[s + i];
         }
     }
-    sort_store_regs<16, VT>(k, v, len, sorted, ccol + d, cval + d);
+    sort_store_regs<4, VT>(k, v, len, false, ccol + d, cval + d);
 }
 
 // Longer rows: output row i is row p[i] of A with columns mapped (pull).
@@ -188,13 +157,15 @@ hp_status_t perm_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
     hipStream_t s = h->stream;
     stage_begin(h);
     hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, scan_tiles(m));
+    if (e == hipSuccess) e = launch_fill_words(s, L.pinv, (size_t)m, 0xFFFFFFFFu);
+    if (e == hipSuccess && !sym) e = launch_fill_words(s, L.qinv, (size_t)n, 0xFFFFFFFFu);
     const int64_t hi = m > n ? m : n;
-    const int grid = (int)std::min<int64_t>((hi + 255) / 256 > 0 ? (hi + 255) / 256 : 1, 16384);
+    const int grid = (int)std::max<int64_t>(1, (hi + 255) / 256);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_perm_prepare<PT>, dim3(grid), dim3(256), 0, s, (const PT *)A->rowptr, p, q,
                            m, n, L.pinv, L.qinv, L.cnt, L.hdr);
         stage_mark(h, "perm.prepare");
-        hipLaunchKernelGGL(k_perm_check, dim3(grid), dim3(256), 0, s, p, q, m, n, L.pinv, L.qinv, L.hdr);
+        hipLaunchKernelGGL(k_perm_check, dim3(grid), dim3(256), 0, s, m, n, L.pinv, L.qinv, !sym, L.hdr);
         stage_mark(h, "perm.check");
         e = hipGetLastError();
     }
@@ -212,13 +183,13 @@ hp_status_t perm_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
     if (info) {
         *info = hp_plan_info_t{};
         info->nnz_out = C->nnz;
-        info->map_monotone = (H.flags & F_NOT_MONOTONE) ? 0 : 1;
+        info->map_monotone = 0;   // rows are always sorted
         info->op = 1;
         for (int b = 0; b < NBINS; b++) {
             info->rows_sorted[b] = H.bin_cnt[b];
             info->class_elems[b] = (int64_t)H.bin_elems[b];
         }
-        info->exec_ws_bytes = seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], vs);
+        info->exec_ws_bytes = seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], H.bin_cnt[BIN_GLOBAL], vs, n);
     }
     return HP_OK;
 }
@@ -254,15 +225,15 @@ hp_status_t perm_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
     if (m > 0) {
         hipLaunchKernelGGL((k_perm_fill_short<PT, VT>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
                            (const PT *)A->rowptr, A->col, (const VT *)A->val, L.pinv, L.qinv,
-                           (const PT *)C->rowptr, C->col, (VT *)C->val, m, n, sorted, L.hdr);
+                           (const PT *)C->rowptr, C->col, (VT *)C->val, m, n, L.hdr);
         stage_mark(h, "perm.fill_short");
     }
     uint32_t cnt[NBINS];
     for (int b = 0; b < NBINS; b++) cnt[b] = (uint32_t)info->rows_sorted[b];
     LoadPerm<PT, VT> ld{(const PT *)A->rowptr, A->col, (const VT *)A->val, p, L.qinv, n};
     hipError_t e = launch_seg_classes<PT, VT, LoadPerm<PT, VT>>(
-        s, (const PT *)C->rowptr, C->col, (VT *)C->val, L.lists, m, cnt, ld, sorted != 0,
-        key_bits(n), false, xws, (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, false);
+        s, (const PT *)C->rowptr, C->col, (VT *)C->val, L.lists, m, cnt, ld, sorted != 0, n, false, xws,
+        (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);
     stage_mark(h, "perm.fill_long");
     stage_end(h);
     return hip_check(h, e == hipSuccess ? hipGetLastError() : e, "permute exec");

@@ -4,15 +4,21 @@
 // Every segment is one output row [rowptr[r], rowptr[r+1]); keys are the new
 // column indices, distinct inside a row; values travel with their keys.  A
 // Loader supplies element k of row r: either the row already written in
-// place (LoadInPlace) or an operation-specific gather (for example permute
-// reads row p[r] of A and maps its columns), so a gather and the sort are
-// one pass.  Rows are grouped by length into classes decided during the
-// count scan:
-//   THREAD  2..16     one lane, bitonic network in registers
-//   WAVE    17..64    one wavefront, rank = number of smaller keys (LDS)
-//   BLOCK   65..4096  one workgroup, bitonic sort in LDS
-//   GLOBAL  > 4096    one workgroup, LSD radix (8-bit digits) through a
-//                     temporary region; stable ranks from wavefront match
+// place (LoadInPlace) or an operation-specific gather (permute reads row
+// p[r] of A and maps its columns), so a gather and the sort are one pass.
+//
+// Length classes:
+//   THREAD  2..16     one lane per row, bitonic network in registers
+//   WAVE    17..256   one wavefront, rank = number of smaller keys (LDS)
+//   BLOCK   257..4096 one workgroup: 64-element runs ranked per wavefront,
+//                     then merged pairwise in LDS (merge-path ranks)
+//   GLOBAL  > 4096    split by key range into buckets of width 4096 (one
+//                     workgroup per row, LDS histogram), then every bucket
+//                     (at most 4096 distinct keys) sorted by its own
+//                     workgroup as in BLOCK.  Columns beyond 2^24 buckets
+//                     fall back to an LSD radix sort per row.
+// Rows of <= 64 entries can also be sorted without lists by k_sort_small,
+// which walks all rows in groups of 64.
 #pragma once
 #include "hp_internal.hpp"
 
@@ -67,17 +73,10 @@ __device__ __forceinline__ void sort_store_regs(int32_t (&k)[N], VT (&v)[N], int
         }
 }
 
-template <typename PT, typename VT, typename LD>
-__global__ __launch_bounds__(256) void k_seg_thread(const PT *__restrict__ rowptr, int32_t *okey,
-                                                   VT *oval, const uint32_t *__restrict__ list,
-                                                   uint32_t count, LD ld, int sorted,
-                                                   const DevHdr *hdr) {
-    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= count || hdr->err) return;
-    int64_t row = list[t];
-    int64_t b = rowptr[row];
-    int len = (int)(rowptr[row + 1] - b);
-    int64_t sb = ld.base(row);
+// One lane sorts one row of <= 16 entries read through the loader.
+template <typename VT, typename LD>
+__device__ __forceinline__ void lane_sort_row(const LD &ld, int64_t sb, int len, bool sorted,
+                                              int32_t *okey, VT *oval) {
     if (len <= 4) {
         int32_t k[4];
         VT v[4];
@@ -87,7 +86,7 @@ __global__ __launch_bounds__(256) void k_seg_thread(const PT *__restrict__ rowpt
             v[i] = VT(0);
             if (i < len) ld.get(sb, i, k[i], v[i]);
         }
-        sort_store_regs<4, VT>(k, v, len, sorted, okey + b, oval + b);
+        sort_store_regs<4, VT>(k, v, len, sorted, okey, oval);
         return;
     }
     int32_t k[16];
@@ -98,7 +97,69 @@ __global__ __launch_bounds__(256) void k_seg_thread(const PT *__restrict__ rowpt
         v[i] = VT(0);
         if (i < len) ld.get(sb, i, k[i], v[i]);
     }
-    sort_store_regs<16, VT>(k, v, len, sorted, okey + b, oval + b);
+    sort_store_regs<16, VT>(k, v, len, sorted, okey, oval);
+}
+
+// One wavefront sorts one row of <= 256 entries (up to 4 per lane): every
+// key's rank is the number of smaller keys, read 4 at a time from LDS.
+template <typename VT, typename LD>
+__device__ __forceinline__ void wave_sort_row(const LD &ld, int64_t sb, int len, bool sorted,
+                                              int32_t *okey, VT *oval, int32_t *s_k) {
+    const int l = lane_id();
+    int32_t mk[4];
+    VT mv[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        mk[q] = INT32_MAX;
+        mv[q] = VT(0);
+        const int x = q * WAVE + l;
+        if (x < len) ld.get(sb, x, mk[q], mv[q]);
+    }
+    if (sorted) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int x = q * WAVE + l;
+            if (x < len) {
+                okey[x] = mk[q];
+                oval[x] = mv[q];
+            }
+        }
+        return;
+    }
+    const int len4 = (len + 3) & ~3;
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+        if (q * WAVE < len4) s_k[q * WAVE + l] = mk[q];   // padding keys are INT32_MAX
+    __builtin_amdgcn_wave_barrier();
+    int rank[4] = {0, 0, 0, 0};
+    for (int i = 0; i < len4; i += 4) {
+        const int4 o = *reinterpret_cast<const int4 *>(s_k + i);
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            rank[q] += (o.x < mk[q]) + (o.y < mk[q]) + (o.z < mk[q]) + (o.w < mk[q]);
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int x = q * WAVE + l;
+        if (x < len) {
+            okey[rank[q]] = mk[q];
+            oval[rank[q]] = mv[q];
+        }
+    }
+}
+
+template <typename PT, typename VT, typename LD>
+__global__ __launch_bounds__(256) void k_seg_thread(const PT *__restrict__ rowptr, int32_t *okey,
+                                                   VT *oval, const uint32_t *__restrict__ list,
+                                                   uint32_t count, LD ld, int sorted,
+                                                   const DevHdr *hdr) {
+    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count || hdr->err) return;
+    int64_t row = list[t];
+    int64_t b = rowptr[row];
+    int len = (int)(rowptr[row + 1] - b);
+    lane_sort_row<VT, LD>(ld, ld.base(row), len, sorted != 0, okey + b, oval + b);
 }
 
 template <typename PT, typename VT, typename LD>
@@ -106,28 +167,98 @@ __global__ __launch_bounds__(256) void k_seg_wave(const PT *__restrict__ rowptr,
                                                  VT *oval, const uint32_t *__restrict__ list,
                                                  uint32_t count, LD ld, int sorted,
                                                  const DevHdr *hdr) {
-    __shared__ int32_t s_k[4][WAVE];
-    const int w = threadIdx.x / WAVE, l = lane_id();
+    __shared__ __align__(16) int32_t s_k[4][WAVE_MAX];
+    const int w = threadIdx.x / WAVE;
     uint32_t t = blockIdx.x * 4 + w;
     if (t >= count || hdr->err) return;
     int64_t row = list[t];
     int64_t b = rowptr[row];
     int len = (int)(rowptr[row + 1] - b);
-    int64_t sb = ld.base(row);
-    int32_t mk = INT32_MAX;
-    VT mv = VT(0);
-    if (l < len) ld.get(sb, l, mk, mv);
-    int rank = l;
-    if (!sorted) {
-        s_k[w][l] = mk;
-        __builtin_amdgcn_wave_barrier();
-        rank = 0;
-        for (int i = 0; i < len; i++) rank += s_k[w][i] < mk;
+    wave_sort_row<VT, LD>(ld, ld.base(row), len, sorted != 0, okey + b, oval + b, s_k[w]);
+}
+
+// All rows of <= SMALL_MAX entries, without lists: each wavefront takes 64
+// consecutive rows; rows of <= 16 are sorted by their own lane, rows of
+// 17..64 by the whole wavefront one after another.  Longer rows are left to
+// the class kernels.
+template <typename PT, typename VT, typename LD>
+__global__ __launch_bounds__(256) void k_sort_small(const PT *__restrict__ rowptr, int32_t *okey,
+                                                   VT *oval, int64_t nrows, LD ld,
+                                                   const DevHdr *hdr) {
+    __shared__ __align__(16) int32_t s_k[4][WAVE_MAX];
+    if (hdr->err) return;
+    const int w = threadIdx.x / WAVE, l = lane_id();
+    const int64_t row = ((int64_t)blockIdx.x * 4 + w) * WAVE + l;
+    int len = 0;
+    int64_t b = 0;
+    if (row < nrows) {
+        b = rowptr[row];
+        len = (int)(rowptr[row + 1] - b);
     }
-    if (l < len) {
-        okey[b + rank] = mk;
-        oval[b + rank] = mv;
+    if (len >= 2 && len <= (int)THREAD_MAX) lane_sort_row<VT, LD>(ld, ld.base(row), len, false, okey + b, oval + b);
+    uint64_t mid = ballot(len > (int)THREAD_MAX && len <= (int)SMALL_MAX);
+    while (mid) {
+        const int src = __ffsll((long long)mid) - 1;
+        mid &= mid - 1;
+        const int64_t r = __shfl(row, src, WAVE);
+        const int64_t rb = __shfl(b, src, WAVE);
+        const int rl = __shfl(len, src, WAVE);
+        wave_sort_row<VT, LD>(ld, ld.base(r), rl, false, okey + rb, oval + rb, s_k[w]);
     }
+}
+
+// ---- workgroup LDS sort of <= 4096 keys with their 16-bit source index ----
+// In: s_k0/s_i0 hold N (a multiple of 64) keys, real keys distinct, padded
+// with INT_MAX.  Out: sorted (key, index) pairs in buffer 0 or 1 (returned).
+__device__ int block_sort_lds(int32_t *s_k0, uint16_t *s_i0, int32_t *s_k1, uint16_t *s_i1, int N) {
+    const int w = threadIdx.x / WAVE, l = lane_id();
+    // 1. every 64-element run sorted by one wavefront (rank by counting)
+    for (int c = w; c * WAVE < N; c += 4) {
+        const int x = c * WAVE + l;
+        const int32_t mk = s_k0[x];
+        const uint16_t mi = s_i0[x];
+        int rank = 0;
+        const int32_t *run = s_k0 + c * WAVE;
+        for (int i = 0; i < WAVE; i++) {
+            const int32_t o = run[i];
+            rank += (o < mk) || (o == mk && i < l);   // pads (equal keys) keep lane order
+        }
+        s_k1[c * WAVE + rank] = mk;
+        s_i1[c * WAVE + rank] = mi;
+    }
+    __syncthreads();
+    int cur = 1;
+    int32_t *ka[2] = {s_k0, s_k1};
+    uint16_t *ia[2] = {s_i0, s_i1};
+    // 2. merge runs pairwise: an element's output rank is its rank in its own
+    //    run plus the number of elements of the other run before it (ties:
+    //    the left run first, which also keeps the padding in place)
+    for (int width = WAVE; width < N; width <<= 1) {
+        const int32_t *ik = ka[cur];
+        const uint16_t *ii = ia[cur];
+        int32_t *ok = ka[cur ^ 1];
+        uint16_t *oi = ia[cur ^ 1];
+        for (int x = threadIdx.x; x < N; x += 256) {
+            const int a0 = (x / (2 * width)) * 2 * width;
+            const bool in_a = (x - a0) < width;
+            const int own = in_a ? (x - a0) : (x - a0 - width);
+            const int o0 = in_a ? a0 + width : a0;
+            const int olen = in_a ? min(width, N - (a0 + width)) : width;
+            const int32_t key = ik[x];
+            int lo = 0, hi = olen > 0 ? olen : 0;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                const int32_t o = ik[o0 + mid];
+                if (in_a ? (o < key) : (o <= key)) lo = mid + 1;
+                else hi = mid;
+            }
+            ok[a0 + own + lo] = key;
+            oi[a0 + own + lo] = ii[x];
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    return cur;
 }
 
 template <typename PT, typename VT, typename LD>
@@ -135,16 +266,17 @@ __global__ __launch_bounds__(256) void k_seg_block(const PT *__restrict__ rowptr
                                                   VT *oval, const uint32_t *__restrict__ list,
                                                   uint32_t count, LD ld, int sorted,
                                                   const DevHdr *hdr) {
-    __shared__ int32_t s_k[BLOCK_MAX];
-    __shared__ VT s_v[BLOCK_MAX];
+    __shared__ int32_t s_k[2][BLOCK_MAX];
+    __shared__ uint16_t s_i[2][BLOCK_MAX];
     uint32_t t = blockIdx.x;
     if (t >= count || hdr->err) return;
     int64_t row = list[t];
     int64_t b = rowptr[row];
-    int len = (int)(rowptr[row + 1] - b);
+    int64_t len64 = rowptr[row + 1] - b;
     int64_t sb = ld.base(row);
-    if (sorted) {
-        for (int i = threadIdx.x; i < len; i += 256) {
+    if (sorted || len64 > BLOCK_MAX) {
+        // already in order: copy through the loader
+        for (int64_t i = threadIdx.x; i < len64; i += 256) {
             int32_t kk;
             VT vv;
             ld.get(sb, i, kk, vv);
@@ -153,50 +285,158 @@ __global__ __launch_bounds__(256) void k_seg_block(const PT *__restrict__ rowptr
         }
         return;
     }
-    int N = 128;
-    while (N < len) N <<= 1;
+    const int len = (int)len64;
+    const int N = (len + WAVE - 1) / WAVE * WAVE;
     for (int i = threadIdx.x; i < N; i += 256) {
         int32_t kk = INT32_MAX;
-        VT vv = VT(0);
-        if (i < len) ld.get(sb, i, kk, vv);
-        s_k[i] = kk;
-        s_v[i] = vv;
+        if (i < len) {
+            VT vv;
+            ld.get(sb, i, kk, vv);
+        }
+        s_k[0][i] = kk;
+        s_i[0][i] = (uint16_t)i;
     }
     __syncthreads();
-    for (int size = 2; size <= N; size <<= 1) {
-        for (int j = size >> 1; j > 0; j >>= 1) {
-            for (int p = threadIdx.x; p < N / 2; p += 256) {
-                int i = 2 * j * (p / j) + (p % j);
-                int l = i + j;
-                bool up = (i & size) == 0;
-                int32_t a = s_k[i], c = s_k[l];
-                if ((a > c) == up) {
-                    s_k[i] = c;
-                    s_k[l] = a;
-                    VT tv = s_v[i];
-                    s_v[i] = s_v[l];
-                    s_v[l] = tv;
-                }
-            }
-            __syncthreads();
+    const int cur = block_sort_lds(s_k[0], s_i[0], s_k[1], s_i[1], N);
+    // gather every value first: with an in-place loader the row is both the
+    // source and the destination
+    constexpr int PER = BLOCK_MAX / 256;
+    VT vr[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int i = q * 256 + threadIdx.x;
+        vr[q] = VT(0);
+        if (i < len) {
+            int32_t kk;
+            ld.get(sb, s_i[cur][i], kk, vr[q]);
         }
     }
-    for (int i = threadIdx.x; i < len; i += 256) {
-        okey[b + i] = s_k[i];
-        oval[b + i] = s_v[i];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int i = q * 256 + threadIdx.x;
+        if (i < len) {
+            okey[b + i] = s_k[cur][i];
+            oval[b + i] = vr[q];
+        }
     }
 }
 
-// LSD radix over one long row.  X = the output row, Y = its temporary
-// region.  Pass 0 reads through the loader; the last pass writes X.  When
-// the loader reads X itself (in-place) and the pass count is odd, the data
-// is first copied to Y so that no pass reads and writes the same array.
+// ---- GLOBAL class, step 1: split one long row into key buckets ------------
+// Bucket of key k is k >> 12 (width 4096), so a bucket holds at most 4096
+// distinct keys.  Elements are placed into the row's temporary region in
+// bucket order (arbitrary order inside a bucket); the bucket start offsets
+// go to bstart[t * (nb + 1) + ...].
+constexpr int BKT_SHIFT = 12;
+constexpr int BKT_MAXNB = 4096;
+
+template <typename PT, typename VT, typename LD>
+__global__ __launch_bounds__(256) void k_seg_bucket(const PT *__restrict__ rowptr,
+                                                   const uint32_t *__restrict__ list,
+                                                   const uint64_t *__restrict__ goff, uint32_t count,
+                                                   LD ld, int nb, int32_t *tkey, VT *tval,
+                                                   uint32_t *bstart, const DevHdr *hdr) {
+    __shared__ uint32_t s_h[BKT_MAXNB + 1];
+    __shared__ uint32_t s_sw[4];
+    uint32_t t = blockIdx.x;
+    if (t >= count || hdr->err) return;
+    const int64_t row = list[t];
+    const int64_t b = rowptr[row];
+    const int64_t len = rowptr[row + 1] - b;
+    const int64_t sb = ld.base(row);
+    int32_t *yk = tkey + goff[t];
+    VT *yv = tval + goff[t];
+    for (int i = threadIdx.x; i <= nb; i += 256) s_h[i] = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < len; i += 256) {
+        int32_t kk;
+        VT vv;
+        ld.get(sb, i, kk, vv);
+        atomicAdd(&s_h[(uint32_t)kk >> BKT_SHIFT], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of the histogram, 256 threads over nb+1 counters
+    const int per = (nb + 1 + 255) / 256;
+    uint32_t loc = 0;
+    for (int q = 0; q < per; q++) {
+        int i = threadIdx.x * per + q;
+        if (i <= nb) loc += s_h[i];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan<256, uint32_t>(loc, s_sw, tot);
+    for (int q = 0; q < per; q++) {
+        int i = threadIdx.x * per + q;
+        if (i <= nb) {
+            uint32_t c = s_h[i];
+            s_h[i] = run;
+            bstart[(int64_t)t * (nb + 1) + i] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < len; i += 256) {
+        int32_t kk;
+        VT vv;
+        ld.get(sb, i, kk, vv);
+        const uint32_t pos = atomicAdd(&s_h[(uint32_t)kk >> BKT_SHIFT], 1u);
+        yk[pos] = kk;
+        yv[pos] = vv;
+    }
+}
+
+// ---- GLOBAL class, step 2: sort every bucket in LDS into the output row ----
+template <typename PT, typename VT>
+__global__ __launch_bounds__(256) void k_seg_bucket_sort(const PT *__restrict__ rowptr, int32_t *okey,
+                                                        VT *oval, const uint32_t *__restrict__ list,
+                                                        const uint64_t *__restrict__ goff,
+                                                        uint32_t count, int nb, const int32_t *tkey,
+                                                        const VT *tval, const uint32_t *bstart,
+                                                        const DevHdr *hdr) {
+    __shared__ int32_t s_k[2][BLOCK_MAX];
+    __shared__ uint16_t s_i[2][BLOCK_MAX];
+    const int64_t item = blockIdx.x;
+    const uint32_t t = (uint32_t)(item / nb);
+    const int bk = (int)(item % nb);
+    if (t >= count || hdr->err) return;
+    const uint32_t *bs = bstart + (int64_t)t * (nb + 1);
+    const uint32_t s0 = bs[bk], s1 = bs[bk + 1];
+    const int len = (int)(s1 - s0);
+    if (len == 0) return;
+    const int64_t row = list[t];
+    const int64_t ob = (int64_t)rowptr[row] + s0;
+    const int32_t *yk = tkey + goff[t] + s0;
+    const VT *yv = tval + goff[t] + s0;
+    if (len > BLOCK_MAX) {
+        // only possible with repeated keys (a non-canonical input): copy
+        for (int i = threadIdx.x; i < len; i += 256) {
+            okey[ob + i] = yk[i];
+            oval[ob + i] = yv[i];
+        }
+        return;
+    }
+    const int N = (len + WAVE - 1) / WAVE * WAVE;
+    for (int i = threadIdx.x; i < N; i += 256) {
+        s_k[0][i] = i < len ? yk[i] : INT32_MAX;
+        s_i[0][i] = (uint16_t)i;
+    }
+    __syncthreads();
+    const int cur = block_sort_lds(s_k[0], s_i[0], s_k[1], s_i[1], N);
+    for (int i = threadIdx.x; i < len; i += 256) {
+        okey[ob + i] = s_k[cur][i];
+        oval[ob + i] = yv[s_i[cur][i]];
+    }
+}
+
+// ---- GLOBAL class fallback (more than 2^24 output columns): LSD radix ------
+// X = the output row, Y = its temporary region.  Pass 0 reads through the
+// loader; the last pass writes X.  When the loader reads X itself and the
+// pass count is odd, the data is first copied to Y.
 template <typename PT, typename VT, typename LD>
 __global__ __launch_bounds__(256) void k_seg_global(const PT *__restrict__ rowptr, int32_t *okey,
                                                    VT *oval, const uint32_t *__restrict__ list,
                                                    const uint64_t *__restrict__ goff, uint32_t count,
-                                                   LD ld, int sorted, int kbits, int inplace,
-                                                   int32_t *tkey, VT *tval, const DevHdr *hdr) {
+                                                   LD ld, int kbits, int inplace, int32_t *tkey,
+                                                   VT *tval, const DevHdr *hdr) {
     __shared__ uint32_t s_hist[256];
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_wc[4][256];
@@ -211,16 +451,6 @@ __global__ __launch_bounds__(256) void k_seg_global(const PT *__restrict__ rowpt
     VT *xv = oval + b;
     int32_t *yk = tkey + goff[t];
     VT *yv = tval + goff[t];
-    if (sorted) {
-        for (int64_t i = threadIdx.x; i < len; i += 256) {
-            int32_t kk;
-            VT vv;
-            ld.get(sb, i, kk, vv);
-            xk[i] = kk;
-            xv[i] = vv;
-        }
-        return;
-    }
     const int w = threadIdx.x / WAVE;
     const uint64_t lt = lanemask_lt();
     const int passes = (kbits + 7) / 8;
@@ -231,9 +461,8 @@ __global__ __launch_bounds__(256) void k_seg_global(const PT *__restrict__ rowpt
             yv[i] = xv[i];
         }
         __syncthreads();
-        from_loader = false;   // data now in Y
+        from_loader = false;
     }
-    // destination of pass p: X when (passes-1-p) is even, else Y
     for (int i = threadIdx.x; i < 4 * 256; i += 256) (&s_wc[0][0])[i] = 0;
     for (int pass = 0; pass < passes; pass++) {
         const int shift = 8 * pass;
@@ -269,7 +498,10 @@ __global__ __launch_bounds__(256) void k_seg_global(const PT *__restrict__ rowpt
             VT v = VT(0);
             if (valid) {
                 if (use_ld) ld.get(sb, i, k, v);
-                else { k = sk[i]; v = sv[i]; }
+                else {
+                    k = sk[i];
+                    v = sv[i];
+                }
             }
             uint32_t d = ((uint32_t)k >> shift) & 255u;
             uint64_t peers = ballot(valid);
@@ -301,20 +533,38 @@ __global__ __launch_bounds__(256) void k_seg_global(const PT *__restrict__ rowpt
     }
 }
 
-// Launch the classes present in the plan's bin counts.  lists holds NBINS
-// lists of capacity cap, followed by cap uint64 temporary offsets for the
-// GLOBAL class; tmp holds round256(glob_elems*4) key bytes then the values.
+// Class lists: NBINS lists of capacity cap, then cap uint64 temporary
+// offsets for the GLOBAL class.  The exec workspace holds the GLOBAL rows'
+// temporary keys (round256(elems*4) bytes), then their values, then the
+// bucket tables (rows * (nb + 1) uint32).
+inline int seg_nbuckets(int64_t ncols_out) {
+    int64_t nb = (ncols_out + (1 << BKT_SHIFT) - 1) >> BKT_SHIFT;
+    return nb < 1 ? 1 : (int)nb;
+}
+
+inline size_t seg_tmp_bytes(uint64_t glob_elems, uint64_t glob_rows, size_t vsize, int64_t ncols_out) {
+    if (!glob_elems) return 0;
+    size_t kb = (glob_elems * 4 + 255) & ~uint64_t(255);
+    size_t vb = (glob_elems * vsize + 255) & ~uint64_t(255);
+    int nb = seg_nbuckets(ncols_out);
+    size_t bb = nb <= BKT_MAXNB ? glob_rows * (size_t)(nb + 1) * 4 : 0;
+    return kb + vb + bb + 256;
+}
+
+inline size_t seg_list_words(int64_t cap) { return (size_t)cap * NBINS + (size_t)cap * 2 + 4; }
+
 template <typename PT, typename VT, typename LD>
 hipError_t launch_seg_classes(hipStream_t s, const PT *rowptr, int32_t *okey, VT *oval,
                               const uint32_t *lists, int64_t cap, const uint32_t *cnt, LD ld,
-                              bool sorted, int kbits, bool inplace, void *tmp, uint64_t glob_elems,
-                              const DevHdr *hdr, bool do_thread) {
+                              bool sorted, int64_t ncols_out, bool inplace, void *tmp,
+                              uint64_t glob_elems, const DevHdr *hdr, bool do_thread,
+                              bool do_wave = true) {
     const uint64_t *goff = reinterpret_cast<const uint64_t *>(lists + NBINS * cap);
     if (do_thread && cnt[BIN_THREAD])
         hipLaunchKernelGGL((k_seg_thread<PT, VT, LD>), dim3((cnt[BIN_THREAD] + 255) / 256), dim3(256),
                            0, s, rowptr, okey, oval, lists + BIN_THREAD * cap, cnt[BIN_THREAD], ld,
                            (int)sorted, hdr);
-    if (cnt[BIN_WAVE])
+    if (do_wave && cnt[BIN_WAVE])
         hipLaunchKernelGGL((k_seg_wave<PT, VT, LD>), dim3((cnt[BIN_WAVE] + 3) / 4), dim3(256), 0, s,
                            rowptr, okey, oval, lists + BIN_WAVE * cap, cnt[BIN_WAVE], ld, (int)sorted,
                            hdr);
@@ -323,19 +573,26 @@ hipError_t launch_seg_classes(hipStream_t s, const PT *rowptr, int32_t *okey, VT
                            okey, oval, lists + BIN_BLOCK * cap, cnt[BIN_BLOCK], ld, (int)sorted, hdr);
     if (cnt[BIN_GLOBAL]) {
         int32_t *tk = (int32_t *)tmp;
-        VT *tv = (VT *)((char *)tmp + ((glob_elems * sizeof(int32_t) + 255) & ~uint64_t(255)));
-        hipLaunchKernelGGL((k_seg_global<PT, VT, LD>), dim3(cnt[BIN_GLOBAL]), dim3(256), 0, s, rowptr,
-                           okey, oval, lists + BIN_GLOBAL * cap, goff, cnt[BIN_GLOBAL], ld, (int)sorted,
-                           kbits, (int)inplace, tk, tv, hdr);
+        char *p = (char *)tmp + ((glob_elems * sizeof(int32_t) + 255) & ~uint64_t(255));
+        VT *tv = (VT *)p;
+        uint32_t *bst = (uint32_t *)(p + ((glob_elems * sizeof(VT) + 255) & ~uint64_t(255)));
+        const int nb = seg_nbuckets(ncols_out);
+        if (sorted) {
+            hipLaunchKernelGGL((k_seg_block<PT, VT, LD>), dim3(cnt[BIN_GLOBAL]), dim3(256), 0, s, rowptr,
+                               okey, oval, lists + BIN_GLOBAL * cap, cnt[BIN_GLOBAL], ld, 1, hdr);
+        } else if (nb <= BKT_MAXNB) {
+            hipLaunchKernelGGL((k_seg_bucket<PT, VT, LD>), dim3(cnt[BIN_GLOBAL]), dim3(256), 0, s, rowptr,
+                               lists + BIN_GLOBAL * cap, goff, cnt[BIN_GLOBAL], ld, nb, tk, tv, bst, hdr);
+            hipLaunchKernelGGL((k_seg_bucket_sort<PT, VT>), dim3((unsigned)((int64_t)cnt[BIN_GLOBAL] * nb)),
+                               dim3(256), 0, s, rowptr, okey, oval, lists + BIN_GLOBAL * cap, goff,
+                               cnt[BIN_GLOBAL], nb, tk, tv, bst, hdr);
+        } else {
+            hipLaunchKernelGGL((k_seg_global<PT, VT, LD>), dim3(cnt[BIN_GLOBAL]), dim3(256), 0, s, rowptr,
+                               okey, oval, lists + BIN_GLOBAL * cap, goff, cnt[BIN_GLOBAL], ld,
+                               key_bits(ncols_out), (int)inplace, tk, tv, hdr);
+        }
     }
     return hipGetLastError();
 }
-
-inline size_t seg_tmp_bytes(uint64_t glob_elems, size_t vsize) {
-    if (!glob_elems) return 0;
-    return ((glob_elems * 4 + 255) & ~uint64_t(255)) + glob_elems * vsize + 256;
-}
-
-inline size_t seg_list_words(int64_t cap) { return (size_t)cap * NBINS + (size_t)cap * 2 + 4; }
 
 }  // namespace hp

@@ -2,21 +2,25 @@
 //
 // Identify (Sec. 4.5 Step 1) on one GPU: instead of converting I and J to
 // sparse vectors and binary-searching each selected column (the appendix
-// algorithm for extraction), J becomes an O(1) lookup structure:
-//   bm    membership bitmap over A's columns (L2 resident),
-//   dm    "column selected more than once" bitmap,
-//   jpos  for a selected column c: a position j with J[j] = c, or, for a
-//         repeated column, the head (~t) of a chain through the repeat
-//         records (Dj, Dn) ending in the first position.
-// Every selected row I[i] is streamed once to count its hits (with
-// multiplicity: a column selected k times yields k entries), and once more
-// in exec to write them.  Rows are processed in two ways:
-//   small rows (<= SR_LB entries) in row chunks: all rows whose merge-path
-//     start i + sps[i] falls in [w*SR_D, (w+1)*SR_D); rows never split, so
-//     entries land in scan order (already sorted when J is increasing);
-//   big rows in fixed chunks of SR_BD entries spread over workgroups; each
-//     chunk reserves its block of the row with an atomic cursor, and big
-//     rows are always sorted afterwards (deterministic final order).
+// algorithm for extraction), J becomes an O(1) lookup structure over A's
+// columns, built without contended atomics:
+//   mark  one byte per column, set for selected columns (plain stores),
+//   bm    the same as a bitmap (L2 resident), packed from mark,
+//   jpos  for a selected column c a position j with J[j] = c (the last
+//         plain store wins), or, for a column selected several times, the
+//         head ~t of a chain through Dn that visits every other position
+//         and ends in the winner,
+//   dm    bitmap of columns selected more than once.
+// Every selected row I[i] is then streamed twice: once to count its hits
+// (with multiplicity: a column selected k times yields k entries), once in
+// exec to write them.  Work is split per wavefront:
+//   row groups  64 consecutive rows of <= SR_LB entries; a wave-local
+//               merge path assigns 8 entries per lane per step; hits are
+//               written in scan order (so already sorted when J increases);
+//   big rows    chunks of SR_BW entries, one wavefront each, located with a
+//               cooperative 64-ary search over the chunk prefix; each chunk
+//               reserves its block of the row with an atomic cursor, and big
+//               rows are always sorted afterwards.
 // Build (Sec. 4.2 Step 3) is the segmented sort of hp_segsort.hpp.
 #include "hp_internal.hpp"
 #include "hp_segsort.hpp"
@@ -26,354 +30,383 @@ using namespace hp;
 namespace {
 
 constexpr int SR_BLOCK = 256;
-constexpr int64_t SR_D = 1024;    // merge-path items (rows + entries) per small chunk
-constexpr int64_t SR_LB = 1024;   // rows above this many entries are big
-constexpr int64_t SR_BD = 4096;   // entries per big-row chunk
-constexpr int SR_GRID = 2048;     // persistent workgroups for count and gather
+constexpr int SR_U = 8;                       // entries per lane per step
+constexpr int64_t SR_LB = 256;                // rows above this many entries are big
+constexpr int64_t SR_BW = WAVE * SR_U;        // entries per big-row chunk
+constexpr int SR_BIGBLOCKS = 2048;            // persistent workgroups for big chunks (launched first)
+constexpr int NMSLOTS = 64;                   // spread "J not increasing" flag slots
 
 struct SprefLayout {
     DevHdr *hdr;
-    uint64_t *tiles;       // 3 scans
-    uint32_t *zero;        // bm | dm | cnt, cleared together
-    uint32_t *bm, *dm;
+    uint64_t *tiles;       // 2 scans
+    uint32_t *zero;        // mark | dm | cnt | nmslots, cleared together
+    uint8_t *mark;
+    uint32_t *dm, *nm;
     int32_t *cnt;
-    int32_t *jpos;
-    int32_t *Dc, *Dj, *Dn; // repeat records
+    uint32_t *bm;
+    int32_t *jpos, *Dn;
     int64_t *rs;           // start of row I[i] in A
-    int32_t *rl, *rls, *ch;
-    int64_t *sps, *cp;
+    int32_t *rl, *ch;
+    int64_t *cp;
     int32_t *cursor;       // big-row fill cursors (exec)
     uint32_t *lists;
-    size_t nzero;
+    size_t nzero, nw;
 };
 
 SprefLayout spref_layout(Carve &c, int64_t n, int64_t nI, int64_t nJ) {
     SprefLayout L;
-    const size_t nw = (size_t)((n + 31) / 32) + 1;
+    L.nw = (((size_t)((n + 31) / 32) + 1) + 3) & ~size_t(3);   // keeps cnt 16-byte aligned
     const size_t st = scan_tiles(nI);
     L.hdr = c.take<DevHdr>(1);
-    L.tiles = c.take<uint64_t>(3 * st);
-    L.nzero = 2 * nw + (size_t)nI;
+    L.tiles = c.take<uint64_t>(2 * st);
+    const size_t markw = L.nw * 8;             // nw*32 bytes of marks
+    L.nzero = markw + L.nw + (size_t)nI + NMSLOTS * 32 + 8;
     L.zero = c.take<uint32_t>(L.nzero);
-    L.bm = L.zero;
-    L.dm = L.zero ? L.zero + nw : nullptr;
-    L.cnt = L.zero ? (int32_t *)(L.zero + 2 * nw) : nullptr;
+    L.mark = (uint8_t *)L.zero;
+    L.dm = L.zero ? L.zero + markw : nullptr;
+    L.cnt = L.zero ? (int32_t *)(L.zero + markw + L.nw) : nullptr;
+    L.nm = L.zero ? L.zero + markw + L.nw + nI + 8 : nullptr;
+    L.bm = c.take<uint32_t>(L.nw);
     L.jpos = c.take<int32_t>(n + 1);
-    L.Dc = c.take<int32_t>(nJ + 1);
-    L.Dj = c.take<int32_t>(nJ + 1);
     L.Dn = c.take<int32_t>(nJ + 1);
     L.rs = c.take<int64_t>(nI + 1);
     L.rl = c.take<int32_t>(nI + 1);
-    L.rls = c.take<int32_t>(nI + 1);
     L.ch = c.take<int32_t>(nI + 1);
-    L.sps = c.take<int64_t>(nI + 1);
     L.cp = c.take<int64_t>(nI + 1);
     L.cursor = c.take<int32_t>(nI + 1);
     L.lists = c.take<uint32_t>(seg_list_words(nI));
     return L;
 }
 
-// ---- J tables -------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_spref_jbuild(const int32_t *__restrict__ J, int64_t nJ,
-                                                     int64_t n, uint32_t *bm, uint32_t *dm,
-                                                     int32_t *jpos, int32_t *Dc, int32_t *Dj,
-                                                     DevHdr *hdr) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+// ---- J tables ---------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_spref_jscatter(const int32_t *__restrict__ J, int64_t nJ,
+                                                       int64_t n, uint8_t *mark, int32_t *jpos,
+                                                       uint32_t *nm, DevHdr *hdr) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     bool notmono = false;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nJ; j += stride) {
+    if (j < nJ) {
         const int32_t c = J[j];
         if (j + 1 < nJ && c >= J[j + 1]) notmono = true;
         if (c < 0 || c >= n) {
-            atomicOr(&hdr->err, E_RANGE);
-            continue;
-        }
-        const uint32_t bit = 1u << (c & 31);
-        const uint32_t old = atomicOr(&bm[c >> 5], bit);
-        if (old & bit) {
-            // a later occurrence of column c: record it for the chain
-            atomicOr(&dm[c >> 5], bit);
-            uint32_t t = atomicAdd(&hdr->ndup, 1u);
-            Dc[t] = c;
-            Dj[t] = (int32_t)j;
+            atomicOr(&hdr->err, E_RANGE);   // error path only
         } else {
-            jpos[c] = (int32_t)j;     // the single first occurrence
+            mark[c] = 1;
+            jpos[c] = (int32_t)j;
         }
     }
-    uint64_t b = ballot(notmono);
-    if (b && lane_id() == __ffsll((long long)b) - 1) atomicOr(&hdr->flags, F_NOT_MONOTONE);
+    if (__syncthreads_or(notmono) && threadIdx.x == 0) nm[(blockIdx.x & (NMSLOTS - 1)) * 32] = 1u;
 }
 
-// Link the repeat records of each column into a chain headed by jpos[c]:
-// jpos[c] = ~t_last, Dn[t] = previous head, ..., the last link holds the
-// first occurrence (>= 0).  Chain order is arbitrary; rows are sorted later.
-__global__ __launch_bounds__(256) void k_spref_jlink(int32_t *jpos, const int32_t *__restrict__ Dc,
-                                                    int32_t *Dn, const DevHdr *hdr) {
-    const uint32_t nd = hdr->ndup;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nd; t += gridDim.x * blockDim.x)
-        Dn[t] = atomicExch(&jpos[Dc[t]], ~(int32_t)t);
+__global__ __launch_bounds__(256) void k_spref_jpack(const int32_t *__restrict__ J, int64_t nJ,
+                                                    int64_t n, const uint8_t *__restrict__ mark,
+                                                    uint32_t *bm, int64_t nw,
+                                                    const int32_t *__restrict__ jpos, int32_t *Dn,
+                                                    uint32_t *dm) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < nw) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(mark + t * 32);
+        const uint4 a = p[0], b = p[1];
+        const uint32_t w8[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        uint32_t m = 0;
+#pragma unroll
+        for (int q = 0; q < 8; q++)
+#pragma unroll
+            for (int y = 0; y < 4; y++) m |= ((w8[q] >> (8 * y)) & 0xffu ? 1u : 0u) << (4 * q + y);
+        bm[t] = m;
+    }
+    if (t < nJ) {
+        const int32_t c = J[t];
+        int32_t loser = 0;
+        if (c >= 0 && c < n && jpos[c] != (int32_t)t) {
+            loser = 1;
+            atomicOr(&dm[c >> 5], 1u << (c & 31));
+        }
+        Dn[t] = loser;
+    }
 }
 
-// ---- selected rows --------------------------------------------------------
+// Link every non-winning position of a repeated column into the chain
+// headed by jpos[c]: jpos[c] = ~t_last, Dn[t] = previous head, ..., ending
+// in the winner (>= 0).  Chain order is arbitrary; rows are sorted later.
+__global__ __launch_bounds__(256) void k_spref_jlink(const int32_t *__restrict__ J, int64_t nJ,
+                                                    int32_t *jpos, int32_t *Dn) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < nJ && Dn[t] == 1) Dn[t] = atomicExch(&jpos[J[t]], ~(int32_t)t);
+}
+
+// ---- selected rows ----------------------------------------------------------
 template <typename PT>
 __global__ __launch_bounds__(256) void k_spref_rows(const PT *__restrict__ arow,
                                                    const int32_t *__restrict__ I, int64_t nI,
-                                                   int64_t m, int64_t *rs, int32_t *rl, int32_t *rls,
-                                                   int32_t *ch, DevHdr *hdr) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nI; i += stride) {
-        const int32_t r = I[i];
-        int64_t s = 0, len = 0;
-        if (r < 0 || r >= m) atomicOr(&hdr->err, E_RANGE);
-        else {
-            s = arow[r];
-            len = arow[r + 1] - s;
-        }
-        rs[i] = s;
-        rl[i] = (int32_t)len;
-        const bool big = len > SR_LB;
-        rls[i] = big ? 0 : (int32_t)len;
-        ch[i] = big ? (int32_t)((len + SR_BD - 1) / SR_BD) : 0;
+                                                   int64_t m, int64_t *rs, int32_t *rl, int32_t *ch,
+                                                   DevHdr *hdr) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nI) return;
+    const int32_t r = I[i];
+    int64_t s = 0, len = 0;
+    if (r < 0 || r >= m) atomicOr(&hdr->err, E_RANGE);   // error path only
+    else {
+        s = arow[r];
+        len = arow[r + 1] - s;
     }
+    rs[i] = s;
+    rl[i] = (int32_t)len;
+    ch[i] = len > SR_LB ? (int32_t)((len + SR_BW - 1) / SR_BW) : 0;
 }
 
 // ---- shared pieces of count and gather -------------------------------------
-__device__ __forceinline__ bool test_bit(const uint32_t *bm, int64_t c) {
-    return (bm[c >> 5] >> (c & 31)) & 1u;
+__device__ __forceinline__ bool test_bit(const uint32_t *b, int64_t c) {
+    return (b[c >> 5] >> (c & 31)) & 1u;
 }
 
-// Number of output entries a hit on column c produces (its multiplicity in J).
+// Output entries produced by a hit on column c (its multiplicity in J).
 __device__ __forceinline__ int mult_of(int64_t c, const uint32_t *dm, const int32_t *jpos,
                                        const int32_t *Dn) {
     if (!test_bit(dm, c)) return 1;
-    int m = 1;
+    int k = 1;
     int32_t v = jpos[c];
     while (v < 0) {
-        m++;
+        k++;
         v = Dn[~v];
     }
-    return m;
+    return k;
 }
 
-// Smallest i in [0, nI] with i + sps[i] >= d.
-__device__ __forceinline__ int64_t diag_lb(const int64_t *sps, int64_t nI, int64_t d) {
-    int64_t lo = 0, hi = nI;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (mid + sps[mid] < d) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// Largest i in [0, n) with a[i] <= x (a nondecreasing, a[0] <= x).
-template <typename T>
-__device__ __forceinline__ int64_t last_le(const T *a, int64_t n, int64_t x) {
-    int64_t lo = 0, hi = n;
-    while (hi - lo > 1) {
-        int64_t mid = (lo + hi) >> 1;
-        if ((int64_t)a[mid] <= x) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-struct ChunkSmem {
-    int64_t sps[SR_D + 2];
-    int64_t rs[SR_D + 1];
-    int32_t cnt[SR_D + 1];
-    int32_t scan[2 * SR_LB + 8];
-    int64_t misc[8];
-    int32_t red[8];
-};
-
-// Load the rows of small chunk w into shared memory; returns the row count.
-__device__ __forceinline__ int64_t load_small_chunk(ChunkSmem &sm, int64_t w, const int64_t *sps,
-                                                    const int64_t *rs, int64_t nI, int64_t &i0) {
-    if (threadIdx.x == 0) {
-        sm.misc[0] = diag_lb(sps, nI, w * SR_D);
-        sm.misc[1] = diag_lb(sps, nI, (w + 1) * SR_D);
-    }
-    __syncthreads();
-    i0 = sm.misc[0];
-    const int64_t nr = sm.misc[1] - i0;
-    for (int64_t r = threadIdx.x; r <= nr; r += SR_BLOCK) {
-        sm.sps[r] = sps[i0 + r];
-        if (r < nr) {
-            sm.rs[r] = rs[i0 + r];
-            sm.cnt[r] = 0;
-        }
-    }
-    __syncthreads();
-    return nr;
-}
-
-// ---- count (plan) -----------------------------------------------------------
-__global__ __launch_bounds__(SR_BLOCK) void k_spref_count(
-    const int32_t *__restrict__ acol, int64_t n, const int64_t *__restrict__ rs,
-    const int32_t *__restrict__ rl, const int64_t *__restrict__ sps, const int64_t *__restrict__ cp,
-    int64_t nI, const uint32_t *__restrict__ bm, const uint32_t *__restrict__ dm,
-    const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn, int32_t *cnt,
-    const DevHdr *hdr) {
-    __shared__ ChunkSmem sm;
-    if (hdr->err) return;
-    const int64_t S = sps[nI];
-    const int64_t nsmall = (nI + S + SR_D - 1) / SR_D;
-    const int64_t total = nsmall + cp[nI];
-    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-        if (w < nsmall) {
-            int64_t i0;
-            const int64_t nr = load_small_chunk(sm, w, sps, rs, nI, i0);
-            const int64_t E0 = sm.sps[0], E = sm.sps[nr] - E0;
-            for (int64_t e = threadIdx.x; e < E; e += SR_BLOCK) {
-                const int64_t r = last_le(sm.sps, nr + 1, E0 + e);
-                const int64_t c = clampc(acol[sm.rs[r] + (E0 + e - sm.sps[r])], n);
-                if (test_bit(bm, c)) atomicAdd(&sm.cnt[r], mult_of(c, dm, jpos, Dn));
-            }
-            __syncthreads();
-            for (int64_t r = threadIdx.x; r < nr; r += SR_BLOCK)
-                if (rl[i0 + r] <= SR_LB) cnt[i0 + r] = sm.cnt[r];
-            __syncthreads();
-        } else {
-            const int64_t g = w - nsmall;
-            if (threadIdx.x == 0) sm.misc[0] = last_le(cp, nI + 1, g);
-            __syncthreads();
-            const int64_t i = sm.misc[0];
-            const int64_t b = (g - cp[i]) * SR_BD;
-            const int64_t e = min(b + SR_BD, (int64_t)rl[i]);
-            const int64_t base = rs[i];
-            int32_t local = 0;
-            for (int64_t k = b + threadIdx.x; k < e; k += SR_BLOCK) {
-                const int64_t c = clampc(acol[base + k], n);
-                if (test_bit(bm, c)) local += mult_of(c, dm, jpos, Dn);
-            }
-            int32_t tot;
-            block_excl_scan<SR_BLOCK, int32_t>(local, sm.red, tot);
-            if (threadIdx.x == 0 && tot) atomicAdd(&cnt[i], tot);
-            __syncthreads();
-        }
-    }
-}
-
-// ---- gather (exec) ----------------------------------------------------------
-template <typename PT, typename VT>
+template <typename VT>
 __device__ __forceinline__ void emit_hits(int64_t c, VT v, int64_t pos, const uint32_t *dm,
-                                          const int32_t *jpos, const int32_t *Dj,
-                                          const int32_t *Dn, int32_t *ccol, VT *cval) {
+                                          const int32_t *jpos, const int32_t *Dn, int32_t *ccol,
+                                          VT *cval) {
     int32_t x = jpos[c];
-    if (!test_bit(dm, c)) {
-        ccol[pos] = x;
-        cval[pos] = v;
-        return;
-    }
-    while (x < 0) {
-        ccol[pos] = Dj[~x];
-        cval[pos] = v;
-        pos++;
-        x = Dn[~x];
+    if (test_bit(dm, c)) {
+        while (x < 0) {
+            ccol[pos] = ~x;
+            cval[pos] = v;
+            pos++;
+            x = Dn[~x];
+        }
     }
     ccol[pos] = x;
     cval[pos] = v;
 }
 
+// Largest i in [0, n) with a[i] <= x, a nondecreasing and a[0] <= x; the
+// wavefront probes 64 positions per round (4 rounds for 2^24 entries).
+__device__ __forceinline__ int64_t wave_search_le(const int64_t *a, int64_t n, int64_t x) {
+    int64_t lo = 0, hi = n;
+    const int l = lane_id();
+    while (hi - lo > 1) {
+        const int64_t step = (hi - lo + WAVE - 1) / WAVE;
+        const int64_t idx = lo + (int64_t)l * step;
+        const bool le = idx < hi && a[idx] <= x;
+        const uint64_t msk = ballot(le);
+        const int last = 63 - __clzll((long long)msk);
+        lo = lo + (int64_t)last * step;
+        hi = min(hi, lo + step);
+    }
+    return lo;
+}
+
+// Row (0..63) of the wave-local concatenation holding entry e.
+__device__ __forceinline__ int row_of(const int32_t *start, int32_t e) {
+    int lo = 0, hi = WAVE;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+struct GroupSmem {
+    int32_t start[WAVE + 1];
+    int32_t cnt[WAVE];
+    int64_t rs[WAVE];
+    int64_t crow[WAVE];
+};
+
+// ---- count (plan) -------------------------------------------------------------
+__global__ __launch_bounds__(SR_BLOCK) void k_spref_count(
+    const int32_t *__restrict__ acol, int64_t n, const int64_t *__restrict__ rs,
+    const int32_t *__restrict__ rl, const int64_t *__restrict__ cp, int64_t nI, int64_t ngb,
+    const uint32_t *__restrict__ bm, const uint32_t *__restrict__ dm,
+    const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn, int32_t *cnt,
+    const DevHdr *hdr) {
+    __shared__ GroupSmem gs[SR_BLOCK / WAVE];
+    if (hdr->err) return;
+    const int w = threadIdx.x / WAVE, l = lane_id();
+    if (blockIdx.x >= SR_BIGBLOCKS) {
+        GroupSmem &g = gs[w];
+        const int64_t i = ((int64_t)(blockIdx.x - SR_BIGBLOCKS) * 4 + w) * WAVE + l;
+        int len = 0;
+        bool small = false;
+        if (i < nI) {
+            const int L = rl[i];
+            small = L <= SR_LB;
+            if (small) {
+                len = L;
+                g.rs[l] = rs[i];
+            }
+        }
+        const int incl = wave_incl_scan(len);
+        const int E = __shfl(incl, WAVE - 1, WAVE);
+        g.start[l] = incl - len;
+        g.cnt[l] = 0;
+        __builtin_amdgcn_wave_barrier();
+        for (int e0 = 0; e0 < E; e0 += SR_BW) {
+            int64_t c[SR_U];
+            int rr[SR_U];
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) {
+                const int e = e0 + u * WAVE + l;
+                c[u] = -1;
+                rr[u] = 0;
+                if (e < E) {
+                    const int r = row_of(g.start, e);
+                    rr[u] = r;
+                    c[u] = clampc(acol[g.rs[r] + (e - g.start[r])], n);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SR_U; u++)
+                if (c[u] >= 0 && test_bit(bm, c[u])) atomicAdd(&g.cnt[rr[u]], mult_of(c[u], dm, jpos, Dn));
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (small) cnt[i] = g.cnt[l];
+        return;
+    }
+    // big-row chunks, one wavefront each (these workgroups come first)
+    const int64_t nbig = cp[nI];
+    const int64_t nwaves = (int64_t)SR_BIGBLOCKS * 4;
+    for (int64_t q = (int64_t)blockIdx.x * 4 + w; q < nbig; q += nwaves) {
+        const int64_t row = wave_search_le(cp, nI + 1, q);
+        const int64_t b = (q - cp[row]) * SR_BW;
+        const int64_t e = min(b + SR_BW, (int64_t)rl[row]);
+        const int64_t base = rs[row];
+        int sum = 0;
+#pragma unroll
+        for (int u = 0; u < SR_U; u++) {
+            const int64_t k = b + u * WAVE + l;
+            if (k < e) {
+                const int64_t c = clampc(acol[base + k], n);
+                if (test_bit(bm, c)) sum += mult_of(c, dm, jpos, Dn);
+            }
+        }
+        sum = wave_sum(sum);
+        if (l == 0 && sum) atomicAdd(&cnt[row], sum);
+    }
+}
+
+// ---- gather (exec) ------------------------------------------------------------
+// Within one step of SR_U slices, lane l of slice u holds entry e0+64u+l, so
+// slices in order are entries in scan order.  For each slice the wavefront
+// computes an exclusive scan of the hit multiplicities; a hit's position in
+// its row is the row's running count plus the scan minus the scan at the
+// row's first lane in the slice.
 template <typename PT, typename VT>
 __global__ __launch_bounds__(SR_BLOCK) void k_spref_gather(
     const int32_t *__restrict__ acol, const VT *__restrict__ aval, int64_t n,
-    const int64_t *__restrict__ rs, const int32_t *__restrict__ rl, const int64_t *__restrict__ sps,
-    const int64_t *__restrict__ cp, int64_t nI, const uint32_t *__restrict__ bm,
-    const uint32_t *__restrict__ dm, const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dj,
-    const int32_t *__restrict__ Dn, const PT *__restrict__ crow, int32_t *ccol, VT *cval,
-    int32_t *cursor, const DevHdr *hdr) {
-    __shared__ ChunkSmem sm;
+    const int64_t *__restrict__ rs, const int32_t *__restrict__ rl, const int64_t *__restrict__ cp,
+    int64_t nI, int64_t ngb, const uint32_t *__restrict__ bm, const uint32_t *__restrict__ dm,
+    const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn, const PT *__restrict__ crow,
+    int32_t *ccol, VT *cval, int32_t *cursor, const DevHdr *hdr) {
+    __shared__ GroupSmem gs[SR_BLOCK / WAVE];
     if (hdr->err) return;
-    const int64_t S = sps[nI];
-    const int64_t nsmall = (nI + S + SR_D - 1) / SR_D;
-    const int64_t total = nsmall + cp[nI];
-    constexpr int EPT = (int)((2 * SR_LB + SR_BLOCK - 1) / SR_BLOCK);   // entries per thread
-    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-        if (w < nsmall) {
-            int64_t i0;
-            const int64_t nr = load_small_chunk(sm, w, sps, rs, nI, i0);
-            const int64_t E0 = sm.sps[0], E = sm.sps[nr] - E0;
-            int64_t cc[EPT];
-            int32_t mm[EPT], rr[EPT];
-            int64_t kk[EPT];
-            int32_t run = 0;
-#pragma unroll
-            for (int q = 0; q < EPT; q++) {
-                const int64_t e = q * SR_BLOCK + threadIdx.x;
-                int32_t mult = 0;
-                cc[q] = 0;
-                rr[q] = 0;
-                kk[q] = 0;
-                if (e < E) {
-                    const int64_t r = last_le(sm.sps, nr + 1, E0 + e);
-                    const int64_t k = sm.rs[r] + (E0 + e - sm.sps[r]);
-                    const int64_t c = clampc(acol[k], n);
-                    if (test_bit(bm, c)) mult = mult_of(c, dm, jpos, Dn);
-                    cc[q] = c;
-                    rr[q] = (int32_t)r;
-                    kk[q] = k;
-                }
-                mm[q] = mult;
-                int32_t tot;
-                const int32_t ex = block_excl_scan<SR_BLOCK, int32_t>(mult, sm.red, tot);
-                if (e < E) sm.scan[e] = run + ex;
-                run += tot;
-                if (E <= (q + 1) * SR_BLOCK) break;   // uniform across the block
+    const int w = threadIdx.x / WAVE, l = lane_id();
+    const uint64_t le_mask = (l == 63) ? ~0ull : ((2ull << l) - 1);
+    if (blockIdx.x >= SR_BIGBLOCKS) {
+        GroupSmem &g = gs[w];
+        const int64_t i = ((int64_t)(blockIdx.x - SR_BIGBLOCKS) * 4 + w) * WAVE + l;
+        int len = 0;
+        if (i < nI) {
+            const int L = rl[i];
+            if (L <= SR_LB) {
+                len = L;
+                g.rs[l] = rs[i];
+                g.crow[l] = (int64_t)crow[i];
             }
-            if (threadIdx.x == 0) sm.scan[E] = run;
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < EPT; q++) {
-                const int64_t e = q * SR_BLOCK + threadIdx.x;
-                if (e < E && mm[q]) {
-                    const int64_t r = rr[q];
-                    const int64_t first = sm.sps[r] - E0;
-                    const int64_t pos = (int64_t)crow[i0 + r] + sm.scan[e] - sm.scan[first];
-                    emit_hits<PT, VT>(cc[q], aval[kk[q]], pos, dm, jpos, Dj, Dn, ccol, cval);
-                }
-            }
-            __syncthreads();
-        } else {
-            const int64_t g = w - nsmall;
-            if (threadIdx.x == 0) sm.misc[0] = last_le(cp, nI + 1, g);
-            __syncthreads();
-            const int64_t i = sm.misc[0];
-            const int64_t b = (g - cp[i]) * SR_BD;
-            const int64_t e = min(b + SR_BD, (int64_t)rl[i]);
-            const int64_t base = rs[i];
-            constexpr int BPT = (int)(SR_BD / SR_BLOCK);
-            int64_t cc[BPT];
-            int32_t mm[BPT];
-            int32_t mine = 0;
-#pragma unroll
-            for (int q = 0; q < BPT; q++) {
-                const int64_t k = b + (int64_t)threadIdx.x * BPT + q;    // blocked: keeps entry order
-                int32_t mult = 0;
-                cc[q] = 0;
-                if (k < e) {
-                    const int64_t c = clampc(acol[base + k], n);
-                    if (test_bit(bm, c)) mult = mult_of(c, dm, jpos, Dn);
-                    cc[q] = c;
-                }
-                mm[q] = mult;
-                mine += mult;
-            }
-            int32_t tot;
-            int32_t ex = block_excl_scan<SR_BLOCK, int32_t>(mine, sm.red, tot);
-            if (threadIdx.x == 0) sm.misc[1] = tot ? atomicAdd(&cursor[i], tot) : 0;
-            __syncthreads();
-            int64_t pos = (int64_t)crow[i] + sm.misc[1] + ex;
-#pragma unroll
-            for (int q = 0; q < BPT; q++) {
-                if (mm[q]) {
-                    const int64_t k = b + (int64_t)threadIdx.x * BPT + q;
-                    emit_hits<PT, VT>(cc[q], aval[base + k], pos, dm, jpos, Dj, Dn, ccol, cval);
-                    pos += mm[q];
-                }
-            }
-            __syncthreads();
         }
+        const int incl = wave_incl_scan(len);
+        const int E = __shfl(incl, WAVE - 1, WAVE);
+        g.start[l] = incl - len;
+        g.cnt[l] = 0;            // running output count per row
+        __builtin_amdgcn_wave_barrier();
+        for (int e0 = 0; e0 < E; e0 += SR_BW) {
+            int64_t c[SR_U], k[SR_U];
+            int rr[SR_U], mm[SR_U];
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) {
+                const int e = e0 + u * WAVE + l;
+                c[u] = -1;
+                rr[u] = -1 - l;  // distinct per idle lane: never joins a segment
+                k[u] = 0;
+                if (e < E) {
+                    const int r = row_of(g.start, e);
+                    rr[u] = r;
+                    k[u] = g.rs[r] + (e - g.start[r]);
+                    c[u] = clampc(acol[k[u]], n);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SR_U; u++)
+                mm[u] = (c[u] >= 0 && test_bit(bm, c[u])) ? mult_of(c[u], dm, jpos, Dn) : 0;
+            VT v[SR_U];
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) v[u] = mm[u] ? aval[k[u]] : VT(0);
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) {
+                const int ex = wave_incl_scan(mm[u]) - mm[u];
+                const int prev_r = __shfl_up(rr[u], 1, WAVE);
+                const int next_r = __shfl_down(rr[u], 1, WAVE);
+                const bool is_start = l == 0 || prev_r != rr[u];
+                const bool is_last = l == WAVE - 1 || next_r != rr[u];
+                const uint64_t starts = ballot(is_start);
+                const int first = 63 - __clzll((long long)(starts & le_mask));
+                const int base_ex = __shfl(ex, first, WAVE);
+                if (mm[u]) {
+                    const int r = rr[u];
+                    const int64_t pos = g.crow[r] + g.cnt[r] + (ex - base_ex);
+                    emit_hits<VT>(c[u], v[u], pos, dm, jpos, Dn, ccol, cval);
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (rr[u] >= 0 && is_last) g.cnt[rr[u]] += ex + mm[u] - base_ex;
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        return;
+    }
+    // big-row chunks: positions inside the chunk in scan order, the chunk's
+    // block of the row reserved with the row's cursor (workgroups come first)
+    const int64_t nbig = cp[nI];
+    const int64_t nwaves = (int64_t)SR_BIGBLOCKS * 4;
+    for (int64_t q = (int64_t)blockIdx.x * 4 + w; q < nbig; q += nwaves) {
+        const int64_t row = wave_search_le(cp, nI + 1, q);
+        const int64_t b = (q - cp[row]) * SR_BW;
+        const int64_t e = min(b + SR_BW, (int64_t)rl[row]);
+        const int64_t base = rs[row];
+        int64_t c[SR_U];
+        int mm[SR_U];
+#pragma unroll
+        for (int u = 0; u < SR_U; u++) {
+            const int64_t kk = b + u * WAVE + l;
+            c[u] = -1;
+            if (kk < e) c[u] = clampc(acol[base + kk], n);
+        }
+        int run = 0;
+        int ex[SR_U];
+#pragma unroll
+        for (int u = 0; u < SR_U; u++) {
+            mm[u] = (c[u] >= 0 && test_bit(bm, c[u])) ? mult_of(c[u], dm, jpos, Dn) : 0;
+            const int inc = wave_incl_scan(mm[u]);
+            ex[u] = run + inc - mm[u];
+            run += __shfl(inc, WAVE - 1, WAVE);
+        }
+        int32_t cb = 0;
+        if (l == 0 && run) cb = atomicAdd(&cursor[row], run);
+        cb = __shfl(cb, 0, WAVE);
+        const int64_t ob = (int64_t)crow[row] + cb;
+#pragma unroll
+        for (int u = 0; u < SR_U; u++)
+            if (mm[u]) emit_hits<VT>(c[u], aval[base + b + u * WAVE + l], ob + ex[u], dm, jpos, Dn, ccol, cval);
     }
 }
 
@@ -391,6 +424,8 @@ hp_status_t spref_check_args(hp_handle_t h, const hp_csr_t *A, const int32_t *I,
     if (!C->rowptr) return fail(h, HP_ERR_INVALID_ARG, "C->rowptr is NULL");
     return HP_OK;
 }
+
+inline int grid1(int64_t n) { return (int)std::max<int64_t>(1, (n + 255) / 256); }
 
 template <typename PT>
 hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int64_t nI,
@@ -414,32 +449,32 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     const size_t st = scan_tiles(nI);
     hipStream_t s = h->stream;
     stage_begin(h);
-    hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, 3 * st);
+    hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, 2 * st);
     if (e == hipSuccess) e = launch_clear_words(s, L.zero, L.nzero);
     stage_mark(h, "spref.init");
-    const int gj = (int)std::max<int64_t>(1, std::min<int64_t>((nJ + 255) / 256, 4096));
-    const int gi = (int)std::max<int64_t>(1, std::min<int64_t>((nI + 255) / 256, 4096));
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_spref_jbuild, dim3(gj), dim3(256), 0, s, J, nJ, n, L.bm, L.dm, L.jpos, L.Dc,
-                           L.Dj, L.hdr);
-        hipLaunchKernelGGL(k_spref_jlink, dim3(gj), dim3(256), 0, s, L.jpos, L.Dc, L.Dn, L.hdr);
+        hipLaunchKernelGGL(k_spref_jscatter, dim3(grid1(nJ)), dim3(256), 0, s, J, nJ, n, L.mark, L.jpos,
+                           L.nm, L.hdr);
+        hipLaunchKernelGGL(k_spref_jpack, dim3(grid1(std::max<int64_t>(nJ, (int64_t)L.nw))), dim3(256), 0,
+                           s, J, nJ, n, L.mark, L.bm, (int64_t)L.nw, L.jpos, L.Dn, L.dm);
+        hipLaunchKernelGGL(k_spref_jlink, dim3(grid1(nJ)), dim3(256), 0, s, J, nJ, L.jpos, L.Dn);
         stage_mark(h, "spref.jtables");
-        hipLaunchKernelGGL(k_spref_rows<PT>, dim3(gi), dim3(256), 0, s, (const PT *)A->rowptr, I, nI, m,
-                           L.rs, L.rl, L.rls, L.ch, L.hdr);
+        hipLaunchKernelGGL(k_spref_rows<PT>, dim3(grid1(nI)), dim3(256), 0, s, (const PT *)A->rowptr, I,
+                           nI, m, L.rs, L.rl, L.ch, L.hdr);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = launch_scan_counts<int64_t>(s, L.rls, L.sps, nI, L.hdr, 0, L.tiles, 0, nullptr, 0);
-    if (e == hipSuccess) e = launch_scan_counts<int64_t>(s, L.ch, L.cp, nI, L.hdr, 1, L.tiles + st, 0, nullptr, 0);
+    if (e == hipSuccess) e = launch_scan_counts<int64_t>(s, L.ch, L.cp, nI, L.hdr, 0, L.tiles, 0, nullptr, 0);
     stage_mark(h, "spref.rows");
+    const int64_t ngb = (nI + 4 * WAVE - 1) / (4 * WAVE);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_spref_count, dim3(SR_GRID), dim3(SR_BLOCK), 0, s, A->col, n, L.rs, L.rl, L.sps,
-                           L.cp, nI, L.bm, L.dm, L.jpos, L.Dn, L.cnt, L.hdr);
+        hipLaunchKernelGGL(k_spref_count, dim3((unsigned)(ngb + SR_BIGBLOCKS)), dim3(SR_BLOCK), 0, s, A->col,
+                           n, L.rs, L.rl, L.cp, nI, ngb, L.bm, L.dm, L.jpos, L.Dn, L.cnt, L.hdr);
         stage_mark(h, "spref.count");
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
-        e = launch_scan_counts<PT>(s, L.cnt, (PT *)C->rowptr, nI, L.hdr, 2, L.tiles + 2 * st, 3, L.lists, nI,
-                                   L.ch);
+        e = launch_scan_counts<PT>(s, L.cnt, (PT *)C->rowptr, nI, L.hdr, 1, L.tiles + st, 3, L.lists, nI,
+                                   L.ch, L.nm);
         stage_mark(h, "spref.scan");
     }
     if (e == hipSuccess) e = readback_hdr(h, L.hdr);
@@ -448,7 +483,7 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     const DevHdr &H = *h->host_hdr;
     hp_status_t stt = status_from_err(h, H.err, "spref");
     if (stt) return stt;
-    C->nnz = (int64_t)H.total[2];
+    C->nnz = (int64_t)H.total[1];
     if (info) {
         *info = hp_plan_info_t{};
         info->nnz_out = C->nnz;
@@ -458,10 +493,8 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
             info->rows_sorted[b] = H.bin_cnt[b];
             info->class_elems[b] = (int64_t)H.bin_elems[b];
         }
-        info->aux[0] = (int64_t)H.total[0];   // entries scanned in small rows
-        info->aux[1] = (int64_t)H.total[1];   // big-row chunks
-        info->aux[2] = (int64_t)H.ndup;       // repeated J positions
-        info->exec_ws_bytes = seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], vs);
+        info->aux[1] = (int64_t)H.total[0];   // big-row chunks
+        info->exec_ws_bytes = seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], H.bin_cnt[BIN_GLOBAL], vs, nJ);
     }
     return HP_OK;
 }
@@ -491,12 +524,13 @@ hp_status_t spref_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     Carve c(ws);
     SprefLayout L = spref_layout(c, n, nI, nJ);
     hipStream_t s = h->stream;
+    const int64_t ngb = (nI + 4 * WAVE - 1) / (4 * WAVE);
     stage_begin(h);
     hipError_t e = hipSuccess;
     if (info->aux[1] > 0) e = launch_clear_words(s, L.cursor, (size_t)nI);
     if (e == hipSuccess && info->nnz_out > 0) {
-        hipLaunchKernelGGL((k_spref_gather<PT, VT>), dim3(SR_GRID), dim3(SR_BLOCK), 0, s, A->col,
-                           (const VT *)A->val, n, L.rs, L.rl, L.sps, L.cp, nI, L.bm, L.dm, L.jpos, L.Dj,
+        hipLaunchKernelGGL((k_spref_gather<PT, VT>), dim3((unsigned)(ngb + SR_BIGBLOCKS)), dim3(SR_BLOCK), 0,
+                           s, A->col, (const VT *)A->val, n, L.rs, L.rl, L.cp, nI, ngb, L.bm, L.dm, L.jpos,
                            L.Dn, (const PT *)C->rowptr, C->col, (VT *)C->val, L.cursor, L.hdr);
         stage_mark(h, "spref.gather");
         e = hipGetLastError();
@@ -505,9 +539,12 @@ hp_status_t spref_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
         uint32_t cnt[NBINS];
         for (int b = 0; b < NBINS; b++) cnt[b] = (uint32_t)info->rows_sorted[b];
         LoadInPlace<PT, VT> ld{(const PT *)C->rowptr, C->col, (const VT *)C->val};
+        if (!info->map_monotone)
+            hipLaunchKernelGGL((k_sort_small<PT, VT, LoadInPlace<PT, VT>>), dim3((unsigned)ngb), dim3(256), 0,
+                               s, (const PT *)C->rowptr, C->col, (VT *)C->val, nI, ld, L.hdr);
         e = launch_seg_classes<PT, VT, LoadInPlace<PT, VT>>(
-            s, (const PT *)C->rowptr, C->col, (VT *)C->val, L.lists, nI, cnt, ld, false, key_bits(nJ),
-            true, xws, (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);
+            s, (const PT *)C->rowptr, C->col, (VT *)C->val, L.lists, nI, cnt, ld, false, nJ, true, xws,
+            (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);
         stage_mark(h, "spref.sort");
     }
     stage_end(h);

@@ -71,6 +71,7 @@ hp_status_string = _sig("hp_status_string", [ctypes.c_int], ctypes.c_char_p)
 hp_last_error = _sig("hp_last_error", [_P], ctypes.c_char_p)
 hp_enable_timing = _sig("hp_enable_timing", [_P, ctypes.c_int])
 hp_stage_times = _sig("hp_stage_times", [_P, ctypes.POINTER(ctypes.c_float),
+                                         ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_char_p), ctypes.c_int])
 hp_permute_workspace = _sig("hp_permute_workspace", [_P, _CSRP, ctypes.POINTER(_SZ)])
 hp_permute_plan = _sig("hp_permute_plan", [_P, _CSRP, _P, _P, _CSRP, _P, _SZ, _INFOP])
@@ -164,10 +165,12 @@ class Handle:
         self.check(hp_enable_timing(self.h, 1 if on else 0))
 
     def stage_times(self):
+        """{stage: (total_ms, launches)} since the previous call."""
         ms = (ctypes.c_float * 64)()
+        cnt = (ctypes.c_int * 64)()
         nm = (ctypes.c_char_p * 64)()
-        k = hp_stage_times(self.h, ms, nm, 64)
-        return [(nm[i].decode(), float(ms[i])) for i in range(k)]
+        k = hp_stage_times(self.h, ms, cnt, nm, 64)
+        return {nm[i].decode(): (float(ms[i]), int(cnt[i])) for i in range(k)}
 
     def _alloc(self, nbytes):
         return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=f"cuda:{self.device}")
