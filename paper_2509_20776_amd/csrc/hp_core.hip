@@ -263,9 +263,11 @@ size_t scan_tiles(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) 
 //   2  every row of >= 2 entries
 //   3  rows longer than SMALL_MAX when `all` (shorter ones are sorted by
 //      k_sort_small), else only flagged rows
+//   4  only flagged rows
 __device__ __forceinline__ int class_of(int64_t len, int mode, bool all, bool flagged) {
     if (len < 2) return -1;
     if (mode == 1 && len <= 4) return -1;
+    if (mode == 4 && !flagged) return -1;
     if (mode == 3) {
         if (all) {
             if (len <= SMALL_MAX) return -1;
@@ -283,7 +285,7 @@ template <typename PT>
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_counts(
     const int32_t *__restrict__ cnt, PT *__restrict__ out, int64_t n, DevHdr *hdr, int slot,
     uint64_t *tile_state, int classify, uint32_t *lists, int64_t cap, uint64_t *goff,
-    const int32_t *__restrict__ force, const uint32_t *__restrict__ nmslots) {
+    const uint8_t *__restrict__ force, const uint32_t *__restrict__ nmslots) {
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_wave[SCAN_BLOCK / WAVE];
     __shared__ uint64_t s_excl;
@@ -378,7 +380,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_counts(
 #pragma unroll
         for (int k = 0; k < SCAN_ITEMS; k++) {
             const bool valid = base + k < n;
-            const bool fl = (classify == 3 && valid && !all) ? force[base + k] != 0 : false;
+            const bool fl = ((classify == 3 && !all) || classify == 4) && valid ? force[base + k] != 0 : false;
             bin[k] = valid ? class_of(v[k], classify, all, fl) : -1;
             off[k] = 0;
             eoff[k] = 0;
@@ -416,7 +418,7 @@ __global__ void k_scan_empty(PT *out, DevHdr *hdr, int slot) {
 template <typename PT>
 hipError_t launch_scan_counts(hipStream_t s, const int32_t *cnt, PT *out, int64_t n, DevHdr *hdr,
                               int slot, uint64_t *tile_state, int classify, uint32_t *bin_lists,
-                              int64_t bin_cap, const int32_t *force, const uint32_t *nmslots) {
+                              int64_t bin_cap, const uint8_t *force, const uint32_t *nmslots) {
     if (n == 0) {
         hipLaunchKernelGGL(k_scan_empty<PT>, dim3(1), dim3(64), 0, s, out, hdr, slot);
         return hipGetLastError();
@@ -430,9 +432,9 @@ hipError_t launch_scan_counts(hipStream_t s, const int32_t *cnt, PT *out, int64_
 
 template hipError_t launch_scan_counts<int32_t>(hipStream_t, const int32_t *, int32_t *, int64_t,
                                                 DevHdr *, int, uint64_t *, int, uint32_t *, int64_t,
-                                                const int32_t *, const uint32_t *);
+                                                const uint8_t *, const uint32_t *);
 template hipError_t launch_scan_counts<int64_t>(hipStream_t, const int32_t *, int64_t *, int64_t,
                                                 DevHdr *, int, uint64_t *, int, uint32_t *, int64_t,
-                                                const int32_t *, const uint32_t *);
+                                                const uint8_t *, const uint32_t *);
 
 }  // namespace hp

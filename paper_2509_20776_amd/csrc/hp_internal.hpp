@@ -180,13 +180,14 @@ hipError_t readback_hdr(hp_handle_t h, DevHdr *dev);
 // THREAD_MAX, 2 all rows of >= 2 entries, 3 rows longer than WAVE_MAX when
 // any of the 64 spread flag slots nmslots[32*k] is set (the column map is
 // not monotone; F_NOT_MONOTONE is then raised), else only rows with
-// force[i] != 0 (class lists, see hp_segsort.hpp).  tile_state must hold scan_tiles(n)
+// force[i] != 0; 4 only rows with force[i] != 0 (class lists, see
+// hp_segsort.hpp).  tile_state must hold scan_tiles(n)
 // zeroed words and hdr->ticket[slot] must be zero (launch_init_hdr does both).
 size_t scan_tiles(int64_t n);
 template <typename PT>
 hipError_t launch_scan_counts(hipStream_t s, const int32_t *cnt, PT *out, int64_t n, DevHdr *hdr,
                               int slot, uint64_t *tile_state, int classify, uint32_t *bin_lists,
-                              int64_t bin_cap, const int32_t *force = nullptr,
+                              int64_t bin_cap, const uint8_t *force = nullptr,
                               const uint32_t *nmslots = nullptr);
 
 }  // namespace hp

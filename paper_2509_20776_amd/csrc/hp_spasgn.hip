@@ -1,0 +1,518 @@
+// spasgn: C = A with A(I, J) = B (paper Sec. 2.3; HipAssign, Sec. 4.7).
+//
+// B is expanded to B'[I[i], J[j]] = B[i, j] (stored entries only) and added
+// to A with a user-chosen addition (the Add step of Sec. 4.7):
+//   SECOND  where both hold an entry B's value wins (select-second),
+//   PLUS    where both hold an entry the values are added,
+//   REPLACE every A entry inside I x J is dropped first (block replace).
+// On one GPU the Identify/Exchange/Build of B' collapses into per-row work:
+//   plan : fill -1, scatter rowinv[I[i]] = i and colinv[J[j]] = j, check
+//          that I and J repeat no index (Sec. 2.3 requires distinct ones);
+//          count every output row: rows outside I keep A's length, rows in
+//          I count the surviving A entries plus B's row; scan into rowptr.
+//   exec : rows outside I  streaming copy, 64 rows per wavefront;
+//          rows in I       one wavefront per row stages A's columns and B's
+//                          mapped columns in LDS, resolves collisions and
+//                          writes the row sorted (merge by co-rank when the
+//                          mapped B row is increasing, rank by count
+//                          otherwise).  Rows longer than AS_WCAP are written
+//                          unsorted and sorted by the segmented sort.
+#include "hp_internal.hpp"
+#include "hp_segsort.hpp"
+
+using namespace hp;
+
+namespace {
+
+constexpr int AS_WCAP = 256;   // A + B entries one wavefront resolves in LDS
+
+struct AsgLayout {
+    DevHdr *hdr;
+    uint64_t *tiles;
+    int32_t *rowinv, *colinv, *cnt;
+    uint8_t *force;
+    uint32_t *lists;
+};
+
+AsgLayout asg_layout(Carve &c, int64_t m, int64_t n) {
+    AsgLayout L;
+    L.hdr = c.take<DevHdr>(1);
+    L.tiles = c.take<uint64_t>(scan_tiles(m));
+    L.rowinv = c.take<int32_t>(m + 1);
+    L.colinv = c.take<int32_t>(n + 1);
+    L.cnt = c.take<int32_t>(m + 1);
+    L.force = c.take<uint8_t>(m + 16);
+    L.lists = c.take<uint32_t>(seg_list_words(m));
+    return L;
+}
+
+__global__ __launch_bounds__(256) void k_asg_inv(const int32_t *__restrict__ I, int64_t nI,
+                                                const int32_t *__restrict__ J, int64_t nJ, int64_t m,
+                                                int64_t n, int32_t *rowinv, int32_t *colinv,
+                                                DevHdr *hdr) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < nI) {
+        const int32_t r = I[t];
+        if (r < 0 || r >= m) atomicOr(&hdr->err, E_RANGE);   // error path only
+        else rowinv[r] = (int32_t)t;
+    }
+    if (t < nJ) {
+        const int32_t c = J[t];
+        if (c < 0 || c >= n) atomicOr(&hdr->err, E_RANGE);
+        else colinv[c] = (int32_t)t;
+    }
+}
+
+// A repeated index leaves one of its positions unrecorded.
+__global__ __launch_bounds__(256) void k_asg_dup(const int32_t *__restrict__ I, int64_t nI,
+                                                const int32_t *__restrict__ J, int64_t nJ, int64_t m,
+                                                int64_t n, const int32_t *__restrict__ rowinv,
+                                                const int32_t *__restrict__ colinv, DevHdr *hdr) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool dup = false;
+    if (t < nI) {
+        const int32_t r = I[t];
+        dup |= r >= 0 && r < m && rowinv[r] != (int32_t)t;
+    }
+    if (t < nJ) {
+        const int32_t c = J[t];
+        dup |= c >= 0 && c < n && colinv[c] != (int32_t)t;
+    }
+    if (dup) atomicOr(&hdr->err, E_DUP);   // error path only
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void k_asg_count_rest(const PT *__restrict__ arow, int64_t m,
+                                                       const int32_t *__restrict__ rowinv, int32_t *cnt,
+                                                       uint8_t *force, const DevHdr *hdr) {
+    if (hdr->err) return;
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= m || rowinv[r] >= 0) return;
+    cnt[r] = (int32_t)(arow[r + 1] - arow[r]);
+    force[r] = 0;
+}
+
+__device__ __forceinline__ uint32_t vadd(uint32_t a, uint32_t b) {
+    return __float_as_uint(__uint_as_float(a) + __uint_as_float(b));
+}
+__device__ __forceinline__ uint64_t vadd(uint64_t a, uint64_t b) {
+    return (uint64_t)__double_as_longlong(__longlong_as_double((long long)a) +
+                                          __longlong_as_double((long long)b));
+}
+
+// Number of elements < key in the sorted array a[0, len).
+template <typename T>
+__device__ __forceinline__ int lower_bound_n(const T *a, int64_t len, int64_t key) {
+    int64_t lo = 0, hi = len;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (int)lo;
+}
+
+template <typename T>
+__device__ __forceinline__ int64_t find_n(const T *a, int64_t len, int64_t key) {
+    const int64_t p = lower_bound_n(a, len, key);
+    return (p < len && (int64_t)a[p] == key) ? p : -1;
+}
+
+// Number of entries of the (unsorted) array a[0, len) below key.
+__device__ __forceinline__ int count_less(const int32_t *a, int len, int32_t key) {
+    int c = 0;
+    for (int x = 0; x < len; x++) c += a[x] < key;
+    return c;
+}
+
+struct RowSmem {
+    int32_t a[AS_WCAP];    // A's columns
+    int32_t b[AS_WCAP];    // B's columns (indices into J)
+    int32_t k[AS_WCAP];    // B's mapped columns J[b]
+    int32_t ak[AS_WCAP];   // surviving A columns, compacted
+    int32_t o[AS_WCAP];    // all output keys (unsorted case)
+};
+
+// One wavefront per row of B (row I[i] of A).  COUNT: write cnt and the
+// sort flag.  Otherwise write the merged row of C.
+template <typename PT, typename VT, bool COUNT>
+__global__ __launch_bounds__(256) void k_asg_rows_I(
+    const PT *__restrict__ arow, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
+    const PT *__restrict__ brow, const int32_t *__restrict__ bcol, const VT *__restrict__ bval,
+    const int32_t *__restrict__ I, int64_t nI, const int32_t *__restrict__ J, int64_t nJ,
+    const int32_t *__restrict__ colinv, int64_t n, int op, const PT *__restrict__ crow, int32_t *ccol,
+    VT *cval, int32_t *cnt, uint8_t *force, const DevHdr *hdr) {
+    __shared__ __align__(16) RowSmem sm_all[4];
+    if (hdr->err) return;
+    const int w = threadIdx.x / WAVE, l = lane_id();
+    const int64_t i = (int64_t)blockIdx.x * 4 + w;
+    if (i >= nI) return;
+    RowSmem &sm = sm_all[w];
+    const int64_t r = I[i];
+    const int64_t as = arow[r], La = arow[r + 1] - as;
+    const int64_t bs = brow[i], Lb = brow[i + 1] - bs;
+    const bool replace = op == HP_OP_REPLACE, plus = op == HP_OP_PLUS;
+
+    if (COUNT && La * 16 <= Lb) {
+        // few A entries against a long B row: binary-search B in memory
+        // instead of staging it (the count pass then reads little of B)
+        const int32_t *bc = bcol + bs;
+        int nak = 0;
+        for (int64_t a0 = 0; a0 < La; a0 += WAVE) {
+            const int64_t a = a0 + l;
+            bool kept = false;
+            if (a < La) {
+                const int32_t jb = colinv[clampc(acol[as + a], n)];
+                kept = replace ? jb < 0 : (jb < 0 || find_n(bc, Lb, jb) < 0);
+            }
+            nak += __popcll(ballot(kept));
+        }
+        if (l == 0) {
+            cnt[r] = (int32_t)(nak + Lb);
+            force[r] = La + Lb > AS_WCAP ? 1 : 0;
+        }
+        return;
+    }
+    if (La + Lb <= AS_WCAP) {
+        for (int x = l; x < La; x += WAVE) sm.a[x] = acol[as + x];
+        for (int x = l; x < Lb; x += WAVE) {
+            const int32_t cb = bcol[bs + x];
+            sm.b[x] = cb;
+            if (!COUNT) sm.k[x] = J[clampc(cb, nJ)];
+        }
+        __builtin_amdgcn_wave_barrier();
+        // surviving A entries, compacted in A order
+        int nak = 0;
+        for (int a0 = 0; a0 < La; a0 += WAVE) {
+            const int a = a0 + l;
+            bool kept = false;
+            if (a < La) {
+                const int32_t jb = colinv[clampc(sm.a[a], n)];
+                kept = replace ? jb < 0 : (jb < 0 || find_n(sm.b, Lb, jb) < 0);
+            }
+            const uint64_t msk = ballot(kept);
+            if (!COUNT && kept) sm.ak[nak + __popcll(msk & lanemask_lt())] = sm.a[a];
+            nak += __popcll(msk);
+        }
+        if (COUNT) {
+            if (l == 0) {
+                cnt[r] = (int32_t)(nak + Lb);
+                force[r] = 0;
+            }
+            return;
+        }
+        __builtin_amdgcn_wave_barrier();
+        bool inc = true;
+        for (int t0 = 0; t0 + 1 < Lb; t0 += WAVE) {
+            const int t = t0 + l;
+            const bool bad = t + 1 < Lb && sm.k[t] >= sm.k[t + 1];
+            inc = inc && ballot(bad) == 0;
+        }
+        const int64_t d = crow[r];
+        const int L = nak + (int)Lb;
+        if (!inc) {
+            for (int x = l; x < nak; x += WAVE) sm.o[x] = sm.ak[x];
+            for (int x = l; x < Lb; x += WAVE) sm.o[nak + x] = sm.k[x];
+            __builtin_amdgcn_wave_barrier();
+        }
+        // surviving A entries
+        int rank = 0;
+        for (int a0 = 0; a0 < La; a0 += WAVE) {
+            const int a = a0 + l;
+            bool kept = false;
+            int32_t key = 0;
+            if (a < La) {
+                key = sm.a[a];
+                const int32_t jb = colinv[clampc(key, n)];
+                kept = replace ? jb < 0 : (jb < 0 || find_n(sm.b, Lb, jb) < 0);
+            }
+            const uint64_t msk = ballot(kept);
+            if (kept) {
+                const int own = rank + __popcll(msk & lanemask_lt());
+                int pos;
+                if (inc) pos = own + lower_bound_n(sm.k, Lb, key);
+                else pos = count_less(sm.o, L, key);
+                ccol[d + pos] = key;
+                cval[d + pos] = aval[as + a];
+            }
+            rank += __popcll(msk);
+        }
+        // B' entries (values combined with A's where both exist for PLUS)
+        for (int t = l; t < Lb; t += WAVE) {
+            const int32_t key = sm.k[t];
+            VT v = bval[bs + t];
+            if (plus) {
+                const int64_t p = find_n(sm.a, La, key);
+                if (p >= 0) v = vadd(aval[as + p], v);
+            }
+            const int pos = inc ? t + lower_bound_n(sm.ak, nak, key) : count_less(sm.o, L, key);
+            ccol[d + pos] = key;
+            cval[d + pos] = v;
+        }
+        return;
+    }
+
+    // Long row: resolve collisions against the rows in global memory, write
+    // surviving A entries then B' entries, and leave the order to the
+    // segmented sort (force flag set by the count pass).
+    const int32_t *ac = acol + as;
+    const int32_t *bc = bcol + bs;
+    int nak = 0;
+    for (int64_t a0 = 0; a0 < La; a0 += WAVE) {
+        const int64_t a = a0 + l;
+        bool kept = false;
+        if (a < La) {
+            const int32_t jb = colinv[clampc(ac[a], n)];
+            kept = replace ? jb < 0 : (jb < 0 || find_n(bc, Lb, jb) < 0);
+        }
+        const uint64_t msk = ballot(kept);
+        if (!COUNT && kept) {
+            const int64_t pos = (int64_t)crow[r] + nak + __popcll(msk & lanemask_lt());
+            ccol[pos] = ac[a];
+            cval[pos] = aval[as + a];
+        }
+        nak += __popcll(msk);
+    }
+    if (COUNT) {
+        if (l == 0) {
+            cnt[r] = (int32_t)(nak + Lb);
+            force[r] = 1;
+        }
+        return;
+    }
+    for (int64_t t = l; t < Lb; t += WAVE) {
+        const int32_t key = J[clampc(bc[t], nJ)];
+        VT v = bval[bs + t];
+        if (plus) {
+            const int64_t p = find_n(ac, La, key);
+            if (p >= 0) v = vadd(aval[as + p], v);
+        }
+        const int64_t pos = (int64_t)crow[r] + nak + t;
+        ccol[pos] = key;
+        cval[pos] = v;
+    }
+}
+
+// Rows outside I: copy A's row to C's row, 64 rows per wavefront, entries
+// spread over lanes (coalesced reads and writes).
+template <typename PT, typename VT>
+__global__ __launch_bounds__(256) void k_asg_copy_rest(const PT *__restrict__ arow,
+                                                      const int32_t *__restrict__ acol,
+                                                      const VT *__restrict__ aval, int64_t m,
+                                                      const int32_t *__restrict__ rowinv,
+                                                      const PT *__restrict__ crow, int32_t *ccol,
+                                                      VT *cval, const DevHdr *hdr) {
+    __shared__ int32_t s_start[4][WAVE];
+    __shared__ int64_t s_as[4][WAVE], s_cs[4][WAVE];
+    if (hdr->err) return;
+    const int w = threadIdx.x / WAVE, l = lane_id();
+    const int64_t r = ((int64_t)blockIdx.x * 4 + w) * WAVE + l;
+    int len = 0;
+    if (r < m && rowinv[r] < 0) {
+        const int64_t a = arow[r];
+        len = (int)(arow[r + 1] - a);
+        s_as[w][l] = a;
+        s_cs[w][l] = crow[r];
+    }
+    const int incl = wave_incl_scan(len);
+    const int E = __shfl(incl, WAVE - 1, WAVE);
+    s_start[w][l] = incl - len;
+    __builtin_amdgcn_wave_barrier();
+    for (int e0 = 0; e0 < E; e0 += WAVE * 8) {
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int e = e0 + u * WAVE + l;
+            if (e < E) {
+                int lo = 0, hi = WAVE;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_start[w][mid] <= e) lo = mid;
+                    else hi = mid;
+                }
+                const int off = e - s_start[w][lo];
+                ccol[s_cs[w][lo] + off] = acol[s_as[w][lo] + off];
+                cval[s_cs[w][lo] + off] = aval[s_as[w][lo] + off];
+            }
+        }
+    }
+}
+
+hp_status_t asg_check_args(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, const int32_t *I,
+                           const int32_t *J, hp_asgn_op_t op, const hp_csr_t *C) {
+    hp_status_t st = check_csr_args(h, A, "A");
+    if (st) return st;
+    st = check_csr_args(h, B, "B");
+    if (st) return st;
+    if (!C) return fail(h, HP_ERR_INVALID_ARG, "C is NULL");
+    if (op != HP_OP_SECOND && op != HP_OP_PLUS && op != HP_OP_REPLACE)
+        return fail(h, HP_ERR_INVALID_ARG, "unknown assignment operator");
+    if (B->ptr_type != A->ptr_type || B->val_type != A->val_type)
+        return fail(h, HP_ERR_INVALID_ARG, "B must have A's ptr_type and val_type");
+    if ((B->nrows > 0 && !I) || (B->ncols > 0 && !J)) return fail(h, HP_ERR_INVALID_ARG, "I or J is NULL");
+    if (C->nrows != A->nrows || C->ncols != A->ncols) return fail(h, HP_ERR_SHAPE, "C must have A's shape");
+    if (C->ptr_type != A->ptr_type || C->val_type != A->val_type)
+        return fail(h, HP_ERR_INVALID_ARG, "C must have A's ptr_type and val_type");
+    if (!C->rowptr) return fail(h, HP_ERR_INVALID_ARG, "C->rowptr is NULL");
+    return HP_OK;
+}
+
+inline int gridn(int64_t n, int per = 256) { return (int)std::max<int64_t>(1, (n + per - 1) / per); }
+
+template <typename PT, typename VT>
+hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, const int32_t *I,
+                       const int32_t *J, hp_asgn_op_t op, hp_csr_t *C, void *ws, size_t ws_bytes,
+                       hp_plan_info_t *info) {
+    const int64_t m = A->nrows, n = A->ncols, nI = B->nrows, nJ = B->ncols;
+    Carve need(nullptr);
+    asg_layout(need, m, n);
+    if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "spasgn plan workspace too small");
+    const size_t ps = sizeof(PT), vs = sizeof(VT);
+    const void *ins[] = {A->rowptr, A->col, A->val, B->rowptr, B->col, B->val, I, J};
+    const size_t insz[] = {(size_t)(m + 1) * ps, (size_t)A->nnz * 4, (size_t)A->nnz * vs,
+                           (size_t)(nI + 1) * ps, (size_t)B->nnz * 4, (size_t)B->nnz * vs,
+                           (size_t)nI * 4, (size_t)nJ * 4};
+    for (int k = 0; k < 8; k++)
+        if (overlaps(C->rowptr, (m + 1) * ps, ins[k], insz[k]) || overlaps(ws, ws_bytes, ins[k], insz[k]))
+            return fail(h, HP_ERR_ALIAS, "output or workspace overlaps an input");
+    if (overlaps(C->rowptr, (m + 1) * ps, ws, ws_bytes))
+        return fail(h, HP_ERR_ALIAS, "C->rowptr overlaps the workspace");
+    Carve c(ws);
+    AsgLayout L = asg_layout(c, m, n);
+    hipStream_t s = h->stream;
+    stage_begin(h);
+    hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, scan_tiles(m));
+    if (e == hipSuccess) e = launch_fill_words(s, L.rowinv, (size_t)m, 0xFFFFFFFFu);
+    if (e == hipSuccess) e = launch_fill_words(s, L.colinv, (size_t)n, 0xFFFFFFFFu);
+    if (e == hipSuccess) {
+        const int64_t hi = std::max(nI, nJ);
+        hipLaunchKernelGGL(k_asg_inv, dim3(gridn(hi)), dim3(256), 0, s, I, nI, J, nJ, m, n, L.rowinv,
+                           L.colinv, L.hdr);
+        hipLaunchKernelGGL(k_asg_dup, dim3(gridn(hi)), dim3(256), 0, s, I, nI, J, nJ, m, n, L.rowinv,
+                           L.colinv, L.hdr);
+        stage_mark(h, "asgn.tables");
+        hipLaunchKernelGGL(k_asg_count_rest<PT>, dim3(gridn(m)), dim3(256), 0, s, (const PT *)A->rowptr, m,
+                           L.rowinv, L.cnt, L.force, L.hdr);
+        if (nI > 0)
+            hipLaunchKernelGGL((k_asg_rows_I<PT, VT, true>), dim3(gridn(nI, 4)), dim3(256), 0, s,
+                               (const PT *)A->rowptr, A->col, (const VT *)A->val, (const PT *)B->rowptr, B->col,
+                               (const VT *)B->val, I, nI, J, nJ, L.colinv, n, (int)op, (const PT *)nullptr,
+                               (int32_t *)nullptr, (VT *)nullptr, L.cnt, L.force, L.hdr);
+        stage_mark(h, "asgn.count");
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        e = launch_scan_counts<PT>(s, L.cnt, (PT *)C->rowptr, m, L.hdr, 0, L.tiles, 4, L.lists, m, L.force);
+        stage_mark(h, "asgn.scan");
+    }
+    if (e == hipSuccess) e = readback_hdr(h, L.hdr);
+    stage_end(h);
+    if (e != hipSuccess) return hip_check(h, e, "spasgn plan");
+    const DevHdr &H = *h->host_hdr;
+    hp_status_t stt = status_from_err(h, H.err, "spasgn");
+    if (stt) return stt;
+    C->nnz = (int64_t)H.total[0];
+    if (info) {
+        *info = hp_plan_info_t{};
+        info->nnz_out = C->nnz;
+        info->op = 3;
+        for (int b = 0; b < NBINS; b++) {
+            info->rows_sorted[b] = H.bin_cnt[b];
+            info->class_elems[b] = (int64_t)H.bin_elems[b];
+        }
+        info->aux[0] = (int64_t)op;
+        info->exec_ws_bytes = seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], H.bin_cnt[BIN_GLOBAL], vs, n);
+    }
+    return HP_OK;
+}
+
+template <typename PT, typename VT>
+hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, const int32_t *I,
+                       const int32_t *J, hp_asgn_op_t op, hp_csr_t *C, void *ws, size_t ws_bytes,
+                       const hp_plan_info_t *info, void *xws, size_t xws_bytes) {
+    const int64_t m = A->nrows, n = A->ncols, nI = B->nrows, nJ = B->ncols;
+    Carve need(nullptr);
+    asg_layout(need, m, n);
+    if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "spasgn workspace too small");
+    if (!info || info->op != 3 || info->aux[0] != (int64_t)op)
+        return fail(h, HP_ERR_INVALID_ARG, "info is not from hp_spasgn_plan with this operator");
+    if (xws_bytes < info->exec_ws_bytes || (info->exec_ws_bytes && !xws))
+        return fail(h, HP_ERR_WORKSPACE, "spasgn exec workspace too small");
+    if (C->nnz != info->nnz_out) return fail(h, HP_ERR_INVALID_ARG, "C->nnz differs from the plan");
+    if (C->nnz > 0 && (!C->col || !C->val)) return fail(h, HP_ERR_INVALID_ARG, "C->col/val is NULL");
+    const size_t vs = sizeof(VT), ps = sizeof(PT);
+    const void *ins[] = {A->rowptr, A->col, A->val, B->rowptr, B->col, B->val, I, J, ws, xws, C->rowptr};
+    const size_t insz[] = {(size_t)(m + 1) * ps, (size_t)A->nnz * 4, (size_t)A->nnz * vs,
+                           (size_t)(nI + 1) * ps, (size_t)B->nnz * 4, (size_t)B->nnz * vs,
+                           (size_t)nI * 4, (size_t)nJ * 4, ws_bytes, xws_bytes, (size_t)(m + 1) * ps};
+    for (int k = 0; k < 11; k++)
+        if (overlaps(C->col, (size_t)C->nnz * 4, ins[k], insz[k]) ||
+            overlaps(C->val, (size_t)C->nnz * vs, ins[k], insz[k]))
+            return fail(h, HP_ERR_ALIAS, "C->col/val overlaps an input or workspace");
+    Carve c(ws);
+    AsgLayout L = asg_layout(c, m, n);
+    hipStream_t s = h->stream;
+    stage_begin(h);
+    hipLaunchKernelGGL((k_asg_copy_rest<PT, VT>), dim3(gridn(m)), dim3(256), 0, s, (const PT *)A->rowptr,
+                       A->col, (const VT *)A->val, m, L.rowinv, (const PT *)C->rowptr, C->col, (VT *)C->val,
+                       L.hdr);
+    stage_mark(h, "asgn.copy");
+    if (nI > 0)
+        hipLaunchKernelGGL((k_asg_rows_I<PT, VT, false>), dim3(gridn(nI, 4)), dim3(256), 0, s,
+                           (const PT *)A->rowptr, A->col, (const VT *)A->val, (const PT *)B->rowptr, B->col,
+                           (const VT *)B->val, I, nI, J, nJ, L.colinv, n, (int)op, (const PT *)C->rowptr, C->col,
+                           (VT *)C->val, L.cnt, L.force, L.hdr);
+    stage_mark(h, "asgn.merge");
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        uint32_t cnt[NBINS];
+        for (int b = 0; b < NBINS; b++) cnt[b] = (uint32_t)info->rows_sorted[b];
+        LoadInPlace<PT, VT> ld{(const PT *)C->rowptr, C->col, (const VT *)C->val};
+        e = launch_seg_classes<PT, VT, LoadInPlace<PT, VT>>(s, (const PT *)C->rowptr, C->col, (VT *)C->val,
+                                                            L.lists, m, cnt, ld, false, n, true, xws,
+                                                            (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);
+        stage_mark(h, "asgn.sort");
+    }
+    stage_end(h);
+    return hip_check(h, e == hipSuccess ? hipGetLastError() : e, "spasgn exec");
+}
+
+}  // namespace
+
+extern "C" hp_status_t hp_spasgn_workspace(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B,
+                                           size_t *bytes) {
+    if (!h || !bytes) return HP_ERR_INVALID_ARG;
+    hp_status_t st = check_csr_args(h, A, "A");
+    if (st) return st;
+    (void)B;
+    Carve c(nullptr);
+    asg_layout(c, A->nrows, A->ncols);
+    *bytes = c.size();
+    return HP_OK;
+}
+
+extern "C" hp_status_t hp_spasgn_plan(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B,
+                                      const int32_t *I, const int32_t *J, hp_asgn_op_t op, hp_csr_t *C,
+                                      void *ws, size_t ws_bytes, hp_plan_info_t *info) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    hp_status_t st = asg_check_args(h, A, B, I, J, op, C);
+    if (st) return st;
+    const bool p64 = A->ptr_type == HP_IDX_I64, v64 = A->val_type == HP_VAL_F64;
+    if (!p64 && !v64) return asg_plan_t<int32_t, uint32_t>(h, A, B, I, J, op, C, ws, ws_bytes, info);
+    if (!p64 && v64) return asg_plan_t<int32_t, uint64_t>(h, A, B, I, J, op, C, ws, ws_bytes, info);
+    if (p64 && !v64) return asg_plan_t<int64_t, uint32_t>(h, A, B, I, J, op, C, ws, ws_bytes, info);
+    return asg_plan_t<int64_t, uint64_t>(h, A, B, I, J, op, C, ws, ws_bytes, info);
+}
+
+extern "C" hp_status_t hp_spasgn_exec(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B,
+                                      const int32_t *I, const int32_t *J, hp_asgn_op_t op, hp_csr_t *C,
+                                      void *ws, size_t ws_bytes, const hp_plan_info_t *info, void *xws,
+                                      size_t xws_bytes) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    hp_status_t st = asg_check_args(h, A, B, I, J, op, C);
+    if (st) return st;
+    const bool p64 = A->ptr_type == HP_IDX_I64, v64 = A->val_type == HP_VAL_F64;
+    if (!p64 && !v64) return asg_exec_t<int32_t, uint32_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, xws, xws_bytes);
+    if (!p64 && v64) return asg_exec_t<int32_t, uint64_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, xws, xws_bytes);
+    if (p64 && !v64) return asg_exec_t<int64_t, uint32_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, xws, xws_bytes);
+    return asg_exec_t<int64_t, uint64_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, xws, xws_bytes);
+}

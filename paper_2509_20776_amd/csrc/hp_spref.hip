@@ -47,6 +47,7 @@ struct SprefLayout {
     int32_t *jpos, *Dn;
     int64_t *rs;           // start of row I[i] in A
     int32_t *rl, *ch;
+    uint8_t *big;          // 1 for rows assembled by big-row chunks
     int64_t *cp;
     int32_t *cursor;       // big-row fill cursors (exec)
     uint32_t *lists;
@@ -72,6 +73,7 @@ SprefLayout spref_layout(Carve &c, int64_t n, int64_t nI, int64_t nJ) {
     L.rs = c.take<int64_t>(nI + 1);
     L.rl = c.take<int32_t>(nI + 1);
     L.ch = c.take<int32_t>(nI + 1);
+    L.big = c.take<uint8_t>(nI + 1);
     L.cp = c.take<int64_t>(nI + 1);
     L.cursor = c.take<int32_t>(nI + 1);
     L.lists = c.take<uint32_t>(seg_list_words(nI));
@@ -139,7 +141,7 @@ template <typename PT>
 __global__ __launch_bounds__(256) void k_spref_rows(const PT *__restrict__ arow,
                                                    const int32_t *__restrict__ I, int64_t nI,
                                                    int64_t m, int64_t *rs, int32_t *rl, int32_t *ch,
-                                                   DevHdr *hdr) {
+                                                   uint8_t *big, DevHdr *hdr) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nI) return;
     const int32_t r = I[i];
@@ -152,6 +154,7 @@ __global__ __launch_bounds__(256) void k_spref_rows(const PT *__restrict__ arow,
     rs[i] = s;
     rl[i] = (int32_t)len;
     ch[i] = len > SR_LB ? (int32_t)((len + SR_BW - 1) / SR_BW) : 0;
+    big[i] = len > SR_LB ? 1 : 0;
 }
 
 // ---- shared pieces of count and gather -------------------------------------
@@ -460,7 +463,7 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
         hipLaunchKernelGGL(k_spref_jlink, dim3(grid1(nJ)), dim3(256), 0, s, J, nJ, L.jpos, L.Dn);
         stage_mark(h, "spref.jtables");
         hipLaunchKernelGGL(k_spref_rows<PT>, dim3(grid1(nI)), dim3(256), 0, s, (const PT *)A->rowptr, I,
-                           nI, m, L.rs, L.rl, L.ch, L.hdr);
+                           nI, m, L.rs, L.rl, L.ch, L.big, L.hdr);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = launch_scan_counts<int64_t>(s, L.ch, L.cp, nI, L.hdr, 0, L.tiles, 0, nullptr, 0);
@@ -474,7 +477,7 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     }
     if (e == hipSuccess) {
         e = launch_scan_counts<PT>(s, L.cnt, (PT *)C->rowptr, nI, L.hdr, 1, L.tiles + st, 3, L.lists, nI,
-                                   L.ch, L.nm);
+                                   L.big, L.nm);
         stage_mark(h, "spref.scan");
     }
     if (e == hipSuccess) e = readback_hdr(h, L.hdr);

@@ -1,0 +1,86 @@
+// Canonical-CSR check: rowptr[0] = 0, rowptr non-decreasing, rowptr[m] =
+// nnz, every column in [0, ncols) and columns strictly increasing inside a
+// row.  Row starts are marked in a byte array so that the entry pass can
+// tell "first entry of a row" from "follows an entry of the same row".
+#include "hp_internal.hpp"
+
+using namespace hp;
+
+namespace {
+
+template <typename PT>
+__global__ __launch_bounds__(256) void k_val_rows(const PT *__restrict__ rowptr, int64_t m, int64_t nnz,
+                                                 uint8_t *start, DevHdr *hdr) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r > m) return;
+    const int64_t s = rowptr[r];
+    bool bad = false;
+    if (r == 0) bad |= s != 0;
+    if (r == m) bad |= s != nnz;
+    if (r < m) {
+        const int64_t e = rowptr[r + 1];
+        bad |= e < s || s < 0 || e > nnz;
+        if (!bad && e > s) start[s] = 1;
+    }
+    if (bad) atomicOr(&hdr->err, E_NONCANON);   // error path only
+}
+
+__global__ __launch_bounds__(256) void k_val_entries(const int32_t *__restrict__ col, int64_t nnz,
+                                                    int64_t n, const uint8_t *__restrict__ start,
+                                                    DevHdr *hdr) {
+    if (hdr->err) return;
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= nnz) return;
+    const int32_t c = col[k];
+    uint32_t e = 0;
+    if (c < 0 || c >= n) e |= E_RANGE;
+    if (k > 0 && !start[k] && col[k - 1] >= c) e |= E_NONCANON;
+    if (e) atomicOr(&hdr->err, e);   // error path only
+}
+
+size_t val_ws(const hp_csr_t *A) {
+    Carve c(nullptr);
+    c.take<DevHdr>(1);
+    c.take<uint8_t>((size_t)A->nnz + 16);
+    return c.size();
+}
+
+}  // namespace
+
+extern "C" hp_status_t hp_validate_workspace(hp_handle_t h, const hp_csr_t *A, size_t *bytes) {
+    if (!h || !bytes) return HP_ERR_INVALID_ARG;
+    hp_status_t st = check_csr_args(h, A, "A");
+    if (st) return st;
+    *bytes = val_ws(A);
+    return HP_OK;
+}
+
+extern "C" hp_status_t hp_validate_csr(hp_handle_t h, const hp_csr_t *A, void *ws, size_t ws_bytes) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    hp_status_t st = check_csr_args(h, A, "A");
+    if (st) return st;
+    if (!ws || ws_bytes < val_ws(A)) return fail(h, HP_ERR_WORKSPACE, "validate workspace too small");
+    Carve c(ws);
+    DevHdr *hdr = c.take<DevHdr>(1);
+    uint8_t *start = c.take<uint8_t>((size_t)A->nnz + 16);
+    hipStream_t s = h->stream;
+    const int64_t m = A->nrows, nnz = A->nnz;
+    hipError_t e = launch_init_hdr(s, hdr, nullptr, 0);
+    if (e == hipSuccess) e = launch_clear_words(s, start, ((size_t)nnz + 16) / 4);
+    if (e == hipSuccess) {
+        const unsigned gr = (unsigned)std::max<int64_t>(1, (m + 1 + 255) / 256);
+        if (A->ptr_type == HP_IDX_I64)
+            hipLaunchKernelGGL(k_val_rows<int64_t>, dim3(gr), dim3(256), 0, s, (const int64_t *)A->rowptr, m, nnz,
+                               start, hdr);
+        else
+            hipLaunchKernelGGL(k_val_rows<int32_t>, dim3(gr), dim3(256), 0, s, (const int32_t *)A->rowptr, m, nnz,
+                               start, hdr);
+        if (nnz > 0)
+            hipLaunchKernelGGL(k_val_entries, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, A->col, nnz,
+                               A->ncols, start, hdr);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = readback_hdr(h, hdr);
+    if (e != hipSuccess) return hip_check(h, e, "validate");
+    return status_from_err(h, h->host_hdr->err, "validate");
+}

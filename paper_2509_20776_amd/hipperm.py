@@ -79,6 +79,12 @@ hp_permute_exec = _sig("hp_permute_exec", [_P, _CSRP, _P, _P, _CSRP, _P, _SZ, _I
 hp_spref_workspace = _sig("hp_spref_workspace", [_P, _CSRP, _I64, _I64, ctypes.POINTER(_SZ)])
 hp_spref_plan = _sig("hp_spref_plan", [_P, _CSRP, _P, _I64, _P, _I64, _CSRP, _P, _SZ, _INFOP])
 hp_spref_exec = _sig("hp_spref_exec", [_P, _CSRP, _P, _I64, _P, _I64, _CSRP, _P, _SZ, _INFOP, _P, _SZ])
+hp_validate_workspace = _sig("hp_validate_workspace", [_P, _CSRP, ctypes.POINTER(_SZ)])
+hp_validate_csr = _sig("hp_validate_csr", [_P, _CSRP, _P, _SZ])
+hp_spasgn_workspace = _sig("hp_spasgn_workspace", [_P, _CSRP, _CSRP, ctypes.POINTER(_SZ)])
+hp_spasgn_plan = _sig("hp_spasgn_plan", [_P, _CSRP, _CSRP, _P, _P, ctypes.c_int, _CSRP, _P, _SZ, _INFOP])
+hp_spasgn_exec = _sig("hp_spasgn_exec", [_P, _CSRP, _CSRP, _P, _P, ctypes.c_int, _CSRP, _P, _SZ, _INFOP,
+                                         _P, _SZ])
 
 @dataclass
 class CSR:
@@ -175,6 +181,15 @@ class Handle:
     def _alloc(self, nbytes):
         return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=f"cuda:{self.device}")
 
+    def validate(self, A):
+        """Raise HPError unless A is canonical CSR (hp_validate_csr)."""
+        self._stream()
+        Ac = to_csr_t(A)
+        need = _SZ(0)
+        self.check(hp_validate_workspace(self.h, ctypes.byref(Ac), ctypes.byref(need)))
+        ws = self._alloc(need.value)
+        self.check(hp_validate_csr(self.h, ctypes.byref(Ac), _dptr(ws), ws.numel()))
+
     # ---- permute -----------------------------------------------------------
     def permute_plan(self, A, p, q=None, ws=None):
         """Plan C = P A Q^T; returns (C with rowptr filled, ws, info)."""
@@ -245,6 +260,49 @@ class Handle:
         C, ws, info = self.spref_plan(A, I, J)
         return self.spref_exec(A, I, J, C, ws, info)
 
+    # ---- spasgn ------------------------------------------------------------
+    @staticmethod
+    def _op(op):
+        if isinstance(op, str):
+            if op not in OPS:
+                raise HPError(1, f"unknown operator {op!r}")
+            return OPS[op]
+        return int(op)
+
+    def spasgn_plan(self, A, B, I, J, op="second", ws=None):
+        """Plan C = A with A(I, J) = B; returns (C with rowptr filled, ws, info)."""
+        self._stream()
+        if int(I.numel()) != B.nrows or int(J.numel()) != B.ncols:
+            raise HPError(6, "B must be |I| x |J|")
+        Ac, Bc = to_csr_t(A), to_csr_t(B)
+        need = _SZ(0)
+        self.check(hp_spasgn_workspace(self.h, ctypes.byref(Ac), ctypes.byref(Bc), ctypes.byref(need)))
+        if ws is None or ws.numel() < need.value:
+            ws = self._alloc(need.value)
+        rowptr = torch.empty(A.nrows + 1, dtype=A.rowptr.dtype, device=A.rowptr.device)
+        Cc = hp_csr_t(A.nrows, A.ncols, 0, Ac.ptr_type, Ac.val_type, _dptr(rowptr), None, None)
+        info = hp_plan_info_t()
+        self.check(hp_spasgn_plan(self.h, ctypes.byref(Ac), ctypes.byref(Bc), _idx(I), _idx(J),
+                                  self._op(op), ctypes.byref(Cc), _dptr(ws), ws.numel(), ctypes.byref(info)))
+        C = CSR(A.nrows, A.ncols, rowptr, torch.empty(Cc.nnz, dtype=torch.int32, device=A.col.device),
+                torch.empty(Cc.nnz, dtype=A.val.dtype, device=A.val.device))
+        return C, ws, info
+
+    def spasgn_exec(self, A, B, I, J, C, ws, info, op="second", xws=None):
+        self._stream()
+        Ac, Bc, Cc = to_csr_t(A), to_csr_t(B), to_csr_t(C)
+        if info.exec_ws_bytes and (xws is None or xws.numel() < info.exec_ws_bytes):
+            xws = self._alloc(info.exec_ws_bytes)
+        self.check(hp_spasgn_exec(self.h, ctypes.byref(Ac), ctypes.byref(Bc), _idx(I), _idx(J),
+                                  self._op(op), ctypes.byref(Cc), _dptr(ws), ws.numel(), ctypes.byref(info),
+                                  _dptr(xws) if xws is not None else None,
+                                  xws.numel() if xws is not None else 0))
+        return C
+
+    def spasgn(self, A, B, I, J, op="second"):
+        C, ws, info = self.spasgn_plan(A, B, I, J, op)
+        return self.spasgn_exec(A, B, I, J, C, ws, info, op)
+
 
 _default = {}
 
@@ -263,3 +321,8 @@ def permute(A, p, q=None, device: int = 0) -> CSR:
 def spref(A, I, J, device: int = 0) -> CSR:
     """C = A(I, J) with C[i, j] = A[I[i], J[j]]; repeated/unordered indices allowed."""
     return handle(device).spref(A, I, J)
+
+
+def spasgn(A, B, I, J, op="second", device: int = 0) -> CSR:
+    """C = A with A(I, J) = B; op: "second" (overwrite), "plus" or "replace" (block)."""
+    return handle(device).spasgn(A, B, I, J, op)

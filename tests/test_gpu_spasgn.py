@@ -1,0 +1,135 @@
+"""GPU parity for spasgn (A(I, J) = B): bit-exact against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests._gpu import assert_same, mixed_csr, np_csr, rows_of, sample_rows
+
+pytestmark = pytest.mark.gpu
+OPS = ["second", "plus", "replace"]
+
+
+@pytest.fixture(scope="module")
+def hp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_20776_amd import hipperm
+    return hipperm
+
+
+def _t(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.int32), device="cuda")
+
+
+def _block(seed, nI, nJ, density, ptr, vdt):
+    return synth.bernoulli_block(nI, nJ, density, seed, "tblk", ptr, vdt, "cuda")
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_grid_contiguous_block(hp, op):
+    w = synth.workload_grid(side=128, frac=0.10, density=0.02, device="cuda")
+    A, B, I, J = w["A"], w["B"], w["I"], w["J"]
+    C = hp.spasgn(A, B, I, J, op)
+    assert_same(np_csr(C), oracle.spasgn(A, B, I, J, op), f"grid {op}")
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("ptr,vdt", [(torch.int32, torch.float32), (torch.int64, torch.float64)])
+def test_rmat_random_index_sets(hp, op, ptr, vdt):
+    A = synth.rmat(12, 8, 3, "asg", symmetric=False, ptr_dtype=ptr, val_dtype=vdt, device="cuda")
+    rng = np.random.default_rng(4)
+    I = _t(rng.choice(A.nrows, 700, replace=False))
+    J = _t(rng.choice(A.ncols, 900, replace=False))
+    B = _block(5, 700, 900, 0.03, ptr, vdt)
+    C = hp.spasgn(A, B, I, J, op)
+    assert_same(np_csr(C), oracle.spasgn(A, B, I, J, op), f"rmat {op}")
+    # sorted index sets take the merge path
+    Is, Js = torch.sort(I).values, torch.sort(J).values
+    C2 = hp.spasgn(A, B, Is, Js, op)
+    assert_same(np_csr(C2), oracle.spasgn(A, B, Is, Js, op), f"rmat sorted {op}")
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_long_rows_fallback(hp, op):
+    m, n = 300, 6000
+    A = mixed_csr(31, m, n, [0, 3, 100, 250, 700, 5000])
+    rng = np.random.default_rng(8)
+    I = _t(rng.choice(m, 120, replace=False))
+    J = _t(rng.choice(n, 5000, replace=False))
+    B = mixed_csr(32, 120, 5000, [0, 10, 200, 300, 4500])
+    C = hp.spasgn(A, B, I, J, op)
+    assert_same(np_csr(C), oracle.spasgn(A, B, I, J, op), f"long rows {op}")
+
+
+def test_empty_and_errors(hp):
+    A = mixed_csr(33, 40, 50, [0, 2, 6])
+    I = _t([3, 7, 9])
+    J = _t([1, 4])
+    B0 = mixed_csr(34, 3, 2, [0])
+    assert_same(np_csr(hp.spasgn(A, B0, I, J)), np_csr(A), "empty B")
+    e = _t(np.zeros(0))
+    Be = mixed_csr(35, 0, 0, [0])
+    assert_same(np_csr(hp.spasgn(A, Be, e, e)), np_csr(A), "empty I, J")
+    B = mixed_csr(36, 3, 2, [1, 2])
+    with pytest.raises(hp.HPError) as ex:
+        hp.spasgn(A, B, _t([3, 3, 9]), J)
+    assert ex.value.name == "HP_ERR_DUPLICATE_INDEX"
+    with pytest.raises(hp.HPError) as ex:
+        hp.spasgn(A, B, I, _t([1, 50]))
+    assert ex.value.name == "HP_ERR_INDEX_RANGE"
+    with pytest.raises(hp.HPError) as ex:
+        hp.spasgn(A, B, _t([3, 7]), J)
+    assert ex.value.name == "HP_ERR_SHAPE"
+
+
+def test_streaming_round_trip(hp):
+    """80% of the edges plus four 5% parts assigned back gives A again."""
+    A = synth.rmat(11, 8, 9, "rt", symmetric=False, device="cuda")
+    rp, col, val = np_csr(A)
+    rows = np.repeat(np.arange(A.nrows), np.diff(rp))
+    lab = np.random.default_rng(10).choice(5, size=len(col), p=[0.8, 0.05, 0.05, 0.05, 0.05])
+
+    def sub(mask):
+        r, c, v = rows[mask], col[mask], val[mask]
+        return r, c, v
+
+    r0, c0, v0 = sub(lab == 0)
+    cnt = np.bincount(r0, minlength=A.nrows)
+    cur = synth.CSR(A.nrows, A.ncols, torch.from_numpy(np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)).cuda(),
+                    torch.from_numpy(c0).cuda(), torch.from_numpy(v0).cuda())
+    for part in range(1, 5):
+        r, c, v = sub(lab == part)
+        I = np.unique(r)
+        J = np.unique(c)
+        ri = np.searchsorted(I, r)
+        cj = np.searchsorted(J, c).astype(np.int32)
+        order = np.lexsort((cj, ri))
+        bc = np.bincount(ri, minlength=len(I))
+        B = synth.CSR(len(I), len(J), torch.from_numpy(np.concatenate([[0], np.cumsum(bc)]).astype(np.int32)).cuda(),
+                      torch.from_numpy(cj[order]).cuda(), torch.from_numpy(v[order]).cuda())
+        cur = hp.spasgn(cur, B, _t(I), _t(J), "second")
+    assert_same(np_csr(cur), np_csr(A), "round trip")
+
+
+def test_grid_full_size_sampled(hp):
+    """4096^2 grid, int64 rowptr, fp64; I = J a contiguous 10% range; B at density 1e-4."""
+    w = synth.workload_grid(side=4096, device="cuda")
+    A, B, I, J = w["A"], w["B"], w["I"], w["J"]
+    C = hp.spasgn(A, B, I, J, "second")
+    torch.cuda.synchronize()
+    r0, r1 = int(I[0]), int(I[-1]) + 1
+    rows = np.unique(np.concatenate([sample_rows(17, A.nrows, 16), np.arange(r0, r0 + 8),
+                                     np.arange(r1 - 8, r1 + 8)]))
+    assert_same(rows_of(C, rows), oracle.spasgn(A, B, I, J, "second", rows=rows), "sampled rows")
+    # rows outside I are A's rows, shifted
+    arp, crp = A.rowptr, C.rowptr
+    assert torch.equal(C.col[:int(crp[r0])], A.col[:int(arp[r0])])
+    assert torch.equal(C.col[int(crp[r1]):], A.col[int(arp[r1]):])
+    assert torch.equal(C.val[int(crp[r1]):].view(torch.int64), A.val[int(arp[r1]):].view(torch.int64))
+    # block replace then extraction returns B exactly
+    R = hp.spasgn(A, B, I, J, "replace")
+    X = hp.spref(R, I, J)
+    assert torch.equal(X.rowptr, B.rowptr) and torch.equal(X.col, B.col)
+    assert torch.equal(X.val.view(torch.int64), B.val.view(torch.int64))
