@@ -169,6 +169,58 @@ hp_status_t hp_spasgn_exec(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, 
                            size_t ws_bytes, const hp_plan_info_t *info, void *xws,
                            size_t xws_bytes);
 
+/* ---- batched form -------------------------------------------------------- */
+/* Many extraction (paper Sec. 2.2, Alg. 3) and permutation (Sec. 2.1,
+ * Alg. 1) requests run together.  The plan half (J tables / inverse
+ * permutations, counts, rowptr scans of every request) is a short sequence of
+ * stage launches, each running the tiles of every request on persistent
+ * workgroups, followed by one readback of all output sizes.  The exec half
+ * (fill and row sort of every request) is a second sequence of stage
+ * launches, captured once in a hipGraph and replayed for any later batch
+ * with the same workspace, arena, grid and stage shapes.  Stream order
+ * between the stages is the only inter-tile dependency.  The number of
+ * persistent workgroups is picked per size class by timing candidates the
+ * first time the class is seen (the halves are idempotent).
+ * Results are identical, bit for bit, to separate plain calls.
+ * All requests of one batch share ptr_type and val_type.
+ * Ownership: the caller owns the workspace and the arena; results point
+ * into the arena.  hp_batch_exec must follow the hp_batch_plan of the same
+ * batch on the same handle and workspace. */
+typedef enum { HP_REQ_SPREF = 0, HP_REQ_PERMUTE = 1 } hp_req_kind_t;
+
+typedef struct {
+    int32_t kind;          /* hp_req_kind_t                                        */
+    int32_t status;        /* out: hp_status_t of this request after plan/exec     */
+    hp_csr_t A;            /* input matrix (device arrays)                         */
+    const int32_t *I, *J;  /* spref: selected rows / columns (device)              */
+    int64_t nI, nJ;
+    const int32_t *p, *q;  /* permute: permutations (device); q NULL = symmetric    */
+    hp_csr_t C;            /* out: shape/types/nnz after plan; rowptr/col/val point
+                              into the arena after exec                            */
+} hp_request_t;
+
+typedef struct {
+    size_t arena_bytes;    /* arena the exec call needs                            */
+    int64_t nnz_total;     /* sum of the requests' output nnz                       */
+    int32_t failed;        /* requests whose plan status is not HP_OK               */
+    int32_t grid_plan;     /* persistent workgroups per plan stage (autotuned)     */
+    int64_t tiles_plan;    /* tiles over all plan stages                            */
+    int64_t tiles_exec;    /* tiles over all exec stages (set by exec)              */
+    int32_t grid_exec;     /* persistent workgroups per exec stage (set by exec)    */
+    int32_t reserved;
+} hp_batch_info_t;
+
+/* Workspace for a batch (tables, counters and rowptrs of every request). */
+hp_status_t hp_batch_workspace(hp_handle_t h, const hp_request_t *reqs, int n, size_t *bytes);
+/* Plan every request: per-request status and C.nnz; info->arena_bytes.
+ * Returns HP_OK even when single requests fail (see reqs[k].status). */
+hp_status_t hp_batch_plan(hp_handle_t h, hp_request_t *reqs, int n, void *ws, size_t ws_bytes,
+                          hp_batch_info_t *info);
+/* Exec the planned requests into the caller's arena (rowptr, col, val of
+ * every request with status HP_OK; failed requests are skipped). */
+hp_status_t hp_batch_exec(hp_handle_t h, hp_request_t *reqs, int n, void *ws, size_t ws_bytes,
+                          hp_batch_info_t *info, void *arena, size_t arena_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,772 @@
+// Batched form: many extraction / permutation requests planned and executed
+// together.
+//
+// Every request is broken into phases of tiles (a tile = one workgroup of
+// work, run by the same tile functions as the plain per-call kernels):
+//   spref  plan  0 clear  1 J scatter  2 selected rows  3 J pack  4 J link
+//                5 long-row chunk scan  6 count  7 rowptr scan (+ classes)
+//          exec  0 clear cursors, copy rowptr  1 gather  2 short-row sort
+//                3-7 class sorts (thread, wave, block, bucket split, bucket)
+//   permute plan 0 clear, fill -1  1 scatter inverses + counts  2 check
+//                3 rowptr scan (+ classes)
+//          exec  0 copy rowptr  1 short rows  3-7 class sorts (pull from A)
+// Phases are grouped into stages (stage_of): a stage only holds phases
+// whose inputs were written by earlier stages, so one launch per stage runs
+// the tiles of every request of the batch, and stream order between the
+// launches is the only dependency mechanism -- no workgroup ever waits for
+// another one's tile, except inside a scan.  The workgroups of a launch are
+// persistent and take tiles from an atomic ticket in queue order, so the
+// tiles of one scan start in order and its look-back only waits on tiles
+// that are already running (the same argument as the plain scan kernel).
+// The exec half is captured once as a hipGraph and replayed.
+#include "hp_internal.hpp"
+#include "hp_scan.hpp"
+#include "hp_segsort.hpp"
+#include "hp_spref_tiles.hpp"
+#include "hp_perm_tiles.hpp"
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace hp;
+
+namespace {
+
+constexpr int NPH = 8;                 // phases per half
+constexpr int NST = 6;                 // stages per half (at most)
+constexpr int CLEAR_PER_TILE = 4096;   // words cleared / copied per tile
+
+// Stage of each phase, per half and request kind (-1: phase not used).
+//   spref plan: {0} {1,2} {3,5} {4} {6} {7}; exec: {0} {1} {2..6} {7}
+//   permute plan: {0} {1} {2} {3};  exec: {0,1} {3..6} {7}
+constexpr int8_t STAGE_OF[2][2][NPH] = {
+    {{0, 1, 1, 2, 3, 2, 4, 5}, {0, 1, 2, 3, -1, -1, -1, -1}},
+    {{0, 1, 2, 2, 2, 2, 2, 3}, {0, 0, -1, 1, 1, 1, 1, 2}},
+};
+
+struct ReqDev {
+    int32_t kind, sym, monotone, active;
+    int64_t m, n, nnz, nI, nJ, nrows_out, ncols_out;
+    const void *arow;
+    const int32_t *acol;
+    const void *aval;
+    const int32_t *I, *J, *p, *q;
+    DevHdr *hdr;
+    uint32_t *zero;          // cleared in plan phase 0
+    int64_t nzero;
+    int32_t *fill;           // filled with -1 in plan phase 0 (permute)
+    int64_t nfill;
+    uint64_t *tiles0, *tiles1;
+    uint8_t *mark;
+    uint32_t *dm, *nm, *bm;
+    int64_t nw;
+    int32_t *cnt, *jpos, *Dn;
+    int64_t *rs;
+    int32_t *rl, *ch;
+    uint8_t *big;
+    int64_t *cp;
+    int32_t *cursor;
+    uint32_t *lists;
+    int32_t *pinv, *qinv;
+    void *crow_tmp;          // rowptr of the result, written by plan
+    void *crow;              // exec: arena copies
+    int32_t *ccol;
+    void *cval;
+    void *tmp;
+    uint64_t glob_elems;
+    int32_t nb, nbw;
+    uint32_t cls[NBINS];
+};
+
+struct QEntry {
+    int64_t first;       // first ticket of the entry within its stage
+    int32_t req, phase;
+};
+
+union BatchSmem {
+    ScanSmem scan;
+    spref::GroupSmem gs[4];
+    SegSmemWave wave;
+    SegSmemBlock block;
+    SegSmemBucket bucket;
+};
+
+__device__ inline void clear_tile(int64_t tile, uint32_t *p, int64_t n) {
+    const int64_t b = tile * CLEAR_PER_TILE;
+    for (int64_t k = b + threadIdx.x; k < min(b + CLEAR_PER_TILE, n); k += 256) p[k] = 0u;
+}
+__device__ inline void fill_tile(int64_t tile, int32_t *p, int64_t n) {
+    const int64_t b = tile * CLEAR_PER_TILE;
+    for (int64_t k = b + threadIdx.x; k < min(b + CLEAR_PER_TILE, n); k += 256) p[k] = -1;
+}
+template <typename PT>
+__device__ inline void copy_rowptr_tile(int64_t tile, const PT *src, PT *dst, int64_t n) {
+    const int64_t b = tile * CLEAR_PER_TILE;
+    for (int64_t k = b + threadIdx.x; k < min(b + CLEAR_PER_TILE, n); k += 256) dst[k] = src[k];
+}
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <typename PT, typename VT>
+__device__ void run_tile(int half, int phase, int64_t tile, const ReqDev &r, BatchSmem &sm) {
+    uint64_t *goff = reinterpret_cast<uint64_t *>(r.lists + NBINS * (r.kind == HP_REQ_SPREF ? r.nI : r.m));
+    const int64_t cap = r.kind == HP_REQ_SPREF ? r.nI : r.m;
+    if (half == 0) {
+        if (r.kind == HP_REQ_SPREF) {
+            switch (phase) {
+                case 0:
+                    clear_tile(tile, r.zero, r.nzero);
+                    if (tile == 0 && threadIdx.x == 0 && r.nrows_out == 0) ((PT *)r.crow_tmp)[0] = 0;
+                    break;
+                case 1: spref::spref_jscatter_tile(tile, r.J, r.nJ, r.n, r.mark, r.jpos, r.nm, r.hdr); break;
+                case 2:
+                    spref::spref_rows_tile<PT>(tile, (const PT *)r.arow, r.I, r.nI, r.m, r.rs, r.rl, r.ch, r.big,
+                                               r.hdr);
+                    break;
+                case 3: spref::spref_jpack_tile(tile, r.J, r.nJ, r.n, r.mark, r.bm, r.nw, r.jpos, r.Dn, r.dm); break;
+                case 4: spref::spref_jlink_tile(tile, r.J, r.nJ, r.jpos, r.Dn); break;
+                case 5:
+                    scan_counts_tile<int64_t>(tile, sm.scan, r.ch, r.cp, r.nI, r.hdr, 0, r.tiles0, 0, nullptr, 0,
+                                              nullptr, nullptr, nullptr);
+                    break;
+                case 6:
+                    spref::spref_count_tile(tile, r.nbw, sm.gs, r.acol, r.n, r.rs, r.rl, r.cp, r.nI, r.bm, r.dm,
+                                            r.jpos, r.Dn, r.cnt, r.hdr);
+                    break;
+                case 7:
+                    scan_counts_tile<PT>(tile, sm.scan, r.cnt, (PT *)r.crow_tmp, r.nI, r.hdr, 1, r.tiles1, 3,
+                                         r.lists, cap, goff, r.big, r.nm);
+                    break;
+            }
+        } else {
+            switch (phase) {
+                case 0: {
+                    const int64_t nct = cdiv(r.nzero, CLEAR_PER_TILE);
+                    if (tile < nct) {
+                        clear_tile(tile, r.zero, r.nzero);
+                        if (tile == 0 && threadIdx.x == 0 && r.nrows_out == 0) ((PT *)r.crow_tmp)[0] = 0;
+                    } else {
+                        fill_tile(tile - nct, r.fill, r.nfill);
+                    }
+                    break;
+                }
+                case 1:
+                    perm::perm_prepare_tile<PT>(tile, (const PT *)r.arow, r.p, r.sym ? nullptr : r.q, r.m, r.n,
+                                                r.pinv, r.qinv, r.cnt, r.hdr);
+                    break;
+                case 2: perm::perm_check_tile(tile, r.m, r.n, r.pinv, r.qinv, !r.sym, r.hdr); break;
+                case 3:
+                    scan_counts_tile<PT>(tile, sm.scan, r.cnt, (PT *)r.crow_tmp, r.m, r.hdr, 0, r.tiles0, 1, r.lists,
+                                         cap, goff, nullptr, nullptr);
+                    break;
+            }
+        }
+        return;
+    }
+    // exec half
+    const PT *crow = (const PT *)r.crow_tmp;
+    int32_t *tk = (int32_t *)r.tmp;
+    char *tp = (char *)r.tmp + ((r.glob_elems * sizeof(int32_t) + 255) & ~uint64_t(255));
+    VT *tv = (VT *)tp;
+    uint32_t *bst = (uint32_t *)(tp + ((r.glob_elems * sizeof(VT) + 255) & ~uint64_t(255)));
+    if (r.kind == HP_REQ_SPREF) {
+        LoadInPlace<PT, VT> ld{crow, r.ccol, (const VT *)r.cval};
+        switch (phase) {
+            case 0: {
+                const int64_t nct = cdiv(r.nI, CLEAR_PER_TILE);
+                if (tile < nct) clear_tile(tile, (uint32_t *)r.cursor, r.nI);
+                else copy_rowptr_tile<PT>(tile - nct, crow, (PT *)r.crow, r.nrows_out + 1);
+                break;
+            }
+            case 1:
+                spref::spref_gather_tile<PT, VT>(tile, r.nbw, sm.gs, r.acol, (const VT *)r.aval, r.n, r.rs, r.rl, r.cp,
+                                                 r.nI, r.bm, r.dm, r.jpos, r.Dn, crow, r.ccol, (VT *)r.cval, r.cursor,
+                                                 r.hdr);
+                break;
+            case 2: sort_small_tile<PT, VT>(tile, sm.wave, crow, r.ccol, (VT *)r.cval, r.nI, ld, r.hdr); break;
+            case 3:
+                seg_thread_tile<PT, VT>(tile, crow, r.ccol, (VT *)r.cval, r.lists + BIN_THREAD * cap, r.cls[BIN_THREAD],
+                                        ld, 0, r.hdr);
+                break;
+            case 4:
+                seg_wave_tile<PT, VT>(tile, sm.wave, crow, r.ccol, (VT *)r.cval, r.lists + BIN_WAVE * cap,
+                                      r.cls[BIN_WAVE], ld, 0, r.hdr);
+                break;
+            case 5:
+                seg_block_tile<PT, VT>(tile, sm.block, crow, r.ccol, (VT *)r.cval, r.lists + BIN_BLOCK * cap,
+                                       r.cls[BIN_BLOCK], ld, 0, r.hdr);
+                break;
+            case 6:
+                seg_bucket_tile<PT, VT>(tile, sm.bucket, crow, r.lists + BIN_GLOBAL * cap, goff, r.cls[BIN_GLOBAL], ld,
+                                        r.nb, tk, tv, bst, r.hdr);
+                break;
+            case 7:
+                seg_bucket_sort_tile<PT, VT>(tile, sm.block, crow, r.ccol, (VT *)r.cval, r.lists + BIN_GLOBAL * cap,
+                                             goff, r.cls[BIN_GLOBAL], r.nb, tk, tv, bst, r.hdr);
+                break;
+        }
+    } else {
+        perm::LoadPerm<PT, VT> ld{(const PT *)r.arow, r.acol, (const VT *)r.aval, r.p, r.qinv, r.n};
+        switch (phase) {
+            case 0: copy_rowptr_tile<PT>(tile, crow, (PT *)r.crow, r.nrows_out + 1); break;
+            case 1:
+                perm::perm_fill_short_tile<PT, VT>(tile, (const PT *)r.arow, r.acol, (const VT *)r.aval, r.pinv, r.qinv,
+                                                   crow, r.ccol, (VT *)r.cval, r.m, r.n, r.hdr);
+                break;
+            case 3:
+                seg_thread_tile<PT, VT>(tile, crow, r.ccol, (VT *)r.cval, r.lists + BIN_THREAD * cap, r.cls[BIN_THREAD],
+                                        ld, 0, r.hdr);
+                break;
+            case 4:
+                seg_wave_tile<PT, VT>(tile, sm.wave, crow, r.ccol, (VT *)r.cval, r.lists + BIN_WAVE * cap,
+                                      r.cls[BIN_WAVE], ld, 0, r.hdr);
+                break;
+            case 5:
+                seg_block_tile<PT, VT>(tile, sm.block, crow, r.ccol, (VT *)r.cval, r.lists + BIN_BLOCK * cap,
+                                       r.cls[BIN_BLOCK], ld, 0, r.hdr);
+                break;
+            case 6:
+                seg_bucket_tile<PT, VT>(tile, sm.bucket, crow, r.lists + BIN_GLOBAL * cap, goff, r.cls[BIN_GLOBAL], ld,
+                                        r.nb, tk, tv, bst, r.hdr);
+                break;
+            case 7:
+                seg_bucket_sort_tile<PT, VT>(tile, sm.block, crow, r.ccol, (VT *)r.cval, r.lists + BIN_GLOBAL * cap,
+                                             goff, r.cls[BIN_GLOBAL], r.nb, tk, tv, bst, r.hdr);
+                break;
+        }
+    }
+}
+
+__global__ void k_batch_reset(uint32_t *ticket, int nticket, DevHdr *hdrs, int64_t nhdr_words) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (i < nticket) ticket[i] = 0;
+    for (int64_t k = i; k < nhdr_words; k += stride) reinterpret_cast<uint32_t *>(hdrs)[k] = 0;
+}
+
+// One stage: persistent workgroups take tickets until the stage's tiles run
+// out.  q holds the stage's (request, phase) entries in queue order.
+template <typename PT, typename VT>
+__global__ __launch_bounds__(256) void k_batch_stage(int half, const QEntry *__restrict__ q, int nq, int64_t total,
+                                                    const ReqDev *__restrict__ reqs, uint32_t *ticket) {
+    __shared__ __align__(16) BatchSmem sm;
+    __shared__ int64_t s_t;
+    __shared__ int32_t s_e;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int64_t t = atomicAdd(ticket, 1u);
+            int lo = 0;
+            if (t < total) {
+                int hi = nq;   // last entry with first <= t
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (q[mid].first <= t) lo = mid;
+                    else hi = mid;
+                }
+            }
+            s_t = t;
+            s_e = lo;
+        }
+        __syncthreads();
+        const int64_t t = s_t;
+        if (t >= total) break;
+        const QEntry e = q[s_e];
+        run_tile<PT, VT>(half, e.phase, t - e.first, reqs[e.req], sm);
+        __syncthreads();   // LDS and s_t are reused by the next tile
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct Global {
+    uint32_t *ticket;    // [0, NST): plan stages, [NST, 2 NST): exec stages
+    DevHdr *hdrs;
+    ReqDev *reqs;
+    QEntry *queue;
+};
+
+size_t req_scratch(hp::Carve &c, const hp_request_t &rq, ReqDev &d) {
+    const size_t before = c.off;
+    const int64_t m = rq.A.nrows, n = rq.A.ncols;
+    const size_t ps = rq.A.ptr_type == HP_IDX_I64 ? 8 : 4;
+    if (rq.kind == HP_REQ_SPREF) {
+        const int64_t nI = rq.nI, nJ = rq.nJ;
+        const size_t st = scan_tiles(nI);
+        d.nw = (int64_t)((((size_t)((n + 31) / 32) + 1) + 3) & ~size_t(3));
+        const size_t markw = (size_t)d.nw * 8;
+        // zero region: tile states (2 scans) | marks | dm | cnt | nm
+        d.nzero = (int64_t)(4 * st + markw + d.nw + nI + 8 + 64 * 32);
+        d.zero = c.take<uint32_t>((size_t)d.nzero);
+        if (d.zero) {
+            d.tiles0 = (uint64_t *)d.zero;
+            d.tiles1 = (uint64_t *)d.zero + st;
+            uint32_t *z = d.zero + 4 * st;
+            d.mark = (uint8_t *)z;
+            d.dm = z + markw;
+            d.cnt = (int32_t *)(z + markw + d.nw);
+            d.nm = z + markw + d.nw + nI + 8;
+        }
+        d.bm = c.take<uint32_t>((size_t)d.nw);
+        d.jpos = c.take<int32_t>(n + 1);
+        d.Dn = c.take<int32_t>(nJ + 1);
+        d.rs = c.take<int64_t>(nI + 1);
+        d.rl = c.take<int32_t>(nI + 1);
+        d.ch = c.take<int32_t>(nI + 1);
+        d.big = c.take<uint8_t>(nI + 16);
+        d.cp = c.take<int64_t>(nI + 1);
+        d.cursor = c.take<int32_t>(nI + 1);
+        d.lists = c.take<uint32_t>(seg_list_words(nI));
+        d.crow_tmp = c.take<char>((size_t)(nI + 1) * ps);
+    } else {
+        const size_t st = scan_tiles(m);
+        const bool sym = rq.q == nullptr;
+        d.nzero = (int64_t)(2 * st);
+        d.zero = c.take<uint32_t>((size_t)d.nzero);
+        if (d.zero) d.tiles0 = (uint64_t *)d.zero;
+        d.nfill = m + (sym ? 0 : n);
+        d.fill = c.take<int32_t>((size_t)d.nfill + 1);
+        if (d.fill) {
+            d.pinv = d.fill;
+            d.qinv = sym ? d.fill : d.fill + m;
+        }
+        d.cnt = c.take<int32_t>(m + 1);
+        d.lists = c.take<uint32_t>(seg_list_words(m));
+        d.crow_tmp = c.take<char>((size_t)(m + 1) * ps);
+    }
+    return c.off - before;
+}
+
+Global global_layout(hp::Carve &c, int n) {
+    Global g;
+    g.ticket = c.take<uint32_t>(64);
+    g.hdrs = c.take<DevHdr>((size_t)n);
+    g.reqs = c.take<ReqDev>((size_t)n);
+    g.queue = c.take<QEntry>((size_t)n * NPH + 8);
+    return g;
+}
+
+hp_status_t check_req(hp_handle_t h, const hp_request_t &r, int k, int32_t pt, int32_t vt) {
+    std::string w = "request " + std::to_string(k);
+    hp_status_t st = check_csr_args(h, &r.A, w.c_str());
+    if (st) return st;
+    if (r.A.ptr_type != pt || r.A.val_type != vt)
+        return fail(h, HP_ERR_INVALID_ARG, w + ": all requests of a batch share ptr_type and val_type");
+    if (r.kind == HP_REQ_SPREF) {
+        if (r.nI < 0 || r.nJ < 0 || r.nI > INT32_MAX || r.nJ > INT32_MAX)
+            return fail(h, HP_ERR_INVALID_ARG, w + ": bad index-vector length");
+        if ((r.nI > 0 && !r.I) || (r.nJ > 0 && !r.J)) return fail(h, HP_ERR_INVALID_ARG, w + ": I or J is NULL");
+    } else if (r.kind == HP_REQ_PERMUTE) {
+        if (!r.q && r.A.nrows != r.A.ncols) return fail(h, HP_ERR_SHAPE, w + ": symmetric permute needs square A");
+        if (r.A.nrows > 0 && !r.p) return fail(h, HP_ERR_INVALID_ARG, w + ": p is NULL");
+    } else {
+        return fail(h, HP_ERR_INVALID_ARG, w + ": unknown request kind");
+    }
+    return HP_OK;
+}
+
+struct BatchState {
+    const void *ws = nullptr;
+    int n = -1;
+    std::vector<DevHdr> hdrs;
+    std::vector<ReqDev> devs;
+};
+
+std::map<hp_handle_t, BatchState> g_state;        // last plan per handle
+struct GraphKey {
+    const void *ws, *arena;
+    int grid, pv;
+    std::array<int64_t, NST> total;
+    std::array<int, NST + 1> off;
+    bool operator<(const GraphKey &o) const {
+        return std::tie(ws, arena, grid, pv, total, off) < std::tie(o.ws, o.arena, o.grid, o.pv, o.total, o.off);
+    }
+};
+struct GraphEntry {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+};
+std::map<hp_handle_t, std::map<GraphKey, GraphEntry>> g_graphs;
+std::map<std::string, int> g_tuned;                // autotuned grid per size class
+
+int num_cus(hp_handle_t h) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, h->device) != hipSuccess) return 256;
+    return p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+}
+
+// Phase tile counts of one request.
+void plan_tiles(const hp_request_t &rq, const ReqDev &d, int64_t *nt) {
+    for (int k = 0; k < NPH; k++) nt[k] = 0;
+    if (rq.kind == HP_REQ_SPREF) {
+        const int64_t ngb = cdiv(rq.nI, 4 * WAVE);
+        nt[0] = cdiv(d.nzero, CLEAR_PER_TILE);
+        nt[1] = cdiv(rq.nJ, 256);
+        nt[2] = cdiv(rq.nI, 256);
+        nt[3] = cdiv(std::max<int64_t>(rq.nJ, d.nw), 256);
+        nt[4] = cdiv(rq.nJ, 256);
+        nt[5] = cdiv(rq.nI, SCAN_TILE);
+        nt[6] = d.nbw + ngb;
+        nt[7] = cdiv(rq.nI, SCAN_TILE);
+    } else {
+        const int64_t hi = std::max(rq.A.nrows, rq.A.ncols);
+        nt[0] = cdiv(d.nzero, CLEAR_PER_TILE) + cdiv(d.nfill, CLEAR_PER_TILE);
+        nt[1] = cdiv(hi, 256);
+        nt[2] = cdiv(hi, 256);
+        nt[3] = cdiv(rq.A.nrows, SCAN_TILE);
+    }
+}
+
+void exec_tiles(const hp_request_t &rq, const ReqDev &d, int64_t *nt) {
+    for (int k = 0; k < NPH; k++) nt[k] = 0;
+    if (!d.active) return;
+    const uint32_t *c = d.cls;
+    if (rq.kind == HP_REQ_SPREF) {
+        const int64_t ngb = cdiv(rq.nI, 4 * WAVE);
+        nt[0] = cdiv(rq.nI, CLEAR_PER_TILE) + cdiv(rq.nI + 1, CLEAR_PER_TILE);
+        nt[1] = d.nbw + ngb;
+        nt[2] = d.monotone ? 0 : ngb;
+    } else {
+        nt[0] = cdiv(rq.A.nrows + 1, CLEAR_PER_TILE);
+        nt[1] = cdiv(rq.A.nrows, 256);
+    }
+    nt[3] = cdiv(c[BIN_THREAD], 256);
+    nt[4] = cdiv(c[BIN_WAVE], 4);
+    nt[5] = c[BIN_BLOCK];
+    nt[6] = c[BIN_GLOBAL];
+    nt[7] = (int64_t)c[BIN_GLOBAL] * d.nb;
+}
+
+// Stage queues of one half: the entries of every stage, phase by phase and
+// request by request, with stage-relative first tickets.
+struct Stages {
+    std::vector<QEntry> q;        // all stages, concatenated
+    int off[NST + 1] = {0};       // entries of stage s: q[off[s], off[s+1])
+    int64_t total[NST] = {0};     // tiles of stage s
+    int64_t tiles() const {
+        int64_t t = 0;
+        for (int k = 0; k < NST; k++) t += total[k];
+        return t;
+    }
+};
+
+void build_stages(int half, const hp_request_t *reqs, const std::vector<std::array<int64_t, NPH>> &nt, Stages &S) {
+    S.q.clear();
+    const int n = (int)nt.size();
+    for (int st = 0; st < NST; st++) {
+        S.off[st] = (int)S.q.size();
+        int64_t t = 0;
+        for (int ph = 0; ph < NPH; ph++)
+            for (int r = 0; r < n; r++) {
+                const int kind = reqs[r].kind == HP_REQ_SPREF ? 0 : 1;
+                const int64_t k = nt[r][ph];
+                if (k <= 0 || STAGE_OF[half][kind][ph] != st) continue;
+                QEntry e;
+                e.first = t;
+                e.req = r;
+                e.phase = ph;
+                S.q.push_back(e);
+                t += k;
+            }
+        S.total[st] = t;
+    }
+    S.off[NST] = (int)S.q.size();
+}
+
+template <typename PT, typename VT>
+hipError_t launch_half(hp_handle_t h, int half, const Global &g, int n, const Stages &S, int grid) {
+    hipStream_t s = h->stream;
+    const int64_t hw = half == 0 ? (int64_t)n * (int64_t)(sizeof(DevHdr) / 4) : 0;
+    uint32_t *tk = g.ticket + half * NST;
+    hipLaunchKernelGGL(k_batch_reset, dim3(half == 0 ? 64 : 1), dim3(256), 0, s, tk, NST, g.hdrs, hw);
+    for (int st = 0; st < NST; st++) {
+        const int64_t tot = S.total[st];
+        if (tot <= 0) continue;
+        const int gr = (int)std::min<int64_t>(tot, grid);
+        hipLaunchKernelGGL((k_batch_stage<PT, VT>), dim3(gr), dim3(256), 0, s, half, g.queue + S.off[st],
+                           S.off[st + 1] - S.off[st], tot, g.reqs, tk + st);
+    }
+    return hipGetLastError();
+}
+
+// Time one half at a few persistent grid sizes and keep the fastest per size
+// class (both halves are idempotent: every run starts from cleared state and
+// rewrites the same outputs).
+template <typename PT, typename VT>
+int tune_grid(hp_handle_t h, int half, const Global &g, int n, const Stages &S, const std::string &key) {
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) return it->second;
+    const int cus = num_cus(h);
+    const int cand[3] = {cus, 2 * cus, 4 * cus};
+    int best = cand[1];
+    if (getenv("HP_NO_TUNE")) return best;
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    for (int c : cand) {
+        hipEventRecord(e0, h->stream);
+        launch_half<PT, VT>(h, half, g, n, S, c);
+        hipEventRecord(e1, h->stream);
+        hipEventSynchronize(e1);
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    g_tuned[key] = best;
+    return best;
+}
+
+std::string size_class(const char *half, int32_t pt, int32_t vt, int64_t total) {
+    int lg = 0;
+    while ((int64_t(1) << lg) < total) lg++;
+    char buf[96];
+    snprintf(buf, sizeof buf, "%s/p%d/v%d/t2^%d", half, pt, vt, lg);
+    return buf;
+}
+
+template <typename PT, typename VT>
+hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, size_t ws_bytes,
+                         hp_batch_info_t *info) {
+    hp::Carve need(nullptr);
+    global_layout(need, n);
+    std::vector<ReqDev> devs(n);
+    for (int k = 0; k < n; k++) req_scratch(need, reqs[k], devs[k]);
+    if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "batch workspace too small");
+    hp::Carve c(ws);
+    Global g = global_layout(c, n);
+    const int cus = num_cus(h);
+    for (int k = 0; k < n; k++) {
+        ReqDev &d = devs[k];
+        d = ReqDev{};
+        req_scratch(c, reqs[k], d);
+        const hp_request_t &r = reqs[k];
+        d.kind = r.kind;
+        d.sym = r.q == nullptr;
+        d.active = 1;
+        d.m = r.A.nrows;
+        d.n = r.A.ncols;
+        d.nnz = r.A.nnz;
+        d.arow = r.A.rowptr;
+        d.acol = r.A.col;
+        d.aval = r.A.val;
+        d.I = r.I;
+        d.J = r.J;
+        d.p = r.p;
+        d.q = r.q;
+        d.nI = r.kind == HP_REQ_SPREF ? r.nI : 0;
+        d.nJ = r.kind == HP_REQ_SPREF ? r.nJ : 0;
+        d.nrows_out = r.kind == HP_REQ_SPREF ? r.nI : r.A.nrows;
+        d.ncols_out = r.kind == HP_REQ_SPREF ? r.nJ : r.A.ncols;
+        d.hdr = g.hdrs + k;
+        // long-row workers: about one per 2^20 nonzeros of A, at most one per CU
+        d.nbw = (r.kind == HP_REQ_SPREF && r.nI > 0)
+                    ? (int32_t)std::min<int64_t>(cus, std::max<int64_t>(1, r.A.nnz >> 20)) : 0;
+    }
+    std::vector<std::array<int64_t, NPH>> nt(n);
+    for (int k = 0; k < n; k++) plan_tiles(reqs[k], devs[k], nt[k].data());
+    Stages S;
+    build_stages(0, reqs, nt, S);
+    const int64_t total = S.tiles();
+    hipStream_t s = h->stream;
+    hipError_t e = hipMemcpyAsync(g.reqs, devs.data(), sizeof(ReqDev) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !S.q.empty())
+        e = hipMemcpyAsync(g.queue, S.q.data(), sizeof(QEntry) * S.q.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_check(h, e, "batch plan upload");
+    const std::string key = size_class("plan", reqs[0].A.ptr_type, reqs[0].A.val_type, total);
+    const int grid = tune_grid<PT, VT>(h, 0, g, n, S, key);
+    stage_begin(h);
+    e = launch_half<PT, VT>(h, 0, g, n, S, grid);
+    stage_mark(h, "batch.plan");
+    BatchState &bs = g_state[h];
+    bs.hdrs.resize(n);
+    if (e == hipSuccess) e = hipMemcpyAsync(bs.hdrs.data(), g.hdrs, sizeof(DevHdr) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_check(h, e, "batch plan");
+    // per-request results and the arena
+    const size_t ps = sizeof(PT), vs = sizeof(VT);
+    size_t arena = 0;
+    int failed = 0;
+    int64_t nnz_total = 0;
+    for (int k = 0; k < n; k++) {
+        hp_request_t &r = reqs[k];
+        ReqDev &d = devs[k];
+        const DevHdr &H = bs.hdrs[k];
+        hp_status_t st = status_from_err(h, H.err, "batch request");
+        r.C = hp_csr_t{};
+        r.C.nrows = d.nrows_out;
+        r.C.ncols = d.ncols_out;
+        r.C.ptr_type = r.A.ptr_type;
+        r.C.val_type = r.A.val_type;
+        const int slot = r.kind == HP_REQ_SPREF ? 1 : 0;
+        r.C.nnz = st == HP_OK ? (int64_t)H.total[slot] : 0;
+        d.monotone = r.kind == HP_REQ_SPREF ? ((H.flags & F_NOT_MONOTONE) ? 0 : 1) : 0;
+        d.glob_elems = H.bin_elems[BIN_GLOBAL];
+        d.nb = seg_nbuckets(d.ncols_out);
+        for (int b = 0; b < NBINS; b++) d.cls[b] = H.bin_cnt[b];
+        if (st == HP_OK && H.bin_cnt[BIN_GLOBAL] && d.nb > BKT_MAXNB)
+            st = fail(h, HP_ERR_INVALID_ARG, "batch: rows above 2048 entries with more than 2^23 output columns");
+        r.status = st;
+        d.active = st == HP_OK;
+        if (st != HP_OK) {
+            failed++;
+            continue;
+        }
+        nnz_total += r.C.nnz;
+        arena = (arena + 255) & ~size_t(255);
+        arena += (size_t)(d.nrows_out + 1) * ps + 256;
+        arena = (arena + 255) & ~size_t(255);
+        arena += (size_t)r.C.nnz * 4 + 256;
+        arena = (arena + 255) & ~size_t(255);
+        arena += (size_t)r.C.nnz * vs + 256;
+        arena = (arena + 255) & ~size_t(255);
+        arena += seg_tmp_bytes(d.glob_elems, d.cls[BIN_GLOBAL], vs, d.ncols_out);
+    }
+    bs.ws = ws;
+    bs.n = n;
+    bs.devs = devs;
+    if (info) {
+        *info = hp_batch_info_t{};
+        info->arena_bytes = arena + 256;
+        info->nnz_total = nnz_total;
+        info->failed = failed;
+        info->grid_plan = grid;
+        info->tiles_plan = total;
+    }
+    return HP_OK;
+}
+
+template <typename PT, typename VT>
+hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, size_t ws_bytes,
+                         hp_batch_info_t *info, void *arena, size_t arena_bytes) {
+    auto it = g_state.find(h);
+    if (it == g_state.end() || it->second.ws != ws || it->second.n != n)
+        return fail(h, HP_ERR_INVALID_ARG, "hp_batch_exec needs the preceding hp_batch_plan of this batch");
+    BatchState &bs = it->second;
+    if (!info || arena_bytes < info->arena_bytes || (info->arena_bytes > 256 && !arena))
+        return fail(h, HP_ERR_WORKSPACE, "batch arena too small");
+    hp::Carve c(ws);
+    Global g = global_layout(c, n);
+    std::vector<ReqDev> devs = bs.devs;
+    const size_t ps = sizeof(PT), vs = sizeof(VT);
+    hp::Carve a(arena);
+    for (int k = 0; k < n; k++) {
+        ReqDev &d = devs[k];
+        hp_request_t &r = reqs[k];
+        if (!d.active) continue;
+        d.crow = a.take<char>((size_t)(d.nrows_out + 1) * ps);
+        d.ccol = a.take<int32_t>((size_t)r.C.nnz);
+        d.cval = a.take<char>((size_t)r.C.nnz * vs);
+        d.tmp = a.take<char>(seg_tmp_bytes(d.glob_elems, d.cls[BIN_GLOBAL], vs, d.ncols_out));
+        r.C.rowptr = d.crow;
+        r.C.col = d.ccol;
+        r.C.val = d.cval;
+    }
+    if (a.size() > arena_bytes) return fail(h, HP_ERR_WORKSPACE, "batch arena too small");
+    std::vector<std::array<int64_t, NPH>> nt(n);
+    for (int k = 0; k < n; k++) exec_tiles(reqs[k], devs[k], nt[k].data());
+    Stages S;
+    build_stages(1, reqs, nt, S);
+    const int64_t total = S.tiles();
+    hipStream_t s = h->stream;
+    hipError_t e = hipMemcpyAsync(g.reqs, devs.data(), sizeof(ReqDev) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !S.q.empty())
+        e = hipMemcpyAsync(g.queue, S.q.data(), sizeof(QEntry) * S.q.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_check(h, e, "batch exec upload");
+    const std::string key = size_class("exec", reqs[0].A.ptr_type, reqs[0].A.val_type, total);
+    const int grid = tune_grid<PT, VT>(h, 1, g, n, S, key);
+    // exec runs from a captured graph, replayed for any batch with the same
+    // workspace, arena, grid and stage shapes (queue and request records are
+    // uploaded before every launch)
+    GraphKey gk{ws, arena, grid, (int)(ps * 16 + vs), {}, {}};
+    std::copy(S.total, S.total + NST, gk.total.begin());
+    std::copy(S.off, S.off + NST + 1, gk.off.begin());
+    GraphEntry &ge = g_graphs[h][gk];
+    stage_begin(h);
+    if (!ge.ge) {
+        hipStream_t cs;
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) {
+            hipStream_t keep = h->stream;
+            h->stream = cs;
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t le = launch_half<PT, VT>(h, 1, g, n, S, grid);
+                e = hipStreamEndCapture(cs, &ge.g);
+                if (e == hipSuccess) e = le;
+            }
+            h->stream = keep;
+            hipStreamDestroy(cs);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&ge.ge, ge.g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            ge.ge = nullptr;
+            return hip_check(h, e, "batch exec graph capture");
+        }
+    }
+    e = hipGraphLaunch(ge.ge, s);
+    stage_mark(h, "batch.exec");
+    if (e != hipSuccess) return hip_check(h, e, "batch exec");
+    if (info) {
+        info->tiles_exec = total;
+        info->grid_exec = grid;
+    }
+    return HP_OK;
+}
+
+}  // namespace
+
+extern "C" hp_status_t hp_batch_workspace(hp_handle_t h, const hp_request_t *reqs, int n, size_t *bytes) {
+    if (!h || !bytes || n < 0 || (n > 0 && !reqs)) return HP_ERR_INVALID_ARG;
+    hp::Carve c(nullptr);
+    global_layout(c, n);
+    for (int k = 0; k < n; k++) {
+        hp_status_t st = check_req(h, reqs[k], k, reqs[0].A.ptr_type, reqs[0].A.val_type);
+        if (st) return st;
+        ReqDev d{};
+        req_scratch(c, reqs[k], d);
+    }
+    *bytes = c.size();
+    return HP_OK;
+}
+
+extern "C" hp_status_t hp_batch_plan(hp_handle_t h, hp_request_t *reqs, int n, void *ws, size_t ws_bytes,
+                                     hp_batch_info_t *info) {
+    if (!h || n < 0 || (n > 0 && !reqs)) return HP_ERR_INVALID_ARG;
+    if (n == 0) {
+        if (info) *info = hp_batch_info_t{};
+        return HP_OK;
+    }
+    for (int k = 0; k < n; k++) {
+        hp_status_t st = check_req(h, reqs[k], k, reqs[0].A.ptr_type, reqs[0].A.val_type);
+        if (st) return st;
+    }
+    const bool p64 = reqs[0].A.ptr_type == HP_IDX_I64, v64 = reqs[0].A.val_type == HP_VAL_F64;
+    if (!p64 && !v64) return batch_plan_t<int32_t, uint32_t>(h, reqs, n, ws, ws_bytes, info);
+    if (!p64 && v64) return batch_plan_t<int32_t, uint64_t>(h, reqs, n, ws, ws_bytes, info);
+    if (p64 && !v64) return batch_plan_t<int64_t, uint32_t>(h, reqs, n, ws, ws_bytes, info);
+    return batch_plan_t<int64_t, uint64_t>(h, reqs, n, ws, ws_bytes, info);
+}
+
+extern "C" hp_status_t hp_batch_exec(hp_handle_t h, hp_request_t *reqs, int n, void *ws, size_t ws_bytes,
+                                     hp_batch_info_t *info, void *arena, size_t arena_bytes) {
+    if (!h || n < 0 || (n > 0 && !reqs)) return HP_ERR_INVALID_ARG;
+    if (n == 0) return HP_OK;
+    const bool p64 = reqs[0].A.ptr_type == HP_IDX_I64, v64 = reqs[0].A.val_type == HP_VAL_F64;
+    if (!p64 && !v64) return batch_exec_t<int32_t, uint32_t>(h, reqs, n, ws, ws_bytes, info, arena, arena_bytes);
+    if (!p64 && v64) return batch_exec_t<int32_t, uint64_t>(h, reqs, n, ws, ws_bytes, info, arena, arena_bytes);
+    if (p64 && !v64) return batch_exec_t<int64_t, uint32_t>(h, reqs, n, ws, ws_bytes, info, arena, arena_bytes);
+    return batch_exec_t<int64_t, uint64_t>(h, reqs, n, ws, ws_bytes, info, arena, arena_bytes);
+}

@@ -28,7 +28,7 @@ enum { BIN_THREAD = 0, BIN_WAVE = 1, BIN_BLOCK = 2, BIN_GLOBAL = 3, NBINS = 4 };
 constexpr int64_t THREAD_MAX = 16;     // rows sorted in registers by one lane
 constexpr int64_t SMALL_MAX = 64;      // rows k_sort_small sorts with one wavefront
 constexpr int64_t WAVE_MAX = 256;      // rows sorted by one wavefront (4 keys per lane)
-constexpr int64_t BLOCK_MAX = 4096;    // rows sorted in LDS by one workgroup
+constexpr int64_t BLOCK_MAX = 2048;    // rows sorted in LDS by one workgroup
 
 struct DevHdr {
     uint32_t err;

@@ -14,8 +14,10 @@
 //          class kernels       longer rows gathered from A (pull) and sorted
 #include "hp_internal.hpp"
 #include "hp_segsort.hpp"
+#include "hp_perm_tiles.hpp"
 
 using namespace hp;
+using namespace hp::perm;
 
 namespace {
 
@@ -38,87 +40,22 @@ PermLayout perm_layout(Carve &c, int64_t m, int64_t n, bool sym) {
 }
 
 template <typename PT>
-__global__ __launch_bounds__(256) void k_perm_prepare(const PT *__restrict__ arow,
-                                                     const int32_t *__restrict__ p,
-                                                     const int32_t *__restrict__ q, int64_t m,
-                                                     int64_t n, int32_t *pinv, int32_t *qinv,
-                                                     int32_t *cnt, DevHdr *hdr) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t < m) {
-        const int32_t r = p[t];
-        if (r < 0 || r >= m) {
-            atomicOr(&hdr->err, E_RANGE);     // error path only
-            cnt[t] = 0;
-        } else {
-            pinv[r] = (int32_t)t;
-            cnt[t] = (int32_t)(arow[r + 1] - arow[r]);
-        }
-    }
-    if (q && t < n) {
-        const int32_t c = q[t];
-        if (c < 0 || c >= n) atomicOr(&hdr->err, E_RANGE);
-        else qinv[c] = (int32_t)t;
-    }
+__global__ __launch_bounds__(256) void k_perm_prepare(const PT *__restrict__ arow, const int32_t *__restrict__ p,
+                                                     const int32_t *__restrict__ q, int64_t m, int64_t n,
+                                                     int32_t *pinv, int32_t *qinv, int32_t *cnt, DevHdr *hdr) {
+    perm_prepare_tile<PT>(blockIdx.x, arow, p, q, m, n, pinv, qinv, cnt, hdr);
 }
-
-// pinv and qinv start filled with -1 and every in-range value of p (q) has
-// been scattered: a slot left at -1 means some value is missing, hence
-// (m values in m slots) another is repeated.  Sequential reads only.
 __global__ __launch_bounds__(256) void k_perm_check(int64_t m, int64_t n, const int32_t *__restrict__ pinv,
-                                                   const int32_t *__restrict__ qinv, bool general,
-                                                   DevHdr *hdr) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    bool bad = false;
-    if (t < m) bad |= pinv[t] < 0;
-    if (general && t < n) bad |= qinv[t] < 0;
-    if (bad) atomicOr(&hdr->err, E_NOTPERM);   // error path only
+                                                   const int32_t *__restrict__ qinv, bool general, DevHdr *hdr) {
+    perm_check_tile(blockIdx.x, m, n, pinv, qinv, general, hdr);
 }
-
-// Rows of at most 4 entries: one lane per SOURCE row r, streamed in order
-// (coalesced reads of A, local reads of qinv for banded matrices), written
-// to output row pinv[r] after an in-register sort of the mapped columns.
-// Longer rows go through the class kernels (pull from A).
 template <typename PT, typename VT>
 __global__ __launch_bounds__(256) void k_perm_fill_short(
     const PT *__restrict__ arow, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
     const int32_t *__restrict__ pinv, const int32_t *__restrict__ cmap, const PT *__restrict__ crow,
     int32_t *__restrict__ ccol, VT *__restrict__ cval, int64_t m, int64_t n, const DevHdr *hdr) {
-    if (hdr->err) return;
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= m) return;
-    const int64_t s = arow[r];
-    const int len = (int)(arow[r + 1] - s);
-    if (len == 0 || len > 4) return;
-    const int64_t d = crow[pinv[r]];
-    int32_t k[4];
-    VT v[4];
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        k[i] = INT32_MAX;
-        v[i] = VT(0);
-        if (i < len) {
-            k[i] = cmap[clampc(acol[s + i], n)];
-            v[i] = aval[s + i];
-        }
-    }
-    sort_store_regs<4, VT>(k, v, len, false, ccol + d, cval + d);
+    perm_fill_short_tile<PT, VT>(blockIdx.x, arow, acol, aval, pinv, cmap, crow, ccol, cval, m, n, hdr);
 }
-
-// Longer rows: output row i is row p[i] of A with columns mapped (pull).
-template <typename PT, typename VT>
-struct LoadPerm {
-    const PT *arow;
-    const int32_t *acol;
-    const VT *aval;
-    const int32_t *p;
-    const int32_t *cmap;
-    int64_t n;
-    __device__ __forceinline__ int64_t base(int64_t row) const { return arow[p[row]]; }
-    __device__ __forceinline__ void get(int64_t b, int64_t k, int32_t &kk, VT &vv) const {
-        kk = cmap[clampc(acol[b + k], n)];
-        vv = aval[b + k];
-    }
-};
 
 hp_status_t perm_check_args(hp_handle_t h, const hp_csr_t *A, const int32_t *p, const int32_t *q,
                             const hp_csr_t *C) {

@@ -1,0 +1,186 @@
+// Single-pass exclusive scan (decoupled look-back) with row classification,
+// as a tile function shared by the plain per-call kernels and the batched
+// persistent kernel.
+//
+// Tiles are started in launch order (an atomic ticket in the plain kernel,
+// the batch queue order otherwise), so a tile only ever waits on tiles that
+// are already running: every wait ends.  The wait is still bounded
+// (SCAN_WAIT_TICKS); reaching it raises E_TIMEOUT and the kernel finishes.
+#pragma once
+#include "hp_internal.hpp"
+
+namespace hp {
+
+constexpr int SCAN_BLOCK = 256;   // threads of a scan tile
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+constexpr uint64_t ST_AGG = 1ull << 62, ST_PRE = 2ull << 62, ST_VAL = (1ull << 62) - 1;
+constexpr uint64_t SCAN_WAIT_TICKS = 10000000ull;   // 0.1 s of the 100 MHz wall clock
+
+
+// Sort class of a row of `len` entries under classification `mode`:
+//   1  rows longer than 4 (shorter rows are sorted by the producer itself)
+//   2  every row of >= 2 entries
+//   3  rows longer than SMALL_MAX when `all` (shorter ones are sorted by
+//      k_sort_small), else only flagged rows
+//   4  only flagged rows
+__device__ __forceinline__ int class_of(int64_t len, int mode, bool all, bool flagged) {
+    if (len < 2) return -1;
+    if (mode == 1 && len <= 4) return -1;
+    if (mode == 4 && !flagged) return -1;
+    if (mode == 3) {
+        if (all) {
+            if (len <= SMALL_MAX) return -1;
+        } else if (!flagged) {
+            return -1;
+        }
+    }
+    if (len <= THREAD_MAX) return BIN_THREAD;
+    if (len <= WAVE_MAX) return BIN_WAVE;
+    if (len <= BLOCK_MAX) return BIN_BLOCK;
+    return BIN_GLOBAL;
+}
+
+struct ScanSmem {
+    uint64_t wave[SCAN_BLOCK / WAVE];
+    uint64_t excl;
+    uint32_t bc[NBINS], bbase[NBINS];
+    unsigned long long ge, gbase;
+    int all;
+};
+
+// One tile of the single-pass exclusive scan of n int32 counts into out
+// (PT, n+1 entries).  Tiles must be started in increasing order (the
+// caller's ticket) so that a tile only waits on running tiles.
+template <typename PT>
+__device__ void scan_counts_tile(int64_t tile, ScanSmem &sm, const int32_t *__restrict__ cnt,
+                                 PT *__restrict__ out, int64_t n, DevHdr *hdr, int slot,
+                                 uint64_t *tile_state, int classify, uint32_t *lists, int64_t cap,
+                                 uint64_t *goff, const uint8_t *__restrict__ force,
+                                 const uint32_t *__restrict__ nmslots) {
+    uint64_t *s_wave = sm.wave;
+    uint64_t &s_excl = sm.excl;
+    uint32_t *s_bc = sm.bc, *s_bbase = sm.bbase;
+    unsigned long long &s_ge = sm.ge, &s_gbase = sm.gbase;
+    int &s_all = sm.all;
+    if (threadIdx.x == 0) {
+        s_ge = 0;
+        s_all = 1;
+    }
+    if (threadIdx.x < NBINS) s_bc[threadIdx.x] = 0;
+    if (classify == 3 && threadIdx.x < WAVE) {
+        // any block of the J-table build that saw J out of order
+        uint64_t any = ballot(ld_agent(&nmslots[threadIdx.x * 32]) != 0);
+        if (threadIdx.x == 0) s_all = any != 0;
+    }
+    __syncthreads();
+    const int64_t base = tile * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int32_t v[SCAN_ITEMS];
+    if (base + SCAN_ITEMS <= n) {
+        const int4 *p4 = reinterpret_cast<const int4 *>(cnt + base);
+        int4 a = p4[0], b = p4[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; k++) v[k] = (base + k < n) ? cnt[base + k] : 0;
+    }
+    uint64_t tsum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) tsum += (uint64_t)(uint32_t)v[k];
+    uint64_t tile_total;
+    uint64_t texcl = block_excl_scan<SCAN_BLOCK, uint64_t>(tsum, s_wave, tile_total);
+
+    if (threadIdx.x < WAVE) {
+        // publish this tile's aggregate, then look back for its prefix
+        if (lane_id() == 0)
+            st_agent(&tile_state[tile], (tile == 0 ? ST_PRE : ST_AGG) | (tile_total & ST_VAL));
+        uint64_t excl = 0;
+        if (tile > 0) {
+            int64_t j = tile - 1;
+            const uint64_t t0 = wall_clock64();
+            uint32_t spins = 0;
+            while (true) {
+                int64_t idx = j - lane_id();
+                uint64_t s = idx >= 0 ? ld_agent(&tile_state[idx]) : ST_PRE;
+                uint64_t flag = s & ~ST_VAL;
+                uint64_t pre = ballot(flag == ST_PRE);
+                uint64_t inval = ballot(flag == 0);
+                int fp = pre ? __ffsll((long long)pre) - 1 : 64;
+                uint64_t need = fp >= 63 ? ~0ull : ((2ull << fp) - 1);
+                if (inval & need) {
+                    // bounded wait: 0.1 s of the 100 MHz wall clock, or stop at
+                    // once when another wait of this request already gave up
+                    ++spins;
+                    const bool give_up = (wall_clock64() - t0 > SCAN_WAIT_TICKS) ||
+                                         ((spins & 63) == 0 && (ld_agent(&hdr->err) & E_TIMEOUT));
+                    if (__shfl(give_up ? 1 : 0, 0, WAVE)) {
+                        if (lane_id() == 0) raise_err(hdr, E_TIMEOUT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                uint64_t part = (lane_id() <= fp) ? (s & ST_VAL) : 0;
+                excl += wave_sum(part);
+                if (pre) break;
+                j -= WAVE;
+            }
+            if (lane_id() == 0) st_agent(&tile_state[tile], ST_PRE | ((excl + tile_total) & ST_VAL));
+        }
+        if (lane_id() == 0) s_excl = excl;
+    }
+    __syncthreads();
+    uint64_t run = s_excl + texcl;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        if (base + k < n) out[base + k] = (PT)run;
+        run += (uint32_t)v[k];
+    }
+    const int64_t last_base = (n - 1) / SCAN_TILE;
+    if (tile == last_base && threadIdx.x == SCAN_BLOCK - 1) {
+        uint64_t total = s_excl + tile_total;
+        out[n] = (PT)total;
+        hdr->total[slot] = total;
+        if (sizeof(PT) == 4 && total > (uint64_t)INT32_MAX) raise_err(hdr, E_OVERFLOW);
+        if (classify == 3 && s_all) atomicOr(&hdr->flags, F_NOT_MONOTONE);
+    }
+    if (classify) {
+        // block-aggregated append to the class lists: LDS offsets, then a
+        // handful of global atomics per tile
+        const bool all = s_all != 0;
+        int bin[SCAN_ITEMS];
+        uint32_t off[SCAN_ITEMS];
+        unsigned long long eoff[SCAN_ITEMS];
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; k++) {
+            const bool valid = base + k < n;
+            const bool fl = ((classify == 3 && !all) || classify == 4) && valid ? force[base + k] != 0 : false;
+            bin[k] = valid ? class_of(v[k], classify, all, fl) : -1;
+            off[k] = 0;
+            eoff[k] = 0;
+            if (bin[k] >= 0) {
+                off[k] = atomicAdd(&s_bc[bin[k]], 1u);
+                if (bin[k] == BIN_GLOBAL) eoff[k] = atomicAdd(&s_ge, (unsigned long long)(uint32_t)v[k]);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < NBINS && s_bc[threadIdx.x])
+            s_bbase[threadIdx.x] = atomicAdd(&hdr->bin_cnt[threadIdx.x], s_bc[threadIdx.x]);
+        if (threadIdx.x == NBINS && s_ge)
+            s_gbase = atomicAdd((unsigned long long *)&hdr->bin_elems[BIN_GLOBAL], s_ge);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; k++) {
+            if (bin[k] < 0) continue;
+            const uint32_t pos = s_bbase[bin[k]] + off[k];
+            if (pos < cap) {
+                lists[(int64_t)bin[k] * cap + pos] = (uint32_t)(base + k);
+                if (bin[k] == BIN_GLOBAL) goff[pos] = s_gbase + eoff[k];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace hp

@@ -10,13 +10,14 @@
 // Length classes:
 //   THREAD  2..16     one lane per row, bitonic network in registers
 //   WAVE    17..256   one wavefront, rank = number of smaller keys (LDS)
-//   BLOCK   257..4096 one workgroup: 64-element runs ranked per wavefront,
+//   BLOCK   257..2048 one workgroup: 64-element runs ranked per wavefront,
 //                     then merged pairwise in LDS (merge-path ranks)
-//   GLOBAL  > 4096    split by key range into buckets of width 4096 (one
+//   GLOBAL  > 2048    split by key range into buckets of width 2048 (one
 //                     workgroup per row, LDS histogram), then every bucket
-//                     (at most 4096 distinct keys) sorted by its own
-//                     workgroup as in BLOCK.  Columns beyond 2^24 buckets
-//                     fall back to an LSD radix sort per row.
+//                     (at most 2048 distinct keys) sorted by its own
+//                     workgroup as in BLOCK.  More than 4096 buckets (over
+//                     2^23 output columns) falls back to an LSD radix sort
+//                     per row.
 // Rows of <= 64 entries can also be sorted without lists by k_sort_small,
 // which walks all rows in groups of 64.
 #pragma once
@@ -149,12 +150,17 @@ __device__ __forceinline__ void wave_sort_row(const LD &ld, int64_t sb, int len,
     }
 }
 
+// Shared-memory blocks of the tile functions (the batched kernel overlays
+// them in one buffer).
+struct SegSmemWave {
+    int32_t k[4][WAVE_MAX];
+};
+
 template <typename PT, typename VT, typename LD>
-__global__ __launch_bounds__(256) void k_seg_thread(const PT *__restrict__ rowptr, int32_t *okey,
-                                                   VT *oval, const uint32_t *__restrict__ list,
-                                                   uint32_t count, LD ld, int sorted,
-                                                   const DevHdr *hdr) {
-    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void seg_thread_tile(int64_t bid, const PT *__restrict__ rowptr, int32_t *okey, VT *oval,
+                                const uint32_t *__restrict__ list, uint32_t count, const LD &ld, int sorted,
+                                const DevHdr *hdr) {
+    const int64_t t = bid * 256 + threadIdx.x;
     if (t >= count || hdr->err) return;
     int64_t row = list[t];
     int64_t b = rowptr[row];
@@ -163,18 +169,33 @@ __global__ __launch_bounds__(256) void k_seg_thread(const PT *__restrict__ rowpt
 }
 
 template <typename PT, typename VT, typename LD>
-__global__ __launch_bounds__(256) void k_seg_wave(const PT *__restrict__ rowptr, int32_t *okey,
-                                                 VT *oval, const uint32_t *__restrict__ list,
-                                                 uint32_t count, LD ld, int sorted,
-                                                 const DevHdr *hdr) {
-    __shared__ __align__(16) int32_t s_k[4][WAVE_MAX];
+__global__ __launch_bounds__(256) void k_seg_thread(const PT *__restrict__ rowptr, int32_t *okey,
+                                                   VT *oval, const uint32_t *__restrict__ list,
+                                                   uint32_t count, LD ld, int sorted,
+                                                   const DevHdr *hdr) {
+    seg_thread_tile<PT, VT, LD>(blockIdx.x, rowptr, okey, oval, list, count, ld, sorted, hdr);
+}
+
+template <typename PT, typename VT, typename LD>
+__device__ void seg_wave_tile(int64_t bid, SegSmemWave &sm, const PT *__restrict__ rowptr, int32_t *okey,
+                              VT *oval, const uint32_t *__restrict__ list, uint32_t count, const LD &ld,
+                              int sorted, const DevHdr *hdr) {
     const int w = threadIdx.x / WAVE;
-    uint32_t t = blockIdx.x * 4 + w;
+    const int64_t t = bid * 4 + w;
     if (t >= count || hdr->err) return;
     int64_t row = list[t];
     int64_t b = rowptr[row];
     int len = (int)(rowptr[row + 1] - b);
-    wave_sort_row<VT, LD>(ld, ld.base(row), len, sorted != 0, okey + b, oval + b, s_k[w]);
+    wave_sort_row<VT, LD>(ld, ld.base(row), len, sorted != 0, okey + b, oval + b, sm.k[w]);
+}
+
+template <typename PT, typename VT, typename LD>
+__global__ __launch_bounds__(256) void k_seg_wave(const PT *__restrict__ rowptr, int32_t *okey,
+                                                 VT *oval, const uint32_t *__restrict__ list,
+                                                 uint32_t count, LD ld, int sorted,
+                                                 const DevHdr *hdr) {
+    __shared__ __align__(16) SegSmemWave sm;
+    seg_wave_tile<PT, VT, LD>(blockIdx.x, sm, rowptr, okey, oval, list, count, ld, sorted, hdr);
 }
 
 // All rows of <= SMALL_MAX entries, without lists: each wavefront takes 64
@@ -182,13 +203,11 @@ __global__ __launch_bounds__(256) void k_seg_wave(const PT *__restrict__ rowptr,
 // 17..64 by the whole wavefront one after another.  Longer rows are left to
 // the class kernels.
 template <typename PT, typename VT, typename LD>
-__global__ __launch_bounds__(256) void k_sort_small(const PT *__restrict__ rowptr, int32_t *okey,
-                                                   VT *oval, int64_t nrows, LD ld,
-                                                   const DevHdr *hdr) {
-    __shared__ __align__(16) int32_t s_k[4][WAVE_MAX];
+__device__ void sort_small_tile(int64_t bid, SegSmemWave &sm, const PT *__restrict__ rowptr, int32_t *okey,
+                                VT *oval, int64_t nrows, const LD &ld, const DevHdr *hdr) {
     if (hdr->err) return;
     const int w = threadIdx.x / WAVE, l = lane_id();
-    const int64_t row = ((int64_t)blockIdx.x * 4 + w) * WAVE + l;
+    const int64_t row = (bid * 4 + w) * WAVE + l;
     int len = 0;
     int64_t b = 0;
     if (row < nrows) {
@@ -203,11 +222,19 @@ __global__ __launch_bounds__(256) void k_sort_small(const PT *__restrict__ rowpt
         const int64_t r = __shfl(row, src, WAVE);
         const int64_t rb = __shfl(b, src, WAVE);
         const int rl = __shfl(len, src, WAVE);
-        wave_sort_row<VT, LD>(ld, ld.base(r), rl, false, okey + rb, oval + rb, s_k[w]);
+        wave_sort_row<VT, LD>(ld, ld.base(r), rl, false, okey + rb, oval + rb, sm.k[w]);
     }
 }
 
-// ---- workgroup LDS sort of <= 4096 keys with their 16-bit source index ----
+template <typename PT, typename VT, typename LD>
+__global__ __launch_bounds__(256) void k_sort_small(const PT *__restrict__ rowptr, int32_t *okey,
+                                                   VT *oval, int64_t nrows, LD ld,
+                                                   const DevHdr *hdr) {
+    __shared__ __align__(16) SegSmemWave sm;
+    sort_small_tile<PT, VT, LD>(blockIdx.x, sm, rowptr, okey, oval, nrows, ld, hdr);
+}
+
+// ---- workgroup LDS sort of <= BLOCK_MAX keys with their 16-bit source index ----
 // In: s_k0/s_i0 hold N (a multiple of 64) keys, real keys distinct, padded
 // with INT_MAX.  Out: sorted (key, index) pairs in buffer 0 or 1 (returned).
 __device__ int block_sort_lds(int32_t *s_k0, uint16_t *s_i0, int32_t *s_k1, uint16_t *s_i1, int N) {
@@ -261,14 +288,16 @@ __device__ int block_sort_lds(int32_t *s_k0, uint16_t *s_i0, int32_t *s_k1, uint
     return cur;
 }
 
+struct SegSmemBlock {
+    int32_t k[2][BLOCK_MAX];
+    uint16_t i[2][BLOCK_MAX];
+};
+
 template <typename PT, typename VT, typename LD>
-__global__ __launch_bounds__(256) void k_seg_block(const PT *__restrict__ rowptr, int32_t *okey,
-                                                  VT *oval, const uint32_t *__restrict__ list,
-                                                  uint32_t count, LD ld, int sorted,
-                                                  const DevHdr *hdr) {
-    __shared__ int32_t s_k[2][BLOCK_MAX];
-    __shared__ uint16_t s_i[2][BLOCK_MAX];
-    uint32_t t = blockIdx.x;
+__device__ void seg_block_tile(int64_t bid, SegSmemBlock &sm, const PT *__restrict__ rowptr, int32_t *okey,
+                               VT *oval, const uint32_t *__restrict__ list, uint32_t count, const LD &ld,
+                               int sorted, const DevHdr *hdr) {
+    const int64_t t = bid;
     if (t >= count || hdr->err) return;
     int64_t row = list[t];
     int64_t b = rowptr[row];
@@ -293,11 +322,11 @@ __global__ __launch_bounds__(256) void k_seg_block(const PT *__restrict__ rowptr
             VT vv;
             ld.get(sb, i, kk, vv);
         }
-        s_k[0][i] = kk;
-        s_i[0][i] = (uint16_t)i;
+        sm.k[0][i] = kk;
+        sm.i[0][i] = (uint16_t)i;
     }
     __syncthreads();
-    const int cur = block_sort_lds(s_k[0], s_i[0], s_k[1], s_i[1], N);
+    const int cur = block_sort_lds(sm.k[0], sm.i[0], sm.k[1], sm.i[1], N);
     // gather every value first: with an in-place loader the row is both the
     // source and the destination
     constexpr int PER = BLOCK_MAX / 256;
@@ -308,7 +337,7 @@ __global__ __launch_bounds__(256) void k_seg_block(const PT *__restrict__ rowptr
         vr[q] = VT(0);
         if (i < len) {
             int32_t kk;
-            ld.get(sb, s_i[cur][i], kk, vr[q]);
+            ld.get(sb, sm.i[cur][i], kk, vr[q]);
         }
     }
     __syncthreads();
@@ -316,29 +345,42 @@ __global__ __launch_bounds__(256) void k_seg_block(const PT *__restrict__ rowptr
     for (int q = 0; q < PER; q++) {
         const int i = q * 256 + threadIdx.x;
         if (i < len) {
-            okey[b + i] = s_k[cur][i];
+            okey[b + i] = sm.k[cur][i];
             oval[b + i] = vr[q];
         }
     }
 }
 
+template <typename PT, typename VT, typename LD>
+__global__ __launch_bounds__(256) void k_seg_block(const PT *__restrict__ rowptr, int32_t *okey,
+                                                  VT *oval, const uint32_t *__restrict__ list,
+                                                  uint32_t count, LD ld, int sorted,
+                                                  const DevHdr *hdr) {
+    __shared__ SegSmemBlock sm;
+    seg_block_tile<PT, VT, LD>(blockIdx.x, sm, rowptr, okey, oval, list, count, ld, sorted, hdr);
+}
+
 // ---- GLOBAL class, step 1: split one long row into key buckets ------------
-// Bucket of key k is k >> 12 (width 4096), so a bucket holds at most 4096
+// Bucket of key k is k >> BKT_SHIFT, so a bucket holds at most BLOCK_MAX
 // distinct keys.  Elements are placed into the row's temporary region in
 // bucket order (arbitrary order inside a bucket); the bucket start offsets
 // go to bstart[t * (nb + 1) + ...].
-constexpr int BKT_SHIFT = 12;
+constexpr int BKT_SHIFT = 11;   // bucket width 2048 = BLOCK_MAX
 constexpr int BKT_MAXNB = 4096;
 
+struct SegSmemBucket {
+    uint32_t h[BKT_MAXNB + 1];
+    uint32_t sw[4];
+};
+
 template <typename PT, typename VT, typename LD>
-__global__ __launch_bounds__(256) void k_seg_bucket(const PT *__restrict__ rowptr,
-                                                   const uint32_t *__restrict__ list,
-                                                   const uint64_t *__restrict__ goff, uint32_t count,
-                                                   LD ld, int nb, int32_t *tkey, VT *tval,
-                                                   uint32_t *bstart, const DevHdr *hdr) {
-    __shared__ uint32_t s_h[BKT_MAXNB + 1];
-    __shared__ uint32_t s_sw[4];
-    uint32_t t = blockIdx.x;
+__device__ void seg_bucket_tile(int64_t bid, SegSmemBucket &sm, const PT *__restrict__ rowptr,
+                                const uint32_t *__restrict__ list, const uint64_t *__restrict__ goff,
+                                uint32_t count, const LD &ld, int nb, int32_t *tkey, VT *tval, uint32_t *bstart,
+                                const DevHdr *hdr) {
+    uint32_t *s_h = sm.h;
+    uint32_t *s_sw = sm.sw;
+    const int64_t t = bid;
     if (t >= count || hdr->err) return;
     const int64_t row = list[t];
     const int64_t b = rowptr[row];
@@ -382,19 +424,29 @@ __global__ __launch_bounds__(256) void k_seg_bucket(const PT *__restrict__ rowpt
         yk[pos] = kk;
         yv[pos] = vv;
     }
+    __syncthreads();
+}
+
+template <typename PT, typename VT, typename LD>
+__global__ __launch_bounds__(256) void k_seg_bucket(const PT *__restrict__ rowptr,
+                                                   const uint32_t *__restrict__ list,
+                                                   const uint64_t *__restrict__ goff, uint32_t count,
+                                                   LD ld, int nb, int32_t *tkey, VT *tval,
+                                                   uint32_t *bstart, const DevHdr *hdr) {
+    __shared__ SegSmemBucket sm;
+    seg_bucket_tile<PT, VT, LD>(blockIdx.x, sm, rowptr, list, goff, count, ld, nb, tkey, tval, bstart, hdr);
 }
 
 // ---- GLOBAL class, step 2: sort every bucket in LDS into the output row ----
 template <typename PT, typename VT>
-__global__ __launch_bounds__(256) void k_seg_bucket_sort(const PT *__restrict__ rowptr, int32_t *okey,
-                                                        VT *oval, const uint32_t *__restrict__ list,
-                                                        const uint64_t *__restrict__ goff,
-                                                        uint32_t count, int nb, const int32_t *tkey,
-                                                        const VT *tval, const uint32_t *bstart,
-                                                        const DevHdr *hdr) {
-    __shared__ int32_t s_k[2][BLOCK_MAX];
-    __shared__ uint16_t s_i[2][BLOCK_MAX];
-    const int64_t item = blockIdx.x;
+__device__ void seg_bucket_sort_tile(int64_t bid, SegSmemBlock &sm, const PT *__restrict__ rowptr,
+                                     int32_t *okey, VT *oval, const uint32_t *__restrict__ list,
+                                     const uint64_t *__restrict__ goff, uint32_t count, int nb,
+                                     const int32_t *tkey, const VT *tval, const uint32_t *bstart,
+                                     const DevHdr *hdr) {
+    auto &s_k = sm.k;
+    auto &s_i = sm.i;
+    const int64_t item = bid;
     const uint32_t t = (uint32_t)(item / nb);
     const int bk = (int)(item % nb);
     if (t >= count || hdr->err) return;
@@ -425,6 +477,19 @@ __global__ __launch_bounds__(256) void k_seg_bucket_sort(const PT *__restrict__ 
         okey[ob + i] = s_k[cur][i];
         oval[ob + i] = yv[s_i[cur][i]];
     }
+    __syncthreads();
+}
+
+template <typename PT, typename VT>
+__global__ __launch_bounds__(256) void k_seg_bucket_sort(const PT *__restrict__ rowptr, int32_t *okey,
+                                                        VT *oval, const uint32_t *__restrict__ list,
+                                                        const uint64_t *__restrict__ goff,
+                                                        uint32_t count, int nb, const int32_t *tkey,
+                                                        const VT *tval, const uint32_t *bstart,
+                                                        const DevHdr *hdr) {
+    __shared__ SegSmemBlock sm;
+    seg_bucket_sort_tile<PT, VT>(blockIdx.x, sm, rowptr, okey, oval, list, goff, count, nb, tkey, tval, bstart,
+                                 hdr);
 }
 
 // ---- GLOBAL class fallback (more than 2^24 output columns): LSD radix ------

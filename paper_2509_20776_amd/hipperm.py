@@ -50,6 +50,18 @@ class hp_plan_info_t(ctypes.Structure):
                 ("aux", ctypes.c_int64 * 4)]
 
 
+class hp_request_t(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("status", ctypes.c_int32), ("A", hp_csr_t),
+                ("I", ctypes.c_void_p), ("J", ctypes.c_void_p), ("nI", ctypes.c_int64),
+                ("nJ", ctypes.c_int64), ("p", ctypes.c_void_p), ("q", ctypes.c_void_p), ("C", hp_csr_t)]
+
+
+class hp_batch_info_t(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_size_t), ("nnz_total", ctypes.c_int64), ("failed", ctypes.c_int32),
+                ("grid_plan", ctypes.c_int32), ("tiles_plan", ctypes.c_int64), ("tiles_exec", ctypes.c_int64),
+                ("grid_exec", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _SZ = ctypes.c_size_t
@@ -79,6 +91,11 @@ hp_permute_exec = _sig("hp_permute_exec", [_P, _CSRP, _P, _P, _CSRP, _P, _SZ, _I
 hp_spref_workspace = _sig("hp_spref_workspace", [_P, _CSRP, _I64, _I64, ctypes.POINTER(_SZ)])
 hp_spref_plan = _sig("hp_spref_plan", [_P, _CSRP, _P, _I64, _P, _I64, _CSRP, _P, _SZ, _INFOP])
 hp_spref_exec = _sig("hp_spref_exec", [_P, _CSRP, _P, _I64, _P, _I64, _CSRP, _P, _SZ, _INFOP, _P, _SZ])
+_REQP = ctypes.POINTER(hp_request_t)
+_BINFOP = ctypes.POINTER(hp_batch_info_t)
+hp_batch_workspace = _sig("hp_batch_workspace", [_P, _REQP, ctypes.c_int, ctypes.POINTER(_SZ)])
+hp_batch_plan = _sig("hp_batch_plan", [_P, _REQP, ctypes.c_int, _P, _SZ, _BINFOP])
+hp_batch_exec = _sig("hp_batch_exec", [_P, _REQP, ctypes.c_int, _P, _SZ, _BINFOP, _P, _SZ])
 hp_validate_workspace = _sig("hp_validate_workspace", [_P, _CSRP, ctypes.POINTER(_SZ)])
 hp_validate_csr = _sig("hp_validate_csr", [_P, _CSRP, _P, _SZ])
 hp_spasgn_workspace = _sig("hp_spasgn_workspace", [_P, _CSRP, _CSRP, ctypes.POINTER(_SZ)])
@@ -302,6 +319,80 @@ class Handle:
     def spasgn(self, A, B, I, J, op="second"):
         C, ws, info = self.spasgn_plan(A, B, I, J, op)
         return self.spasgn_exec(A, B, I, J, C, ws, info, op)
+
+
+KINDS = {"spref": 0, "permute": 1}
+
+
+class Batch:
+    """Many spref / permute requests planned and executed together
+    (hp_batch_plan / hp_batch_exec).  Each request is a dict with
+    kind="spref" (A, I, J) or kind="permute" (A, p, q=None)."""
+
+    def __init__(self, handle: "Handle", requests):
+        self.hd = handle
+        self.requests = list(requests)
+        n = len(self.requests)
+        self.arr = (hp_request_t * max(n, 1))()
+        for k, r in enumerate(self.requests):
+            rq = self.arr[k]
+            rq.kind = KINDS[r["kind"]]
+            rq.A = to_csr_t(r["A"])
+            if r["kind"] == "spref":
+                rq.I, rq.J = _idx(r["I"]), _idx(r["J"])
+                rq.nI, rq.nJ = int(r["I"].numel()), int(r["J"].numel())
+            else:
+                rq.p, rq.q = _idx(r["p"]), _idx(r.get("q"))
+        self.ws = None
+        self.arena = None
+        self.info = hp_batch_info_t()
+
+    def plan(self):
+        self.hd._stream()
+        n = len(self.requests)
+        need = _SZ(0)
+        self.hd.check(hp_batch_workspace(self.hd.h, self.arr, n, ctypes.byref(need)))
+        if self.ws is None or self.ws.numel() < need.value:
+            self.ws = self.hd._alloc(need.value)
+        self.hd.check(hp_batch_plan(self.hd.h, self.arr, n, _dptr(self.ws), self.ws.numel(),
+                                    ctypes.byref(self.info)))
+        return [int(self.arr[k].status) for k in range(n)]
+
+    def exec(self):
+        self.hd._stream()
+        n = len(self.requests)
+        if self.arena is None or self.arena.numel() < self.info.arena_bytes:
+            self.arena = self.hd._alloc(self.info.arena_bytes)
+        self.hd.check(hp_batch_exec(self.hd.h, self.arr, n, _dptr(self.ws), self.ws.numel(),
+                                    ctypes.byref(self.info), _dptr(self.arena), self.arena.numel()))
+
+    def results(self):
+        """CSR views into the arena (None for requests that failed)."""
+        base = self.arena.data_ptr()
+        out = []
+        for k, r in enumerate(self.requests):
+            rq = self.arr[k]
+            if rq.status != 0:
+                out.append(None)
+                continue
+            C = rq.C
+            pt = torch.int64 if C.ptr_type == 1 else torch.int32
+            vt = torch.float64 if C.val_type == 1 else torch.float32
+
+            def view(ptr, count, dt):
+                es = torch.empty(0, dtype=dt).element_size()
+                if count == 0:
+                    return torch.empty(0, dtype=dt, device=self.arena.device)
+                off = ptr - base
+                return self.arena[off:off + count * es].view(dt)
+            out.append(CSR(int(C.nrows), int(C.ncols), view(C.rowptr, int(C.nrows) + 1, pt),
+                           view(C.col or base, int(C.nnz), torch.int32), view(C.val or base, int(C.nnz), vt)))
+        return out
+
+    def run(self):
+        self.plan()
+        self.exec()
+        return self.results()
 
 
 _default = {}
