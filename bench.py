@@ -225,6 +225,20 @@ def run_grid_assign(hp, args):
     return res
 
 
+def copy_calibration(mib):
+    """A plain device-to-device copy of known size: under rocprofv3 --pmc its
+    FETCH_SIZE / WRITE_SIZE per dispatch give the factor that turns counter
+    readings into HBM bytes."""
+    n = mib << 20
+    src = torch.ones(n // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    _sync()
+    log(f"[bench] copy calibration: {n} bytes read and {n} bytes written per copy")
+    del src, dst
+
+
 WORKLOADS = {"rmat-extract": run_rmat_extract, "grid-permute": run_grid_permute,
              "grid-assign": run_grid_assign}
 
@@ -240,6 +254,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-extras", dest="extras", action="store_false")
+    ap.add_argument("--copy-cal-mb", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
@@ -249,6 +265,8 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     from paper_2509_20776_amd import hipperm as hp
+    if args.copy_cal_mb > 0:
+        copy_calibration(args.copy_cal_mb)
     head = WORKLOADS[args.workload](hp, args)
     also = {}
     if args.extras:

@@ -47,10 +47,13 @@ constexpr int CLEAR_PER_TILE = 4096;   // words cleared / copied per tile
 // Stage of each phase, per half and request kind (-1: phase not used).
 //   spref plan: {0} {1,2} {3,5} {4} {6} {7}; exec: {0} {1} {2..6} {7}
 //   permute plan: {0} {1} {2} {3};  exec: {0,1} {3..6} {7}
+// Phase 7 of exec (ranking long rows through a 128 KB LDS bitmap) is the
+// only content of exec stage RANK_STAGE, which runs its own kernel.
 constexpr int8_t STAGE_OF[2][2][NPH] = {
     {{0, 1, 1, 2, 3, 2, 4, 5}, {0, 1, 2, 3, -1, -1, -1, -1}},
-    {{0, 1, 2, 2, 2, 2, 2, 3}, {0, 0, -1, 1, 1, 1, 1, 2}},
+    {{0, 1, 2, 2, 2, 2, 2, 3}, {0, 0, -1, 1, 1, 1, 1, 3}},
 };
+constexpr int RANK_STAGE = 3;
 
 struct ReqDev {
     int32_t kind, sym, monotone, active;
@@ -207,10 +210,6 @@ __device__ void run_tile(int half, int phase, int64_t tile, const ReqDev &r, Bat
                 seg_bucket_tile<PT, VT>(tile, sm.bucket, crow, r.lists + BIN_GLOBAL * cap, goff, r.cls[BIN_GLOBAL], ld,
                                         r.nb, tk, tv, bst, r.hdr);
                 break;
-            case 7:
-                seg_bucket_sort_tile<PT, VT>(tile, sm.block, crow, r.ccol, (VT *)r.cval, r.lists + BIN_GLOBAL * cap,
-                                             goff, r.cls[BIN_GLOBAL], r.nb, tk, tv, bst, r.hdr);
-                break;
         }
     } else {
         perm::LoadPerm<PT, VT> ld{(const PT *)r.arow, r.acol, (const VT *)r.aval, r.p, r.qinv, r.n};
@@ -236,11 +235,28 @@ __device__ void run_tile(int half, int phase, int64_t tile, const ReqDev &r, Bat
                 seg_bucket_tile<PT, VT>(tile, sm.bucket, crow, r.lists + BIN_GLOBAL * cap, goff, r.cls[BIN_GLOBAL], ld,
                                         r.nb, tk, tv, bst, r.hdr);
                 break;
-            case 7:
-                seg_bucket_sort_tile<PT, VT>(tile, sm.block, crow, r.ccol, (VT *)r.cval, r.lists + BIN_GLOBAL * cap,
-                                             goff, r.cls[BIN_GLOBAL], r.nb, tk, tv, bst, r.hdr);
-                break;
         }
+    }
+}
+
+// Exec phase 7: rank one bucket of a long row (RANK_THREADS threads).
+template <typename PT, typename VT>
+__device__ void run_rank_tile(int64_t tile, const ReqDev &r, SegSmemRank &sm) {
+    const PT *crow = (const PT *)r.crow_tmp;
+    const int64_t cap = r.kind == HP_REQ_SPREF ? r.nI : r.m;
+    const uint64_t *goff = reinterpret_cast<const uint64_t *>(r.lists + NBINS * cap);
+    int32_t *tk = (int32_t *)r.tmp;
+    char *tp = (char *)r.tmp + ((r.glob_elems * sizeof(int32_t) + 255) & ~uint64_t(255));
+    VT *tv = (VT *)tp;
+    const uint32_t *bst = (const uint32_t *)(tp + ((r.glob_elems * sizeof(VT) + 255) & ~uint64_t(255)));
+    if (r.kind == HP_REQ_SPREF) {
+        LoadInPlace<PT, VT> ld{crow, r.ccol, (const VT *)r.cval};
+        seg_rank_tile<PT, VT>(tile, sm, crow, r.ccol, (VT *)r.cval, r.lists + BIN_GLOBAL * cap, goff,
+                              r.cls[BIN_GLOBAL], ld, r.nb, tk, tv, bst, r.hdr);
+    } else {
+        perm::LoadPerm<PT, VT> ld{(const PT *)r.arow, r.acol, (const VT *)r.aval, r.p, r.qinv, r.n};
+        seg_rank_tile<PT, VT>(tile, sm, crow, r.ccol, (VT *)r.cval, r.lists + BIN_GLOBAL * cap, goff,
+                              r.cls[BIN_GLOBAL], ld, r.nb, tk, tv, bst, r.hdr);
     }
 }
 
@@ -280,6 +296,38 @@ __global__ __launch_bounds__(256) void k_batch_stage(int half, const QEntry *__r
         const QEntry e = q[s_e];
         run_tile<PT, VT>(half, e.phase, t - e.first, reqs[e.req], sm);
         __syncthreads();   // LDS and s_t are reused by the next tile
+    }
+}
+
+// The rank stage of exec, same scheme with RANK_THREADS-wide workgroups.
+template <typename PT, typename VT>
+__global__ __launch_bounds__(RANK_THREADS) void k_batch_rank_stage(const QEntry *__restrict__ q, int nq,
+                                                                  int64_t total, const ReqDev *__restrict__ reqs,
+                                                                  uint32_t *ticket) {
+    __shared__ __align__(16) SegSmemRank sm;
+    __shared__ int64_t s_t;
+    __shared__ int32_t s_e;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int64_t t = atomicAdd(ticket, 1u);
+            int lo = 0;
+            if (t < total) {
+                int hi = nq;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (q[mid].first <= t) lo = mid;
+                    else hi = mid;
+                }
+            }
+            s_t = t;
+            s_e = lo;
+        }
+        __syncthreads();
+        const int64_t t = s_t;
+        if (t >= total) break;
+        const QEntry e = q[s_e];
+        run_rank_tile<PT, VT>(t - e.first, reqs[e.req], sm);
+        __syncthreads();
     }
 }
 
@@ -396,11 +444,7 @@ struct GraphEntry {
 std::map<hp_handle_t, std::map<GraphKey, GraphEntry>> g_graphs;
 std::map<std::string, int> g_tuned;                // autotuned grid per size class
 
-int num_cus(hp_handle_t h) {
-    hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, h->device) != hipSuccess) return 256;
-    return p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
-}
+int num_cus(hp_handle_t h) { return h->num_cus; }
 
 // Phase tile counts of one request.
 void plan_tiles(const hp_request_t &rq, const ReqDev &d, int64_t *nt) {
@@ -440,7 +484,7 @@ void exec_tiles(const hp_request_t &rq, const ReqDev &d, int64_t *nt) {
     nt[3] = cdiv(c[BIN_THREAD], 256);
     nt[4] = cdiv(c[BIN_WAVE], 4);
     nt[5] = c[BIN_BLOCK];
-    nt[6] = c[BIN_GLOBAL];
+    nt[6] = d.nb > 1 ? c[BIN_GLOBAL] : 0;
     nt[7] = (int64_t)c[BIN_GLOBAL] * d.nb;
 }
 
@@ -490,8 +534,13 @@ hipError_t launch_half(hp_handle_t h, int half, const Global &g, int n, const St
         const int64_t tot = S.total[st];
         if (tot <= 0) continue;
         const int gr = (int)std::min<int64_t>(tot, grid);
-        hipLaunchKernelGGL((k_batch_stage<PT, VT>), dim3(gr), dim3(256), 0, s, half, g.queue + S.off[st],
-                           S.off[st + 1] - S.off[st], tot, g.reqs, tk + st);
+        if (half == 1 && st == RANK_STAGE)   // one 1024-thread workgroup per CU at most
+            hipLaunchKernelGGL((k_batch_rank_stage<PT, VT>), dim3((int)std::min<int64_t>(tot, num_cus(h))),
+                               dim3(RANK_THREADS), 0, s, g.queue + S.off[st], S.off[st + 1] - S.off[st], tot,
+                               g.reqs, tk + st);
+        else
+            hipLaunchKernelGGL((k_batch_stage<PT, VT>), dim3(gr), dim3(256), 0, s, half, g.queue + S.off[st],
+                               S.off[st + 1] - S.off[st], tot, g.reqs, tk + st);
     }
     return hipGetLastError();
 }
@@ -616,8 +665,6 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
         d.glob_elems = H.bin_elems[BIN_GLOBAL];
         d.nb = seg_nbuckets(d.ncols_out);
         for (int b = 0; b < NBINS; b++) d.cls[b] = H.bin_cnt[b];
-        if (st == HP_OK && H.bin_cnt[BIN_GLOBAL] && d.nb > BKT_MAXNB)
-            st = fail(h, HP_ERR_INVALID_ARG, "batch: rows above 2048 entries with more than 2^23 output columns");
         r.status = st;
         d.active = st == HP_OK;
         if (st != HP_OK) {

@@ -122,6 +122,9 @@ extern "C" hp_status_t hp_create(hp_handle_t *out, int device) {
         delete h;
         return HP_ERR_HIP;
     }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        h->num_cus = prop.multiProcessorCount;
     *out = h;
     return HP_OK;
 }

@@ -144,6 +144,7 @@ struct hp_stage_rec {
 };
 struct hp_handle_s {
     int device = 0;
+    int num_cus = 256;                     // compute units of the device
     hipStream_t stream = nullptr;
     hp::DevHdr *host_hdr = nullptr;        // pinned readback block
     std::string last_error;

@@ -12,12 +12,9 @@
 //   WAVE    17..256   one wavefront, rank = number of smaller keys (LDS)
 //   BLOCK   257..2048 one workgroup: 64-element runs ranked per wavefront,
 //                     then merged pairwise in LDS (merge-path ranks)
-//   GLOBAL  > 2048    split by key range into buckets of width 2048 (one
-//                     workgroup per row, LDS histogram), then every bucket
-//                     (at most 2048 distinct keys) sorted by its own
-//                     workgroup as in BLOCK.  More than 4096 buckets (over
-//                     2^23 output columns) falls back to an LSD radix sort
-//                     per row.
+//   GLOBAL  > 2048    ranked through an LDS bitmap of the key range (one
+//                     1024-thread workgroup per 2^20 columns of the row;
+//                     wider rows are split by key range first).
 // Rows of <= 64 entries can also be sorted without lists by k_sort_small,
 // which walks all rows in groups of 64.
 #pragma once
@@ -360,19 +357,38 @@ __global__ __launch_bounds__(256) void k_seg_block(const PT *__restrict__ rowptr
     seg_block_tile<PT, VT, LD>(blockIdx.x, sm, rowptr, okey, oval, list, count, ld, sorted, hdr);
 }
 
-// ---- GLOBAL class, step 1: split one long row into key buckets ------------
-// Bucket of key k is k >> BKT_SHIFT, so a bucket holds at most BLOCK_MAX
-// distinct keys.  Elements are placed into the row's temporary region in
-// bucket order (arbitrary order inside a bucket); the bucket start offsets
-// go to bstart[t * (nb + 1) + ...].
-constexpr int BKT_SHIFT = 11;   // bucket width 2048 = BLOCK_MAX
-constexpr int BKT_MAXNB = 4096;
+// ---- GLOBAL class ------------------------------------------------------------
+// Keys of one row are distinct, so sorting a long row is ranking: mark every
+// key in an LDS bitmap of its key range, prefix-count the bitmap, and the
+// rank of a key is the number of marked bits below it.  A bitmap covers
+// 2^RB_SHIFT keys (128 KB of LDS); rows whose output has more columns are
+// first split by key range into buckets of that width (one workgroup per row,
+// LDS histogram), and every non-empty bucket is ranked by its own workgroup.
+// When one bucket covers all columns the split is skipped: the rank
+// workgroup reads the row through the loader and stashes it in the row's
+// temporary region, so in-place rows can be rewritten.
+constexpr int BKT_SHIFT = 20;                        // keys per bucket = bitmap bits
+constexpr int BKT_MAXNB = 4096;                      // buckets per row (2^31 columns need 2048)
+constexpr int RANK_THREADS = 1024;
+constexpr int RB_WORDS = 1 << (BKT_SHIFT - 5);       // 32768 bitmap words
+constexpr int RB_GRP = 8;                            // words per prefix group
+constexpr int RB_NGRP = RB_WORDS / RB_GRP;           // 4096 prefix entries
 
 struct SegSmemBucket {
     uint32_t h[BKT_MAXNB + 1];
     uint32_t sw[4];
 };
 
+struct SegSmemRank {
+    uint32_t bm[RB_WORDS];
+    uint32_t pre[RB_NGRP];
+    uint32_t sw[RANK_THREADS / WAVE];
+};
+
+// Split one long row into key buckets of width 2^BKT_SHIFT (256 threads).
+// Elements are placed into the row's temporary region in bucket order
+// (arbitrary order inside a bucket); the bucket start offsets go to
+// bstart[t * (nb + 1) + ...].
 template <typename PT, typename VT, typename LD>
 __device__ void seg_bucket_tile(int64_t bid, SegSmemBucket &sm, const PT *__restrict__ rowptr,
                                 const uint32_t *__restrict__ list, const uint64_t *__restrict__ goff,
@@ -437,165 +453,102 @@ __global__ __launch_bounds__(256) void k_seg_bucket(const PT *__restrict__ rowpt
     seg_bucket_tile<PT, VT, LD>(blockIdx.x, sm, rowptr, list, goff, count, ld, nb, tkey, tval, bstart, hdr);
 }
 
-// ---- GLOBAL class, step 2: sort every bucket in LDS into the output row ----
-template <typename PT, typename VT>
-__device__ void seg_bucket_sort_tile(int64_t bid, SegSmemBlock &sm, const PT *__restrict__ rowptr,
-                                     int32_t *okey, VT *oval, const uint32_t *__restrict__ list,
-                                     const uint64_t *__restrict__ goff, uint32_t count, int nb,
-                                     const int32_t *tkey, const VT *tval, const uint32_t *bstart,
-                                     const DevHdr *hdr) {
-    auto &s_k = sm.k;
-    auto &s_i = sm.i;
-    const int64_t item = bid;
-    const uint32_t t = (uint32_t)(item / nb);
+// Rank one bucket (item = t * nb + bucket) of GLOBAL row list[t] with
+// RANK_THREADS threads.  nb == 1: the row comes through the loader and is
+// stashed in its temporary region first; nb > 1: the bucket is read from the
+// temporary region the split wrote.  Every thread reads back only the
+// elements it stashed itself.
+template <typename PT, typename VT, typename LD>
+__device__ void seg_rank_tile(int64_t item, SegSmemRank &sm, const PT *__restrict__ rowptr, int32_t *okey,
+                              VT *oval, const uint32_t *__restrict__ list, const uint64_t *__restrict__ goff,
+                              uint32_t count, const LD &ld, int nb, int32_t *tkey, VT *tval,
+                              const uint32_t *__restrict__ bstart, const DevHdr *hdr) {
+    const int64_t t = item / nb;
     const int bk = (int)(item % nb);
     if (t >= count || hdr->err) return;
-    const uint32_t *bs = bstart + (int64_t)t * (nb + 1);
-    const uint32_t s0 = bs[bk], s1 = bs[bk + 1];
-    const int len = (int)(s1 - s0);
-    if (len == 0) return;
     const int64_t row = list[t];
-    const int64_t ob = (int64_t)rowptr[row] + s0;
-    const int32_t *yk = tkey + goff[t] + s0;
-    const VT *yv = tval + goff[t] + s0;
-    if (len > BLOCK_MAX) {
-        // only possible with repeated keys (a non-canonical input): copy
-        for (int i = threadIdx.x; i < len; i += 256) {
-            okey[ob + i] = yk[i];
-            oval[ob + i] = yv[i];
-        }
-        return;
+    const int64_t b = rowptr[row];
+    int64_t s0 = 0, len = rowptr[row + 1] - b;
+    if (nb > 1) {
+        const uint32_t *bs = bstart + t * (nb + 1);
+        s0 = bs[bk];
+        len = (int64_t)bs[bk + 1] - s0;
     }
-    const int N = (len + WAVE - 1) / WAVE * WAVE;
-    for (int i = threadIdx.x; i < N; i += 256) {
-        s_k[0][i] = i < len ? yk[i] : INT32_MAX;
-        s_i[0][i] = (uint16_t)i;
-    }
+    if (len == 0) return;
+    int32_t *yk = tkey + goff[t] + s0;
+    VT *yv = tval + goff[t] + s0;
+    const uint32_t kbase = (uint32_t)bk << BKT_SHIFT;
+    const int tid = threadIdx.x;
+    uint4 *bm4 = reinterpret_cast<uint4 *>(sm.bm);
+    for (int i = tid; i < RB_WORDS / 4; i += RANK_THREADS) bm4[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
-    const int cur = block_sort_lds(s_k[0], s_i[0], s_k[1], s_i[1], N);
-    for (int i = threadIdx.x; i < len; i += 256) {
-        okey[ob + i] = s_k[cur][i];
-        oval[ob + i] = yv[s_i[cur][i]];
-    }
-    __syncthreads();
-}
-
-template <typename PT, typename VT>
-__global__ __launch_bounds__(256) void k_seg_bucket_sort(const PT *__restrict__ rowptr, int32_t *okey,
-                                                        VT *oval, const uint32_t *__restrict__ list,
-                                                        const uint64_t *__restrict__ goff,
-                                                        uint32_t count, int nb, const int32_t *tkey,
-                                                        const VT *tval, const uint32_t *bstart,
-                                                        const DevHdr *hdr) {
-    __shared__ SegSmemBlock sm;
-    seg_bucket_sort_tile<PT, VT>(blockIdx.x, sm, rowptr, okey, oval, list, goff, count, nb, tkey, tval, bstart,
-                                 hdr);
-}
-
-// ---- GLOBAL class fallback (more than 2^24 output columns): LSD radix ------
-// X = the output row, Y = its temporary region.  Pass 0 reads through the
-// loader; the last pass writes X.  When the loader reads X itself and the
-// pass count is odd, the data is first copied to Y.
-template <typename PT, typename VT, typename LD>
-__global__ __launch_bounds__(256) void k_seg_global(const PT *__restrict__ rowptr, int32_t *okey,
-                                                   VT *oval, const uint32_t *__restrict__ list,
-                                                   const uint64_t *__restrict__ goff, uint32_t count,
-                                                   LD ld, int kbits, int inplace, int32_t *tkey,
-                                                   VT *tval, const DevHdr *hdr) {
-    __shared__ uint32_t s_hist[256];
-    __shared__ uint32_t s_base[256];
-    __shared__ uint32_t s_wc[4][256];
-    __shared__ uint32_t s_sw[4];
-    uint32_t t = blockIdx.x;
-    if (t >= count || hdr->err) return;
-    int64_t row = list[t];
-    int64_t b = rowptr[row];
-    int64_t len = rowptr[row + 1] - b;
-    int64_t sb = ld.base(row);
-    int32_t *xk = okey + b;
-    VT *xv = oval + b;
-    int32_t *yk = tkey + goff[t];
-    VT *yv = tval + goff[t];
-    const int w = threadIdx.x / WAVE;
-    const uint64_t lt = lanemask_lt();
-    const int passes = (kbits + 7) / 8;
-    bool from_loader = true;
-    if (inplace && (passes & 1)) {
-        for (int64_t i = threadIdx.x; i < len; i += 256) {
-            yk[i] = xk[i];
-            yv[i] = xv[i];
-        }
-        __syncthreads();
-        from_loader = false;
-    }
-    for (int i = threadIdx.x; i < 4 * 256; i += 256) (&s_wc[0][0])[i] = 0;
-    for (int pass = 0; pass < passes; pass++) {
-        const int shift = 8 * pass;
-        const bool to_x = ((passes - 1 - pass) & 1) == 0;
-        int32_t *dk = to_x ? xk : yk;
-        VT *dv = to_x ? xv : yv;
-        const int32_t *sk = to_x ? yk : xk;
-        const VT *sv = to_x ? yv : xv;
-        const bool use_ld = pass == 0 && from_loader;
-        s_hist[threadIdx.x] = 0;
-        __syncthreads();
-        for (int64_t i = threadIdx.x; i < len; i += 256) {
+    if (nb == 1) {
+        const int64_t sb = ld.base(row);
+        for (int64_t i = tid; i < len; i += RANK_THREADS) {
             int32_t kk;
-            if (use_ld) {
-                VT vv;
-                ld.get(sb, i, kk, vv);
-            } else {
-                kk = sk[i];
-            }
-            atomicAdd(&s_hist[((uint32_t)kk >> shift) & 255u], 1u);
+            VT vv;
+            ld.get(sb, i, kk, vv);
+            yk[i] = kk;
+            yv[i] = vv;
+            const uint32_t d = (uint32_t)kk;
+            atomicOr(&sm.bm[d >> 5], 1u << (d & 31));
         }
-        __syncthreads();
-        {
-            uint32_t tot;
-            uint32_t ex = block_excl_scan<256, uint32_t>(s_hist[threadIdx.x], s_sw, tot);
-            s_base[threadIdx.x] = ex;
-        }
-        __syncthreads();
-        for (int64_t c0 = 0; c0 < len; c0 += 256) {
-            int64_t i = c0 + threadIdx.x;
-            bool valid = i < len;
-            int32_t k = 0;
-            VT v = VT(0);
-            if (valid) {
-                if (use_ld) ld.get(sb, i, k, v);
-                else {
-                    k = sk[i];
-                    v = sv[i];
-                }
-            }
-            uint32_t d = ((uint32_t)k >> shift) & 255u;
-            uint64_t peers = ballot(valid);
-#pragma unroll
-            for (int bit = 0; bit < 8; bit++) {
-                uint64_t bb = ballot((d >> bit) & 1u);
-                peers &= ((d >> bit) & 1u) ? bb : ~bb;
-            }
-            uint32_t rank = (uint32_t)__popcll(peers & lt);
-            if (valid && rank == 0) s_wc[w][d] = (uint32_t)__popcll(peers);
-            __syncthreads();
-            if (valid) {
-                uint32_t off = s_base[d] + rank;
-                for (int ww = 0; ww < w; ww++) off += s_wc[ww][d];
-                dk[off] = k;
-                dv[off] = v;
-            }
-            __syncthreads();
-            {
-                const uint32_t dd = threadIdx.x;
-                s_base[dd] += s_wc[0][dd] + s_wc[1][dd] + s_wc[2][dd] + s_wc[3][dd];
-                s_wc[0][dd] = 0;
-                s_wc[1][dd] = 0;
-                s_wc[2][dd] = 0;
-                s_wc[3][dd] = 0;
-            }
-            __syncthreads();
+    } else {
+        for (int64_t i = tid; i < len; i += RANK_THREADS) {
+            const uint32_t d = (uint32_t)yk[i] - kbase;
+            atomicOr(&sm.bm[d >> 5], 1u << (d & 31));
         }
     }
+    __syncthreads();
+    // prefix counts of the bitmap in groups of RB_GRP words
+    constexpr int GPT = RB_NGRP / RANK_THREADS;   // groups per thread
+    uint32_t c[GPT];
+    uint32_t loc = 0;
+#pragma unroll
+    for (int g = 0; g < GPT; g++) {
+        const uint4 *w4 = bm4 + (size_t)(tid * GPT + g) * (RB_GRP / 4);
+        uint32_t n = 0;
+#pragma unroll
+        for (int q = 0; q < RB_GRP / 4; q++) {
+            const uint4 w = w4[q];
+            n += __popc(w.x) + __popc(w.y) + __popc(w.z) + __popc(w.w);
+        }
+        c[g] = n;
+        loc += n;
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan<RANK_THREADS, uint32_t>(loc, sm.sw, tot);
+#pragma unroll
+    for (int g = 0; g < GPT; g++) {
+        sm.pre[tid * GPT + g] = run;
+        run += c[g];
+    }
+    __syncthreads();
+    const int64_t ob = b + s0;
+    for (int64_t i = tid; i < len; i += RANK_THREADS) {
+        const int32_t kk = yk[i];
+        const VT vv = yv[i];
+        const uint32_t d = (uint32_t)kk - kbase;
+        const uint32_t w = d >> 5;
+        const uint32_t g0 = w & ~uint32_t(RB_GRP - 1);
+        uint32_t r = sm.pre[w / RB_GRP] + __popc(sm.bm[w] & ((1u << (d & 31)) - 1u));
+        for (uint32_t u = g0; u < w; u++) r += __popc(sm.bm[u]);
+        okey[ob + r] = kk;
+        oval[ob + r] = vv;
+    }
+    __syncthreads();
+}
+
+template <typename PT, typename VT, typename LD>
+__global__ __launch_bounds__(RANK_THREADS) void k_seg_rank(const PT *__restrict__ rowptr, int32_t *okey, VT *oval,
+                                                          const uint32_t *__restrict__ list,
+                                                          const uint64_t *__restrict__ goff, uint32_t count, LD ld,
+                                                          int nb, int32_t *tkey, VT *tval,
+                                                          const uint32_t *__restrict__ bstart,
+                                                          const DevHdr *hdr) {
+    __shared__ __align__(16) SegSmemRank sm;
+    seg_rank_tile<PT, VT, LD>(blockIdx.x, sm, rowptr, okey, oval, list, goff, count, ld, nb, tkey, tval, bstart,
+                              hdr);
 }
 
 // Class lists: NBINS lists of capacity cap, then cap uint64 temporary
@@ -645,16 +598,13 @@ hipError_t launch_seg_classes(hipStream_t s, const PT *rowptr, int32_t *okey, VT
         if (sorted) {
             hipLaunchKernelGGL((k_seg_block<PT, VT, LD>), dim3(cnt[BIN_GLOBAL]), dim3(256), 0, s, rowptr,
                                okey, oval, lists + BIN_GLOBAL * cap, cnt[BIN_GLOBAL], ld, 1, hdr);
-        } else if (nb <= BKT_MAXNB) {
-            hipLaunchKernelGGL((k_seg_bucket<PT, VT, LD>), dim3(cnt[BIN_GLOBAL]), dim3(256), 0, s, rowptr,
-                               lists + BIN_GLOBAL * cap, goff, cnt[BIN_GLOBAL], ld, nb, tk, tv, bst, hdr);
-            hipLaunchKernelGGL((k_seg_bucket_sort<PT, VT>), dim3((unsigned)((int64_t)cnt[BIN_GLOBAL] * nb)),
-                               dim3(256), 0, s, rowptr, okey, oval, lists + BIN_GLOBAL * cap, goff,
-                               cnt[BIN_GLOBAL], nb, tk, tv, bst, hdr);
         } else {
-            hipLaunchKernelGGL((k_seg_global<PT, VT, LD>), dim3(cnt[BIN_GLOBAL]), dim3(256), 0, s, rowptr,
-                               okey, oval, lists + BIN_GLOBAL * cap, goff, cnt[BIN_GLOBAL], ld,
-                               key_bits(ncols_out), (int)inplace, tk, tv, hdr);
+            if (nb > 1)
+                hipLaunchKernelGGL((k_seg_bucket<PT, VT, LD>), dim3(cnt[BIN_GLOBAL]), dim3(256), 0, s, rowptr,
+                                   lists + BIN_GLOBAL * cap, goff, cnt[BIN_GLOBAL], ld, nb, tk, tv, bst, hdr);
+            hipLaunchKernelGGL((k_seg_rank<PT, VT, LD>), dim3((unsigned)((int64_t)cnt[BIN_GLOBAL] * nb)),
+                               dim3(RANK_THREADS), 0, s, rowptr, okey, oval, lists + BIN_GLOBAL * cap, goff,
+                               cnt[BIN_GLOBAL], ld, nb, tk, tv, bst, hdr);
         }
     }
     return hipGetLastError();

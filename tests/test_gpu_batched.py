@@ -145,3 +145,20 @@ def test_batched_isolates_failed_request(hp):
     assert got[1] is None and got[3] is None
     assert_same(np_csr(got[0]), np_csr(hp.permute(A, p)), "ok permute")
     assert_same(np_csr(got[2]), np_csr(hp.spref(A, I, I)), "ok spref")
+
+
+def test_batched_long_rows_wide(hp):
+    _say("batched: long rows with more than 2^20 output columns")
+    n = 2_500_000
+    A = mixed_csr(91, 24, n, [0, 5, 2500, 20000], torch.int32, torch.float32)
+    I = synth.subset(92, A.nrows, 30, repeat_frac=0.2, device="cuda")
+    J = synth.subset(93, n, 2_200_000, device="cuda")
+    reqs = [dict(kind="spref", A=A, I=I, J=J),
+            dict(kind="permute", A=A, p=synth.randperm(94, A.nrows, "cuda"), q=synth.randperm(95, n, "cuda")),
+            dict(kind="spref", A=A, I=I, J=J[:900_000])]
+    b = hp.Batch(hp.handle(0), reqs)
+    assert b.plan() == [0, 0, 0]
+    b.exec()
+    got = b.results()
+    for k, r in enumerate(reqs):
+        assert_same(np_csr(got[k]), np_csr(_plain(hp, r)), f"request {k} ({r['kind']})")

@@ -97,3 +97,14 @@ def test_grid_full_size_sampled(hp):
     B = hp.permute(C, pinv, qinv)
     assert torch.equal(B.rowptr, A.rowptr) and torch.equal(B.col, A.col)
     assert torch.equal(B.val.view(torch.int64), A.val.view(torch.int64))
+
+
+def test_long_rows_over_2pow20_columns(hp):
+    """Rows above 2048 entries with more than 2^20 columns (bucketed ranking)."""
+    n = 2_200_000
+    A = mixed_csr(81, 30, n, [0, 3, 900, 5000, 40000], torch.int64, torch.float64)
+    p = synth.randperm(82, A.nrows, "cuda")
+    q = synth.randperm(83, n, "cuda")
+    C = hp.permute(A, p, q)
+    torch.cuda.synchronize()
+    assert_same(np_csr(C), oracle.permute(A, p, q), "permute")

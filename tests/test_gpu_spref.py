@@ -129,3 +129,21 @@ def test_rmat_full_size_sampled(hp):
     assert bool(torch.all((C.col[1:] > C.col[:-1]) | ~same_row[1:]))
     C2 = hp.spref(A, I, J)
     assert torch.equal(C2.col, C.col) and torch.equal(C2.val.view(torch.int32), C.val.view(torch.int32))
+
+
+@pytest.mark.parametrize("ptr", [torch.int32, torch.int64])
+def test_long_rows_over_2pow20_columns(hp, ptr):
+    """Output rows above 2048 entries with more than 2^20 output columns:
+    long rows are split by key range before ranking (3 buckets here)."""
+    n = 3_000_000
+    A = mixed_csr(77, 40, n, [0, 7, 300, 3000, 12000, 30000], ptr, torch.float32)
+    I = synth.subset(78, A.nrows, 50, repeat_frac=0.3, device="cuda")
+    J = synth.subset(79, n, 2_500_000, repeat_frac=0.01, device="cuda")
+    C = hp.spref(A, I, J)
+    torch.cuda.synchronize()
+    rows = sample_rows(80, I.numel(), 6)
+    assert_same(rows_of(C, rows), oracle.spref(A, I, J, rows=rows), "sampled rows")
+    cr = C.rowptr.long()
+    same_row = torch.ones(C.nnz, dtype=torch.bool, device="cuda")
+    same_row[cr[:-1][cr[:-1] < C.nnz]] = False
+    assert bool(torch.all((C.col[1:] > C.col[:-1]) | ~same_row[1:]))
