@@ -186,17 +186,20 @@ hp_status_t hp_spasgn_exec(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, 
  * Ownership: the caller owns the workspace and the arena; results point
  * into the arena.  hp_batch_exec must follow the hp_batch_plan of the same
  * batch on the same handle and workspace. */
-typedef enum { HP_REQ_SPREF = 0, HP_REQ_PERMUTE = 1 } hp_req_kind_t;
+typedef enum { HP_REQ_SPREF = 0, HP_REQ_PERMUTE = 1, HP_REQ_SPASGN = 2 } hp_req_kind_t;
 
 typedef struct {
-    int32_t kind;          /* hp_req_kind_t                                        */
+    int32_t kind;          /* hp_req_kind_t (the batched calls take SPREF, PERMUTE) */
     int32_t status;        /* out: hp_status_t of this request after plan/exec     */
     hp_csr_t A;            /* input matrix (device arrays)                         */
-    const int32_t *I, *J;  /* spref: selected rows / columns (device)              */
-    int64_t nI, nJ;
+    const int32_t *I, *J;  /* spref, spasgn: row / column index vectors (device)   */
+    int64_t nI, nJ;        /* spasgn: taken from B                                 */
     const int32_t *p, *q;  /* permute: permutations (device); q NULL = symmetric    */
     hp_csr_t C;            /* out: shape/types/nnz after plan; rowptr/col/val point
                               into the arena after exec                            */
+    hp_csr_t B;            /* spasgn: the |I| x |J| block                          */
+    int32_t op;            /* spasgn: hp_asgn_op_t                                 */
+    int32_t pad;
 } hp_request_t;
 
 typedef struct {
@@ -207,8 +210,10 @@ typedef struct {
     int64_t tiles_plan;    /* tiles over all plan stages                            */
     int64_t tiles_exec;    /* tiles over all exec stages (set by exec)              */
     int32_t grid_exec;     /* persistent workgroups per exec stage (set by exec)    */
-    int32_t reserved;
+    int32_t flags;         /* in: HP_BATCH_NO_GRAPH launches exec directly          */
 } hp_batch_info_t;
+
+#define HP_BATCH_NO_GRAPH 1
 
 /* Workspace for a batch (tables, counters and rowptrs of every request). */
 hp_status_t hp_batch_workspace(hp_handle_t h, const hp_request_t *reqs, int n, size_t *bytes);
@@ -220,6 +225,56 @@ hp_status_t hp_batch_plan(hp_handle_t h, hp_request_t *reqs, int n, void *ws, si
  * every request with status HP_OK; failed requests are skipped). */
 hp_status_t hp_batch_exec(hp_handle_t h, hp_request_t *reqs, int n, void *ws, size_t ws_bytes,
                           hp_batch_info_t *info, void *arena, size_t arena_bytes);
+
+/* ---- served form ---------------------------------------------------------- */
+/* A request server on one device.  Requests (extraction, assignment,
+ * permutation) on caller-owned, resident, immutable matrices are submitted
+ * as they arrive and complete asynchronously.  Worker threads, each with its
+ * own handle and stream, take whatever requests are pending when they become
+ * free (continuous batching): extraction and permutation requests of one
+ * index/value type go through the batched calls above (up to max_batch per
+ * batch), assignment requests through the plain calls.  Up to max_inflight
+ * batches run at once on separate streams.
+ * Memory: every workspace and every result is carved from the caller's
+ * device buffer `pool` (pool_bytes, the HBM budget).  A batch is admitted
+ * when its workspace fits the free pool space; after its plan, its exact
+ * output arena must fit too.  While memory is short a batch waits for
+ * running batches to finish; a batch that cannot fit while no other batch
+ * runs is split into single requests, and a single request that cannot fit
+ * then completes with HP_ERR_REJECTED (unreleased results count as used).
+ * Results stay in the pool until hp_server_release.
+ * Latency is measured on the host: submit, start of the request's batch,
+ * and the end of its exec (stream synchronised), in ns of a monotonic clock. */
+typedef struct hp_server_s *hp_server_t;
+
+typedef struct {
+    int32_t max_inflight;  /* worker threads / streams (1..16; 0 = 4)              */
+    int32_t max_batch;     /* requests per batch (0 = 256)                         */
+} hp_server_config_t;
+
+typedef struct {
+    uint64_t id;           /* from hp_server_submit                                */
+    int32_t status;        /* hp_status_t of the request                           */
+    int32_t batch_size;    /* requests in the batch it ran in                      */
+    hp_csr_t C;            /* the result (arrays inside the pool) when status OK   */
+    int64_t t_submit_ns, t_start_ns, t_done_ns;
+} hp_completion_t;
+
+hp_status_t hp_server_create(hp_server_t *out, int device, void *pool, size_t pool_bytes,
+                             const hp_server_config_t *cfg);
+/* Copies *req (the matrices and index vectors it points to must stay valid
+ * and unchanged until the request completes); *id receives its id. */
+hp_status_t hp_server_submit(hp_server_t s, const hp_request_t *req, uint64_t *id);
+/* Moves up to cap completions into out (*n of them); never blocks. */
+hp_status_t hp_server_poll(hp_server_t s, hp_completion_t *out, int cap, int *n);
+/* Blocks until every submitted request has completed. */
+hp_status_t hp_server_drain(hp_server_t s);
+/* Returns the pool space of a completed request's result. */
+hp_status_t hp_server_release(hp_server_t s, uint64_t id);
+/* Pool bytes in use (workspaces and unreleased results) and the peak. */
+hp_status_t hp_server_memory(hp_server_t s, size_t *in_use, size_t *peak);
+/* Drains, stops the workers and frees the server (not the pool). */
+hp_status_t hp_server_destroy(hp_server_t s);
 
 #ifdef __cplusplus
 }

@@ -26,18 +26,12 @@ HIP_FLAGS = [
 
 
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
-                  if f.endswith(".hip") or f.endswith(".cpp"))
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    if src.endswith(".cpp"):
-        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-I", "/opt/rocm/include",
-               "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(HERE, "..", "include"),
-               "-c", src, "-o", obj]
-    else:
-        cmd = [HIPCC, *HIP_FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *HIP_FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -32,6 +32,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -414,6 +415,8 @@ hp_status_t check_req(hp_handle_t h, const hp_request_t &r, int k, int32_t pt, i
     } else if (r.kind == HP_REQ_PERMUTE) {
         if (!r.q && r.A.nrows != r.A.ncols) return fail(h, HP_ERR_SHAPE, w + ": symmetric permute needs square A");
         if (r.A.nrows > 0 && !r.p) return fail(h, HP_ERR_INVALID_ARG, w + ": p is NULL");
+    } else if (r.kind == HP_REQ_SPASGN) {
+        return fail(h, HP_ERR_INVALID_ARG, w + ": assignment requests are not batched (use hp_spasgn_*)");
     } else {
         return fail(h, HP_ERR_INVALID_ARG, w + ": unknown request kind");
     }
@@ -443,6 +446,7 @@ struct GraphEntry {
 };
 std::map<hp_handle_t, std::map<GraphKey, GraphEntry>> g_graphs;
 std::map<std::string, int> g_tuned;                // autotuned grid per size class
+std::mutex g_mu;                                   // guards the three maps (handles may run concurrently)
 
 int num_cus(hp_handle_t h) { return h->num_cus; }
 
@@ -550,8 +554,11 @@ hipError_t launch_half(hp_handle_t h, int half, const Global &g, int n, const St
 // rewrites the same outputs).
 template <typename PT, typename VT>
 int tune_grid(hp_handle_t h, int half, const Global &g, int n, const Stages &S, const std::string &key) {
-    auto it = g_tuned.find(key);
-    if (it != g_tuned.end()) return it->second;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) return it->second;
+    }
     const int cus = num_cus(h);
     const int cand[3] = {cus, 2 * cus, 4 * cus};
     int best = cand[1];
@@ -574,6 +581,7 @@ int tune_grid(hp_handle_t h, int half, const Global &g, int n, const Stages &S, 
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_mu);
     g_tuned[key] = best;
     return best;
 }
@@ -639,7 +647,12 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
     stage_begin(h);
     e = launch_half<PT, VT>(h, 0, g, n, S, grid);
     stage_mark(h, "batch.plan");
-    BatchState &bs = g_state[h];
+    BatchState *bsp;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        bsp = &g_state[h];   // map nodes are stable; one handle is used by one thread at a time
+    }
+    BatchState &bs = *bsp;
     bs.hdrs.resize(n);
     if (e == hipSuccess) e = hipMemcpyAsync(bs.hdrs.data(), g.hdrs, sizeof(DevHdr) * n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -698,10 +711,15 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
 template <typename PT, typename VT>
 hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, size_t ws_bytes,
                          hp_batch_info_t *info, void *arena, size_t arena_bytes) {
-    auto it = g_state.find(h);
-    if (it == g_state.end() || it->second.ws != ws || it->second.n != n)
+    BatchState *bsp = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_state.find(h);
+        if (it != g_state.end()) bsp = &it->second;
+    }
+    if (!bsp || bsp->ws != ws || bsp->n != n)
         return fail(h, HP_ERR_INVALID_ARG, "hp_batch_exec needs the preceding hp_batch_plan of this batch");
-    BatchState &bs = it->second;
+    BatchState &bs = *bsp;
     if (!info || arena_bytes < info->arena_bytes || (info->arena_bytes > 256 && !arena))
         return fail(h, HP_ERR_WORKSPACE, "batch arena too small");
     hp::Carve c(ws);
@@ -740,8 +758,21 @@ hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
     GraphKey gk{ws, arena, grid, (int)(ps * 16 + vs), {}, {}};
     std::copy(S.total, S.total + NST, gk.total.begin());
     std::copy(S.off, S.off + NST + 1, gk.off.begin());
-    GraphEntry &ge = g_graphs[h][gk];
     stage_begin(h);
+    if (info->flags & HP_BATCH_NO_GRAPH) {
+        e = launch_half<PT, VT>(h, 1, g, n, S, grid);
+        stage_mark(h, "batch.exec");
+        if (e != hipSuccess) return hip_check(h, e, "batch exec");
+        info->tiles_exec = total;
+        info->grid_exec = grid;
+        return HP_OK;
+    }
+    GraphEntry *gep;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        gep = &g_graphs[h][gk];
+    }
+    GraphEntry &ge = *gep;
     if (!ge.ge) {
         hipStream_t cs;
         e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -774,6 +805,22 @@ hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
 }
 
 }  // namespace
+
+namespace hp {
+// Drops the per-handle batch state and graphs (called by hp_destroy).
+void batch_release_handle(hp_handle_t h) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_state.erase(h);
+    auto it = g_graphs.find(h);
+    if (it != g_graphs.end()) {
+        for (auto &kv : it->second) {
+            if (kv.second.ge) hipGraphExecDestroy(kv.second.ge);
+            if (kv.second.g) hipGraphDestroy(kv.second.g);
+        }
+        g_graphs.erase(it);
+    }
+}
+}  // namespace hp
 
 extern "C" hp_status_t hp_batch_workspace(hp_handle_t h, const hp_request_t *reqs, int n, size_t *bytes) {
     if (!h || !bytes || n < 0 || (n > 0 && !reqs)) return HP_ERR_INVALID_ARG;

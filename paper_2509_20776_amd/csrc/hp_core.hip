@@ -131,6 +131,7 @@ extern "C" hp_status_t hp_create(hp_handle_t *out, int device) {
 
 extern "C" hp_status_t hp_destroy(hp_handle_t h) {
     if (!h) return HP_ERR_INVALID_ARG;
+    hp::batch_release_handle(h);
     for (auto &e : h->ev) hipEventDestroy(e);
     if (h->host_hdr) hipHostFree(h->host_hdr);
     delete h;

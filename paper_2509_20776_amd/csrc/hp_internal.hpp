@@ -166,6 +166,8 @@ size_t idx_size(int32_t t);
 size_t val_size(int32_t t);
 hp_status_t check_csr_args(hp_handle_t h, const hp_csr_t *A, const char *name);
 
+void batch_release_handle(hp_handle_t h);   // forget batch plans and graphs of h
+
 // Stage timing (no-ops unless enabled).
 void stage_begin(hp_handle_t h);
 void stage_mark(hp_handle_t h, const char *name);   // closes the previous stage

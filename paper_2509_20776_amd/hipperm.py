@@ -53,13 +53,27 @@ class hp_plan_info_t(ctypes.Structure):
 class hp_request_t(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("status", ctypes.c_int32), ("A", hp_csr_t),
                 ("I", ctypes.c_void_p), ("J", ctypes.c_void_p), ("nI", ctypes.c_int64),
-                ("nJ", ctypes.c_int64), ("p", ctypes.c_void_p), ("q", ctypes.c_void_p), ("C", hp_csr_t)]
+                ("nJ", ctypes.c_int64), ("p", ctypes.c_void_p), ("q", ctypes.c_void_p), ("C", hp_csr_t),
+                ("B", hp_csr_t), ("op", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class hp_batch_info_t(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_size_t), ("nnz_total", ctypes.c_int64), ("failed", ctypes.c_int32),
                 ("grid_plan", ctypes.c_int32), ("tiles_plan", ctypes.c_int64), ("tiles_exec", ctypes.c_int64),
-                ("grid_exec", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("grid_exec", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class hp_server_config_t(ctypes.Structure):
+    _fields_ = [("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
+class hp_completion_t(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("C", hp_csr_t), ("t_submit_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+BATCH_NO_GRAPH = 1
 
 
 _P = ctypes.c_void_p
@@ -102,6 +116,15 @@ hp_spasgn_workspace = _sig("hp_spasgn_workspace", [_P, _CSRP, _CSRP, ctypes.POIN
 hp_spasgn_plan = _sig("hp_spasgn_plan", [_P, _CSRP, _CSRP, _P, _P, ctypes.c_int, _CSRP, _P, _SZ, _INFOP])
 hp_spasgn_exec = _sig("hp_spasgn_exec", [_P, _CSRP, _CSRP, _P, _P, ctypes.c_int, _CSRP, _P, _SZ, _INFOP,
                                          _P, _SZ])
+hp_server_create = _sig("hp_server_create", [ctypes.POINTER(_P), ctypes.c_int, _P, _SZ,
+                                             ctypes.POINTER(hp_server_config_t)])
+hp_server_submit = _sig("hp_server_submit", [_P, _REQP, ctypes.POINTER(ctypes.c_uint64)])
+hp_server_poll = _sig("hp_server_poll", [_P, ctypes.POINTER(hp_completion_t), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int)])
+hp_server_drain = _sig("hp_server_drain", [_P])
+hp_server_release = _sig("hp_server_release", [_P, ctypes.c_uint64])
+hp_server_memory = _sig("hp_server_memory", [_P, ctypes.POINTER(_SZ), ctypes.POINTER(_SZ)])
+hp_server_destroy = _sig("hp_server_destroy", [_P])
 
 @dataclass
 class CSR:
@@ -321,7 +344,7 @@ class Handle:
         return self.spasgn_exec(A, B, I, J, C, ws, info, op)
 
 
-KINDS = {"spref": 0, "permute": 1}
+KINDS = {"spref": 0, "permute": 1, "spasgn": 2}
 
 
 class Batch:
@@ -358,8 +381,11 @@ class Batch:
                                     ctypes.byref(self.info)))
         return [int(self.arr[k].status) for k in range(n)]
 
-    def exec(self):
+    def exec(self, graph: bool = True):
+        """Run the exec half: replayed from a captured hipGraph (graph=True)
+        or launched directly."""
         self.hd._stream()
+        self.info.flags = 0 if graph else BATCH_NO_GRAPH
         n = len(self.requests)
         if self.arena is None or self.arena.numel() < self.info.arena_bytes:
             self.arena = self.hd._alloc(self.info.arena_bytes)
@@ -368,31 +394,116 @@ class Batch:
 
     def results(self):
         """CSR views into the arena (None for requests that failed)."""
-        base = self.arena.data_ptr()
-        out = []
-        for k, r in enumerate(self.requests):
-            rq = self.arr[k]
-            if rq.status != 0:
-                out.append(None)
-                continue
-            C = rq.C
-            pt = torch.int64 if C.ptr_type == 1 else torch.int32
-            vt = torch.float64 if C.val_type == 1 else torch.float32
-
-            def view(ptr, count, dt):
-                es = torch.empty(0, dtype=dt).element_size()
-                if count == 0:
-                    return torch.empty(0, dtype=dt, device=self.arena.device)
-                off = ptr - base
-                return self.arena[off:off + count * es].view(dt)
-            out.append(CSR(int(C.nrows), int(C.ncols), view(C.rowptr, int(C.nrows) + 1, pt),
-                           view(C.col or base, int(C.nnz), torch.int32), view(C.val or base, int(C.nnz), vt)))
-        return out
+        return [_csr_view(self.arena, self.arr[k].C) if self.arr[k].status == 0 else None
+                for k in range(len(self.requests))]
 
     def run(self):
         self.plan()
         self.exec()
         return self.results()
+
+
+def _csr_view(buf: torch.Tensor, C: hp_csr_t) -> CSR:
+    """CSR whose arrays are views into the device buffer `buf` that holds them."""
+    base = buf.data_ptr()
+    pt = torch.int64 if C.ptr_type == 1 else torch.int32
+    vt = torch.float64 if C.val_type == 1 else torch.float32
+
+    def view(ptr, count, dt):
+        if count == 0:
+            return torch.empty(0, dtype=dt, device=buf.device)
+        es = torch.empty(0, dtype=dt).element_size()
+        off = ptr - base
+        return buf[off:off + count * es].view(dt)
+    return CSR(int(C.nrows), int(C.ncols), view(C.rowptr, int(C.nrows) + 1, pt),
+               view(C.col or base, int(C.nnz), torch.int32), view(C.val or base, int(C.nnz), vt))
+
+
+class Server:
+    """Served form (hp_server_*): submit requests as they arrive; workers run
+    them in continuous batches on their own streams inside an HBM budget of
+    `pool_bytes` (a device buffer this object allocates once).
+
+    submit(kind, A, ...) -> id; poll() -> list of completion dicts with the
+    result as CSR views into the pool (valid until release(id))."""
+
+    def __init__(self, pool_bytes: int, device: int = 0, max_inflight: int = 4, max_batch: int = 256):
+        torch.cuda.set_device(device)
+        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+        cfg = hp_server_config_t(max_inflight, max_batch)
+        h = _P()
+        code = hp_server_create(ctypes.byref(h), device, _dptr(self.pool), pool_bytes, ctypes.byref(cfg))
+        if code != 0:
+            raise HPError(code, "hp_server_create failed")
+        self.h = h
+        self._keep = {}        # id -> tensors the request points to
+        self.device = device
+
+    def submit(self, kind: str, A: CSR, I=None, J=None, p=None, q=None, B: Optional[CSR] = None,
+               op: str = "second") -> int:
+        rq = hp_request_t()
+        rq.kind = KINDS[kind]
+        rq.A = to_csr_t(A)
+        keep = [A, I, J, p, q, B]
+        if kind == "spref":
+            rq.I, rq.J = _idx(I), _idx(J)
+            rq.nI, rq.nJ = int(I.numel()), int(J.numel())
+        elif kind == "permute":
+            rq.p, rq.q = _idx(p), _idx(q)
+        else:
+            if int(I.numel()) != B.nrows or int(J.numel()) != B.ncols:
+                raise HPError(6, "B must be |I| x |J|")
+            rq.B = to_csr_t(B)
+            rq.I, rq.J = _idx(I), _idx(J)
+            rq.nI, rq.nJ = int(I.numel()), int(J.numel())
+            rq.op = OPS[op]
+        rid = ctypes.c_uint64(0)
+        code = hp_server_submit(self.h, ctypes.byref(rq), ctypes.byref(rid))
+        if code != 0:
+            raise HPError(code, "hp_server_submit rejected the request")
+        self._keep[rid.value] = keep
+        return rid.value
+
+    def poll(self, cap: int = 4096):
+        buf = (hp_completion_t * cap)()
+        n = ctypes.c_int(0)
+        code = hp_server_poll(self.h, buf, cap, ctypes.byref(n))
+        if code != 0:
+            raise HPError(code, "hp_server_poll")
+        out = []
+        for k in range(n.value):
+            c = buf[k]
+            self._keep.pop(c.id, None)
+            out.append(dict(id=c.id, status=c.status, batch_size=c.batch_size,
+                            C=_csr_view(self.pool, c.C) if c.status == 0 else None,
+                            t_submit_ns=c.t_submit_ns, t_start_ns=c.t_start_ns, t_done_ns=c.t_done_ns))
+        return out
+
+    def drain(self):
+        code = hp_server_drain(self.h)
+        if code != 0:
+            raise HPError(code, "hp_server_drain")
+
+    def release(self, rid: int):
+        code = hp_server_release(self.h, rid)
+        if code != 0:
+            raise HPError(code, f"hp_server_release({rid})")
+
+    def memory(self):
+        a, b = _SZ(0), _SZ(0)
+        hp_server_memory(self.h, ctypes.byref(a), ctypes.byref(b))
+        return a.value, b.value
+
+    def close(self):
+        if self.h:
+            hp_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _default = {}
