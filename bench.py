@@ -239,8 +239,229 @@ def copy_calibration(mib):
     del src, dst
 
 
+def _scanned(A, I):
+    rp = A.rowptr.long()
+    Il = I.long()
+    return int((rp[Il + 1] - rp[Il]).sum())
+
+
+def run_batched(hp, args):
+    """512 extraction / permutation requests (50/50) over a pool of 64 directed
+    R-MAT matrices (scale U{12..20}, edge factor U{8..32}, int32 CSR, fp32),
+    index subsets of 5-50%: one batched plan + graph-replayed exec per step,
+    against the same 512 requests as plain calls back-to-back on one stream."""
+    t = time.time()
+    pool = synth.batched_pool(count=args.batch_pool, device="cuda")
+    reqs = synth.batched_requests(pool, count=args.batch_requests, device="cuda")
+    for r in reqs:
+        r["A"] = pool[r["mat"]]
+    _sync()
+    log(f"[bench] batched: {len(pool)} matrices ({sum(A.nnz for A in pool)} nnz), {len(reqs)} requests, "
+        f"generated in {time.time()-t:.1f}s")
+    h = hp.handle(0)
+    b = hp.Batch(h, reqs)
+    st = b.plan()
+    assert all(x == 0 for x in st), st
+    b.exec()
+    _sync()
+    nbytes, scanned = 0, 0
+    for k, r in enumerate(reqs):
+        A = r["A"]
+        if r["kind"] == "spref":
+            S = _scanned(A, r["I"])
+            scanned += S
+            nbytes += spref_bytes(A, r["I"].numel(), r["J"].numel(), S, int(b.arr[k].C.nnz))["total"]
+        else:
+            scanned += A.nnz
+            nbytes += permute_bytes(A)["total"]
+
+    def step_batched():
+        b.plan()
+        b.exec()
+
+    def step_plain():
+        for r in reqs:
+            if r["kind"] == "spref":
+                hp.spref(r["A"], r["I"], r["J"])
+            else:
+                hp.permute(r["A"], r["p"], r["q"])
+
+    steps = max(2, args.steps // 5)
+    sec_b = _timed(step_batched, steps, 1)
+    sec_p = _timed(step_plain, steps, 1)
+    return dict(value=scanned / sec_b, unit="nnz/s", ms_per_step=sec_b * 1e3,
+                plain_ms_per_step=sec_p * 1e3, speedup_vs_plain=sec_p / sec_b,
+                algorithmic_GBps=nbytes / sec_b / 1e9, plain_algorithmic_GBps=nbytes / sec_p / 1e9,
+                grid_plan=int(b.info.grid_plan), grid_exec=int(b.info.grid_exec),
+                tiles_plan=int(b.info.tiles_plan), tiles_exec=int(b.info.tiles_exec),
+                config={"workload": "batched", "desc": "%d spref/permute requests (50/50) on a pool of %d R-MAT "
+                        "(scale U{12..20}, ef U{8..32}), int32 CSR, fp32, subsets 5-50%%; value = scanned nnz/s "
+                        "of one batched plan+exec (exec replayed from a hipGraph)" % (len(reqs), len(pool)),
+                        "requests": len(reqs), "pool": len(pool), "scanned_nnz": scanned})
+
+
+def _served_pool(args):
+    """Resident pool: R-MAT (ef 16, symmetrised) and Erdos-Renyi (degree 16)
+    matrices alternating, scale U{lo..hi}, int32 / int64 rowptr alternating,
+    fp32 values."""
+    key = synth.stream_key(0, "served-pool")
+    n = args.served_pool
+    sc = synth.randint_below(synth.stream_key(key, "scale"), n, args.served_scale_hi - 15) + 16
+    pool = []
+    for t in range(n):
+        ptr = torch.int32 if t % 4 < 2 else torch.int64
+        s = int(sc[t])
+        if t % 2 == 0:
+            A = synth.rmat(s, 16, 0, f"served-rmat-{t}", symmetric=True, ptr_dtype=ptr, device="cuda")
+        else:
+            A = synth.erdos_renyi(1 << s, 1 << s, 16.0, 0, f"served-er-{t}", ptr_dtype=ptr,
+                                  val_dtype=torch.float32, device="cuda")
+        pool.append(A)
+    return pool
+
+
+def _served_variants(pool, per=4):
+    """Per matrix: `per` extraction index pairs (5-50%, 1% repeats), `per`
+    permutation pairs, `per` assignment blocks (I, J 1-10%, nnz(B) ~ 1% of
+    nnz(A), ops cycling select-second / plus / replace)."""
+    out = []
+    for m, A in enumerate(pool):
+        key = synth.stream_key(0, "served-var", m)
+        fr = synth.values(synth.stream_key(key, "fr"), 4 * per, torch.float64)
+        v = {"spref": [], "permute": [], "spasgn": []}
+        for k in range(per):
+            f1 = 0.05 + 0.45 * float(fr[4 * k]); f2 = 0.05 + 0.45 * float(fr[4 * k + 1])
+            I = synth.subset(synth.stream_key(key, "I", k), A.nrows, max(1, int(f1 * A.nrows)), repeat_frac=0.01,
+                             device="cuda")
+            J = synth.subset(synth.stream_key(key, "J", k), A.ncols, max(1, int(f2 * A.ncols)), repeat_frac=0.01,
+                             device="cuda")
+            v["spref"].append(dict(kind="spref", A=A, I=I, J=J))
+            v["permute"].append(dict(kind="permute", A=A, p=synth.randperm(synth.stream_key(key, "p", k), A.nrows,
+                                                                             "cuda"),
+                                     q=synth.randperm(synth.stream_key(key, "q", k), A.ncols, "cuda")))
+            g1 = 0.01 + 0.09 * float(fr[4 * k + 2]); g2 = 0.01 + 0.09 * float(fr[4 * k + 3])
+            nI, nJ = max(1, int(g1 * A.nrows)), max(1, int(g2 * A.ncols))
+            aI = synth.subset(synth.stream_key(key, "aI", k), A.nrows, nI, device="cuda")
+            aJ = synth.subset(synth.stream_key(key, "aJ", k), A.ncols, nJ, device="cuda")
+            B = synth.bernoulli_block(nI, nJ, min(1.0, 0.01 * A.nnz / (nI * nJ)), 0, f"served-B-{m}-{k}",
+                                      ptr_dtype=A.rowptr.dtype, val_dtype=torch.float32, device="cuda")
+            v["spasgn"].append(dict(kind="spasgn", A=A, I=aI, J=aJ, B=B, op=["second", "plus", "replace"][k % 3]))
+        out.append(v)
+    return out
+
+
+def _pctl(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def run_served(hp, args):
+    """Poisson arrivals (2,000 req/s by default), mix 60/20/20 spref / spasgn /
+    permute over a resident pool; latency = completion - arrival.  The same
+    trace is replayed through the plain per-call path (one stream, FIFO)."""
+    import numpy as np
+    t = time.time()
+    pool = _served_pool(args)
+    var = _served_variants(pool)
+    _sync()
+    log(f"[bench] served: pool of {len(pool)} ({sum(A.nnz for A in pool)} nnz), generated in {time.time()-t:.1f}s")
+    arr = synth.poisson_arrivals(args.served_rate, args.served_seconds, 0, "served-arrivals").numpy()
+    key = synth.stream_key(0, "served-trace")
+    n = len(arr)
+    u = synth.values(synth.stream_key(key, "kind"), n, torch.float64).numpy()
+    mi = synth.randint_below(synth.stream_key(key, "mat"), n, len(pool)).numpy()
+    vi = synth.randint_below(synth.stream_key(key, "var"), n, 4).numpy()
+    trace = []
+    for k in range(n):
+        kind = "spref" if u[k] <= 0.6 else ("spasgn" if u[k] <= 0.8 else "permute")
+        trace.append(var[int(mi[k])][kind][int(vi[k])])
+
+    def submit(srv, r):
+        if r["kind"] == "spref":
+            return srv.submit("spref", r["A"], I=r["I"], J=r["J"])
+        if r["kind"] == "permute":
+            return srv.submit("permute", r["A"], p=r["p"], q=r["q"])
+        return srv.submit("spasgn", r["A"], I=r["I"], J=r["J"], B=r["B"], op=r["op"])
+
+    def out_nnz(C):
+        return int(C.col.numel())
+
+    # warm the kernels and the tuner once per kind and type
+    srv = hp.Server(args.served_budget_gb << 30, max_inflight=args.served_streams, max_batch=args.served_max_batch)
+    for v in var[:4]:
+        for kind in ("spref", "spasgn", "permute"):
+            submit(srv, v[kind][0])
+    srv.drain()
+    for c in srv.poll():
+        if c["status"] == 0:
+            srv.release(c["id"])
+    # served run
+    lat, nnz_done, status_bad, bsz = [], 0, 0, []
+    t0 = time.perf_counter()
+    ns0 = time.monotonic_ns()
+    pend = {}
+
+    def collect():
+        nonlocal nnz_done, status_bad
+        for c in srv.poll():
+            k = pend.pop(c["id"])
+            if c["status"] != 0:
+                status_bad += 1
+            else:
+                nnz_done += out_nnz(c["C"])
+                srv.release(c["id"])
+            lat.append((c["t_done_ns"] - (ns0 + int(arr[k] * 1e9))) / 1e6)
+            bsz.append(c["batch_size"])
+
+    for k in range(n):
+        dt = arr[k] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        pend[submit(srv, trace[k])] = k
+        if k % 64 == 0:
+            collect()
+    srv.drain()
+    collect()
+    wall = time.perf_counter() - t0
+    in_use, peak = srv.memory()
+    srv.close()
+    # the same trace through plain calls, FIFO on one stream
+    lat_p, nnz_p = [], 0
+    t0 = time.perf_counter()
+    for k in range(n if args.served_plain else 0):
+        dt = arr[k] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        r = trace[k]
+        if r["kind"] == "spref":
+            C = hp.spref(r["A"], r["I"], r["J"])
+        elif r["kind"] == "permute":
+            C = hp.permute(r["A"], r["p"], r["q"])
+        else:
+            C = hp.spasgn(r["A"], r["B"], r["I"], r["J"], r["op"])
+        _sync()
+        nnz_p += out_nnz(C)
+        lat_p.append((time.perf_counter() - t0 - arr[k]) * 1e3)
+        if time.perf_counter() - t0 > args.served_seconds * 10 + 10:
+            log(f"[bench] plain replay stopped after {k+1} of {n} requests (time cap)")
+            break
+    wall_p = max(time.perf_counter() - t0, 1e-9)
+    return dict(value=len(lat) / wall, unit="req/s", ms_per_step=wall * 1e3 / max(1, len(lat)),
+                p50_ms=_pctl(lat, 50), p99_ms=_pctl(lat, 99), out_nnz_per_s=nnz_done / wall,
+                failed=status_bad, mean_batch=float(np.mean(bsz)) if bsz else 0.0,
+                pool_peak_bytes=int(peak),
+                plain={"req_per_s": len(lat_p) / wall_p, "p50_ms": _pctl(lat_p, 50), "p99_ms": _pctl(lat_p, 99),
+                       "out_nnz_per_s": nnz_p / wall_p, "completed": len(lat_p)},
+                config={"workload": "served", "desc": "Poisson %g req/s for %g s, 60/20/20 spref/spasgn/permute "
+                        "on %d resident matrices (R-MAT ef16 sym / ER deg 16, scale U{16..%d}, int32/int64 "
+                        "rowptr, fp32), %d streams, batches of at most %d, pool budget %d GB"
+                        % (args.served_rate, args.served_seconds, len(pool), args.served_scale_hi,
+                           args.served_streams, args.served_max_batch, args.served_budget_gb),
+                        "requests": n})
+
+
 WORKLOADS = {"rmat-extract": run_rmat_extract, "grid-permute": run_grid_permute,
-             "grid-assign": run_grid_assign}
+             "grid-assign": run_grid_assign, "batched": run_batched, "served": run_served}
 
 
 def main():
@@ -254,6 +475,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-extras", dest="extras", action="store_false")
+    ap.add_argument("--batch-pool", type=int, default=64)
+    ap.add_argument("--batch-requests", type=int, default=512)
+    ap.add_argument("--served-pool", type=int, default=32)
+    ap.add_argument("--served-scale-hi", type=int, default=20)
+    ap.add_argument("--served-rate", type=float, default=2000.0)
+    ap.add_argument("--served-seconds", type=float, default=2.0)
+    ap.add_argument("--served-streams", type=int, default=4)
+    ap.add_argument("--served-budget-gb", type=int, default=64)
+    ap.add_argument("--served-max-batch", type=int, default=16)
+    ap.add_argument("--no-served-plain", dest="served_plain", action="store_false")
     ap.add_argument("--copy-cal-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -276,17 +507,16 @@ def main():
             a2 = argparse.Namespace(**vars(args))
             a2.cpu_baseline = False
             r = fn(hp, a2)
-            also[name] = {k: r[k] for k in ("value", "unit", "ms_per_step", "algorithmic_GBps",
-                                            "hbm_frac_step", "roofline", "stages_us", "config") if k in r}
+            also[name] = {k: v for k, v in r.items() if k != "cpu_baseline"}
             log(f"[bench] {name}: {r['value']:.3e} {r['unit']}, {r['ms_per_step']:.3f} ms/step")
     out = {"metric": METRIC, "value": head["value"], "unit": head["unit"], "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
            "data": "synthetic", "config": head["config"], "roofline": head.get("roofline"),
            "cpu_baseline": head.get("cpu_baseline")}
-    for k in ("out_nnz_per_s", "algorithmic_GBps", "hbm_frac_step", "stages_us"):
-        if k in head:
-            out[k] = head[k]
+    for k, v in head.items():
+        if k not in out and k not in ("cpu_baseline",):
+            out[k] = v
     if also:
         out["also"] = also
     print(json.dumps(out), flush=True)

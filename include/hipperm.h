@@ -210,10 +210,11 @@ typedef struct {
     int64_t tiles_plan;    /* tiles over all plan stages                            */
     int64_t tiles_exec;    /* tiles over all exec stages (set by exec)              */
     int32_t grid_exec;     /* persistent workgroups per exec stage (set by exec)    */
-    int32_t flags;         /* in: HP_BATCH_NO_GRAPH launches exec directly          */
+    int32_t flags;         /* in: HP_BATCH_NO_GRAPH, HP_BATCH_NO_TUNE               */
 } hp_batch_info_t;
 
-#define HP_BATCH_NO_GRAPH 1
+#define HP_BATCH_NO_GRAPH 1   /* launch exec directly instead of a captured graph   */
+#define HP_BATCH_NO_TUNE 2    /* fixed grid (2 workgroups per CU), no timing runs    */
 
 /* Workspace for a batch (tables, counters and rowptrs of every request). */
 hp_status_t hp_batch_workspace(hp_handle_t h, const hp_request_t *reqs, int n, size_t *bytes);

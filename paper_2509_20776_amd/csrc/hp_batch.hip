@@ -553,7 +553,9 @@ hipError_t launch_half(hp_handle_t h, int half, const Global &g, int n, const St
 // class (both halves are idempotent: every run starts from cleared state and
 // rewrites the same outputs).
 template <typename PT, typename VT>
-int tune_grid(hp_handle_t h, int half, const Global &g, int n, const Stages &S, const std::string &key) {
+int tune_grid(hp_handle_t h, int half, const Global &g, int n, const Stages &S, const std::string &key,
+              bool tune) {
+    if (!tune) return 2 * num_cus(h);
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_tuned.find(key);
@@ -643,7 +645,7 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
         e = hipMemcpyAsync(g.queue, S.q.data(), sizeof(QEntry) * S.q.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_check(h, e, "batch plan upload");
     const std::string key = size_class("plan", reqs[0].A.ptr_type, reqs[0].A.val_type, total);
-    const int grid = tune_grid<PT, VT>(h, 0, g, n, S, key);
+    const int grid = tune_grid<PT, VT>(h, 0, g, n, S, key, !(info && (info->flags & HP_BATCH_NO_TUNE)));
     stage_begin(h);
     e = launch_half<PT, VT>(h, 0, g, n, S, grid);
     stage_mark(h, "batch.plan");
@@ -698,7 +700,9 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
     bs.n = n;
     bs.devs = devs;
     if (info) {
+        const int32_t flags = info->flags;   // caller's option bits survive the plan
         *info = hp_batch_info_t{};
+        info->flags = flags;
         info->arena_bytes = arena + 256;
         info->nnz_total = nnz_total;
         info->failed = failed;
@@ -751,7 +755,7 @@ hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
         e = hipMemcpyAsync(g.queue, S.q.data(), sizeof(QEntry) * S.q.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_check(h, e, "batch exec upload");
     const std::string key = size_class("exec", reqs[0].A.ptr_type, reqs[0].A.val_type, total);
-    const int grid = tune_grid<PT, VT>(h, 1, g, n, S, key);
+    const int grid = tune_grid<PT, VT>(h, 1, g, n, S, key, !(info->flags & HP_BATCH_NO_TUNE));
     // exec runs from a captured graph, replayed for any batch with the same
     // workspace, arena, grid and stage shapes (queue and request records are
     // uploaded before every launch)
@@ -770,7 +774,18 @@ hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
     GraphEntry *gep;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        gep = &g_graphs[h][gk];
+        auto &graphs = g_graphs[h];
+        if (graphs.size() >= 64 && !graphs.count(gk)) {
+            // bound the cache: drop every graph of this handle (its stream is idle
+            // only after the last launch, so synchronise before destroying)
+            hipStreamSynchronize(s);
+            for (auto &kv : graphs) {
+                if (kv.second.ge) hipGraphExecDestroy(kv.second.ge);
+                if (kv.second.g) hipGraphDestroy(kv.second.g);
+            }
+            graphs.clear();
+        }
+        gep = &graphs[gk];
     }
     GraphEntry &ge = *gep;
     if (!ge.ge) {

@@ -191,7 +191,9 @@ std::vector<Pending> run_batch(hp_server_s *S, hp_handle_t h, hipStream_t st, st
     std::vector<hp_request_t> reqs(n);
     for (int k = 0; k < n; k++) reqs[k] = B[k].r;
     hp_batch_info_t info{};
-    info.flags = HP_BATCH_NO_GRAPH;   // every batch has its own shape: launch directly
+    // every batch has its own shape: launch directly, with the fixed grid
+    // (timing runs would add to the latency of the first batch of a class)
+    info.flags = HP_BATCH_NO_GRAPH | HP_BATCH_NO_TUNE;
     hp_status_t s = hp_batch_plan(h, reqs.data(), n, S->pool + ws_off, wsb, &info);
     size_t a_off = RangeAlloc::NONE;
     std::vector<Pending> back;

@@ -74,6 +74,7 @@ class hp_completion_t(ctypes.Structure):
 
 
 BATCH_NO_GRAPH = 1
+BATCH_NO_TUNE = 2
 
 
 _P = ctypes.c_void_p
