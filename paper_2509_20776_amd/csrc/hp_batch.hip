@@ -70,7 +70,7 @@ struct ReqDev {
     int64_t nfill;
     uint64_t *tiles0, *tiles1;
     uint8_t *mark;
-    uint32_t *dm, *nm, *bm;
+    uint32_t *dm, *nm, *bm, *b2;
     int64_t nw;
     int32_t *cnt, *jpos, *Dn;
     int64_t *rs;
@@ -135,14 +135,14 @@ __device__ void run_tile(int half, int phase, int64_t tile, const ReqDev &r, Bat
                                                r.hdr);
                     break;
                 case 3: spref::spref_jpack_tile(tile, r.J, r.nJ, r.n, r.mark, r.bm, r.nw, r.jpos, r.Dn, r.dm); break;
-                case 4: spref::spref_jlink_tile(tile, r.J, r.nJ, r.jpos, r.Dn); break;
+                case 4: spref::spref_jlink_tile(tile, r.J, r.nJ, r.jpos, r.Dn, r.bm, r.dm, r.b2, r.nw); break;
                 case 5:
                     scan_counts_tile<int64_t>(tile, sm.scan, r.ch, r.cp, r.nI, r.hdr, 0, r.tiles0, 0, nullptr, 0,
                                               nullptr, nullptr, nullptr);
                     break;
                 case 6:
-                    spref::spref_count_tile(tile, r.nbw, sm.gs, r.acol, r.n, r.rs, r.rl, r.cp, r.nI, r.bm, r.dm,
-                                            r.jpos, r.Dn, r.cnt, r.hdr);
+                    spref::spref_count_tile(tile, r.nbw, sm.gs, r.acol, r.n, r.rs, r.rl, r.cp, r.nI, r.b2, r.jpos,
+                                            r.Dn, r.cnt, r.hdr);
                     break;
                 case 7:
                     scan_counts_tile<PT>(tile, sm.scan, r.cnt, (PT *)r.crow_tmp, r.nI, r.hdr, 1, r.tiles1, 3,
@@ -191,7 +191,7 @@ __device__ void run_tile(int half, int phase, int64_t tile, const ReqDev &r, Bat
             }
             case 1:
                 spref::spref_gather_tile<PT, VT>(tile, r.nbw, sm.gs, r.acol, (const VT *)r.aval, r.n, r.rs, r.rl, r.cp,
-                                                 r.nI, r.bm, r.dm, r.jpos, r.Dn, crow, r.ccol, (VT *)r.cval, r.cursor,
+                                                 r.nI, r.b2, r.jpos, r.Dn, crow, r.ccol, (VT *)r.cval, r.cursor,
                                                  r.hdr);
                 break;
             case 2: sort_small_tile<PT, VT>(tile, sm.wave, crow, r.ccol, (VT *)r.cval, r.nI, ld, r.hdr); break;
@@ -364,6 +364,7 @@ size_t req_scratch(hp::Carve &c, const hp_request_t &rq, ReqDev &d) {
             d.nm = z + markw + d.nw + nI + 8;
         }
         d.bm = c.take<uint32_t>((size_t)d.nw);
+        d.b2 = c.take<uint32_t>(2 * (size_t)d.nw);
         d.jpos = c.take<int32_t>(n + 1);
         d.Dn = c.take<int32_t>(nJ + 1);
         d.rs = c.take<int64_t>(nI + 1);
@@ -459,7 +460,7 @@ void plan_tiles(const hp_request_t &rq, const ReqDev &d, int64_t *nt) {
         nt[1] = cdiv(rq.nJ, 256);
         nt[2] = cdiv(rq.nI, 256);
         nt[3] = cdiv(std::max<int64_t>(rq.nJ, d.nw), 256);
-        nt[4] = cdiv(rq.nJ, 256);
+        nt[4] = cdiv(std::max<int64_t>(rq.nJ, 2 * d.nw), 256);
         nt[5] = cdiv(rq.nI, SCAN_TILE);
         nt[6] = d.nbw + ngb;
         nt[7] = cdiv(rq.nI, SCAN_TILE);

@@ -10,7 +10,9 @@
 //         plain store wins), or, for a column selected several times, the
 //         head ~t of a chain through Dn that visits every other position
 //         and ends in the winner,
-//   dm    bitmap of columns selected more than once.
+//   dm    bitmap of columns selected more than once,
+//   b2    bm and dm interleaved (2 bits per column), the one table the
+//         count and gather passes read per scanned entry.
 // Every selected row I[i] is then streamed twice: once to count its hits
 // (with multiplicity: a column selected k times yields k entries), once in
 // exec to write them.  Work is split per wavefront:
@@ -38,7 +40,7 @@ struct SprefLayout {
     uint8_t *mark;
     uint32_t *dm, *nm;
     int32_t *cnt;
-    uint32_t *bm;
+    uint32_t *bm, *b2;     // column bitmap; 2-bit map (selected, repeated)
     int32_t *jpos, *Dn;
     int64_t *rs;           // start of row I[i] in A
     int32_t *rl, *ch;
@@ -63,6 +65,7 @@ SprefLayout spref_layout(Carve &c, int64_t n, int64_t nI, int64_t nJ) {
     L.cnt = L.zero ? (int32_t *)(L.zero + markw + L.nw) : nullptr;
     L.nm = L.zero ? L.zero + markw + L.nw + nI + 8 : nullptr;
     L.bm = c.take<uint32_t>(L.nw);
+    L.b2 = c.take<uint32_t>(2 * L.nw);
     L.jpos = c.take<int32_t>(n + 1);
     L.Dn = c.take<int32_t>(nJ + 1);
     L.rs = c.take<int64_t>(nI + 1);
@@ -86,8 +89,9 @@ __global__ __launch_bounds__(256) void k_spref_jpack(const int32_t *__restrict__
     spref_jpack_tile(blockIdx.x, J, nJ, n, mark, bm, nw, jpos, Dn, dm);
 }
 __global__ __launch_bounds__(256) void k_spref_jlink(const int32_t *__restrict__ J, int64_t nJ, int32_t *jpos,
-                                                    int32_t *Dn) {
-    spref_jlink_tile(blockIdx.x, J, nJ, jpos, Dn);
+                                                    int32_t *Dn, const uint32_t *__restrict__ bm,
+                                                    const uint32_t *__restrict__ dm, uint32_t *b2, int64_t nw) {
+    spref_jlink_tile(blockIdx.x, J, nJ, jpos, Dn, bm, dm, b2, nw);
 }
 template <typename PT>
 __global__ __launch_bounds__(256) void k_spref_rows(const PT *__restrict__ arow, const int32_t *__restrict__ I,
@@ -98,23 +102,22 @@ __global__ __launch_bounds__(256) void k_spref_rows(const PT *__restrict__ arow,
 __global__ __launch_bounds__(SR_BLOCK) void k_spref_count(
     const int32_t *__restrict__ acol, int64_t n, const int64_t *__restrict__ rs,
     const int32_t *__restrict__ rl, const int64_t *__restrict__ cp, int64_t nI, int64_t ngb,
-    const uint32_t *__restrict__ bm, const uint32_t *__restrict__ dm,
-    const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn, int32_t *cnt,
-    const DevHdr *hdr) {
+    const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn,
+    int32_t *cnt, const DevHdr *hdr) {
     __shared__ GroupSmem gs[SR_BLOCK / WAVE];
     (void)ngb;
-    spref_count_tile(blockIdx.x, SR_BIGBLOCKS, gs, acol, n, rs, rl, cp, nI, bm, dm, jpos, Dn, cnt, hdr);
+    spref_count_tile(blockIdx.x, SR_BIGBLOCKS, gs, acol, n, rs, rl, cp, nI, b2, jpos, Dn, cnt, hdr);
 }
 template <typename PT, typename VT>
 __global__ __launch_bounds__(SR_BLOCK) void k_spref_gather(
     const int32_t *__restrict__ acol, const VT *__restrict__ aval, int64_t n,
     const int64_t *__restrict__ rs, const int32_t *__restrict__ rl, const int64_t *__restrict__ cp,
-    int64_t nI, int64_t ngb, const uint32_t *__restrict__ bm, const uint32_t *__restrict__ dm,
-    const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn, const PT *__restrict__ crow,
-    int32_t *ccol, VT *cval, int32_t *cursor, const DevHdr *hdr) {
+    int64_t nI, int64_t ngb, const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos,
+    const int32_t *__restrict__ Dn, const PT *__restrict__ crow, int32_t *ccol, VT *cval, int32_t *cursor,
+    const DevHdr *hdr) {
     __shared__ GroupSmem gs[SR_BLOCK / WAVE];
     (void)ngb;
-    spref_gather_tile<PT, VT>(blockIdx.x, SR_BIGBLOCKS, gs, acol, aval, n, rs, rl, cp, nI, bm, dm, jpos, Dn, crow,
+    spref_gather_tile<PT, VT>(blockIdx.x, SR_BIGBLOCKS, gs, acol, aval, n, rs, rl, cp, nI, b2, jpos, Dn, crow,
                               ccol, cval, cursor, hdr);
 }
 
@@ -165,7 +168,8 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
                            L.nm, L.hdr);
         hipLaunchKernelGGL(k_spref_jpack, dim3(grid1(std::max<int64_t>(nJ, (int64_t)L.nw))), dim3(256), 0,
                            s, J, nJ, n, L.mark, L.bm, (int64_t)L.nw, L.jpos, L.Dn, L.dm);
-        hipLaunchKernelGGL(k_spref_jlink, dim3(grid1(nJ)), dim3(256), 0, s, J, nJ, L.jpos, L.Dn);
+        hipLaunchKernelGGL(k_spref_jlink, dim3(grid1(std::max<int64_t>(nJ, 2 * (int64_t)L.nw))), dim3(256), 0, s, J,
+                           nJ, L.jpos, L.Dn, L.bm, L.dm, L.b2, (int64_t)L.nw);
         stage_mark(h, "spref.jtables");
         hipLaunchKernelGGL(k_spref_rows<PT>, dim3(grid1(nI)), dim3(256), 0, s, (const PT *)A->rowptr, I,
                            nI, m, L.rs, L.rl, L.ch, L.big, L.hdr);
@@ -176,7 +180,7 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     const int64_t ngb = (nI + 4 * WAVE - 1) / (4 * WAVE);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_spref_count, dim3((unsigned)(ngb + SR_BIGBLOCKS)), dim3(SR_BLOCK), 0, s, A->col,
-                           n, L.rs, L.rl, L.cp, nI, ngb, L.bm, L.dm, L.jpos, L.Dn, L.cnt, L.hdr);
+                           n, L.rs, L.rl, L.cp, nI, ngb, L.b2, L.jpos, L.Dn, L.cnt, L.hdr);
         stage_mark(h, "spref.count");
         e = hipGetLastError();
     }
@@ -238,7 +242,7 @@ hp_status_t spref_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     if (info->aux[1] > 0) e = launch_clear_words(s, L.cursor, (size_t)nI);
     if (e == hipSuccess && info->nnz_out > 0) {
         hipLaunchKernelGGL((k_spref_gather<PT, VT>), dim3((unsigned)(ngb + SR_BIGBLOCKS)), dim3(SR_BLOCK), 0,
-                           s, A->col, (const VT *)A->val, n, L.rs, L.rl, L.cp, nI, ngb, L.bm, L.dm, L.jpos,
+                           s, A->col, (const VT *)A->val, n, L.rs, L.rl, L.cp, nI, ngb, L.b2, L.jpos,
                            L.Dn, (const PT *)C->rowptr, C->col, (VT *)C->val, L.cursor, L.hdr);
         stage_mark(h, "spref.gather");
         e = hipGetLastError();

@@ -60,13 +60,34 @@ __device__ inline void spref_jpack_tile(int64_t bid, const int32_t *__restrict__
     }
 }
 
-// Link every non-winning position of a repeated column into the chain
-// headed by jpos[c]: jpos[c] = ~t_last, Dn[t] = previous head, ..., ending
-// in the winner (>= 0).  Chain order is arbitrary; rows are sorted later.
+// Spread the 16 low bits of x to the even bit positions.
+__device__ __forceinline__ uint32_t spread16(uint32_t x) {
+    x &= 0xffffu;
+    x = (x | (x << 8)) & 0x00ff00ffu;
+    x = (x | (x << 4)) & 0x0f0f0f0fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
+// Two independent pieces in one tile range:
+//  * link every non-winning position of a repeated column into the chain
+//    headed by jpos[c]: jpos[c] = ~t_last, Dn[t] = previous head, ...,
+//    ending in the winner (>= 0); chain order is arbitrary (rows are sorted
+//    later);
+//  * interleave the column bitmap and the repeated-column bitmap into the
+//    2-bit map b2 (bit 2k: column selected, bit 2k+1: selected more than
+//    once, for column 16 w + k of word w), so a lookup is one load.
 __device__ inline void spref_jlink_tile(int64_t bid, const int32_t *__restrict__ J, int64_t nJ, int32_t *jpos,
-                                        int32_t *Dn) {
+                                        int32_t *Dn, const uint32_t *__restrict__ bm,
+                                        const uint32_t *__restrict__ dm, uint32_t *b2, int64_t nw) {
     const int64_t t = bid * 256 + threadIdx.x;
     if (t < nJ && Dn[t] == 1) Dn[t] = atomicExch(&jpos[J[t]], ~(int32_t)t);
+    if (t < 2 * nw) {
+        const int sh = (int)(t & 1) * 16;
+        const uint32_t m16 = bm[t >> 1] >> sh, d16 = dm[t >> 1] >> sh;
+        b2[t] = spread16(m16) | (spread16(d16) << 1);
+    }
 }
 
 // ---- selected rows ----------------------------------------------------------
@@ -90,16 +111,10 @@ __device__ inline void spref_rows_tile(int64_t bid, const PT *__restrict__ arow,
 }
 
 // ---- shared pieces of count and gather -------------------------------------
-__device__ __forceinline__ bool test_bit(const uint32_t *b, int64_t c) {
-    return (b[c >> 5] >> (c & 31)) & 1u;
-}
-
-// Output entries produced by a hit on column c (its multiplicity in J).
-__device__ __forceinline__ int mult_of(int64_t c, const uint32_t *dm, const int32_t *jpos,
-                                       const int32_t *Dn) {
-    if (!test_bit(dm, c)) return 1;
+// Length of the chain of J positions of a repeated column: jpos[c] = ~t
+// links to Dn[t], ..., ending in the winning position (>= 0).
+__device__ __forceinline__ int chain_len(int32_t v, const int32_t *Dn) {
     int k = 1;
-    int32_t v = jpos[c];
     while (v < 0) {
         k++;
         v = Dn[~v];
@@ -107,18 +122,42 @@ __device__ __forceinline__ int mult_of(int64_t c, const uint32_t *dm, const int3
     return k;
 }
 
+// Hit multiplicities of one step of SR_U slots (columns c, valid flags ok).
+// Every slot's word of the 2-bit map is loaded (one divergent access per
+// slot, all issued before any is used, so the loads of a step overlap); the
+// chain walk only runs for repeated columns.
+__device__ __forceinline__ void step_mult(const int64_t (&c)[SR_U], const bool (&ok)[SR_U],
+                                          const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos,
+                                          const int32_t *__restrict__ Dn, int (&mm)[SR_U]) {
+    uint32_t bw[SR_U];
+#pragma unroll
+    for (int u = 0; u < SR_U; u++) bw[u] = b2[c[u] >> 4];
+    bool dup[SR_U], any = false;
+#pragma unroll
+    for (int u = 0; u < SR_U; u++) {
+        const uint32_t f = bw[u] >> ((c[u] & 15) << 1);
+        const bool hit = ok[u] && (f & 1u);
+        mm[u] = hit ? 1 : 0;
+        dup[u] = hit && (f & 2u);
+        any |= dup[u];
+    }
+    if (ballot(any)) {
+#pragma unroll
+        for (int u = 0; u < SR_U; u++)
+            if (dup[u]) mm[u] = chain_len(jpos[c[u]], Dn);
+    }
+}
+
+// Write the output entries of one hit whose jpos entry is x: one entry for a
+// column that occurs once in J (x >= 0), the whole chain otherwise.
 template <typename VT>
-__device__ __forceinline__ void emit_hits(int64_t c, VT v, int64_t pos, const uint32_t *dm,
-                                          const int32_t *jpos, const int32_t *Dn, int32_t *ccol,
-                                          VT *cval) {
-    int32_t x = jpos[c];
-    if (test_bit(dm, c)) {
-        while (x < 0) {
-            ccol[pos] = ~x;
-            cval[pos] = v;
-            pos++;
-            x = Dn[~x];
-        }
+__device__ __forceinline__ void emit_chain(int32_t x, VT v, int64_t pos, const int32_t *__restrict__ Dn,
+                                           int32_t *ccol, VT *cval) {
+    while (x < 0) {
+        ccol[pos] = ~x;
+        cval[pos] = v;
+        pos++;
+        x = Dn[~x];
     }
     ccol[pos] = x;
     cval[pos] = v;
@@ -141,6 +180,26 @@ __device__ __forceinline__ int64_t wave_search_le(const int64_t *a, int64_t n, i
     return lo;
 }
 
+// Row of chunk q (largest r with cp[r] <= q), given the row of an earlier
+// chunk: the next rows are probed 64 at a time (big rows are a few percent
+// of the rows, so the answer is nearly always in the first probe), with a
+// full search as the fallback.
+__device__ __forceinline__ int64_t next_chunk_row(const int64_t *cp, int64_t nI, int64_t row, int64_t q) {
+    const int l = lane_id();
+    const int64_t idx = row + 1 + l;
+    const bool le = idx <= nI && cp[idx] <= q;
+    const uint64_t msk = ballot(le);
+    if (!(msk >> 63)) return row + 1 + (63 - __clzll((long long)msk));   // lane 0 is always set
+    const int64_t lo = row + 64;
+    return lo + wave_search_le(cp + lo, nI + 1 - lo, q);
+}
+
+// Contiguous chunk range of big-row wavefront gw of nwaves.
+__device__ __forceinline__ void chunk_range(int64_t nbig, int64_t gw, int64_t nwaves, int64_t &q0, int64_t &q1) {
+    q0 = nbig * gw / nwaves;
+    q1 = nbig * (gw + 1) / nwaves;
+}
+
 // Row (0..63) of the wave-local concatenation holding entry e.
 __device__ __forceinline__ int row_of(const int32_t *start, int32_t e) {
     int lo = 0, hi = WAVE;
@@ -160,13 +219,15 @@ struct GroupSmem {
 };
 
 // ---- count (plan) -------------------------------------------------------------
-// Tile bid of the count pass: bid < nbw are the long-row workers (persistent
-// over the chunks), then one tile per 256 selected rows.
+// Tile bid of the count pass: bid < nbw are the long-row workers (a
+// contiguous range of chunks per wavefront), then one tile per 256 selected
+// rows (64 rows per wavefront, walked as one concatenation).  Every step
+// issues its column loads together, then its bitmap loads together.
 __device__ inline void spref_count_tile(
     int64_t bid, int64_t nbw, GroupSmem *gs, const int32_t *__restrict__ acol, int64_t n,
     const int64_t *__restrict__ rs, const int32_t *__restrict__ rl, const int64_t *__restrict__ cp, int64_t nI,
-    const uint32_t *__restrict__ bm, const uint32_t *__restrict__ dm, const int32_t *__restrict__ jpos,
-    const int32_t *__restrict__ Dn, int32_t *cnt, const DevHdr *hdr) {
+    const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn,
+    int32_t *cnt, const DevHdr *hdr) {
     if (hdr->err) return;
     const int w = threadIdx.x / WAVE, l = lane_id();
     if (bid >= nbw) {
@@ -188,44 +249,67 @@ __device__ inline void spref_count_tile(
         g.cnt[l] = 0;
         __builtin_amdgcn_wave_barrier();
         for (int e0 = 0; e0 < E; e0 += SR_BW) {
-            int64_t c[SR_U];
-            int rr[SR_U];
+            int64_t k[SR_U], c[SR_U];
+            int rr[SR_U], mm[SR_U];
+            bool ok[SR_U];
 #pragma unroll
             for (int u = 0; u < SR_U; u++) {
                 const int e = e0 + u * WAVE + l;
-                c[u] = -1;
-                rr[u] = 0;
-                if (e < E) {
-                    const int r = row_of(g.start, e);
-                    rr[u] = r;
-                    c[u] = clampc(acol[g.rs[r] + (e - g.start[r])], n);
-                }
+                ok[u] = e < E;
+                const int ec = ok[u] ? e : E - 1;
+                const int r = row_of(g.start, ec);
+                rr[u] = r;
+                k[u] = g.rs[r] + (ec - g.start[r]);
             }
+            int32_t raw[SR_U];
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) raw[u] = acol[k[u]];
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) c[u] = clampc(raw[u], n);
+            step_mult(c, ok, b2, jpos, Dn, mm);
 #pragma unroll
             for (int u = 0; u < SR_U; u++)
-                if (c[u] >= 0 && test_bit(bm, c[u])) atomicAdd(&g.cnt[rr[u]], mult_of(c[u], dm, jpos, Dn));
+                if (mm[u]) atomicAdd(&g.cnt[rr[u]], mm[u]);
         }
         __builtin_amdgcn_wave_barrier();
         if (small) cnt[i] = g.cnt[l];
         return;
     }
-    // big-row chunks, one wavefront each (these workgroups come first)
+    // big-row chunks: every wavefront takes a contiguous range of chunks
+    // (these workgroups come first)
     const int64_t nbig = cp[nI];
-    const int64_t nwaves = nbw * 4;
-    for (int64_t q = bid * 4 + w; q < nbig; q += nwaves) {
-        const int64_t row = wave_search_le(cp, nI + 1, q);
-        const int64_t b = (q - cp[row]) * SR_BW;
-        const int64_t e = min(b + SR_BW, (int64_t)rl[row]);
-        const int64_t base = rs[row];
-        int sum = 0;
+    int64_t q0, q1;
+    chunk_range(nbig, bid * 4 + w, nbw * 4, q0, q1);
+    if (q0 >= q1) return;
+    int64_t row = wave_search_le(cp, nI + 1, q0);
+    int64_t rbeg = cp[row], rend = cp[row + 1], base = rs[row];
+    int64_t rlen = rl[row];
+    for (int64_t q = q0; q < q1; q++) {
+        if (q >= rend) {
+            row = next_chunk_row(cp, nI, row, q);
+            rbeg = cp[row];
+            rend = cp[row + 1];
+            base = rs[row];
+            rlen = rl[row];
+        }
+        const int64_t b = (q - rbeg) * SR_BW;
+        const int64_t e = min(b + SR_BW, rlen);
+        int64_t c[SR_U];
+        int mm[SR_U];
+        bool ok[SR_U];
+        int32_t raw[SR_U];
 #pragma unroll
         for (int u = 0; u < SR_U; u++) {
-            const int64_t k = b + u * WAVE + l;
-            if (k < e) {
-                const int64_t c = clampc(acol[base + k], n);
-                if (test_bit(bm, c)) sum += mult_of(c, dm, jpos, Dn);
-            }
+            const int64_t kk = b + u * WAVE + l;
+            ok[u] = kk < e;
+            raw[u] = acol[base + (ok[u] ? kk : e - 1)];
         }
+#pragma unroll
+        for (int u = 0; u < SR_U; u++) c[u] = clampc(raw[u], n);
+        step_mult(c, ok, b2, jpos, Dn, mm);
+        int sum = 0;
+#pragma unroll
+        for (int u = 0; u < SR_U; u++) sum += mm[u];
         sum = wave_sum(sum);
         if (l == 0 && sum) atomicAdd(&cnt[row], sum);
     }
@@ -236,13 +320,14 @@ __device__ inline void spref_count_tile(
 // slices in order are entries in scan order.  For each slice the wavefront
 // computes an exclusive scan of the hit multiplicities; a hit's position in
 // its row is the row's running count plus the scan minus the scan at the
-// row's first lane in the slice.
+// row's first lane in the slice.  Loads go in three rounds per step: columns
+// and values, bitmap words, then the J positions of the hits.
 template <typename PT, typename VT>
 __device__ inline void spref_gather_tile(
     int64_t bid, int64_t nbw, GroupSmem *gs, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
     int64_t n, const int64_t *__restrict__ rs, const int32_t *__restrict__ rl, const int64_t *__restrict__ cp,
-    int64_t nI, const uint32_t *__restrict__ bm, const uint32_t *__restrict__ dm,
-    const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn, const PT *__restrict__ crow,
+    int64_t nI, const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos,
+    const int32_t *__restrict__ Dn, const PT *__restrict__ crow,
     int32_t *ccol, VT *cval, int32_t *cursor, const DevHdr *hdr) {
     if (hdr->err) return;
     const int w = threadIdx.x / WAVE, l = lane_id();
@@ -267,25 +352,28 @@ __device__ inline void spref_gather_tile(
         for (int e0 = 0; e0 < E; e0 += SR_BW) {
             int64_t c[SR_U], k[SR_U];
             int rr[SR_U], mm[SR_U];
+            bool ok[SR_U];
 #pragma unroll
             for (int u = 0; u < SR_U; u++) {
                 const int e = e0 + u * WAVE + l;
-                c[u] = -1;
-                rr[u] = -1 - l;  // distinct per idle lane: never joins a segment
-                k[u] = 0;
-                if (e < E) {
-                    const int r = row_of(g.start, e);
-                    rr[u] = r;
-                    k[u] = g.rs[r] + (e - g.start[r]);
-                    c[u] = clampc(acol[k[u]], n);
-                }
+                ok[u] = e < E;
+                const int ec = ok[u] ? e : E - 1;
+                const int r = row_of(g.start, ec);
+                rr[u] = ok[u] ? r : -1 - l;   // distinct per idle lane: never joins a segment
+                k[u] = g.rs[r] + (ec - g.start[r]);
             }
-#pragma unroll
-            for (int u = 0; u < SR_U; u++)
-                mm[u] = (c[u] >= 0 && test_bit(bm, c[u])) ? mult_of(c[u], dm, jpos, Dn) : 0;
+            int32_t raw[SR_U];
             VT v[SR_U];
 #pragma unroll
-            for (int u = 0; u < SR_U; u++) v[u] = mm[u] ? aval[k[u]] : VT(0);
+            for (int u = 0; u < SR_U; u++) raw[u] = acol[k[u]];
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) v[u] = aval[k[u]];
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) c[u] = clampc(raw[u], n);
+            step_mult(c, ok, b2, jpos, Dn, mm);
+            int32_t jv[SR_U];
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) jv[u] = mm[u] ? jpos[c[u]] : 0;
 #pragma unroll
             for (int u = 0; u < SR_U; u++) {
                 const int ex = wave_incl_scan(mm[u]) - mm[u];
@@ -298,8 +386,7 @@ __device__ inline void spref_gather_tile(
                 const int base_ex = __shfl(ex, first, WAVE);
                 if (mm[u]) {
                     const int r = rr[u];
-                    const int64_t pos = g.crow[r] + g.cnt[r] + (ex - base_ex);
-                    emit_hits<VT>(c[u], v[u], pos, dm, jpos, Dn, ccol, cval);
+                    emit_chain<VT>(jv[u], v[u], g.crow[r] + g.cnt[r] + (ex - base_ex), Dn, ccol, cval);
                 }
                 __builtin_amdgcn_wave_barrier();
                 if (rr[u] >= 0 && is_last) g.cnt[rr[u]] += ex + mm[u] - base_ex;
@@ -311,25 +398,46 @@ __device__ inline void spref_gather_tile(
     // big-row chunks: positions inside the chunk in scan order, the chunk's
     // block of the row reserved with the row's cursor (workgroups come first)
     const int64_t nbig = cp[nI];
-    const int64_t nwaves = nbw * 4;
-    for (int64_t q = bid * 4 + w; q < nbig; q += nwaves) {
-        const int64_t row = wave_search_le(cp, nI + 1, q);
-        const int64_t b = (q - cp[row]) * SR_BW;
-        const int64_t e = min(b + SR_BW, (int64_t)rl[row]);
-        const int64_t base = rs[row];
+    int64_t q0, q1;
+    chunk_range(nbig, bid * 4 + w, nbw * 4, q0, q1);
+    if (q0 >= q1) return;
+    int64_t row = wave_search_le(cp, nI + 1, q0);
+    int64_t rbeg = cp[row], rend = cp[row + 1], base = rs[row];
+    int64_t rlen = rl[row], orow = (int64_t)crow[row];
+    for (int64_t q = q0; q < q1; q++) {
+        if (q >= rend) {
+            row = next_chunk_row(cp, nI, row, q);
+            rbeg = cp[row];
+            rend = cp[row + 1];
+            base = rs[row];
+            rlen = rl[row];
+            orow = (int64_t)crow[row];
+        }
+        const int64_t b = (q - rbeg) * SR_BW;
+        const int64_t e = min(b + SR_BW, rlen);
         int64_t c[SR_U];
         int mm[SR_U];
+        bool ok[SR_U];
+        int32_t raw[SR_U];
+        VT v[SR_U];
 #pragma unroll
         for (int u = 0; u < SR_U; u++) {
             const int64_t kk = b + u * WAVE + l;
-            c[u] = -1;
-            if (kk < e) c[u] = clampc(acol[base + kk], n);
+            ok[u] = kk < e;
+            const int64_t kc = base + (ok[u] ? kk : e - 1);
+            raw[u] = acol[kc];
+            v[u] = aval[kc];
         }
+#pragma unroll
+        for (int u = 0; u < SR_U; u++) c[u] = clampc(raw[u], n);
+        step_mult(c, ok, b2, jpos, Dn, mm);
+        int32_t jv[SR_U];
+#pragma unroll
+        for (int u = 0; u < SR_U; u++) jv[u] = mm[u] ? jpos[c[u]] : 0;
         int run = 0;
         int ex[SR_U];
 #pragma unroll
         for (int u = 0; u < SR_U; u++) {
-            mm[u] = (c[u] >= 0 && test_bit(bm, c[u])) ? mult_of(c[u], dm, jpos, Dn) : 0;
             const int inc = wave_incl_scan(mm[u]);
             ex[u] = run + inc - mm[u];
             run += __shfl(inc, WAVE - 1, WAVE);
@@ -337,10 +445,10 @@ __device__ inline void spref_gather_tile(
         int32_t cb = 0;
         if (l == 0 && run) cb = atomicAdd(&cursor[row], run);
         cb = __shfl(cb, 0, WAVE);
-        const int64_t ob = (int64_t)crow[row] + cb;
+        const int64_t ob = orow + cb;
 #pragma unroll
         for (int u = 0; u < SR_U; u++)
-            if (mm[u]) emit_hits<VT>(c[u], aval[base + b + u * WAVE + l], ob + ex[u], dm, jpos, Dn, ccol, cval);
+            if (mm[u]) emit_chain<VT>(jv[u], v[u], ob + ex[u], Dn, ccol, cval);
     }
 }
 
