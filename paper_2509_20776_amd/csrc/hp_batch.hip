@@ -85,6 +85,8 @@ struct ReqDev {
     int32_t *ccol;
     void *cval;
     void *tmp;
+    uint64_t *hmS, *hmB;     // spref hit masks
+    int64_t capb;
     uint64_t glob_elems;
     int32_t nb, nbw;
     uint32_t cls[NBINS];
@@ -142,7 +144,7 @@ __device__ void run_tile(int half, int phase, int64_t tile, const ReqDev &r, Bat
                     break;
                 case 6:
                     spref::spref_count_tile(tile, r.nbw, sm.gs, r.acol, r.n, r.rs, r.rl, r.cp, r.nI, r.b2, r.jpos,
-                                            r.Dn, r.cnt, r.hdr);
+                                            r.Dn, r.cnt, r.hmS, r.hmB, r.capb, r.hdr);
                     break;
                 case 7:
                     scan_counts_tile<PT>(tile, sm.scan, r.cnt, (PT *)r.crow_tmp, r.nI, r.hdr, 1, r.tiles1, 3,
@@ -192,7 +194,7 @@ __device__ void run_tile(int half, int phase, int64_t tile, const ReqDev &r, Bat
             case 1:
                 spref::spref_gather_tile<PT, VT>(tile, r.nbw, sm.gs, r.acol, (const VT *)r.aval, r.n, r.rs, r.rl, r.cp,
                                                  r.nI, r.b2, r.jpos, r.Dn, crow, r.ccol, (VT *)r.cval, r.cursor,
-                                                 r.hdr);
+                                                 r.hmS, r.hmB, r.capb, r.hdr);
                 break;
             case 2: sort_small_tile<PT, VT>(tile, sm.wave, crow, r.ccol, (VT *)r.cval, r.nI, ld, r.hdr); break;
             case 3:
@@ -375,6 +377,9 @@ size_t req_scratch(hp::Carve &c, const hp_request_t &rq, ReqDev &d) {
         d.cursor = c.take<int32_t>(nI + 1);
         d.lists = c.take<uint32_t>(seg_list_words(nI));
         d.crow_tmp = c.take<char>((size_t)(nI + 1) * ps);
+        d.capb = spref::hit_mask_big_cap(rq.A.nnz);
+        d.hmS = c.take<uint64_t>((size_t)spref::hit_mask_small_words(nI));
+        d.hmB = c.take<uint64_t>((size_t)d.capb * spref::SR_U);
     } else {
         const size_t st = scan_tiles(m);
         const bool sym = rq.q == nullptr;

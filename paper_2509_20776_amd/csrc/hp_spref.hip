@@ -48,10 +48,12 @@ struct SprefLayout {
     int64_t *cp;
     int32_t *cursor;       // big-row fill cursors (exec)
     uint32_t *lists;
+    uint64_t *hmS, *hmB;   // hit masks of the count pass (small-row steps, big-row chunks)
+    int64_t capb;          // big-row chunks the masks can hold
     size_t nzero, nw;
 };
 
-SprefLayout spref_layout(Carve &c, int64_t n, int64_t nI, int64_t nJ) {
+SprefLayout spref_layout(Carve &c, int64_t n, int64_t nI, int64_t nJ, int64_t nnzA) {
     SprefLayout L;
     L.nw = (((size_t)((n + 31) / 32) + 1) + 3) & ~size_t(3);   // keeps cnt 16-byte aligned
     const size_t st = scan_tiles(nI);
@@ -75,6 +77,9 @@ SprefLayout spref_layout(Carve &c, int64_t n, int64_t nI, int64_t nJ) {
     L.cp = c.take<int64_t>(nI + 1);
     L.cursor = c.take<int32_t>(nI + 1);
     L.lists = c.take<uint32_t>(seg_list_words(nI));
+    L.capb = hit_mask_big_cap(nnzA);
+    L.hmS = c.take<uint64_t>((size_t)hit_mask_small_words(nI));
+    L.hmB = c.take<uint64_t>((size_t)L.capb * SR_U);
     return L;
 }
 
@@ -103,10 +108,10 @@ __global__ __launch_bounds__(SR_BLOCK) void k_spref_count(
     const int32_t *__restrict__ acol, int64_t n, const int64_t *__restrict__ rs,
     const int32_t *__restrict__ rl, const int64_t *__restrict__ cp, int64_t nI, int64_t ngb,
     const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn,
-    int32_t *cnt, const DevHdr *hdr) {
+    int32_t *cnt, uint64_t *hmS, uint64_t *hmB, int64_t capb, const DevHdr *hdr) {
     __shared__ GroupSmem gs[SR_BLOCK / WAVE];
     (void)ngb;
-    spref_count_tile(blockIdx.x, SR_BIGBLOCKS, gs, acol, n, rs, rl, cp, nI, b2, jpos, Dn, cnt, hdr);
+    spref_count_tile(blockIdx.x, SR_BIGBLOCKS, gs, acol, n, rs, rl, cp, nI, b2, jpos, Dn, cnt, hmS, hmB, capb, hdr);
 }
 template <typename PT, typename VT>
 __global__ __launch_bounds__(SR_BLOCK) void k_spref_gather(
@@ -114,11 +119,11 @@ __global__ __launch_bounds__(SR_BLOCK) void k_spref_gather(
     const int64_t *__restrict__ rs, const int32_t *__restrict__ rl, const int64_t *__restrict__ cp,
     int64_t nI, int64_t ngb, const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos,
     const int32_t *__restrict__ Dn, const PT *__restrict__ crow, int32_t *ccol, VT *cval, int32_t *cursor,
-    const DevHdr *hdr) {
+    const uint64_t *__restrict__ hmS, const uint64_t *__restrict__ hmB, int64_t capb, const DevHdr *hdr) {
     __shared__ GroupSmem gs[SR_BLOCK / WAVE];
     (void)ngb;
     spref_gather_tile<PT, VT>(blockIdx.x, SR_BIGBLOCKS, gs, acol, aval, n, rs, rl, cp, nI, b2, jpos, Dn, crow,
-                              ccol, cval, cursor, hdr);
+                              ccol, cval, cursor, hmS, hmB, capb, hdr);
 }
 
 hp_status_t spref_check_args(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int64_t nI,
@@ -144,7 +149,7 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
                          hp_plan_info_t *info) {
     const int64_t m = A->nrows, n = A->ncols;
     Carve need(nullptr);
-    spref_layout(need, n, nI, nJ);
+    spref_layout(need, n, nI, nJ, A->nnz);
     if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "spref plan workspace too small");
     const size_t ps = sizeof(PT), vs = val_size(A->val_type);
     const void *ins[] = {A->rowptr, A->col, A->val, I, J};
@@ -156,7 +161,7 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     if (overlaps(C->rowptr, (nI + 1) * ps, ws, ws_bytes))
         return fail(h, HP_ERR_ALIAS, "C->rowptr overlaps the workspace");
     Carve c(ws);
-    SprefLayout L = spref_layout(c, n, nI, nJ);
+    SprefLayout L = spref_layout(c, n, nI, nJ, A->nnz);
     const size_t st = scan_tiles(nI);
     hipStream_t s = h->stream;
     stage_begin(h);
@@ -180,7 +185,8 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     const int64_t ngb = (nI + 4 * WAVE - 1) / (4 * WAVE);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_spref_count, dim3((unsigned)(ngb + SR_BIGBLOCKS)), dim3(SR_BLOCK), 0, s, A->col,
-                           n, L.rs, L.rl, L.cp, nI, ngb, L.b2, L.jpos, L.Dn, L.cnt, L.hdr);
+                           n, L.rs, L.rl, L.cp, nI, ngb, L.b2, L.jpos, L.Dn, L.cnt, L.hmS, L.hmB, L.capb,
+                           L.hdr);
         stage_mark(h, "spref.count");
         e = hipGetLastError();
     }
@@ -217,7 +223,7 @@ hp_status_t spref_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
                          const hp_plan_info_t *info, void *xws, size_t xws_bytes) {
     const int64_t m = A->nrows, n = A->ncols;
     Carve need(nullptr);
-    spref_layout(need, n, nI, nJ);
+    spref_layout(need, n, nI, nJ, A->nnz);
     if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "spref workspace too small");
     if (!info || info->op != 2) return fail(h, HP_ERR_INVALID_ARG, "info is not from hp_spref_plan");
     if (xws_bytes < info->exec_ws_bytes || (info->exec_ws_bytes && !xws))
@@ -234,7 +240,7 @@ hp_status_t spref_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
             overlaps(C->val, (size_t)C->nnz * vs, ins[k], insz[k]))
             return fail(h, HP_ERR_ALIAS, "C->col/val overlaps an input or workspace");
     Carve c(ws);
-    SprefLayout L = spref_layout(c, n, nI, nJ);
+    SprefLayout L = spref_layout(c, n, nI, nJ, A->nnz);
     hipStream_t s = h->stream;
     const int64_t ngb = (nI + 4 * WAVE - 1) / (4 * WAVE);
     stage_begin(h);
@@ -243,7 +249,8 @@ hp_status_t spref_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     if (e == hipSuccess && info->nnz_out > 0) {
         hipLaunchKernelGGL((k_spref_gather<PT, VT>), dim3((unsigned)(ngb + SR_BIGBLOCKS)), dim3(SR_BLOCK), 0,
                            s, A->col, (const VT *)A->val, n, L.rs, L.rl, L.cp, nI, ngb, L.b2, L.jpos,
-                           L.Dn, (const PT *)C->rowptr, C->col, (VT *)C->val, L.cursor, L.hdr);
+                           L.Dn, (const PT *)C->rowptr, C->col, (VT *)C->val, L.cursor, L.hmS, L.hmB, L.capb,
+                           L.hdr);
         stage_mark(h, "spref.gather");
         e = hipGetLastError();
     }
@@ -272,7 +279,7 @@ extern "C" hp_status_t hp_spref_workspace(hp_handle_t h, const hp_csr_t *A, int6
     if (st) return st;
     if (nI < 0 || nJ < 0) return fail(h, HP_ERR_INVALID_ARG, "negative index-vector length");
     Carve c(nullptr);
-    spref_layout(c, A->ncols, nI, nJ);
+    spref_layout(c, A->ncols, nI, nJ, A->nnz);
     *bytes = c.size();
     return HP_OK;
 }

@@ -12,6 +12,16 @@ constexpr int SR_BLOCK = 256;
 constexpr int SR_U = 8;                       // entries per lane per step
 constexpr int64_t SR_LB = 256;                // rows above this many entries are big
 constexpr int64_t SR_BW = WAVE * SR_U;        // entries per big-row chunk
+constexpr int SR_STEPS = (int)(WAVE * SR_LB / SR_BW);   // most steps of a 64-row group (32)
+
+// The count pass leaves, for every step of SR_U slots, one 64-bit word per
+// slot with the lanes that hit (a ballot), so the gather pass reads one
+// uniform word per slot instead of looking every entry up again:
+//   small rows: hmS[(group * SR_STEPS + step) * SR_U + slot], group = 64 rows;
+//   big rows:   hmB[chunk * SR_U + slot] while the chunk count fits capb
+//               (both passes test nbig <= capb the same way).
+inline int64_t hit_mask_small_words(int64_t nI) { return ((nI + WAVE - 1) / WAVE) * SR_STEPS * SR_U; }
+inline int64_t hit_mask_big_cap(int64_t nnzA) { return nnzA / 256 + 64; }
 constexpr int SR_BIGBLOCKS = 2048;            // persistent workgroups for big chunks (launched first)
 constexpr int NMSLOTS = 64;                   // spread "J not increasing" flag slots
 
@@ -148,6 +158,35 @@ __device__ __forceinline__ void step_mult(const int64_t (&c)[SR_U], const bool (
     }
 }
 
+// Gather side of the hit masks: the slots' hit bits come from the count
+// pass's words w[0..SR_U), so only the hits look anything up (their J
+// position; a negative one heads the chain of a repeated column).
+__device__ __forceinline__ void hits_from_mask(const uint64_t *__restrict__ w, const int32_t (&raw)[SR_U],
+                                               int64_t n, const int32_t *__restrict__ jpos,
+                                               const int32_t *__restrict__ Dn, int64_t (&c)[SR_U],
+                                               int32_t (&jv)[SR_U], int (&mm)[SR_U]) {
+    const int l = lane_id();
+    bool hit[SR_U];
+#pragma unroll
+    for (int u = 0; u < SR_U; u++) {
+        hit[u] = (w[u] >> l) & 1ull;
+        c[u] = clampc(raw[u], n);
+    }
+#pragma unroll
+    for (int u = 0; u < SR_U; u++) jv[u] = hit[u] ? jpos[c[u]] : 0;
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < SR_U; u++) {
+        mm[u] = hit[u] ? 1 : 0;
+        any |= hit[u] && jv[u] < 0;
+    }
+    if (ballot(any)) {
+#pragma unroll
+        for (int u = 0; u < SR_U; u++)
+            if (hit[u] && jv[u] < 0) mm[u] = chain_len(jv[u], Dn);
+    }
+}
+
 // Write the output entries of one hit whose jpos entry is x: one entry for a
 // column that occurs once in J (x >= 0), the whole chain otherwise.
 template <typename VT>
@@ -227,12 +266,13 @@ __device__ inline void spref_count_tile(
     int64_t bid, int64_t nbw, GroupSmem *gs, const int32_t *__restrict__ acol, int64_t n,
     const int64_t *__restrict__ rs, const int32_t *__restrict__ rl, const int64_t *__restrict__ cp, int64_t nI,
     const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn,
-    int32_t *cnt, const DevHdr *hdr) {
+    int32_t *cnt, uint64_t *hmS, uint64_t *hmB, int64_t capb, const DevHdr *hdr) {
     if (hdr->err) return;
     const int w = threadIdx.x / WAVE, l = lane_id();
     if (bid >= nbw) {
         GroupSmem &g = gs[w];
-        const int64_t i = ((bid - nbw) * 4 + w) * WAVE + l;
+        const int64_t gw = (bid - nbw) * 4 + w;
+        const int64_t i = gw * WAVE + l;
         int len = 0;
         bool small = false;
         if (i < nI) {
@@ -267,6 +307,13 @@ __device__ inline void spref_count_tile(
 #pragma unroll
             for (int u = 0; u < SR_U; u++) c[u] = clampc(raw[u], n);
             step_mult(c, ok, b2, jpos, Dn, mm);
+            uint64_t hm = 0;
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) {
+                const uint64_t b = ballot(mm[u] != 0);
+                if (l == u) hm = b;
+            }
+            if (l < SR_U) hmS[(gw * SR_STEPS + e0 / SR_BW) * SR_U + l] = hm;
 #pragma unroll
             for (int u = 0; u < SR_U; u++)
                 if (mm[u]) atomicAdd(&g.cnt[rr[u]], mm[u]);
@@ -307,6 +354,15 @@ __device__ inline void spref_count_tile(
 #pragma unroll
         for (int u = 0; u < SR_U; u++) c[u] = clampc(raw[u], n);
         step_mult(c, ok, b2, jpos, Dn, mm);
+        if (nbig <= capb) {
+            uint64_t hm = 0;
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) {
+                const uint64_t bb = ballot(mm[u] != 0);
+                if (l == u) hm = bb;
+            }
+            if (l < SR_U) hmB[q * SR_U + l] = hm;
+        }
         int sum = 0;
 #pragma unroll
         for (int u = 0; u < SR_U; u++) sum += mm[u];
@@ -328,13 +384,15 @@ __device__ inline void spref_gather_tile(
     int64_t n, const int64_t *__restrict__ rs, const int32_t *__restrict__ rl, const int64_t *__restrict__ cp,
     int64_t nI, const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos,
     const int32_t *__restrict__ Dn, const PT *__restrict__ crow,
-    int32_t *ccol, VT *cval, int32_t *cursor, const DevHdr *hdr) {
+    int32_t *ccol, VT *cval, int32_t *cursor, const uint64_t *__restrict__ hmS,
+    const uint64_t *__restrict__ hmB, int64_t capb, const DevHdr *hdr) {
     if (hdr->err) return;
     const int w = threadIdx.x / WAVE, l = lane_id();
     const uint64_t le_mask = (l == 63) ? ~0ull : ((2ull << l) - 1);
     if (bid >= nbw) {
         GroupSmem &g = gs[w];
-        const int64_t i = ((bid - nbw) * 4 + w) * WAVE + l;
+        const int64_t gw = (bid - nbw) * 4 + w;
+        const int64_t i = gw * WAVE + l;
         int len = 0;
         if (i < nI) {
             const int L = rl[i];
@@ -364,16 +422,13 @@ __device__ inline void spref_gather_tile(
             }
             int32_t raw[SR_U];
             VT v[SR_U];
+            const uint64_t *hw = hmS + (gw * SR_STEPS + e0 / SR_BW) * SR_U;
 #pragma unroll
             for (int u = 0; u < SR_U; u++) raw[u] = acol[k[u]];
 #pragma unroll
             for (int u = 0; u < SR_U; u++) v[u] = aval[k[u]];
-#pragma unroll
-            for (int u = 0; u < SR_U; u++) c[u] = clampc(raw[u], n);
-            step_mult(c, ok, b2, jpos, Dn, mm);
             int32_t jv[SR_U];
-#pragma unroll
-            for (int u = 0; u < SR_U; u++) jv[u] = mm[u] ? jpos[c[u]] : 0;
+            hits_from_mask(hw, raw, n, jpos, Dn, c, jv, mm);
 #pragma unroll
             for (int u = 0; u < SR_U; u++) {
                 const int ex = wave_incl_scan(mm[u]) - mm[u];
@@ -398,6 +453,7 @@ __device__ inline void spref_gather_tile(
     // big-row chunks: positions inside the chunk in scan order, the chunk's
     // block of the row reserved with the row's cursor (workgroups come first)
     const int64_t nbig = cp[nI];
+    const bool use_mask = nbig <= capb;
     int64_t q0, q1;
     chunk_range(nbig, bid * 4 + w, nbw * 4, q0, q1);
     if (q0 >= q1) return;
@@ -428,12 +484,16 @@ __device__ inline void spref_gather_tile(
             raw[u] = acol[kc];
             v[u] = aval[kc];
         }
-#pragma unroll
-        for (int u = 0; u < SR_U; u++) c[u] = clampc(raw[u], n);
-        step_mult(c, ok, b2, jpos, Dn, mm);
         int32_t jv[SR_U];
+        if (use_mask) {
+            hits_from_mask(hmB + q * SR_U, raw, n, jpos, Dn, c, jv, mm);
+        } else {
 #pragma unroll
-        for (int u = 0; u < SR_U; u++) jv[u] = mm[u] ? jpos[c[u]] : 0;
+            for (int u = 0; u < SR_U; u++) c[u] = clampc(raw[u], n);
+            step_mult(c, ok, b2, jpos, Dn, mm);
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) jv[u] = mm[u] ? jpos[c[u]] : 0;
+        }
         int run = 0;
         int ex[SR_U];
 #pragma unroll

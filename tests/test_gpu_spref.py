@@ -147,3 +147,18 @@ def test_long_rows_over_2pow20_columns(hp, ptr):
     same_row = torch.ones(C.nnz, dtype=torch.bool, device="cuda")
     same_row[cr[:-1][cr[:-1] < C.nnz]] = False
     assert bool(torch.all((C.col[1:] > C.col[:-1]) | ~same_row[1:]))
+
+
+def test_big_row_selected_many_times(hp):
+    """A long row selected hundreds of times: more long-row chunks than the
+    count pass can record masks for, so the gather looks entries up itself."""
+    A = mixed_csr(61, 300, 20000, [0, 2, 9, 6000], torch.int32, torch.float32)
+    rp = A.rowptr.cpu().numpy()
+    hub = int(np.argmax(np.diff(rp)))
+    I = torch.tensor([hub] * 250 + list(range(0, 300, 7)), dtype=torch.int32, device="cuda")
+    I = I[torch.randperm(I.numel(), generator=torch.Generator().manual_seed(3)).to("cuda")]
+    J = synth.subset(62, A.ncols, 9000, repeat_frac=0.05, device="cuda")
+    C = hp.spref(A, I, J)
+    torch.cuda.synchronize()
+    rows = sample_rows(63, I.numel(), 12)
+    assert_same(rows_of(C, rows), oracle.spref(A, I, J, rows=rows), "sampled rows")
