@@ -86,6 +86,7 @@ struct ReqDev {
     void *cval;
     void *tmp;
     uint64_t *hmS, *hmB;     // spref hit masks
+    uint8_t *gflag;          // spref 64-row groups left unsorted by the gather
     int64_t capb;
     uint64_t glob_elems;
     int32_t nb, nbw;
@@ -100,6 +101,7 @@ struct QEntry {
 union BatchSmem {
     ScanSmem scan;
     spref::GroupSmem gs[4];
+    spref::GroupCore gc[4];
     SegSmemWave wave;
     SegSmemBlock block;
     SegSmemBucket bucket;
@@ -143,7 +145,7 @@ __device__ void run_tile(int half, int phase, int64_t tile, const ReqDev &r, Bat
                                               nullptr, nullptr, nullptr);
                     break;
                 case 6:
-                    spref::spref_count_tile(tile, r.nbw, sm.gs, r.acol, r.n, r.rs, r.rl, r.cp, r.nI, r.b2, r.jpos,
+                    spref::spref_count_tile(tile, r.nbw, sm.gc, r.acol, r.n, r.rs, r.rl, r.cp, r.nI, r.b2, r.jpos,
                                             r.Dn, r.cnt, r.hmS, r.hmB, r.capb, r.hdr);
                     break;
                 case 7:
@@ -194,9 +196,11 @@ __device__ void run_tile(int half, int phase, int64_t tile, const ReqDev &r, Bat
             case 1:
                 spref::spref_gather_tile<PT, VT>(tile, r.nbw, sm.gs, r.acol, (const VT *)r.aval, r.n, r.rs, r.rl, r.cp,
                                                  r.nI, r.b2, r.jpos, r.Dn, crow, r.ccol, (VT *)r.cval, r.cursor,
-                                                 r.hmS, r.hmB, r.capb, r.hdr);
+                                                 r.hmS, r.hmB, r.capb, !r.monotone, r.gflag, r.hdr);
                 break;
-            case 2: sort_small_tile<PT, VT>(tile, sm.wave, crow, r.ccol, (VT *)r.cval, r.nI, ld, r.hdr); break;
+            case 2:
+                sort_small_tile<PT, VT>(tile, sm.wave, crow, r.ccol, (VT *)r.cval, r.nI, ld, r.hdr, r.gflag, r.big);
+                break;
             case 3:
                 seg_thread_tile<PT, VT>(tile, crow, r.ccol, (VT *)r.cval, r.lists + BIN_THREAD * cap, r.cls[BIN_THREAD],
                                         ld, 0, r.hdr);
@@ -380,6 +384,7 @@ size_t req_scratch(hp::Carve &c, const hp_request_t &rq, ReqDev &d) {
         d.capb = spref::hit_mask_big_cap(rq.A.nnz);
         d.hmS = c.take<uint64_t>((size_t)spref::hit_mask_small_words(nI));
         d.hmB = c.take<uint64_t>((size_t)d.capb * spref::SR_U);
+        d.gflag = c.take<uint8_t>((size_t)((nI + WAVE - 1) / WAVE) + 1);
     } else {
         const size_t st = scan_tiles(m);
         const bool sym = rq.q == nullptr;

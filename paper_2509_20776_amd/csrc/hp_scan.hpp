@@ -21,8 +21,9 @@ constexpr uint64_t SCAN_WAIT_TICKS = 10000000ull;   // 0.1 s of the 100 MHz wall
 // Sort class of a row of `len` entries under classification `mode`:
 //   1  rows longer than 4 (shorter rows are sorted by the producer itself)
 //   2  every row of >= 2 entries
-//   3  rows longer than SMALL_MAX when `all` (shorter ones are sorted by
-//      k_sort_small), else only flagged rows
+//   3  when `all`: flagged rows and rows longer than SMALL_MAX (shorter
+//      unflagged rows are sorted by the extraction gather or by
+//      k_sort_small); else only flagged rows
 //   4  only flagged rows
 __device__ __forceinline__ int class_of(int64_t len, int mode, bool all, bool flagged) {
     if (len < 2) return -1;
@@ -30,7 +31,7 @@ __device__ __forceinline__ int class_of(int64_t len, int mode, bool all, bool fl
     if (mode == 4 && !flagged) return -1;
     if (mode == 3) {
         if (all) {
-            if (len <= SMALL_MAX) return -1;
+            if (len <= SMALL_MAX && !flagged) return -1;
         } else if (!flagged) {
             return -1;
         }
@@ -155,7 +156,7 @@ __device__ void scan_counts_tile(int64_t tile, ScanSmem &sm, const int32_t *__re
 #pragma unroll
         for (int k = 0; k < SCAN_ITEMS; k++) {
             const bool valid = base + k < n;
-            const bool fl = ((classify == 3 && !all) || classify == 4) && valid ? force[base + k] != 0 : false;
+            const bool fl = (classify == 3 || classify == 4) && valid ? force[base + k] != 0 : false;
             bin[k] = valid ? class_of(v[k], classify, all, fl) : -1;
             off[k] = 0;
             eoff[k] = 0;

@@ -198,16 +198,22 @@ __global__ __launch_bounds__(256) void k_seg_wave(const PT *__restrict__ rowptr,
 // All rows of <= SMALL_MAX entries, without lists: each wavefront takes 64
 // consecutive rows; rows of <= 16 are sorted by their own lane, rows of
 // 17..64 by the whole wavefront one after another.  Longer rows are left to
-// the class kernels.
+// the class kernels.  With gflag, only the 64-row groups flagged there are
+// visited, and rows with skip[row] set (sorted through the class lists) are
+// left alone.
 template <typename PT, typename VT, typename LD>
 __device__ void sort_small_tile(int64_t bid, SegSmemWave &sm, const PT *__restrict__ rowptr, int32_t *okey,
-                                VT *oval, int64_t nrows, const LD &ld, const DevHdr *hdr) {
+                                VT *oval, int64_t nrows, const LD &ld, const DevHdr *hdr,
+                                const uint8_t *__restrict__ gflag = nullptr,
+                                const uint8_t *__restrict__ skip = nullptr) {
     if (hdr->err) return;
     const int w = threadIdx.x / WAVE, l = lane_id();
-    const int64_t row = (bid * 4 + w) * WAVE + l;
+    const int64_t grp = bid * 4 + w;
+    if (gflag && (grp * WAVE >= nrows || !gflag[grp])) return;
+    const int64_t row = grp * WAVE + l;
     int len = 0;
     int64_t b = 0;
-    if (row < nrows) {
+    if (row < nrows && !(skip && skip[row])) {
         b = rowptr[row];
         len = (int)(rowptr[row + 1] - b);
     }
@@ -226,9 +232,10 @@ __device__ void sort_small_tile(int64_t bid, SegSmemWave &sm, const PT *__restri
 template <typename PT, typename VT, typename LD>
 __global__ __launch_bounds__(256) void k_sort_small(const PT *__restrict__ rowptr, int32_t *okey,
                                                    VT *oval, int64_t nrows, LD ld,
-                                                   const DevHdr *hdr) {
+                                                   const DevHdr *hdr, const uint8_t *gflag = nullptr,
+                                                   const uint8_t *skip = nullptr) {
     __shared__ __align__(16) SegSmemWave sm;
-    sort_small_tile<PT, VT, LD>(blockIdx.x, sm, rowptr, okey, oval, nrows, ld, hdr);
+    sort_small_tile<PT, VT, LD>(blockIdx.x, sm, rowptr, okey, oval, nrows, ld, hdr, gflag, skip);
 }
 
 // ---- workgroup LDS sort of <= BLOCK_MAX keys with their 16-bit source index ----

@@ -49,6 +49,7 @@ struct SprefLayout {
     int32_t *cursor;       // big-row fill cursors (exec)
     uint32_t *lists;
     uint64_t *hmS, *hmB;   // hit masks of the count pass (small-row steps, big-row chunks)
+    uint8_t *gflag;        // 64-row groups left unsorted by the gather
     int64_t capb;          // big-row chunks the masks can hold
     size_t nzero, nw;
 };
@@ -80,6 +81,7 @@ SprefLayout spref_layout(Carve &c, int64_t n, int64_t nI, int64_t nJ, int64_t nn
     L.capb = hit_mask_big_cap(nnzA);
     L.hmS = c.take<uint64_t>((size_t)hit_mask_small_words(nI));
     L.hmB = c.take<uint64_t>((size_t)L.capb * SR_U);
+    L.gflag = c.take<uint8_t>((size_t)((nI + WAVE - 1) / WAVE) + 1);
     return L;
 }
 
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(SR_BLOCK) void k_spref_count(
     const int32_t *__restrict__ rl, const int64_t *__restrict__ cp, int64_t nI, int64_t ngb,
     const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn,
     int32_t *cnt, uint64_t *hmS, uint64_t *hmB, int64_t capb, const DevHdr *hdr) {
-    __shared__ GroupSmem gs[SR_BLOCK / WAVE];
+    __shared__ GroupCore gs[SR_BLOCK / WAVE];
     (void)ngb;
     spref_count_tile(blockIdx.x, SR_BIGBLOCKS, gs, acol, n, rs, rl, cp, nI, b2, jpos, Dn, cnt, hmS, hmB, capb, hdr);
 }
@@ -119,11 +121,12 @@ __global__ __launch_bounds__(SR_BLOCK) void k_spref_gather(
     const int64_t *__restrict__ rs, const int32_t *__restrict__ rl, const int64_t *__restrict__ cp,
     int64_t nI, int64_t ngb, const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos,
     const int32_t *__restrict__ Dn, const PT *__restrict__ crow, int32_t *ccol, VT *cval, int32_t *cursor,
-    const uint64_t *__restrict__ hmS, const uint64_t *__restrict__ hmB, int64_t capb, const DevHdr *hdr) {
+    const uint64_t *__restrict__ hmS, const uint64_t *__restrict__ hmB, int64_t capb, int sort_out,
+    uint8_t *gflag, const DevHdr *hdr) {
     __shared__ GroupSmem gs[SR_BLOCK / WAVE];
     (void)ngb;
     spref_gather_tile<PT, VT>(blockIdx.x, SR_BIGBLOCKS, gs, acol, aval, n, rs, rl, cp, nI, b2, jpos, Dn, crow,
-                              ccol, cval, cursor, hmS, hmB, capb, hdr);
+                              ccol, cval, cursor, hmS, hmB, capb, sort_out != 0, gflag, hdr);
 }
 
 hp_status_t spref_check_args(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int64_t nI,
@@ -250,7 +253,7 @@ hp_status_t spref_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
         hipLaunchKernelGGL((k_spref_gather<PT, VT>), dim3((unsigned)(ngb + SR_BIGBLOCKS)), dim3(SR_BLOCK), 0,
                            s, A->col, (const VT *)A->val, n, L.rs, L.rl, L.cp, nI, ngb, L.b2, L.jpos,
                            L.Dn, (const PT *)C->rowptr, C->col, (VT *)C->val, L.cursor, L.hmS, L.hmB, L.capb,
-                           L.hdr);
+                           info->map_monotone ? 0 : 1, L.gflag, L.hdr);
         stage_mark(h, "spref.gather");
         e = hipGetLastError();
     }
@@ -260,7 +263,8 @@ hp_status_t spref_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
         LoadInPlace<PT, VT> ld{(const PT *)C->rowptr, C->col, (const VT *)C->val};
         if (!info->map_monotone)
             hipLaunchKernelGGL((k_sort_small<PT, VT, LoadInPlace<PT, VT>>), dim3((unsigned)ngb), dim3(256), 0,
-                               s, (const PT *)C->rowptr, C->col, (VT *)C->val, nI, ld, L.hdr);
+                               s, (const PT *)C->rowptr, C->col, (VT *)C->val, nI, ld, L.hdr,
+                               (const uint8_t *)L.gflag, (const uint8_t *)L.big);
         e = launch_seg_classes<PT, VT, LoadInPlace<PT, VT>>(
             s, (const PT *)C->rowptr, C->col, (VT *)C->val, L.lists, nI, cnt, ld, false, nJ, true, xws,
             (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);

@@ -202,6 +202,17 @@ __device__ __forceinline__ void emit_chain(int32_t x, VT v, int64_t pos, const i
     cval[pos] = v;
 }
 
+template <typename VT>
+__device__ __forceinline__ VT stage_val(uint64_t b) {
+    if constexpr (sizeof(VT) == 8) return (VT)b;
+    else return (VT)(uint32_t)b;
+}
+
+struct GroupSmem;
+template <typename VT>
+__device__ __forceinline__ void stage_chain(int32_t x, VT v, int idx, int row, const int32_t *__restrict__ Dn,
+                                            GroupSmem &g);
+
 // Largest i in [0, n) with a[i] <= x, a nondecreasing and a[0] <= x; the
 // wavefront probes 64 positions per round (4 rounds for 2^24 entries).
 __device__ __forceinline__ int64_t wave_search_le(const int64_t *a, int64_t n, int64_t x) {
@@ -250,12 +261,43 @@ __device__ __forceinline__ int row_of(const int32_t *start, int32_t e) {
     return lo;
 }
 
-struct GroupSmem {
+// Gather staging: when the output rows must be sorted, the short rows
+// (<= SMALL_MAX output entries) of a 64-row group are assembled in LDS, then
+// each entry is written at its rank within its row, so no separate sort pass
+// touches them.  A group whose short rows hold more than SR_STAGE entries
+// writes straight to the output and is flagged for the small-row sort.
+constexpr int SR_STAGE = 512;
+
+struct GroupCore {               // per-wavefront state of a 64-row group
     int32_t start[WAVE + 1];
     int32_t cnt[WAVE];
     int64_t rs[WAVE];
     int64_t crow[WAVE];
 };
+
+struct GroupSmem : GroupCore {   // the gather adds its staging area
+    int32_t soff[WAVE];                 // staging offset of a staged row, else -1
+    int32_t scnt[WAVE];                 // output entries of the row
+    int32_t skey[SR_STAGE];
+    uint64_t sval[SR_STAGE];            // value bits (fp32 in the low half)
+    uint8_t srow[SR_STAGE];
+};
+
+// Like emit_chain, into the group's LDS staging area (with the row index).
+template <typename VT>
+__device__ __forceinline__ void stage_chain(int32_t x, VT v, int idx, int row, const int32_t *__restrict__ Dn,
+                                            GroupSmem &g) {
+    while (x < 0) {
+        g.skey[idx] = ~x;
+        g.sval[idx] = (uint64_t)v;
+        g.srow[idx] = (uint8_t)row;
+        idx++;
+        x = Dn[~x];
+    }
+    g.skey[idx] = x;
+    g.sval[idx] = (uint64_t)v;
+    g.srow[idx] = (uint8_t)row;
+}
 
 // ---- count (plan) -------------------------------------------------------------
 // Tile bid of the count pass: bid < nbw are the long-row workers (a
@@ -263,14 +305,14 @@ struct GroupSmem {
 // rows (64 rows per wavefront, walked as one concatenation).  Every step
 // issues its column loads together, then its bitmap loads together.
 __device__ inline void spref_count_tile(
-    int64_t bid, int64_t nbw, GroupSmem *gs, const int32_t *__restrict__ acol, int64_t n,
+    int64_t bid, int64_t nbw, GroupCore *gs, const int32_t *__restrict__ acol, int64_t n,
     const int64_t *__restrict__ rs, const int32_t *__restrict__ rl, const int64_t *__restrict__ cp, int64_t nI,
     const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn,
     int32_t *cnt, uint64_t *hmS, uint64_t *hmB, int64_t capb, const DevHdr *hdr) {
     if (hdr->err) return;
     const int w = threadIdx.x / WAVE, l = lane_id();
     if (bid >= nbw) {
-        GroupSmem &g = gs[w];
+        GroupCore &g = gs[w];
         const int64_t gw = (bid - nbw) * 4 + w;
         const int64_t i = gw * WAVE + l;
         int len = 0;
@@ -385,7 +427,7 @@ __device__ inline void spref_gather_tile(
     int64_t nI, const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos,
     const int32_t *__restrict__ Dn, const PT *__restrict__ crow,
     int32_t *ccol, VT *cval, int32_t *cursor, const uint64_t *__restrict__ hmS,
-    const uint64_t *__restrict__ hmB, int64_t capb, const DevHdr *hdr) {
+    const uint64_t *__restrict__ hmB, int64_t capb, bool sort_out, uint8_t *gflag, const DevHdr *hdr) {
     if (hdr->err) return;
     const int w = threadIdx.x / WAVE, l = lane_id();
     const uint64_t le_mask = (l == 63) ? ~0ull : ((2ull << l) - 1);
@@ -393,15 +435,26 @@ __device__ inline void spref_gather_tile(
         GroupSmem &g = gs[w];
         const int64_t gw = (bid - nbw) * 4 + w;
         const int64_t i = gw * WAVE + l;
-        int len = 0;
+        int len = 0, nout = 0;
         if (i < nI) {
             const int L = rl[i];
             if (L <= SR_LB) {
                 len = L;
                 g.rs[l] = rs[i];
-                g.crow[l] = (int64_t)crow[i];
+                const int64_t c0 = (int64_t)crow[i];
+                g.crow[l] = c0;
+                nout = (int)((int64_t)crow[i + 1] - c0);
             }
         }
+        // rows staged in LDS (sorted output wanted, 1..SMALL_MAX entries)
+        const bool st_row = sort_out && nout >= 1 && nout <= (int)SMALL_MAX;
+        const int sc = st_row ? nout : 0;
+        const int sincl = wave_incl_scan(sc);
+        const int stot = __shfl(sincl, WAVE - 1, WAVE);
+        const bool staging = stot <= SR_STAGE;
+        g.soff[l] = (staging && st_row) ? sincl - sc : -1;
+        g.scnt[l] = nout;
+        if (sort_out && l == 0) gflag[gw] = staging ? 0 : 1;   // 1: left for the small-row sort
         const int incl = wave_incl_scan(len);
         const int E = __shfl(incl, WAVE - 1, WAVE);
         g.start[l] = incl - len;
@@ -441,11 +494,28 @@ __device__ inline void spref_gather_tile(
                 const int base_ex = __shfl(ex, first, WAVE);
                 if (mm[u]) {
                     const int r = rr[u];
-                    emit_chain<VT>(jv[u], v[u], g.crow[r] + g.cnt[r] + (ex - base_ex), Dn, ccol, cval);
+                    const int pos = g.cnt[r] + (ex - base_ex);
+                    const int so = g.soff[r];
+                    if (so >= 0) stage_chain<VT>(jv[u], v[u], so + pos, r, Dn, g);
+                    else emit_chain<VT>(jv[u], v[u], g.crow[r] + pos, Dn, ccol, cval);
                 }
                 __builtin_amdgcn_wave_barrier();
                 if (rr[u] >= 0 && is_last) g.cnt[rr[u]] += ex + mm[u] - base_ex;
                 __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (staging && stot > 0) {
+            // every staged entry goes to its rank within its row
+            __builtin_amdgcn_wave_barrier();
+            for (int e = l; e < stot; e += WAVE) {
+                const int r = g.srow[e];
+                const int s0 = g.soff[r], nr = g.scnt[r];
+                const int32_t key = g.skey[e];
+                int rank = 0;
+                for (int q = 0; q < nr; q++) rank += g.skey[s0 + q] < key;
+                const int64_t o = g.crow[r] + rank;
+                ccol[o] = key;
+                cval[o] = stage_val<VT>(g.sval[e]);
             }
         }
         return;
