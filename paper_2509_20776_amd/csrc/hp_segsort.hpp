@@ -124,17 +124,22 @@ __device__ __forceinline__ void wave_sort_row(const LD &ld, int64_t sb, int len,
         }
         return;
     }
-    const int len4 = (len + 3) & ~3;
+    const int len16 = (len + 15) & ~15;
 #pragma unroll
     for (int q = 0; q < 4; q++)
-        if (q * WAVE < len4) s_k[q * WAVE + l] = mk[q];   // padding keys are INT32_MAX
+        if (q * WAVE < len16) s_k[q * WAVE + l] = mk[q];   // padding keys are INT32_MAX
     __builtin_amdgcn_wave_barrier();
     int rank[4] = {0, 0, 0, 0};
-    for (int i = 0; i < len4; i += 4) {
-        const int4 o = *reinterpret_cast<const int4 *>(s_k + i);
+    // 16 keys per round: four 16-byte LDS reads issued before any is used
+    for (int i = 0; i < len16; i += 16) {
+        int4 o[4];
 #pragma unroll
-        for (int q = 0; q < 4; q++)
-            rank[q] += (o.x < mk[q]) + (o.y < mk[q]) + (o.z < mk[q]) + (o.w < mk[q]);
+        for (int r = 0; r < 4; r++) o[r] = *reinterpret_cast<const int4 *>(s_k + i + 4 * r);
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                rank[q] += (o[r].x < mk[q]) + (o[r].y < mk[q]) + (o[r].z < mk[q]) + (o[r].w < mk[q]);
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -149,7 +154,7 @@ __device__ __forceinline__ void wave_sort_row(const LD &ld, int64_t sb, int len,
 
 // Shared-memory blocks of the tile functions (the batched kernel overlays
 // them in one buffer).
-struct SegSmemWave {
+struct alignas(16) SegSmemWave {
     int32_t k[4][WAVE_MAX];
 };
 
