@@ -12,7 +12,7 @@
 namespace hp {
 
 constexpr int SCAN_BLOCK = 256;   // threads of a scan tile
-constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_ITEMS = 16;   // 4096 counts per tile: fewer tiles, tickets and look-back rounds
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
 constexpr uint64_t ST_AGG = 1ull << 62, ST_PRE = 2ull << 62, ST_VAL = (1ull << 62) - 1;
 constexpr uint64_t SCAN_WAIT_TICKS = 10000000ull;   // 0.1 s of the 100 MHz wall clock
@@ -79,9 +79,16 @@ __device__ void scan_counts_tile(int64_t tile, ScanSmem &sm, const int32_t *__re
     int32_t v[SCAN_ITEMS];
     if (base + SCAN_ITEMS <= n) {
         const int4 *p4 = reinterpret_cast<const int4 *>(cnt + base);
-        int4 a = p4[0], b = p4[1];
-        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        int4 a[SCAN_ITEMS / 4];
+#pragma unroll
+        for (int q = 0; q < SCAN_ITEMS / 4; q++) a[q] = p4[q];
+#pragma unroll
+        for (int q = 0; q < SCAN_ITEMS / 4; q++) {
+            v[4 * q] = a[q].x;
+            v[4 * q + 1] = a[q].y;
+            v[4 * q + 2] = a[q].z;
+            v[4 * q + 3] = a[q].w;
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < SCAN_ITEMS; k++) v[k] = (base + k < n) ? cnt[base + k] : 0;
