@@ -22,7 +22,7 @@ enum : uint32_t {
     E_RANGE = 1u, E_NOTPERM = 2u, E_DUP = 4u, E_NONCANON = 8u, E_OVERFLOW = 16u,
     E_TIMEOUT = 32u, E_CAPACITY = 64u,
 };
-enum : uint32_t { F_NOT_MONOTONE = 1u };
+enum : uint32_t { F_NOT_MONOTONE = 1u, F_NOT_RANGE = 2u };   // F_NOT_RANGE: J is not J[0] + (0, 1, 2, ...)
 
 enum { BIN_THREAD = 0, BIN_WAVE = 1, BIN_BLOCK = 2, BIN_GLOBAL = 3, NBINS = 4 };
 constexpr int64_t THREAD_MAX = 16;     // rows sorted in registers by one lane

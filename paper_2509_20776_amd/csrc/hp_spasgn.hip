@@ -32,6 +32,8 @@ struct AsgLayout {
     int32_t *rowinv, *colinv, *cnt;
     uint8_t *force;
     uint32_t *lists;
+    int32_t *llist;        // rows of B whose A row is too long for the one-thread count
+    uint32_t *lcount;
 };
 
 AsgLayout asg_layout(Carve &c, int64_t m, int64_t n) {
@@ -43,6 +45,8 @@ AsgLayout asg_layout(Carve &c, int64_t m, int64_t n) {
     L.cnt = c.take<int32_t>(m + 1);
     L.force = c.take<uint8_t>(m + 16);
     L.lists = c.take<uint32_t>(seg_list_words(m));
+    L.llist = c.take<int32_t>(m + 1);
+    L.lcount = c.take<uint32_t>(64);
     return L;
 }
 
@@ -56,11 +60,17 @@ __global__ __launch_bounds__(256) void k_asg_inv(const int32_t *__restrict__ I, 
         if (r < 0 || r >= m) atomicOr(&hdr->err, E_RANGE);   // error path only
         else rowinv[r] = (int32_t)t;
     }
+    bool gap = false;
     if (t < nJ) {
         const int32_t c = J[t];
         if (c < 0 || c >= n) atomicOr(&hdr->err, E_RANGE);
         else colinv[c] = (int32_t)t;
+        gap = t + 1 < nJ && J[t + 1] != c + 1;
     }
+    // J a contiguous range? (then the merge maps B's columns without a
+    // lookup); the flag is read first so that few blocks write it
+    if (__syncthreads_or(gap) && threadIdx.x == 0 && !(ld_agent(&hdr->flags) & F_NOT_RANGE))
+        atomicOr(&hdr->flags, F_NOT_RANGE);
 }
 
 // A repeated index leaves one of its positions unrecorded.
@@ -90,6 +100,67 @@ __global__ __launch_bounds__(256) void k_asg_count_rest(const PT *__restrict__ a
     if (r >= m || rowinv[r] >= 0) return;
     cnt[r] = (int32_t)(arow[r + 1] - arow[r]);
     force[r] = 0;
+}
+
+// Count pass for the rows of B, 16 lanes per row i (row I[i] of A), four
+// rows per wavefront: the group loads B's row (<= 256 columns) into
+// registers with coalesced loads, then tests each of the <= 16 A columns
+// against it with one ballot.  Rows with longer A or B rows go to llist for
+// the one-wavefront count.
+constexpr int AS_G = 16;   // lanes per row; also the A and B/16 limits
+
+template <typename PT>
+__global__ __launch_bounds__(256) void k_asg_count_I(const PT *__restrict__ arow, const int32_t *__restrict__ acol,
+                                                    const PT *__restrict__ brow, const int32_t *__restrict__ bcol,
+                                                    const int32_t *__restrict__ I, int64_t nI,
+                                                    const int32_t *__restrict__ colinv, int64_t n, int op,
+                                                    int32_t *cnt, uint8_t *force, int32_t *llist, uint32_t *lcount,
+                                                    const DevHdr *hdr) {
+    if (hdr->err) return;
+    const int l = lane_id(), g = l / AS_G, x = l % AS_G;
+    const int64_t i = (int64_t)blockIdx.x * (256 / AS_G) + (threadIdx.x / WAVE) * (WAVE / AS_G) + g;
+    const bool valid = i < nI;
+    int64_t r = 0, as = 0, La = 0, bs = 0, Lb = 0;
+    if (valid) {
+        r = I[i];
+        as = arow[r];
+        La = arow[r + 1] - as;
+        bs = brow[i];
+        Lb = brow[i + 1] - bs;
+    }
+    const bool small = valid && La <= AS_G && Lb <= AS_G * AS_G;
+    // rare: rows for the wavefront count (one atomic per wavefront)
+    const bool lng = valid && !small && x == 0;
+    const uint64_t lm = ballot(lng);
+    if (lm) {
+        uint32_t base = 0;
+        if (l == 0) base = atomicAdd(lcount, (uint32_t)__popcll(lm));
+        base = __shfl(base, 0, WAVE);
+        if (lng) llist[base + __popcll(lm & lanemask_lt())] = (int32_t)i;
+    }
+    int32_t bc[AS_G];
+#pragma unroll
+    for (int q = 0; q < AS_G; q++) {
+        const int64_t t = q * AS_G + x;
+        bc[q] = small && t < Lb ? bcol[bs + t] : INT32_MIN;
+    }
+    int32_t jb = -1;
+    if (small && x < La) jb = colinv[clampc(acol[as + x], n)];
+    const bool replace = op == HP_OP_REPLACE;
+    int nak = 0;
+    for (int a = 0; a < AS_G; a++) {
+        const int32_t ja = __shfl(jb, g * AS_G + a, WAVE);
+        bool hit = false;
+#pragma unroll
+        for (int q = 0; q < AS_G; q++) hit |= bc[q] == ja;
+        const bool ghit = ((ballot(hit) >> (g * AS_G)) & 0xffffull) != 0;
+        const bool kept = ja < 0 || (!replace && !ghit);
+        nak += (small && a < La && kept) ? 1 : 0;
+    }
+    if (small && x == 0) {
+        cnt[r] = (int32_t)(nak + Lb);
+        force[r] = La + Lb > AS_WCAP ? 1 : 0;
+    }
 }
 
 __device__ __forceinline__ uint32_t vadd(uint32_t a, uint32_t b) {
@@ -133,21 +204,16 @@ struct RowSmem {
     int32_t o[AS_WCAP];    // all output keys (unsorted case)
 };
 
-// One wavefront per row of B (row I[i] of A).  COUNT: write cnt and the
+// One wavefront for row i of B (row I[i] of A).  COUNT: write cnt and the
 // sort flag.  Otherwise write the merged row of C.
 template <typename PT, typename VT, bool COUNT>
-__global__ __launch_bounds__(256) void k_asg_rows_I(
-    const PT *__restrict__ arow, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
-    const PT *__restrict__ brow, const int32_t *__restrict__ bcol, const VT *__restrict__ bval,
-    const int32_t *__restrict__ I, int64_t nI, const int32_t *__restrict__ J, int64_t nJ,
+__device__ void asg_row_I(
+    int64_t i, RowSmem &sm, const PT *__restrict__ arow, const int32_t *__restrict__ acol,
+    const VT *__restrict__ aval, const PT *__restrict__ brow, const int32_t *__restrict__ bcol,
+    const VT *__restrict__ bval, const int32_t *__restrict__ I, const int32_t *__restrict__ J, int64_t nJ,
     const int32_t *__restrict__ colinv, int64_t n, int op, const PT *__restrict__ crow, int32_t *ccol,
-    VT *cval, int32_t *cnt, uint8_t *force, const DevHdr *hdr) {
-    __shared__ __align__(16) RowSmem sm_all[4];
-    if (hdr->err) return;
-    const int w = threadIdx.x / WAVE, l = lane_id();
-    const int64_t i = (int64_t)blockIdx.x * 4 + w;
-    if (i >= nI) return;
-    RowSmem &sm = sm_all[w];
+    VT *cval, int32_t *cnt, uint8_t *force) {
+    const int l = lane_id();
     const int64_t r = I[i];
     const int64_t as = arow[r], La = arow[r + 1] - as;
     const int64_t bs = brow[i], Lb = brow[i + 1] - bs;
@@ -293,6 +359,160 @@ __global__ __launch_bounds__(256) void k_asg_rows_I(
     }
 }
 
+template <typename PT, typename VT, bool COUNT>
+__global__ __launch_bounds__(256) void k_asg_rows_I(
+    const PT *__restrict__ arow, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
+    const PT *__restrict__ brow, const int32_t *__restrict__ bcol, const VT *__restrict__ bval,
+    const int32_t *__restrict__ I, int64_t nI, const int32_t *__restrict__ J, int64_t nJ,
+    const int32_t *__restrict__ colinv, int64_t n, int op, const PT *__restrict__ crow, int32_t *ccol,
+    VT *cval, int32_t *cnt, uint8_t *force, const DevHdr *hdr) {
+    __shared__ __align__(16) RowSmem sm_all[4];
+    if (hdr->err) return;
+    const int w = threadIdx.x / WAVE;
+    const int64_t i = (int64_t)blockIdx.x * 4 + w;
+    if (i >= nI) return;
+    asg_row_I<PT, VT, COUNT>(i, sm_all[w], arow, acol, aval, brow, bcol, bval, I, J, nJ, colinv, n, op, crow,
+                             ccol, cval, cnt, force);
+}
+
+// The rows the 16-lane kernels left in llist: persistent wavefronts, one
+// row at a time (count or merge).
+template <typename PT, typename VT, bool COUNT>
+__global__ __launch_bounds__(256) void k_asg_rows_list(
+    const PT *__restrict__ arow, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
+    const PT *__restrict__ brow, const int32_t *__restrict__ bcol, const VT *__restrict__ bval,
+    const int32_t *__restrict__ I, const int32_t *__restrict__ J, int64_t nJ,
+    const int32_t *__restrict__ colinv, int64_t n, int op, const PT *__restrict__ crow, int32_t *ccol,
+    VT *cval, int32_t *cnt, uint8_t *force, const int32_t *__restrict__ llist, const uint32_t *__restrict__ lcount,
+    const DevHdr *hdr) {
+    __shared__ __align__(16) RowSmem sm_all[4];
+    if (hdr->err) return;
+    const int w = threadIdx.x / WAVE;
+    const uint32_t nl = *lcount;
+    for (uint32_t t = blockIdx.x * 4 + w; t < nl; t += gridDim.x * 4)
+        asg_row_I<PT, VT, COUNT>(llist[t], sm_all[w], arow, acol, aval, brow, bcol, bval, I, J, nJ, colinv, n, op,
+                                 crow, ccol, cval, cnt, force);
+}
+
+// Merge pass, 16 lanes per row of B as in the count: the group holds B's
+// row in registers (columns, values, mapped columns J[b]) and A's <= 16
+// entries one per lane.  When the mapped columns increase along the row,
+// a B' entry goes to t + (kept A entries below it) and a kept A entry to
+// its rank among the kept ones + (B' entries below it); collisions drop
+// the A entry (PLUS adds its value to B's first).  Other rows go to llist.
+template <typename PT, typename VT>
+__global__ __launch_bounds__(256) void k_asg_merge_I(
+    const PT *__restrict__ arow, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
+    const PT *__restrict__ brow, const int32_t *__restrict__ bcol, const VT *__restrict__ bval,
+    const int32_t *__restrict__ I, int64_t nI, const int32_t *__restrict__ J, int64_t nJ,
+    const int32_t *__restrict__ colinv, int64_t n, int op, const PT *__restrict__ crow, int32_t *ccol, VT *cval,
+    int32_t *llist, uint32_t *lcount, int jrange, const DevHdr *hdr) {
+    if (hdr->err) return;
+    const int32_t j0 = nJ > 0 ? J[0] : 0;
+    const int l = lane_id(), g = l / AS_G, x = l % AS_G;
+    const int64_t i = (int64_t)blockIdx.x * (256 / AS_G) + (threadIdx.x / WAVE) * (WAVE / AS_G) + g;
+    const bool valid = i < nI;
+    int64_t r = 0, as = 0, La = 0, bs = 0, Lb = 0;
+    if (valid) {
+        r = I[i];
+        as = arow[r];
+        La = arow[r + 1] - as;
+        bs = brow[i];
+        Lb = brow[i + 1] - bs;
+    }
+    bool small = valid && La <= AS_G && Lb <= AS_G * AS_G;
+    int32_t bc[AS_G], bk[AS_G];
+    VT bv[AS_G];
+#pragma unroll
+    for (int q = 0; q < AS_G; q++) {
+        const int64_t t = q * AS_G + x;
+        const bool in = small && t < Lb;
+        bc[q] = in ? bcol[bs + t] : INT32_MIN;
+        bv[q] = in ? bval[bs + t] : VT(0);
+    }
+#pragma unroll
+    for (int q = 0; q < AS_G; q++)
+        bk[q] = bc[q] == INT32_MIN ? INT32_MAX : (jrange ? j0 + (int32_t)clampc(bc[q], nJ) : J[clampc(bc[q], nJ)]);
+    int32_t ak = INT32_MAX, jb = -1;
+    VT av = VT(0);
+    if (small && x < La) {
+        ak = acol[as + x];
+        av = aval[as + x];
+        jb = colinv[clampc(ak, n)];
+    }
+    // mapped columns increasing along the row? (t order: q major, lane minor)
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < AS_G; q++) {
+        const int32_t nx_same = __shfl_down(bk[q], 1, AS_G);
+        const int32_t nx_wrap = q + 1 < AS_G ? __shfl(bk[q + 1], g * AS_G, WAVE) : INT32_MAX;
+        const int32_t nxt = x < AS_G - 1 ? nx_same : nx_wrap;
+        const int64_t t = q * AS_G + x;
+        bad |= t + 1 < Lb && bk[q] >= nxt;
+    }
+    const bool inc = ((ballot(bad) >> (g * AS_G)) & 0xffffull) == 0;
+    const bool mine = small && inc;
+    const bool lng = valid && !mine && x == 0;
+    const uint64_t lm = ballot(lng);
+    if (lm) {
+        uint32_t base = 0;
+        if (l == 0) base = atomicAdd(lcount, (uint32_t)__popcll(lm));
+        base = __shfl(base, 0, WAVE);
+        if (lng) llist[base + __popcll(lm & lanemask_lt())] = (int32_t)i;
+    }
+    // collisions: drop the A entry; PLUS adds its value into B's
+    const bool replace = op == HP_OP_REPLACE, plus = op == HP_OP_PLUS;
+    uint32_t kept = 0;   // bit a: A entry a survives
+    for (int a = 0; a < AS_G; a++) {
+        const int32_t ja = __shfl(jb, g * AS_G + a, WAVE);
+        const VT va = __shfl(av, g * AS_G + a, WAVE);
+        bool hit = false;
+#pragma unroll
+        for (int q = 0; q < AS_G; q++) {
+            const bool h = ja >= 0 && bc[q] == ja;
+            hit |= h;
+            if (h && plus) bv[q] = vadd(va, bv[q]);
+        }
+        const bool ghit = ((ballot(hit) >> (g * AS_G)) & 0xffffull) != 0;
+        if (a < La && (ja < 0 || (!replace && !ghit))) kept |= 1u << a;
+    }
+    if (!mine) return;
+    const int64_t d = crow[r];
+    // B' entries
+    int32_t akr[AS_G];   // the group's kept A columns (INT32_MAX otherwise)
+#pragma unroll
+    for (int a = 0; a < AS_G; a++) {
+        const int32_t ka = __shfl(ak, g * AS_G + a, WAVE);
+        akr[a] = ((kept >> a) & 1u) ? ka : INT32_MAX;
+    }
+#pragma unroll
+    for (int q = 0; q < AS_G; q++) {
+        const int64_t t = q * AS_G + x;
+        int below = 0;
+#pragma unroll
+        for (int a = 0; a < AS_G; a++) below += akr[a] < bk[q];
+        if (t < Lb) {
+            ccol[d + t + below] = bk[q];
+            cval[d + t + below] = bv[q];
+        }
+    }
+    // kept A entries
+    for (int a = 0; a < AS_G; a++) {
+        if (!((kept >> a) & 1u)) continue;   // uniform within the group
+        const int32_t ka = __shfl(ak, g * AS_G + a, WAVE);
+        int cntb = 0;
+#pragma unroll
+        for (int q = 0; q < AS_G; q++) cntb += bk[q] < ka;
+#pragma unroll
+        for (int off = AS_G / 2; off > 0; off >>= 1) cntb += __shfl_xor(cntb, off, AS_G);
+        if (x == a) {
+            const int64_t pos = d + __popc(kept & ((1u << a) - 1u)) + cntb;
+            ccol[pos] = ka;
+            cval[pos] = av;
+        }
+    }
+}
+
 // Rows outside I: copy A's row to C's row, 64 rows per wavefront, entries
 // spread over lanes (coalesced reads and writes).
 template <typename PT, typename VT>
@@ -392,11 +612,17 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
         stage_mark(h, "asgn.tables");
         hipLaunchKernelGGL(k_asg_count_rest<PT>, dim3(gridn(m)), dim3(256), 0, s, (const PT *)A->rowptr, m,
                            L.rowinv, L.cnt, L.force, L.hdr);
-        if (nI > 0)
-            hipLaunchKernelGGL((k_asg_rows_I<PT, VT, true>), dim3(gridn(nI, 4)), dim3(256), 0, s,
-                               (const PT *)A->rowptr, A->col, (const VT *)A->val, (const PT *)B->rowptr, B->col,
-                               (const VT *)B->val, I, nI, J, nJ, L.colinv, n, (int)op, (const PT *)nullptr,
-                               (int32_t *)nullptr, (VT *)nullptr, L.cnt, L.force, L.hdr);
+        if (nI > 0) {
+            e = launch_clear_words(s, L.lcount, 1);
+            hipLaunchKernelGGL(k_asg_count_I<PT>, dim3(gridn(nI, 256 / AS_G)), dim3(256), 0, s, (const PT *)A->rowptr, A->col,
+                               (const PT *)B->rowptr, B->col, I, nI, L.colinv, n, (int)op, L.cnt, L.force, L.llist,
+                               L.lcount, L.hdr);
+            hipLaunchKernelGGL((k_asg_rows_list<PT, VT, true>), dim3((unsigned)std::min<int64_t>(gridn(nI, 4), 1024)),
+                               dim3(256), 0, s, (const PT *)A->rowptr, A->col, (const VT *)A->val,
+                               (const PT *)B->rowptr, B->col, (const VT *)B->val, I, J, nJ, L.colinv, n, (int)op,
+                               (const PT *)nullptr, (int32_t *)nullptr, (VT *)nullptr, L.cnt, L.force, L.llist,
+                               L.lcount, L.hdr);
+        }
         stage_mark(h, "asgn.count");
         e = hipGetLastError();
     }
@@ -420,6 +646,7 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
             info->class_elems[b] = (int64_t)H.bin_elems[b];
         }
         info->aux[0] = (int64_t)op;
+        info->aux[1] = (H.flags & F_NOT_RANGE) ? 0 : 1;   // J contiguous
         info->exec_ws_bytes = seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], H.bin_cnt[BIN_GLOBAL], vs, n);
     }
     return HP_OK;
@@ -456,11 +683,17 @@ hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
                        A->col, (const VT *)A->val, m, L.rowinv, (const PT *)C->rowptr, C->col, (VT *)C->val,
                        L.hdr);
     stage_mark(h, "asgn.copy");
-    if (nI > 0)
-        hipLaunchKernelGGL((k_asg_rows_I<PT, VT, false>), dim3(gridn(nI, 4)), dim3(256), 0, s,
+    if (nI > 0) {
+        launch_clear_words(s, L.lcount, 1);
+        hipLaunchKernelGGL((k_asg_merge_I<PT, VT>), dim3(gridn(nI, 256 / AS_G)), dim3(256), 0, s,
                            (const PT *)A->rowptr, A->col, (const VT *)A->val, (const PT *)B->rowptr, B->col,
                            (const VT *)B->val, I, nI, J, nJ, L.colinv, n, (int)op, (const PT *)C->rowptr, C->col,
-                           (VT *)C->val, L.cnt, L.force, L.hdr);
+                           (VT *)C->val, L.llist, L.lcount, (int)info->aux[1], L.hdr);
+        hipLaunchKernelGGL((k_asg_rows_list<PT, VT, false>), dim3((unsigned)std::min<int64_t>(gridn(nI, 4), 1024)),
+                           dim3(256), 0, s, (const PT *)A->rowptr, A->col, (const VT *)A->val, (const PT *)B->rowptr,
+                           B->col, (const VT *)B->val, I, J, nJ, L.colinv, n, (int)op, (const PT *)C->rowptr, C->col,
+                           (VT *)C->val, L.cnt, L.force, L.llist, L.lcount, L.hdr);
+    }
     stage_mark(h, "asgn.merge");
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
