@@ -19,6 +19,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -86,12 +87,48 @@ def spasgn_bytes(A, B, nI, nJ, nnz_out):
     return dict(total=4 * (nI + nJ) + rd + (A.nrows + 1) * sp + nnz_out * (4 + sv))
 
 
-def roofline(stages, name, bytes_per_launch):
+def _source_digest(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(stage, workload):
+    """HBM bytes per launch of `stage` on `workload` from a committed counter
+    summary in profiles/ (rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs,
+    scaled by the counters of a 1 GiB device copy).  None when there is no
+    summary or the kernel's sources changed since the counters were taken."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".txt"):
+            continue
+        with open(os.path.join(pdir, name)) as fh:
+            for line in fh:
+                if not line.startswith("traffic-json: "):
+                    continue
+                rec = json.loads(line[len("traffic-json: "):])
+                if rec.get("stage") != stage or rec.get("workload") != workload:
+                    continue
+                try:
+                    if _source_digest(rec["sources"]) != rec["sources_sha256_16"]:
+                        return None
+                except OSError:
+                    return None
+                return int(rec["traffic_bytes_per_launch"])
+    return None
+
+
+def roofline(stages, name, bytes_per_launch, workload=None):
     tot_ms, cnt = stages[name]
     avg_s = tot_ms / 1e3 / max(cnt, 1)
     ach = bytes_per_launch / avg_s / 1e9
     return {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
+            "traffic": measured_traffic(name, workload) if workload else None,
             "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": int(bytes_per_launch)}
 
 
@@ -127,8 +164,6 @@ def run_rmat_extract(hp, args):
     stages = h.stage_times()
     h.timing(False)
     b = spref_bytes(A, I.numel(), J.numel(), S, nnz_out)
-    dom = max(stages, key=lambda k: stages[k][0])
-    per = b.get(dom.split(".")[-1])
     res = dict(value=S / sec, unit="nnz/s", ms_per_step=sec * 1e3,
                config={"workload": "rmat-extract", "desc": "C = A(I,J); R-MAT scale %d ef16 symmetrised, "
                        "int32 CSR, fp32; I,J 25%% unsorted subsets with 1%% repeats" % args.scale,
@@ -137,10 +172,9 @@ def run_rmat_extract(hp, args):
                out_nnz_per_s=nnz_out / sec, algorithmic_GBps=b["total"] / sec / 1e9,
                hbm_frac_step=b["total"] / sec / 1e9 / HBM_PEAK_GBPS,
                stages_us={k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in stages.items()})
-    if per is not None:
-        res["roofline"] = roofline(stages, dom, per)
-    else:
-        res["roofline"] = roofline(stages, "spref.gather", b["gather"])
+    # the dominant kernel of the step is the gather (one launch per step; the
+    # sort stage is several smaller kernels)
+    res["roofline"] = roofline(stages, "spref.gather", b["gather"], "rmat-extract")
     if args.cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_spref(A, I, J, args.cpu_seconds)
     return res
@@ -191,7 +225,7 @@ def run_grid_permute(hp, args):
                        "fp64, independent random P, Q" % (args.side, args.side), "nrows": A.nrows, "nnz": A.nnz},
                algorithmic_GBps=b["total"] / sec / 1e9, hbm_frac_step=b["total"] / sec / 1e9 / HBM_PEAK_GBPS,
                stages_us={k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in stages.items()})
-    res["roofline"] = roofline(stages, "perm.fill_short", b["fill_short"])
+    res["roofline"] = roofline(stages, "perm.fill_short", b["fill_short"], "grid-permute")
     return res
 
 

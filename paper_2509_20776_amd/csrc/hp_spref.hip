@@ -246,9 +246,9 @@ hp_status_t spref_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     SprefLayout L = spref_layout(c, n, nI, nJ, A->nnz);
     hipStream_t s = h->stream;
     const int64_t ngb = (nI + 4 * WAVE - 1) / (4 * WAVE);
-    stage_begin(h);
     hipError_t e = hipSuccess;
     if (info->aux[1] > 0) e = launch_clear_words(s, L.cursor, (size_t)nI);
+    stage_begin(h);   // the gather stage is the gather kernel alone
     if (e == hipSuccess && info->nnz_out > 0) {
         hipLaunchKernelGGL((k_spref_gather<PT, VT>), dim3((unsigned)(ngb + SR_BIGBLOCKS)), dim3(SR_BLOCK), 0,
                            s, A->col, (const VT *)A->val, n, L.rs, L.rl, L.cp, nI, ngb, L.b2, L.jpos,
