@@ -98,11 +98,80 @@ __device__ __forceinline__ void lane_sort_row(const LD &ld, int64_t sb, int len,
     sort_store_regs<16, VT>(k, v, len, sorted, okey, oval);
 }
 
-// One wavefront sorts one row of <= 256 entries (up to 4 per lane): every
-// key's rank is the number of smaller keys, read 4 at a time from LDS.
+// Bitonic sorting network over 64*E 32-bit words held E per lane (element
+// e = l*E + q), ascending.  Partners e ^ j with j < E sit in the same lane;
+// larger j are lane distance j/E apart, swapped through cross-lane shuffles.
+template <int E>
+__device__ __forceinline__ void bitonic_wave(uint32_t (&x)[E]) {
+    const int l = lane_id();
+#pragma unroll
+    for (int k = 2; k <= WAVE * E; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j >= 1; j >>= 1) {
+            if (j < E) {
+#pragma unroll
+                for (int q = 0; q < E; q++) {
+                    if (q & j) continue;
+                    const bool asc = ((l * E + q) & k) == 0;
+                    const uint32_t a = x[q], b = x[q | j];
+                    const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+                    x[q] = asc ? lo : hi;
+                    x[q | j] = asc ? hi : lo;
+                }
+            } else {
+                // k > j >= E: the direction and the pair side are lane bits
+                const bool keep_min = (((l * E) & k) == 0) == (((l * E) & j) == 0);
+#pragma unroll
+                for (int q = 0; q < E; q++) {
+                    const uint32_t o = (uint32_t)__shfl_xor((int)x[q], j / E, WAVE);
+                    x[q] = keep_min ? (o < x[q] ? o : x[q]) : (o < x[q] ? x[q] : o);
+                }
+            }
+        }
+    }
+}
+
+// Row of len <= 64*E entries whose keys are below 2^24: each key is packed
+// with its position (key << 8 | position), the packed words are sorted by
+// the network (distinct, so the order is total), and every output slot
+// takes its value back from LDS by the position.  Padding words are all
+// ones and sort last (a real word equals it only when len == 256).
+template <int E, typename VT>
+__device__ __forceinline__ void wave_sort_packed(const int32_t (&mk)[4], const VT (&mv)[4], int len,
+                                                 int32_t *okey, VT *oval, uint32_t *s_k, VT *s_v) {
+    const int l = lane_id();
+    uint32_t x[E];
+#pragma unroll
+    for (int q = 0; q < E; q++) {
+        const int e = q * WAVE + l;
+        x[q] = 0xFFFFFFFFu;
+        if (e < len) {
+            x[q] = ((uint32_t)mk[q] << 8) | (uint32_t)e;
+            s_v[e] = mv[q];
+        }
+    }
+    bitonic_wave<E>(x);
+#pragma unroll
+    for (int q = 0; q < E; q++) s_k[l * E + q] = x[q];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < E; q++) {
+        const int e = q * WAVE + l;
+        if (e < len) {
+            const uint32_t w = s_k[e];
+            okey[e] = (int32_t)(w >> 8);
+            oval[e] = s_v[w & 255u];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// One wavefront sorts one row of <= 256 entries (up to 4 per lane).  Keys
+// below 2^24 go through the packed bitonic network; otherwise every key's
+// rank is the number of smaller keys, read 16 at a time from LDS.
 template <typename VT, typename LD>
 __device__ __forceinline__ void wave_sort_row(const LD &ld, int64_t sb, int len, bool sorted,
-                                              int32_t *okey, VT *oval, int32_t *s_k) {
+                                              int32_t *okey, VT *oval, int32_t *s_k, VT *s_v) {
     const int l = lane_id();
     int32_t mk[4];
     VT mv[4];
@@ -122,6 +191,16 @@ __device__ __forceinline__ void wave_sort_row(const LD &ld, int64_t sb, int len,
                 oval[x] = mv[q];
             }
         }
+        return;
+    }
+    bool wide = false;
+#pragma unroll
+    for (int q = 0; q < 4; q++) wide |= q * WAVE + l < len && (uint32_t)mk[q] >= (1u << 24);
+    if (ballot(wide) == 0) {
+        uint32_t *sk = reinterpret_cast<uint32_t *>(s_k);
+        if (len <= WAVE) wave_sort_packed<1, VT>(mk, mv, len, okey, oval, sk, s_v);
+        else if (len <= 2 * WAVE) wave_sort_packed<2, VT>(mk, mv, len, okey, oval, sk, s_v);
+        else wave_sort_packed<4, VT>(mk, mv, len, okey, oval, sk, s_v);
         return;
     }
     const int len16 = (len + 15) & ~15;
@@ -156,6 +235,7 @@ __device__ __forceinline__ void wave_sort_row(const LD &ld, int64_t sb, int len,
 // them in one buffer).
 struct alignas(16) SegSmemWave {
     int32_t k[4][WAVE_MAX];
+    uint64_t v[4][WAVE_MAX];   // values by source position (packed-key sort)
 };
 
 template <typename PT, typename VT, typename LD>
@@ -188,7 +268,8 @@ __device__ void seg_wave_tile(int64_t bid, SegSmemWave &sm, const PT *__restrict
     int64_t row = list[t];
     int64_t b = rowptr[row];
     int len = (int)(rowptr[row + 1] - b);
-    wave_sort_row<VT, LD>(ld, ld.base(row), len, sorted != 0, okey + b, oval + b, sm.k[w]);
+    wave_sort_row<VT, LD>(ld, ld.base(row), len, sorted != 0, okey + b, oval + b, sm.k[w],
+                          reinterpret_cast<VT *>(sm.v[w]));
 }
 
 template <typename PT, typename VT, typename LD>
@@ -230,7 +311,8 @@ __device__ void sort_small_tile(int64_t bid, SegSmemWave &sm, const PT *__restri
         const int64_t r = __shfl(row, src, WAVE);
         const int64_t rb = __shfl(b, src, WAVE);
         const int rl = __shfl(len, src, WAVE);
-        wave_sort_row<VT, LD>(ld, ld.base(r), rl, false, okey + rb, oval + rb, sm.k[w]);
+        wave_sort_row<VT, LD>(ld, ld.base(r), rl, false, okey + rb, oval + rb, sm.k[w],
+                              reinterpret_cast<VT *>(sm.v[w]));
     }
 }
 
