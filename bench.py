@@ -12,7 +12,8 @@ of the selected rows of A) per second over the timed steps.
 The same JSON line carries the roofline of the step's dominant kernel
 (algorithmic bytes per launch / its HIP-event-timed average duration), the
 oracle timed on a bounded sample of the same workload on the host cores,
-and secondary workloads (grid permutation, assignment) under "also".
+and secondary workloads (grid permutation, assignment, fused assignment and
+permutation, batched and served forms) under "also".
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -259,6 +260,50 @@ def run_grid_assign(hp, args):
     return res
 
 
+def run_grid_assign_permute(hp, args):
+    """Fused C = P (A (+) B') Q^T against the two separate calls, same inputs."""
+    w = synth.workload_grid(side=args.side, device="cuda")
+    A, B, I, J, p, q = w["A"], w["B"], w["I"], w["J"], w["p"], w["q"]
+    h = hp.handle(0)
+    C, ws, info = h.spasgn_permute_plan(A, B, I, J, p, q, "second")
+    h.spasgn_permute_exec(A, B, I, J, p, q, C, ws, info, "second")
+    nnz_out = C.nnz
+    del C
+    _, wsa, _ = h.spasgn_plan(A, B, I, J, "second")
+    _, wsp, _ = h.permute_plan(A, p, q)
+
+    def step():
+        C, _, inf = h.spasgn_permute_plan(A, B, I, J, p, q, "second", ws=ws)
+        h.spasgn_permute_exec(A, B, I, J, p, q, C, ws, inf, "second")
+
+    def step_separate():
+        X, _, inf = h.spasgn_plan(A, B, I, J, "second", ws=wsa)
+        h.spasgn_exec(A, B, I, J, X, wsa, inf, "second")
+        C, _, inf2 = h.permute_plan(X, p, q, ws=wsp)
+        h.permute_exec(X, p, q, C, wsp, inf2)
+
+    nsteps = max(3, args.steps // 4)
+    sec_sep = _timed(step_separate, nsteps, args.warmup)
+    for _ in range(args.warmup):
+        step()
+    _sync()
+    h.timing(True)
+    sec = _timed(step, nsteps, 0)
+    stages = h.stage_times()
+    h.timing(False)
+    b = spasgn_bytes(A, B, I.numel(), J.numel(), nnz_out)
+    b["total"] += 4 * (A.nrows + A.ncols)
+    res = dict(value=(A.nnz + B.nnz) / sec, unit="nnz/s", ms_per_step=sec * 1e3,
+               config={"workload": "grid-assign-permute",
+                       "desc": "P (A with A(I,J) = B) Q^T fused (select-second); %dx%d grid, int64 rowptr, "
+                       "fp64; I = J contiguous 10%% range; B density 1e-4; independent random P, Q"
+                       % (args.side, args.side), "nnz_A": A.nnz, "nnz_B": B.nnz, "nnz_out": nnz_out},
+               separate_ms_per_step=sec_sep * 1e3, speedup_vs_separate=sec_sep / sec,
+               algorithmic_GBps=b["total"] / sec / 1e9, hbm_frac_step=b["total"] / sec / 1e9 / HBM_PEAK_GBPS,
+               stages_us={k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in stages.items()})
+    return res
+
+
 def copy_calibration(mib):
     """A plain device-to-device copy of known size: under rocprofv3 --pmc its
     FETCH_SIZE / WRITE_SIZE per dispatch give the factor that turns counter
@@ -495,7 +540,8 @@ def run_served(hp, args):
 
 
 WORKLOADS = {"rmat-extract": run_rmat_extract, "grid-permute": run_grid_permute,
-             "grid-assign": run_grid_assign, "batched": run_batched, "served": run_served}
+             "grid-assign": run_grid_assign, "grid-assign-permute": run_grid_assign_permute,
+             "batched": run_batched, "served": run_served}
 
 
 def main():

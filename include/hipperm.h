@@ -169,6 +169,34 @@ hp_status_t hp_spasgn_exec(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, 
                            size_t ws_bytes, const hp_plan_info_t *info, void *xws,
                            size_t xws_bytes);
 
+/* ---- fused assign and permute: C = P (A (+) B') Q^T (Sec. 5.8, Sec. 5.9) -- */
+/* One pass that both assigns B into A(I, J) with operator op (as
+ * hp_spasgn) and permutes the result (as hp_permute):
+ *   C[i, j] = X[p[i], q[j]],  X = A with A(I, J) = B under op.
+ * The paper fuses the two by changing only where entries are sent; here the
+ * merge of each source row writes straight to output row pinv[r] with its
+ * columns mapped through qinv, and one sort pass orders every output row.
+ * The result is bit-identical to hp_spasgn followed by hp_permute.
+ * I, J, op, B: as hp_spasgn.  p, q: as hp_permute (q NULL = symmetric form,
+ * needs m == n; exec must get q NULL exactly when plan did).
+ * C: caller sets nrows=m, ncols=n, types equal to A's, rowptr (m+1); plan
+ * writes rowptr and nnz, exec writes col and val.  ws (size from
+ * hp_spasgn_permute_workspace, independent of q) must be kept unchanged
+ * from plan to exec; xws holds info->exec_ws_bytes.
+ * Errors: INDEX_RANGE, DUPLICATE_INDEX, NOT_PERMUTATION, SHAPE, OVERFLOW,
+ * WORKSPACE, ALIAS. */
+hp_status_t hp_spasgn_permute_workspace(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B,
+                                        size_t *bytes);
+hp_status_t hp_spasgn_permute_plan(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B,
+                                   const int32_t *I, const int32_t *J, hp_asgn_op_t op,
+                                   const int32_t *p, const int32_t *q, hp_csr_t *C, void *ws,
+                                   size_t ws_bytes, hp_plan_info_t *info);
+hp_status_t hp_spasgn_permute_exec(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B,
+                                   const int32_t *I, const int32_t *J, hp_asgn_op_t op,
+                                   const int32_t *p, const int32_t *q, hp_csr_t *C, void *ws,
+                                   size_t ws_bytes, const hp_plan_info_t *info, void *xws,
+                                   size_t xws_bytes);
+
 /* ---- batched form -------------------------------------------------------- */
 /* Many extraction (paper Sec. 2.2, Alg. 3) and permutation (Sec. 2.1,
  * Alg. 1) requests run together.  The plan half (J tables / inverse

@@ -19,6 +19,7 @@
 //                          unsorted and sorted by the segmented sort.
 #include "hp_internal.hpp"
 #include "hp_segsort.hpp"
+#include "hp_perm_tiles.hpp"
 
 using namespace hp;
 
@@ -30,14 +31,20 @@ struct AsgLayout {
     DevHdr *hdr;
     uint64_t *tiles;
     int32_t *rowinv, *colinv, *cnt;
+    int32_t *pinv, *qinv, *cnt_out;   // fused assign-and-permute only
+    uint8_t *fflag;                   // fused: output rows the sort pass must order
     uint8_t *force;
     uint32_t *lists;
     int32_t *llist;        // rows of B whose A row is too long for the one-thread count
     uint32_t *lcount;
 };
 
-AsgLayout asg_layout(Carve &c, int64_t m, int64_t n) {
+// The fused form always reserves qinv, so its workspace size does not depend
+// on q; the symmetric form (q null) then uses pinv for both maps.
+AsgLayout asg_layout(Carve &c, int64_t m, int64_t n, bool fused = false, bool sym = false) {
     AsgLayout L;
+    L.pinv = L.qinv = L.cnt_out = nullptr;
+    L.fflag = nullptr;
     L.hdr = c.take<DevHdr>(1);
     L.tiles = c.take<uint64_t>(scan_tiles(m));
     L.rowinv = c.take<int32_t>(m + 1);
@@ -47,7 +54,52 @@ AsgLayout asg_layout(Carve &c, int64_t m, int64_t n) {
     L.lists = c.take<uint32_t>(seg_list_words(m));
     L.llist = c.take<int32_t>(m + 1);
     L.lcount = c.take<uint32_t>(64);
+    if (fused) {
+        L.pinv = c.take<int32_t>(m + 1);
+        L.qinv = c.take<int32_t>(n + 1);
+        L.cnt_out = c.take<int32_t>(m + 1);
+        L.fflag = c.take<uint8_t>(m + 16);
+        if (sym) L.qinv = L.pinv;
+    }
     return L;
+}
+
+// Fused assign-and-permute tables: pinv[p[t]] = t, qinv[q[t]] = t.
+__global__ __launch_bounds__(256) void k_fused_perm(const int32_t *__restrict__ p, const int32_t *__restrict__ q,
+                                                   int64_t m, int64_t n, int32_t *pinv, int32_t *qinv,
+                                                   DevHdr *hdr) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < m) {
+        const int32_t r = p[t];
+        if (r < 0 || r >= m) atomicOr(&hdr->err, E_RANGE);   // error path only
+        else pinv[r] = (int32_t)t;
+    }
+    if (q && t < n) {
+        const int32_t c = q[t];
+        if (c < 0 || c >= n) atomicOr(&hdr->err, E_RANGE);
+        else qinv[c] = (int32_t)t;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fused_check(int64_t m, int64_t n, const int32_t *__restrict__ pinv,
+                                                    const int32_t *__restrict__ qinv, bool general, DevHdr *hdr) {
+    perm::perm_check_tile(blockIdx.x, m, n, pinv, qinv, general, hdr);
+}
+
+// Output row i holds row p[i] of the assignment result.  The sort pass
+// orders merged rows (rows of I) and copied rows longer than THREAD_MAX;
+// shorter copied rows are sorted by the copy itself.
+__global__ __launch_bounds__(256) void k_fused_counts(const int32_t *__restrict__ p, int64_t m,
+                                                     const int32_t *__restrict__ cnt,
+                                                     const int32_t *__restrict__ rowinv, int32_t *cnt_out,
+                                                     uint8_t *fflag, const DevHdr *hdr) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int32_t r = p[i];
+    const bool ok = r >= 0 && r < m && !hdr->err;
+    const int32_t c = ok ? cnt[r] : 0;
+    cnt_out[i] = c;
+    fflag[i] = ok && (rowinv[r] >= 0 || c > (int32_t)THREAD_MAX) ? 1 : 0;
 }
 
 __global__ __launch_bounds__(256) void k_asg_inv(const int32_t *__restrict__ I, int64_t nI,
@@ -196,6 +248,17 @@ __device__ __forceinline__ int count_less(const int32_t *a, int len, int32_t key
     return c;
 }
 
+// Where the rows of A (+) B' go: row r of the assignment result is written
+// to output row dest[r] with every column c stored as cmap[c] (the fused
+// assign-and-permute; null maps = the plain assignment, rows in place).
+struct OutMap {
+    const int32_t *dest;
+    const int32_t *cmap;
+    int64_t n;   // cmap entries; a column outside [0, n) is clamped, never read out of bounds
+    __device__ __forceinline__ int64_t row(int64_t r) const { return dest ? dest[r] : r; }
+    __device__ __forceinline__ int32_t col(int32_t c) const { return cmap ? cmap[clampc(c, n)] : c; }
+};
+
 struct RowSmem {
     int32_t a[AS_WCAP];    // A's columns
     int32_t b[AS_WCAP];    // B's columns (indices into J)
@@ -212,7 +275,7 @@ __device__ void asg_row_I(
     const VT *__restrict__ aval, const PT *__restrict__ brow, const int32_t *__restrict__ bcol,
     const VT *__restrict__ bval, const int32_t *__restrict__ I, const int32_t *__restrict__ J, int64_t nJ,
     const int32_t *__restrict__ colinv, int64_t n, int op, const PT *__restrict__ crow, int32_t *ccol,
-    VT *cval, int32_t *cnt, uint8_t *force) {
+    VT *cval, int32_t *cnt, uint8_t *force, OutMap om = OutMap{nullptr, nullptr, 0}) {
     const int l = lane_id();
     const int64_t r = I[i];
     const int64_t as = arow[r], La = arow[r + 1] - as;
@@ -274,7 +337,7 @@ __device__ void asg_row_I(
             const bool bad = t + 1 < Lb && sm.k[t] >= sm.k[t + 1];
             inc = inc && ballot(bad) == 0;
         }
-        const int64_t d = crow[r];
+        const int64_t d = crow[om.row(r)];
         const int L = nak + (int)Lb;
         if (!inc) {
             for (int x = l; x < nak; x += WAVE) sm.o[x] = sm.ak[x];
@@ -298,7 +361,7 @@ __device__ void asg_row_I(
                 int pos;
                 if (inc) pos = own + lower_bound_n(sm.k, Lb, key);
                 else pos = count_less(sm.o, L, key);
-                ccol[d + pos] = key;
+                ccol[d + pos] = om.col(key);
                 cval[d + pos] = aval[as + a];
             }
             rank += __popcll(msk);
@@ -312,7 +375,7 @@ __device__ void asg_row_I(
                 if (p >= 0) v = vadd(aval[as + p], v);
             }
             const int pos = inc ? t + lower_bound_n(sm.ak, nak, key) : count_less(sm.o, L, key);
-            ccol[d + pos] = key;
+            ccol[d + pos] = om.col(key);
             cval[d + pos] = v;
         }
         return;
@@ -333,8 +396,8 @@ __device__ void asg_row_I(
         }
         const uint64_t msk = ballot(kept);
         if (!COUNT && kept) {
-            const int64_t pos = (int64_t)crow[r] + nak + __popcll(msk & lanemask_lt());
-            ccol[pos] = ac[a];
+            const int64_t pos = (int64_t)crow[om.row(r)] + nak + __popcll(msk & lanemask_lt());
+            ccol[pos] = om.col(ac[a]);
             cval[pos] = aval[as + a];
         }
         nak += __popcll(msk);
@@ -353,8 +416,8 @@ __device__ void asg_row_I(
             const int64_t p = find_n(ac, La, key);
             if (p >= 0) v = vadd(aval[as + p], v);
         }
-        const int64_t pos = (int64_t)crow[r] + nak + t;
-        ccol[pos] = key;
+        const int64_t pos = (int64_t)crow[om.row(r)] + nak + t;
+        ccol[pos] = om.col(key);
         cval[pos] = v;
     }
 }
@@ -384,14 +447,14 @@ __global__ __launch_bounds__(256) void k_asg_rows_list(
     const int32_t *__restrict__ I, const int32_t *__restrict__ J, int64_t nJ,
     const int32_t *__restrict__ colinv, int64_t n, int op, const PT *__restrict__ crow, int32_t *ccol,
     VT *cval, int32_t *cnt, uint8_t *force, const int32_t *__restrict__ llist, const uint32_t *__restrict__ lcount,
-    const DevHdr *hdr) {
+    const DevHdr *hdr, OutMap om = OutMap{nullptr, nullptr, 0}) {
     __shared__ __align__(16) RowSmem sm_all[4];
     if (hdr->err) return;
     const int w = threadIdx.x / WAVE;
     const uint32_t nl = *lcount;
     for (uint32_t t = blockIdx.x * 4 + w; t < nl; t += gridDim.x * 4)
         asg_row_I<PT, VT, COUNT>(llist[t], sm_all[w], arow, acol, aval, brow, bcol, bval, I, J, nJ, colinv, n, op,
-                                 crow, ccol, cval, cnt, force);
+                                 crow, ccol, cval, cnt, force, om);
 }
 
 // Merge pass, 16 lanes per row of B as in the count: the group holds B's
@@ -406,7 +469,7 @@ __global__ __launch_bounds__(256) void k_asg_merge_I(
     const PT *__restrict__ brow, const int32_t *__restrict__ bcol, const VT *__restrict__ bval,
     const int32_t *__restrict__ I, int64_t nI, const int32_t *__restrict__ J, int64_t nJ,
     const int32_t *__restrict__ colinv, int64_t n, int op, const PT *__restrict__ crow, int32_t *ccol, VT *cval,
-    int32_t *llist, uint32_t *lcount, int jrange, const DevHdr *hdr) {
+    int32_t *llist, uint32_t *lcount, int jrange, const DevHdr *hdr, OutMap om = OutMap{nullptr, nullptr, 0}) {
     if (hdr->err) return;
     const int32_t j0 = nJ > 0 ? J[0] : 0;
     const int l = lane_id(), g = l / AS_G, x = l % AS_G;
@@ -477,7 +540,7 @@ __global__ __launch_bounds__(256) void k_asg_merge_I(
         if (a < La && (ja < 0 || (!replace && !ghit))) kept |= 1u << a;
     }
     if (!mine) return;
-    const int64_t d = crow[r];
+    const int64_t d = crow[om.row(r)];
     // B' entries
     int32_t akr[AS_G];   // the group's kept A columns (INT32_MAX otherwise)
 #pragma unroll
@@ -492,7 +555,7 @@ __global__ __launch_bounds__(256) void k_asg_merge_I(
 #pragma unroll
         for (int a = 0; a < AS_G; a++) below += akr[a] < bk[q];
         if (t < Lb) {
-            ccol[d + t + below] = bk[q];
+            ccol[d + t + below] = om.col(bk[q]);
             cval[d + t + below] = bv[q];
         }
     }
@@ -507,21 +570,36 @@ __global__ __launch_bounds__(256) void k_asg_merge_I(
         for (int off = AS_G / 2; off > 0; off >>= 1) cntb += __shfl_xor(cntb, off, AS_G);
         if (x == a) {
             const int64_t pos = d + __popc(kept & ((1u << a) - 1u)) + cntb;
-            ccol[pos] = ka;
+            ccol[pos] = om.col(ka);
             cval[pos] = av;
         }
     }
 }
 
+// Entry k of a row of A with its column mapped (fused form).
+template <typename VT>
+struct LoadMapped {
+    const int32_t *acol;
+    const VT *aval;
+    OutMap om;
+    __device__ __forceinline__ void get(int64_t b, int64_t k, int32_t &kk, VT &vv) const {
+        kk = om.col(acol[b + k]);
+        vv = aval[b + k];
+    }
+};
+
 // Rows outside I: copy A's row to C's row, 64 rows per wavefront, entries
-// spread over lanes (coalesced reads and writes).
-template <typename PT, typename VT>
+// spread over lanes (coalesced reads and writes).  SORT_SHORT (fused form):
+// a row of at most THREAD_MAX entries is instead mapped, sorted in its own
+// lane's registers and stored there; the flags leave it out of the sort pass.
+template <typename PT, typename VT, bool SORT_SHORT = false>
 __global__ __launch_bounds__(256) void k_asg_copy_rest(const PT *__restrict__ arow,
                                                       const int32_t *__restrict__ acol,
                                                       const VT *__restrict__ aval, int64_t m,
                                                       const int32_t *__restrict__ rowinv,
                                                       const PT *__restrict__ crow, int32_t *ccol,
-                                                      VT *cval, const DevHdr *hdr) {
+                                                      VT *cval, const DevHdr *hdr,
+                                                      OutMap om = OutMap{nullptr, nullptr, 0}) {
     __shared__ int32_t s_start[4][WAVE];
     __shared__ int64_t s_as[4][WAVE], s_cs[4][WAVE];
     if (hdr->err) return;
@@ -531,8 +609,13 @@ __global__ __launch_bounds__(256) void k_asg_copy_rest(const PT *__restrict__ ar
     if (r < m && rowinv[r] < 0) {
         const int64_t a = arow[r];
         len = (int)(arow[r + 1] - a);
+        const int64_t d = crow[om.row(r)];
+        if (SORT_SHORT && len <= (int)THREAD_MAX) {
+            if (len > 0) lane_sort_row<VT>(LoadMapped<VT>{acol, aval, om}, a, len, false, ccol + d, cval + d);
+            len = 0;
+        }
         s_as[w][l] = a;
-        s_cs[w][l] = crow[r];
+        s_cs[w][l] = d;
     }
     const int incl = wave_incl_scan(len);
     const int E = __shfl(incl, WAVE - 1, WAVE);
@@ -550,7 +633,7 @@ __global__ __launch_bounds__(256) void k_asg_copy_rest(const PT *__restrict__ ar
                     else hi = mid;
                 }
                 const int off = e - s_start[w][lo];
-                ccol[s_cs[w][lo] + off] = acol[s_as[w][lo] + off];
+                ccol[s_cs[w][lo] + off] = om.col(acol[s_as[w][lo] + off]);
                 cval[s_cs[w][lo] + off] = aval[s_as[w][lo] + off];
             }
         }
@@ -578,31 +661,46 @@ hp_status_t asg_check_args(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, 
 
 inline int gridn(int64_t n, int per = 256) { return (int)std::max<int64_t>(1, (n + per - 1) / per); }
 
+// Plan of the assignment; with fused, also of the permutation of its result
+// (C = P (A (+) B') Q^T, p non-null, q null for the symmetric form).
 template <typename PT, typename VT>
 hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, const int32_t *I,
                        const int32_t *J, hp_asgn_op_t op, hp_csr_t *C, void *ws, size_t ws_bytes,
-                       hp_plan_info_t *info) {
+                       hp_plan_info_t *info, bool fused = false, const int32_t *p = nullptr,
+                       const int32_t *q = nullptr) {
     const int64_t m = A->nrows, n = A->ncols, nI = B->nrows, nJ = B->ncols;
+    const bool sym = fused && q == nullptr;
     Carve need(nullptr);
-    asg_layout(need, m, n);
+    asg_layout(need, m, n, fused, sym);
     if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "spasgn plan workspace too small");
     const size_t ps = sizeof(PT), vs = sizeof(VT);
-    const void *ins[] = {A->rowptr, A->col, A->val, B->rowptr, B->col, B->val, I, J};
+    const void *ins[] = {A->rowptr, A->col, A->val, B->rowptr, B->col, B->val, I, J, p, q};
     const size_t insz[] = {(size_t)(m + 1) * ps, (size_t)A->nnz * 4, (size_t)A->nnz * vs,
                            (size_t)(nI + 1) * ps, (size_t)B->nnz * 4, (size_t)B->nnz * vs,
-                           (size_t)nI * 4, (size_t)nJ * 4};
-    for (int k = 0; k < 8; k++)
+                           (size_t)nI * 4, (size_t)nJ * 4, p ? (size_t)m * 4 : 0, q ? (size_t)n * 4 : 0};
+    for (int k = 0; k < 10; k++)
         if (overlaps(C->rowptr, (m + 1) * ps, ins[k], insz[k]) || overlaps(ws, ws_bytes, ins[k], insz[k]))
             return fail(h, HP_ERR_ALIAS, "output or workspace overlaps an input");
     if (overlaps(C->rowptr, (m + 1) * ps, ws, ws_bytes))
         return fail(h, HP_ERR_ALIAS, "C->rowptr overlaps the workspace");
     Carve c(ws);
-    AsgLayout L = asg_layout(c, m, n);
+    AsgLayout L = asg_layout(c, m, n, fused, sym);
     hipStream_t s = h->stream;
     stage_begin(h);
     hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, scan_tiles(m));
     if (e == hipSuccess) e = launch_fill_words(s, L.rowinv, (size_t)m, 0xFFFFFFFFu);
     if (e == hipSuccess) e = launch_fill_words(s, L.colinv, (size_t)n, 0xFFFFFFFFu);
+    if (fused) {
+        if (e == hipSuccess) e = launch_fill_words(s, L.pinv, (size_t)m, 0xFFFFFFFFu);
+        if (e == hipSuccess && !sym) e = launch_fill_words(s, L.qinv, (size_t)n, 0xFFFFFFFFu);
+        if (e == hipSuccess) {
+            const int64_t hi = std::max(m, n);
+            hipLaunchKernelGGL(k_fused_perm, dim3(gridn(hi)), dim3(256), 0, s, p, q, m, n, L.pinv, L.qinv, L.hdr);
+            hipLaunchKernelGGL(k_fused_check, dim3(gridn(hi)), dim3(256), 0, s, m, n, L.pinv, L.qinv, !sym,
+                               L.hdr);
+            e = hipGetLastError();
+        }
+    }
     if (e == hipSuccess) {
         const int64_t hi = std::max(nI, nJ);
         hipLaunchKernelGGL(k_asg_inv, dim3(gridn(hi)), dim3(256), 0, s, I, nI, J, nJ, m, n, L.rowinv,
@@ -626,7 +724,13 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
         stage_mark(h, "asgn.count");
         e = hipGetLastError();
     }
-    if (e == hipSuccess) {
+    if (e == hipSuccess && fused) {
+        // flagged output rows only: classification mode 4
+        hipLaunchKernelGGL(k_fused_counts, dim3(gridn(m)), dim3(256), 0, s, p, m, L.cnt, L.rowinv, L.cnt_out,
+                           L.fflag, L.hdr);
+        e = launch_scan_counts<PT>(s, L.cnt_out, (PT *)C->rowptr, m, L.hdr, 0, L.tiles, 4, L.lists, m, L.fflag);
+        stage_mark(h, "asgn.scan");
+    } else if (e == hipSuccess) {
         e = launch_scan_counts<PT>(s, L.cnt, (PT *)C->rowptr, m, L.hdr, 0, L.tiles, 4, L.lists, m, L.force);
         stage_mark(h, "asgn.scan");
     }
@@ -640,13 +744,14 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
     if (info) {
         *info = hp_plan_info_t{};
         info->nnz_out = C->nnz;
-        info->op = 3;
+        info->op = fused ? 4 : 3;
         for (int b = 0; b < NBINS; b++) {
             info->rows_sorted[b] = H.bin_cnt[b];
             info->class_elems[b] = (int64_t)H.bin_elems[b];
         }
         info->aux[0] = (int64_t)op;
         info->aux[1] = (H.flags & F_NOT_RANGE) ? 0 : 1;   // J contiguous
+        info->aux[2] = sym ? 1 : 0;
         info->exec_ws_bytes = seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], H.bin_cnt[BIN_GLOBAL], vs, n);
     }
     return HP_OK;
@@ -655,44 +760,57 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
 template <typename PT, typename VT>
 hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, const int32_t *I,
                        const int32_t *J, hp_asgn_op_t op, hp_csr_t *C, void *ws, size_t ws_bytes,
-                       const hp_plan_info_t *info, void *xws, size_t xws_bytes) {
+                       const hp_plan_info_t *info, void *xws, size_t xws_bytes, bool fused = false,
+                       const int32_t *p = nullptr, const int32_t *q = nullptr) {
     const int64_t m = A->nrows, n = A->ncols, nI = B->nrows, nJ = B->ncols;
+    const bool sym = fused && q == nullptr;
     Carve need(nullptr);
-    asg_layout(need, m, n);
+    asg_layout(need, m, n, fused, sym);
     if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "spasgn workspace too small");
-    if (!info || info->op != 3 || info->aux[0] != (int64_t)op)
-        return fail(h, HP_ERR_INVALID_ARG, "info is not from hp_spasgn_plan with this operator");
+    if (!info || info->op != (fused ? 4 : 3) || info->aux[0] != (int64_t)op)
+        return fail(h, HP_ERR_INVALID_ARG,
+                    fused ? "info is not from hp_spasgn_permute_plan with this operator"
+                          : "info is not from hp_spasgn_plan with this operator");
+    if (fused && info->aux[2] != (q ? 0 : 1))
+        return fail(h, HP_ERR_INVALID_ARG, "q differs in nullness from the plan");
     if (xws_bytes < info->exec_ws_bytes || (info->exec_ws_bytes && !xws))
         return fail(h, HP_ERR_WORKSPACE, "spasgn exec workspace too small");
     if (C->nnz != info->nnz_out) return fail(h, HP_ERR_INVALID_ARG, "C->nnz differs from the plan");
     if (C->nnz > 0 && (!C->col || !C->val)) return fail(h, HP_ERR_INVALID_ARG, "C->col/val is NULL");
     const size_t vs = sizeof(VT), ps = sizeof(PT);
-    const void *ins[] = {A->rowptr, A->col, A->val, B->rowptr, B->col, B->val, I, J, ws, xws, C->rowptr};
+    const void *ins[] = {A->rowptr, A->col, A->val, B->rowptr, B->col, B->val, I, J, ws, xws, C->rowptr, p, q};
     const size_t insz[] = {(size_t)(m + 1) * ps, (size_t)A->nnz * 4, (size_t)A->nnz * vs,
                            (size_t)(nI + 1) * ps, (size_t)B->nnz * 4, (size_t)B->nnz * vs,
-                           (size_t)nI * 4, (size_t)nJ * 4, ws_bytes, xws_bytes, (size_t)(m + 1) * ps};
-    for (int k = 0; k < 11; k++)
+                           (size_t)nI * 4, (size_t)nJ * 4, ws_bytes, xws_bytes, (size_t)(m + 1) * ps,
+                           p ? (size_t)m * 4 : 0, q ? (size_t)n * 4 : 0};
+    for (int k = 0; k < 13; k++)
         if (overlaps(C->col, (size_t)C->nnz * 4, ins[k], insz[k]) ||
             overlaps(C->val, (size_t)C->nnz * vs, ins[k], insz[k]))
             return fail(h, HP_ERR_ALIAS, "C->col/val overlaps an input or workspace");
     Carve c(ws);
-    AsgLayout L = asg_layout(c, m, n);
+    AsgLayout L = asg_layout(c, m, n, fused, sym);
+    const OutMap om{L.pinv, L.qinv, n};   // null maps for the plain assignment
     hipStream_t s = h->stream;
     stage_begin(h);
-    hipLaunchKernelGGL((k_asg_copy_rest<PT, VT>), dim3(gridn(m)), dim3(256), 0, s, (const PT *)A->rowptr,
-                       A->col, (const VT *)A->val, m, L.rowinv, (const PT *)C->rowptr, C->col, (VT *)C->val,
-                       L.hdr);
+    if (fused)
+        hipLaunchKernelGGL((k_asg_copy_rest<PT, VT, true>), dim3(gridn(m)), dim3(256), 0, s, (const PT *)A->rowptr,
+                           A->col, (const VT *)A->val, m, L.rowinv, (const PT *)C->rowptr, C->col, (VT *)C->val,
+                           L.hdr, om);
+    else
+        hipLaunchKernelGGL((k_asg_copy_rest<PT, VT>), dim3(gridn(m)), dim3(256), 0, s, (const PT *)A->rowptr,
+                           A->col, (const VT *)A->val, m, L.rowinv, (const PT *)C->rowptr, C->col, (VT *)C->val,
+                           L.hdr, om);
     stage_mark(h, "asgn.copy");
     if (nI > 0) {
         launch_clear_words(s, L.lcount, 1);
         hipLaunchKernelGGL((k_asg_merge_I<PT, VT>), dim3(gridn(nI, 256 / AS_G)), dim3(256), 0, s,
                            (const PT *)A->rowptr, A->col, (const VT *)A->val, (const PT *)B->rowptr, B->col,
                            (const VT *)B->val, I, nI, J, nJ, L.colinv, n, (int)op, (const PT *)C->rowptr, C->col,
-                           (VT *)C->val, L.llist, L.lcount, (int)info->aux[1], L.hdr);
+                           (VT *)C->val, L.llist, L.lcount, (int)info->aux[1], L.hdr, om);
         hipLaunchKernelGGL((k_asg_rows_list<PT, VT, false>), dim3((unsigned)std::min<int64_t>(gridn(nI, 4), 1024)),
                            dim3(256), 0, s, (const PT *)A->rowptr, A->col, (const VT *)A->val, (const PT *)B->rowptr,
                            B->col, (const VT *)B->val, I, J, nJ, L.colinv, n, (int)op, (const PT *)C->rowptr, C->col,
-                           (VT *)C->val, L.cnt, L.force, L.llist, L.lcount, L.hdr);
+                           (VT *)C->val, L.cnt, L.force, L.llist, L.lcount, L.hdr, om);
     }
     stage_mark(h, "asgn.merge");
     hipError_t e = hipGetLastError();
@@ -748,4 +866,60 @@ extern "C" hp_status_t hp_spasgn_exec(hp_handle_t h, const hp_csr_t *A, const hp
     if (!p64 && v64) return asg_exec_t<int32_t, uint64_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, xws, xws_bytes);
     if (p64 && !v64) return asg_exec_t<int64_t, uint32_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, xws, xws_bytes);
     return asg_exec_t<int64_t, uint64_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, xws, xws_bytes);
+}
+
+namespace {
+hp_status_t fused_check_args(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, const int32_t *I,
+                             const int32_t *J, hp_asgn_op_t op, const int32_t *p, const int32_t *q,
+                             const hp_csr_t *C) {
+    hp_status_t st = asg_check_args(h, A, B, I, J, op, C);
+    if (st) return st;
+    if (!q && A->nrows != A->ncols) return fail(h, HP_ERR_SHAPE, "symmetric permute needs a square A");
+    if (A->nrows > 0 && !p) return fail(h, HP_ERR_INVALID_ARG, "p is NULL");
+    return HP_OK;
+}
+}  // namespace
+
+extern "C" hp_status_t hp_spasgn_permute_workspace(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B,
+                                                   size_t *bytes) {
+    if (!h || !bytes) return HP_ERR_INVALID_ARG;
+    hp_status_t st = check_csr_args(h, A, "A");
+    if (st) return st;
+    (void)B;
+    Carve c(nullptr);
+    asg_layout(c, A->nrows, A->ncols, true, false);
+    *bytes = c.size();
+    return HP_OK;
+}
+
+extern "C" hp_status_t hp_spasgn_permute_plan(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B,
+                                              const int32_t *I, const int32_t *J, hp_asgn_op_t op,
+                                              const int32_t *p, const int32_t *q, hp_csr_t *C, void *ws,
+                                              size_t ws_bytes, hp_plan_info_t *info) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    hp_status_t st = fused_check_args(h, A, B, I, J, op, p, q, C);
+    if (st) return st;
+    const bool p64 = A->ptr_type == HP_IDX_I64, v64 = A->val_type == HP_VAL_F64;
+    if (!p64 && !v64) return asg_plan_t<int32_t, uint32_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, true, p, q);
+    if (!p64 && v64) return asg_plan_t<int32_t, uint64_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, true, p, q);
+    if (p64 && !v64) return asg_plan_t<int64_t, uint32_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, true, p, q);
+    return asg_plan_t<int64_t, uint64_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, true, p, q);
+}
+
+extern "C" hp_status_t hp_spasgn_permute_exec(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B,
+                                              const int32_t *I, const int32_t *J, hp_asgn_op_t op,
+                                              const int32_t *p, const int32_t *q, hp_csr_t *C, void *ws,
+                                              size_t ws_bytes, const hp_plan_info_t *info, void *xws,
+                                              size_t xws_bytes) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    hp_status_t st = fused_check_args(h, A, B, I, J, op, p, q, C);
+    if (st) return st;
+    const bool p64 = A->ptr_type == HP_IDX_I64, v64 = A->val_type == HP_VAL_F64;
+    if (!p64 && !v64)
+        return asg_exec_t<int32_t, uint32_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, xws, xws_bytes, true, p, q);
+    if (!p64 && v64)
+        return asg_exec_t<int32_t, uint64_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, xws, xws_bytes, true, p, q);
+    if (p64 && !v64)
+        return asg_exec_t<int64_t, uint32_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, xws, xws_bytes, true, p, q);
+    return asg_exec_t<int64_t, uint64_t>(h, A, B, I, J, op, C, ws, ws_bytes, info, xws, xws_bytes, true, p, q);
 }

@@ -117,6 +117,11 @@ hp_spasgn_workspace = _sig("hp_spasgn_workspace", [_P, _CSRP, _CSRP, ctypes.POIN
 hp_spasgn_plan = _sig("hp_spasgn_plan", [_P, _CSRP, _CSRP, _P, _P, ctypes.c_int, _CSRP, _P, _SZ, _INFOP])
 hp_spasgn_exec = _sig("hp_spasgn_exec", [_P, _CSRP, _CSRP, _P, _P, ctypes.c_int, _CSRP, _P, _SZ, _INFOP,
                                          _P, _SZ])
+hp_spasgn_permute_workspace = _sig("hp_spasgn_permute_workspace", [_P, _CSRP, _CSRP, ctypes.POINTER(_SZ)])
+hp_spasgn_permute_plan = _sig("hp_spasgn_permute_plan", [_P, _CSRP, _CSRP, _P, _P, ctypes.c_int, _P, _P, _CSRP,
+                                                         _P, _SZ, _INFOP])
+hp_spasgn_permute_exec = _sig("hp_spasgn_permute_exec", [_P, _CSRP, _CSRP, _P, _P, ctypes.c_int, _P, _P, _CSRP,
+                                                         _P, _SZ, _INFOP, _P, _SZ])
 hp_server_create = _sig("hp_server_create", [ctypes.POINTER(_P), ctypes.c_int, _P, _SZ,
                                              ctypes.POINTER(hp_server_config_t)])
 hp_server_submit = _sig("hp_server_submit", [_P, _REQP, ctypes.POINTER(ctypes.c_uint64)])
@@ -344,6 +349,43 @@ class Handle:
         C, ws, info = self.spasgn_plan(A, B, I, J, op)
         return self.spasgn_exec(A, B, I, J, C, ws, info, op)
 
+    # ---- fused assign + permute -------------------------------------------
+    def spasgn_permute_plan(self, A, B, I, J, p, q=None, op="second", ws=None):
+        """Plan C = P (A with A(I, J) = B) Q^T; returns (C with rowptr filled, ws, info)."""
+        self._stream()
+        if int(I.numel()) != B.nrows or int(J.numel()) != B.ncols:
+            raise HPError(6, "B must be |I| x |J|")
+        Ac, Bc = to_csr_t(A), to_csr_t(B)
+        need = _SZ(0)
+        self.check(hp_spasgn_permute_workspace(self.h, ctypes.byref(Ac), ctypes.byref(Bc), ctypes.byref(need)))
+        if ws is None or ws.numel() < need.value:
+            ws = self._alloc(need.value)
+        rowptr = torch.empty(A.nrows + 1, dtype=A.rowptr.dtype, device=A.rowptr.device)
+        Cc = hp_csr_t(A.nrows, A.ncols, 0, Ac.ptr_type, Ac.val_type, _dptr(rowptr), None, None)
+        info = hp_plan_info_t()
+        self.check(hp_spasgn_permute_plan(self.h, ctypes.byref(Ac), ctypes.byref(Bc), _idx(I), _idx(J),
+                                          self._op(op), _idx(p), _idx(q), ctypes.byref(Cc), _dptr(ws),
+                                          ws.numel(), ctypes.byref(info)))
+        C = CSR(A.nrows, A.ncols, rowptr, torch.empty(Cc.nnz, dtype=torch.int32, device=A.col.device),
+                torch.empty(Cc.nnz, dtype=A.val.dtype, device=A.val.device))
+        return C, ws, info
+
+    def spasgn_permute_exec(self, A, B, I, J, p, q, C, ws, info, op="second", xws=None):
+        self._stream()
+        Ac, Bc, Cc = to_csr_t(A), to_csr_t(B), to_csr_t(C)
+        if info.exec_ws_bytes and (xws is None or xws.numel() < info.exec_ws_bytes):
+            xws = self._alloc(info.exec_ws_bytes)
+        self.check(hp_spasgn_permute_exec(self.h, ctypes.byref(Ac), ctypes.byref(Bc), _idx(I), _idx(J),
+                                          self._op(op), _idx(p), _idx(q), ctypes.byref(Cc), _dptr(ws),
+                                          ws.numel(), ctypes.byref(info),
+                                          _dptr(xws) if xws is not None else None,
+                                          xws.numel() if xws is not None else 0))
+        return C
+
+    def spasgn_permute(self, A, B, I, J, p, q=None, op="second"):
+        C, ws, info = self.spasgn_permute_plan(A, B, I, J, p, q, op)
+        return self.spasgn_permute_exec(A, B, I, J, p, q, C, ws, info, op)
+
 
 KINDS = {"spref": 0, "permute": 1, "spasgn": 2}
 
@@ -529,3 +571,8 @@ def spref(A, I, J, device: int = 0) -> CSR:
 def spasgn(A, B, I, J, op="second", device: int = 0) -> CSR:
     """C = A with A(I, J) = B; op: "second" (overwrite), "plus" or "replace" (block)."""
     return handle(device).spasgn(A, B, I, J, op)
+
+
+def spasgn_permute(A, B, I, J, p, q=None, op="second", device: int = 0) -> CSR:
+    """C = P X Q^T with X = A after A(I, J) = B under op, in one fused pass."""
+    return handle(device).spasgn_permute(A, B, I, J, p, q, op)
