@@ -64,21 +64,14 @@ AsgLayout asg_layout(Carve &c, int64_t m, int64_t n, bool fused = false, bool sy
     return L;
 }
 
-// Fused assign-and-permute tables: pinv[p[t]] = t, qinv[q[t]] = t.
-__global__ __launch_bounds__(256) void k_fused_perm(const int32_t *__restrict__ p, const int32_t *__restrict__ q,
-                                                   int64_t m, int64_t n, int32_t *pinv, int32_t *qinv,
-                                                   DevHdr *hdr) {
+// Fused form, after the counts: the rows of I get the top bit of their
+// count (the sort pass must order them whatever their length).
+__global__ __launch_bounds__(256) void k_fused_mark(const int32_t *__restrict__ I, int64_t nI, int64_t m,
+                                                   int32_t *cnt, const DevHdr *hdr) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t < m) {
-        const int32_t r = p[t];
-        if (r < 0 || r >= m) atomicOr(&hdr->err, E_RANGE);   // error path only
-        else pinv[r] = (int32_t)t;
-    }
-    if (q && t < n) {
-        const int32_t c = q[t];
-        if (c < 0 || c >= n) atomicOr(&hdr->err, E_RANGE);
-        else qinv[c] = (int32_t)t;
-    }
+    if (t >= nI || hdr->err) return;
+    const int32_t r = I[t];
+    if (r >= 0 && r < m) cnt[r] = (int32_t)((uint32_t)cnt[r] | 0x80000000u);
 }
 
 __global__ __launch_bounds__(256) void k_fused_check(int64_t m, int64_t n, const int32_t *__restrict__ pinv,
@@ -86,20 +79,30 @@ __global__ __launch_bounds__(256) void k_fused_check(int64_t m, int64_t n, const
     perm::perm_check_tile(blockIdx.x, m, n, pinv, qinv, general, hdr);
 }
 
-// Output row i holds row p[i] of the assignment result.  The sort pass
-// orders merged rows (rows of I) and copied rows longer than THREAD_MAX;
-// shorter copied rows are sorted by the copy itself.
-__global__ __launch_bounds__(256) void k_fused_counts(const int32_t *__restrict__ p, int64_t m,
-                                                     const int32_t *__restrict__ cnt,
-                                                     const int32_t *__restrict__ rowinv, int32_t *cnt_out,
-                                                     uint8_t *fflag, const DevHdr *hdr) {
+// Output row i holds row p[i] of the assignment result: scatter the
+// inverse permutations (pinv[p[i]] = i, qinv[q[i]] = i) and take the row's
+// count.  The sort pass orders merged rows (rows of I) and copied rows
+// longer than THREAD_MAX; shorter copied rows are sorted by the copy itself.
+__global__ __launch_bounds__(256) void k_fused_counts(const int32_t *__restrict__ p, const int32_t *__restrict__ q,
+                                                     int64_t m, int64_t n, const int32_t *__restrict__ cnt,
+                                                     int32_t *pinv, int32_t *qinv, int32_t *cnt_out,
+                                                     uint8_t *fflag, DevHdr *hdr) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    const int32_t r = p[i];
-    const bool ok = r >= 0 && r < m && !hdr->err;
-    const int32_t c = ok ? cnt[r] : 0;
-    cnt_out[i] = c;
-    fflag[i] = ok && (rowinv[r] >= 0 || c > (int32_t)THREAD_MAX) ? 1 : 0;
+    if (i < m) {
+        const int32_t r = p[i];
+        const bool ok = r >= 0 && r < m;
+        if (!ok) atomicOr(&hdr->err, E_RANGE);   // error path only
+        else pinv[r] = (int32_t)i;
+        const uint32_t c = ok ? (uint32_t)cnt[r] : 0u;
+        const int32_t len = (int32_t)(c & 0x7FFFFFFFu);
+        cnt_out[i] = len;
+        fflag[i] = (c >> 31) || len > (int32_t)THREAD_MAX ? 1 : 0;
+    }
+    if (q && i < n) {
+        const int32_t c = q[i];
+        if (c < 0 || c >= n) atomicOr(&hdr->err, E_RANGE);
+        else qinv[c] = (int32_t)i;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_asg_inv(const int32_t *__restrict__ I, int64_t nI,
@@ -523,10 +526,14 @@ __global__ __launch_bounds__(256) void k_asg_merge_I(
         base = __shfl(base, 0, WAVE);
         if (lng) llist[base + __popcll(lm & lanemask_lt())] = (int32_t)i;
     }
-    // collisions: drop the A entry; PLUS adds its value into B's
+    // collisions: drop the A entry; PLUS adds its value into B's.  The loops
+    // over A entries stop at the longest A row among the wave's groups.
+    int amax = small ? (int)La : 0;
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) amax = max(amax, __shfl_xor(amax, off, WAVE));
     const bool replace = op == HP_OP_REPLACE, plus = op == HP_OP_PLUS;
     uint32_t kept = 0;   // bit a: A entry a survives
-    for (int a = 0; a < AS_G; a++) {
+    for (int a = 0; a < amax; a++) {
         const int32_t ja = __shfl(jb, g * AS_G + a, WAVE);
         const VT va = __shfl(av, g * AS_G + a, WAVE);
         bool hit = false;
@@ -541,26 +548,26 @@ __global__ __launch_bounds__(256) void k_asg_merge_I(
     }
     if (!mine) return;
     const int64_t d = crow[om.row(r)];
-    // B' entries
-    int32_t akr[AS_G];   // the group's kept A columns (INT32_MAX otherwise)
+    // B' entries, each shifted by the kept A entries with smaller columns
+    int below[AS_G];
 #pragma unroll
-    for (int a = 0; a < AS_G; a++) {
-        const int32_t ka = __shfl(ak, g * AS_G + a, WAVE);
-        akr[a] = ((kept >> a) & 1u) ? ka : INT32_MAX;
+    for (int q = 0; q < AS_G; q++) below[q] = 0;
+    for (int a = 0; a < amax; a++) {
+        int32_t ka = __shfl(ak, g * AS_G + a, WAVE);
+        if (!((kept >> a) & 1u)) ka = INT32_MAX;
+#pragma unroll
+        for (int q = 0; q < AS_G; q++) below[q] += ka < bk[q];
     }
 #pragma unroll
     for (int q = 0; q < AS_G; q++) {
         const int64_t t = q * AS_G + x;
-        int below = 0;
-#pragma unroll
-        for (int a = 0; a < AS_G; a++) below += akr[a] < bk[q];
         if (t < Lb) {
-            ccol[d + t + below] = om.col(bk[q]);
-            cval[d + t + below] = bv[q];
+            ccol[d + t + below[q]] = om.col(bk[q]);
+            cval[d + t + below[q]] = bv[q];
         }
     }
     // kept A entries
-    for (int a = 0; a < AS_G; a++) {
+    for (int a = 0; a < amax; a++) {
         if (!((kept >> a) & 1u)) continue;   // uniform within the group
         const int32_t ka = __shfl(ak, g * AS_G + a, WAVE);
         int cntb = 0;
@@ -693,13 +700,6 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
     if (fused) {
         if (e == hipSuccess) e = launch_fill_words(s, L.pinv, (size_t)m, 0xFFFFFFFFu);
         if (e == hipSuccess && !sym) e = launch_fill_words(s, L.qinv, (size_t)n, 0xFFFFFFFFu);
-        if (e == hipSuccess) {
-            const int64_t hi = std::max(m, n);
-            hipLaunchKernelGGL(k_fused_perm, dim3(gridn(hi)), dim3(256), 0, s, p, q, m, n, L.pinv, L.qinv, L.hdr);
-            hipLaunchKernelGGL(k_fused_check, dim3(gridn(hi)), dim3(256), 0, s, m, n, L.pinv, L.qinv, !sym,
-                               L.hdr);
-            e = hipGetLastError();
-        }
     }
     if (e == hipSuccess) {
         const int64_t hi = std::max(nI, nJ);
@@ -725,9 +725,13 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
         e = hipGetLastError();
     }
     if (e == hipSuccess && fused) {
+        const int64_t hi = std::max(m, n);
+        if (nI > 0)
+            hipLaunchKernelGGL(k_fused_mark, dim3(gridn(nI)), dim3(256), 0, s, I, nI, m, L.cnt, L.hdr);
+        hipLaunchKernelGGL(k_fused_counts, dim3(gridn(hi)), dim3(256), 0, s, p, sym ? nullptr : q, m, n, L.cnt,
+                           L.pinv, L.qinv, L.cnt_out, L.fflag, L.hdr);
+        hipLaunchKernelGGL(k_fused_check, dim3(gridn(hi)), dim3(256), 0, s, m, n, L.pinv, L.qinv, !sym, L.hdr);
         // flagged output rows only: classification mode 4
-        hipLaunchKernelGGL(k_fused_counts, dim3(gridn(m)), dim3(256), 0, s, p, m, L.cnt, L.rowinv, L.cnt_out,
-                           L.fflag, L.hdr);
         e = launch_scan_counts<PT>(s, L.cnt_out, (PT *)C->rowptr, m, L.hdr, 0, L.tiles, 4, L.lists, m, L.fflag);
         stage_mark(h, "asgn.scan");
     } else if (e == hipSuccess) {
