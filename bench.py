@@ -88,6 +88,18 @@ def spasgn_bytes(A, B, nI, nJ, nnz_out):
     return dict(total=4 * (nI + nJ) + rd + (A.nrows + 1) * sp + nnz_out * (4 + sv))
 
 
+def merge_bytes(A, B, I, nnz_out):
+    """Bytes the assignment merge of the rows of I must move once: I, A's row
+    bounds and entries of those rows, B, and the merged rows written."""
+    sp, sv = _esize(A.rowptr), _esize(A.val)
+    nI = I.numel()
+    Il = I.long()
+    na_i = int((A.rowptr[Il + 1] - A.rowptr[Il]).sum())
+    nout_i = nnz_out - (A.nnz - na_i)
+    return (4 * nI + 2 * nI * sp + na_i * (4 + sv) + (nI + 1) * sp + B.nnz * (4 + sv) + nI * sp
+            + nout_i * (4 + sv))
+
+
 def _source_digest(files):
     h = hashlib.sha256()
     for f in files:
@@ -257,6 +269,7 @@ def run_grid_assign(hp, args):
                        "nnz_A": A.nnz, "nnz_B": B.nnz, "nnz_out": nnz_out},
                algorithmic_GBps=b["total"] / sec / 1e9, hbm_frac_step=b["total"] / sec / 1e9 / HBM_PEAK_GBPS,
                stages_us={k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in stages.items()})
+    res["roofline"] = roofline(stages, "asgn.merge", merge_bytes(A, B, I, nnz_out), "grid-assign")
     return res
 
 
@@ -283,7 +296,7 @@ def run_grid_assign_permute(hp, args):
         h.permute_exec(X, p, q, C, wsp, inf2)
 
     nsteps = max(3, args.steps // 4)
-    sec_sep = _timed(step_separate, nsteps, args.warmup)
+    sec_sep = _timed(step_separate, nsteps, args.warmup) if args.fused_separate else None
     for _ in range(args.warmup):
         step()
     _sync()
@@ -298,10 +311,46 @@ def run_grid_assign_permute(hp, args):
                        "desc": "P (A with A(I,J) = B) Q^T fused (select-second); %dx%d grid, int64 rowptr, "
                        "fp64; I = J contiguous 10%% range; B density 1e-4; independent random P, Q"
                        % (args.side, args.side), "nnz_A": A.nnz, "nnz_B": B.nnz, "nnz_out": nnz_out},
-               separate_ms_per_step=sec_sep * 1e3, speedup_vs_separate=sec_sep / sec,
+               separate_ms_per_step=sec_sep * 1e3 if sec_sep else None,
+               speedup_vs_separate=sec_sep / sec if sec_sep else None,
                algorithmic_GBps=b["total"] / sec / 1e9, hbm_frac_step=b["total"] / sec / 1e9 / HBM_PEAK_GBPS,
                stages_us={k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in stages.items()})
+    res["roofline"] = roofline(stages, "asgn.merge", merge_bytes(A, B, I, nnz_out), "grid-assign-permute")
     return res
+
+
+def run_incremental(hp, args):
+    """Nine ~2% blocks assigned back into the ~80% part of an R-MAT graph, one
+    per step, with a symmetric random permutation fused into every step;
+    beside it the same steps as separate calls, assignment only, and one
+    permutation before the first step.  Load imbalance on an 8 x 8 grid."""
+    from paper_2509_20776_amd import incremental as inc
+    w = synth.workload_incremental(scale=args.incr_scale, device="cuda")
+    A = w["A"]
+    h = hp.handle(0)
+    sp = inc.split(h, A, w["I"], w["J"])
+    perms = [(p, None) for p in w["P"]]
+    inc.run(h, sp, "fused", perms, measure=False)      # warm-up
+    out = {}
+    for mode in inc.MODES:
+        r = inc.run(h, sp, mode, perms)
+        out[mode] = r
+        log(f"[bench] incremental {mode}: " + " ".join(f"{t:.2f}" for t in r.step_ms) + " ms; imbalance "
+            + " ".join(f"{x:.2f}" for x in r.imbalance))
+    f = out["fused"]
+    moved = sum(f.nnz[k] + sp.B[k].nnz for k in range(len(sp.B)))
+    sec = sum(f.step_ms) / 1e3
+    mean = lambda r: sum(r.step_ms) / len(r.step_ms)
+    return dict(value=moved / sec, unit="nnz/s", ms_per_step=mean(f),
+                config={"workload": "incremental", "desc": "R-MAT scale %d ef 16 symmetrised (int32, fp32); 9 "
+                        "blocks of ~2%% of the entries (disjoint 4%% row sets x random 50%% column sets) assigned "
+                        "back into the rest, one per step, select-second, symmetric random permutation per step"
+                        % args.incr_scale, "nnz_A": A.nnz, "nnz_large": sp.large.nnz,
+                        "nnz_blocks": [b.nnz for b in sp.B]},
+                step_ms={m: [round(t, 3) for t in r.step_ms] for m, r in out.items()},
+                ms_per_step_by_mode={m: round(mean(r), 3) for m, r in out.items()},
+                speedup_fused_vs_separate=mean(out["separate"]) / mean(f),
+                imbalance_8x8={m: [round(x, 3) for x in r.imbalance] for m, r in out.items()})
 
 
 def copy_calibration(mib):
@@ -541,6 +590,7 @@ def run_served(hp, args):
 
 WORKLOADS = {"rmat-extract": run_rmat_extract, "grid-permute": run_grid_permute,
              "grid-assign": run_grid_assign, "grid-assign-permute": run_grid_assign_permute,
+             "incremental": run_incremental,
              "batched": run_batched, "served": run_served}
 
 
@@ -552,6 +602,7 @@ def main():
     ap.add_argument("--workload", default="rmat-extract", choices=sorted(WORKLOADS))
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--side", type=int, default=4096)
+    ap.add_argument("--incr-scale", type=int, default=22)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-extras", dest="extras", action="store_false")
@@ -565,6 +616,8 @@ def main():
     ap.add_argument("--served-budget-gb", type=int, default=64)
     ap.add_argument("--served-max-batch", type=int, default=16)
     ap.add_argument("--no-served-plain", dest="served_plain", action="store_false")
+    ap.add_argument("--no-fused-separate", dest="fused_separate", action="store_false",
+                    help="grid-assign-permute: skip timing the two separate calls (for per-kernel profiles)")
     ap.add_argument("--copy-cal-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration under rocprofv3)")
     args = ap.parse_args()

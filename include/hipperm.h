@@ -197,6 +197,30 @@ hp_status_t hp_spasgn_permute_exec(hp_handle_t h, const hp_csr_t *A, const hp_cs
                                    size_t ws_bytes, const hp_plan_info_t *info, void *xws,
                                    size_t xws_bytes);
 
+/* ---- incremental-update bookkeeping (Sec. 5.9) ----------------------------- */
+/* The paper's incremental experiment rebuilds a graph from a large part by
+ * assigning small parts back, one per step, each fused with a random
+ * permutation, and tracks the load imbalance over a process grid.  These
+ * three non-blocking calls are what a driver of that workload needs between
+ * steps; all arrays are device int32 unless stated.
+ *
+ * hp_gather_index: out[t] = map[idx[t]] for t < n (relabels a part's
+ *   original indices, or composes permutations); an idx entry outside
+ *   [0, nmap) gives -1.  out may be idx itself (in place) but must not
+ *   overlap map (ALIAS).
+ * hp_invert_perm: pinv[p[t]] = t for t < n (p a permutation of [0, n);
+ *   entries outside [0, n) are skipped, other slots of pinv are left as
+ *   they were).  pinv must not overlap p (ALIAS).
+ * hp_block_nnz: counts[bi * gc + bj] (uint64, gr * gc entries, overwritten)
+ *   = stored entries of A in grid block (bi, bj), where row r belongs to
+ *   grid row r * gr / nrows and column c to grid column c * gc / ncols.
+ *   1 <= gr * gc <= 4096, gr, gc >= 1.  The load imbalance is the largest
+ *   count over the mean. */
+hp_status_t hp_gather_index(hp_handle_t h, const int32_t *map, int64_t nmap, const int32_t *idx,
+                            int64_t n, int32_t *out);
+hp_status_t hp_invert_perm(hp_handle_t h, const int32_t *p, int64_t n, int32_t *pinv);
+hp_status_t hp_block_nnz(hp_handle_t h, const hp_csr_t *A, int32_t gr, int32_t gc, uint64_t *counts);
+
 /* ---- batched form -------------------------------------------------------- */
 /* Many extraction (paper Sec. 2.2, Alg. 3) and permutation (Sec. 2.1,
  * Alg. 1) requests run together.  The plan half (J tables / inverse

@@ -1,0 +1,112 @@
+// Bookkeeping of the incremental-update workload (paper Sec. 5.9): a graph
+// is rebuilt from a large part by assigning small parts back, with a fresh
+// random permutation fused into every step.  Between steps the driver maps
+// the parts' original row and column labels to the current ones, composes
+// the permutations, and measures the load balance of the current matrix
+// over a process grid (the paper's load-imbalance metric: the largest block
+// nonzero count over the mean).  None of these calls blocks.
+#include "hp_internal.hpp"
+
+namespace hp {
+namespace {
+
+__global__ __launch_bounds__(256) void k_gather_index(const int32_t *__restrict__ map, int64_t nmap,
+                                                     const int32_t *idx, int64_t n, int32_t *out) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int32_t i = idx[t];
+    out[t] = (i >= 0 && i < nmap) ? map[i] : -1;
+}
+
+__global__ __launch_bounds__(256) void k_invert_perm(const int32_t *__restrict__ p, int64_t n,
+                                                    int32_t *__restrict__ pinv) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int32_t r = p[t];
+    if (r >= 0 && r < n) pinv[r] = (int32_t)t;
+}
+
+constexpr int BLK_MAX = 4096;   // grid blocks a histogram holds in LDS
+constexpr int ROWS_PER_WG = 1024;
+
+// Row r lies in grid row r*gr/m, column c in grid column c*gc/n.  Each
+// wavefront walks whole rows (lanes over the entries) into a workgroup
+// histogram in LDS, flushed once with 64-bit atomics.
+template <typename PT>
+__global__ __launch_bounds__(256) void k_block_nnz(const PT *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                                  int64_t m, int64_t n, int gr, int gc,
+                                                  unsigned long long *counts) {
+    __shared__ uint32_t hist[BLK_MAX];
+    const int nb = gr * gc;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) hist[k] = 0u;
+    __syncthreads();
+    const int w = threadIdx.x / WAVE, l = lane_id();
+    for (int64_t base = (int64_t)blockIdx.x * ROWS_PER_WG; base < m; base += (int64_t)gridDim.x * ROWS_PER_WG) {
+        const int64_t end = base + ROWS_PER_WG < m ? base + ROWS_PER_WG : m;
+        for (int64_t r = base + w; r < end; r += 4) {
+            const int64_t bi = r * gr / m;
+            const int64_t s = rowptr[r], e = rowptr[r + 1];
+            for (int64_t k = s + l; k < e; k += WAVE) {
+                const int64_t c = clampc(col[k], n);
+                atomicAdd(&hist[bi * gc + c * gc / n], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nb; k += blockDim.x)
+        if (hist[k]) atomicAdd(&counts[k], (unsigned long long)hist[k]);
+}
+
+inline int grid_of(int64_t n) { return (int)std::max<int64_t>(1, (n + 255) / 256); }
+
+}  // namespace
+}  // namespace hp
+
+using namespace hp;
+
+extern "C" hp_status_t hp_gather_index(hp_handle_t h, const int32_t *map, int64_t nmap, const int32_t *idx,
+                                       int64_t n, int32_t *out) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    if (n < 0 || nmap < 0) return fail(h, HP_ERR_INVALID_ARG, "negative length");
+    if (n == 0) return HP_OK;
+    if (!idx || !out || (nmap > 0 && !map)) return fail(h, HP_ERR_INVALID_ARG, "NULL array");
+    if (overlaps(out, (size_t)n * 4, map, (size_t)nmap * 4))
+        return fail(h, HP_ERR_ALIAS, "out overlaps map");
+    if (out != idx && overlaps(out, (size_t)n * 4, idx, (size_t)n * 4))
+        return fail(h, HP_ERR_ALIAS, "out partly overlaps idx");
+    hipLaunchKernelGGL(k_gather_index, dim3(grid_of(n)), dim3(256), 0, h->stream, map, nmap, idx, n, out);
+    return hip_check(h, hipGetLastError(), "gather_index");
+}
+
+extern "C" hp_status_t hp_invert_perm(hp_handle_t h, const int32_t *p, int64_t n, int32_t *pinv) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    if (n < 0) return fail(h, HP_ERR_INVALID_ARG, "negative length");
+    if (n == 0) return HP_OK;
+    if (!p || !pinv) return fail(h, HP_ERR_INVALID_ARG, "NULL array");
+    if (overlaps(p, (size_t)n * 4, pinv, (size_t)n * 4)) return fail(h, HP_ERR_ALIAS, "pinv overlaps p");
+    hipLaunchKernelGGL(k_invert_perm, dim3(grid_of(n)), dim3(256), 0, h->stream, p, n, pinv);
+    return hip_check(h, hipGetLastError(), "invert_perm");
+}
+
+extern "C" hp_status_t hp_block_nnz(hp_handle_t h, const hp_csr_t *A, int32_t gr, int32_t gc, uint64_t *counts) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    hp_status_t st = check_csr_args(h, A, "A");
+    if (st) return st;
+    if (gr < 1 || gc < 1 || (int64_t)gr * gc > BLK_MAX)
+        return fail(h, HP_ERR_INVALID_ARG, "grid must have 1..4096 blocks");
+    if (!counts) return fail(h, HP_ERR_INVALID_ARG, "counts is NULL");
+    hipError_t e = launch_clear_words(h->stream, counts, (size_t)gr * gc * 2);
+    const int64_t m = A->nrows;
+    if (e == hipSuccess && m > 0 && A->ncols > 0 && A->nnz > 0) {
+        const int grid = (int)std::min<int64_t>(2048, (m + ROWS_PER_WG - 1) / ROWS_PER_WG);
+        unsigned long long *cnt = reinterpret_cast<unsigned long long *>(counts);
+        if (A->ptr_type == HP_IDX_I64)
+            hipLaunchKernelGGL(k_block_nnz<int64_t>, dim3(grid), dim3(256), 0, h->stream,
+                               (const int64_t *)A->rowptr, A->col, m, A->ncols, gr, gc, cnt);
+        else
+            hipLaunchKernelGGL(k_block_nnz<int32_t>, dim3(grid), dim3(256), 0, h->stream,
+                               (const int32_t *)A->rowptr, A->col, m, A->ncols, gr, gc, cnt);
+        e = hipGetLastError();
+    }
+    return hip_check(h, e, "block_nnz");
+}

@@ -26,6 +26,12 @@ using namespace hp;
 namespace {
 
 constexpr int AS_WCAP = 256;   // A + B entries one wavefront resolves in LDS
+// Rows outside I longer than ASG_LONG are not copied by the wavefront that
+// owns their 64-row group (hub rows at neighbouring ids would serialise on
+// it) but by a workgroup of their own, and rows longer than ASG_HUGE by
+// every workgroup together.
+constexpr int64_t ASG_LONG = 512;
+constexpr int64_t ASG_HUGE = 65536;
 
 struct AsgLayout {
     DevHdr *hdr;
@@ -36,12 +42,14 @@ struct AsgLayout {
     uint8_t *force;
     uint32_t *lists;
     int32_t *llist;        // rows of B whose A row is too long for the one-thread count
-    uint32_t *lcount;
+    uint32_t *lcount;      // [0]: llist entries, [1]: rlong entries, [2]: rhuge entries
+    int32_t *rlong;        // rows outside I of ASG_LONG+1..ASG_HUGE entries (a workgroup each)
+    int32_t *rhuge;        // rows outside I longer than ASG_HUGE (the whole grid each)
 };
 
 // The fused form always reserves qinv, so its workspace size does not depend
 // on q; the symmetric form (q null) then uses pinv for both maps.
-AsgLayout asg_layout(Carve &c, int64_t m, int64_t n, bool fused = false, bool sym = false) {
+AsgLayout asg_layout(Carve &c, int64_t m, int64_t n, int64_t nnzA, bool fused = false, bool sym = false) {
     AsgLayout L;
     L.pinv = L.qinv = L.cnt_out = nullptr;
     L.fflag = nullptr;
@@ -54,6 +62,8 @@ AsgLayout asg_layout(Carve &c, int64_t m, int64_t n, bool fused = false, bool sy
     L.lists = c.take<uint32_t>(seg_list_words(m));
     L.llist = c.take<int32_t>(m + 1);
     L.lcount = c.take<uint32_t>(64);
+    L.rlong = c.take<int32_t>(std::min<int64_t>(m, nnzA / ASG_LONG) + 1);
+    L.rhuge = c.take<int32_t>(std::min<int64_t>(m, nnzA / ASG_HUGE) + 1);
     if (fused) {
         L.pinv = c.take<int32_t>(m + 1);
         L.qinv = c.take<int32_t>(n + 1);
@@ -149,12 +159,28 @@ __global__ __launch_bounds__(256) void k_asg_dup(const int32_t *__restrict__ I, 
 template <typename PT>
 __global__ __launch_bounds__(256) void k_asg_count_rest(const PT *__restrict__ arow, int64_t m,
                                                        const int32_t *__restrict__ rowinv, int32_t *cnt,
-                                                       uint8_t *force, const DevHdr *hdr) {
+                                                       uint8_t *force, int32_t *rlong, int32_t *rhuge,
+                                                       uint32_t *nlong, const DevHdr *hdr) {
     if (hdr->err) return;
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= m || rowinv[r] >= 0) return;
-    cnt[r] = (int32_t)(arow[r + 1] - arow[r]);
-    force[r] = 0;
+    const bool rest = r < m && rowinv[r] < 0;
+    const int64_t len = rest ? (int64_t)(arow[r + 1] - arow[r]) : 0;
+    if (rest) {
+        cnt[r] = (int32_t)len;
+        force[r] = 0;
+    }
+    // at most nnz(A) / ASG_LONG (ASG_HUGE) rows qualify: the lists cannot overflow
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        const bool lng = k == 0 ? (len > ASG_LONG && len <= ASG_HUGE) : len > ASG_HUGE;
+        const uint64_t lm = ballot(lng);
+        if (lm) {
+            uint32_t base = 0;
+            if (lane_id() == 0) base = atomicAdd(nlong + k, (uint32_t)__popcll(lm));
+            base = __shfl(base, 0, WAVE);
+            if (lng) (k == 0 ? rlong : rhuge)[base + __popcll(lm & lanemask_lt())] = (int32_t)r;
+        }
+    }
 }
 
 // Count pass for the rows of B, 16 lanes per row i (row I[i] of A), four
@@ -616,6 +642,7 @@ __global__ __launch_bounds__(256) void k_asg_copy_rest(const PT *__restrict__ ar
     if (r < m && rowinv[r] < 0) {
         const int64_t a = arow[r];
         len = (int)(arow[r + 1] - a);
+        if (len > ASG_LONG) len = 0;   // k_asg_copy_long
         const int64_t d = crow[om.row(r)];
         if (SORT_SHORT && len <= (int)THREAD_MAX) {
             if (len > 0) lane_sort_row<VT>(LoadMapped<VT>{acol, aval, om}, a, len, false, ccol + d, cval + d);
@@ -643,6 +670,38 @@ __global__ __launch_bounds__(256) void k_asg_copy_rest(const PT *__restrict__ ar
                 ccol[s_cs[w][lo] + off] = om.col(acol[s_as[w][lo] + off]);
                 cval[s_cs[w][lo] + off] = aval[s_as[w][lo] + off];
             }
+        }
+    }
+}
+
+// Rows outside I longer than ASG_LONG, coalesced reads and writes: a
+// workgroup per row of the rlong list, then every workgroup together on each
+// row of the rhuge list.
+template <typename PT, typename VT>
+__global__ __launch_bounds__(256) void k_asg_copy_long(const PT *__restrict__ arow, const int32_t *__restrict__ acol,
+                                                      const VT *__restrict__ aval, const int32_t *__restrict__ rlong,
+                                                      const int32_t *__restrict__ rhuge,
+                                                      const uint32_t *__restrict__ nlong, const PT *__restrict__ crow,
+                                                      int32_t *ccol, VT *cval, const DevHdr *hdr, OutMap om) {
+    if (hdr->err) return;
+    const uint32_t nl = nlong[0], nh = nlong[1];
+    for (uint32_t i = blockIdx.x; i < nl; i += gridDim.x) {
+        const int64_t r = rlong[i];
+        const int64_t a = arow[r], len = arow[r + 1] - a;
+        const int64_t d = crow[om.row(r)];
+        for (int64_t e = threadIdx.x; e < len; e += blockDim.x) {
+            ccol[d + e] = om.col(acol[a + e]);
+            cval[d + e] = aval[a + e];
+        }
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (uint32_t i = 0; i < nh; i++) {
+        const int64_t r = rhuge[i];
+        const int64_t a = arow[r], len = arow[r + 1] - a;
+        const int64_t d = crow[om.row(r)];
+        for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < len; e += stride) {
+            ccol[d + e] = om.col(acol[a + e]);
+            cval[d + e] = aval[a + e];
         }
     }
 }
@@ -678,7 +737,7 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
     const int64_t m = A->nrows, n = A->ncols, nI = B->nrows, nJ = B->ncols;
     const bool sym = fused && q == nullptr;
     Carve need(nullptr);
-    asg_layout(need, m, n, fused, sym);
+    asg_layout(need, m, n, A->nnz, fused, sym);
     if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "spasgn plan workspace too small");
     const size_t ps = sizeof(PT), vs = sizeof(VT);
     const void *ins[] = {A->rowptr, A->col, A->val, B->rowptr, B->col, B->val, I, J, p, q};
@@ -691,7 +750,7 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
     if (overlaps(C->rowptr, (m + 1) * ps, ws, ws_bytes))
         return fail(h, HP_ERR_ALIAS, "C->rowptr overlaps the workspace");
     Carve c(ws);
-    AsgLayout L = asg_layout(c, m, n, fused, sym);
+    AsgLayout L = asg_layout(c, m, n, A->nnz, fused, sym);
     hipStream_t s = h->stream;
     stage_begin(h);
     hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, scan_tiles(m));
@@ -708,10 +767,10 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
         hipLaunchKernelGGL(k_asg_dup, dim3(gridn(hi)), dim3(256), 0, s, I, nI, J, nJ, m, n, L.rowinv,
                            L.colinv, L.hdr);
         stage_mark(h, "asgn.tables");
+        e = launch_clear_words(s, L.lcount, 3);
         hipLaunchKernelGGL(k_asg_count_rest<PT>, dim3(gridn(m)), dim3(256), 0, s, (const PT *)A->rowptr, m,
-                           L.rowinv, L.cnt, L.force, L.hdr);
+                           L.rowinv, L.cnt, L.force, L.rlong, L.rhuge, L.lcount + 1, L.hdr);
         if (nI > 0) {
-            e = launch_clear_words(s, L.lcount, 1);
             hipLaunchKernelGGL(k_asg_count_I<PT>, dim3(gridn(nI, 256 / AS_G)), dim3(256), 0, s, (const PT *)A->rowptr, A->col,
                                (const PT *)B->rowptr, B->col, I, nI, L.colinv, n, (int)op, L.cnt, L.force, L.llist,
                                L.lcount, L.hdr);
@@ -769,7 +828,7 @@ hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
     const int64_t m = A->nrows, n = A->ncols, nI = B->nrows, nJ = B->ncols;
     const bool sym = fused && q == nullptr;
     Carve need(nullptr);
-    asg_layout(need, m, n, fused, sym);
+    asg_layout(need, m, n, A->nnz, fused, sym);
     if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "spasgn workspace too small");
     if (!info || info->op != (fused ? 4 : 3) || info->aux[0] != (int64_t)op)
         return fail(h, HP_ERR_INVALID_ARG,
@@ -792,7 +851,7 @@ hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
             overlaps(C->val, (size_t)C->nnz * vs, ins[k], insz[k]))
             return fail(h, HP_ERR_ALIAS, "C->col/val overlaps an input or workspace");
     Carve c(ws);
-    AsgLayout L = asg_layout(c, m, n, fused, sym);
+    AsgLayout L = asg_layout(c, m, n, A->nnz, fused, sym);
     const OutMap om{L.pinv, L.qinv, n};   // null maps for the plain assignment
     hipStream_t s = h->stream;
     stage_begin(h);
@@ -804,6 +863,9 @@ hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
         hipLaunchKernelGGL((k_asg_copy_rest<PT, VT>), dim3(gridn(m)), dim3(256), 0, s, (const PT *)A->rowptr,
                            A->col, (const VT *)A->val, m, L.rowinv, (const PT *)C->rowptr, C->col, (VT *)C->val,
                            L.hdr, om);
+    hipLaunchKernelGGL((k_asg_copy_long<PT, VT>), dim3(2048), dim3(256), 0, s, (const PT *)A->rowptr, A->col,
+                       (const VT *)A->val, L.rlong, L.rhuge, L.lcount + 1, (const PT *)C->rowptr, C->col,
+                       (VT *)C->val, L.hdr, om);
     stage_mark(h, "asgn.copy");
     if (nI > 0) {
         launch_clear_words(s, L.lcount, 1);
@@ -840,7 +902,7 @@ extern "C" hp_status_t hp_spasgn_workspace(hp_handle_t h, const hp_csr_t *A, con
     if (st) return st;
     (void)B;
     Carve c(nullptr);
-    asg_layout(c, A->nrows, A->ncols);
+    asg_layout(c, A->nrows, A->ncols, A->nnz);
     *bytes = c.size();
     return HP_OK;
 }
@@ -891,7 +953,7 @@ extern "C" hp_status_t hp_spasgn_permute_workspace(hp_handle_t h, const hp_csr_t
     if (st) return st;
     (void)B;
     Carve c(nullptr);
-    asg_layout(c, A->nrows, A->ncols, true, false);
+    asg_layout(c, A->nrows, A->ncols, A->nnz, true, false);
     *bytes = c.size();
     return HP_OK;
 }

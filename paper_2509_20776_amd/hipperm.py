@@ -122,6 +122,9 @@ hp_spasgn_permute_plan = _sig("hp_spasgn_permute_plan", [_P, _CSRP, _CSRP, _P, _
                                                          _P, _SZ, _INFOP])
 hp_spasgn_permute_exec = _sig("hp_spasgn_permute_exec", [_P, _CSRP, _CSRP, _P, _P, ctypes.c_int, _P, _P, _CSRP,
                                                          _P, _SZ, _INFOP, _P, _SZ])
+hp_gather_index = _sig("hp_gather_index", [_P, _P, _I64, _P, _I64, _P])
+hp_invert_perm = _sig("hp_invert_perm", [_P, _P, _I64, _P])
+hp_block_nnz = _sig("hp_block_nnz", [_P, _CSRP, ctypes.c_int32, ctypes.c_int32, _P])
 hp_server_create = _sig("hp_server_create", [ctypes.POINTER(_P), ctypes.c_int, _P, _SZ,
                                              ctypes.POINTER(hp_server_config_t)])
 hp_server_submit = _sig("hp_server_submit", [_P, _REQP, ctypes.POINTER(ctypes.c_uint64)])
@@ -348,6 +351,32 @@ class Handle:
     def spasgn(self, A, B, I, J, op="second"):
         C, ws, info = self.spasgn_plan(A, B, I, J, op)
         return self.spasgn_exec(A, B, I, J, C, ws, info, op)
+
+    # ---- incremental-update bookkeeping -------------------------------------
+    def gather_index(self, map_, idx, out=None):
+        """out[t] = map_[idx[t]] (-1 where idx[t] is outside map_)."""
+        self._stream()
+        if out is None:
+            out = torch.empty_like(idx)
+        self.check(hp_gather_index(self.h, _idx(map_), int(map_.numel()), _idx(idx), int(idx.numel()), _idx(out)))
+        return out
+
+    def invert_perm(self, p, out=None):
+        """pinv with pinv[p[t]] = t."""
+        self._stream()
+        if out is None:
+            out = torch.empty_like(p)
+        self.check(hp_invert_perm(self.h, _idx(p), int(p.numel()), _idx(out)))
+        return out
+
+    def block_nnz(self, A, gr, gc, out=None):
+        """Stored entries of A per block of a gr x gc grid (device int64, row-major)."""
+        self._stream()
+        if out is None:
+            out = torch.empty(gr * gc, dtype=torch.int64, device=A.col.device)
+        Ac = to_csr_t(A)
+        self.check(hp_block_nnz(self.h, ctypes.byref(Ac), gr, gc, _dptr(out)))
+        return out
 
     # ---- fused assign + permute -------------------------------------------
     def spasgn_permute_plan(self, A, B, I, J, p, q=None, op="second", ws=None):

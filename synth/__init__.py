@@ -318,6 +318,27 @@ def workload_grid(seed: int = 0, side: int = 4096, frac: float = 0.10, density: 
     return out
 
 
+def workload_incremental(seed: int = 0, scale: int = 22, edge_factor: int = 16, parts: int = 9,
+                         part_frac: float = 0.02, col_frac: float = 0.5, device="cpu"):
+    """Incremental update: R-MAT scale/ef symmetrised (int32 CSR, fp32, hubs at
+    low ids); `parts` disjoint random row sets of part_frac/col_frac of the
+    rows each, each with an independent random (unsorted, distinct) column
+    set of col_frac of the columns, so every block holds about part_frac of
+    the entries; one symmetric random permutation per step."""
+    A = rmat(scale, edge_factor, seed, "cfg-incr", symmetric=True,
+             ptr_dtype=torch.int32, val_dtype=torch.float32, device=device)
+    n = A.nrows
+    kr = max(1, int(n * part_frac / col_frac))
+    if kr * parts > n:
+        raise ValueError("row sets do not fit")
+    rows = randperm(stream_key(seed, "cfg-incr", "rows"), n, device)
+    I = [rows[k * kr:(k + 1) * kr].clone() for k in range(parts)]
+    J = [subset(stream_key(seed, "cfg-incr", "J", k), n, max(1, int(n * col_frac)), device=device)
+         for k in range(parts)]
+    P = [randperm(stream_key(seed, "cfg-incr", "p", k), n, device) for k in range(parts)]
+    return dict(A=A, I=I, J=J, P=P)
+
+
 def batched_pool(seed: int = 0, count: int = 64, scale_lo: int = 12, scale_hi: int = 20,
                  ef_lo: int = 8, ef_hi: int = 32, device="cpu"):
     """Pool of directed R-MAT matrices (int32 CSR, fp32) with scale and edge

@@ -146,3 +146,15 @@ def test_grid_full_size(hp):
     k = len(rows)
     exp = oracle.permute((k, A.ncols) + tuple(X), np.arange(k, dtype=np.int32), q)
     assert_same(rows_of(C, rows), exp, "sampled rows vs oracle")
+
+
+def test_rows_outside_I_of_every_copy_path(hp):
+    """Fused form over rows outside I of every copy class (see the plain test)."""
+    _say("fused: rows of 3 to 70000 entries outside I")
+    m, n = 48, 100_000
+    A = mixed_csr(71, m, n, [0, 3, 600, 70_000, 2_000, 1, 66_000, 513])
+    rng = np.random.default_rng(72)
+    I = _t(rng.choice(m, 6, replace=False))
+    J = _t(rng.choice(n, 3000, replace=False))
+    B = mixed_csr(73, 6, 3000, [0, 40, 700])
+    _check(hp, A, B, I, J, synth.randperm(74, m, "cuda"), synth.randperm(75, n, "cuda"), "plus", "copy paths")

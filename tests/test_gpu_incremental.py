@@ -1,0 +1,103 @@
+"""Incremental update driver: the fused and separate modes give the same
+matrices; after the last step the matrix is A relabelled by the composed
+permutations (the oracle's permutation of A), and A itself without
+permutations; the block counts behind the load-imbalance metric match a
+direct count."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests._gpu import assert_same, np_csr
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_20776_amd import hipperm, incremental
+    return hipperm, incremental
+
+
+def _block_counts(A, gr, gc):
+    rp, col, _ = np_csr(A)
+    rows = np.repeat(np.arange(A.nrows), np.diff(rp))
+    bi = rows * gr // A.nrows
+    bj = col.astype(np.int64) * gc // A.ncols
+    return np.bincount(bi * gc + bj, minlength=gr * gc)
+
+
+def test_helpers(env):
+    hp, _ = env
+    _say("incremental: gather_index, invert_perm, block_nnz")
+    h = hp.handle(0)
+    p = synth.randperm(1, 1000, "cuda")
+    pinv = h.invert_perm(p)
+    assert torch.equal(p[pinv.long()], torch.arange(1000, dtype=torch.int32, device="cuda"))
+    idx = torch.tensor([5, -1, 999, 1000, 0], dtype=torch.int32, device="cuda")
+    g = h.gather_index(p, idx)
+    pc = p.cpu().numpy()
+    assert g.cpu().tolist() == [pc[5], -1, pc[999], -1, pc[0]]
+    x = idx.clone()
+    h.gather_index(p, x, out=x)     # in place
+    assert x.cpu().tolist() == g.cpu().tolist()
+    A = synth.rmat(10, 8, 2, "inc-bn", symmetric=False, device="cuda")
+    for gr, gc in [(8, 8), (1, 1), (3, 5), (64, 64)]:
+        got = h.block_nnz(A, gr, gc).cpu().numpy()
+        assert np.array_equal(got, _block_counts(A, gr, gc)), (gr, gc)
+    with pytest.raises(hp.HPError):
+        h.block_nnz(A, 65, 64)
+
+
+@pytest.mark.parametrize("sym", [True, False])
+def test_modes_small(env, sym):
+    hp, inc = env
+    _say(f"incremental: R-MAT scale 10, 9 blocks, symmetric {sym}")
+    h = hp.handle(0)
+    w = synth.workload_incremental(seed=3, scale=10, device="cuda")
+    A = w["A"]
+    perms = [(p, None if sym else synth.randperm(synth.stream_key(7, "q", k), A.ncols, "cuda"))
+             for k, p in enumerate(w["P"])]
+    sp = inc.split(h, A, w["I"], w["J"])
+    assert sp.large.nnz + sum(b.nnz for b in sp.B) == A.nnz
+    fused = inc.run(h, sp, "fused", perms)
+    sep = inc.run(h, sp, "separate", perms)
+    assert_same(np_csr(fused.C), np_csr(sep.C), "fused vs separate")
+    assert fused.nnz == sep.nnz and fused.imbalance == sep.imbalance
+    assert fused.nnz[-1] == A.nnz
+    q = fused.q_total
+    assert_same(np_csr(fused.C), oracle.permute(A, fused.p_total, q), "final vs oracle permutation of A")
+    plain = inc.run(h, sp, "assign", perms)
+    assert_same(np_csr(plain.C), np_csr(A), "assign only restores A")
+    once = inc.run(h, sp, "perm-once", perms)
+    p0, q0 = perms[0]
+    assert_same(np_csr(once.C), oracle.permute(A, p0, q0), "one permutation then assignments")
+    # the metric: direct count of the final matrix
+    cnt = _block_counts(fused.C, 8, 8)
+    assert abs(fused.imbalance[-1] - cnt.max() / cnt.mean()) < 1e-9
+
+
+def test_full_size(env):
+    """R-MAT scale 22 as in the incremental workload: the fused steps end at
+    the GPU permutation of A by the composed permutation, bit for bit."""
+    hp, inc = env
+    _say("incremental: R-MAT scale 22, fused steps")
+    h = hp.handle(0)
+    w = synth.workload_incremental(scale=22, device="cuda")
+    A = w["A"]
+    sp = inc.split(h, A, w["I"], w["J"])
+    r = inc.run(h, sp, "fused", [(p, None) for p in w["P"]])
+    ref = h.permute(A, r.p_total, None)
+    torch.cuda.synchronize()
+    assert torch.equal(r.C.rowptr, ref.rowptr) and torch.equal(r.C.col, ref.col)
+    assert torch.equal(r.C.val.view(torch.int32), ref.val.view(torch.int32))
+    assert r.imbalance[-1] < 1.5 < r.imbalance[0]

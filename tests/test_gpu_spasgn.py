@@ -133,3 +133,17 @@ def test_grid_full_size_sampled(hp):
     X = hp.spref(R, I, J)
     assert torch.equal(X.rowptr, B.rowptr) and torch.equal(X.col, B.col)
     assert torch.equal(X.val.view(torch.int64), B.val.view(torch.int64))
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_rows_outside_I_of_every_copy_path(hp, op):
+    """Rows outside I of every length class of the copy: the 64-row wavefront
+    copy, a workgroup per row (over 512 entries) and the whole grid per row
+    (over 65536 entries), with long rows at neighbouring ids."""
+    m, n = 48, 100_000
+    A = mixed_csr(71, m, n, [0, 3, 600, 70_000, 2_000, 1, 66_000, 513])
+    rng = np.random.default_rng(72)
+    I = _t(rng.choice(m, 6, replace=False))
+    J = _t(rng.choice(n, 3000, replace=False))
+    B = mixed_csr(73, 6, 3000, [0, 40, 700])
+    assert_same(np_csr(hp.spasgn(A, B, I, J, op)), oracle.spasgn(A, B, I, J, op), f"copy paths {op}")
