@@ -38,7 +38,7 @@ struct AsgLayout {
     uint64_t *tiles;
     int32_t *rowinv, *colinv, *cnt;
     int32_t *pinv, *qinv, *cnt_out;   // fused assign-and-permute only
-    uint8_t *fflag;                   // fused: output rows the sort pass must order
+    uint8_t *fflag;                   // fused: 2 merged row, 1 copied row the sort pass pulls, 0 done
     uint8_t *force;
     uint32_t *lists;
     int32_t *llist;        // rows of B whose A row is too long for the one-thread count
@@ -91,8 +91,9 @@ __global__ __launch_bounds__(256) void k_fused_check(int64_t m, int64_t n, const
 
 // Output row i holds row p[i] of the assignment result: scatter the
 // inverse permutations (pinv[p[i]] = i, qinv[q[i]] = i) and take the row's
-// count.  The sort pass orders merged rows (rows of I) and copied rows
-// longer than THREAD_MAX; shorter copied rows are sorted by the copy itself.
+// count.  The sort pass orders the merged rows (rows of I, flag 2) in place
+// and fills rows outside I longer than THREAD_MAX (flag 1) straight from A;
+// shorter rows outside I are sorted by the copy itself.
 __global__ __launch_bounds__(256) void k_fused_counts(const int32_t *__restrict__ p, const int32_t *__restrict__ q,
                                                      int64_t m, int64_t n, const int32_t *__restrict__ cnt,
                                                      int32_t *pinv, int32_t *qinv, int32_t *cnt_out,
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(256) void k_fused_counts(const int32_t *__restrict_
         const uint32_t c = ok ? (uint32_t)cnt[r] : 0u;
         const int32_t len = (int32_t)(c & 0x7FFFFFFFu);
         cnt_out[i] = len;
-        fflag[i] = (c >> 31) || len > (int32_t)THREAD_MAX ? 1 : 0;
+        fflag[i] = (c >> 31) ? 2 : (len > (int32_t)THREAD_MAX ? 1 : 0);
     }
     if (q && i < n) {
         const int32_t c = q[i];
@@ -624,7 +625,8 @@ struct LoadMapped {
 // Rows outside I: copy A's row to C's row, 64 rows per wavefront, entries
 // spread over lanes (coalesced reads and writes).  SORT_SHORT (fused form):
 // a row of at most THREAD_MAX entries is instead mapped, sorted in its own
-// lane's registers and stored there; the flags leave it out of the sort pass.
+// lane's registers and stored there, and longer rows are left to the sort
+// pass, which reads them from A (LoadFused).
 template <typename PT, typename VT, bool SORT_SHORT = false>
 __global__ __launch_bounds__(256) void k_asg_copy_rest(const PT *__restrict__ arow,
                                                       const int32_t *__restrict__ acol,
@@ -644,8 +646,9 @@ __global__ __launch_bounds__(256) void k_asg_copy_rest(const PT *__restrict__ ar
         len = (int)(arow[r + 1] - a);
         if (len > ASG_LONG) len = 0;   // k_asg_copy_long
         const int64_t d = crow[om.row(r)];
-        if (SORT_SHORT && len <= (int)THREAD_MAX) {
-            if (len > 0) lane_sort_row<VT>(LoadMapped<VT>{acol, aval, om}, a, len, false, ccol + d, cval + d);
+        if (SORT_SHORT) {
+            if (len > 0 && len <= (int)THREAD_MAX)
+                lane_sort_row<VT>(LoadMapped<VT>{acol, aval, om}, a, len, false, ccol + d, cval + d);
             len = 0;
         }
         s_as[w][l] = a;
@@ -705,6 +708,37 @@ __global__ __launch_bounds__(256) void k_asg_copy_long(const PT *__restrict__ ar
         }
     }
 }
+
+// Sort-pass loader of the fused form: a merged row (flag 2) is read back
+// from C in place; any other listed row i is row p[i] of A with its columns
+// mapped through qinv (bit 62 of the base tells the two apart).
+template <typename PT, typename VT>
+struct LoadFused {
+    static constexpr int64_t IN_C = int64_t(1) << 62;
+    const PT *arow;
+    const int32_t *acol;
+    const VT *aval;
+    const int32_t *p;
+    const int32_t *qinv;
+    int64_t n;
+    const PT *crow;
+    const int32_t *ccol;
+    const VT *cval;
+    const uint8_t *fflag;
+    __device__ __forceinline__ int64_t base(int64_t row) const {
+        return fflag[row] == 2 ? ((int64_t)crow[row] | IN_C) : (int64_t)arow[p[row]];
+    }
+    __device__ __forceinline__ void get(int64_t b, int64_t k, int32_t &kk, VT &vv) const {
+        if (b & IN_C) {
+            b &= ~IN_C;
+            kk = ccol[b + k];
+            vv = cval[b + k];
+        } else {
+            kk = qinv[clampc(acol[b + k], n)];
+            vv = aval[b + k];
+        }
+    }
+};
 
 hp_status_t asg_check_args(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, const int32_t *I,
                            const int32_t *J, hp_asgn_op_t op, const hp_csr_t *C) {
@@ -863,9 +897,10 @@ hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
         hipLaunchKernelGGL((k_asg_copy_rest<PT, VT>), dim3(gridn(m)), dim3(256), 0, s, (const PT *)A->rowptr,
                            A->col, (const VT *)A->val, m, L.rowinv, (const PT *)C->rowptr, C->col, (VT *)C->val,
                            L.hdr, om);
-    hipLaunchKernelGGL((k_asg_copy_long<PT, VT>), dim3(2048), dim3(256), 0, s, (const PT *)A->rowptr, A->col,
-                       (const VT *)A->val, L.rlong, L.rhuge, L.lcount + 1, (const PT *)C->rowptr, C->col,
-                       (VT *)C->val, L.hdr, om);
+    if (!fused)   // the fused sort pass fills long rows outside I from A
+        hipLaunchKernelGGL((k_asg_copy_long<PT, VT>), dim3(2048), dim3(256), 0, s, (const PT *)A->rowptr, A->col,
+                           (const VT *)A->val, L.rlong, L.rhuge, L.lcount + 1, (const PT *)C->rowptr, C->col,
+                           (VT *)C->val, L.hdr, om);
     stage_mark(h, "asgn.copy");
     if (nI > 0) {
         launch_clear_words(s, L.lcount, 1);
@@ -883,10 +918,19 @@ hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
     if (e == hipSuccess) {
         uint32_t cnt[NBINS];
         for (int b = 0; b < NBINS; b++) cnt[b] = (uint32_t)info->rows_sorted[b];
-        LoadInPlace<PT, VT> ld{(const PT *)C->rowptr, C->col, (const VT *)C->val};
-        e = launch_seg_classes<PT, VT, LoadInPlace<PT, VT>>(s, (const PT *)C->rowptr, C->col, (VT *)C->val,
-                                                            L.lists, m, cnt, ld, false, n, true, xws,
-                                                            (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);
+        if (fused) {
+            LoadFused<PT, VT> ld{(const PT *)A->rowptr, A->col, (const VT *)A->val, p, L.qinv, n,
+                                 (const PT *)C->rowptr, C->col, (const VT *)C->val, L.fflag};
+            e = launch_seg_classes<PT, VT, LoadFused<PT, VT>>(s, (const PT *)C->rowptr, C->col, (VT *)C->val,
+                                                              L.lists, m, cnt, ld, false, n, true, xws,
+                                                              (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);
+        } else {
+            LoadInPlace<PT, VT> ld{(const PT *)C->rowptr, C->col, (const VT *)C->val};
+            e = launch_seg_classes<PT, VT, LoadInPlace<PT, VT>>(s, (const PT *)C->rowptr, C->col, (VT *)C->val,
+                                                                L.lists, m, cnt, ld, false, n, true, xws,
+                                                                (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr,
+                                                                true);
+        }
         stage_mark(h, "asgn.sort");
     }
     stage_end(h);
