@@ -65,7 +65,9 @@ def _bind(lib):
     lib.orc_spref.argtypes = [I64, I64, P, P, P, ctypes.c_int, P, I64, P, I64, P, I64, P, P, P, I64, P]
     lib.orc_spasgn.argtypes = [I64, I64, P, P, P, ctypes.c_int, I64, I64, P, P, P,
                                P, I64, P, I64, ctypes.c_int, P, I64, P, P, P, I64, P]
-    for f in (lib.orc_check_csr, lib.orc_permute, lib.orc_spref, lib.orc_spasgn):
+    lib.orc_spref_dcsc.argtypes = [I64, I64, I64, P, P, P, P, ctypes.c_int, P, I64, P, I64, P, I64, P, P, P,
+                                   I64, P]
+    for f in (lib.orc_check_csr, lib.orc_permute, lib.orc_spref, lib.orc_spasgn, lib.orc_spref_dcsc):
         f.restype = ctypes.c_int
     return lib
 
@@ -174,4 +176,39 @@ def spasgn(A, B, I, J, op="second", rows=None, lib=None):
         return lib.orc_spasgn(m, n, _ptr(rp), _ptr(c), _ptr(v), v.itemsize, bm, bn, _ptr(brp),
                               _ptr(bc), _ptr(bv), _ptr(I), len(I), _ptr(J), len(J), OPS[op],
                               _ptr(r), ns, _ptr(ptr), _ptr(oc), _ptr(ov), cap, ctypes.byref(need))
+    return _two_call(fn, nout, v.dtype)
+
+
+def _dcsc(A):
+    """(m, n, nzc, jc or None, colptr int64, row int32, val) as numpy arrays;
+    A has attributes nrows, ncols, jc (None for CSC), colptr, row, val, or is
+    that tuple."""
+    if hasattr(A, "colptr"):
+        m, n, jc, cp, r, v = A.nrows, A.ncols, A.jc, A.colptr, A.row, A.val
+    else:
+        m, n, jc, cp, r, v = A
+    conv = lambda t: t.cpu().numpy() if hasattr(t, "cpu") else np.asarray(t)
+    cp = np.ascontiguousarray(conv(cp), dtype=np.int64)
+    r = np.ascontiguousarray(conv(r), dtype=np.int32)
+    v = np.ascontiguousarray(conv(v))
+    jc = None if jc is None else np.ascontiguousarray(conv(jc), dtype=np.int32)
+    nzc = len(cp) - 1
+    return m, n, nzc, jc, cp, r, v
+
+
+def spref_dcsc(A, I, J, cols=None, lib=None):
+    """C = A(I, J) for column-compressed A (CSC, or DCSC with jc): returns
+    the CSC of C, (colptr int64 [len(cols)+1], row int32, val), for the
+    requested output columns (all when cols is None)."""
+    lib = lib or _load()
+    m, n, nzc, jc, cp, r, v = _dcsc(A)
+    I = _ivec(I)
+    J = _ivec(J)
+    c, ns = _rows(cols)
+    nout = ns if c is not None else len(J)
+
+    def fn(ptr, orow, ov, cap, need):
+        return lib.orc_spref_dcsc(m, n, nzc, _ptr(jc), _ptr(cp), _ptr(r), _ptr(v), v.itemsize, _ptr(I), len(I),
+                                  _ptr(J), len(J), _ptr(c), ns, _ptr(ptr), _ptr(orow), _ptr(ov), cap,
+                                  ctypes.byref(need))
     return _two_call(fn, nout, v.dtype)

@@ -11,6 +11,8 @@
  *
  *   permute   (Sec. 2.1):  A'[i,j] = A[pvec[i], qvec[j]]   for all i < m, j < n
  *   extract   (Sec. 2.2):  B[i,j]  = A[pvec[i], qvec[j]]   for all (i,j) in pvec x qvec
+ *             (also on column-compressed CSC/DCSC storage, walking the
+ *             selected columns as the appendix's Alg. 5 does)
  *   assign    (Sec. 2.3, and the Add step of Sec. 4.7):
  *                          B'[pvec[i], qvec[j]] = B[i,j]   for stored entries of B
  *                          A_new = A (+) B'   with a user-chosen addition
@@ -173,6 +175,79 @@ int orc_spref(int64_t m, int64_t n, const int64_t *rowptr, const int32_t *col,
                 copy_val(out_val, cnt, val, k, vsize);
             }
             cnt++;
+        }
+        out_ptr[s + 1] = cnt;
+    }
+    *need = cnt;
+    return ORC_OK;
+}
+
+/* ---- extraction on column-compressed storage (Sec. 2.2, appendix Alg. 5) */
+
+/* Stored column holding column id c: with jc (doubly compressed, Sec. 4.1)
+ * the k with jc[k] == c, by binary search over the nzc stored ids, or -1;
+ * without jc (plain CSC) every column is stored and k = c. */
+static int64_t find_stored_col(const int32_t *jc, int64_t nzc, int32_t c)
+{
+    if (!jc) return c;
+    int64_t lo = 0, hi = nzc - 1;
+    while (lo <= hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (jc[mid] == c) return mid;
+        if (jc[mid] < c) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+/* Position of row r among the row indices of stored column k, by binary
+ * search (the membership test of Alg. 5), or -1. */
+static int64_t find_in_col(const int64_t *colptr, const int32_t *row, int64_t k, int32_t r)
+{
+    int64_t lo = colptr[k], hi = colptr[k + 1] - 1;
+    while (lo <= hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (row[mid] == r) return mid;
+        if (row[mid] < r) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+/* C = A(I, J) with A and C column-compressed: for every selected column
+ * J[j] and every selected row I[i], C[i, j] = A[I[i], J[j]] when the binary
+ * search finds I[i] in that column.  Output in CSC: out_ptr over the output
+ * columns (all nJ, or the listed `cols`), out_row holds positions i in I,
+ * ascending within a column.  jc == NULL: A is plain CSC (colptr has n+1
+ * entries, nzc ignored). */
+int orc_spref_dcsc(int64_t m, int64_t n, int64_t nzc, const int32_t *jc, const int64_t *colptr,
+                   const int32_t *row, const void *val, int vsize, const int32_t *I, int64_t nI,
+                   const int32_t *J, int64_t nJ, const int64_t *cols, int64_t ns,
+                   int64_t *out_ptr, int32_t *out_row, void *out_val, int64_t cap, int64_t *need)
+{
+    if (vsize != 4 && vsize != 8) return ORC_INVALID_ARG;
+    if (nI < 0 || nJ < 0 || (jc && (nzc < 0 || nzc > n))) return ORC_INVALID_ARG;
+    int st = check_range(I, nI, m);
+    if (st != ORC_OK) return st;
+    st = check_range(J, nJ, n);
+    if (st != ORC_OK) return st;
+    if (!cols) ns = nJ;
+    int64_t cnt = 0;
+    out_ptr[0] = 0;
+    for (int64_t s = 0; s < ns; s++) {
+        int64_t j = cols ? cols[s] : s;
+        if (j < 0 || j >= nJ) return ORC_INDEX_RANGE;
+        int64_t k = find_stored_col(jc, nzc, J[j]);
+        if (k >= 0) {
+            for (int64_t i = 0; i < nI; i++) {
+                int64_t p = find_in_col(colptr, row, k, I[i]);
+                if (p < 0) continue;
+                if (cnt < cap) {
+                    out_row[cnt] = (int32_t)i;
+                    copy_val(out_val, cnt, val, p, vsize);
+                }
+                cnt++;
+            }
         }
         out_ptr[s + 1] = cnt;
     }

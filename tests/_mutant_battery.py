@@ -10,7 +10,7 @@ import numpy as np
 sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 import oracle  # noqa: E402
 from tests import test_oracle_pins as T  # noqa: E402
-from tests._util import assert_csr_equal, rand_csr  # noqa: E402
+from tests._util import assert_csr_equal, rand_csr, to_dcsc  # noqa: E402
 
 
 def battery(lib):
@@ -23,6 +23,9 @@ def battery(lib):
             I = rng.integers(0, m, 2 * m)
             J = rng.integers(0, n, 2 * n)
             assert_csr_equal(oracle.spref(A, I, J, lib=lib), T._brute_spref(A, I, J), "spref")
+            for compress in (True, False):
+                assert_csr_equal(oracle.spref_dcsc(to_dcsc(A, compress), I, J, lib=lib),
+                                 T._brute_spref_csc(A, I, J), "spref dcsc")
             for op in ("second", "plus", "replace"):
                 for _ in range(3):
                     A2, B, I2, J2 = T._rand_assign(rng, m, n, vd)

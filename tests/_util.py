@@ -100,3 +100,24 @@ def ints(xs):
 
 def floats(xs, dtype=np.float64):
     return np.array([float(x) for x in xs], dtype=dtype)
+
+
+def to_dcsc(A, compress=True):
+    """(m, n, jc or None, colptr, row, val) of a CSR triple: the CSC from
+    SciPy, and with compress the stored non-empty columns only (DCSC)."""
+    m, n = A[0], A[1]
+    S = to_scipy(A).tocsc()
+    S.sort_indices()
+    cp = np.asarray(S.indptr, dtype=np.int64)
+    if not compress:
+        return (m, n, None, cp, np.asarray(S.indices, dtype=np.int32), np.asarray(S.data))
+    nz = np.nonzero(np.diff(cp))[0]
+    cpz = np.concatenate([[0], np.cumsum(np.diff(cp)[nz])]).astype(np.int64)
+    return (m, n, nz.astype(np.int32), cpz, np.asarray(S.indices, dtype=np.int32), np.asarray(S.data))
+
+
+def csc_of(S):
+    """(colptr, row, val) of a SciPy matrix in CSC with sorted row indices."""
+    S = S.tocsc().copy()
+    S.sort_indices()
+    return (np.asarray(S.indptr, dtype=np.int64), np.asarray(S.indices, dtype=np.int32), np.asarray(S.data))

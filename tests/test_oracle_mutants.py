@@ -33,6 +33,10 @@ MUTANTS = {
     "asgn_replace_off_by_one": ("colpos[col[ka]] >= 0", "colpos[col[ka]] > 0"),
     "perm_no_dup_check": ("if (seen[v[i]]) { st = ORC_NOT_PERMUTATION; break; }", ""),
     "asgn_no_dup_check": ("if (seen[v[i]]) { st = ORC_DUPLICATE_INDEX; break; }", ""),
+    "dcsc_stored_col_unmapped": ("if (jc[mid] == c) return mid;", "if (jc[mid] == c) return c < nzc ? c : mid;"),
+    "dcsc_row_not_position": ("out_row[cnt] = (int32_t)i;", "out_row[cnt] = I[i];"),
+    "dcsc_search_skips_last": ("int64_t lo = colptr[k], hi = colptr[k + 1] - 1;",
+                               "int64_t lo = colptr[k], hi = colptr[k + 1] - 2;"),
 }
 
 

@@ -8,8 +8,8 @@ import numpy as np
 import pytest
 
 import oracle
-from tests._util import (assert_csr_equal, dense, floats, from_dense, from_scipy, ints,
-                         rand_csr, read_golden, selection, to_scipy)
+from tests._util import (assert_csr_equal, csc_of, dense, floats, from_dense, from_scipy, ints,
+                         rand_csr, read_golden, selection, to_dcsc, to_scipy)
 
 SHAPES = [(1, 1), (2, 3), (5, 5), (7, 4), (9, 13), (16, 16), (33, 20)]
 
@@ -310,3 +310,77 @@ def test_error_statuses():
     assert oracle.check_csr(A) == "OK"
     bad = (6, 5, A[2], A[3][::-1].copy(), A[4])
     assert oracle.check_csr(bad) != "OK"
+
+
+# ------------------------------------------- extraction on CSC / DCSC -------
+
+def _brute_spref_csc(A, I, J):
+    """CSC of C = A(I, J) from the dense matrix (fancy indexing of numpy)."""
+    D, M = dense(A)
+    Dc, Mc = D[np.ix_(I, J)].T, M[np.ix_(I, J)].T    # CSR of C^T is the CSC of C
+    return from_dense(Dc, Mc)
+
+
+def test_golden_spref_dcsc():
+    g = read_golden("spref_dcsc_3x5.txt")
+    m, n = ints(g["shape"])
+    A = (int(m), int(n), ints(g["jc"]).astype(np.int32), ints(g["colptr"]), ints(g["row"]).astype(np.int32),
+         floats(g["val"]))
+    got = oracle.spref_dcsc(A, ints(g["I"]), ints(g["J"]))
+    assert_csr_equal(got, (ints(g["expect_colptr"]), ints(g["expect_row"]), floats(g["expect_val"])),
+                     "golden spref dcsc")
+
+
+@pytest.mark.parametrize("shape,density", [((1, 1), 1.0), ((5, 7), 0.4), ((9, 13), 0.3), ((33, 20), 0.1),
+                                           ((40, 120), 0.01), ((16, 16), 0.0)])
+@pytest.mark.parametrize("vdtype", [np.float64, np.float32])
+def test_spref_dcsc_brute_scipy_csr_oracle(shape, density, vdtype):
+    """Against dense brute force, SciPy fancy indexing and the CSR oracle
+    (converted to CSC by SciPy); CSC and DCSC storage give the same C."""
+    rng = np.random.default_rng(shape[0] * 131 + shape[1])
+    m, n = shape
+    A = rand_csr(rng, m, n, density, vdtype)
+    I = rng.integers(0, m, 2 * m + 1)
+    J = rng.integers(0, n, 2 * n + 1)
+    exp = _brute_spref_csc(A, I, J)
+    for compress in (True, False):
+        got = oracle.spref_dcsc(to_dcsc(A, compress), I, J)
+        assert_csr_equal(got, exp, f"dcsc {compress} vs brute")
+    assert_csr_equal(got, csc_of(to_scipy(A)[I][:, J]), "vs scipy")
+    crow, ccol, cval = oracle.spref(A, I, J)
+    C = to_scipy((len(I), len(J), crow, ccol, cval))
+    assert_csr_equal(got, csc_of(C), "vs csr oracle")
+
+
+def test_spref_dcsc_special_cases():
+    rng = np.random.default_rng(5)
+    A = rand_csr(rng, 10, 50, 0.05)
+    Ad = to_dcsc(A)
+    assert len(Ad[2]) < 50                       # some columns are not stored
+    missing = np.setdiff1d(np.arange(50), Ad[2])[:4]
+    # only unstored columns selected: all output columns empty
+    cp, r, v = oracle.spref_dcsc(Ad, np.arange(10), missing)
+    assert list(cp) == [0] * (len(missing) + 1) and len(r) == 0
+    # empty I or J
+    cp, r, v = oracle.spref_dcsc(Ad, np.zeros(0, np.int64), np.arange(50))
+    assert len(cp) == 51 and cp[-1] == 0
+    cp, r, v = oracle.spref_dcsc(Ad, np.arange(10), np.zeros(0, np.int64))
+    assert list(cp) == [0]
+    # identity selection returns A's own CSC
+    assert_csr_equal(oracle.spref_dcsc(Ad, np.arange(10), np.arange(50)), csc_of(to_scipy(A)), "identity")
+    # sampled output columns equal the matching columns of the full result
+    I = rng.integers(0, 10, 12)
+    J = rng.integers(0, 50, 30)
+    full = oracle.spref_dcsc(Ad, I, J)
+    cols = np.array([0, 7, 29, 3])
+    part = oracle.spref_dcsc(Ad, I, J, cols=cols)
+    for s, j in enumerate(cols):
+        a, b = full[0][j], full[0][j + 1]
+        c, d = part[0][s], part[0][s + 1]
+        assert np.array_equal(full[1][a:b], part[1][c:d]) and np.array_equal(full[2][a:b], part[2][c:d])
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.spref_dcsc(Ad, np.array([10]), np.array([0]))
+    assert e.value.name == "INDEX_RANGE"
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.spref_dcsc(Ad, np.array([0]), np.array([50]))
+    assert e.value.name == "INDEX_RANGE"
