@@ -353,6 +353,52 @@ def run_incremental(hp, args):
                 imbalance_8x8={m: [round(x, 3) for x in r.imbalance] for m, r in out.items()})
 
 
+def run_hypersparse_extract(hp, args):
+    """C = A(I, J) on a hypersparse matrix in DCSC (appendix Alg. 5 walks the
+    selected columns): 2^26 x 2^26, 2^24 uniform nonzeros, I and J 25% with
+    1% repeats; beside it the same matrix in plain CSC."""
+    w = synth.workload_hypersparse(scale=args.hyper_scale, device="cuda")
+    A, I, J = w["A"], w["I"], w["J"]
+    h = hp.handle(0)
+    cnt = A.colptr[1:] - A.colptr[:-1]
+    cp = torch.zeros(A.ncols + 1, dtype=torch.int64, device="cuda")
+    cp.index_add_(0, A.jc.long() + 1, cnt)
+    Acsc = synth.DCSC(A.nrows, A.ncols, None, torch.cumsum(cp, 0), A.row, A.val)
+    full = torch.zeros(A.ncols, dtype=torch.int64, device="cuda")
+    full[A.jc.long()] = cnt
+    S = int(full[J.long()].sum())     # entries of the selected columns
+    out = {}
+    for name, M in (("dcsc", A), ("csc", Acsc)):
+        C, ws, info = h.spref_dcsc_plan(M, I, J)
+        h.spref_dcsc_exec(M, I, J, C, ws, info)
+        nnz_out = C.nnz
+        del C
+        xws = [None]
+
+        def step(M=M, ws=ws):
+            C, _, inf = h.spref_dcsc_plan(M, I, J, ws=ws)
+            if inf.exec_ws_bytes and (xws[0] is None or xws[0].numel() < inf.exec_ws_bytes):
+                xws[0] = torch.empty(inf.exec_ws_bytes, dtype=torch.uint8, device="cuda")
+            h.spref_dcsc_exec(M, I, J, C, ws, inf, xws[0])
+
+        for _ in range(args.warmup):
+            step()
+        _sync()
+        h.timing(True)
+        sec = _timed(step, args.steps, 0)
+        out[name] = (sec, h.stage_times(), nnz_out)
+        h.timing(False)
+    sec, stages, nnz_out = out["dcsc"]
+    return dict(value=S / sec, unit="nnz/s", ms_per_step=sec * 1e3,
+                config={"workload": "hypersparse-extract", "desc": "C = A(I,J), A in DCSC (int64 colptr, fp64), "
+                        "2^%d x 2^%d, %d uniform nonzeros (%d stored columns); I, J 25%% unsorted with 1%% repeats; "
+                        "C in CSC" % (args.hyper_scale, args.hyper_scale, A.nnz, A.jc.numel()),
+                        "scanned_nnz": S, "nnz_out": nnz_out},
+                csc_ms_per_step=out["csc"][0] * 1e3,
+                csc_stages_us={k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in out["csc"][1].items()},
+                stages_us={k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in stages.items()})
+
+
 def copy_calibration(mib):
     """A plain device-to-device copy of known size: under rocprofv3 --pmc its
     FETCH_SIZE / WRITE_SIZE per dispatch give the factor that turns counter
@@ -590,7 +636,7 @@ def run_served(hp, args):
 
 WORKLOADS = {"rmat-extract": run_rmat_extract, "grid-permute": run_grid_permute,
              "grid-assign": run_grid_assign, "grid-assign-permute": run_grid_assign_permute,
-             "incremental": run_incremental,
+             "incremental": run_incremental, "hypersparse-extract": run_hypersparse_extract,
              "batched": run_batched, "served": run_served}
 
 
@@ -603,6 +649,7 @@ def main():
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--side", type=int, default=4096)
     ap.add_argument("--incr-scale", type=int, default=22)
+    ap.add_argument("--hyper-scale", type=int, default=26)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-extras", dest="extras", action="store_false")

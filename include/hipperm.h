@@ -85,6 +85,25 @@ typedef struct {
     void *val;          /* device, nnz entries of val_type       */
 } hp_csr_t;
 
+/* Column-compressed matrix (Sec. 4.1 of the paper stores local blocks this
+ * way).  dcsc == 0: CSC, colptr holds ncols+1 entries; jc and nzc are
+ * ignored.  dcsc == 1: DCSC (doubly compressed, for hypersparse matrices):
+ * only the nzc stored columns are kept, jc[k] is the column id of stored
+ * column k (strictly increasing; jc may be NULL only when nzc == 0), colptr
+ * holds nzc+1 entries.  Row indices are strictly increasing within each
+ * column.  All arrays are device memory owned by the caller. */
+typedef struct {
+    int64_t nrows, ncols, nnz, nzc;
+    int32_t ptr_type;   /* hp_idx_t, of colptr  */
+    int32_t val_type;   /* hp_val_t             */
+    int32_t dcsc;       /* 0: CSC, 1: DCSC      */
+    int32_t pad;
+    const int32_t *jc;  /* nzc entries (DCSC)   */
+    void *colptr;       /* nzc+1 (DCSC) or ncols+1 (CSC) entries of ptr_type */
+    int32_t *row;       /* nnz entries          */
+    void *val;          /* nnz entries of val_type */
+} hp_dcsc_t;
+
 /* Filled by every plan call and passed unchanged to the matching exec call
  * (exec needs the class sizes to size its launches without a readback). */
 typedef struct {
@@ -153,6 +172,26 @@ hp_status_t hp_spref_plan(hp_handle_t h, const hp_csr_t *A, const int32_t *I, in
 hp_status_t hp_spref_exec(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int64_t nI,
                           const int32_t *J, int64_t nJ, hp_csr_t *C, void *ws, size_t ws_bytes,
                           const hp_plan_info_t *info, void *xws, size_t xws_bytes);
+
+/* ---- spref on column-compressed input (Sec. 2.2; Alg. 5 of the appendix) -- */
+/* C = A(I, J) for A in CSC or DCSC, with C returned in CSC: column j of C is
+ * column J[j] of A restricted to the rows of I, in the order of I.  This is
+ * the column-oriented form of the extraction (the appendix's algorithm
+ * walks the selected columns and looks each selected row up in them); a
+ * column of J that a DCSC matrix does not store gives an empty column of C.
+ * I, J: as hp_spref (repeats and any order allowed).
+ * C: caller sets nrows=nI, ncols=nJ, ptr_type/val_type equal to A's,
+ * dcsc=0, colptr (nJ+1 entries); plan writes colptr and nnz, exec writes
+ * row and val.  ws from hp_spref_dcsc_workspace, kept from plan to exec.
+ * Errors: INDEX_RANGE, OVERFLOW, SHAPE, WORKSPACE, ALIAS. */
+hp_status_t hp_spref_dcsc_workspace(hp_handle_t h, const hp_dcsc_t *A, int64_t nI, int64_t nJ,
+                                    size_t *bytes);
+hp_status_t hp_spref_dcsc_plan(hp_handle_t h, const hp_dcsc_t *A, const int32_t *I, int64_t nI,
+                               const int32_t *J, int64_t nJ, hp_dcsc_t *C, void *ws, size_t ws_bytes,
+                               hp_plan_info_t *info);
+hp_status_t hp_spref_dcsc_exec(hp_handle_t h, const hp_dcsc_t *A, const int32_t *I, int64_t nI,
+                               const int32_t *J, int64_t nJ, hp_dcsc_t *C, void *ws, size_t ws_bytes,
+                               const hp_plan_info_t *info, void *xws, size_t xws_bytes);
 
 /* ---- spasgn: C = A with A(I, J) = B (Sec. 2.3, Sec. 4.7) ------------------ */
 /* I, J: distinct indices (Sec. 2.3) of lengths B->nrows and B->ncols.

@@ -103,8 +103,49 @@ __global__ __launch_bounds__(256) void k_spref_jlink(const int32_t *__restrict__
 template <typename PT>
 __global__ __launch_bounds__(256) void k_spref_rows(const PT *__restrict__ arow, const int32_t *__restrict__ I,
                                                    int64_t nI, int64_t m, int64_t *rs, int32_t *rl, int32_t *ch,
-                                                   uint8_t *big, DevHdr *hdr) {
-    spref_rows_tile<PT>(blockIdx.x, arow, I, nI, m, rs, rl, ch, big, hdr);
+                                                   uint8_t *big, DevHdr *hdr, DcscIndex dx) {
+    spref_rows_tile<PT>(blockIdx.x, arow, I, nI, m, rs, rl, ch, big, hdr, dx);
+}
+
+// Stored rows per bucket of the doubly compressed index (ids outside
+// [0, m) are skipped: the input is then malformed, never read out of bounds).
+// jc is ascending, so equal buckets sit in runs of lanes: the first lane of
+// each run adds the run's length (one atomic per run, not per row).
+__global__ __launch_bounds__(256) void k_dcsc_buckets(const int32_t *__restrict__ jc, int64_t nzc, int64_t m,
+                                                     int shift, int32_t *cnt) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int l = lane_id();
+    const int32_t r = k < nzc ? jc[k] : -1;
+    const bool ok = r >= 0 && r < m;
+    const int64_t b = ok ? (int64_t)(r >> shift) : -1;
+    const int64_t bp = __shfl_up(b, 1, WAVE);
+    const bool head = ok && (l == 0 || bp != b);
+    const uint64_t heads = ballot(head) | ballot(!ok);   // a run also ends before an invalid lane
+    if (!head) return;
+    const uint64_t after = l == WAVE - 1 ? 0ull : heads >> (l + 1);
+    const int len = after ? __ffsll((long long)after) : WAVE - l;
+    atomicAdd(&cnt[b], len);
+}
+
+// Bucket index of a doubly compressed matrix with m row ids and nzc stored
+// rows: about four stored rows per bucket, so a lookup is one bucket read
+// and a short search; the index takes O(nzc) memory, never O(m).
+struct DcscPlan {
+    int shift = 0;
+    int64_t nb = 1;
+    size_t bytes = 0;
+};
+DcscPlan dcsc_plan(int64_t m, int64_t nzc) {
+    DcscPlan d;
+    const int64_t target = std::max<int64_t>(1, nzc / 4);
+    while (((m + (int64_t(1) << d.shift) - 1) >> d.shift) > target) d.shift++;
+    d.nb = std::max<int64_t>(1, (m + (int64_t(1) << d.shift) - 1) >> d.shift);
+    Carve c(nullptr);
+    c.take<int32_t>(d.nb + 1);
+    c.take<int32_t>(d.nb + 1);
+    c.take<uint64_t>(scan_tiles(d.nb));
+    d.bytes = c.size();
+    return d;
 }
 __global__ __launch_bounds__(SR_BLOCK) void k_spref_count(
     const int32_t *__restrict__ acol, int64_t n, const int64_t *__restrict__ rs,
@@ -146,19 +187,25 @@ hp_status_t spref_check_args(hp_handle_t h, const hp_csr_t *A, const int32_t *I,
 
 inline int grid1(int64_t n) { return (int)std::max<int64_t>(1, (n + 255) / 256); }
 
+// dcsc: A's rows are doubly compressed (only the nzc rows jc[k] stored, the
+// row pointers then have nzc+1 entries; the bucket index follows the
+// extraction's workspace).
 template <typename PT>
 hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int64_t nI,
                          const int32_t *J, int64_t nJ, hp_csr_t *C, void *ws, size_t ws_bytes,
-                         hp_plan_info_t *info) {
+                         hp_plan_info_t *info, bool dcsc = false, const int32_t *jc = nullptr, int64_t nzc = 0) {
     const int64_t m = A->nrows, n = A->ncols;
+    const int64_t nptr = dcsc ? nzc + 1 : m + 1;
     Carve need(nullptr);
     spref_layout(need, n, nI, nJ, A->nnz);
-    if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "spref plan workspace too small");
+    const size_t base = need.size();
+    const DcscPlan dp = dcsc ? dcsc_plan(m, nzc) : DcscPlan{};
+    if (!ws || ws_bytes < base + dp.bytes) return fail(h, HP_ERR_WORKSPACE, "spref plan workspace too small");
     const size_t ps = sizeof(PT), vs = val_size(A->val_type);
-    const void *ins[] = {A->rowptr, A->col, A->val, I, J};
-    const size_t insz[] = {(size_t)(m + 1) * ps, (size_t)A->nnz * 4, (size_t)A->nnz * vs,
-                           (size_t)nI * 4, (size_t)nJ * 4};
-    for (int k = 0; k < 5; k++)
+    const void *ins[] = {A->rowptr, A->col, A->val, I, J, jc};
+    const size_t insz[] = {(size_t)nptr * ps, (size_t)A->nnz * 4, (size_t)A->nnz * vs,
+                           (size_t)nI * 4, (size_t)nJ * 4, jc ? (size_t)nzc * 4 : 0};
+    for (int k = 0; k < 6; k++)
         if (overlaps(C->rowptr, (nI + 1) * ps, ins[k], insz[k]) || overlaps(ws, ws_bytes, ins[k], insz[k]))
             return fail(h, HP_ERR_ALIAS, "output or workspace overlaps an input");
     if (overlaps(C->rowptr, (nI + 1) * ps, ws, ws_bytes))
@@ -170,6 +217,20 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     stage_begin(h);
     hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, 2 * st);
     if (e == hipSuccess) e = launch_clear_words(s, L.zero, L.nzero);
+    DcscIndex dx{nullptr, 0, nullptr, 0};
+    if (dcsc && e == hipSuccess) {
+        Carve cx((char *)ws + base);
+        int32_t *bcnt = cx.take<int32_t>(dp.nb + 1);
+        int32_t *bstart = cx.take<int32_t>(dp.nb + 1);
+        uint64_t *btiles = cx.take<uint64_t>(scan_tiles(dp.nb));
+        e = launch_clear_words(s, bcnt, (size_t)dp.nb + 1);
+        if (e == hipSuccess) e = launch_clear_words(s, btiles, scan_tiles(dp.nb) * 2);
+        if (e == hipSuccess && nzc > 0)
+            hipLaunchKernelGGL(k_dcsc_buckets, dim3(grid1(nzc)), dim3(256), 0, s, jc, nzc, m, dp.shift, bcnt);
+        if (e == hipSuccess)
+            e = launch_scan_counts<int32_t>(s, bcnt, bstart, dp.nb, L.hdr, 2, btiles, 0, nullptr, 0);
+        dx = DcscIndex{jc, nzc, bstart, dp.shift};
+    }
     stage_mark(h, "spref.init");
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_spref_jscatter, dim3(grid1(nJ)), dim3(256), 0, s, J, nJ, n, L.mark, L.jpos,
@@ -180,7 +241,7 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
                            nJ, L.jpos, L.Dn, L.bm, L.dm, L.b2, (int64_t)L.nw);
         stage_mark(h, "spref.jtables");
         hipLaunchKernelGGL(k_spref_rows<PT>, dim3(grid1(nI)), dim3(256), 0, s, (const PT *)A->rowptr, I,
-                           nI, m, L.rs, L.rl, L.ch, L.big, L.hdr);
+                           nI, m, L.rs, L.rl, L.ch, L.big, L.hdr, dx);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = launch_scan_counts<int64_t>(s, L.ch, L.cp, nI, L.hdr, 0, L.tiles, 0, nullptr, 0);
@@ -223,8 +284,9 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
 template <typename PT, typename VT>
 hp_status_t spref_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int64_t nI,
                          const int32_t *J, int64_t nJ, hp_csr_t *C, void *ws, size_t ws_bytes,
-                         const hp_plan_info_t *info, void *xws, size_t xws_bytes) {
+                         const hp_plan_info_t *info, void *xws, size_t xws_bytes, int64_t nptr = -1) {
     const int64_t m = A->nrows, n = A->ncols;
+    if (nptr < 0) nptr = m + 1;
     Carve need(nullptr);
     spref_layout(need, n, nI, nJ, A->nnz);
     if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "spref workspace too small");
@@ -235,7 +297,7 @@ hp_status_t spref_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     if (C->nnz > 0 && (!C->col || !C->val)) return fail(h, HP_ERR_INVALID_ARG, "C->col/val is NULL");
     const size_t vs = sizeof(VT);
     const void *ins[] = {A->rowptr, A->col, A->val, I, J, ws, xws, C->rowptr};
-    const size_t insz[] = {(size_t)(m + 1) * sizeof(PT), (size_t)A->nnz * 4, (size_t)A->nnz * vs,
+    const size_t insz[] = {(size_t)nptr * sizeof(PT), (size_t)A->nnz * 4, (size_t)A->nnz * vs,
                            (size_t)nI * 4, (size_t)nJ * 4, ws_bytes, xws_bytes,
                            (size_t)(nI + 1) * sizeof(PT)};
     for (int k = 0; k < 8; k++)
@@ -313,4 +375,85 @@ extern "C" hp_status_t hp_spref_exec(hp_handle_t h, const hp_csr_t *A, const int
     if (p64 && !v64)
         return spref_exec_t<int64_t, uint32_t>(h, A, I, nI, J, nJ, C, ws, ws_bytes, info, xws, xws_bytes);
     return spref_exec_t<int64_t, uint64_t>(h, A, I, nI, J, nJ, C, ws, ws_bytes, info, xws, xws_bytes);
+}
+
+// ---- column-compressed input ----------------------------------------------
+// A(I, J) on CSC/DCSC is the row extraction of the transpose: the column
+// pointers and row indices of A are the row pointers and columns of A^T,
+// C^T = A^T(J, I), and the CSR of C^T is the CSC of C.
+namespace {
+hp_csr_t transpose_view(const hp_dcsc_t *A) {
+    hp_csr_t T;
+    T.nrows = A->ncols;
+    T.ncols = A->nrows;
+    T.nnz = A->nnz;
+    T.ptr_type = A->ptr_type;
+    T.val_type = A->val_type;
+    T.rowptr = A->colptr;
+    T.col = A->row;
+    T.val = A->val;
+    return T;
+}
+
+hp_status_t dcsc_check(hp_handle_t h, const hp_dcsc_t *A, const hp_dcsc_t *C) {
+    if (!A) return fail(h, HP_ERR_INVALID_ARG, "A is NULL");
+    if (A->dcsc != 0 && A->dcsc != 1) return fail(h, HP_ERR_INVALID_ARG, "A: dcsc must be 0 or 1");
+    if (A->dcsc && (A->nzc < 0 || A->nzc > A->ncols)) return fail(h, HP_ERR_INVALID_ARG, "A: nzc outside [0, ncols]");
+    if (A->dcsc && A->nzc > 0 && !A->jc) return fail(h, HP_ERR_INVALID_ARG, "A: jc is NULL");
+    if (!A->colptr) return fail(h, HP_ERR_INVALID_ARG, "A: colptr is NULL");
+    if (C && C->dcsc) return fail(h, HP_ERR_INVALID_ARG, "C is returned in CSC: C->dcsc must be 0");
+    return HP_OK;
+}
+}  // namespace
+
+extern "C" hp_status_t hp_spref_dcsc_workspace(hp_handle_t h, const hp_dcsc_t *A, int64_t nI, int64_t nJ,
+                                               size_t *bytes) {
+    if (!h || !bytes) return HP_ERR_INVALID_ARG;
+    hp_status_t st = dcsc_check(h, A, nullptr);
+    if (st) return st;
+    const hp_csr_t T = transpose_view(A);
+    st = hp_spref_workspace(h, &T, nJ, nI, bytes);
+    if (st == HP_OK && A->dcsc) *bytes += dcsc_plan(T.nrows, A->nzc).bytes;
+    return st;
+}
+
+extern "C" hp_status_t hp_spref_dcsc_plan(hp_handle_t h, const hp_dcsc_t *A, const int32_t *I, int64_t nI,
+                                          const int32_t *J, int64_t nJ, hp_dcsc_t *C, void *ws, size_t ws_bytes,
+                                          hp_plan_info_t *info) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    hp_status_t st = dcsc_check(h, A, C);
+    if (st) return st;
+    if (!C) return fail(h, HP_ERR_INVALID_ARG, "C is NULL");
+    const hp_csr_t T = transpose_view(A);
+    hp_csr_t CT = transpose_view(C);
+    st = spref_check_args(h, &T, J, nJ, I, nI, &CT);
+    if (st) return st;
+    const bool dc = A->dcsc != 0;
+    st = T.ptr_type == HP_IDX_I32
+             ? spref_plan_t<int32_t>(h, &T, J, nJ, I, nI, &CT, ws, ws_bytes, info, dc, A->jc, A->nzc)
+             : spref_plan_t<int64_t>(h, &T, J, nJ, I, nI, &CT, ws, ws_bytes, info, dc, A->jc, A->nzc);
+    if (st == HP_OK) C->nnz = CT.nnz;
+    return st;
+}
+
+extern "C" hp_status_t hp_spref_dcsc_exec(hp_handle_t h, const hp_dcsc_t *A, const int32_t *I, int64_t nI,
+                                          const int32_t *J, int64_t nJ, hp_dcsc_t *C, void *ws, size_t ws_bytes,
+                                          const hp_plan_info_t *info, void *xws, size_t xws_bytes) {
+    if (!h) return HP_ERR_INVALID_ARG;
+    hp_status_t st = dcsc_check(h, A, C);
+    if (st) return st;
+    if (!C) return fail(h, HP_ERR_INVALID_ARG, "C is NULL");
+    const hp_csr_t T = transpose_view(A);
+    hp_csr_t CT = transpose_view(C);
+    st = spref_check_args(h, &T, J, nJ, I, nI, &CT);
+    if (st) return st;
+    const int64_t nptr = A->dcsc ? A->nzc + 1 : A->ncols + 1;
+    const bool p64 = T.ptr_type == HP_IDX_I64, v64 = T.val_type == HP_VAL_F64;
+    if (!p64 && !v64)
+        return spref_exec_t<int32_t, uint32_t>(h, &T, J, nJ, I, nI, &CT, ws, ws_bytes, info, xws, xws_bytes, nptr);
+    if (!p64 && v64)
+        return spref_exec_t<int32_t, uint64_t>(h, &T, J, nJ, I, nI, &CT, ws, ws_bytes, info, xws, xws_bytes, nptr);
+    if (p64 && !v64)
+        return spref_exec_t<int64_t, uint32_t>(h, &T, J, nJ, I, nI, &CT, ws, ws_bytes, info, xws, xws_bytes, nptr);
+    return spref_exec_t<int64_t, uint64_t>(h, &T, J, nJ, I, nI, &CT, ws, ws_bytes, info, xws, xws_bytes, nptr);
 }

@@ -101,16 +101,42 @@ __device__ inline void spref_jlink_tile(int64_t bid, const int32_t *__restrict__
 }
 
 // ---- selected rows ----------------------------------------------------------
+// Doubly compressed rows: only rows jc[0..nzc) (ascending) are stored, row
+// jc[k] at arow[k].  bstart indexes them by bucket: the stored rows with
+// id >> shift == b are jc[bstart[b] .. bstart[b+1]).  bstart == nullptr:
+// plain row pointers.
+struct DcscIndex {
+    const int32_t *jc;
+    int64_t nzc;
+    const int32_t *bstart;
+    int shift;
+};
+
 template <typename PT>
 __device__ inline void spref_rows_tile(int64_t bid, const PT *__restrict__ arow, const int32_t *__restrict__ I,
                                        int64_t nI, int64_t m, int64_t *rs, int32_t *rl, int32_t *ch, uint8_t *big,
-                                       DevHdr *hdr) {
+                                       DevHdr *hdr, DcscIndex dx = DcscIndex{nullptr, 0, nullptr, 0}) {
     const int64_t i = bid * 256 + threadIdx.x;
     if (i >= nI) return;
     const int32_t r = I[i];
     int64_t s = 0, len = 0;
-    if (r < 0 || r >= m) atomicOr(&hdr->err, E_RANGE);   // error path only
-    else {
+    if (r < 0 || r >= m) {
+        atomicOr(&hdr->err, E_RANGE);   // error path only
+    } else if (dx.bstart) {
+        const int32_t *jc = dx.jc;
+        const int64_t nzc = dx.nzc;
+        const int64_t b = r >> dx.shift;
+        int64_t lo = dx.bstart[b], hi = dx.bstart[b + 1];   // first stored row >= r in the bucket
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (jc[mid] < r) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < nzc && jc[lo] == r) {
+            s = arow[lo];
+            len = arow[lo + 1] - s;
+        }
+    } else {
         s = arow[r];
         len = arow[r + 1] - s;
     }

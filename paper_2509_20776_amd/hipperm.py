@@ -43,6 +43,14 @@ class hp_csr_t(ctypes.Structure):
                 ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
 
 
+class hp_dcsc_t(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("nzc", ctypes.c_int64), ("ptr_type", ctypes.c_int32), ("val_type", ctypes.c_int32),
+                ("dcsc", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("jc", ctypes.c_void_p), ("colptr", ctypes.c_void_p), ("row", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
 class hp_plan_info_t(ctypes.Structure):
     _fields_ = [("nnz_out", ctypes.c_int64), ("exec_ws_bytes", ctypes.c_size_t),
                 ("map_monotone", ctypes.c_int32), ("op", ctypes.c_int32),
@@ -122,6 +130,11 @@ hp_spasgn_permute_plan = _sig("hp_spasgn_permute_plan", [_P, _CSRP, _CSRP, _P, _
                                                          _P, _SZ, _INFOP])
 hp_spasgn_permute_exec = _sig("hp_spasgn_permute_exec", [_P, _CSRP, _CSRP, _P, _P, ctypes.c_int, _P, _P, _CSRP,
                                                          _P, _SZ, _INFOP, _P, _SZ])
+_DCSCP = ctypes.POINTER(hp_dcsc_t)
+hp_spref_dcsc_workspace = _sig("hp_spref_dcsc_workspace", [_P, _DCSCP, _I64, _I64, ctypes.POINTER(_SZ)])
+hp_spref_dcsc_plan = _sig("hp_spref_dcsc_plan", [_P, _DCSCP, _P, _I64, _P, _I64, _DCSCP, _P, _SZ, _INFOP])
+hp_spref_dcsc_exec = _sig("hp_spref_dcsc_exec", [_P, _DCSCP, _P, _I64, _P, _I64, _DCSCP, _P, _SZ, _INFOP,
+                                                 _P, _SZ])
 hp_gather_index = _sig("hp_gather_index", [_P, _P, _I64, _P, _I64, _P])
 hp_invert_perm = _sig("hp_invert_perm", [_P, _P, _I64, _P])
 hp_block_nnz = _sig("hp_block_nnz", [_P, _CSRP, ctypes.c_int32, ctypes.c_int32, _P])
@@ -146,6 +159,23 @@ class CSR:
     @property
     def nnz(self) -> int:
         return int(self.col.numel())
+
+
+@dataclass
+class DCSC:
+    """Column-compressed matrix: CSC when jc is None (colptr has ncols+1
+    entries), else doubly compressed (only the columns jc are stored,
+    colptr has len(jc)+1 entries)."""
+    nrows: int
+    ncols: int
+    jc: Optional[torch.Tensor]
+    colptr: torch.Tensor
+    row: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row.numel())
 
 
 def _ptr_type(t):
@@ -177,6 +207,13 @@ def _dptr(t: Optional[torch.Tensor]):
 def to_csr_t(A) -> hp_csr_t:
     return hp_csr_t(A.nrows, A.ncols, int(A.col.numel()), _ptr_type(A.rowptr), _val_type(A.val),
                     _dptr(A.rowptr), _dptr(A.col), _dptr(A.val))
+
+
+def to_dcsc_t(A) -> hp_dcsc_t:
+    dc = A.jc is not None
+    nzc = int(A.jc.numel()) if dc else int(A.ncols)
+    return hp_dcsc_t(A.nrows, A.ncols, int(A.row.numel()), nzc, _ptr_type(A.colptr), _val_type(A.val),
+                     1 if dc else 0, 0, _idx(A.jc) if dc else None, _dptr(A.colptr), _dptr(A.row), _dptr(A.val))
 
 
 def _idx(x: Optional[torch.Tensor]):
@@ -308,6 +345,40 @@ class Handle:
     def spref(self, A, I, J):
         C, ws, info = self.spref_plan(A, I, J)
         return self.spref_exec(A, I, J, C, ws, info)
+
+    # ---- spref on CSC / DCSC -------------------------------------------------
+    def spref_dcsc_plan(self, A, I, J, ws=None):
+        """Plan C = A(I, J) for column-compressed A; C comes back in CSC."""
+        self._stream()
+        Ac = to_dcsc_t(A)
+        nI, nJ = int(I.numel()), int(J.numel())
+        need = _SZ(0)
+        self.check(hp_spref_dcsc_workspace(self.h, ctypes.byref(Ac), nI, nJ, ctypes.byref(need)))
+        if ws is None or ws.numel() < need.value:
+            ws = self._alloc(need.value)
+        colptr = torch.empty(nJ + 1, dtype=A.colptr.dtype, device=A.colptr.device)
+        Cc = hp_dcsc_t(nI, nJ, 0, nJ, Ac.ptr_type, Ac.val_type, 0, 0, None, _dptr(colptr), None, None)
+        info = hp_plan_info_t()
+        self.check(hp_spref_dcsc_plan(self.h, ctypes.byref(Ac), _idx(I), nI, _idx(J), nJ, ctypes.byref(Cc),
+                                      _dptr(ws), ws.numel(), ctypes.byref(info)))
+        C = DCSC(nI, nJ, None, colptr, torch.empty(Cc.nnz, dtype=torch.int32, device=A.row.device),
+                 torch.empty(Cc.nnz, dtype=A.val.dtype, device=A.val.device))
+        return C, ws, info
+
+    def spref_dcsc_exec(self, A, I, J, C, ws, info, xws=None):
+        self._stream()
+        Ac, Cc = to_dcsc_t(A), to_dcsc_t(C)
+        if info.exec_ws_bytes and (xws is None or xws.numel() < info.exec_ws_bytes):
+            xws = self._alloc(info.exec_ws_bytes)
+        self.check(hp_spref_dcsc_exec(self.h, ctypes.byref(Ac), _idx(I), int(I.numel()), _idx(J), int(J.numel()),
+                                      ctypes.byref(Cc), _dptr(ws), ws.numel(), ctypes.byref(info),
+                                      _dptr(xws) if xws is not None else None,
+                                      xws.numel() if xws is not None else 0))
+        return C
+
+    def spref_dcsc(self, A, I, J):
+        C, ws, info = self.spref_dcsc_plan(A, I, J)
+        return self.spref_dcsc_exec(A, I, J, C, ws, info)
 
     # ---- spasgn ------------------------------------------------------------
     @staticmethod
@@ -595,6 +666,11 @@ def permute(A, p, q=None, device: int = 0) -> CSR:
 def spref(A, I, J, device: int = 0) -> CSR:
     """C = A(I, J) with C[i, j] = A[I[i], J[j]]; repeated/unordered indices allowed."""
     return handle(device).spref(A, I, J)
+
+
+def spref_dcsc(A, I, J, device: int = 0) -> DCSC:
+    """C = A(I, J) for A in CSC/DCSC (a DCSC); C in CSC."""
+    return handle(device).spref_dcsc(A, I, J)
 
 
 def spasgn(A, B, I, J, op="second", device: int = 0) -> CSR:

@@ -149,6 +149,42 @@ def csr_from_sorted_keys(keys: torch.Tensor, nrows: int, ncols: int, vkey: int,
                values(vkey, int(keys.numel()), val_dtype, keys.device))
 
 
+@dataclass
+class DCSC:
+    """Column-compressed matrix: CSC when jc is None (colptr has ncols+1
+    entries), else doubly compressed (only the columns jc are stored)."""
+    nrows: int
+    ncols: int
+    jc: Optional[torch.Tensor]
+    colptr: torch.Tensor
+    row: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row.numel())
+
+
+def dcsc_uniform(m: int, n: int, nnz: int, seed: int = 0, label="hyper", ptr_dtype=torch.int64,
+                 val_dtype=torch.float64, compress: bool = True, device="cpu") -> DCSC:
+    """nnz positions drawn uniformly (with replacement, duplicates removed)
+    over the m x n grid, stored by column; compress keeps only the non-empty
+    columns (DCSC).  With nnz below n most columns are empty (hypersparse)."""
+    key = stream_key(seed, label, m, n)
+    lin = torch.unique(randint_below(stream_key(key, "pos"), nnz, m * n, device), sorted=True)
+    cols = lin // m
+    rows = (lin - cols * m).to(torch.int32)
+    if compress:
+        jc, cnt = torch.unique_consecutive(cols, return_counts=True)
+        jc = jc.to(torch.int32)
+    else:
+        jc, cnt = None, torch.bincount(cols, minlength=n)
+    colptr = torch.zeros(cnt.numel() + 1, dtype=torch.int64, device=lin.device)
+    colptr[1:] = torch.cumsum(cnt, 0)
+    return DCSC(m, n, jc, colptr.to(ptr_dtype), rows.contiguous(),
+                values(stream_key(key, "val"), int(lin.numel()), val_dtype, lin.device))
+
+
 def erdos_renyi(m: int, n: int, avg_deg: float, seed: int = 0, label="er",
                 ptr_dtype=torch.int32, val_dtype=torch.float64, device="cpu") -> CSR:
     """round(m*avg_deg) positions drawn uniformly (with replacement) over the
@@ -298,6 +334,19 @@ def workload_rmat_extract(seed: int = 0, scale: int = 22, edge_factor: int = 16,
     k = int(n * frac)
     I = subset(stream_key(seed, "cfg-rmat", "I"), n, k, False, repeat_frac, device)
     J = subset(stream_key(seed, "cfg-rmat", "J"), n, k, False, repeat_frac, device)
+    return dict(A=A, I=I, J=J)
+
+
+def workload_hypersparse(seed: int = 0, scale: int = 26, per_col: float = 0.25, frac: float = 0.25,
+                         repeat_frac: float = 0.01, compress: bool = True, device="cpu"):
+    """2^scale x 2^scale matrix with per_col * 2^scale uniform nonzeros in
+    DCSC (int64 colptr, fp64), most columns empty; I, J random `frac`
+    unsorted subsets with `repeat_frac` repeated indices."""
+    n = 1 << scale
+    A = dcsc_uniform(n, n, int(per_col * n), seed, "cfg-hyper", torch.int64, torch.float64, compress, device)
+    k = int(n * frac)
+    I = subset(stream_key(seed, "cfg-hyper", "I"), n, k, False, repeat_frac, device)
+    J = subset(stream_key(seed, "cfg-hyper", "J"), n, k, False, repeat_frac, device)
     return dict(A=A, I=I, J=J)
 
 

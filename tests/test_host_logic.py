@@ -26,7 +26,7 @@ def _run_c(tmp_path, src, lang="c"):
 
 def test_struct_layouts_match_binding(tmp_path):
     from paper_2509_20776_amd import hipperm as hp
-    structs = {"hp_csr_t": hp.hp_csr_t, "hp_plan_info_t": hp.hp_plan_info_t,
+    structs = {"hp_csr_t": hp.hp_csr_t, "hp_dcsc_t": hp.hp_dcsc_t, "hp_plan_info_t": hp.hp_plan_info_t,
                "hp_request_t": hp.hp_request_t, "hp_batch_info_t": hp.hp_batch_info_t,
                "hp_server_config_t": hp.hp_server_config_t, "hp_completion_t": hp.hp_completion_t}
     lines = []
