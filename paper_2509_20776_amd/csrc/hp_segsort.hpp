@@ -575,6 +575,7 @@ __global__ __launch_bounds__(256) void k_seg_block(const PT *__restrict__ rowptr
 constexpr int BKT_SHIFT = 20;                        // keys per bucket = bitmap bits
 constexpr int BKT_MAXNB = 4096;                      // buckets per row (2^31 columns need 2048)
 constexpr int RANK_THREADS = 1024;
+constexpr int RANK_U = 8;                            // elements per thread and pass
 constexpr int RB_WORDS = 1 << (BKT_SHIFT - 5);       // 32768 bitmap words
 constexpr int RB_GRP = 8;                            // words per prefix group
 constexpr int RB_NGRP = RB_WORDS / RB_GRP;           // 4096 prefix entries
@@ -687,21 +688,42 @@ __device__ void seg_rank_tile(int64_t item, SegSmemRank &sm, const PT *__restric
     uint4 *bm4 = reinterpret_cast<uint4 *>(sm.bm);
     for (int i = tid; i < RB_WORDS / 4; i += RANK_THREADS) bm4[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
+    // Each pass handles RANK_U elements per thread with all loads issued
+    // before any is used: a row of 17K entries is then 3 rounds of memory
+    // latency per loop instead of 17.
+    constexpr int64_t STEP = (int64_t)RANK_THREADS * RANK_U;
     if (nb == 1) {
         const int64_t sb = ld.base(row);
-        for (int64_t i = tid; i < len; i += RANK_THREADS) {
-            int32_t kk;
-            VT vv;
-            ld.get(sb, i, kk, vv);
-            yk[i] = kk;
-            yv[i] = vv;
-            const uint32_t d = (uint32_t)kk;
-            atomicOr(&sm.bm[d >> 5], 1u << (d & 31));
+        for (int64_t i0 = 0; i0 < len; i0 += STEP) {
+            int32_t kk[RANK_U];
+            VT vv[RANK_U];
+#pragma unroll
+            for (int u = 0; u < RANK_U; u++) {
+                const int64_t i = i0 + u * RANK_THREADS + tid;
+                if (i < len) ld.get(sb, i, kk[u], vv[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < RANK_U; u++) {
+                const int64_t i = i0 + u * RANK_THREADS + tid;
+                if (i < len) {
+                    yk[i] = kk[u];
+                    yv[i] = vv[u];
+                    const uint32_t d = (uint32_t)kk[u];
+                    atomicOr(&sm.bm[d >> 5], 1u << (d & 31));
+                }
+            }
         }
     } else {
-        for (int64_t i = tid; i < len; i += RANK_THREADS) {
-            const uint32_t d = (uint32_t)yk[i] - kbase;
-            atomicOr(&sm.bm[d >> 5], 1u << (d & 31));
+        for (int64_t i0 = 0; i0 < len; i0 += STEP) {
+            uint32_t dd[RANK_U];
+#pragma unroll
+            for (int u = 0; u < RANK_U; u++) {
+                const int64_t i = i0 + u * RANK_THREADS + tid;
+                dd[u] = i < len ? (uint32_t)yk[i] - kbase : 0xFFFFFFFFu;
+            }
+#pragma unroll
+            for (int u = 0; u < RANK_U; u++)
+                if (dd[u] != 0xFFFFFFFFu) atomicOr(&sm.bm[dd[u] >> 5], 1u << (dd[u] & 31));
         }
     }
     __syncthreads();
@@ -730,16 +752,29 @@ __device__ void seg_rank_tile(int64_t item, SegSmemRank &sm, const PT *__restric
     }
     __syncthreads();
     const int64_t ob = b + s0;
-    for (int64_t i = tid; i < len; i += RANK_THREADS) {
-        const int32_t kk = yk[i];
-        const VT vv = yv[i];
-        const uint32_t d = (uint32_t)kk - kbase;
-        const uint32_t w = d >> 5;
-        const uint32_t g0 = w & ~uint32_t(RB_GRP - 1);
-        uint32_t r = sm.pre[w / RB_GRP] + __popc(sm.bm[w] & ((1u << (d & 31)) - 1u));
-        for (uint32_t u = g0; u < w; u++) r += __popc(sm.bm[u]);
-        okey[ob + r] = kk;
-        oval[ob + r] = vv;
+    for (int64_t i0 = 0; i0 < len; i0 += STEP) {
+        int32_t kk[RANK_U];
+        VT vv[RANK_U];
+#pragma unroll
+        for (int u = 0; u < RANK_U; u++) {
+            const int64_t i = i0 + u * RANK_THREADS + tid;
+            if (i < len) {
+                kk[u] = yk[i];
+                vv[u] = yv[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RANK_U; u++) {
+            const int64_t i = i0 + u * RANK_THREADS + tid;
+            if (i >= len) continue;
+            const uint32_t d = (uint32_t)kk[u] - kbase;
+            const uint32_t w = d >> 5;
+            const uint32_t g0 = w & ~uint32_t(RB_GRP - 1);
+            uint32_t r = sm.pre[w / RB_GRP] + __popc(sm.bm[w] & ((1u << (d & 31)) - 1u));
+            for (uint32_t x = g0; x < w; x++) r += __popc(sm.bm[x]);
+            okey[ob + r] = kk[u];
+            oval[ob + r] = vv[u];
+        }
     }
     __syncthreads();
 }
