@@ -334,8 +334,8 @@ __global__ __launch_bounds__(256) void k_sort_small(const PT *__restrict__ rowpt
 // in the same wavefront (shuffles); farther ones are exchanged through LDS,
 // stored q-major so that consecutive threads hit consecutive words.
 
-template <int T, int E>
-__device__ __forceinline__ void bitonic_block(uint64_t (&x)[E], uint64_t *s_x) {
+template <int T, int E, typename W>
+__device__ __forceinline__ void bitonic_block(W (&x)[E], W *s_x) {
     const int t = threadIdx.x;
 #pragma unroll
     for (int k = 2; k <= T * E; k <<= 1) {
@@ -346,8 +346,8 @@ __device__ __forceinline__ void bitonic_block(uint64_t (&x)[E], uint64_t *s_x) {
                 for (int q = 0; q < E; q++) {
                     if (q & j) continue;
                     const bool asc = ((t * E + q) & k) == 0;
-                    const uint64_t a = x[q], b = x[q | j];
-                    const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+                    const W a = x[q], b = x[q | j];
+                    const W lo = a < b ? a : b, hi = a < b ? b : a;
                     x[q] = asc ? lo : hi;
                     x[q | j] = asc ? hi : lo;
                 }
@@ -358,7 +358,11 @@ __device__ __forceinline__ void bitonic_block(uint64_t (&x)[E], uint64_t *s_x) {
                 if (j < WAVE * E) {
 #pragma unroll
                     for (int q = 0; q < E; q++) {
-                        const uint64_t o = (uint64_t)__shfl_xor((unsigned long long)x[q], d, WAVE);
+                        W o;
+                        if constexpr (sizeof(W) == 8)
+                            o = (W)__shfl_xor((unsigned long long)x[q], d, WAVE);
+                        else
+                            o = (W)__shfl_xor((unsigned int)x[q], d, WAVE);
                         x[q] = keep_min ? (o < x[q] ? o : x[q]) : (o < x[q] ? x[q] : o);
                     }
                 } else {
@@ -367,7 +371,7 @@ __device__ __forceinline__ void bitonic_block(uint64_t (&x)[E], uint64_t *s_x) {
                     __syncthreads();
 #pragma unroll
                     for (int q = 0; q < E; q++) {
-                        const uint64_t o = s_x[q * T + (t ^ d)];
+                        const W o = s_x[q * T + (t ^ d)];
                         x[q] = keep_min ? (o < x[q] ? o : x[q]) : (o < x[q] ? x[q] : o);
                     }
                     __syncthreads();
@@ -383,57 +387,70 @@ struct alignas(16) SegSmemBitonic {
     uint64_t v[N];   // values by source position
 };
 
-template <typename VT, typename LD, int T, int E, int N>
+// W = uint64_t: word = key << 32 | position.  W = uint32_t: word = key <<
+// PB | position, for keys below 2^(32 - PB) and rows of at most 2^PB
+// entries (half the compare and shuffle work).
+template <typename VT, typename LD, int T, int E, int N, typename W, int PB>
 __device__ __forceinline__ void bitonic_row(const LD &ld, int64_t sb, int len, int32_t *okey, VT *oval,
                                             SegSmemBitonic<N> &sm) {
     const int t = threadIdx.x;
     VT *sv = reinterpret_cast<VT *>(sm.v);
-    uint64_t x[E];
+    constexpr W PMASK = (W(1) << PB) - 1;
+    W x[E];
 #pragma unroll
     for (int q = 0; q < E; q++) {
         const int i = q * T + t;
-        x[q] = ~0ull;
+        x[q] = ~W(0);
         if (i < len) {
             int32_t kk;
             VT vv;
             ld.get(sb, i, kk, vv);
-            x[q] = ((uint64_t)(uint32_t)kk << 32) | (uint32_t)i;
+            x[q] = ((W)(uint32_t)kk << PB) | (W)i;
             sv[i] = vv;
         }
     }
-    bitonic_block<T, E>(x, sm.x);
+    bitonic_block<T, E, W>(x, reinterpret_cast<W *>(sm.x));
     __syncthreads();   // every value staged (and, in place, every entry read) before any store
 #pragma unroll
     for (int q = 0; q < E; q++) {
         const int e = t * E + q;
         if (e < len) {
-            okey[e] = (int32_t)(x[q] >> 32);
-            oval[e] = sv[(uint32_t)x[q]];
+            okey[e] = (int32_t)(x[q] >> PB);
+            oval[e] = sv[(uint32_t)(x[q] & PMASK)];
         }
     }
 }
 
-// One workgroup of T threads per listed row of at most EMAX*T entries
-// (longer rows of the list are left to another kernel); E = 2, 4, 8 or 16
-// by length, LDS sized for EMAX.  The row sort class BLOCK (257..2048
-// entries) uses T = 256, EMAX = 8: 55 us on the headline extraction's 4.1K
-// such rows, against 86 us for the LDS merge sort it replaced.
+template <typename VT, typename LD, int T, int EMAX, typename W, int PB>
+__device__ __forceinline__ void bitonic_any(const LD &ld, int64_t sb, int len, int32_t *okey, VT *oval,
+                                            SegSmemBitonic<EMAX * T> &sm) {
+    constexpr int N = EMAX * T;
+    if (len <= 2 * T) bitonic_row<VT, LD, T, 2, N, W, PB>(ld, sb, len, okey, oval, sm);
+    else if (EMAX >= 4 && len <= 4 * T) bitonic_row<VT, LD, T, (EMAX >= 4 ? 4 : 2), N, W, PB>(ld, sb, len, okey, oval, sm);
+    else if (EMAX >= 8 && len <= 8 * T) bitonic_row<VT, LD, T, (EMAX >= 8 ? 8 : 2), N, W, PB>(ld, sb, len, okey, oval, sm);
+    else if (EMAX >= 16) bitonic_row<VT, LD, T, (EMAX >= 16 ? 16 : 2), N, W, PB>(ld, sb, len, okey, oval, sm);
+}
+
+// One workgroup of T threads per listed row of at most EMAX*T entries;
+// E = 2, 4, 8 or 16 words a thread by length, LDS sized for EMAX.  narrow
+// (every key below 2^(32 - log2(EMAX*T))): 32-bit words.  The row sort
+// class BLOCK (257..2048 entries) uses T = 256, EMAX = 8.
 template <typename PT, typename VT, typename LD, int T, int EMAX>
 __global__ __launch_bounds__(T) void k_seg_bitonic(const PT *__restrict__ rowptr, int32_t *okey, VT *oval,
                                                   const uint32_t *__restrict__ list, uint32_t count, LD ld,
-                                                  int64_t min_len, const DevHdr *hdr) {
+                                                  int narrow, const DevHdr *hdr) {
     constexpr int N = EMAX * T;
+    constexpr int PB = N <= 2048 ? 11 : (N <= 4096 ? 12 : 13);
+    static_assert(N <= 8192, "position field");
     __shared__ SegSmemBitonic<N> sm;
     if (blockIdx.x >= count || hdr->err) return;
     const int64_t row = list[blockIdx.x];
     const int64_t b = rowptr[row];
     const int64_t len = rowptr[row + 1] - b;
-    if (len < min_len || len > N) return;
+    if (len > N) return;
     const int64_t sb = ld.base(row);
-    if (len <= 2 * T) bitonic_row<VT, LD, T, 2, N>(ld, sb, (int)len, okey + b, oval + b, sm);
-    else if (EMAX >= 4 && len <= 4 * T) bitonic_row<VT, LD, T, (EMAX >= 4 ? 4 : 2), N>(ld, sb, (int)len, okey + b, oval + b, sm);
-    else if (EMAX >= 8 && len <= 8 * T) bitonic_row<VT, LD, T, (EMAX >= 8 ? 8 : 2), N>(ld, sb, (int)len, okey + b, oval + b, sm);
-    else if (EMAX >= 16) bitonic_row<VT, LD, T, (EMAX >= 16 ? 16 : 2), N>(ld, sb, (int)len, okey + b, oval + b, sm);
+    if (narrow) bitonic_any<VT, LD, T, EMAX, uint32_t, PB>(ld, sb, (int)len, okey + b, oval + b, sm);
+    else bitonic_any<VT, LD, T, EMAX, uint64_t, 32>(ld, sb, (int)len, okey + b, oval + b, sm);
 }
 
 // ---- workgroup LDS sort of <= BLOCK_MAX keys with their 16-bit source index ----
@@ -832,7 +849,8 @@ hipError_t launch_seg_classes(hipStream_t s, const PT *rowptr, int32_t *okey, VT
                                okey, oval, lists + BIN_BLOCK * cap, cnt[BIN_BLOCK], ld, 1, hdr);
         else
             hipLaunchKernelGGL((k_seg_bitonic<PT, VT, LD, 256, 8>), dim3(cnt[BIN_BLOCK]), dim3(256), 0, s, rowptr,
-                               okey, oval, lists + BIN_BLOCK * cap, cnt[BIN_BLOCK], ld, (int64_t)0, hdr);
+                               okey, oval, lists + BIN_BLOCK * cap, cnt[BIN_BLOCK], ld,
+                               ncols_out <= (int64_t(1) << 21) ? 1 : 0, hdr);
     }
     if (cnt[BIN_GLOBAL]) {
         int32_t *tk = (int32_t *)tmp;
