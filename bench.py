@@ -56,6 +56,19 @@ def _timed(step, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def _timed_then_staged(h, step, steps):
+    """Seconds per step with stage timing off, then the per-stage device
+    times from as many more steps with timing on.  Stage events cost the
+    GPU a few microseconds each, so the step time is taken without them;
+    the roofline durations come from the events around each stage."""
+    sec = _timed(step, steps, 0)
+    h.timing(True)
+    _timed(step, steps, 0)
+    stages = h.stage_times()
+    h.timing(False)
+    return sec, stages
+
+
 def _esize(t):
     return t.element_size()
 
@@ -172,10 +185,7 @@ def run_rmat_extract(hp, args):
     for _ in range(args.warmup):
         step()
     _sync()
-    h.timing(True)
-    sec = _timed(step, args.steps, 0)
-    stages = h.stage_times()
-    h.timing(False)
+    sec, stages = _timed_then_staged(h, step, args.steps)
     b = spref_bytes(A, I.numel(), J.numel(), S, nnz_out)
     res = dict(value=S / sec, unit="nnz/s", ms_per_step=sec * 1e3,
                config={"workload": "rmat-extract", "desc": "C = A(I,J); R-MAT scale %d ef16 symmetrised, "
@@ -228,10 +238,7 @@ def run_grid_permute(hp, args):
     for _ in range(args.warmup):
         step()
     _sync()
-    h.timing(True)
-    sec = _timed(step, args.steps, 0)
-    stages = h.stage_times()
-    h.timing(False)
+    sec, stages = _timed_then_staged(h, step, args.steps)
     b = permute_bytes(A)
     res = dict(value=A.nnz / sec, unit="nnz/s", ms_per_step=sec * 1e3,
                config={"workload": "grid-permute", "desc": "P A Q^T; %dx%d 5-point grid, int64 rowptr, "
@@ -258,10 +265,7 @@ def run_grid_assign(hp, args):
     for _ in range(args.warmup):
         step()
     _sync()
-    h.timing(True)
-    sec = _timed(step, max(3, args.steps // 4), 0)
-    stages = h.stage_times()
-    h.timing(False)
+    sec, stages = _timed_then_staged(h, step, max(3, args.steps // 4))
     b = spasgn_bytes(A, B, I.numel(), J.numel(), nnz_out)
     res = dict(value=(A.nnz + B.nnz) / sec, unit="nnz/s", ms_per_step=sec * 1e3,
                config={"workload": "grid-assign", "desc": "A(I,J) = B (select-second); %dx%d grid, int64 "
@@ -300,10 +304,7 @@ def run_grid_assign_permute(hp, args):
     for _ in range(args.warmup):
         step()
     _sync()
-    h.timing(True)
-    sec = _timed(step, nsteps, 0)
-    stages = h.stage_times()
-    h.timing(False)
+    sec, stages = _timed_then_staged(h, step, nsteps)
     b = spasgn_bytes(A, B, I.numel(), J.numel(), nnz_out)
     b["total"] += 4 * (A.nrows + A.ncols)
     res = dict(value=(A.nnz + B.nnz) / sec, unit="nnz/s", ms_per_step=sec * 1e3,
@@ -384,10 +385,8 @@ def run_hypersparse_extract(hp, args):
         for _ in range(args.warmup):
             step()
         _sync()
-        h.timing(True)
-        sec = _timed(step, args.steps, 0)
-        out[name] = (sec, h.stage_times(), nnz_out)
-        h.timing(False)
+        sec, st = _timed_then_staged(h, step, args.steps)
+        out[name] = (sec, st, nnz_out)
     sec, stages, nnz_out = out["dcsc"]
     return dict(value=S / sec, unit="nnz/s", ms_per_step=sec * 1e3,
                 config={"workload": "hypersparse-extract", "desc": "C = A(I,J), A in DCSC (int64 colptr, fp64), "

@@ -133,6 +133,7 @@ extern "C" hp_status_t hp_destroy(hp_handle_t h) {
     if (!h) return HP_ERR_INVALID_ARG;
     hp::batch_release_handle(h);
     for (auto &e : h->ev) hipEventDestroy(e);
+    if (h->rb_done) hipEventDestroy(h->rb_done);
     if (h->host_hdr) hipHostFree(h->host_hdr);
     delete h;
     return HP_OK;
@@ -241,10 +242,22 @@ hipError_t launch_init_hdr(hipStream_t s, DevHdr *h, uint64_t *tile_state, size_
     return hipGetLastError();
 }
 
+// The plan's one blocking step.  The host polls an event behind the copy
+// instead of sleeping in a stream synchronisation: the plan returns as soon
+// as the few bytes have landed.  A failed or faulted stream ends the poll
+// with its error.
 hipError_t readback_hdr(hp_handle_t h, DevHdr *dev) {
     hipError_t e = hipMemcpyAsync(h->host_hdr, dev, sizeof(DevHdr), hipMemcpyDeviceToHost, h->stream);
     if (e != hipSuccess) return e;
-    return hipStreamSynchronize(h->stream);
+    if (!h->rb_done && hipEventCreateWithFlags(&h->rb_done, hipEventDisableTiming) != hipSuccess) {
+        h->rb_done = nullptr;
+        return hipStreamSynchronize(h->stream);
+    }
+    e = hipEventRecord(h->rb_done, h->stream);
+    if (e != hipSuccess) return e;
+    while ((e = hipEventQuery(h->rb_done)) == hipErrorNotReady) {
+    }
+    return e;
 }
 
 // ===========================================================================

@@ -153,6 +153,7 @@ struct hp_handle_s {
     size_t ev_used = 0;
     hipEvent_t ev_cur = nullptr;
     std::vector<hp_stage_rec> recs;        // recorded (stage, start, end) triples
+    hipEvent_t rb_done = nullptr;          // marks the end of a plan's readback copy
 };
 
 namespace hp {
