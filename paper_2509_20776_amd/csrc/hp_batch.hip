@@ -103,7 +103,7 @@ union BatchSmem {
     spref::GroupSmem gs[4];
     spref::GroupCore gc[4];
     SegSmemWave wave;
-    SegSmemBlock block;
+    SegSmemBlockBitonic block;
     SegSmemBucket bucket;
 };
 
@@ -210,8 +210,9 @@ __device__ void run_tile(int half, int phase, int64_t tile, const ReqDev &r, Bat
                                       r.cls[BIN_WAVE], ld, 0, r.hdr);
                 break;
             case 5:
-                seg_block_tile<PT, VT>(tile, sm.block, crow, r.ccol, (VT *)r.cval, r.lists + BIN_BLOCK * cap,
-                                       r.cls[BIN_BLOCK], ld, 0, r.hdr);
+                seg_bitonic_tile<PT, VT, decltype(ld), 256, BITONIC_EMAX>(
+                    tile, sm.block, crow, r.ccol, (VT *)r.cval, r.lists + BIN_BLOCK * cap, r.cls[BIN_BLOCK], ld,
+                    bitonic_narrow(r.ncols_out), r.hdr);
                 break;
             case 6:
                 seg_bucket_tile<PT, VT>(tile, sm.bucket, crow, r.lists + BIN_GLOBAL * cap, goff, r.cls[BIN_GLOBAL], ld,
@@ -235,8 +236,9 @@ __device__ void run_tile(int half, int phase, int64_t tile, const ReqDev &r, Bat
                                       r.cls[BIN_WAVE], ld, 0, r.hdr);
                 break;
             case 5:
-                seg_block_tile<PT, VT>(tile, sm.block, crow, r.ccol, (VT *)r.cval, r.lists + BIN_BLOCK * cap,
-                                       r.cls[BIN_BLOCK], ld, 0, r.hdr);
+                seg_bitonic_tile<PT, VT, decltype(ld), 256, BITONIC_EMAX>(
+                    tile, sm.block, crow, r.ccol, (VT *)r.cval, r.lists + BIN_BLOCK * cap, r.cls[BIN_BLOCK], ld,
+                    bitonic_narrow(r.ncols_out), r.hdr);
                 break;
             case 6:
                 seg_bucket_tile<PT, VT>(tile, sm.bucket, crow, r.lists + BIN_GLOBAL * cap, goff, r.cls[BIN_GLOBAL], ld,

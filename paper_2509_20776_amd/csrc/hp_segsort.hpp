@@ -436,15 +436,14 @@ __device__ __forceinline__ void bitonic_any(const LD &ld, int64_t sb, int len, i
 // (every key below 2^(32 - log2(EMAX*T))): 32-bit words.  The row sort
 // class BLOCK (257..2048 entries) uses T = 256, EMAX = 8.
 template <typename PT, typename VT, typename LD, int T, int EMAX>
-__global__ __launch_bounds__(T) void k_seg_bitonic(const PT *__restrict__ rowptr, int32_t *okey, VT *oval,
-                                                  const uint32_t *__restrict__ list, uint32_t count, LD ld,
-                                                  int narrow, const DevHdr *hdr) {
+__device__ void seg_bitonic_tile(int64_t bid, SegSmemBitonic<EMAX * T> &sm, const PT *__restrict__ rowptr,
+                                 int32_t *okey, VT *oval, const uint32_t *__restrict__ list, uint32_t count,
+                                 const LD &ld, int narrow, const DevHdr *hdr) {
     constexpr int N = EMAX * T;
     constexpr int PB = N <= 2048 ? 11 : (N <= 4096 ? 12 : 13);
     static_assert(N <= 8192, "position field");
-    __shared__ SegSmemBitonic<N> sm;
-    if (blockIdx.x >= count || hdr->err) return;
-    const int64_t row = list[blockIdx.x];
+    if (bid >= count || hdr->err) return;
+    const int64_t row = list[bid];
     const int64_t b = rowptr[row];
     const int64_t len = rowptr[row + 1] - b;
     if (len > N) return;
@@ -452,6 +451,19 @@ __global__ __launch_bounds__(T) void k_seg_bitonic(const PT *__restrict__ rowptr
     if (narrow) bitonic_any<VT, LD, T, EMAX, uint32_t, PB>(ld, sb, (int)len, okey + b, oval + b, sm);
     else bitonic_any<VT, LD, T, EMAX, uint64_t, 32>(ld, sb, (int)len, okey + b, oval + b, sm);
 }
+
+template <typename PT, typename VT, typename LD, int T, int EMAX>
+__global__ __launch_bounds__(T) void k_seg_bitonic(const PT *__restrict__ rowptr, int32_t *okey, VT *oval,
+                                                  const uint32_t *__restrict__ list, uint32_t count, LD ld,
+                                                  int narrow, const DevHdr *hdr) {
+    __shared__ SegSmemBitonic<EMAX * T> sm;
+    seg_bitonic_tile<PT, VT, LD, T, EMAX>(blockIdx.x, sm, rowptr, okey, oval, list, count, ld, narrow, hdr);
+}
+
+// Block-class rows (257..BLOCK_MAX entries) in a 256-thread workgroup.
+constexpr int BITONIC_EMAX = (int)(BLOCK_MAX / 256);
+using SegSmemBlockBitonic = SegSmemBitonic<BLOCK_MAX>;
+__host__ __device__ inline int bitonic_narrow(int64_t ncols_out) { return ncols_out <= (int64_t(1) << 21) ? 1 : 0; }
 
 // ---- workgroup LDS sort of <= BLOCK_MAX keys with their 16-bit source index ----
 // In: s_k0/s_i0 hold N (a multiple of 64) keys, real keys distinct, padded
@@ -848,9 +860,9 @@ hipError_t launch_seg_classes(hipStream_t s, const PT *rowptr, int32_t *okey, VT
             hipLaunchKernelGGL((k_seg_block<PT, VT, LD>), dim3(cnt[BIN_BLOCK]), dim3(256), 0, s, rowptr,
                                okey, oval, lists + BIN_BLOCK * cap, cnt[BIN_BLOCK], ld, 1, hdr);
         else
-            hipLaunchKernelGGL((k_seg_bitonic<PT, VT, LD, 256, 8>), dim3(cnt[BIN_BLOCK]), dim3(256), 0, s, rowptr,
-                               okey, oval, lists + BIN_BLOCK * cap, cnt[BIN_BLOCK], ld,
-                               ncols_out <= (int64_t(1) << 21) ? 1 : 0, hdr);
+            hipLaunchKernelGGL((k_seg_bitonic<PT, VT, LD, 256, BITONIC_EMAX>), dim3(cnt[BIN_BLOCK]), dim3(256), 0, s,
+                               rowptr, okey, oval, lists + BIN_BLOCK * cap, cnt[BIN_BLOCK], ld,
+                               bitonic_narrow(ncols_out), hdr);
     }
     if (cnt[BIN_GLOBAL]) {
         int32_t *tk = (int32_t *)tmp;
