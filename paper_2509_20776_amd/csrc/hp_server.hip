@@ -118,7 +118,9 @@ size_t carve_locked(hp_server_s *S, Lock &lk, size_t n, bool holder) {
     }
 }
 
-void run_spasgn(hp_server_s *S, hp_handle_t h, hipStream_t st, Pending p) {
+hipError_t wait_stream(hipStream_t st, hipEvent_t ev);
+
+void run_spasgn(hp_server_s *S, hp_handle_t h, hipStream_t st, hipEvent_t ev, Pending p) {
     hp_request_t &r = p.r;
     const int64_t t0 = now_ns();
     const size_t ps = ptr_bytes(r.A.ptr_type), vs = val_bytes(r.A.val_type);
@@ -169,7 +171,7 @@ void run_spasgn(hp_server_s *S, hp_handle_t h, hipStream_t st, Pending p) {
         C.val = S->pool + out_off + rp_bytes + col_bytes;
         s = hp_spasgn_exec(h, &r.A, &r.B, r.I, r.J, (hp_asgn_op_t)r.op, &C, S->pool + ws_off, wsb, &info,
                            x_off == RangeAlloc::NONE ? nullptr : S->pool + x_off, info.exec_ws_bytes);
-        if (s == HP_OK && hipStreamSynchronize(st) != hipSuccess) s = HP_ERR_HIP;
+        if (s == HP_OK && wait_stream(st, ev) != hipSuccess) s = HP_ERR_HIP;
     }
     Lock lk(S->mu);
     S->alloc.release(ws_off);
@@ -184,8 +186,8 @@ void run_spasgn(hp_server_s *S, hp_handle_t h, hipStream_t st, Pending p) {
 
 // Run one batch of extraction / permutation requests.  Returns the requests
 // to give back to the queue (after a split), empty otherwise.
-std::vector<Pending> run_batch(hp_server_s *S, hp_handle_t h, hipStream_t st, std::vector<Pending> &B,
-                               size_t ws_off, size_t wsb) {
+std::vector<Pending> run_batch(hp_server_s *S, hp_handle_t h, hipStream_t st, hipEvent_t ev,
+                               std::vector<Pending> &B, size_t ws_off, size_t wsb) {
     const int n = (int)B.size();
     const int64_t t0 = now_ns();
     std::vector<hp_request_t> reqs(n);
@@ -218,7 +220,7 @@ std::vector<Pending> run_batch(hp_server_s *S, hp_handle_t h, hipStream_t st, st
     if (s == HP_OK) {
         s = hp_batch_exec(h, reqs.data(), n, S->pool + ws_off, wsb, &info,
                           a_off == RangeAlloc::NONE ? nullptr : S->pool + a_off, info.arena_bytes);
-        if (s == HP_OK && hipStreamSynchronize(st) != hipSuccess) s = HP_ERR_HIP;
+        if (s == HP_OK && wait_stream(st, ev) != hipSuccess) s = HP_ERR_HIP;
     }
     Lock lk(S->mu);
     S->alloc.release(ws_off);
@@ -238,17 +240,107 @@ std::vector<Pending> run_batch(hp_server_s *S, hp_handle_t h, hipStream_t st, st
     return back;
 }
 
+// Wait for the worker's stream by polling an event behind its work (no
+// sleep in a stream synchronisation between a request's end and its
+// completion record).  A failed stream ends the poll with its error.
+hipError_t wait_stream(hipStream_t st, hipEvent_t ev) {
+    if (!ev) return hipStreamSynchronize(st);
+    hipError_t e = hipEventRecord(ev, st);
+    if (e != hipSuccess) return e;
+    while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
+    }
+    return e;
+}
+
+// A lone extraction or permutation runs through the plain calls, which cost
+// less per request than the batched stage launches.  The admission carved
+// [plan workspace | row-pointer staging] as one block at ws_off; the output
+// block (row pointers, columns, values) is carved after the plan, when the
+// output size is known (for a permutation it is nnz(A) and the row pointers
+// go there directly).
+size_t solo_ws_bytes(hp_server_s *S, const hp_request_t &r, size_t *plan_ws) {
+    size_t b = 0;
+    hp_status_t s = r.kind == HP_REQ_SPREF ? hp_spref_workspace(S->ctl, &r.A, r.nI, r.nJ, &b)
+                                           : hp_permute_workspace(S->ctl, &r.A, &b);
+    if (s != HP_OK) return 0;
+    *plan_ws = RangeAlloc::round(b);
+    const int64_t rows = r.kind == HP_REQ_SPREF ? r.nI : r.A.nrows;
+    return *plan_ws + RangeAlloc::round((size_t)(rows + 1) * ptr_bytes(r.A.ptr_type));
+}
+
+void run_solo(hp_server_s *S, hp_handle_t h, hipStream_t st, hipEvent_t ev, Pending &p, size_t ws_off,
+              size_t plan_ws, size_t wsb) {
+    hp_request_t &r = p.r;
+    const int64_t t0 = now_ns();
+    const bool spref = r.kind == HP_REQ_SPREF;
+    const size_t ps = ptr_bytes(r.A.ptr_type), vs = val_bytes(r.A.val_type);
+    const int64_t rows = spref ? r.nI : r.A.nrows;
+    const size_t rp_bytes = RangeAlloc::round((size_t)(rows + 1) * ps);
+    hp_csr_t C{};
+    C.nrows = rows;
+    C.ncols = spref ? r.nJ : r.A.ncols;
+    C.ptr_type = r.A.ptr_type;
+    C.val_type = r.A.val_type;
+    C.rowptr = S->pool + ws_off + plan_ws;   // staging
+    hp_plan_info_t info{};
+    hp_status_t s = spref ? hp_spref_plan(h, &r.A, r.I, r.nI, r.J, r.nJ, &C, S->pool + ws_off, plan_ws, &info)
+                          : hp_permute_plan(h, &r.A, r.p, r.q, &C, S->pool + ws_off, plan_ws, &info);
+    size_t out_off = RangeAlloc::NONE, x_off = RangeAlloc::NONE;
+    if (s == HP_OK) {
+        const size_t col_bytes = RangeAlloc::round((size_t)C.nnz * 4);
+        Lock lk(S->mu);
+        out_off = carve_locked(S, lk, rp_bytes + col_bytes + (size_t)C.nnz * vs, true);
+        if (out_off != RangeAlloc::NONE && info.exec_ws_bytes) {
+            x_off = carve_locked(S, lk, info.exec_ws_bytes, true);
+            if (x_off == RangeAlloc::NONE) {
+                S->alloc.release(out_off);
+                out_off = RangeAlloc::NONE;
+            }
+        }
+        if (out_off == RangeAlloc::NONE) s = HP_ERR_REJECTED;
+    }
+    if (s == HP_OK) {
+        char *ob = S->pool + out_off;
+        if (hipMemcpyAsync(ob, C.rowptr, (size_t)(rows + 1) * ps, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            s = HP_ERR_HIP;
+        C.rowptr = ob;
+        C.col = (int32_t *)(ob + rp_bytes);
+        C.val = ob + rp_bytes + RangeAlloc::round((size_t)C.nnz * 4);
+        void *xw = x_off == RangeAlloc::NONE ? nullptr : S->pool + x_off;
+        if (s == HP_OK)
+            s = spref ? hp_spref_exec(h, &r.A, r.I, r.nI, r.J, r.nJ, &C, S->pool + ws_off, plan_ws, &info, xw,
+                                      info.exec_ws_bytes)
+                      : hp_permute_exec(h, &r.A, r.p, r.q, &C, S->pool + ws_off, plan_ws, &info, xw,
+                                        info.exec_ws_bytes);
+        if (s == HP_OK && wait_stream(st, ev) != hipSuccess) s = HP_ERR_HIP;
+    }
+    (void)wsb;
+    Lock lk(S->mu);
+    S->alloc.release(ws_off);
+    if (x_off != RangeAlloc::NONE) S->alloc.release(x_off);
+    if (out_off != RangeAlloc::NONE) {
+        if (s == HP_OK) S->block_refs[out_off] = 1;
+        else S->alloc.release(out_off);
+    }
+    complete_locked(S, p, s, 1, &C, t0, out_off);
+    S->running--;
+    S->cv_mem.notify_all();
+    S->cv_idle.notify_all();
+}
+
 void worker_main(hp_server_s *S) {
     hipSetDevice(S->device);
     hp_handle_t h = nullptr;
     hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
     bool ok = hp_create(&h, S->device) == HP_OK &&
               hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
               hp_set_stream(h, st) == HP_OK;
+    if (ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
     for (;;) {
         std::vector<Pending> B;
-        size_t wsb = 0, ws_off = RangeAlloc::NONE;
-        bool asgn = false;
+        size_t wsb = 0, ws_off = RangeAlloc::NONE, plan_ws = 0;
+        bool asgn = false, solo = false;
         {
             Lock lk(S->mu);
             S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty(); });
@@ -281,9 +373,14 @@ void worker_main(hp_server_s *S) {
                         }
                     }
                 }
-                std::vector<hp_request_t> tmp(B.size());
-                for (size_t k = 0; k < B.size(); k++) tmp[k] = B[k].r;
-                if (hp_batch_workspace(S->ctl, tmp.data(), (int)tmp.size(), &wsb) != HP_OK) wsb = 0;
+                solo = B.size() == 1;
+                if (solo) {
+                    wsb = solo_ws_bytes(S, B[0].r, &plan_ws);
+                } else {
+                    std::vector<hp_request_t> tmp(B.size());
+                    for (size_t k = 0; k < B.size(); k++) tmp[k] = B[k].r;
+                    if (hp_batch_workspace(S->ctl, tmp.data(), (int)tmp.size(), &wsb) != HP_OK) wsb = 0;
+                }
                 ws_off = carve_locked(S, lk, wsb, false);
                 if (ws_off == RangeAlloc::NONE) {
                     if (B.size() > 1) {
@@ -302,9 +399,11 @@ void worker_main(hp_server_s *S) {
             }
         }
         if (asgn) {
-            run_spasgn(S, h, st, B[0]);
+            run_spasgn(S, h, st, ev, B[0]);
+        } else if (solo) {
+            run_solo(S, h, st, ev, B[0], ws_off, plan_ws, wsb);
         } else {
-            std::vector<Pending> back = run_batch(S, h, st, B, ws_off, wsb);
+            std::vector<Pending> back = run_batch(S, h, st, ev, B, ws_off, wsb);
             if (!back.empty()) {
                 Lock lk(S->mu);
                 for (auto it = back.rbegin(); it != back.rend(); ++it) S->pending.push_front(*it);
@@ -312,6 +411,7 @@ void worker_main(hp_server_s *S) {
             }
         }
     }
+    if (ev) hipEventDestroy(ev);
     if (st) hipStreamDestroy(st);
     if (h) hp_destroy(h);
 }
