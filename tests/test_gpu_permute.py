@@ -108,3 +108,30 @@ def test_long_rows_over_2pow20_columns(hp):
     C = hp.permute(A, p, q)
     torch.cuda.synchronize()
     assert_same(np_csr(C), oracle.permute(A, p, q), "permute")
+
+
+@pytest.mark.parametrize("ptr,vdt", [(torch.int32, torch.float32), (torch.int64, torch.float64)])
+def test_large_random_graph_both_widths(hp, ptr, vdt):
+    """Just over 2^20 rows of a random graph (0-10 entries a row): the whole
+    output equals the fused update with an empty block (a separate fill
+    path), sampled rows equal the oracle, and the inverse permutations
+    restore A."""
+    m = (1 << 20) + 12345
+    A = synth.erdos_renyi(m, m, 3.0, 91, "pb", ptr, vdt, "cuda")
+    p = synth.randperm(92, m, "cuda")
+    q = synth.randperm(93, m, "cuda")
+    C = hp.permute(A, p, q)
+    e = torch.zeros(0, dtype=torch.int32, device="cuda")
+    B0 = synth.CSR(0, 0, torch.zeros(1, dtype=ptr, device="cuda"), e, torch.zeros(0, dtype=vdt, device="cuda"))
+    F = hp.spasgn_permute(A, B0, e, e, p, q, "second")
+    torch.cuda.synchronize()
+    assert torch.equal(C.rowptr, F.rowptr) and torch.equal(C.col, F.col)
+    bits = torch.int64 if vdt == torch.float64 else torch.int32
+    assert torch.equal(C.val.view(bits), F.val.view(bits))
+    rows = sample_rows(94, m, 40)
+    assert_same(rows_of(C, rows), oracle.permute(A, p, q, rows=rows), "sampled rows")
+    pinv = torch.argsort(p.long()).to(torch.int32)
+    qinv = torch.argsort(q.long()).to(torch.int32)
+    R = hp.permute(C, pinv, qinv)
+    assert torch.equal(R.rowptr, A.rowptr) and torch.equal(R.col, A.col)
+    assert torch.equal(R.val.view(bits), A.val.view(bits))
