@@ -531,14 +531,25 @@ def _pctl(x, q):
 def run_served(hp, args):
     """Poisson arrivals (2,000 req/s by default), mix 60/20/20 spref / spasgn /
     permute over a resident pool; latency = completion - arrival.  The same
-    trace is replayed through the plain per-call path (one stream, FIFO)."""
-    import numpy as np
+    trace is replayed through the plain per-call path (one stream, FIFO).
+    With --served-rate2, the same at a second (overload) rate under
+    "overload"."""
     t = time.time()
     pool = _served_pool(args)
     var = _served_variants(pool)
     _sync()
     log(f"[bench] served: pool of {len(pool)} ({sum(A.nnz for A in pool)} nnz), generated in {time.time()-t:.1f}s")
-    arr = synth.poisson_arrivals(args.served_rate, args.served_seconds, 0, "served-arrivals").numpy()
+    res = _served_at(hp, args, pool, var, args.served_rate)
+    if args.served_rate2 > 0:
+        o = _served_at(hp, args, pool, var, args.served_rate2)
+        res["overload"] = {k: o[k] for k in ("value", "p50_ms", "p99_ms", "mean_batch", "failed", "plain")}
+        res["overload"]["rate"] = args.served_rate2
+    return res
+
+
+def _served_at(hp, args, pool, var, rate):
+    import numpy as np
+    arr = synth.poisson_arrivals(rate, args.served_seconds, 0, "served-arrivals").numpy()
     key = synth.stream_key(0, "served-trace")
     n = len(arr)
     u = synth.values(synth.stream_key(key, "kind"), n, torch.float64).numpy()
@@ -628,7 +639,7 @@ def run_served(hp, args):
                 config={"workload": "served", "desc": "Poisson %g req/s for %g s, 60/20/20 spref/spasgn/permute "
                         "on %d resident matrices (R-MAT ef16 sym / ER deg 16, scale U{16..%d}, int32/int64 "
                         "rowptr, fp32), %d streams, batches of at most %d, pool budget %d GB"
-                        % (args.served_rate, args.served_seconds, len(pool), args.served_scale_hi,
+                        % (rate, args.served_seconds, len(pool), args.served_scale_hi,
                            args.served_streams, args.served_max_batch, args.served_budget_gb),
                         "requests": n})
 
@@ -657,6 +668,8 @@ def main():
     ap.add_argument("--served-pool", type=int, default=32)
     ap.add_argument("--served-scale-hi", type=int, default=20)
     ap.add_argument("--served-rate", type=float, default=2000.0)
+    ap.add_argument("--served-rate2", type=float, default=4000.0,
+                    help="second, overload arrival rate for the served leg (0: skip)")
     ap.add_argument("--served-seconds", type=float, default=2.0)
     ap.add_argument("--served-streams", type=int, default=4)
     ap.add_argument("--served-budget-gb", type=int, default=64)
