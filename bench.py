@@ -412,6 +412,43 @@ def copy_calibration(mib):
     del src, dst
 
 
+def stream_copy_gbps(mib=1024, reps=5):
+    """Practical HBM ceiling: a plain device-to-device copy (bytes read +
+    written per second), timed with events on the current stream."""
+    n = mib << 20
+    src = torch.ones(n // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return round(2 * n / sec / 1e9, 1)
+
+
+def run_served_sweep(hp, args):
+    """The served trace at a series of arrival rates, beside the plain
+    per-call replay of each: where each path saturates."""
+    pool = _served_pool(args)
+    var = _served_variants(pool)
+    _sync()
+    pts = []
+    for rate in [float(x) for x in args.served_sweep.split(",")]:
+        r = _served_at(hp, args, pool, var, rate)
+        pts.append({"rate": rate, "req_per_s": round(r["value"], 1), "p50_ms": round(r["p50_ms"], 3),
+                    "p99_ms": round(r["p99_ms"], 3), "mean_batch": round(r["mean_batch"], 2),
+                    "plain_req_per_s": round(r["plain"]["req_per_s"], 1),
+                    "plain_p50_ms": round(r["plain"]["p50_ms"], 3), "plain_p99_ms": round(r["plain"]["p99_ms"], 3)})
+        log(f"[bench] served sweep {rate:g} req/s: {pts[-1]}")
+    last = pts[-1]
+    return dict(value=last["req_per_s"], unit="req/s", ms_per_step=1e3 / max(last["req_per_s"], 1e-9),
+                sweep=pts, config={"workload": "served-sweep", "rates": args.served_sweep})
+
+
 def _scanned(A, I):
     rp = A.rowptr.long()
     Il = I.long()
@@ -647,7 +684,8 @@ def _served_at(hp, args, pool, var, rate):
 WORKLOADS = {"rmat-extract": run_rmat_extract, "grid-permute": run_grid_permute,
              "grid-assign": run_grid_assign, "grid-assign-permute": run_grid_assign_permute,
              "incremental": run_incremental, "hypersparse-extract": run_hypersparse_extract,
-             "batched": run_batched, "served": run_served}
+             "batched": run_batched, "served": run_served, "served-sweep": run_served_sweep}
+EXTRAS_SKIP = {"served-sweep"}   # on request only (--workload served-sweep)
 
 
 def main():
@@ -668,6 +706,8 @@ def main():
     ap.add_argument("--served-pool", type=int, default=32)
     ap.add_argument("--served-scale-hi", type=int, default=20)
     ap.add_argument("--served-rate", type=float, default=2000.0)
+    ap.add_argument("--served-sweep", default="1000,2000,3000,4000,6000",
+                    help="arrival rates of --workload served-sweep")
     ap.add_argument("--served-rate2", type=float, default=4000.0,
                     help="second, overload arrival rate for the served leg (0: skip)")
     ap.add_argument("--served-seconds", type=float, default=2.0)
@@ -694,18 +734,19 @@ def main():
     also = {}
     if args.extras:
         for name, fn in WORKLOADS.items():
-            if name == args.workload:
+            if name == args.workload or name in EXTRAS_SKIP:
                 continue
             a2 = argparse.Namespace(**vars(args))
             a2.cpu_baseline = False
             r = fn(hp, a2)
             also[name] = {k: v for k, v in r.items() if k != "cpu_baseline"}
             log(f"[bench] {name}: {r['value']:.3e} {r['unit']}, {r['ms_per_step']:.3f} ms/step")
+    copy_gbps = stream_copy_gbps()
     out = {"metric": METRIC, "value": head["value"], "unit": head["unit"], "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
            "data": "synthetic", "config": head["config"], "roofline": head.get("roofline"),
-           "cpu_baseline": head.get("cpu_baseline")}
+           "cpu_baseline": head.get("cpu_baseline"), "stream_copy_GBps": copy_gbps}
     for k, v in head.items():
         if k not in out and k not in ("cpu_baseline",):
             out[k] = v
