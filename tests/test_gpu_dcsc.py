@@ -135,3 +135,33 @@ def test_hypersparse_full_size(hp):
         c, d = ep[s], ep[s + 1]
         assert np.array_equal(rows[a:b], er[c:d]), f"column {j}: rows"
         assert np.array_equal(bits(vals[a:b]), bits(ev[c:d])), f"column {j}: values"
+
+
+def test_argument_errors(hp):
+    """Malformed descriptors are rejected on the host, before any launch."""
+    _say("dcsc: argument errors")
+    A = synth.dcsc_uniform(100, 400, 200, 61, "t-arg", torch.int32, torch.float64, True, "cuda")
+    I = synth.subset(62, A.nrows, 20, device="cuda")
+    J = synth.subset(63, A.ncols, 30, device="cuda")
+    h = hp.handle(0)
+    Ad = hp.to_dcsc_t(A)
+    need = hp._SZ(0)
+    import ctypes
+    h.check(hp.hp_spref_dcsc_workspace(h.h, ctypes.byref(Ad), 20, 30, ctypes.byref(need)))
+    bad = hp.to_dcsc_t(A)
+    bad.dcsc = 2
+    assert hp.hp_spref_dcsc_workspace(h.h, ctypes.byref(bad), 20, 30, ctypes.byref(need)) == 1
+    bad = hp.to_dcsc_t(A)
+    bad.nzc = A.ncols + 1
+    assert hp.hp_spref_dcsc_workspace(h.h, ctypes.byref(bad), 20, 30, ctypes.byref(need)) == 1
+    bad = hp.to_dcsc_t(A)
+    bad.jc = None
+    assert hp.hp_spref_dcsc_workspace(h.h, ctypes.byref(bad), 20, 30, ctypes.byref(need)) == 1
+    C, ws, info = h.spref_dcsc_plan(A, I, J)
+    Cc = hp.to_dcsc_t(C)
+    Cc.dcsc = 1   # the output is CSC
+    Ac = hp.to_dcsc_t(A)
+    assert hp.hp_spref_dcsc_exec(h.h, ctypes.byref(Ac), hp._idx(I), 20, hp._idx(J), 30, ctypes.byref(Cc),
+                                 hp._dptr(ws), ws.numel(), ctypes.byref(info), None, 0) == 1
+    h.spref_dcsc_exec(A, I, J, C, ws, info)   # the proper call still works
+    assert C.nnz == oracle.spref_dcsc(A, I, J)[0][-1]

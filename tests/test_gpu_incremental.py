@@ -101,3 +101,15 @@ def test_full_size(env):
     assert torch.equal(r.C.rowptr, ref.rowptr) and torch.equal(r.C.col, ref.col)
     assert torch.equal(r.C.val.view(torch.int32), ref.val.view(torch.int32))
     assert r.imbalance[-1] < 1.5 < r.imbalance[0]
+
+
+def test_helper_errors(env):
+    hp, _ = env
+    h = hp.handle(0)
+    p = synth.randperm(5, 100, "cuda")
+    with pytest.raises(hp.HPError) as ex:   # out overlapping the map
+        h.gather_index(p, p[:10].clone(), out=p[50:60])
+    assert ex.value.name == "HP_ERR_ALIAS"
+    with pytest.raises(hp.HPError) as ex:
+        h.invert_perm(p, out=p)
+    assert ex.value.name == "HP_ERR_ALIAS"
