@@ -156,15 +156,19 @@ __global__ __launch_bounds__(SR_BLOCK) void k_spref_count(
     (void)ngb;
     spref_count_tile(blockIdx.x, SR_BIGBLOCKS, gs, acol, n, rs, rl, cp, nI, b2, jpos, Dn, cnt, hmS, hmB, capb, hdr);
 }
+// Five wavefronts per SIMD (at most 96 VGPRs; the fp32 staging area keeps
+// five workgroups in LDS): the gather is bound by the latency of its
+// dependent loads, and 4 -> 5 wavefronts took it from 218 to 195 us on the
+// R-MAT scale-22 extraction.  The count pass gained nothing from 6 -> 8.
 template <typename PT, typename VT>
-__global__ __launch_bounds__(SR_BLOCK) void k_spref_gather(
+__global__ __launch_bounds__(SR_BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void k_spref_gather(
     const int32_t *__restrict__ acol, const VT *__restrict__ aval, int64_t n,
     const int64_t *__restrict__ rs, const int32_t *__restrict__ rl, const int64_t *__restrict__ cp,
     int64_t nI, int64_t ngb, const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos,
     const int32_t *__restrict__ Dn, const PT *__restrict__ crow, int32_t *ccol, VT *cval, int32_t *cursor,
     const uint64_t *__restrict__ hmS, const uint64_t *__restrict__ hmB, int64_t capb, int sort_out,
     uint8_t *gflag, const DevHdr *hdr) {
-    __shared__ GroupSmem gs[SR_BLOCK / WAVE];
+    __shared__ GroupSmemT<VT> gs[SR_BLOCK / WAVE];
     (void)ngb;
     spref_gather_tile<PT, VT>(blockIdx.x, SR_BIGBLOCKS, gs, acol, aval, n, rs, rl, cp, nI, b2, jpos, Dn, crow,
                               ccol, cval, cursor, hmS, hmB, capb, sort_out != 0, gflag, hdr);

@@ -162,7 +162,7 @@ __device__ __forceinline__ int chain_len(int32_t v, const int32_t *Dn) {
 // Every slot's word of the 2-bit map is loaded (one divergent access per
 // slot, all issued before any is used, so the loads of a step overlap); the
 // chain walk only runs for repeated columns.
-__device__ __forceinline__ void step_mult(const int64_t (&c)[SR_U], const bool (&ok)[SR_U],
+__device__ __forceinline__ void step_mult(const int32_t (&c)[SR_U], const bool (&ok)[SR_U],
                                           const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos,
                                           const int32_t *__restrict__ Dn, int (&mm)[SR_U]) {
     uint32_t bw[SR_U];
@@ -189,14 +189,14 @@ __device__ __forceinline__ void step_mult(const int64_t (&c)[SR_U], const bool (
 // position; a negative one heads the chain of a repeated column).
 __device__ __forceinline__ void hits_from_mask(const uint64_t *__restrict__ w, const int32_t (&raw)[SR_U],
                                                int64_t n, const int32_t *__restrict__ jpos,
-                                               const int32_t *__restrict__ Dn, int64_t (&c)[SR_U],
+                                               const int32_t *__restrict__ Dn, int32_t (&c)[SR_U],
                                                int32_t (&jv)[SR_U], int (&mm)[SR_U]) {
     const int l = lane_id();
     bool hit[SR_U];
 #pragma unroll
     for (int u = 0; u < SR_U; u++) {
         hit[u] = (w[u] >> l) & 1ull;
-        c[u] = clampc(raw[u], n);
+        c[u] = (int32_t)clampc(raw[u], n);
     }
 #pragma unroll
     for (int u = 0; u < SR_U; u++) jv[u] = hit[u] ? jpos[c[u]] : 0;
@@ -234,10 +234,6 @@ __device__ __forceinline__ VT stage_val(uint64_t b) {
     else return (VT)(uint32_t)b;
 }
 
-struct GroupSmem;
-template <typename VT>
-__device__ __forceinline__ void stage_chain(int32_t x, VT v, int idx, int row, const int32_t *__restrict__ Dn,
-                                            GroupSmem &g);
 
 // Largest i in [0, n) with a[i] <= x, a nondecreasing and a[0] <= x; the
 // wavefront probes 64 positions per round (4 rounds for 2^24 entries).
@@ -301,27 +297,33 @@ struct GroupCore {               // per-wavefront state of a 64-row group
     int64_t crow[WAVE];
 };
 
-struct GroupSmem : GroupCore {   // the gather adds its staging area
+// SV holds the value bits: the value type itself in the plain kernel (an
+// fp32 matrix stages 4-byte values, so more wavefronts fit in LDS), 64 bits
+// in the batched kernel, which serves both widths from one layout.
+template <typename SV>
+struct GroupSmemT : GroupCore {  // the gather adds its staging area
     int32_t soff[WAVE];                 // staging offset of a staged row, else -1
     int32_t scnt[WAVE];                 // output entries of the row
     int32_t skey[SR_STAGE];
-    uint64_t sval[SR_STAGE];            // value bits (fp32 in the low half)
+    SV sval[SR_STAGE];
     uint8_t srow[SR_STAGE];
 };
+using GroupSmem = GroupSmemT<uint64_t>;
 
 // Like emit_chain, into the group's LDS staging area (with the row index).
-template <typename VT>
+template <typename VT, typename G>
 __device__ __forceinline__ void stage_chain(int32_t x, VT v, int idx, int row, const int32_t *__restrict__ Dn,
-                                            GroupSmem &g) {
+                                            G &g) {
+    using SV = decltype(+g.sval[0]);
     while (x < 0) {
         g.skey[idx] = ~x;
-        g.sval[idx] = (uint64_t)v;
+        g.sval[idx] = (SV)v;
         g.srow[idx] = (uint8_t)row;
         idx++;
         x = Dn[~x];
     }
     g.skey[idx] = x;
-    g.sval[idx] = (uint64_t)v;
+    g.sval[idx] = (SV)v;
     g.srow[idx] = (uint8_t)row;
 }
 
@@ -357,7 +359,8 @@ __device__ inline void spref_count_tile(
         g.cnt[l] = 0;
         __builtin_amdgcn_wave_barrier();
         for (int e0 = 0; e0 < E; e0 += SR_BW) {
-            int64_t k[SR_U], c[SR_U];
+            int64_t k[SR_U];
+            int32_t c[SR_U];
             int rr[SR_U], mm[SR_U];
             bool ok[SR_U];
 #pragma unroll
@@ -373,7 +376,7 @@ __device__ inline void spref_count_tile(
 #pragma unroll
             for (int u = 0; u < SR_U; u++) raw[u] = acol[k[u]];
 #pragma unroll
-            for (int u = 0; u < SR_U; u++) c[u] = clampc(raw[u], n);
+            for (int u = 0; u < SR_U; u++) c[u] = (int32_t)clampc(raw[u], n);
             step_mult(c, ok, b2, jpos, Dn, mm);
             uint64_t hm = 0;
 #pragma unroll
@@ -409,7 +412,7 @@ __device__ inline void spref_count_tile(
         }
         const int64_t b = (q - rbeg) * SR_BW;
         const int64_t e = min(b + SR_BW, rlen);
-        int64_t c[SR_U];
+        int32_t c[SR_U];
         int mm[SR_U];
         bool ok[SR_U];
         int32_t raw[SR_U];
@@ -420,7 +423,7 @@ __device__ inline void spref_count_tile(
             raw[u] = acol[base + (ok[u] ? kk : e - 1)];
         }
 #pragma unroll
-        for (int u = 0; u < SR_U; u++) c[u] = clampc(raw[u], n);
+        for (int u = 0; u < SR_U; u++) c[u] = (int32_t)clampc(raw[u], n);
         step_mult(c, ok, b2, jpos, Dn, mm);
         if (nbig <= capb) {
             uint64_t hm = 0;
@@ -446,9 +449,9 @@ __device__ inline void spref_count_tile(
 // its row is the row's running count plus the scan minus the scan at the
 // row's first lane in the slice.  Loads go in three rounds per step: columns
 // and values, bitmap words, then the J positions of the hits.
-template <typename PT, typename VT>
+template <typename PT, typename VT, typename G>
 __device__ inline void spref_gather_tile(
-    int64_t bid, int64_t nbw, GroupSmem *gs, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
+    int64_t bid, int64_t nbw, G *gs, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
     int64_t n, const int64_t *__restrict__ rs, const int32_t *__restrict__ rl, const int64_t *__restrict__ cp,
     int64_t nI, const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos,
     const int32_t *__restrict__ Dn, const PT *__restrict__ crow,
@@ -458,7 +461,7 @@ __device__ inline void spref_gather_tile(
     const int w = threadIdx.x / WAVE, l = lane_id();
     const uint64_t le_mask = (l == 63) ? ~0ull : ((2ull << l) - 1);
     if (bid >= nbw) {
-        GroupSmem &g = gs[w];
+        G &g = gs[w];
         const int64_t gw = (bid - nbw) * 4 + w;
         const int64_t i = gw * WAVE + l;
         int len = 0, nout = 0;
@@ -484,10 +487,14 @@ __device__ inline void spref_gather_tile(
         const int incl = wave_incl_scan(len);
         const int E = __shfl(incl, WAVE - 1, WAVE);
         g.start[l] = incl - len;
-        g.cnt[l] = 0;            // running output count per row
         __builtin_amdgcn_wave_barrier();
+        // Rows are contiguous in scan order, so only the row running across
+        // a slice boundary needs its hit count carried: `cur` is the row of
+        // the previous slice's last lane and `carry` its hits so far.
+        int carry = 0, cur = INT32_MIN;
         for (int e0 = 0; e0 < E; e0 += SR_BW) {
-            int64_t c[SR_U], k[SR_U];
+            int64_t k[SR_U];
+            int32_t c[SR_U];
             int rr[SR_U], mm[SR_U];
             bool ok[SR_U];
 #pragma unroll
@@ -510,35 +517,38 @@ __device__ inline void spref_gather_tile(
             hits_from_mask(hw, raw, n, jpos, Dn, c, jv, mm);
 #pragma unroll
             for (int u = 0; u < SR_U; u++) {
+                const int r = rr[u];
                 const int ex = wave_incl_scan(mm[u]) - mm[u];
-                const int prev_r = __shfl_up(rr[u], 1, WAVE);
-                const int next_r = __shfl_down(rr[u], 1, WAVE);
-                const bool is_start = l == 0 || prev_r != rr[u];
-                const bool is_last = l == WAVE - 1 || next_r != rr[u];
-                const uint64_t starts = ballot(is_start);
-                const int first = 63 - __clzll((long long)(starts & le_mask));
+                const int prev_r = __shfl_up(r, 1, WAVE);
+                const bool is_start = r != (l == 0 ? cur : prev_r);
+                const uint64_t mine = ballot(is_start) & le_mask;
+                const int first = mine ? 63 - __clzll((long long)mine) : 0;
                 const int base_ex = __shfl(ex, first, WAVE);
-                if (mm[u]) {
-                    const int r = rr[u];
-                    const int pos = g.cnt[r] + (ex - base_ex);
+                // position of the hit within its row: from the row's first
+                // lane in this slice, or after the carried hits
+                const int pos = mine ? ex - base_ex : carry + ex;
+                if (mm[u] && pos + mm[u] <= g.scnt[r]) {   // within the planned count
                     const int so = g.soff[r];
                     if (so >= 0) stage_chain<VT>(jv[u], v[u], so + pos, r, Dn, g);
                     else emit_chain<VT>(jv[u], v[u], g.crow[r] + pos, Dn, ccol, cval);
                 }
-                __builtin_amdgcn_wave_barrier();
-                if (rr[u] >= 0 && is_last) g.cnt[rr[u]] += ex + mm[u] - base_ex;
-                __builtin_amdgcn_wave_barrier();
+                carry = __shfl(pos + mm[u], WAVE - 1, WAVE);
+                cur = __shfl(r, WAVE - 1, WAVE);
             }
         }
         if (staging && stot > 0) {
             // every staged entry goes to its rank within its row
             __builtin_amdgcn_wave_barrier();
             for (int e = l; e < stot; e += WAVE) {
-                const int r = g.srow[e];
+                // (the masks and checks only matter if the inputs changed
+                // after the plan: every write stays inside its row)
+                const int r = g.srow[e] & (WAVE - 1);
                 const int s0 = g.soff[r], nr = g.scnt[r];
+                if (s0 < 0) continue;
                 const int32_t key = g.skey[e];
                 int rank = 0;
                 for (int q = 0; q < nr; q++) rank += g.skey[s0 + q] < key;
+                if (rank >= nr) continue;
                 const int64_t o = g.crow[r] + rank;
                 ccol[o] = key;
                 cval[o] = stage_val<VT>(g.sval[e]);
@@ -555,7 +565,7 @@ __device__ inline void spref_gather_tile(
     if (q0 >= q1) return;
     int64_t row = wave_search_le(cp, nI + 1, q0);
     int64_t rbeg = cp[row], rend = cp[row + 1], base = rs[row];
-    int64_t rlen = rl[row], orow = (int64_t)crow[row];
+    int64_t rlen = rl[row], orow = (int64_t)crow[row], oend = (int64_t)crow[row + 1];
     for (int64_t q = q0; q < q1; q++) {
         if (q >= rend) {
             row = next_chunk_row(cp, nI, row, q);
@@ -564,10 +574,11 @@ __device__ inline void spref_gather_tile(
             base = rs[row];
             rlen = rl[row];
             orow = (int64_t)crow[row];
+            oend = (int64_t)crow[row + 1];
         }
         const int64_t b = (q - rbeg) * SR_BW;
         const int64_t e = min(b + SR_BW, rlen);
-        int64_t c[SR_U];
+        int32_t c[SR_U];
         int mm[SR_U];
         bool ok[SR_U];
         int32_t raw[SR_U];
@@ -585,7 +596,7 @@ __device__ inline void spref_gather_tile(
             hits_from_mask(hmB + q * SR_U, raw, n, jpos, Dn, c, jv, mm);
         } else {
 #pragma unroll
-            for (int u = 0; u < SR_U; u++) c[u] = clampc(raw[u], n);
+            for (int u = 0; u < SR_U; u++) c[u] = (int32_t)clampc(raw[u], n);
             step_mult(c, ok, b2, jpos, Dn, mm);
 #pragma unroll
             for (int u = 0; u < SR_U; u++) jv[u] = mm[u] ? jpos[c[u]] : 0;
@@ -604,7 +615,7 @@ __device__ inline void spref_gather_tile(
         const int64_t ob = orow + cb;
 #pragma unroll
         for (int u = 0; u < SR_U; u++)
-            if (mm[u]) emit_chain<VT>(jv[u], v[u], ob + ex[u], Dn, ccol, cval);
+            if (mm[u] && ob + ex[u] + mm[u] <= oend) emit_chain<VT>(jv[u], v[u], ob + ex[u], Dn, ccol, cval);
     }
 }
 
