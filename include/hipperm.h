@@ -37,7 +37,9 @@
  *          It must get the same arguments, the same plan workspace (untouched
  *          in between) and the info struct of a plan call that returned
  *          HP_OK, plus an exec workspace of at least info->exec_ws_bytes
- *          (may be NULL when that is 0).
+ *          (may be NULL when that is 0).  Exec trusts the plan: the inputs
+ *          (A, B, the index vectors) must hold the same values as at plan
+ *          time, otherwise the behaviour is undefined.
  */
 #ifndef HIPPERM_H
 #define HIPPERM_H
