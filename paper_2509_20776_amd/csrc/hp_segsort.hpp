@@ -291,12 +291,21 @@ template <typename PT, typename VT, typename LD>
 __device__ void sort_small_tile(int64_t bid, SegSmemWave &sm, const PT *__restrict__ rowptr, int32_t *okey,
                                 VT *oval, int64_t nrows, const LD &ld, const DevHdr *hdr,
                                 const uint8_t *__restrict__ gflag = nullptr,
-                                const uint8_t *__restrict__ skip = nullptr) {
+                                const uint8_t *__restrict__ skip = nullptr,
+                                const int32_t *__restrict__ srows = nullptr, const uint64_t *nshort = nullptr) {
     if (hdr->err) return;
     const int w = threadIdx.x / WAVE, l = lane_id();
     const int64_t grp = bid * 4 + w;
-    if (gflag && (grp * WAVE >= nrows || !gflag[grp])) return;
-    const int64_t row = grp * WAVE + l;
+    // srows: the groups are 64 consecutive entries of this row list
+    // (*nshort of them) instead of 64 consecutive rows
+    const uint64_t nsv = srows ? *nshort : (uint64_t)nrows;
+    const int64_t ngrp = nsv < (uint64_t)nrows ? (int64_t)nsv : nrows;
+    if (gflag && (grp * WAVE >= ngrp || !gflag[grp])) return;
+    int64_t row = grp * WAVE + l;
+    if (srows) {
+        const int32_t r = row < ngrp ? srows[row] : -1;
+        row = (uint32_t)r < (uint64_t)nrows ? (int64_t)r : nrows;
+    }
     int len = 0;
     int64_t b = 0;
     if (row < nrows && !(skip && skip[row])) {
@@ -320,9 +329,10 @@ template <typename PT, typename VT, typename LD>
 __global__ __launch_bounds__(256) void k_sort_small(const PT *__restrict__ rowptr, int32_t *okey,
                                                    VT *oval, int64_t nrows, LD ld,
                                                    const DevHdr *hdr, const uint8_t *gflag = nullptr,
-                                                   const uint8_t *skip = nullptr) {
+                                                   const uint8_t *skip = nullptr, const int32_t *srows = nullptr,
+                                                   const uint64_t *nshort = nullptr) {
     __shared__ __align__(16) SegSmemWave sm;
-    sort_small_tile<PT, VT, LD>(blockIdx.x, sm, rowptr, okey, oval, nrows, ld, hdr, gflag, skip);
+    sort_small_tile<PT, VT, LD>(blockIdx.x, sm, rowptr, okey, oval, nrows, ld, hdr, gflag, skip, srows, nshort);
 }
 
 // ---- workgroup bitonic sort of one row of up to 8*T entries -----------------

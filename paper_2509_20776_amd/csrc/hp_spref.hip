@@ -50,6 +50,8 @@ struct SprefLayout {
     uint32_t *lists;
     uint64_t *hmS, *hmB;   // hit masks of the count pass (small-row steps, big-row chunks)
     uint8_t *gflag;        // 64-row groups left unsorted by the gather
+    int32_t *sflag, *spos; // DCSC: selected rows with 1..SR_LB entries (flags, scan) ...
+    int32_t *srows;        // ... compacted in row order; hdr->total[3] of them
     int64_t capb;          // big-row chunks the masks can hold
     size_t nzero, nw;
 };
@@ -59,7 +61,7 @@ SprefLayout spref_layout(Carve &c, int64_t n, int64_t nI, int64_t nJ, int64_t nn
     L.nw = (((size_t)((n + 31) / 32) + 1) + 3) & ~size_t(3);   // keeps cnt 16-byte aligned
     const size_t st = scan_tiles(nI);
     L.hdr = c.take<DevHdr>(1);
-    L.tiles = c.take<uint64_t>(2 * st);
+    L.tiles = c.take<uint64_t>(3 * st);
     const size_t markw = L.nw * 8;             // nw*32 bytes of marks
     L.nzero = markw + L.nw + (size_t)nI + NMSLOTS * 32 + 8;
     L.zero = c.take<uint32_t>(L.nzero);
@@ -82,6 +84,9 @@ SprefLayout spref_layout(Carve &c, int64_t n, int64_t nI, int64_t nJ, int64_t nn
     L.hmS = c.take<uint64_t>((size_t)hit_mask_small_words(nI));
     L.hmB = c.take<uint64_t>((size_t)L.capb * SR_U);
     L.gflag = c.take<uint8_t>((size_t)((nI + WAVE - 1) / WAVE) + 1);
+    L.sflag = c.take<int32_t>(nI + 1);
+    L.spos = c.take<int32_t>(nI + 1);
+    L.srows = c.take<int32_t>(nI + 1);
     return L;
 }
 
@@ -103,8 +108,12 @@ __global__ __launch_bounds__(256) void k_spref_jlink(const int32_t *__restrict__
 template <typename PT>
 __global__ __launch_bounds__(256) void k_spref_rows(const PT *__restrict__ arow, const int32_t *__restrict__ I,
                                                    int64_t nI, int64_t m, int64_t *rs, int32_t *rl, int32_t *ch,
-                                                   uint8_t *big, DevHdr *hdr, DcscIndex dx) {
-    spref_rows_tile<PT>(blockIdx.x, arow, I, nI, m, rs, rl, ch, big, hdr, dx);
+                                                   uint8_t *big, DevHdr *hdr, DcscIndex dx, int32_t *sflag) {
+    spref_rows_tile<PT>(blockIdx.x, arow, I, nI, m, rs, rl, ch, big, hdr, dx, sflag);
+}
+__global__ __launch_bounds__(256) void k_spref_compact(const int32_t *__restrict__ sflag,
+                                                      const int32_t *__restrict__ spos, int64_t nI, int32_t *srows) {
+    spref_compact_tile(blockIdx.x, sflag, spos, nI, srows);
 }
 
 // Stored rows per bucket of the doubly compressed index (ids outside
@@ -151,10 +160,12 @@ __global__ __launch_bounds__(SR_BLOCK) void k_spref_count(
     const int32_t *__restrict__ acol, int64_t n, const int64_t *__restrict__ rs,
     const int32_t *__restrict__ rl, const int64_t *__restrict__ cp, int64_t nI, int64_t ngb,
     const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn,
-    int32_t *cnt, uint64_t *hmS, uint64_t *hmB, int64_t capb, const DevHdr *hdr) {
+    int32_t *cnt, uint64_t *hmS, uint64_t *hmB, int64_t capb, const DevHdr *hdr, const int32_t *srows,
+    const uint64_t *nshort) {
     __shared__ GroupCore gs[SR_BLOCK / WAVE];
     (void)ngb;
-    spref_count_tile(blockIdx.x, SR_BIGBLOCKS, gs, acol, n, rs, rl, cp, nI, b2, jpos, Dn, cnt, hmS, hmB, capb, hdr);
+    spref_count_tile(blockIdx.x, SR_BIGBLOCKS, gs, acol, n, rs, rl, cp, nI, b2, jpos, Dn, cnt, hmS, hmB, capb, hdr,
+                     srows, nshort);
 }
 // Five wavefronts per SIMD (at most 96 VGPRs; the fp32 staging area keeps
 // five workgroups in LDS): the gather is bound by the latency of its
@@ -167,11 +178,11 @@ __global__ __launch_bounds__(SR_BLOCK) __attribute__((amdgpu_waves_per_eu(5))) v
     int64_t nI, int64_t ngb, const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos,
     const int32_t *__restrict__ Dn, const PT *__restrict__ crow, int32_t *ccol, VT *cval, int32_t *cursor,
     const uint64_t *__restrict__ hmS, const uint64_t *__restrict__ hmB, int64_t capb, int sort_out,
-    uint8_t *gflag, const DevHdr *hdr) {
+    uint8_t *gflag, const DevHdr *hdr, const int32_t *srows, const uint64_t *nshort) {
     __shared__ GroupSmemT<VT> gs[SR_BLOCK / WAVE];
     (void)ngb;
     spref_gather_tile<PT, VT>(blockIdx.x, SR_BIGBLOCKS, gs, acol, aval, n, rs, rl, cp, nI, b2, jpos, Dn, crow,
-                              ccol, cval, cursor, hmS, hmB, capb, sort_out != 0, gflag, hdr);
+                              ccol, cval, cursor, hmS, hmB, capb, sort_out != 0, gflag, hdr, srows, nshort);
 }
 
 hp_status_t spref_check_args(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int64_t nI,
@@ -200,6 +211,11 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
                          hp_plan_info_t *info, bool dcsc = false, const int32_t *jc = nullptr, int64_t nzc = 0) {
     const int64_t m = A->nrows, n = A->ncols;
     const int64_t nptr = dcsc ? nzc + 1 : m + 1;
+    // List the selected rows that have entries when most may have none (a
+    // DCSC matrix, or fewer stored entries than rows), so that count and
+    // gather skip the rest; elsewhere the scan and compaction would cost more
+    // than the empty rows.
+    const bool listed = dcsc || A->nnz < m;
     Carve need(nullptr);
     spref_layout(need, n, nI, nJ, A->nnz);
     const size_t base = need.size();
@@ -219,7 +235,7 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     const size_t st = scan_tiles(nI);
     hipStream_t s = h->stream;
     stage_begin(h);
-    hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, 2 * st);
+    hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, 3 * st);
     if (e == hipSuccess) e = launch_clear_words(s, L.zero, L.nzero);
     DcscIndex dx{nullptr, 0, nullptr, 0};
     if (dcsc && e == hipSuccess) {
@@ -245,16 +261,26 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
                            nJ, L.jpos, L.Dn, L.bm, L.dm, L.b2, (int64_t)L.nw);
         stage_mark(h, "spref.jtables");
         hipLaunchKernelGGL(k_spref_rows<PT>, dim3(grid1(nI)), dim3(256), 0, s, (const PT *)A->rowptr, I,
-                           nI, m, L.rs, L.rl, L.ch, L.big, L.hdr, dx);
+                           nI, m, L.rs, L.rl, L.ch, L.big, L.hdr, dx, listed ? L.sflag : nullptr);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = launch_scan_counts<int64_t>(s, L.ch, L.cp, nI, L.hdr, 0, L.tiles, 0, nullptr, 0);
+    // the short-row list (scan slots: 0 chunks, 1 counts, 2 the DCSC bucket
+    // index, 3 this list)
+    const int32_t *srows = listed ? L.srows : nullptr;
+    const uint64_t *d_nshort = &L.hdr->total[3];
+    if (listed && e == hipSuccess) {
+        e = launch_scan_counts<int32_t>(s, L.sflag, L.spos, nI, L.hdr, 3, L.tiles + 2 * st, 0, nullptr, 0);
+        if (e == hipSuccess && nI > 0)
+            hipLaunchKernelGGL(k_spref_compact, dim3(grid1(nI)), dim3(256), 0, s, (const int32_t *)L.sflag,
+                               (const int32_t *)L.spos, nI, L.srows);
+    }
     stage_mark(h, "spref.rows");
     const int64_t ngb = (nI + 4 * WAVE - 1) / (4 * WAVE);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_spref_count, dim3((unsigned)(ngb + SR_BIGBLOCKS)), dim3(SR_BLOCK), 0, s, A->col,
                            n, L.rs, L.rl, L.cp, nI, ngb, L.b2, L.jpos, L.Dn, L.cnt, L.hmS, L.hmB, L.capb,
-                           L.hdr);
+                           L.hdr, srows, d_nshort);
         stage_mark(h, "spref.count");
         e = hipGetLastError();
     }
@@ -280,6 +306,7 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
             info->class_elems[b] = (int64_t)H.bin_elems[b];
         }
         info->aux[1] = (int64_t)H.total[0];   // big-row chunks
+        info->aux[2] = listed ? (int64_t)H.total[3] : -1;   // listed short rows, or no list
         info->exec_ws_bytes = seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], H.bin_cnt[BIN_GLOBAL], vs, nJ);
     }
     return HP_OK;
@@ -311,15 +338,21 @@ hp_status_t spref_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     Carve c(ws);
     SprefLayout L = spref_layout(c, n, nI, nJ, A->nnz);
     hipStream_t s = h->stream;
-    const int64_t ngb = (nI + 4 * WAVE - 1) / (4 * WAVE);
+    // workgroups of four 64-row groups: over the plan's short-row list when
+    // it made one, else over all selected rows
+    const bool listed = info->aux[2] >= 0;
+    const int64_t nshort = listed ? std::min<int64_t>(info->aux[2], nI) : nI;
+    const int64_t ngs = (nshort + 4 * WAVE - 1) / (4 * WAVE);
+    const int32_t *srows = listed ? L.srows : nullptr;
+    const uint64_t *d_nshort = &L.hdr->total[3];
     hipError_t e = hipSuccess;
     if (info->aux[1] > 0) e = launch_clear_words(s, L.cursor, (size_t)nI);
     stage_begin(h);   // the gather stage is the gather kernel alone
     if (e == hipSuccess && info->nnz_out > 0) {
-        hipLaunchKernelGGL((k_spref_gather<PT, VT>), dim3((unsigned)(ngb + SR_BIGBLOCKS)), dim3(SR_BLOCK), 0,
-                           s, A->col, (const VT *)A->val, n, L.rs, L.rl, L.cp, nI, ngb, L.b2, L.jpos,
+        hipLaunchKernelGGL((k_spref_gather<PT, VT>), dim3((unsigned)(ngs + SR_BIGBLOCKS)), dim3(SR_BLOCK), 0,
+                           s, A->col, (const VT *)A->val, n, L.rs, L.rl, L.cp, nI, ngs, L.b2, L.jpos,
                            L.Dn, (const PT *)C->rowptr, C->col, (VT *)C->val, L.cursor, L.hmS, L.hmB, L.capb,
-                           info->map_monotone ? 0 : 1, L.gflag, L.hdr);
+                           info->map_monotone ? 0 : 1, L.gflag, L.hdr, srows, d_nshort);
         stage_mark(h, "spref.gather");
         e = hipGetLastError();
     }
@@ -327,10 +360,10 @@ hp_status_t spref_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
         uint32_t cnt[NBINS];
         for (int b = 0; b < NBINS; b++) cnt[b] = (uint32_t)info->rows_sorted[b];
         LoadInPlace<PT, VT> ld{(const PT *)C->rowptr, C->col, (const VT *)C->val};
-        if (!info->map_monotone)
-            hipLaunchKernelGGL((k_sort_small<PT, VT, LoadInPlace<PT, VT>>), dim3((unsigned)ngb), dim3(256), 0,
+        if (!info->map_monotone && ngs > 0)
+            hipLaunchKernelGGL((k_sort_small<PT, VT, LoadInPlace<PT, VT>>), dim3((unsigned)ngs), dim3(256), 0,
                                s, (const PT *)C->rowptr, C->col, (VT *)C->val, nI, ld, L.hdr,
-                               (const uint8_t *)L.gflag, (const uint8_t *)L.big);
+                               (const uint8_t *)L.gflag, (const uint8_t *)L.big, srows, d_nshort);
         e = launch_seg_classes<PT, VT, LoadInPlace<PT, VT>>(
             s, (const PT *)C->rowptr, C->col, (VT *)C->val, L.lists, nI, cnt, ld, false, nJ, true, xws,
             (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);

@@ -112,10 +112,16 @@ struct DcscIndex {
     int shift;
 };
 
+// sflag (optional): 1 for a selected row with 1..SR_LB entries, else 0.
+// Scanned and compacted into a row list, it lets the count and gather
+// passes walk only those rows in their 64-row groups, so the empty selected
+// rows (most of them, for a hypersparse matrix) cost nothing after this
+// pass.
 template <typename PT>
 __device__ inline void spref_rows_tile(int64_t bid, const PT *__restrict__ arow, const int32_t *__restrict__ I,
                                        int64_t nI, int64_t m, int64_t *rs, int32_t *rl, int32_t *ch, uint8_t *big,
-                                       DevHdr *hdr, DcscIndex dx = DcscIndex{nullptr, 0, nullptr, 0}) {
+                                       DevHdr *hdr, DcscIndex dx = DcscIndex{nullptr, 0, nullptr, 0},
+                                       int32_t *sflag = nullptr) {
     const int64_t i = bid * 256 + threadIdx.x;
     if (i >= nI) return;
     const int32_t r = I[i];
@@ -144,6 +150,32 @@ __device__ inline void spref_rows_tile(int64_t bid, const PT *__restrict__ arow,
     rl[i] = (int32_t)len;
     ch[i] = len > SR_LB ? (int32_t)((len + SR_BW - 1) / SR_BW) : 0;
     big[i] = len > SR_LB ? 1 : 0;
+    if (sflag) sflag[i] = (len > 0 && len <= SR_LB) ? 1 : 0;
+}
+
+// Compaction of the flagged rows: row i goes to srows[spos[i]] (spos the
+// exclusive scan of sflag), so the list is in row order.
+__device__ inline void spref_compact_tile(int64_t bid, const int32_t *__restrict__ sflag,
+                                          const int32_t *__restrict__ spos, int64_t nI, int32_t *srows) {
+    const int64_t i = bid * 256 + threadIdx.x;
+    if (i < nI && sflag[i]) srows[spos[i]] = (int32_t)i;
+}
+
+// Selected row of lane l in 64-row group gw: from the short list when there
+// is one (nI past its end or for an entry out of range), else gw*64 + l.
+__device__ __forceinline__ int64_t group_row(int64_t gw, int l, int64_t nI, const int32_t *__restrict__ srows,
+                                             int64_t nshort) {
+    const int64_t k = gw * WAVE + l;
+    if (!srows) return k;
+    if (k >= nshort) return nI;
+    const int32_t r = srows[k];
+    return (uint32_t)r < (uint64_t)nI ? (int64_t)r : nI;
+}
+
+// Length of the short-row list, never above nI.
+__device__ __forceinline__ int64_t list_len(const uint64_t *nshort, int64_t nI) {
+    const uint64_t v = *nshort;
+    return v < (uint64_t)nI ? (int64_t)v : nI;
 }
 
 // ---- shared pieces of count and gather -------------------------------------
@@ -336,13 +368,16 @@ __device__ inline void spref_count_tile(
     int64_t bid, int64_t nbw, GroupCore *gs, const int32_t *__restrict__ acol, int64_t n,
     const int64_t *__restrict__ rs, const int32_t *__restrict__ rl, const int64_t *__restrict__ cp, int64_t nI,
     const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn,
-    int32_t *cnt, uint64_t *hmS, uint64_t *hmB, int64_t capb, const DevHdr *hdr) {
+    int32_t *cnt, uint64_t *hmS, uint64_t *hmB, int64_t capb, const DevHdr *hdr,
+    const int32_t *__restrict__ srows = nullptr, const uint64_t *nshort = nullptr) {
     if (hdr->err) return;
     const int w = threadIdx.x / WAVE, l = lane_id();
     if (bid >= nbw) {
         GroupCore &g = gs[w];
         const int64_t gw = (bid - nbw) * 4 + w;
-        const int64_t i = gw * WAVE + l;
+        const int64_t ns = srows ? list_len(nshort, nI) : 0;
+        if (srows && gw * WAVE >= ns) return;
+        const int64_t i = group_row(gw, l, nI, srows, ns);
         int len = 0;
         bool small = false;
         if (i < nI) {
@@ -456,14 +491,17 @@ __device__ inline void spref_gather_tile(
     int64_t nI, const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos,
     const int32_t *__restrict__ Dn, const PT *__restrict__ crow,
     int32_t *ccol, VT *cval, int32_t *cursor, const uint64_t *__restrict__ hmS,
-    const uint64_t *__restrict__ hmB, int64_t capb, bool sort_out, uint8_t *gflag, const DevHdr *hdr) {
+    const uint64_t *__restrict__ hmB, int64_t capb, bool sort_out, uint8_t *gflag, const DevHdr *hdr,
+    const int32_t *__restrict__ srows = nullptr, const uint64_t *nshort = nullptr) {
     if (hdr->err) return;
     const int w = threadIdx.x / WAVE, l = lane_id();
     const uint64_t le_mask = (l == 63) ? ~0ull : ((2ull << l) - 1);
     if (bid >= nbw) {
         G &g = gs[w];
         const int64_t gw = (bid - nbw) * 4 + w;
-        const int64_t i = gw * WAVE + l;
+        const int64_t ns = srows ? list_len(nshort, nI) : 0;
+        if (srows && gw * WAVE >= ns) return;
+        const int64_t i = group_row(gw, l, nI, srows, ns);
         int len = 0, nout = 0;
         if (i < nI) {
             const int L = rl[i];

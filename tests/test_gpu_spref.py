@@ -86,6 +86,26 @@ def test_empty_sets(hp):
     assert_same(np_csr(hp.spref(A, allrows, _t(np.arange(60)))), np_csr(A), "identity extraction")
 
 
+@pytest.mark.parametrize("ptr", [torch.int32, torch.int64])
+def test_fewer_entries_than_rows(hp, ptr):
+    """A matrix with fewer stored entries than rows: the selected rows that
+    have entries are listed first and only they are walked (short and big
+    rows, repeated and unordered I and J, sorted and unsorted output); the
+    same selection on a denser matrix walks every row."""
+    lengths = [0] * 500 + [1, 5, 40, 300, 2]
+    A = mixed_csr(27, 40000, 3000, lengths, ptr, torch.float64)
+    assert A.nnz < A.nrows
+    I = synth.subset(28, A.nrows, 30000, repeat_frac=0.05, device="cuda")
+    J = synth.subset(29, A.ncols, 2000, repeat_frac=0.05, device="cuda")
+    assert_same(np_csr(hp.spref(A, I, J)), oracle.spref(A, I, J), "unsorted I, J")
+    Is, Js = torch.sort(I).values, torch.sort(torch.unique(J)).values
+    assert_same(np_csr(hp.spref(A, Is, Js)), oracle.spref(A, Is, Js), "sorted I, unique sorted J")
+    D = mixed_csr(30, 4000, 3000, [0, 1, 5, 40, 300, 2], ptr, torch.float64)
+    assert D.nnz >= D.nrows
+    I2 = synth.subset(31, D.nrows, 3000, repeat_frac=0.05, device="cuda")
+    assert_same(np_csr(hp.spref(D, I2, J)), oracle.spref(D, I2, J), "denser matrix")
+
+
 def test_errors_and_overflow(hp):
     A = mixed_csr(25, 20, 30, [4])
     with pytest.raises(hp.HPError) as e:
