@@ -105,6 +105,8 @@ __device__ inline void spref_jlink_tile(int64_t bid, const int32_t *__restrict__
 // jc[k] at arow[k].  bstart indexes them by bucket: the stored rows with
 // id >> shift == b are jc[bstart[b] .. bstart[b+1]).  bstart == nullptr:
 // plain row pointers.
+constexpr int DX_PROBE = 8;   // bucket sizes looked up without a search
+
 struct DcscIndex {
     const int32_t *jc;
     int64_t nzc;
@@ -132,15 +134,33 @@ __device__ inline void spref_rows_tile(int64_t bid, const PT *__restrict__ arow,
         const int32_t *jc = dx.jc;
         const int64_t nzc = dx.nzc;
         const int64_t b = r >> dx.shift;
-        int64_t lo = dx.bstart[b], hi = dx.bstart[b + 1];   // first stored row >= r in the bucket
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (jc[mid] < r) lo = mid + 1;
-            else hi = mid;
-        }
-        if (lo < nzc && jc[lo] == r) {
-            s = arow[lo];
-            len = arow[lo + 1] - s;
+        int64_t lo = dx.bstart[b], hi = dx.bstart[b + 1];
+        if (hi - lo <= DX_PROBE) {
+            // a bucket of at most DX_PROBE stored rows: their ids and row
+            // pointers are loaded together (both follow from the bucket
+            // bounds), so the lookup is two rounds of memory latency
+            int32_t cj[DX_PROBE];
+            PT cpv[DX_PROBE + 1];
+#pragma unroll
+            for (int t = 0; t < DX_PROBE; t++) cj[t] = lo + t < hi ? jc[lo + t] : -1;
+#pragma unroll
+            for (int t = 0; t <= DX_PROBE; t++) cpv[t] = lo + t <= hi ? arow[lo + t] : PT(0);
+#pragma unroll
+            for (int t = 0; t < DX_PROBE; t++)
+                if (cj[t] == r) {
+                    s = cpv[t];
+                    len = (int64_t)cpv[t + 1] - s;
+                }
+        } else {
+            while (lo < hi) {   // first stored row >= r in the bucket
+                const int64_t mid = (lo + hi) >> 1;
+                if (jc[mid] < r) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < nzc && jc[lo] == r) {
+                s = arow[lo];
+                len = arow[lo + 1] - s;
+            }
         }
     } else {
         s = arow[r];
