@@ -270,8 +270,14 @@ hipError_t readback_hdr(hp_handle_t h, DevHdr *dev) {
 // ===========================================================================
 size_t scan_tiles(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
 
+// Up to this many tiles the single pass is used (its look-back chains are
+// short); longer scans take three passes.
+constexpr int64_t SCAN_ONEPASS_TILES = 256;
+
+// Four wavefronts per SIMD (at most 128 VGPRs): left alone the compiler
+// keeps all 16 staged values of a lane in flight and drops to two.
 template <typename PT>
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_counts(
+__global__ __launch_bounds__(SCAN_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_scan_counts(
     const int32_t *__restrict__ cnt, PT *__restrict__ out, int64_t n, DevHdr *hdr, int slot,
     uint64_t *tile_state, int classify, uint32_t *lists, int64_t cap, uint64_t *goff,
     const uint8_t *__restrict__ force, const uint32_t *__restrict__ nmslots) {
@@ -281,6 +287,31 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_counts(
     __syncthreads();
     scan_counts_tile<PT>(s_tile, sm, cnt, out, n, hdr, slot, tile_state, classify, lists, cap, goff, force,
                          nmslots);
+}
+
+// Three-pass form for long scans: tile sums, one workgroup scanning them,
+// then every tile scans its counts from its prefix.  The single pass spends
+// its time in look-back chains once there are thousands of tiles (16.8M
+// counts: 145 us single pass).
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int32_t *__restrict__ cnt, int64_t n,
+                                                           uint64_t *partial) {
+    __shared__ uint64_t s_wave[SCAN_BLOCK / WAVE];
+    scan_reduce_tile(blockIdx.x, s_wave, cnt, n, partial);
+}
+
+__global__ __launch_bounds__(PSCAN_BLOCK) void k_scan_partials(uint64_t *partial, int64_t ntiles) {
+    __shared__ uint64_t s_wave[PSCAN_BLOCK / WAVE];
+    scan_partials_block(s_wave, partial, ntiles);
+}
+
+template <typename PT>
+__global__ __launch_bounds__(SCAN_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_scan_down(
+    const int32_t *__restrict__ cnt, PT *__restrict__ out, int64_t n, DevHdr *hdr, int slot,
+    const uint64_t *__restrict__ prefix, int classify, uint32_t *lists, int64_t cap, uint64_t *goff,
+    const uint8_t *__restrict__ force, const uint32_t *__restrict__ nmslots) {
+    __shared__ ScanSmem sm;
+    scan_counts_tile<PT>(blockIdx.x, sm, cnt, out, n, hdr, slot, nullptr, classify, lists, cap, goff, force,
+                         nmslots, prefix);
 }
 
 template <typename PT>
@@ -301,6 +332,14 @@ hipError_t launch_scan_counts(hipStream_t s, const int32_t *cnt, PT *out, int64_
     }
     int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     uint64_t *goff = bin_lists ? reinterpret_cast<uint64_t *>(bin_lists + NBINS * bin_cap) : nullptr;
+    if (tiles > SCAN_ONEPASS_TILES) {
+        // tile_state (scan_tiles(n) words) holds the tile sums, then prefixes
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, cnt, n, tile_state);
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(PSCAN_BLOCK), 0, s, tile_state, tiles);
+        hipLaunchKernelGGL(k_scan_down<PT>, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, cnt, out, n, hdr, slot,
+                           (const uint64_t *)tile_state, classify, bin_lists, bin_cap, goff, force, nmslots);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_scan_counts<PT>, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, cnt, out, n,
                        hdr, slot, tile_state, classify, bin_lists, bin_cap, goff, force, nmslots);
     return hipGetLastError();

@@ -42,23 +42,37 @@ __device__ __forceinline__ int class_of(int64_t len, int mode, bool all, bool fl
     return BIN_GLOBAL;
 }
 
+// Per-wavefront staging of its WAVE*SCAN_ITEMS counts (and later its
+// outputs): read and written 64-wide in index order, used 16 consecutive
+// per lane.  One pad word per 16 keeps both patterns free of bank
+// conflicts.
+constexpr int SCAN_SEG = WAVE * SCAN_ITEMS;
+constexpr int SCAN_STAGE = SCAN_SEG + SCAN_SEG / 16;
+static_assert(SCAN_ITEMS == 16, "the staging offsets below assume 16 counts a lane");
+// word of count j (j + j/16): lane l's item k sits at 17*l + k; the k-th
+// 64-wide row at 68*k + l + l/16 (constant offsets from one base each)
+
 struct ScanSmem {
     uint64_t wave[SCAN_BLOCK / WAVE];
     uint64_t excl;
     uint32_t bc[NBINS], bbase[NBINS];
     unsigned long long ge, gbase;
     int all;
+    uint64_t stage[SCAN_BLOCK / WAVE][SCAN_STAGE];
 };
 
-// One tile of the single-pass exclusive scan of n int32 counts into out
-// (PT, n+1 entries).  Tiles must be started in increasing order (the
-// caller's ticket) so that a tile only waits on running tiles.
+// One tile of the exclusive scan of n int32 counts into out (PT, n+1
+// entries).  Single pass (tile_prefix == nullptr): tiles must be started in
+// increasing order (the caller's ticket) so that a tile only waits on
+// running tiles.  Second pass of the three-pass form: tile_prefix[tile] is
+// the tile's exclusive prefix, and no tile waits.
 template <typename PT>
 __device__ void scan_counts_tile(int64_t tile, ScanSmem &sm, const int32_t *__restrict__ cnt,
                                  PT *__restrict__ out, int64_t n, DevHdr *hdr, int slot,
                                  uint64_t *tile_state, int classify, uint32_t *lists, int64_t cap,
                                  uint64_t *goff, const uint8_t *__restrict__ force,
-                                 const uint32_t *__restrict__ nmslots) {
+                                 const uint32_t *__restrict__ nmslots,
+                                 const uint64_t *__restrict__ tile_prefix = nullptr) {
     uint64_t *s_wave = sm.wave;
     uint64_t &s_excl = sm.excl;
     uint32_t *s_bc = sm.bc, *s_bbase = sm.bbase;
@@ -75,31 +89,38 @@ __device__ void scan_counts_tile(int64_t tile, ScanSmem &sm, const int32_t *__re
         if (threadIdx.x == 0) s_all = any != 0;
     }
     __syncthreads();
-    const int64_t base = tile * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-    int32_t v[SCAN_ITEMS];
-    if (base + SCAN_ITEMS <= n) {
-        const int4 *p4 = reinterpret_cast<const int4 *>(cnt + base);
-        int4 a[SCAN_ITEMS / 4];
+    // Wavefront w owns the SCAN_SEG consecutive counts from seg; lane l
+    // works on 16 consecutive ones (seg + l*16 + k), and the loads and
+    // stores go 64-wide in index order through the wavefront's staging area.
+    const int w = threadIdx.x / WAVE, l = lane_id();
+    const int64_t seg = tile * SCAN_TILE + (int64_t)w * SCAN_SEG;
+    uint32_t *st32 = reinterpret_cast<uint32_t *>(sm.stage[w]);
+    const int rowb = l + (l >> 4), lanb = 17 * l;
+    if (seg + SCAN_SEG <= n) {
+        const int32_t *src = cnt + seg + l;
 #pragma unroll
-        for (int q = 0; q < SCAN_ITEMS / 4; q++) a[q] = p4[q];
-#pragma unroll
-        for (int q = 0; q < SCAN_ITEMS / 4; q++) {
-            v[4 * q] = a[q].x;
-            v[4 * q + 1] = a[q].y;
-            v[4 * q + 2] = a[q].z;
-            v[4 * q + 3] = a[q].w;
-        }
+        for (int k = 0; k < SCAN_ITEMS; k++) st32[rowb + 68 * k] = (uint32_t)src[k * WAVE];
     } else {
-#pragma unroll
-        for (int k = 0; k < SCAN_ITEMS; k++) v[k] = (base + k < n) ? cnt[base + k] : 0;
+        for (int k = 0; k < SCAN_ITEMS; k++) {
+            const int64_t idx = seg + k * WAVE + l;
+            st32[rowb + 68 * k] = idx < n ? (uint32_t)cnt[idx] : 0u;
+        }
     }
+    __builtin_amdgcn_wave_barrier();
+    int32_t v[SCAN_ITEMS];
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) v[k] = (int32_t)st32[lanb + k];
+    __builtin_amdgcn_wave_barrier();
+    const int64_t base = seg + (int64_t)l * SCAN_ITEMS;   // this lane's first count
     uint64_t tsum = 0;
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; k++) tsum += (uint64_t)(uint32_t)v[k];
     uint64_t tile_total;
     uint64_t texcl = block_excl_scan<SCAN_BLOCK, uint64_t>(tsum, s_wave, tile_total);
 
-    if (threadIdx.x < WAVE) {
+    if (tile_prefix) {
+        if (threadIdx.x == 0) s_excl = tile_prefix[tile];
+    } else if (threadIdx.x < WAVE) {
         // publish this tile's aggregate, then look back for its prefix
         if (lane_id() == 0)
             st_agent(&tile_state[tile], (tile == 0 ? ST_PRE : ST_AGG) | (tile_total & ST_VAL));
@@ -139,11 +160,25 @@ __device__ void scan_counts_tile(int64_t tile, ScanSmem &sm, const int32_t *__re
         if (lane_id() == 0) s_excl = excl;
     }
     __syncthreads();
-    uint64_t run = s_excl + texcl;
+    {
+        uint64_t *st64 = sm.stage[w];
+        uint64_t run = s_excl + texcl;
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; k++) {
-        if (base + k < n) out[base + k] = (PT)run;
-        run += (uint32_t)v[k];
+        for (int k = 0; k < SCAN_ITEMS; k++) {
+            st64[lanb + k] = run;
+            run += (uint32_t)v[k];
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (seg + SCAN_SEG <= n) {
+            PT *dst = out + seg + l;
+#pragma unroll
+            for (int k = 0; k < SCAN_ITEMS; k++) dst[k * WAVE] = (PT)st64[rowb + 68 * k];
+        } else {
+            for (int k = 0; k < SCAN_ITEMS; k++) {
+                const int64_t idx = seg + k * WAVE + l;
+                if (idx < n) out[idx] = (PT)st64[rowb + 68 * k];
+            }
+        }
     }
     const int64_t last_base = (n - 1) / SCAN_TILE;
     if (tile == last_base && threadIdx.x == SCAN_BLOCK - 1) {
@@ -162,8 +197,9 @@ __device__ void scan_counts_tile(int64_t tile, ScanSmem &sm, const int32_t *__re
         unsigned long long eoff[SCAN_ITEMS];
 #pragma unroll
         for (int k = 0; k < SCAN_ITEMS; k++) {
-            const bool valid = base + k < n;
-            const bool fl = (classify == 3 || classify == 4) && valid ? force[base + k] != 0 : false;
+            const int64_t idx = base + k;
+            const bool valid = idx < n;
+            const bool fl = (classify == 3 || classify == 4) && valid ? force[idx] != 0 : false;
             bin[k] = valid ? class_of(v[k], classify, all, fl) : -1;
             off[k] = 0;
             eoff[k] = 0;
@@ -189,6 +225,49 @@ __device__ void scan_counts_tile(int64_t tile, ScanSmem &sm, const int32_t *__re
         }
     }
     __syncthreads();
+}
+
+// First pass of the three-pass form: the sum of the tile's counts (the
+// same SCAN_TILE counts as scan_counts_tile, read in 64-wide rows) into
+// partial[tile].
+__device__ inline void scan_reduce_tile(int64_t tile, uint64_t *s_wave, const int32_t *__restrict__ cnt, int64_t n,
+                                        uint64_t *partial) {
+    const int64_t base = tile * SCAN_TILE + threadIdx.x;
+    uint64_t tsum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        const int64_t idx = base + (int64_t)k * SCAN_BLOCK;
+        tsum += idx < n ? (uint64_t)(uint32_t)cnt[idx] : 0;
+    }
+    uint64_t total;
+    (void)block_excl_scan<SCAN_BLOCK, uint64_t>(tsum, s_wave, total);
+    if (threadIdx.x == 0) partial[tile] = total;
+}
+
+// Middle pass: exclusive scan of the ntiles partial sums in place, by one
+// workgroup of PSCAN_BLOCK threads, PSCAN_ITEMS consecutive sums a thread per
+// round.
+constexpr int PSCAN_BLOCK = 1024;
+constexpr int PSCAN_ITEMS = 8;
+__device__ inline void scan_partials_block(uint64_t *s_wave, uint64_t *partial, int64_t ntiles) {
+    uint64_t run = 0;
+    for (int64_t c0 = 0; c0 < ntiles; c0 += (int64_t)PSCAN_BLOCK * PSCAN_ITEMS) {
+        const int64_t b = c0 + (int64_t)threadIdx.x * PSCAN_ITEMS;
+        uint64_t v[PSCAN_ITEMS], t = 0;
+#pragma unroll
+        for (int k = 0; k < PSCAN_ITEMS; k++) {
+            v[k] = b + k < ntiles ? partial[b + k] : 0;
+            t += v[k];
+        }
+        uint64_t tot;
+        uint64_t x = run + block_excl_scan<PSCAN_BLOCK, uint64_t>(t, s_wave, tot);
+#pragma unroll
+        for (int k = 0; k < PSCAN_ITEMS; k++) {
+            if (b + k < ntiles) partial[b + k] = x;
+            x += v[k];
+        }
+        run += tot;
+    }
 }
 
 }  // namespace hp
