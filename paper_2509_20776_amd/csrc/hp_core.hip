@@ -1,6 +1,6 @@
 // Handle, status, timing, and the shared kernels: status-block init, the
-// single-pass exclusive scan with row classification, and the segmented
-// sort used by every operation's Build step.
+// exclusive scan with row classification, and the segmented sort used by
+// every operation's Build step.
 #include "hp_internal.hpp"
 #include "hp_scan.hpp"
 
@@ -261,12 +261,13 @@ hipError_t readback_hdr(hp_handle_t h, DevHdr *dev) {
 }
 
 // ===========================================================================
-// Single-pass exclusive scan (decoupled look-back) with row classification.
+// Exclusive scan with row classification: single pass (decoupled look-back)
+// up to SCAN_ONEPASS_TILES tiles, three passes above.
 //
-// Tiles are taken in launch order from an atomic ticket, so a tile only ever
-// waits on tiles that are already running: every wait ends.  The wait is
-// still bounded (SCAN_WAIT_TICKS); reaching it raises E_TIMEOUT and the kernel
-// finishes normally.
+// In the single pass, tiles are taken in launch order from an atomic ticket,
+// so a tile only ever waits on tiles that are already running: every wait
+// ends.  The wait is still bounded (SCAN_WAIT_TICKS); reaching it raises
+// E_TIMEOUT and the kernel finishes normally.  The three passes never wait.
 // ===========================================================================
 size_t scan_tiles(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
 

@@ -3,8 +3,8 @@
 // Identify (Sec. 4.2 Step 1): the index/value swap of p and q gives pinv
 // and qinv; the destination of source row r is output row pinv[r] and of
 // column c is qinv[c].  On one GPU the Exchange step disappears, and the
-// paper's two-pass count / prefix / scatter becomes count -> single-pass
-// scan -> fill, with the Build-step sort folded into the fill:
+// paper's two-pass count / prefix / scatter becomes count -> scan -> fill,
+// with the Build-step sort folded into the fill:
 //   plan : fill -1      pinv, qinv
 //          k_perm_prepare  scatter pinv, qinv; per-output-row counts; range
 //          k_perm_check    no slot left at -1 (every value occurs once)

@@ -1,11 +1,13 @@
-// Single-pass exclusive scan (decoupled look-back) with row classification,
-// as a tile function shared by the plain per-call kernels and the batched
-// persistent kernel.
+// Exclusive scan with row classification, as tile functions shared by the
+// plain per-call kernels and the batched persistent kernel: the single-pass
+// tile (decoupled look-back), and the pieces of the three-pass form for long
+// scans (tile sums, their scan, the tile pass from a given prefix).
 //
-// Tiles are started in launch order (an atomic ticket in the plain kernel,
-// the batch queue order otherwise), so a tile only ever waits on tiles that
-// are already running: every wait ends.  The wait is still bounded
-// (SCAN_WAIT_TICKS); reaching it raises E_TIMEOUT and the kernel finishes.
+// Single-pass tiles are started in launch order (an atomic ticket in the
+// plain kernel, the batch queue order otherwise), so a tile only ever waits
+// on tiles that are already running: every wait ends.  The wait is still
+// bounded (SCAN_WAIT_TICKS); reaching it raises E_TIMEOUT and the kernel
+// finishes.
 #pragma once
 #include "hp_internal.hpp"
 
