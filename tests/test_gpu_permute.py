@@ -135,3 +135,42 @@ def test_large_random_graph_both_widths(hp, ptr, vdt):
     R = hp.permute(C, pinv, qinv)
     assert torch.equal(R.rowptr, A.rowptr) and torch.equal(R.col, A.col)
     assert torch.equal(R.val.view(bits), A.val.view(bits))
+
+
+def _banded_csr(m, seed, ptr):
+    """m x m CSR with 0-3 entries a row, columns ascending (entry k of row r
+    sits in the k-th quarter of the columns), built on the GPU."""
+    g = torch.Generator().manual_seed(seed)
+    lens = torch.randint(0, 4, (m,), generator=g, dtype=torch.int64).cuda()
+    rowptr = torch.zeros(m + 1, dtype=torch.int64, device="cuda")
+    rowptr[1:] = torch.cumsum(lens, 0)
+    nnz = int(rowptr[-1])
+    row = torch.repeat_interleave(torch.arange(m, device="cuda"), lens)
+    k = torch.arange(nnz, device="cuda") - rowptr[row]
+    quarter = m // 4
+    col = (k * quarter + (row * 2654435761) % quarter).to(torch.int32)
+    val = torch.rand(nnz, generator=g).cuda()
+    return synth.CSR(m, m, rowptr.to(ptr), col, val), lens
+
+
+@pytest.mark.parametrize("m,ptr", [(256 * 4096, torch.int64), (256 * 4096 + 1, torch.int32),
+                                   (8192 * 4096 + 777, torch.int64)])
+def test_scan_sizes(hp, m, ptr):
+    """Row-pointer scans at the single-pass limit (256 tiles of 4096 counts),
+    just above it (three passes), and above 8192 tiles (the tile sums are
+    scanned in more than one round): C's row pointers equal a cumulative
+    sum of the permuted row lengths, sampled rows equal the oracle, and the
+    inverse permutation restores A."""
+    A, lens = _banded_csr(m, 101, ptr)
+    p = synth.randperm(102, m, "cuda")
+    C = hp.permute(A, p)
+    torch.cuda.synchronize()
+    exp = torch.zeros(m + 1, dtype=torch.int64, device="cuda")
+    exp[1:] = torch.cumsum(lens[p.long()], 0)
+    assert torch.equal(C.rowptr.long(), exp)
+    rows = sample_rows(103, m, 24)
+    assert_same(rows_of(C, rows), oracle.permute(A, p, rows=rows), "sampled rows")
+    pinv = torch.argsort(p.long()).to(torch.int32)
+    R = hp.permute(C, pinv)
+    assert torch.equal(R.rowptr, A.rowptr) and torch.equal(R.col, A.col)
+    assert torch.equal(R.val.view(torch.int32), A.val.view(torch.int32))
