@@ -16,9 +16,11 @@
 // Every selected row I[i] is then streamed twice: once to count its hits
 // (with multiplicity: a column selected k times yields k entries), once in
 // exec to write them.  Work is split per wavefront:
-//   row groups  64 consecutive rows of <= SR_LB entries; a wave-local
-//               merge path assigns 8 entries per lane per step; hits are
-//               written in scan order (so already sorted when J increases);
+//   row groups  64 consecutive selected rows of <= SR_LB entries (or 64
+//               consecutive entries of the list of selected rows that have
+//               entries, when most may have none); a wave-local merge path
+//               assigns 8 entries per lane per step; hits are written in
+//               scan order (so already sorted when J increases);
 //   big rows    chunks of SR_BW entries, one wavefront each, located with a
 //               cooperative 64-ary search over the chunk prefix; each chunk
 //               reserves its block of the row with an atomic cursor, and big
