@@ -165,3 +165,29 @@ def test_argument_errors(hp):
                                  hp._dptr(ws), ws.numel(), ctypes.byref(info), None, 0) == 1
     h.spref_dcsc_exec(A, I, J, C, ws, info)   # the proper call still works
     assert C.nnz == oracle.spref_dcsc(A, I, J)[0][-1]
+
+
+@pytest.mark.parametrize("ptr", [torch.int32, torch.int64])
+def test_crowded_and_sparse_buckets(hp, ptr):
+    """Stored columns packed at the low ids (hundreds per bucket of the
+    column index: the searched lookup) and scattered over the rest (a few
+    per bucket: the loaded-together lookup), against the oracle."""
+    m, n = 3000, 100_000
+    dense = mixed_csr(71, 1000, m, [0, 1, 4, 30, 300], ptr, torch.float64)   # columns 0..999 as rows of A^T
+    rng = np.random.default_rng(72)
+    far = np.sort(rng.choice(np.arange(1000, n), 600, replace=False)).astype(np.int32)
+    far_rows = [np.sort(rng.choice(m, int(k), replace=False)).astype(np.int32) for k in rng.integers(1, 6, far.size)]
+    dp = dense.rowptr.cpu().numpy().astype(np.int64)
+    keep = np.nonzero(np.diff(dp))[0].astype(np.int32)          # stored (non-empty) low columns
+    jc = np.concatenate([keep, far])
+    cnt = np.concatenate([np.diff(dp)[keep], [len(r) for r in far_rows]]).astype(np.int64)
+    colptr = np.zeros(jc.size + 1, dtype=np.int64)
+    colptr[1:] = np.cumsum(cnt)
+    row = np.concatenate([dense.col.cpu().numpy()] + far_rows).astype(np.int32)
+    val = synth.values(synth.stream_key(73, "crowded"), row.size, torch.float64)
+    A = synth.DCSC(m, n, torch.as_tensor(jc, device="cuda"), torch.as_tensor(colptr).to(ptr).cuda(),
+                   torch.as_tensor(row, device="cuda"), val.cuda())
+    I = synth.subset(74, m, 1500, repeat_frac=0.05, device="cuda")
+    J = torch.as_tensor(np.concatenate([rng.integers(0, 1000, 3000), rng.choice(far, 400),
+                                        rng.integers(1000, n, 3000)]).astype(np.int32), device="cuda")
+    _same(_np(hp.spref_dcsc(A, I, J)), oracle.spref_dcsc(A, I, J), "crowded and sparse buckets")
