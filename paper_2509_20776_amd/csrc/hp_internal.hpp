@@ -88,6 +88,19 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
     }
     return v;
 }
+// 32-bit counts: data-parallel-primitive moves instead of LDS permutes:
+// row shifts 1, 2, 4, 8 scan each row of 16 lanes, then row broadcasts of
+// lanes 15 and 31 carry the row totals (lanes shifted in from outside a
+// row read 0).  Every lane of the wavefront must be active.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 -> rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 -> rows 2, 3
+    return v;
+}
 
 // Exclusive scan over a workgroup of BLOCK threads; returns the exclusive
 // prefix of `v` and writes the block total.  Uses BLOCK/64 words of LDS.

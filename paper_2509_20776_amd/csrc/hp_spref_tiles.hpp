@@ -596,8 +596,8 @@ __device__ inline void spref_gather_tile(
                     if (so >= 0) stage_chain<VT>(jv[u], v[u], so + pos, r, Dn, g);
                     else emit_chain<VT>(jv[u], v[u], g.crow[r] + pos, Dn, ccol, cval);
                 }
-                carry = __shfl(pos + mm[u], WAVE - 1, WAVE);
-                cur = __shfl(r, WAVE - 1, WAVE);
+                carry = __builtin_amdgcn_readlane(pos + mm[u], WAVE - 1);
+                cur = __builtin_amdgcn_readlane(r, WAVE - 1);
             }
         }
         if (staging && stot > 0) {
