@@ -98,6 +98,38 @@ __device__ __forceinline__ void lane_sort_row(const LD &ld, int64_t sb, int len,
     sort_store_regs<16, VT>(k, v, len, sorted, okey, oval);
 }
 
+// Value held by lane l ^ d (d a power of two below 64; every lane of the
+// wavefront active).  Distances 1 and 2 are DPP quad permutes, 4 and 8 DPP
+// row shifts with a select (the partner is in the same row of 16 lanes);
+// larger distances go through LDS permutes.
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t v, int d) {
+    const int iv = (int)v;
+    const int l = lane_id();
+    if (d == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, iv, 0xB1, 0xf, 0xf, false);   // quad [1,0,3,2]
+    if (d == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, iv, 0x4E, 0xf, 0xf, false);   // quad [2,3,0,1]
+    if (d == 4) {
+        const int up = __builtin_amdgcn_update_dpp(0, iv, 0x104, 0xf, 0xf, false);   // row_shl:4
+        const int dn = __builtin_amdgcn_update_dpp(0, iv, 0x114, 0xf, 0xf, false);   // row_shr:4
+        return (uint32_t)((l & 4) ? dn : up);
+    }
+    if (d == 8) {
+        const int up = __builtin_amdgcn_update_dpp(0, iv, 0x108, 0xf, 0xf, false);   // row_shl:8
+        const int dn = __builtin_amdgcn_update_dpp(0, iv, 0x118, 0xf, 0xf, false);   // row_shr:8
+        return (uint32_t)((l & 8) ? dn : up);
+    }
+    return (uint32_t)__shfl_xor(iv, d, WAVE);
+}
+template <typename W>
+__device__ __forceinline__ W lane_xor(W v, int d) {
+    if constexpr (sizeof(W) == 8) {
+        const uint64_t u = (uint64_t)v;
+        const uint64_t lo = lane_xor32((uint32_t)u, d), hi = lane_xor32((uint32_t)(u >> 32), d);
+        return (W)(lo | (hi << 32));
+    } else {
+        return (W)lane_xor32((uint32_t)v, d);
+    }
+}
+
 // Bitonic sorting network over 64*E 32-bit words held E per lane (element
 // e = l*E + q), ascending.  Partners e ^ j with j < E sit in the same lane;
 // larger j are lane distance j/E apart, swapped through cross-lane shuffles.
@@ -123,7 +155,7 @@ __device__ __forceinline__ void bitonic_wave(uint32_t (&x)[E]) {
                 const bool keep_min = (((l * E) & k) == 0) == (((l * E) & j) == 0);
 #pragma unroll
                 for (int q = 0; q < E; q++) {
-                    const uint32_t o = (uint32_t)__shfl_xor((int)x[q], j / E, WAVE);
+                    const uint32_t o = lane_xor32(x[q], j / E);
                     x[q] = keep_min ? (o < x[q] ? o : x[q]) : (o < x[q] ? x[q] : o);
                 }
             }
@@ -368,11 +400,7 @@ __device__ __forceinline__ void bitonic_block(W (&x)[E], W *s_x) {
                 if (j < WAVE * E) {
 #pragma unroll
                     for (int q = 0; q < E; q++) {
-                        W o;
-                        if constexpr (sizeof(W) == 8)
-                            o = (W)__shfl_xor((unsigned long long)x[q], d, WAVE);
-                        else
-                            o = (W)__shfl_xor((unsigned int)x[q], d, WAVE);
+                        const W o = lane_xor<W>(x[q], d);
                         x[q] = keep_min ? (o < x[q] ? o : x[q]) : (o < x[q] ? x[q] : o);
                     }
                 } else {
@@ -614,7 +642,7 @@ __global__ __launch_bounds__(256) void k_seg_block(const PT *__restrict__ rowptr
 constexpr int BKT_SHIFT = 20;                        // keys per bucket = bitmap bits
 constexpr int BKT_MAXNB = 4096;                      // buckets per row (2^31 columns need 2048)
 constexpr int RANK_THREADS = 1024;
-constexpr int RANK_U = 8;                            // elements per thread and pass
+constexpr int RANK_U = 16;                           // elements per thread and pass
 constexpr int RB_WORDS = 1 << (BKT_SHIFT - 5);       // 32768 bitmap words
 constexpr int RB_GRP = 8;                            // words per prefix group
 constexpr int RB_NGRP = RB_WORDS / RB_GRP;           // 4096 prefix entries
@@ -728,7 +756,7 @@ __device__ void seg_rank_tile(int64_t item, SegSmemRank &sm, const PT *__restric
     for (int i = tid; i < RB_WORDS / 4; i += RANK_THREADS) bm4[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     // Each pass handles RANK_U elements per thread with all loads issued
-    // before any is used: a row of 17K entries is then 3 rounds of memory
+    // before any is used: a row of 17K entries is then 2 rounds of memory
     // latency per loop instead of 17.
     constexpr int64_t STEP = (int64_t)RANK_THREADS * RANK_U;
     if (nb == 1) {
