@@ -6,9 +6,19 @@ the definition from the paper's problem formulation (Sec. 2.1 permutation,
 Sec. 2.2 extraction, Sec. 2.3 assignment with the Add step of Sec. 4.7),
 written out directly in C; see hp_oracle.c.
 
-Parity status: every routine is pinned by the CPU tests in tests/ against
-dense brute force, SciPy indexing, the selection-matrix products of Sec. 2
-and invariants (nothing here is "parity unpinned").
+Two routines per operation: the literal ones (permute, spref, spref_dcsc)
+search every (i, j) pair of the definition; permute_map and spref_map reach
+the same result from the stored entries through inverse index tables (the
+column renaming qinv, the column multimap list[c]), at a cost proportional
+to the entries read, so they finish whole outputs at full benchmark sizes.
+The assignment (spasgn) is a merge of stored entries.  The map routines and
+the assignment take a thread count (rows are independent).
+
+Parity status: every routine, and the sampled-row mode of each, is pinned by
+the CPU tests in tests/ against dense brute force, SciPy indexing, the
+selection-matrix products of Sec. 2, hand-worked examples and invariants,
+and planted mistakes in each must fail a pin (nothing here is "parity
+unpinned").
 """
 from __future__ import annotations
 
@@ -39,7 +49,7 @@ def build(force: bool = False, extra_flags=()) -> str:
     out = _LIB if not extra_flags else os.path.join(_HERE, "liboracle_variant.so")
     if force or extra_flags or not os.path.exists(out) or \
             os.path.getmtime(out) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math",
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
                "-ffp-contract=off", *extra_flags, _SRC, "-o", out]
         subprocess.check_call(cmd)
     return out
@@ -64,10 +74,15 @@ def _bind(lib):
     lib.orc_permute.argtypes = [I64, I64, P, P, P, ctypes.c_int, P, P, P, I64, P, P, P, I64, P]
     lib.orc_spref.argtypes = [I64, I64, P, P, P, ctypes.c_int, P, I64, P, I64, P, I64, P, P, P, I64, P]
     lib.orc_spasgn.argtypes = [I64, I64, P, P, P, ctypes.c_int, I64, I64, P, P, P,
-                               P, I64, P, I64, ctypes.c_int, P, I64, P, P, P, I64, P]
+                               P, I64, P, I64, ctypes.c_int, P, I64, P, P, P, I64, P, ctypes.c_int]
     lib.orc_spref_dcsc.argtypes = [I64, I64, I64, P, P, P, P, ctypes.c_int, P, I64, P, I64, P, I64, P, P, P,
                                    I64, P]
-    for f in (lib.orc_check_csr, lib.orc_permute, lib.orc_spref, lib.orc_spasgn, lib.orc_spref_dcsc):
+    lib.orc_permute_map.argtypes = [I64, I64, P, P, P, ctypes.c_int, P, P, P, I64, P, P, P, I64, P,
+                                    ctypes.c_int]
+    lib.orc_spref_map.argtypes = [I64, I64, P, P, P, ctypes.c_int, P, I64, P, I64, P, I64, P, P, P, I64, P,
+                                  ctypes.c_int]
+    for f in (lib.orc_check_csr, lib.orc_permute, lib.orc_spref, lib.orc_spasgn, lib.orc_spref_dcsc,
+              lib.orc_permute_map, lib.orc_spref_map):
         f.restype = ctypes.c_int
     return lib
 
@@ -160,7 +175,42 @@ def spref(A, I, J, rows=None, lib=None):
     return _two_call(fn, nout, v.dtype)
 
 
-def spasgn(A, B, I, J, op="second", rows=None, lib=None):
+def permute_map(A, p, q=None, rows=None, lib=None, threads=1):
+    """As permute(), through the inverse column map: row i is row p[i] of A
+    with every column c renamed qinv[c], then sorted."""
+    lib = lib or _load()
+    m, n, rp, c, v = _csr(A)
+    p = _ivec(p)
+    q = _ivec(q)
+    r, ns = _rows(rows)
+    nout = ns if r is not None else m
+
+    def fn(ptr, oc, ov, cap, need):
+        return lib.orc_permute_map(m, n, _ptr(rp), _ptr(c), _ptr(v), v.itemsize, _ptr(p), _ptr(q),
+                                   _ptr(r), ns, _ptr(ptr), _ptr(oc), _ptr(ov), cap, ctypes.byref(need),
+                                   int(threads))
+    return _two_call(fn, nout, v.dtype)
+
+
+def spref_map(A, I, J, rows=None, lib=None, threads=1):
+    """As spref(), through the column multimap list[c] = {j : J[j] = c}:
+    every stored entry (I[i], c) is emitted at each j of list[c], then the
+    row is sorted."""
+    lib = lib or _load()
+    m, n, rp, c, v = _csr(A)
+    I = _ivec(I)
+    J = _ivec(J)
+    r, ns = _rows(rows)
+    nout = ns if r is not None else len(I)
+
+    def fn(ptr, oc, ov, cap, need):
+        return lib.orc_spref_map(m, n, _ptr(rp), _ptr(c), _ptr(v), v.itemsize, _ptr(I), len(I),
+                                 _ptr(J), len(J), _ptr(r), ns, _ptr(ptr), _ptr(oc), _ptr(ov), cap,
+                                 ctypes.byref(need), int(threads))
+    return _two_call(fn, nout, v.dtype)
+
+
+def spasgn(A, B, I, J, op="second", rows=None, lib=None, threads=1):
     """Rows of A_new = A (+) B' with B'[I[i], J[j]] = B[i, j] for stored B entries."""
     lib = lib or _load()
     m, n, rp, c, v = _csr(A)
@@ -175,7 +225,8 @@ def spasgn(A, B, I, J, op="second", rows=None, lib=None):
     def fn(ptr, oc, ov, cap, need):
         return lib.orc_spasgn(m, n, _ptr(rp), _ptr(c), _ptr(v), v.itemsize, bm, bn, _ptr(brp),
                               _ptr(bc), _ptr(bv), _ptr(I), len(I), _ptr(J), len(J), OPS[op],
-                              _ptr(r), ns, _ptr(ptr), _ptr(oc), _ptr(ov), cap, ctypes.byref(need))
+                              _ptr(r), ns, _ptr(ptr), _ptr(oc), _ptr(ov), cap, ctypes.byref(need),
+                              int(threads))
     return _two_call(fn, nout, v.dtype)
 
 

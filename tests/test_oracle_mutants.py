@@ -37,6 +37,22 @@ MUTANTS = {
     "dcsc_row_not_position": ("out_row[cnt] = (int32_t)i;", "out_row[cnt] = I[i];"),
     "dcsc_search_skips_last": ("int64_t lo = colptr[k], hi = colptr[k + 1] - 1;",
                                "int64_t lo = colptr[k], hi = colptr[k + 1] - 2;"),
+    # the routines through index tables
+    "pmap_qinv_not_inverted": ("for (int64_t j = 0; j < n; j++) qinv[q[j]] = (int32_t)j;",
+                               "for (int64_t j = 0; j < n; j++) qinv[j] = q[j];"),
+    "pmap_row_unmapped": ("const int64_t src = x->p[i];", "const int64_t src = i;"),
+    "map_rows_left_unsorted": ("    qsort(e, (size_t)n, sizeof(ent_t), cmp_ent);\n", ""),
+    "smap_first_copy_only": ("for (int64_t t = x->lstart[c]; t < x->lstart[c + 1]; t++) {",
+                             "for (int64_t t = x->lstart[c]; t < x->lstart[c + 1] && t == x->lstart[c]; t++) {"),
+    "smap_positions_unmapped": ("work[cnt].c = x->list[t];", "work[cnt].c = (int32_t)(t - x->lstart[c]);"),
+    "smap_row_shifted": ("const int64_t r = x->I[i];", "const int64_t r = x->I[i > 0 ? i - 1 : 0];"),
+    # the sampled-row modes
+    "spref_rows_first_only": ("int64_t i = rows ? rows[s] : s;\n        if (i < 0 || i >= nI) return ORC_INDEX_RANGE;",
+                              "int64_t i = rows ? rows[0] : s;\n        if (i < 0 || i >= nI) return ORC_INDEX_RANGE;"),
+    "perm_rows_first_only": ("int64_t i = rows ? rows[s] : s;\n        if (i < 0 || i >= m) return ORC_INDEX_RANGE;",
+                             "int64_t i = rows ? rows[0] : s;\n        if (i < 0 || i >= m) return ORC_INDEX_RANGE;"),
+    "driver_rows_first_only": ("return rows ? rows[s] : s;", "return rows ? rows[0] : s;"),
+    "driver_all_rows_shifted": ("return rows ? rows[s] : s;", "return rows ? rows[s] : (s % 2 ? s - 1 : s);"),
 }
 
 
@@ -44,7 +60,7 @@ def _build(tmp_path, name, src_text):
     c = tmp_path / f"{name}.c"
     c.write_text(src_text)
     so = tmp_path / f"{name}.so"
-    subprocess.check_call(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", f"-I{os.path.dirname(SRC)}",
+    subprocess.check_call(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-fopenmp", f"-I{os.path.dirname(SRC)}",
                            str(c), "-o", str(so)])
     return str(so)
 

@@ -13,6 +13,36 @@ from tests._util import (assert_csr_equal, csc_of, dense, floats, from_dense, fr
 
 SHAPES = [(1, 1), (2, 3), (5, 5), (7, 4), (9, 13), (16, 16), (33, 20)]
 
+# Both routine families of each operation face every pin: the literal search
+# over all (i, j) pairs and the routine through inverse index tables, the
+# latter single-threaded and split over threads.
+PERMUTES = {
+    "literal": lambda A, p, q=None, rows=None: oracle.permute(A, p, q, rows=rows),
+    "map": lambda A, p, q=None, rows=None: oracle.permute_map(A, p, q, rows=rows),
+    "map-threads": lambda A, p, q=None, rows=None: oracle.permute_map(A, p, q, rows=rows, threads=3),
+}
+SPREFS = {
+    "literal": lambda A, I, J, rows=None: oracle.spref(A, I, J, rows=rows),
+    "map": lambda A, I, J, rows=None: oracle.spref_map(A, I, J, rows=rows),
+    "map-threads": lambda A, I, J, rows=None: oracle.spref_map(A, I, J, rows=rows, threads=3),
+}
+SPASGNS = {
+    "serial": lambda A, B, I, J, op="second", rows=None: oracle.spasgn(A, B, I, J, op, rows=rows),
+    "threads": lambda A, B, I, J, op="second", rows=None: oracle.spasgn(A, B, I, J, op, rows=rows, threads=3),
+}
+
+
+def _rows_of(full, rows):
+    """The listed rows (in list order, repeats kept) of a full result."""
+    rp, c, v = full
+    out_rp, cs, vs = [0], [], []
+    for i in rows:
+        a, b = rp[i], rp[i + 1]
+        cs.append(c[a:b])
+        vs.append(v[a:b])
+        out_rp.append(out_rp[-1] + (b - a))
+    return (np.array(out_rp, np.int64), np.concatenate(cs) if cs else c[:0], np.concatenate(vs) if vs else v[:0])
+
 
 def _brute_permute(A, p, q):
     D, M = dense(A)
@@ -44,47 +74,51 @@ def _brute_spasgn(A, B, I, J, op):
 
 # ---------------------------------------------------------------- golden ---
 
-def test_golden_permute():
+@pytest.mark.parametrize("how", sorted(PERMUTES))
+def test_golden_permute(how):
     g = read_golden("permute_3x4.txt")
     m, n = ints(g["shape"])
     A = (int(m), int(n), ints(g["rowptr"]), ints(g["col"]).astype(np.int32), floats(g["val"]))
-    got = oracle.permute(A, ints(g["p"]), ints(g["q"]))
+    got = PERMUTES[how](A, ints(g["p"]), ints(g["q"]))
     assert_csr_equal(got, (ints(g["expect_rowptr"]), ints(g["expect_col"]), floats(g["expect_val"])),
                      "golden permute")
 
 
-def test_golden_spref():
+@pytest.mark.parametrize("how", sorted(SPREFS))
+def test_golden_spref(how):
     g = read_golden("spref_dup_3x4.txt")
     m, n = ints(g["shape"])
     A = (int(m), int(n), ints(g["rowptr"]), ints(g["col"]).astype(np.int32), floats(g["val"]))
-    got = oracle.spref(A, ints(g["I"]), ints(g["J"]))
+    got = SPREFS[how](A, ints(g["I"]), ints(g["J"]))
     assert_csr_equal(got, (ints(g["expect_rowptr"]), ints(g["expect_col"]), floats(g["expect_val"])),
                      "golden spref")
 
 
+@pytest.mark.parametrize("how", sorted(SPASGNS))
 @pytest.mark.parametrize("op", ["second", "plus", "replace"])
-def test_golden_spasgn(op):
+def test_golden_spasgn(op, how):
     g = read_golden("spasgn_3x4.txt")
     m, n = ints(g["shape"])
     A = (int(m), int(n), ints(g["rowptr"]), ints(g["col"]).astype(np.int32), floats(g["val"]))
     bm, bn = ints(g["Bshape"])
     B = (int(bm), int(bn), ints(g["Browptr"]), ints(g["Bcol"]).astype(np.int32), floats(g["Bval"]))
-    got = oracle.spasgn(A, B, ints(g["I"]), ints(g["J"]), op)
+    got = SPASGNS[how](A, B, ints(g["I"]), ints(g["J"]), op)
     exp = (ints(g[f"{op}_rowptr"]), ints(g[f"{op}_col"]), floats(g[f"{op}_val"]))
     assert_csr_equal(got, exp, f"golden spasgn {op}")
 
 
 # --------------------------------------------------------------- permute ---
 
+@pytest.mark.parametrize("how", sorted(PERMUTES))
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("vdtype", [np.float64, np.float32])
-def test_permute_brute_scipy_selection(shape, vdtype):
+def test_permute_brute_scipy_selection(shape, vdtype, how):
     rng = np.random.default_rng(hash(shape) % 1000)
     m, n = shape
     A = rand_csr(rng, m, n, 0.3, vdtype)
     p = rng.permutation(m)
     q = rng.permutation(n)
-    got = oracle.permute(A, p, q)
+    got = PERMUTES[how](A, p, q)
     assert_csr_equal(got, _brute_permute(A, p, q), "brute")
     S = to_scipy(A)
     assert_csr_equal(got, from_scipy(S[p][:, q]), "scipy fancy indexing")
@@ -93,53 +127,58 @@ def test_permute_brute_scipy_selection(shape, vdtype):
     assert_csr_equal(got, from_scipy(Pm @ S @ Qm.T), "P A Q^T")
 
 
-def test_permute_symmetric_equals_general():
+@pytest.mark.parametrize("how", sorted(PERMUTES))
+def test_permute_symmetric_equals_general(how):
     rng = np.random.default_rng(1)
     A = rand_csr(rng, 12, 12, 0.25)
     p = rng.permutation(12)
-    assert_csr_equal(oracle.permute(A, p), oracle.permute(A, p, p), "symmetric")
-    assert_csr_equal(oracle.permute(A, p), _brute_permute(A, p, p), "symmetric brute")
+    perm = PERMUTES[how]
+    assert_csr_equal(perm(A, p), perm(A, p, p), "symmetric")
+    assert_csr_equal(perm(A, p), _brute_permute(A, p, p), "symmetric brute")
 
 
-def test_permute_invariants():
+@pytest.mark.parametrize("how", sorted(PERMUTES))
+def test_permute_invariants(how):
     rng = np.random.default_rng(2)
     m, n = 40, 30
     A = rand_csr(rng, m, n, 0.2)
     p1, q1 = rng.permutation(m), rng.permutation(n)
     p2, q2 = rng.permutation(m), rng.permutation(n)
-    A1 = oracle.permute(A, p1, q1)
+    perm = PERMUTES[how]
+    A1 = perm(A, p1, q1)
     assert A1[0][-1] == A[2][-1]                       # nnz preserved
     lens = np.diff(A[2])
     assert sorted(np.diff(A1[0])) == sorted(lens)       # row-length multiset preserved
     # inverse permutations restore A byte for byte
-    back = oracle.permute((m, n) + A1, np.argsort(p1), np.argsort(q1))
+    back = perm((m, n) + A1, np.argsort(p1), np.argsort(q1))
     assert_csr_equal(back, A[2:], "inverse")
     # identity
-    assert_csr_equal(oracle.permute(A, np.arange(m), np.arange(n)), A[2:], "identity")
+    assert_csr_equal(perm(A, np.arange(m), np.arange(n)), A[2:], "identity")
     # composition: A''[i,j] = A[p1[p2[i]], q1[q2[j]]]
-    A2 = oracle.permute((m, n) + A1, p2, q2)
-    assert_csr_equal(A2, oracle.permute(A, p1[p2], q1[q2]), "composition")
+    A2 = perm((m, n) + A1, p2, q2)
+    assert_csr_equal(A2, perm(A, p1[p2], q1[q2]), "composition")
 
 
-def test_permute_sampled_rows_match_full():
+@pytest.mark.parametrize("how", sorted(PERMUTES))
+def test_permute_sampled_rows_match_full(how):
     rng = np.random.default_rng(3)
     A = rand_csr(rng, 50, 60, 0.1)
     p, q = rng.permutation(50), rng.permutation(60)
-    full = oracle.permute(A, p, q)
-    rows = np.array([49, 0, 7, 7, 23])
-    part = oracle.permute(A, p, q, rows=rows)
-    for s, i in enumerate(rows):
-        a, b = full[0][i], full[0][i + 1]
-        c, d = part[0][s], part[0][s + 1]
-        np.testing.assert_array_equal(full[1][a:b], part[1][c:d])
-        np.testing.assert_array_equal(full[2][a:b], part[2][c:d])
+    perm = PERMUTES[how]
+    full = _brute_permute(A, p, q)
+    for rows in (np.array([49, 0, 7, 7, 23]), np.arange(50)[::-1].copy(), np.zeros(0, np.int64)):
+        assert_csr_equal(perm(A, p, q, rows=rows), _rows_of(full, rows), f"rows {rows[:5]}")
+    with pytest.raises(oracle.OracleError) as e:
+        perm(A, p, q, rows=np.array([3, 50]))
+    assert e.value.name == "INDEX_RANGE"
 
 
 # ----------------------------------------------------------------- spref ---
 
+@pytest.mark.parametrize("how", sorted(SPREFS))
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("vdtype", [np.float64, np.float32])
-def test_spref_brute_scipy_selection(shape, vdtype):
+def test_spref_brute_scipy_selection(shape, vdtype, how):
     rng = np.random.default_rng(7 + hash(shape) % 1000)
     m, n = shape
     A = rand_csr(rng, m, n, 0.35, vdtype)
@@ -148,7 +187,7 @@ def test_spref_brute_scipy_selection(shape, vdtype):
         nJ = int(rng.integers(0, 2 * n + 1))
         I = rng.integers(0, m, nI)          # duplicates and any order
         J = rng.integers(0, n, nJ)
-        got = oracle.spref(A, I, J)
+        got = SPREFS[how](A, I, J)
         assert_csr_equal(got, _brute_spref(A, I, J), "brute")
         if nI and nJ:
             S = to_scipy(A)
@@ -163,29 +202,52 @@ def test_spref_brute_scipy_selection(shape, vdtype):
         assert got[0][-1] == expect
 
 
-def test_spref_special_cases():
+@pytest.mark.parametrize("how", sorted(SPREFS))
+def test_spref_special_cases(how):
     rng = np.random.default_rng(11)
     m, n = 25, 19
     A = rand_csr(rng, m, n, 0.3)
+    spref = SPREFS[how]
     # whole index sets in order reproduce A
-    assert_csr_equal(oracle.spref(A, np.arange(m), np.arange(n)), A[2:], "identity")
+    assert_csr_equal(spref(A, np.arange(m), np.arange(n)), A[2:], "identity")
     # full permutations make extraction a permutation (Sec. 2.2)
     p, q = rng.permutation(m), rng.permutation(n)
-    assert_csr_equal(oracle.spref(A, p, q), oracle.permute(A, p, q), "perm special case")
+    assert_csr_equal(spref(A, p, q), _brute_permute(A, p, q), "perm special case")
     # sorted unique subsets keep the original order
     I = np.sort(rng.choice(m, 9, replace=False))
     J = np.sort(rng.choice(n, 7, replace=False))
-    got = oracle.spref(A, I, J)
+    got = spref(A, I, J)
     D, M = dense(A)
     assert_csr_equal(got, from_dense(D[I][:, J], M[I][:, J]), "ordered submatrix")
     # empty index sets give an empty, correctly shaped result
-    e = oracle.spref(A, np.zeros(0, np.int64), J)
+    e = spref(A, np.zeros(0, np.int64), J)
     assert e[0].tolist() == [0] and e[1].size == 0
-    e = oracle.spref(A, I, np.zeros(0, np.int64))
+    e = spref(A, I, np.zeros(0, np.int64))
     assert e[0].tolist() == [0] * (len(I) + 1)
+    # one column repeated many times: every copy is emitted, in position order
+    J = np.array([3, 5, 3, 3, 0, 5])
+    assert_csr_equal(spref(A, np.arange(m), J), _brute_spref(A, np.arange(m), J), "repeats")
 
 
-def test_spref_exhaustive_tiny():
+@pytest.mark.parametrize("how", sorted(SPREFS))
+def test_spref_sampled_rows_match_full(how):
+    """The sampled-row mode returns exactly the listed rows of the full
+    result (in list order, repeats kept)."""
+    rng = np.random.default_rng(13)
+    A = rand_csr(rng, 40, 30, 0.3)
+    I = rng.integers(0, 40, 55)
+    J = rng.integers(0, 30, 45)
+    full = _brute_spref(A, I, J)
+    spref = SPREFS[how]
+    for rows in (np.array([54, 0, 9, 9, 31, 2]), np.arange(55)[::-1].copy(), np.zeros(0, np.int64)):
+        assert_csr_equal(spref(A, I, J, rows=rows), _rows_of(full, rows), f"rows {rows[:6]}")
+    with pytest.raises(oracle.OracleError) as e:
+        spref(A, I, J, rows=np.array([0, 55]))
+    assert e.value.name == "INDEX_RANGE"
+
+
+@pytest.mark.parametrize("how", sorted(SPREFS))
+def test_spref_exhaustive_tiny(how):
     """Every index vector of length <= 2 over a 3 x 3 matrix, against brute force."""
     rng = np.random.default_rng(5)
     A = rand_csr(rng, 3, 3, 0.5)
@@ -194,7 +256,7 @@ def test_spref_exhaustive_tiny():
         for J in vecs:
             I_ = np.array(I, dtype=np.int64)
             J_ = np.array(J, dtype=np.int64)
-            assert_csr_equal(oracle.spref(A, I_, J_), _brute_spref(A, I_, J_), f"{I} {J}")
+            assert_csr_equal(SPREFS[how](A, I_, J_), _brute_spref(A, I_, J_), f"{I} {J}")
 
 
 # ---------------------------------------------------------------- spasgn ---
@@ -209,14 +271,15 @@ def _rand_assign(rng, m, n, vdtype=np.float64):
     return A, B, I, J
 
 
+@pytest.mark.parametrize("how", sorted(SPASGNS))
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("vdtype", [np.float64, np.float32])
 @pytest.mark.parametrize("op", ["second", "plus", "replace"])
-def test_spasgn_brute(shape, vdtype, op):
+def test_spasgn_brute(shape, vdtype, op, how):
     rng = np.random.default_rng(17 + hash((shape, op)) % 1000)
     for trial in range(3):
         A, B, I, J = _rand_assign(rng, *shape, vdtype)
-        got = oracle.spasgn(A, B, I, J, op)
+        got = SPASGNS[how](A, B, I, J, op)
         assert_csr_equal(got, _brute_spasgn(A, B, I, J, op), f"brute {op}")
 
 
@@ -264,6 +327,41 @@ def test_spasgn_invariants():
     assert np.array_equal(np.where(~Bp, Dg, 0), np.where(~Bp, Da, 0))
 
 
+@pytest.mark.parametrize("how", sorted(SPASGNS))
+@pytest.mark.parametrize("op", ["second", "plus", "replace"])
+def test_spasgn_sampled_rows_match_full(op, how):
+    """The sampled-row mode returns exactly the listed rows of the full
+    result: rows inside and outside I, repeated and out of order."""
+    rng = np.random.default_rng(41)
+    A, B, I, J = _rand_assign(rng, 30, 24)
+    while len(I) < 3 or len(I) > 27:
+        A, B, I, J = _rand_assign(rng, 30, 24)
+    full = _brute_spasgn(A, B, I, J, op)
+    outside = np.setdiff1d(np.arange(30), I)
+    for rows in (np.array([I[0], outside[0], I[-1], I[0], 29, 0]), np.arange(30)[::-1].copy(),
+                 np.zeros(0, np.int64)):
+        assert_csr_equal(SPASGNS[how](A, B, I, J, op, rows=rows), _rows_of(full, rows), f"rows {rows[:6]}")
+    with pytest.raises(oracle.OracleError) as e:
+        SPASGNS[how](A, B, I, J, op, rows=np.array([30]))
+    assert e.value.name == "INDEX_RANGE"
+
+
+def test_map_routines_thread_count_independent():
+    """The table routines give the same bytes for any thread count on a
+    matrix with long and empty rows."""
+    rng = np.random.default_rng(43)
+    A = rand_csr(rng, 300, 200, 0.05)
+    rp = A[2].copy()
+    p, q = rng.permutation(300), rng.permutation(200)
+    I, J = rng.integers(0, 300, 400), rng.integers(0, 200, 260)
+    base_p = oracle.permute_map(A, p, q)
+    base_s = oracle.spref_map(A, I, J)
+    for t in (2, 5, 16):
+        assert_csr_equal(oracle.permute_map(A, p, q, threads=t), base_p, f"permute {t}")
+        assert_csr_equal(oracle.spref_map(A, I, J, threads=t), base_s, f"spref {t}")
+    assert np.array_equal(rp, A[2])
+
+
 def test_spasgn_round_trip_streaming():
     """Split A's edges into 80% + 4 x 5%, assign the parts back one by one
     (the streaming-update experiment of the assignment results): A returns."""
@@ -299,6 +397,15 @@ def test_error_statuses():
     assert e.value.name == "SHAPE"
     with pytest.raises(oracle.OracleError) as e:
         oracle.spref(A, np.array([0, 6]), np.arange(5))
+    assert e.value.name == "INDEX_RANGE"
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.permute_map(A, np.array([0, 1, 2, 3, 4, 4]), np.arange(5))
+    assert e.value.name == "NOT_PERMUTATION"
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.permute_map(A, np.arange(6))
+    assert e.value.name == "SHAPE"
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.spref_map(A, np.array([0, 1]), np.array([5]))
     assert e.value.name == "INDEX_RANGE"
     B = rand_csr(rng, 2, 2, 0.5)
     with pytest.raises(oracle.OracleError) as e:
