@@ -512,52 +512,16 @@ def run_batched(hp, args):
 
 def _served_pool(args):
     """Resident pool: R-MAT (ef 16, symmetrised) and Erdos-Renyi (degree 16)
-    matrices alternating, scale U{lo..hi}, int32 / int64 rowptr alternating,
+    matrices alternating, scale U{16..hi}, int32 / int64 rowptr alternating,
     fp32 values."""
-    key = synth.stream_key(0, "served-pool")
-    n = args.served_pool
-    sc = synth.randint_below(synth.stream_key(key, "scale"), n, args.served_scale_hi - 15) + 16
-    pool = []
-    for t in range(n):
-        ptr = torch.int32 if t % 4 < 2 else torch.int64
-        s = int(sc[t])
-        if t % 2 == 0:
-            A = synth.rmat(s, 16, 0, f"served-rmat-{t}", symmetric=True, ptr_dtype=ptr, device="cuda")
-        else:
-            A = synth.erdos_renyi(1 << s, 1 << s, 16.0, 0, f"served-er-{t}", ptr_dtype=ptr,
-                                  val_dtype=torch.float32, device="cuda")
-        pool.append(A)
-    return pool
+    return synth.served_pool(0, args.served_pool, 16, args.served_scale_hi, device="cuda")
 
 
 def _served_variants(pool, per=4):
     """Per matrix: `per` extraction index pairs (5-50%, 1% repeats), `per`
     permutation pairs, `per` assignment blocks (I, J 1-10%, nnz(B) ~ 1% of
     nnz(A), ops cycling select-second / plus / replace)."""
-    out = []
-    for m, A in enumerate(pool):
-        key = synth.stream_key(0, "served-var", m)
-        fr = synth.values(synth.stream_key(key, "fr"), 4 * per, torch.float64)
-        v = {"spref": [], "permute": [], "spasgn": []}
-        for k in range(per):
-            f1 = 0.05 + 0.45 * float(fr[4 * k]); f2 = 0.05 + 0.45 * float(fr[4 * k + 1])
-            I = synth.subset(synth.stream_key(key, "I", k), A.nrows, max(1, int(f1 * A.nrows)), repeat_frac=0.01,
-                             device="cuda")
-            J = synth.subset(synth.stream_key(key, "J", k), A.ncols, max(1, int(f2 * A.ncols)), repeat_frac=0.01,
-                             device="cuda")
-            v["spref"].append(dict(kind="spref", A=A, I=I, J=J))
-            v["permute"].append(dict(kind="permute", A=A, p=synth.randperm(synth.stream_key(key, "p", k), A.nrows,
-                                                                             "cuda"),
-                                     q=synth.randperm(synth.stream_key(key, "q", k), A.ncols, "cuda")))
-            g1 = 0.01 + 0.09 * float(fr[4 * k + 2]); g2 = 0.01 + 0.09 * float(fr[4 * k + 3])
-            nI, nJ = max(1, int(g1 * A.nrows)), max(1, int(g2 * A.ncols))
-            aI = synth.subset(synth.stream_key(key, "aI", k), A.nrows, nI, device="cuda")
-            aJ = synth.subset(synth.stream_key(key, "aJ", k), A.ncols, nJ, device="cuda")
-            B = synth.bernoulli_block(nI, nJ, min(1.0, 0.01 * A.nnz / (nI * nJ)), 0, f"served-B-{m}-{k}",
-                                      ptr_dtype=A.rowptr.dtype, val_dtype=torch.float32, device="cuda")
-            v["spasgn"].append(dict(kind="spasgn", A=A, I=aI, J=aJ, B=B, op=["second", "plus", "replace"][k % 3]))
-        out.append(v)
-    return out
+    return synth.served_variants(pool, 0, per, device="cuda")
 
 
 def _pctl(x, q):
@@ -586,16 +550,9 @@ def run_served(hp, args):
 
 def _served_at(hp, args, pool, var, rate):
     import numpy as np
-    arr = synth.poisson_arrivals(rate, args.served_seconds, 0, "served-arrivals").numpy()
-    key = synth.stream_key(0, "served-trace")
+    arr, trace = synth.served_trace(var, rate, args.served_seconds, 0)
+    arr = arr.numpy()
     n = len(arr)
-    u = synth.values(synth.stream_key(key, "kind"), n, torch.float64).numpy()
-    mi = synth.randint_below(synth.stream_key(key, "mat"), n, len(pool)).numpy()
-    vi = synth.randint_below(synth.stream_key(key, "var"), n, 4).numpy()
-    trace = []
-    for k in range(n):
-        kind = "spref" if u[k] <= 0.6 else ("spasgn" if u[k] <= 0.8 else "permute")
-        trace.append(var[int(mi[k])][kind][int(vi[k])])
 
     def submit(srv, r):
         if r["kind"] == "spref":

@@ -25,7 +25,11 @@
  *     (HP_ERR_ALIAS when they share an address).
  *   - Work is enqueued on the handle's stream in order.  The plan calls end
  *     with one blocking readback of a few scalars (output size, error
- *     flags, bin statistics); exec calls never block.
+ *     flags, bin statistics); exec calls never block.  The readback wait is
+ *     a bounded poll: past the host wait limit (environment variable
+ *     HP_HOST_WAIT_MS, default ten minutes) the plan returns HP_ERR_TIMEOUT,
+ *     and the work it enqueued may still be running, so the stream must be
+ *     synchronised before the buffers it uses are freed.
  *   - Errors are returned as hp_status_t; no exception crosses the ABI.
  *     hp_last_error() gives a message for the last failing call.
  *
@@ -64,7 +68,7 @@ typedef enum {
     HP_ERR_CAPACITY = 9,         /* batched: an output exceeded its arena slot     */
     HP_ERR_HIP = 10,             /* a HIP runtime call failed                      */
     HP_ERR_ALIAS = 11,           /* an output array overlaps an input array        */
-    HP_ERR_TIMEOUT = 12,         /* a device-side bounded wait gave up             */
+    HP_ERR_TIMEOUT = 12,         /* a bounded wait (device or host side) gave up   */
     HP_ERR_REJECTED = 13         /* served form: request can never fit the budget  */
 } hp_status_t;
 
@@ -293,6 +297,12 @@ typedef struct {
     hp_csr_t B;            /* spasgn: the |I| x |J| block                          */
     int32_t op;            /* spasgn: hp_asgn_op_t                                 */
     int32_t pad;
+    void *ready;           /* served form only (the batched calls ignore it): a
+                              hipEvent_t the caller recorded on its stream after
+                              writing the inputs; the worker's stream waits for it
+                              before reading them.  NULL: the inputs are complete
+                              at submit.  Must stay valid until the request
+                              completes.                                          */
 } hp_request_t;
 
 typedef struct {
@@ -336,7 +346,17 @@ hp_status_t hp_batch_exec(hp_handle_t h, hp_request_t *reqs, int n, void *ws, si
  * running batches to finish; a batch that cannot fit while no other batch
  * runs is split into single requests, and a single request that cannot fit
  * then completes with HP_ERR_REJECTED (unreleased results count as used).
- * Results stay in the pool until hp_server_release.
+ * Results stay in the pool until hp_server_release; the caller must have
+ * finished every use of a result (synchronised the streams that read it)
+ * before releasing it, since its pool space is then reused.
+ * Stream order: the workers run on their own streams.  A request whose
+ * inputs were written by asynchronous work carries a `ready` event (see
+ * hp_request_t); a completion is reported only after the request's work has
+ * finished on the device.
+ * Waits: workers poll the device with the bounded wait of the plan calls; a
+ * request whose work does not finish within the host wait limit
+ * (HP_HOST_WAIT_MS, default ten minutes) completes with HP_ERR_TIMEOUT, and
+ * its pool space is never reused.
  * Latency is measured on the host: submit, start of the request's batch,
  * and the end of its exec (stream synchronised), in ns of a monotonic clock. */
 typedef struct hp_server_s *hp_server_t;

@@ -439,7 +439,8 @@ hp_status_t check_req(hp_handle_t h, const hp_request_t &r, int k, int32_t pt, i
 struct BatchState {
     const void *ws = nullptr;
     int n = -1;
-    std::vector<DevHdr> hdrs;
+    DevHdr *hdrs = nullptr;      // pinned readback of the request headers
+    int hdr_cap = 0;
     std::vector<ReqDev> devs;
 };
 
@@ -586,7 +587,7 @@ int tune_grid(hp_handle_t h, int half, const Global &g, int n, const Stages &S, 
         hipEventRecord(e0, h->stream);
         launch_half<PT, VT>(h, half, g, n, S, c);
         hipEventRecord(e1, h->stream);
-        hipEventSynchronize(e1);
+        if (wait_event(h, e1, "batch tuner") != HP_OK) break;
         float ms = 0;
         hipEventElapsedTime(&ms, e0, e1);
         if (ms < best_ms) {
@@ -668,10 +669,17 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
         bsp = &g_state[h];   // map nodes are stable; one handle is used by one thread at a time
     }
     BatchState &bs = *bsp;
-    bs.hdrs.resize(n);
-    if (e == hipSuccess) e = hipMemcpyAsync(bs.hdrs.data(), g.hdrs, sizeof(DevHdr) * n, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && bs.hdr_cap < n) {
+        if (bs.hdrs) hipHostFree(bs.hdrs);
+        bs.hdrs = nullptr;
+        bs.hdr_cap = 0;
+        e = hipHostMalloc((void **)&bs.hdrs, sizeof(DevHdr) * n, hipHostMallocDefault);
+        if (e == hipSuccess) bs.hdr_cap = n;
+        else bs.hdrs = nullptr;
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(bs.hdrs, g.hdrs, sizeof(DevHdr) * n, hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_check(h, e, "batch plan");
+    if (hp_status_t ws = wait_stream(h, "batch plan")) return ws;
     // per-request results and the arena
     const size_t ps = sizeof(PT), vs = sizeof(VT);
     size_t arena = 0;
@@ -838,7 +846,11 @@ namespace hp {
 // Drops the per-handle batch state and graphs (called by hp_destroy).
 void batch_release_handle(hp_handle_t h) {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_state.erase(h);
+    auto st = g_state.find(h);
+    if (st != g_state.end()) {
+        if (st->second.hdrs) hipHostFree(st->second.hdrs);
+        g_state.erase(st);
+    }
     auto it = g_graphs.find(h);
     if (it != g_graphs.end()) {
         for (auto &kv : it->second) {

@@ -2,6 +2,7 @@
 // exclusive scan with row classification, and the segmented sort used by
 // every operation's Build step.
 #include "hp_internal.hpp"
+#include "hp_poll.hpp"
 #include "hp_scan.hpp"
 
 #include <algorithm>
@@ -242,22 +243,43 @@ hipError_t launch_init_hdr(hipStream_t s, DevHdr *h, uint64_t *tile_state, size_
     return hipGetLastError();
 }
 
-// The plan's one blocking step.  The host polls an event behind the copy
-// instead of sleeping in a stream synchronisation: the plan returns as soon
-// as the few bytes have landed.  A failed or faulted stream ends the poll
-// with its error.
-hipError_t readback_hdr(hp_handle_t h, DevHdr *dev) {
-    hipError_t e = hipMemcpyAsync(h->host_hdr, dev, sizeof(DevHdr), hipMemcpyDeviceToHost, h->stream);
-    if (e != hipSuccess) return e;
-    if (!h->rb_done && hipEventCreateWithFlags(&h->rb_done, hipEventDisableTiming) != hipSuccess) {
-        h->rb_done = nullptr;
-        return hipStreamSynchronize(h->stream);
-    }
-    e = hipEventRecord(h->rb_done, h->stream);
-    if (e != hipSuccess) return e;
-    while ((e = hipEventQuery(h->rb_done)) == hipErrorNotReady) {
-    }
-    return e;
+// Bounded wait for an event recorded on a stream: polls it (spin, then
+// yield, then sleep between polls) up to the host wait limit.  A failed or
+// faulted stream ends the wait with its error; reaching the limit gives
+// HP_ERR_TIMEOUT (the queued work may still run: the caller must
+// synchronise the stream before it frees buffers that work uses).
+hp_status_t wait_event(hp_handle_t h, hipEvent_t ev, const char *what) {
+    hipError_t err = hipSuccess;
+    const WaitResult r = wait_until(
+        [&] {
+            const hipError_t q = hipEventQuery(ev);
+            if (q == hipSuccess) return Poll::READY;
+            if (q == hipErrorNotReady) return Poll::PENDING;
+            err = q;
+            return Poll::FAILED;
+        },
+        default_wait_policy());
+    if (r == WaitResult::DONE) return HP_OK;
+    if (r == WaitResult::FAILED) return hip_check(h, err, what);
+    return fail(h, HP_ERR_TIMEOUT, std::string(what) + ": host wait limit reached (HP_HOST_WAIT_MS)");
+}
+
+// The plan's one blocking step: the device header is copied to pinned host
+// memory and an event behind the copy is polled, so the plan returns as soon
+// as the few bytes have landed.
+hp_status_t readback_hdr(hp_handle_t h, DevHdr *dev, const char *what) {
+    const hipError_t e = hipMemcpyAsync(h->host_hdr, dev, sizeof(DevHdr), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_check(h, e, what);
+    return wait_stream(h, what);
+}
+
+// Bounded wait for everything enqueued so far on the handle's stream.
+hp_status_t wait_stream(hp_handle_t h, const char *what) {
+    hipError_t e = hipSuccess;
+    if (!h->rb_done) e = hipEventCreateWithFlags(&h->rb_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(h->rb_done, h->stream);
+    if (e != hipSuccess) return hip_check(h, e, what);
+    return wait_event(h, h->rb_done, what);
 }
 
 // ===========================================================================

@@ -190,7 +190,13 @@ void stage_end(hp_handle_t h);
 // Common kernels, launched from host wrappers in hp_core.hip --------------
 hipError_t launch_clear_words(hipStream_t s, void *p, size_t nwords32);
 hipError_t launch_init_hdr(hipStream_t s, DevHdr *h, uint64_t *tile_state, size_t ntiles);
-hipError_t readback_hdr(hp_handle_t h, DevHdr *dev);
+// Copies the device header into h->host_hdr and waits for it (bounded:
+// HP_ERR_TIMEOUT past the host wait limit); `what` names the call in errors.
+hp_status_t readback_hdr(hp_handle_t h, DevHdr *dev, const char *what);
+// Bounded wait for an event already recorded on a stream (h may be NULL).
+hp_status_t wait_event(hp_handle_t h, hipEvent_t ev, const char *what);
+// Bounded wait for all work enqueued so far on the handle's stream.
+hp_status_t wait_stream(hp_handle_t h, const char *what);
 
 // Exclusive scan of n counts (int32 in) into out (PT, n+1 entries); out[n]
 // = total; hdr->total[slot] = total.  classify: 0 none, 1 rows longer than

@@ -110,9 +110,9 @@ hp_status_t perm_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
         e = launch_scan_counts<PT>(s, L.cnt, (PT *)C->rowptr, m, L.hdr, 0, L.tiles, 1, L.lists, m);
         stage_mark(h, "perm.scan");
     }
-    if (e == hipSuccess) e = readback_hdr(h, L.hdr);
-    stage_end(h);
     if (e != hipSuccess) return hip_check(h, e, "permute plan");
+    if (hp_status_t rb = readback_hdr(h, L.hdr, "permute plan")) return rb;
+    stage_end(h);
     const DevHdr &H = *h->host_hdr;
     hp_status_t st = status_from_err(h, H.err, "permute");
     if (st) return st;

@@ -118,9 +118,7 @@ size_t carve_locked(hp_server_s *S, Lock &lk, size_t n, bool holder) {
     }
 }
 
-hipError_t wait_stream(hipStream_t st, hipEvent_t ev);
-
-void run_spasgn(hp_server_s *S, hp_handle_t h, hipStream_t st, hipEvent_t ev, Pending p) {
+void run_spasgn(hp_server_s *S, hp_handle_t h, hipStream_t st, Pending p) {
     hp_request_t &r = p.r;
     const int64_t t0 = now_ns();
     const size_t ps = ptr_bytes(r.A.ptr_type), vs = val_bytes(r.A.val_type);
@@ -171,13 +169,15 @@ void run_spasgn(hp_server_s *S, hp_handle_t h, hipStream_t st, hipEvent_t ev, Pe
         C.val = S->pool + out_off + rp_bytes + col_bytes;
         s = hp_spasgn_exec(h, &r.A, &r.B, r.I, r.J, (hp_asgn_op_t)r.op, &C, S->pool + ws_off, wsb, &info,
                            x_off == RangeAlloc::NONE ? nullptr : S->pool + x_off, info.exec_ws_bytes);
-        if (s == HP_OK && wait_stream(st, ev) != hipSuccess) s = HP_ERR_HIP;
+        if (s == HP_OK) s = wait_stream(h, "server");
     }
     Lock lk(S->mu);
-    S->alloc.release(ws_off);
-    if (x_off != RangeAlloc::NONE) S->alloc.release(x_off);
-    if (s == HP_OK) S->block_refs[out_off] = 1;
-    else S->alloc.release(out_off);
+    if (s != HP_ERR_TIMEOUT) {   // after a timeout the stream may still use the blocks: never reuse them
+        S->alloc.release(ws_off);
+        if (x_off != RangeAlloc::NONE) S->alloc.release(x_off);
+        if (s == HP_OK) S->block_refs[out_off] = 1;
+        else S->alloc.release(out_off);
+    }
     complete_locked(S, p, s, 1, &C, t0, out_off);
     S->running--;
     S->cv_mem.notify_all();
@@ -186,7 +186,7 @@ void run_spasgn(hp_server_s *S, hp_handle_t h, hipStream_t st, hipEvent_t ev, Pe
 
 // Run one batch of extraction / permutation requests.  Returns the requests
 // to give back to the queue (after a split), empty otherwise.
-std::vector<Pending> run_batch(hp_server_s *S, hp_handle_t h, hipStream_t st, hipEvent_t ev,
+std::vector<Pending> run_batch(hp_server_s *S, hp_handle_t h, hipStream_t st,
                                std::vector<Pending> &B, size_t ws_off, size_t wsb) {
     const int n = (int)B.size();
     const int64_t t0 = now_ns();
@@ -220,10 +220,11 @@ std::vector<Pending> run_batch(hp_server_s *S, hp_handle_t h, hipStream_t st, hi
     if (s == HP_OK) {
         s = hp_batch_exec(h, reqs.data(), n, S->pool + ws_off, wsb, &info,
                           a_off == RangeAlloc::NONE ? nullptr : S->pool + a_off, info.arena_bytes);
-        if (s == HP_OK && wait_stream(st, ev) != hipSuccess) s = HP_ERR_HIP;
+        if (s == HP_OK) s = wait_stream(h, "server");
     }
     Lock lk(S->mu);
-    S->alloc.release(ws_off);
+    if (s == HP_ERR_TIMEOUT) a_off = RangeAlloc::NONE;   // the stream may still use the blocks: never reuse them
+    else S->alloc.release(ws_off);
     int live = 0;
     for (int k = 0; k < n; k++) {
         const hp_status_t rs = s != HP_OK ? s : (hp_status_t)reqs[k].status;
@@ -238,18 +239,6 @@ std::vector<Pending> run_batch(hp_server_s *S, hp_handle_t h, hipStream_t st, hi
     S->cv_mem.notify_all();
     S->cv_idle.notify_all();
     return back;
-}
-
-// Wait for the worker's stream by polling an event behind its work (no
-// sleep in a stream synchronisation between a request's end and its
-// completion record).  A failed stream ends the poll with its error.
-hipError_t wait_stream(hipStream_t st, hipEvent_t ev) {
-    if (!ev) return hipStreamSynchronize(st);
-    hipError_t e = hipEventRecord(ev, st);
-    if (e != hipSuccess) return e;
-    while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
-    }
-    return e;
 }
 
 // A lone extraction or permutation runs through the plain calls, which cost
@@ -268,7 +257,7 @@ size_t solo_ws_bytes(hp_server_s *S, const hp_request_t &r, size_t *plan_ws) {
     return *plan_ws + RangeAlloc::round((size_t)(rows + 1) * ptr_bytes(r.A.ptr_type));
 }
 
-void run_solo(hp_server_s *S, hp_handle_t h, hipStream_t st, hipEvent_t ev, Pending &p, size_t ws_off,
+void run_solo(hp_server_s *S, hp_handle_t h, hipStream_t st, Pending &p, size_t ws_off,
               size_t plan_ws, size_t wsb) {
     hp_request_t &r = p.r;
     const int64_t t0 = now_ns();
@@ -312,11 +301,15 @@ void run_solo(hp_server_s *S, hp_handle_t h, hipStream_t st, hipEvent_t ev, Pend
                                       info.exec_ws_bytes)
                       : hp_permute_exec(h, &r.A, r.p, r.q, &C, S->pool + ws_off, plan_ws, &info, xw,
                                         info.exec_ws_bytes);
-        if (s == HP_OK && wait_stream(st, ev) != hipSuccess) s = HP_ERR_HIP;
+        if (s == HP_OK) s = wait_stream(h, "server");
     }
     (void)wsb;
     Lock lk(S->mu);
-    S->alloc.release(ws_off);
+    if (s == HP_ERR_TIMEOUT) {   // the stream may still use the blocks: never reuse them
+        x_off = out_off = RangeAlloc::NONE;
+    } else {
+        S->alloc.release(ws_off);
+    }
     if (x_off != RangeAlloc::NONE) S->alloc.release(x_off);
     if (out_off != RangeAlloc::NONE) {
         if (s == HP_OK) S->block_refs[out_off] = 1;
@@ -332,11 +325,9 @@ void worker_main(hp_server_s *S) {
     hipSetDevice(S->device);
     hp_handle_t h = nullptr;
     hipStream_t st = nullptr;
-    hipEvent_t ev = nullptr;
     bool ok = hp_create(&h, S->device) == HP_OK &&
               hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
               hp_set_stream(h, st) == HP_OK;
-    if (ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
     for (;;) {
         std::vector<Pending> B;
         size_t wsb = 0, ws_off = RangeAlloc::NONE, plan_ws = 0;
@@ -398,12 +389,15 @@ void worker_main(hp_server_s *S) {
                 S->running++;
             }
         }
+        // the worker's stream waits for the caller's writes of each input
+        for (auto &pb : B)
+            if (pb.r.ready) hipStreamWaitEvent(st, (hipEvent_t)pb.r.ready, 0);
         if (asgn) {
-            run_spasgn(S, h, st, ev, B[0]);
+            run_spasgn(S, h, st, B[0]);
         } else if (solo) {
-            run_solo(S, h, st, ev, B[0], ws_off, plan_ws, wsb);
+            run_solo(S, h, st, B[0], ws_off, plan_ws, wsb);
         } else {
-            std::vector<Pending> back = run_batch(S, h, st, ev, B, ws_off, wsb);
+            std::vector<Pending> back = run_batch(S, h, st, B, ws_off, wsb);
             if (!back.empty()) {
                 Lock lk(S->mu);
                 for (auto it = back.rbegin(); it != back.rend(); ++it) S->pending.push_front(*it);
@@ -411,7 +405,6 @@ void worker_main(hp_server_s *S) {
             }
         }
     }
-    if (ev) hipEventDestroy(ev);
     if (st) hipStreamDestroy(st);
     if (h) hp_destroy(h);
 }

@@ -831,9 +831,9 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
         e = launch_scan_counts<PT>(s, L.cnt, (PT *)C->rowptr, m, L.hdr, 0, L.tiles, 4, L.lists, m, L.force);
         stage_mark(h, "asgn.scan");
     }
-    if (e == hipSuccess) e = readback_hdr(h, L.hdr);
-    stage_end(h);
     if (e != hipSuccess) return hip_check(h, e, "spasgn plan");
+    if (hp_status_t rb = readback_hdr(h, L.hdr, "spasgn plan")) return rb;
+    stage_end(h);
     const DevHdr &H = *h->host_hdr;
     hp_status_t stt = status_from_err(h, H.err, "spasgn");
     if (stt) return stt;

@@ -291,9 +291,9 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
                                    L.big, L.nm);
         stage_mark(h, "spref.scan");
     }
-    if (e == hipSuccess) e = readback_hdr(h, L.hdr);
-    stage_end(h);
     if (e != hipSuccess) return hip_check(h, e, "spref plan");
+    if (hp_status_t rb = readback_hdr(h, L.hdr, "spref plan")) return rb;
+    stage_end(h);
     const DevHdr &H = *h->host_hdr;
     hp_status_t stt = status_from_err(h, H.err, "spref");
     if (stt) return stt;

@@ -80,7 +80,7 @@ extern "C" hp_status_t hp_validate_csr(hp_handle_t h, const hp_csr_t *A, void *w
                                A->ncols, start, hdr);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = readback_hdr(h, hdr);
     if (e != hipSuccess) return hip_check(h, e, "validate");
+    if (hp_status_t rb = readback_hdr(h, hdr, "validate")) return rb;
     return status_from_err(h, h->host_hdr->err, "validate");
 }

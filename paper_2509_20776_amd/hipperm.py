@@ -62,7 +62,7 @@ class hp_request_t(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("status", ctypes.c_int32), ("A", hp_csr_t),
                 ("I", ctypes.c_void_p), ("J", ctypes.c_void_p), ("nI", ctypes.c_int64),
                 ("nJ", ctypes.c_int64), ("p", ctypes.c_void_p), ("q", ctypes.c_void_p), ("C", hp_csr_t),
-                ("B", hp_csr_t), ("op", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("B", hp_csr_t), ("op", ctypes.c_int32), ("pad", ctypes.c_int32), ("ready", ctypes.c_void_p)]
 
 
 class hp_batch_info_t(ctypes.Structure):
@@ -600,6 +600,12 @@ class Server:
             rq.I, rq.J = _idx(I), _idx(J)
             rq.nI, rq.nJ = int(I.numel()), int(J.numel())
             rq.op = OPS[op]
+        # the inputs may still be being written on the caller's stream: the
+        # worker's stream waits for this event before it reads them
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(self.device))
+        rq.ready = ctypes.c_void_p(ev.cuda_event)
+        keep.append(ev)
         rid = ctypes.c_uint64(0)
         code = hp_server_submit(self.h, ctypes.byref(rq), ctypes.byref(rid))
         if code != 0:
@@ -628,6 +634,10 @@ class Server:
             raise HPError(code, "hp_server_drain")
 
     def release(self, rid: int):
+        """Return a result's pool space.  Work already queued on the current
+        stream may still read the result, so that stream is synchronised
+        first (the space is reused by later requests at once)."""
+        torch.cuda.current_stream(self.device).synchronize()
         code = hp_server_release(self.h, rid)
         if code != 0:
             raise HPError(code, f"hp_server_release({rid})")

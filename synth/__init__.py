@@ -429,3 +429,72 @@ def batched_requests(pool, seed: int = 0, count: int = 512, kinds=("spref", "per
                              I=subset(stream_key(rk, "I"), A.nrows, ki, device=device),
                              J=subset(stream_key(rk, "J"), A.ncols, kj, device=device)))
     return reqs
+
+
+def served_pool(seed: int = 0, count: int = 32, scale_lo: int = 16, scale_hi: int = 24, scales=None,
+                device="cpu"):
+    """Resident pool of the served workload: R-MAT (edge factor 16,
+    symmetrised) and Erdos-Renyi (degree 16) matrices alternating, scale
+    uniform in [scale_lo, scale_hi] (or the given list), int32 / int64 row
+    pointers alternating in pairs, fp32 values."""
+    key = stream_key(seed, "served-pool")
+    if scales is None:
+        sc = randint_below(stream_key(key, "scale"), count, scale_hi - scale_lo + 1) + scale_lo
+        scales = [int(x) for x in sc]
+    pool = []
+    for t, s in enumerate(scales):
+        ptr = torch.int32 if t % 4 < 2 else torch.int64
+        if t % 2 == 0:
+            A = rmat(s, 16, seed, f"served-rmat-{t}", symmetric=True, ptr_dtype=ptr, device=device)
+        else:
+            A = erdos_renyi(1 << s, 1 << s, 16.0, seed, f"served-er-{t}", ptr_dtype=ptr,
+                            val_dtype=torch.float32, device=device)
+        pool.append(A)
+    return pool
+
+
+def served_variants(pool, seed: int = 0, per: int = 4, device="cpu"):
+    """Per pool matrix: `per` extraction index pairs (5-50% of rows and
+    columns, 1% repeats, unsorted), `per` permutation pairs, and `per`
+    assignment blocks (distinct I, J of 1-10%, nnz(B) about 1% of nnz(A),
+    operators cycling select-second / plus / replace)."""
+    out = []
+    for m, A in enumerate(pool):
+        key = stream_key(seed, "served-var", m)
+        fr = values(stream_key(key, "fr"), 4 * per, torch.float64)
+        v = {"spref": [], "permute": [], "spasgn": []}
+        for k in range(per):
+            f1 = 0.05 + 0.45 * float(fr[4 * k])
+            f2 = 0.05 + 0.45 * float(fr[4 * k + 1])
+            I = subset(stream_key(key, "I", k), A.nrows, max(1, int(f1 * A.nrows)), repeat_frac=0.01, device=device)
+            J = subset(stream_key(key, "J", k), A.ncols, max(1, int(f2 * A.ncols)), repeat_frac=0.01, device=device)
+            v["spref"].append(dict(kind="spref", A=A, I=I, J=J))
+            v["permute"].append(dict(kind="permute", A=A, p=randperm(stream_key(key, "p", k), A.nrows, device),
+                                     q=randperm(stream_key(key, "q", k), A.ncols, device)))
+            g1 = 0.01 + 0.09 * float(fr[4 * k + 2])
+            g2 = 0.01 + 0.09 * float(fr[4 * k + 3])
+            nI, nJ = max(1, int(g1 * A.nrows)), max(1, int(g2 * A.ncols))
+            aI = subset(stream_key(key, "aI", k), A.nrows, nI, device=device)
+            aJ = subset(stream_key(key, "aJ", k), A.ncols, nJ, device=device)
+            B = bernoulli_block(nI, nJ, min(1.0, 0.01 * A.nnz / (nI * nJ)), seed, f"served-B-{m}-{k}",
+                                ptr_dtype=A.rowptr.dtype, val_dtype=torch.float32, device=device)
+            v["spasgn"].append(dict(kind="spasgn", A=A, I=aI, J=aJ, B=B, op=["second", "plus", "replace"][k % 3]))
+        out.append(v)
+    return out
+
+
+def served_trace(variants, rate_hz: float, duration_s: float, seed: int = 0):
+    """Poisson arrivals with a 60/20/20 extraction / assignment / permutation
+    mix over the pool's variants: (arrival times in s, list of requests)."""
+    arr = poisson_arrivals(rate_hz, duration_s, seed, "served-arrivals")
+    key = stream_key(seed, "served-trace")
+    n = int(arr.numel())
+    u = values(stream_key(key, "kind"), n, torch.float64)
+    mi = randint_below(stream_key(key, "mat"), n, len(variants))
+    per = len(variants[0]["spref"]) if variants else 1
+    vi = randint_below(stream_key(key, "var"), n, per)
+    trace = []
+    for k in range(n):
+        kind = "spref" if u[k] <= 0.6 else ("spasgn" if u[k] <= 0.8 else "permute")
+        trace.append(variants[int(mi[k])][kind][int(vi[k])])
+    return arr, trace

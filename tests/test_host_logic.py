@@ -1,6 +1,9 @@
 """Host-side logic that needs no GPU: the struct layouts the Python binding
-marshals match the C header, and the served form's range allocator keeps
-its invariants under random traffic (compiled natively with g++)."""
+marshals match the C header; the served form's range allocator keeps its
+invariants under random traffic; the bounded host wait ends on completion,
+on a failure and at its time limit, and stops spinning after its first
+polls.  The C++ parts are compiled natively with g++, once plainly and once
+with AddressSanitizer and UndefinedBehaviorSanitizer (host code only)."""
 import ctypes
 import os
 import subprocess
@@ -13,15 +16,21 @@ INC = os.path.join(ROOT, "include")
 CSRC = os.path.join(ROOT, "paper_2509_20776_amd", "csrc")
 
 
-def _run_c(tmp_path, src, lang="c"):
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+
+
+def _run_c(tmp_path, src, lang="c", flags=()):
     ext = "c" if lang == "c" else "cpp"
     f = tmp_path / f"t.{ext}"
     f.write_text(src)
     exe = tmp_path / "t"
     cc = ["gcc", "-std=c99"] if lang == "c" else ["g++", "-std=c++17", "-O1"]
-    subprocess.run(cc + ["-I", INC, "-I", CSRC,
-                         str(f), "-o", str(exe)], check=True, capture_output=True, text=True)
-    return subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    subprocess.run(cc + list(flags) + ["-I", INC, "-I", CSRC,
+                                       str(f), "-o", str(exe)], check=True, capture_output=True, text=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, env=env)
+    assert r.returncode == 0, r.stdout + r.stderr
+    return r.stdout
 
 
 def test_struct_layouts_match_binding(tmp_path):
@@ -46,7 +55,8 @@ def test_struct_layouts_match_binding(tmp_path):
             assert got[(name, fname)] == getattr(cls, fname).offset, (name, fname)
 
 
-def test_range_allocator_invariants(tmp_path):
+@pytest.mark.parametrize("flags", [(), tuple(SANITIZE)], ids=["plain", "asan-ubsan"])
+def test_range_allocator_invariants(tmp_path, flags):
     src = textwrap.dedent(r"""
         #include <cstdio>
         #include <cstdlib>
@@ -89,5 +99,72 @@ def test_range_allocator_invariants(tmp_path):
             return 0;
         }
     """)
-    out = _run_c(tmp_path, src, lang="c++")
+    out = _run_c(tmp_path, src, lang="c++", flags=flags)
+    assert out.startswith("OK"), out
+
+
+@pytest.mark.parametrize("flags", [(), tuple(SANITIZE)], ids=["plain", "asan-ubsan"])
+def test_bounded_wait(tmp_path, flags):
+    """hp_poll.hpp driven by a fake query and a fake clock: it returns at
+    completion or failure, times out at the limit, spins only for the first
+    polls, then yields, then sleeps; the limit comes from HP_HOST_WAIT_MS."""
+    src = textwrap.dedent(r"""
+        #include <cstdio>
+        #include <cstdlib>
+        #include <vector>
+        #include "hp_poll.hpp"
+        using namespace hp;
+        #define CHECK(c) do { if (!(c)) { printf("FAIL line %d: %s\n", __LINE__, #c); return 1; } } while (0)
+        int main() {
+            WaitPolicy pol{50'000'000, 8, 16, 20'000};
+            int64_t clock = 0;
+            std::vector<int64_t> pauses;
+            auto now = [&] { return clock; };
+            auto pause = [&](int64_t ns) { pauses.push_back(ns); clock += ns > 0 ? ns : 100; };
+            // ready at the 5th query: no pause inside the spin burst
+            int q = 0;
+            int64_t polls = 0;
+            WaitResult r = wait_until([&] { return ++q >= 5 ? Poll::READY : Poll::PENDING; }, pol, now, pause, &polls);
+            CHECK(r == WaitResult::DONE && polls == 5 && pauses.empty());
+            // a failure ends the wait at once
+            q = 0;
+            r = wait_until([&] { return ++q >= 3 ? Poll::FAILED : Poll::PENDING; }, pol, now, pause, &polls);
+            CHECK(r == WaitResult::FAILED && polls == 3);
+            // never ready: spin burst, then yields, then sleeps, until the limit
+            pauses.clear();
+            clock = 0;
+            r = wait_until([&] { clock += 1000; return Poll::PENDING; }, pol, now, pause, &polls);
+            CHECK(r == WaitResult::TIMED_OUT);
+            CHECK(clock >= pol.limit_ns && clock < pol.limit_ns + 2 * (pol.sleep_ns + 2000));
+            CHECK(polls == (int64_t)pauses.size() + pol.spin_polls);
+            for (size_t k = 0; k < pauses.size(); k++)
+                CHECK(pauses[k] == (k < (size_t)pol.yield_polls ? 0 : pol.sleep_ns));
+            // no limit: waits as long as it takes
+            WaitPolicy forever{0, 2, 2, 1000};
+            q = 0;
+            r = wait_until([&] { return ++q >= 100000 ? Poll::READY : Poll::PENDING; }, forever, now, pause, &polls);
+            CHECK(r == WaitResult::DONE && polls == 100000);
+            // the real clock and pauses: a query that becomes ready after 3 ms
+            const int64_t t0 = steady_ns();
+            r = wait_until([&] { return steady_ns() - t0 > 3'000'000 ? Poll::READY : Poll::PENDING; },
+                           default_wait_policy());
+            CHECK(r == WaitResult::DONE);
+            // and one that never does, with a 20 ms limit
+            WaitPolicy short_pol = default_wait_policy();
+            short_pol.limit_ns = 20'000'000;
+            const int64_t t1 = steady_ns();
+            r = wait_until([] { return Poll::PENDING; }, short_pol);
+            CHECK(r == WaitResult::TIMED_OUT && steady_ns() - t1 >= 20'000'000);
+            // the limit's source
+            unsetenv("HP_HOST_WAIT_MS");
+            CHECK(host_wait_limit_ns() == int64_t(600) * 1000000000);
+            setenv("HP_HOST_WAIT_MS", "250", 1);
+            CHECK(host_wait_limit_ns() == 250'000'000);
+            setenv("HP_HOST_WAIT_MS", "zero", 1);
+            CHECK(host_wait_limit_ns() == int64_t(600) * 1000000000);
+            puts("OK");
+            return 0;
+        }
+    """)
+    out = _run_c(tmp_path, src, lang="c++", flags=flags)
     assert out.startswith("OK"), out
