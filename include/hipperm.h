@@ -164,6 +164,33 @@ hp_status_t hp_permute_exec(hp_handle_t h, const hp_csr_t *A, const int32_t *p, 
                             hp_csr_t *C, void *ws, size_t ws_bytes, const hp_plan_info_t *info,
                             void *xws, size_t xws_bytes);
 
+/* ---- permute that allocates nothing --------------------------------------- */
+/* For callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  hp_permute_plan and
+ * hp_permute_exec in one call, with both workspaces taken from a fixed
+ * device array inside the library (HP_NOALLOC_SCRATCH_BYTES on every device
+ * the library runs on, held until the process ends) instead of caller
+ * workspaces.  The call allocates nothing (no hipMalloc or hipFree, no
+ * event or stream creation); like the plan it blocks once, on the readback
+ * of the output's row classes.
+ * A, p, q: as hp_permute_plan.  C: as hp_permute_plan, and C->col and
+ * C->val must hold nnz(A) entries (a permutation keeps nnz); plan writes
+ * C->rowptr and C->nnz, exec C->col and C->val.
+ * Limit: the plan workspace (hp_permute_workspace: about 36 bytes per row
+ * of a square matrix, so up to about 1.8M rows) and, for rows longer than
+ * 2048 entries, the exec workspace must fit the array together; otherwise
+ * HP_ERR_WORKSPACE (when only the exec part does not fit, C->rowptr has
+ * already been written).  Stage timing must be off (HP_ERR_INVALID_ARG).
+ * Every call on one device shares that device's array, which keeps the
+ * last call's contents; each call clears what it needs cleared (status
+ * block, scan tiles, inverse maps) before use.  Calls that overlap on one
+ * device (other threads, other streams or handles) race on the array and
+ * give undefined results: serialise them.
+ * Errors: as hp_permute_plan and hp_permute_exec, plus WORKSPACE. */
+#define HP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+hp_status_t hp_permute_noalloc(hp_handle_t h, const hp_csr_t *A, const int32_t *p, const int32_t *q,
+                               hp_csr_t *C);
+
 /* ---- spref: C = A(I, J), C[i,j] = A[I[i], J[j]] (Sec. 2.2) -------------- */
 /* I (nI entries) and J (nJ entries) may repeat values and be in any order:
  * a repeated row (column) is replicated, order follows I and J.

@@ -181,6 +181,9 @@ size_t val_size(int32_t t);
 hp_status_t check_csr_args(hp_handle_t h, const hp_csr_t *A, const char *name);
 
 void batch_release_handle(hp_handle_t h);   // forget batch plans and graphs of h
+// Looks up the device address of the fixed scratch array of hp_permute_noalloc
+// on `device` (which the caller has made current); once per device.
+hp_status_t noalloc_setup(int device);
 
 // Stage timing (no-ops unless enabled).
 void stage_begin(hp_handle_t h);

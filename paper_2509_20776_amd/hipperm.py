@@ -135,6 +135,7 @@ hp_spref_dcsc_workspace = _sig("hp_spref_dcsc_workspace", [_P, _DCSCP, _I64, _I6
 hp_spref_dcsc_plan = _sig("hp_spref_dcsc_plan", [_P, _DCSCP, _P, _I64, _P, _I64, _DCSCP, _P, _SZ, _INFOP])
 hp_spref_dcsc_exec = _sig("hp_spref_dcsc_exec", [_P, _DCSCP, _P, _I64, _P, _I64, _DCSCP, _P, _SZ, _INFOP,
                                                  _P, _SZ])
+hp_permute_noalloc = _sig("hp_permute_noalloc", [_P, _CSRP, _P, _P, _CSRP])
 hp_gather_index = _sig("hp_gather_index", [_P, _P, _I64, _P, _I64, _P])
 hp_invert_perm = _sig("hp_invert_perm", [_P, _P, _I64, _P])
 hp_block_nnz = _sig("hp_block_nnz", [_P, _CSRP, ctypes.c_int32, ctypes.c_int32, _P])
@@ -310,6 +311,21 @@ class Handle:
     def permute(self, A, p, q=None):
         C, ws, info = self.permute_plan(A, p, q)
         return self.permute_exec(A, p, q, C, ws, info)
+
+    def permute_noalloc(self, A, p, q=None, out=None):
+        """C = P A Q^T through hp_permute_noalloc: the library takes its
+        workspaces from its fixed scratch array.  `out` (a CSR of A's shape
+        and types with nnz(A) entries) receives the result; without it one
+        is allocated here, before the call."""
+        self._stream()
+        Ac = to_csr_t(A)
+        if out is None:
+            out = CSR(A.nrows, A.ncols, torch.empty(A.nrows + 1, dtype=A.rowptr.dtype, device=A.rowptr.device),
+                      torch.empty(A.nnz, dtype=torch.int32, device=A.col.device),
+                      torch.empty(A.nnz, dtype=A.val.dtype, device=A.val.device))
+        Cc = to_csr_t(out)
+        self.check(hp_permute_noalloc(self.h, ctypes.byref(Ac), _idx(p), _idx(q), ctypes.byref(Cc)))
+        return out
 
     # ---- spref -------------------------------------------------------------
     def spref_plan(self, A, I, J, ws=None):
