@@ -199,29 +199,107 @@ def run_rmat_extract(hp, args):
     # sort stage is several smaller kernels)
     res["roofline"] = roofline(stages, "spref.gather", b["gather"], "rmat-extract")
     if args.cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline_spref(A, I, J, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline_spref(A, I, J, args.cpu_reps)
     return res
 
 
-def cpu_baseline_spref(A, I, J, seconds):
-    """The oracle (literal definition, one thread) on the first rows of I."""
+def _host_cpus():
+    """(threads the oracle may use here, CPU model name).  The thread count
+    is the CPUs this process may run on, capped by OMP_NUM_THREADS when set."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return max(1, n), model
+
+
+def cpu_baseline_spref(A, I, J, reps=3):
+    """The oracle's extraction through the column multimap (its routine whose
+    cost is the entries read) on the whole headline workload, inputs already
+    in host memory: single-threaded and row-parallel over the host's CPUs,
+    median of `reps` runs each."""
     import numpy as np
     import oracle
-    Ah = A.to("cpu")
-    Ih, Jh = I.cpu(), J.cpu()
-    rp = Ah.rowptr.numpy().astype(np.int64)
-    Inp = Ih.numpy().astype(np.int64)
-    done, scanned, t0 = 0, 0, time.perf_counter()
-    chunk = 16
-    while time.perf_counter() - t0 < seconds and done < len(Inp):
-        rows = np.arange(done, min(done + chunk, len(Inp)))
-        oracle.spref(Ah, Ih, Jh, rows=rows)
-        scanned += int((rp[Inp[rows] + 1] - rp[Inp[rows]]).sum())
-        done += len(rows)
-    el = time.perf_counter() - t0
-    return {"value": scanned / el, "unit": "nnz/s", "cores": 1, "kind": "oracle",
-            "sample": f"rows I[0:{done}] of {len(Inp)} ({scanned} scanned nnz), literal definition "
-                      f"(binary search of every J position in each selected row), {el:.1f}s"}
+    Ah = (A.nrows, A.ncols, A.rowptr.cpu().numpy().astype(np.int64), A.col.cpu().numpy(), A.val.cpu().numpy())
+    Ih, Jh = I.cpu().numpy().astype(np.int32), J.cpu().numpy().astype(np.int32)
+    rp = Ah[2]
+    Il = Ih.astype(np.int64)
+    scanned = int((rp[Il + 1] - rp[Il]).sum())
+    nt, model = _host_cpus()
+
+    def med(threads):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.spref_map(Ah, Ih, Jh, threads=threads)
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[len(ts) // 2]
+
+    t1 = med(1)
+    tn = med(nt)
+    return {"value": scanned / tn, "unit": "nnz/s", "cores": nt, "kind": "oracle",
+            "sample": f"the whole extraction ({len(Ih)} rows of I, {scanned} scanned nnz), oracle routine through the "
+                      f"column multimap, row-parallel over {nt} threads, median of {reps} runs ({tn:.2f} s)",
+            "single_thread": {"value": scanned / t1, "unit": "nnz/s", "cores": 1, "seconds": round(t1, 3)},
+            "cpu_model": model}
+
+
+def run_er_small_latency(hp, args):
+    """Latency of single small calls: P A P^T and A(I, I) on the Erdos-Renyi
+    4096 x 4096 matrix (average degree 8, int32 CSR, fp64; I 1024 sorted
+    unique rows), each call plan + exec with reused workspaces, timed on the
+    host from the call to the end of its device work; p10 / p50 / p90 over
+    `lat_reps` calls.  The permutation through the no-allocation entry point
+    is timed beside it."""
+    import numpy as np
+    w = synth.workload_er_small(device="cuda")
+    A, p, I = w["A"], w["p"], w["I"]
+    h = hp.handle(0)
+    _, wsp, _ = h.permute_plan(A, p)
+    _, wss, _ = h.spref_plan(A, I, I)
+    out = hp.CSR(A.nrows, A.ncols, torch.empty_like(A.rowptr), torch.empty_like(A.col), torch.empty_like(A.val))
+
+    def perm():
+        C, _, inf = h.permute_plan(A, p, ws=wsp)
+        h.permute_exec(A, p, None, C, wsp, inf)
+
+    def sp():
+        C, _, inf = h.spref_plan(A, I, I, ws=wss)
+        h.spref_exec(A, I, I, C, wss, inf)
+
+    def noalloc():
+        h.permute_noalloc(A, p, out=out)
+
+    res = {}
+    for name, fn in (("permute", perm), ("spref", sp), ("permute_noalloc", noalloc)):
+        for _ in range(10):
+            fn()
+        _sync()
+        ts = []
+        for _ in range(args.lat_reps):
+            t0 = time.perf_counter()
+            fn()
+            _sync()
+            ts.append((time.perf_counter() - t0) * 1e6)
+        q = np.percentile(np.asarray(ts), [10, 50, 90])
+        res[name] = {"p10_us": round(float(q[0]), 1), "p50_us": round(float(q[1]), 1), "p90_us": round(float(q[2]), 1)}
+    return dict(value=res["permute"]["p50_us"], unit="us", higher_is_better=False,
+                ms_per_step=res["permute"]["p50_us"] / 1e3, latency=res,
+                config={"workload": "er-small-latency", "desc": "single calls, plan + exec, host-timed to completion: "
+                        "P A P^T and A(I,I) on ER 4096^2 avg degree 8 (int32, fp64), I = 1024 sorted unique rows; "
+                        "p10/p50/p90 over %d calls" % args.lat_reps, "nnz": A.nnz, "reps": args.lat_reps})
 
 
 def run_grid_permute(hp, args):
@@ -430,6 +508,36 @@ def stream_copy_gbps(mib=1024, reps=5):
     return round(2 * n / sec / 1e9, 1)
 
 
+def random_access_ceiling(mib=64, count=1 << 24, reps=5):
+    """Practical rate of random 4-byte accesses, the bound of a permutation
+    of a matrix whose rows move to random places: `count` random reads
+    (gather) and, separately, `count` random writes (scatter, distinct
+    targets) into a table of `mib` MiB, with torch's indexing kernels,
+    timed with events.  Returns accesses per second of each."""
+    n = (mib << 20) // 4
+    table = torch.arange(n, dtype=torch.int32, device="cuda")
+    key = synth.stream_key(0, "random-ceiling")
+    idx = synth.randperm(key, n, "cuda")[:count].long()
+    vals = torch.ones(count, dtype=torch.int32, device="cuda")
+    out = torch.empty(count, dtype=torch.int32, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for name, fn in (("gather", lambda: torch.index_select(table, 0, idx, out=out)),
+                     ("scatter", lambda: table.index_copy_(0, idx, vals))):
+        fn()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / reps
+        res[name + "_per_s"] = round(count / sec / 1e9, 2) * 1e9
+    res["table_MiB"] = mib
+    res["accesses"] = count
+    del table, idx, vals, out
+    return res
+
+
 def run_served_sweep(hp, args):
     """The served trace at a series of arrival rates, beside the plain
     per-call replay of each: where each path saturates."""
@@ -474,6 +582,14 @@ def run_batched(hp, args):
     assert all(x == 0 for x in st), st
     b.exec()
     _sync()
+    # every batched result is byte-identical to its plain call
+    bits = lambda t: t.view(torch.int64 if t.element_size() == 8 else torch.int32)
+    for k, (r, C) in enumerate(zip(reqs, b.results())):
+        P = hp.spref(r["A"], r["I"], r["J"]) if r["kind"] == "spref" else hp.permute(r["A"], r["p"], r["q"])
+        if not (torch.equal(C.rowptr, P.rowptr) and torch.equal(C.col, P.col) and torch.equal(bits(C.val), bits(P.val))):
+            raise AssertionError(f"batched request {k} ({r['kind']}) differs from its plain call")
+    del P
+    log(f"[bench] batched: all {len(reqs)} results equal their plain calls")
     nbytes, scanned = 0, 0
     for k, r in enumerate(reqs):
         A = r["A"]
@@ -502,7 +618,7 @@ def run_batched(hp, args):
     return dict(value=scanned / sec_b, unit="nnz/s", ms_per_step=sec_b * 1e3,
                 plain_ms_per_step=sec_p * 1e3, speedup_vs_plain=sec_p / sec_b,
                 algorithmic_GBps=nbytes / sec_b / 1e9, plain_algorithmic_GBps=nbytes / sec_p / 1e9,
-                grid_plan=int(b.info.grid_plan), grid_exec=int(b.info.grid_exec),
+                equal_to_plain=True, grid_plan=int(b.info.grid_plan), grid_exec=int(b.info.grid_exec),
                 tiles_plan=int(b.info.tiles_plan), tiles_exec=int(b.info.tiles_exec),
                 config={"workload": "batched", "desc": "%d spref/permute requests (50/50) on a pool of %d R-MAT "
                         "(scale U{12..20}, ef U{8..32}), int32 CSR, fp32, subsets 5-50%%; value = scanned nnz/s "
@@ -573,33 +689,48 @@ def _served_at(hp, args, pool, var, rate):
     for c in srv.poll():
         if c["status"] == 0:
             srv.release(c["id"])
-    # served run
-    lat, nnz_done, status_bad, bsz = [], 0, 0, []
-    t0 = time.perf_counter()
+    # served run: a collector thread takes completions and releases their
+    # results as soon as they arrive, while this thread submits on schedule
+    import threading
+    lat, bsz = [], []
+    stats = {"nnz": 0, "bad": 0}
     ns0 = time.monotonic_ns()
     pend = {}
+    submitted_all = threading.Event()
+    lock = threading.Lock()          # a completion's id is in pend before it can be polled
 
-    def collect():
-        nonlocal nnz_done, status_bad
-        for c in srv.poll():
-            k = pend.pop(c["id"])
-            if c["status"] != 0:
-                status_bad += 1
-            else:
-                nnz_done += out_nnz(c["C"])
-                srv.release(c["id"])
-            lat.append((c["t_done_ns"] - (ns0 + int(arr[k] * 1e9))) / 1e6)
-            bsz.append(c["batch_size"])
+    def collect_loop():
+        while True:
+            with lock:
+                got = srv.poll()
+            for c in got:
+                k = pend.pop(c["id"])
+                if c["status"] != 0:
+                    stats["bad"] += 1
+                else:
+                    stats["nnz"] += out_nnz(c["C"])
+                    srv.release(c["id"])
+                lat.append((c["t_done_ns"] - (ns0 + int(arr[k] * 1e9))) / 1e6)
+                bsz.append(c["batch_size"])
+            if not got:
+                if submitted_all.is_set() and not pend:
+                    return
+                time.sleep(0.0005)
 
+    t0 = time.perf_counter()
+    ns0 = time.monotonic_ns()
+    collector = threading.Thread(target=collect_loop, daemon=True)
+    collector.start()
     for k in range(n):
         dt = arr[k] - (time.perf_counter() - t0)
         if dt > 0:
             time.sleep(dt)
-        pend[submit(srv, trace[k])] = k
-        if k % 64 == 0:
-            collect()
+        with lock:
+            pend[submit(srv, trace[k])] = k
+    submitted_all.set()
     srv.drain()
-    collect()
+    collector.join()
+    nnz_done, status_bad = stats["nnz"], stats["bad"]
     wall = time.perf_counter() - t0
     in_use, peak = srv.memory()
     srv.close()
@@ -620,11 +751,13 @@ def _served_at(hp, args, pool, var, rate):
         _sync()
         nnz_p += out_nnz(C)
         lat_p.append((time.perf_counter() - t0 - arr[k]) * 1e3)
-        if time.perf_counter() - t0 > args.served_seconds * 10 + 10:
+        if time.perf_counter() - t0 > args.served_seconds * args.served_plain_cap:
             log(f"[bench] plain replay stopped after {k+1} of {n} requests (time cap)")
             break
     wall_p = max(time.perf_counter() - t0, 1e-9)
+    done_rate = (len(lat) - status_bad) / wall
     return dict(value=len(lat) / wall, unit="req/s", ms_per_step=wall * 1e3 / max(1, len(lat)),
+                offered_req_per_s=rate, overloaded=bool(done_rate < 0.95 * rate),
                 p50_ms=_pctl(lat, 50), p99_ms=_pctl(lat, 99), out_nnz_per_s=nnz_done / wall,
                 failed=status_bad, mean_batch=float(np.mean(bsz)) if bsz else 0.0,
                 pool_peak_bytes=int(peak),
@@ -638,7 +771,8 @@ def _served_at(hp, args, pool, var, rate):
                         "requests": n})
 
 
-WORKLOADS = {"rmat-extract": run_rmat_extract, "grid-permute": run_grid_permute,
+WORKLOADS = {"rmat-extract": run_rmat_extract, "er-small-latency": run_er_small_latency,
+             "grid-permute": run_grid_permute,
              "grid-assign": run_grid_assign, "grid-assign-permute": run_grid_assign_permute,
              "incremental": run_incremental, "hypersparse-extract": run_hypersparse_extract,
              "batched": run_batched, "served": run_served, "served-sweep": run_served_sweep}
@@ -655,19 +789,22 @@ def main():
     ap.add_argument("--side", type=int, default=4096)
     ap.add_argument("--incr-scale", type=int, default=22)
     ap.add_argument("--hyper-scale", type=int, default=26)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-reps", type=int, default=3, help="oracle runs per thread count (median reported)")
+    ap.add_argument("--lat-reps", type=int, default=100, help="calls per latency measurement")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-extras", dest="extras", action="store_false")
     ap.add_argument("--batch-pool", type=int, default=64)
     ap.add_argument("--batch-requests", type=int, default=512)
     ap.add_argument("--served-pool", type=int, default=32)
-    ap.add_argument("--served-scale-hi", type=int, default=20)
+    ap.add_argument("--served-scale-hi", type=int, default=24)
     ap.add_argument("--served-rate", type=float, default=2000.0)
     ap.add_argument("--served-sweep", default="1000,2000,3000,4000,6000",
                     help="arrival rates of --workload served-sweep")
-    ap.add_argument("--served-rate2", type=float, default=4000.0,
-                    help="second, overload arrival rate for the served leg (0: skip)")
-    ap.add_argument("--served-seconds", type=float, default=2.0)
+    ap.add_argument("--served-rate2", type=float, default=0.0,
+                    help="second arrival rate for the served leg (0: skip)")
+    ap.add_argument("--served-seconds", type=float, default=10.0)
+    ap.add_argument("--served-plain-cap", type=float, default=3.0,
+                    help="the plain replay stops after this many times the trace length")
     ap.add_argument("--served-streams", type=int, default=4)
     ap.add_argument("--served-budget-gb", type=int, default=64)
     ap.add_argument("--served-max-batch", type=int, default=16)
@@ -699,11 +836,13 @@ def main():
             also[name] = {k: v for k, v in r.items() if k != "cpu_baseline"}
             log(f"[bench] {name}: {r['value']:.3e} {r['unit']}, {r['ms_per_step']:.3f} ms/step")
     copy_gbps = stream_copy_gbps()
+    rand = random_access_ceiling()
     out = {"metric": METRIC, "value": head["value"], "unit": head["unit"], "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
            "data": "synthetic", "config": head["config"], "roofline": head.get("roofline"),
-           "cpu_baseline": head.get("cpu_baseline"), "stream_copy_GBps": copy_gbps}
+           "cpu_baseline": head.get("cpu_baseline"), "stream_copy_GBps": copy_gbps,
+           "random_access_ceiling": rand}
     for k, v in head.items():
         if k not in out and k not in ("cpu_baseline",):
             out[k] = v

@@ -148,6 +148,14 @@ int hp_stage_times(hp_handle_t h, float *ms_total, int *count, const char **name
 /* Canonical-CSR check (rowptr monotone, columns in range, strictly
  * ascending in each row).  Returns HP_OK, HP_ERR_NOT_CANONICAL or
  * HP_ERR_INDEX_RANGE.  ws must hold hp_validate_workspace() bytes. */
+/* Input validation inside the plans: when enabled, every plan on CSR input
+ * (permute, spref, spasgn and the fused form; A, and B for assignments)
+ * first runs the canonical-CSR check above on its inputs, with one extra
+ * blocking readback, and returns HP_ERR_NOT_CANONICAL or HP_ERR_INDEX_RANGE
+ * before launching anything else.  Off by default (non-canonical input is
+ * then undefined behaviour); hp_create switches it on when the environment
+ * variable HP_VALIDATE is set to anything but "0". */
+hp_status_t hp_set_validate(hp_handle_t h, int enable);
 hp_status_t hp_validate_workspace(hp_handle_t h, const hp_csr_t *A, size_t *bytes);
 hp_status_t hp_validate_csr(hp_handle_t h, const hp_csr_t *A, void *ws, size_t ws_bytes);
 
@@ -177,10 +185,11 @@ hp_status_t hp_permute_exec(hp_handle_t h, const hp_csr_t *A, const int32_t *p, 
  * C->val must hold nnz(A) entries (a permutation keeps nnz); plan writes
  * C->rowptr and C->nnz, exec C->col and C->val.
  * Limit: the plan workspace (hp_permute_workspace: about 36 bytes per row
- * of a square matrix, so up to about 1.8M rows) and, for rows longer than
- * 2048 entries, the exec workspace must fit the array together; otherwise
- * HP_ERR_WORKSPACE (when only the exec part does not fit, C->rowptr has
- * already been written).  Stage timing must be off (HP_ERR_INVALID_ARG).
+ * of a square matrix) and the exec workspace (4 bytes per stored entry,
+ * plus temporaries for rows longer than 2048 entries) must fit the array
+ * together, e.g. 1M rows with 6M entries; otherwise HP_ERR_WORKSPACE (when
+ * only the exec part does not fit, C->rowptr has already been written).
+ * Stage timing must be off (HP_ERR_INVALID_ARG).
  * Every call on one device shares that device's array, which keeps the
  * last call's contents; each call clears what it needs cleared (status
  * block, scan tiles, inverse maps) before use.  Calls that overlap on one
@@ -294,17 +303,21 @@ hp_status_t hp_invert_perm(hp_handle_t h, const int32_t *p, int64_t n, int32_t *
 hp_status_t hp_block_nnz(hp_handle_t h, const hp_csr_t *A, int32_t gr, int32_t gc, uint64_t *counts);
 
 /* ---- batched form -------------------------------------------------------- */
-/* Many extraction (paper Sec. 2.2, Alg. 3) and permutation (Sec. 2.1,
- * Alg. 1) requests run together.  The plan half (J tables / inverse
- * permutations, counts, rowptr scans of every request) is a short sequence of
- * stage launches, each running the tiles of every request on persistent
+/* Many extraction (paper Sec. 2.2, Alg. 3), permutation (Sec. 2.1, Alg. 1)
+ * and assignment (Sec. 2.3, Alg. 4) requests run together.  The plan half
+ * of the extractions and permutations (J tables / inverse permutations,
+ * counts, rowptr scans of every request) is a short sequence of stage
+ * launches, each running the tiles of every request on persistent
  * workgroups, followed by one readback of all output sizes.  The exec half
  * (fill and row sort of every request) is a second sequence of stage
  * launches, captured once in a hipGraph and replayed for any later batch
  * with the same workspace, arena, grid and stage shapes.  Stream order
  * between the stages is the only inter-tile dependency.  The number of
  * persistent workgroups is picked per size class by timing candidates the
- * first time the class is seen (the halves are idempotent).
+ * first time the class is seen (the halves are idempotent).  Assignment
+ * requests (streaming merges of whole matrices) run the assignment's own
+ * plan and exec kernels on the same stream, inside the same captured graph
+ * for exec; their row pointers and plan tables live in the batch workspace.
  * Results are identical, bit for bit, to separate plain calls.
  * All requests of one batch share ptr_type and val_type.
  * Ownership: the caller owns the workspace and the arena; results point
@@ -313,11 +326,11 @@ hp_status_t hp_block_nnz(hp_handle_t h, const hp_csr_t *A, int32_t gr, int32_t g
 typedef enum { HP_REQ_SPREF = 0, HP_REQ_PERMUTE = 1, HP_REQ_SPASGN = 2 } hp_req_kind_t;
 
 typedef struct {
-    int32_t kind;          /* hp_req_kind_t (the batched calls take SPREF, PERMUTE) */
+    int32_t kind;          /* hp_req_kind_t                                        */
     int32_t status;        /* out: hp_status_t of this request after plan/exec     */
     hp_csr_t A;            /* input matrix (device arrays)                         */
     const int32_t *I, *J;  /* spref, spasgn: row / column index vectors (device)   */
-    int64_t nI, nJ;        /* spasgn: taken from B                                 */
+    int64_t nI, nJ;        /* lengths of I and J (spasgn: equal B's shape)         */
     const int32_t *p, *q;  /* permute: permutations (device); q NULL = symmetric    */
     hp_csr_t C;            /* out: shape/types/nnz after plan; rowptr/col/val point
                               into the arena after exec                            */
@@ -364,15 +377,17 @@ hp_status_t hp_batch_exec(hp_handle_t h, hp_request_t *reqs, int n, void *ws, si
  * own handle and stream, take whatever requests are pending when they become
  * free (continuous batching): extraction and permutation requests of one
  * index/value type go through the batched calls above (up to max_batch per
- * batch), assignment requests through the plain calls.  Up to max_inflight
- * batches run at once on separate streams.
+ * batch), assignment requests and requests over matrices of more than 2^22
+ * stored entries (which fill the GPU by themselves) through the plain
+ * calls.  Up to max_inflight batches run at once on separate streams.
  * Memory: every workspace and every result is carved from the caller's
  * device buffer `pool` (pool_bytes, the HBM budget).  A batch is admitted
  * when its workspace fits the free pool space; after its plan, its exact
  * output arena must fit too.  While memory is short a batch waits for
  * running batches to finish; a batch that cannot fit while no other batch
- * runs is split into single requests, and a single request that cannot fit
- * then completes with HP_ERR_REJECTED (unreleased results count as used).
+ * runs waits (up to release_wait_ms) for the caller to release results, is
+ * then split into single requests, and a single request that still cannot
+ * fit completes with HP_ERR_REJECTED (unreleased results count as used).
  * Results stay in the pool until hp_server_release; the caller must have
  * finished every use of a result (synchronised the streams that read it)
  * before releasing it, since its pool space is then reused.
@@ -389,8 +404,13 @@ hp_status_t hp_batch_exec(hp_handle_t h, hp_request_t *reqs, int n, void *ws, si
 typedef struct hp_server_s *hp_server_t;
 
 typedef struct {
-    int32_t max_inflight;  /* worker threads / streams (1..16; 0 = 4)              */
-    int32_t max_batch;     /* requests per batch (0 = 256)                         */
+    int32_t max_inflight;    /* worker threads / streams (1..16; 0 = 4)            */
+    int32_t max_batch;       /* requests per batch (0 = 256)                       */
+    int32_t release_wait_ms; /* a request that does not fit while no other batch
+                                runs waits this long for the caller to release
+                                results before it is rejected (0 = 1000 ms;
+                                negative: rejected at once)                        */
+    int32_t reserved;        /* set to 0                                           */
 } hp_server_config_t;
 
 typedef struct {

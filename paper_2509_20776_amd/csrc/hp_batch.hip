@@ -24,6 +24,7 @@
 #include "hp_segsort.hpp"
 #include "hp_spref_tiles.hpp"
 #include "hp_perm_tiles.hpp"
+#include "hp_tunecache.hpp"
 
 #include <algorithm>
 #include <array>
@@ -91,6 +92,8 @@ struct ReqDev {
     uint64_t glob_elems;
     int32_t nb, nbw;
     uint32_t cls[NBINS];
+    void *aws;               // assignment: its own plan workspace (host-side use only)
+    size_t aws_bytes;
 };
 
 struct QEntry {
@@ -350,10 +353,21 @@ struct Global {
     QEntry *queue;
 };
 
-size_t req_scratch(hp::Carve &c, const hp_request_t &rq, ReqDev &d) {
+size_t req_scratch(hp_handle_t h, hp::Carve &c, const hp_request_t &rq, ReqDev &d) {
     const size_t before = c.off;
     const int64_t m = rq.A.nrows, n = rq.A.ncols;
     const size_t ps = rq.A.ptr_type == HP_IDX_I64 ? 8 : 4;
+    if (rq.kind == HP_REQ_SPASGN) {
+        // an assignment runs through the assignment's own kernels: its plan
+        // workspace and its row pointers (written by plan, copied into the
+        // arena by exec) live here
+        size_t b = 0;
+        hp_spasgn_workspace(h, &rq.A, &rq.B, &b);
+        d.aws_bytes = b;
+        d.aws = c.take<char>(b);
+        d.crow_tmp = c.take<char>((size_t)(m + 1) * ps);
+        return c.off - before;
+    }
     if (rq.kind == HP_REQ_SPREF) {
         const int64_t nI = rq.nI, nJ = rq.nJ;
         const size_t st = scan_tiles(nI);
@@ -429,7 +443,13 @@ hp_status_t check_req(hp_handle_t h, const hp_request_t &r, int k, int32_t pt, i
         if (!r.q && r.A.nrows != r.A.ncols) return fail(h, HP_ERR_SHAPE, w + ": symmetric permute needs square A");
         if (r.A.nrows > 0 && !r.p) return fail(h, HP_ERR_INVALID_ARG, w + ": p is NULL");
     } else if (r.kind == HP_REQ_SPASGN) {
-        return fail(h, HP_ERR_INVALID_ARG, w + ": assignment requests are not batched (use hp_spasgn_*)");
+        st = check_csr_args(h, &r.B, (w + " B").c_str());
+        if (st) return st;
+        if (r.B.ptr_type != pt || r.B.val_type != vt)
+            return fail(h, HP_ERR_INVALID_ARG, w + ": B must have the batch's ptr_type and val_type");
+        if (r.nI != r.B.nrows || r.nJ != r.B.ncols) return fail(h, HP_ERR_SHAPE, w + ": B must be |I| x |J|");
+        if ((r.nI > 0 && !r.I) || (r.nJ > 0 && !r.J)) return fail(h, HP_ERR_INVALID_ARG, w + ": I or J is NULL");
+        if (r.op < HP_OP_SECOND || r.op > HP_OP_REPLACE) return fail(h, HP_ERR_INVALID_ARG, w + ": bad op");
     } else {
         return fail(h, HP_ERR_INVALID_ARG, w + ": unknown request kind");
     }
@@ -442,6 +462,7 @@ struct BatchState {
     DevHdr *hdrs = nullptr;      // pinned readback of the request headers
     int hdr_cap = 0;
     std::vector<ReqDev> devs;
+    std::vector<hp_plan_info_t> asg;   // plan infos of the assignment requests
 };
 
 std::map<hp_handle_t, BatchState> g_state;        // last plan per handle
@@ -450,8 +471,10 @@ struct GraphKey {
     int grid, pv;
     std::array<int64_t, NST> total;
     std::array<int, NST + 1> off;
+    std::vector<int64_t> asg;    // shapes of the assignment requests' launches
     bool operator<(const GraphKey &o) const {
-        return std::tie(ws, arena, grid, pv, total, off) < std::tie(o.ws, o.arena, o.grid, o.pv, o.total, o.off);
+        return std::tie(ws, arena, grid, pv, total, off, asg) <
+               std::tie(o.ws, o.arena, o.grid, o.pv, o.total, o.off, o.asg);
     }
 };
 struct GraphEntry {
@@ -467,6 +490,7 @@ int num_cus(hp_handle_t h) { return h->num_cus; }
 // Phase tile counts of one request.
 void plan_tiles(const hp_request_t &rq, const ReqDev &d, int64_t *nt) {
     for (int k = 0; k < NPH; k++) nt[k] = 0;
+    if (rq.kind == HP_REQ_SPASGN) return;   // runs its own kernels
     if (rq.kind == HP_REQ_SPREF) {
         const int64_t ngb = cdiv(rq.nI, 4 * WAVE);
         nt[0] = cdiv(d.nzero, CLEAR_PER_TILE);
@@ -488,7 +512,7 @@ void plan_tiles(const hp_request_t &rq, const ReqDev &d, int64_t *nt) {
 
 void exec_tiles(const hp_request_t &rq, const ReqDev &d, int64_t *nt) {
     for (int k = 0; k < NPH; k++) nt[k] = 0;
-    if (!d.active) return;
+    if (!d.active || rq.kind == HP_REQ_SPASGN) return;
     const uint32_t *c = d.cls;
     if (rq.kind == HP_REQ_SPREF) {
         const int64_t ngb = cdiv(rq.nI, 4 * WAVE);
@@ -565,33 +589,51 @@ hipError_t launch_half(hp_handle_t h, int half, const Global &g, int n, const St
 
 // Time one half at a few persistent grid sizes and keep the fastest per size
 // class (both halves are idempotent: every run starts from cleared state and
-// rewrites the same outputs).
+// rewrites the same outputs).  Each candidate runs TUNE_SAMPLES times and
+// counts with its median.  Choices persist in the tuner cache file
+// (hp_tunecache.hpp), loaded on first use, so a size class is timed once per
+// machine.
+constexpr int TUNE_SAMPLES = 3;
+bool g_cache_loaded = false;
+
 template <typename PT, typename VT>
 int tune_grid(hp_handle_t h, int half, const Global &g, int n, const Stages &S, const std::string &key,
               bool tune) {
-    if (!tune) return 2 * num_cus(h);
+    const int cus = num_cus(h);
+    if (!tune) return 2 * cus;
+    const std::string path = tune_cache_path();
     {
         std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_cache_loaded) {
+            for (auto &kv : tune_cache_load(path)) g_tuned.emplace(kv.first, kv.second);
+            g_cache_loaded = true;
+        }
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) return it->second;
     }
-    const int cus = num_cus(h);
-    const int cand[3] = {cus, 2 * cus, 4 * cus};
+    const int cand[4] = {cus, 2 * cus, 4 * cus, 8 * cus};
     int best = cand[1];
     if (getenv("HP_NO_TUNE")) return best;
     float best_ms = 1e30f;
+    bool ok = true;
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     for (int c : cand) {
-        hipEventRecord(e0, h->stream);
-        launch_half<PT, VT>(h, half, g, n, S, c);
-        hipEventRecord(e1, h->stream);
-        if (wait_event(h, e1, "batch tuner") != HP_OK) break;
-        float ms = 0;
-        hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_ms) {
-            best_ms = ms;
+        float t[TUNE_SAMPLES];
+        for (int r = 0; r < TUNE_SAMPLES && ok; r++) {
+            hipEventRecord(e0, h->stream);
+            launch_half<PT, VT>(h, half, g, n, S, c);
+            hipEventRecord(e1, h->stream);
+            if (wait_event(h, e1, "batch tuner") != HP_OK) ok = false;
+            t[r] = 0;
+            hipEventElapsedTime(&t[r], e0, e1);
+        }
+        if (!ok) break;
+        std::sort(t, t + TUNE_SAMPLES);
+        const float med = t[TUNE_SAMPLES / 2];
+        if (med < best_ms) {
+            best_ms = med;
             best = c;
         }
     }
@@ -599,15 +641,44 @@ int tune_grid(hp_handle_t h, int half, const Global &g, int n, const Stages &S, 
     hipEventDestroy(e1);
     std::lock_guard<std::mutex> lk(g_mu);
     g_tuned[key] = best;
+    if (ok) tune_cache_store(path, key, best);
     return best;
 }
 
-std::string size_class(const char *half, int32_t pt, int32_t vt, int64_t total) {
+// Size class of a half: device (compute units), index and value types, and
+// log2 of its tile count.
+std::string size_class(hp_handle_t h, const char *half, int32_t pt, int32_t vt, int64_t total) {
     int lg = 0;
     while ((int64_t(1) << lg) < total) lg++;
     char buf[96];
-    snprintf(buf, sizeof buf, "%s/p%d/v%d/t2^%d", half, pt, vt, lg);
+    snprintf(buf, sizeof buf, "batch/cu%d/%s/p%d/v%d/t2^%d", num_cus(h), half, pt, vt, lg);
     return buf;
+}
+
+__global__ void k_copy_words(uint32_t *__restrict__ dst, const uint32_t *__restrict__ src, int64_t n) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        dst[k] = src[k];
+}
+
+// The assignment requests of a batch: row pointers from the plan's copy in
+// the workspace into the arena (a kernel, so that a captured graph holds no
+// copy node), then the assignment's own exec kernels on the handle's stream.
+hp_status_t run_assignments(hp_handle_t h, hp_request_t *reqs, int n, const std::vector<ReqDev> &devs,
+                            const std::vector<hp_plan_info_t> &asg) {
+    for (int k = 0; k < n; k++) {
+        hp_request_t &r = reqs[k];
+        const ReqDev &d = devs[k];
+        if (r.kind != HP_REQ_SPASGN || !d.active) continue;
+        const int64_t words = (r.A.nrows + 1) * (r.A.ptr_type == HP_IDX_I64 ? 2 : 1);
+        const int grid = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (words + 255) / 256));
+        hipLaunchKernelGGL(k_copy_words, dim3(grid), dim3(256), 0, h->stream, (uint32_t *)d.crow,
+                           (const uint32_t *)d.crow_tmp, words);
+        if (hipError_t e = hipGetLastError()) return hip_check(h, e, "batch assignment rowptr copy");
+        const hp_status_t st = hp_spasgn_exec(h, &r.A, &r.B, r.I, r.J, (hp_asgn_op_t)r.op, &r.C, d.aws, d.aws_bytes,
+                                              &asg[k], d.tmp, asg[k].exec_ws_bytes);
+        if (st) return st;
+    }
+    return HP_OK;
 }
 
 template <typename PT, typename VT>
@@ -616,7 +687,7 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
     hp::Carve need(nullptr);
     global_layout(need, n);
     std::vector<ReqDev> devs(n);
-    for (int k = 0; k < n; k++) req_scratch(need, reqs[k], devs[k]);
+    for (int k = 0; k < n; k++) req_scratch(h, need, reqs[k], devs[k]);
     if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "batch workspace too small");
     hp::Carve c(ws);
     Global g = global_layout(c, n);
@@ -624,7 +695,7 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
     for (int k = 0; k < n; k++) {
         ReqDev &d = devs[k];
         d = ReqDev{};
-        req_scratch(c, reqs[k], d);
+        req_scratch(h, c, reqs[k], d);
         const hp_request_t &r = reqs[k];
         d.kind = r.kind;
         d.sym = r.q == nullptr;
@@ -658,7 +729,7 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
     if (e == hipSuccess && !S.q.empty())
         e = hipMemcpyAsync(g.queue, S.q.data(), sizeof(QEntry) * S.q.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_check(h, e, "batch plan upload");
-    const std::string key = size_class("plan", reqs[0].A.ptr_type, reqs[0].A.val_type, total);
+    const std::string key = size_class(h, "plan", reqs[0].A.ptr_type, reqs[0].A.val_type, total);
     const int grid = tune_grid<PT, VT>(h, 0, g, n, S, key, !(info && (info->flags & HP_BATCH_NO_TUNE)));
     stage_begin(h);
     e = launch_half<PT, VT>(h, 0, g, n, S, grid);
@@ -680,6 +751,24 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
     if (e == hipSuccess) e = hipMemcpyAsync(bs.hdrs, g.hdrs, sizeof(DevHdr) * n, hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_check(h, e, "batch plan");
     if (hp_status_t ws = wait_stream(h, "batch plan")) return ws;
+    // assignment requests: the assignment's own plan on the same stream,
+    // row pointers into the batch workspace (exec copies them to the arena)
+    std::vector<hp_plan_info_t> asg(n);
+    std::vector<hp_status_t> asg_st(n, HP_OK);
+    std::vector<int64_t> asg_nnz(n, 0);
+    for (int k = 0; k < n; k++) {
+        hp_request_t &r = reqs[k];
+        if (r.kind != HP_REQ_SPASGN) continue;
+        hp_csr_t Ct{};
+        Ct.nrows = r.A.nrows;
+        Ct.ncols = r.A.ncols;
+        Ct.ptr_type = r.A.ptr_type;
+        Ct.val_type = r.A.val_type;
+        Ct.rowptr = devs[k].crow_tmp;
+        asg_st[k] = hp_spasgn_plan(h, &r.A, &r.B, r.I, r.J, (hp_asgn_op_t)r.op, &Ct, devs[k].aws, devs[k].aws_bytes,
+                                   &asg[k]);
+        asg_nnz[k] = Ct.nnz;
+    }
     // per-request results and the arena
     const size_t ps = sizeof(PT), vs = sizeof(VT);
     size_t arena = 0;
@@ -688,6 +777,31 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
     for (int k = 0; k < n; k++) {
         hp_request_t &r = reqs[k];
         ReqDev &d = devs[k];
+        if (r.kind == HP_REQ_SPASGN) {
+            const hp_status_t st = asg_st[k];
+            r.C = hp_csr_t{};
+            r.C.nrows = r.A.nrows;
+            r.C.ncols = r.A.ncols;
+            r.C.ptr_type = r.A.ptr_type;
+            r.C.val_type = r.A.val_type;
+            r.C.nnz = st == HP_OK ? asg_nnz[k] : 0;
+            r.status = st;
+            d.active = st == HP_OK;
+            if (st != HP_OK) {
+                failed++;
+                continue;
+            }
+            nnz_total += r.C.nnz;
+            arena = (arena + 255) & ~size_t(255);
+            arena += (size_t)(r.A.nrows + 1) * ps + 256;
+            arena = (arena + 255) & ~size_t(255);
+            arena += (size_t)r.C.nnz * 4 + 256;
+            arena = (arena + 255) & ~size_t(255);
+            arena += (size_t)r.C.nnz * vs + 256;
+            arena = (arena + 255) & ~size_t(255);
+            arena += asg[k].exec_ws_bytes + 256;
+            continue;
+        }
         const DevHdr &H = bs.hdrs[k];
         hp_status_t st = status_from_err(h, H.err, "batch request");
         r.C = hp_csr_t{};
@@ -720,6 +834,7 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
     bs.ws = ws;
     bs.n = n;
     bs.devs = devs;
+    bs.asg = asg;
     if (info) {
         const int32_t flags = info->flags;   // caller's option bits survive the plan
         *info = hp_batch_info_t{};
@@ -759,7 +874,8 @@ hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
         d.crow = a.take<char>((size_t)(d.nrows_out + 1) * ps);
         d.ccol = a.take<int32_t>((size_t)r.C.nnz);
         d.cval = a.take<char>((size_t)r.C.nnz * vs);
-        d.tmp = a.take<char>(seg_tmp_bytes(d.glob_elems, d.cls[BIN_GLOBAL], vs, d.ncols_out));
+        d.tmp = r.kind == HP_REQ_SPASGN ? a.take<char>(bs.asg[k].exec_ws_bytes)
+                                        : a.take<char>(seg_tmp_bytes(d.glob_elems, d.cls[BIN_GLOBAL], vs, d.ncols_out));
         r.C.rowptr = d.crow;
         r.C.col = d.ccol;
         r.C.val = d.cval;
@@ -775,17 +891,27 @@ hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
     if (e == hipSuccess && !S.q.empty())
         e = hipMemcpyAsync(g.queue, S.q.data(), sizeof(QEntry) * S.q.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_check(h, e, "batch exec upload");
-    const std::string key = size_class("exec", reqs[0].A.ptr_type, reqs[0].A.val_type, total);
+    const std::string key = size_class(h, "exec", reqs[0].A.ptr_type, reqs[0].A.val_type, total);
     const int grid = tune_grid<PT, VT>(h, 1, g, n, S, key, !(info->flags & HP_BATCH_NO_TUNE));
     // exec runs from a captured graph, replayed for any batch with the same
     // workspace, arena, grid and stage shapes (queue and request records are
     // uploaded before every launch)
-    GraphKey gk{ws, arena, grid, (int)(ps * 16 + vs), {}, {}};
+    GraphKey gk{ws, arena, grid, (int)(ps * 16 + vs), {}, {}, {}};
     std::copy(S.total, S.total + NST, gk.total.begin());
     std::copy(S.off, S.off + NST + 1, gk.off.begin());
+    for (int k = 0; k < n; k++) {
+        if (reqs[k].kind != HP_REQ_SPASGN || !devs[k].active) continue;
+        const hp_plan_info_t &pi = bs.asg[k];
+        gk.asg.insert(gk.asg.end(), {k, pi.nnz_out, (int64_t)pi.exec_ws_bytes, pi.map_monotone, pi.op,
+                                     (int64_t)reqs[k].op});
+        for (int b = 0; b < 4; b++) gk.asg.insert(gk.asg.end(), {pi.rows_sorted[b], pi.class_elems[b], pi.aux[b]});
+    }
     stage_begin(h);
     if (info->flags & HP_BATCH_NO_GRAPH) {
         e = launch_half<PT, VT>(h, 1, g, n, S, grid);
+        if (e == hipSuccess) {
+            if (hp_status_t as = run_assignments(h, reqs, n, devs, bs.asg)) return as;
+        }
         stage_mark(h, "batch.exec");
         if (e != hipSuccess) return hip_check(h, e, "batch exec");
         info->tiles_exec = total;
@@ -818,8 +944,10 @@ hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
             e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
                 hipError_t le = launch_half<PT, VT>(h, 1, g, n, S, grid);
+                const hp_status_t as = le == hipSuccess ? run_assignments(h, reqs, n, devs, bs.asg) : HP_OK;
                 e = hipStreamEndCapture(cs, &ge.g);
                 if (e == hipSuccess) e = le;
+                if (e == hipSuccess && as != HP_OK) e = hipErrorUnknown;
             }
             h->stream = keep;
             hipStreamDestroy(cs);
@@ -870,7 +998,7 @@ extern "C" hp_status_t hp_batch_workspace(hp_handle_t h, const hp_request_t *req
         hp_status_t st = check_req(h, reqs[k], k, reqs[0].A.ptr_type, reqs[0].A.val_type);
         if (st) return st;
         ReqDev d{};
-        req_scratch(c, reqs[k], d);
+        req_scratch(h, c, reqs[k], d);
     }
     *bytes = c.size();
     return HP_OK;

@@ -126,6 +126,7 @@ extern "C" hp_status_t hp_create(hp_handle_t *out, int device) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         h->num_cus = prop.multiProcessorCount;
+    h->validate = hp::validate_from_env();
     // the readback event, made here so that later calls create nothing
     if (hipEventCreateWithFlags(&h->rb_done, hipEventDisableTiming) != hipSuccess) h->rb_done = nullptr;
     // this device's copy of the fixed scratch array (hp_permute_noalloc);

@@ -167,6 +167,7 @@ struct hp_handle_s {
     hipEvent_t ev_cur = nullptr;
     std::vector<hp_stage_rec> recs;        // recorded (stage, start, end) triples
     hipEvent_t rb_done = nullptr;          // marks the end of a plan's readback copy
+    bool validate = false;                 // plans check their CSR inputs first (HP_VALIDATE)
 };
 
 namespace hp {
@@ -181,6 +182,10 @@ size_t val_size(int32_t t);
 hp_status_t check_csr_args(hp_handle_t h, const hp_csr_t *A, const char *name);
 
 void batch_release_handle(hp_handle_t h);   // forget batch plans and graphs of h
+// Input validation of the plans (hp_validate.hip): whether HP_VALIDATE asks
+// for it, and the check itself (a no-op unless h->validate).
+bool validate_from_env();
+hp_status_t validate_input(hp_handle_t h, const hp_csr_t *M, DevHdr *hdr, const char *what);
 // Looks up the device address of the fixed scratch array of hp_permute_noalloc
 // on `device` (which the caller has made current); once per device.
 hp_status_t noalloc_setup(int device);

@@ -88,5 +88,79 @@ struct LoadPerm {
     }
 };
 
+// ---- pull fill of the plain permutation ---------------------------------------
+// Output row i is row p[i] of A with every column c renamed qinv[c].  The
+// renaming is done once for all stored entries by a streaming pass (colq,
+// in A's storage order: coalesced reads of the columns, and for banded
+// matrices local reads of qinv), so the fill itself reads each source row
+// once, at a random place, and writes the output rows in order: random
+// reads and coalesced writes, instead of the random partial-line writes of
+// a push to row pinv[r].
+
+// colq[k] = cmap[col[k]] for the 1024 entries k of tile bid.
+__device__ inline void perm_colmap_tile(int64_t bid, const int32_t *__restrict__ acol, int64_t nnz, int64_t n,
+                                        const int32_t *__restrict__ cmap, int32_t *__restrict__ colq) {
+    const int64_t b = bid * 1024 + threadIdx.x;
+    int32_t c[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int64_t k = b + u * 256;
+        c[u] = k < nnz ? acol[k] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int64_t k = b + u * 256;
+        if (k < nnz) colq[k] = cmap[clampc(c[u], n)];
+    }
+}
+
+// Output rows of at most 4 entries, one lane per output row i (in order).
+template <typename PT, typename VT>
+__device__ inline void perm_pull_short_tile(int64_t bid, const PT *__restrict__ arow, const int32_t *__restrict__ colq,
+                                            const VT *__restrict__ aval, const int32_t *__restrict__ p,
+                                            const PT *__restrict__ crow, int32_t *__restrict__ ccol,
+                                            VT *__restrict__ cval, int64_t m, const DevHdr *hdr) {
+    if (hdr->err) return;
+    const int64_t i = bid * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int32_t pr = p[i];
+    const int64_t src = (uint32_t)pr < (uint64_t)m ? (int64_t)pr : 0;   // p was checked by the plan
+    const int64_t s = arow[src];
+    const int len = (int)(arow[src + 1] - s);
+    if (len == 0 || len > 4) return;
+    const int64_t d = crow[i];
+    int32_t k[4];
+    VT v[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        k[u] = INT32_MAX;
+        v[u] = VT(0);
+        if (u < len) {
+            k[u] = colq[s + u];
+            v[u] = aval[s + u];
+        }
+    }
+    sort_store_regs<4, VT>(k, v, len, false, ccol + d, cval + d);
+}
+
+// Longer output rows: the class sorts pull row p[i] with its columns
+// already renamed in colq.
+template <typename PT, typename VT>
+struct LoadPermMapped {
+    const PT *arow;
+    const int32_t *colq;
+    const VT *aval;
+    const int32_t *p;
+    int64_t m;
+    __device__ __forceinline__ int64_t base(int64_t row) const {
+        const int32_t pr = p[row];
+        return arow[(uint32_t)pr < (uint64_t)m ? (int64_t)pr : 0];
+    }
+    __device__ __forceinline__ void get(int64_t b, int64_t k, int32_t &kk, VT &vv) const {
+        kk = colq[b + k];
+        vv = aval[b + k];
+    }
+};
+
 }  // namespace perm
 }  // namespace hp

@@ -49,12 +49,21 @@ __global__ __launch_bounds__(256) void k_perm_check(int64_t m, int64_t n, const 
                                                    const int32_t *__restrict__ qinv, bool general, DevHdr *hdr) {
     perm_check_tile(blockIdx.x, m, n, pinv, qinv, general, hdr);
 }
+__global__ __launch_bounds__(256) void k_perm_colmap(const int32_t *__restrict__ acol, int64_t nnz, int64_t n,
+                                                    const int32_t *__restrict__ cmap, int32_t *__restrict__ colq) {
+    perm_colmap_tile(blockIdx.x, acol, nnz, n, cmap, colq);
+}
 template <typename PT, typename VT>
-__global__ __launch_bounds__(256) void k_perm_fill_short(
-    const PT *__restrict__ arow, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
-    const int32_t *__restrict__ pinv, const int32_t *__restrict__ cmap, const PT *__restrict__ crow,
-    int32_t *__restrict__ ccol, VT *__restrict__ cval, int64_t m, int64_t n, const DevHdr *hdr) {
-    perm_fill_short_tile<PT, VT>(blockIdx.x, arow, acol, aval, pinv, cmap, crow, ccol, cval, m, n, hdr);
+__global__ __launch_bounds__(256) void k_perm_pull_short(const PT *__restrict__ arow, const int32_t *__restrict__ colq,
+                                                        const VT *__restrict__ aval, const int32_t *__restrict__ p,
+                                                        const PT *__restrict__ crow, int32_t *__restrict__ ccol,
+                                                        VT *__restrict__ cval, int64_t m, const DevHdr *hdr) {
+    perm_pull_short_tile<PT, VT>(blockIdx.x, arow, colq, aval, p, crow, ccol, cval, m, hdr);
+}
+
+// Exec workspace: the class sorts' temporaries, then the renamed columns.
+size_t perm_xws_bytes(size_t seg_bytes, int64_t nnz) {
+    return ((seg_bytes + 255) & ~size_t(255)) + (((size_t)nnz * 4 + 255) & ~size_t(255));
 }
 
 hp_status_t perm_check_args(hp_handle_t h, const hp_csr_t *A, const int32_t *p, const int32_t *q,
@@ -92,6 +101,7 @@ hp_status_t perm_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
     Carve c(ws);
     PermLayout L = perm_layout(c, m, n, sym);
     hipStream_t s = h->stream;
+    if (hp_status_t v = validate_input(h, A, L.hdr, "permute plan: A")) return v;
     stage_begin(h);
     hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, scan_tiles(m));
     if (e == hipSuccess) e = launch_fill_words(s, L.pinv, (size_t)m, 0xFFFFFFFFu);
@@ -126,7 +136,8 @@ hp_status_t perm_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
             info->rows_sorted[b] = H.bin_cnt[b];
             info->class_elems[b] = (int64_t)H.bin_elems[b];
         }
-        info->exec_ws_bytes = seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], H.bin_cnt[BIN_GLOBAL], vs, n);
+        info->exec_ws_bytes = perm_xws_bytes(seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], H.bin_cnt[BIN_GLOBAL], vs, n),
+                                             A->nnz);
     }
     return HP_OK;
 }
@@ -159,16 +170,26 @@ hp_status_t perm_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
     hipStream_t s = h->stream;
     const int sorted = info->map_monotone;
     stage_begin(h);
+    const size_t seg_bytes = seg_tmp_bytes((uint64_t)info->class_elems[BIN_GLOBAL], (uint64_t)info->rows_sorted[BIN_GLOBAL],
+                                           vs, n);
+    if (info->exec_ws_bytes < perm_xws_bytes(seg_bytes, A->nnz))
+        return fail(h, HP_ERR_INVALID_ARG, "info is not from hp_permute_plan of this matrix");
+    int32_t *colq = (int32_t *)((char *)xws + ((seg_bytes + 255) & ~size_t(255)));
+    if (A->nnz > 0) {
+        hipLaunchKernelGGL(k_perm_colmap, dim3((unsigned)((A->nnz + 1023) / 1024)), dim3(256), 0, s, A->col, A->nnz,
+                           n, L.qinv, colq);
+        stage_mark(h, "perm.colmap");
+    }
     if (m > 0) {
-        hipLaunchKernelGGL((k_perm_fill_short<PT, VT>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
-                           (const PT *)A->rowptr, A->col, (const VT *)A->val, L.pinv, L.qinv,
-                           (const PT *)C->rowptr, C->col, (VT *)C->val, m, n, L.hdr);
+        hipLaunchKernelGGL((k_perm_pull_short<PT, VT>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                           (const PT *)A->rowptr, colq, (const VT *)A->val, p, (const PT *)C->rowptr, C->col,
+                           (VT *)C->val, m, L.hdr);
         stage_mark(h, "perm.fill_short");
     }
     uint32_t cnt[NBINS];
     for (int b = 0; b < NBINS; b++) cnt[b] = (uint32_t)info->rows_sorted[b];
-    LoadPerm<PT, VT> ld{(const PT *)A->rowptr, A->col, (const VT *)A->val, p, L.qinv, n};
-    hipError_t e = launch_seg_classes<PT, VT, LoadPerm<PT, VT>>(
+    LoadPermMapped<PT, VT> ld{(const PT *)A->rowptr, colq, (const VT *)A->val, p, m};
+    hipError_t e = launch_seg_classes<PT, VT, LoadPermMapped<PT, VT>>(
         s, (const PT *)C->rowptr, C->col, (VT *)C->val, L.lists, m, cnt, ld, sorted != 0, n, false, xws,
         (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);
     stage_mark(h, "perm.fill_long");

@@ -2,9 +2,10 @@
 // HBM budget).  Host code only; the GPU work is the batched and plain calls.
 //
 // Workers (one thread, handle and non-blocking stream each) loop:
-//   1. under the lock, take pending requests: an assignment alone, or up to
-//      max_batch extraction/permutation requests of the first one's index
-//      and value types (FIFO order otherwise);
+//   1. under the lock, take pending requests: an assignment alone, a request
+//      over a large matrix alone, or up to max_batch extraction/permutation
+//      requests of the first one's index and value types (FIFO order
+//      otherwise);
 //   2. admit: carve the batch workspace from the pool, waiting while it does
 //      not fit and other batches run; a batch that cannot fit even with
 //      nothing else running is split, a single request is rejected;
@@ -44,6 +45,10 @@ struct Pending {
     int64_t t_submit;
     bool solo;   // run in a batch of its own (after a split)
 };
+
+// Extraction and permutation requests over matrices with more stored
+// entries than this run alone through the plain calls, never in a batch.
+constexpr int64_t BATCH_MAX_NNZ = int64_t(1) << 22;
 
 size_t ptr_bytes(int32_t t) { return t == HP_IDX_I64 ? 8 : 4; }
 size_t val_bytes(int32_t t) { return t == HP_VAL_F64 ? 8 : 4; }
@@ -102,16 +107,22 @@ void release_block_locked(hp_server_s *S, size_t off) {
 
 // Wait (under the lock) until a block of n bytes can be carved; returns its
 // offset, or NONE when waiting cannot help: the block is larger than the
-// pool, or no other batch is running that could return memory.  A caller
+// pool, or no other batch is running that could return memory and the
+// caller has not released results within the release wait (only a single
+// request waits for releases: a batch is split instead).  A caller
 // that already counts in `running` (it holds a workspace and waits for its
 // output arena) passes holder = true and is counted as waiting meanwhile.
-size_t carve_locked(hp_server_s *S, Lock &lk, size_t n, bool holder) {
+size_t carve_locked(hp_server_s *S, Lock &lk, size_t n, bool holder, bool single) {
+    const int64_t wait = single ? (int64_t)std::max(0, S->cfg.release_wait_ms) * 1000000 : 0;
+    const int64_t deadline = now_ns() + wait;
     for (;;) {
         const size_t off = S->alloc.alloc(n);
         if (off != RangeAlloc::NONE) return off;
         if (!S->alloc.fits_empty(n)) return RangeAlloc::NONE;
         const int others = S->running - S->waiting - (holder ? 1 : 0);
-        if (others <= 0) return RangeAlloc::NONE;
+        // nothing running will return memory: only the caller's releases of
+        // results can, and they are waited for up to the release wait
+        if (others <= 0 && (S->result_block.empty() || now_ns() >= deadline)) return RangeAlloc::NONE;
         if (holder) S->waiting++;
         S->cv_mem.wait_for(lk, std::chrono::milliseconds(20));
         if (holder) S->waiting--;
@@ -133,9 +144,9 @@ void run_spasgn(hp_server_s *S, hp_handle_t h, hipStream_t st, Pending p) {
         Lock lk(S->mu);
         s = hp_spasgn_workspace(S->ctl, &r.A, &r.B, &wsb);
         if (s == HP_OK) {
-            ws_off = carve_locked(S, lk, wsb, false);
+            ws_off = carve_locked(S, lk, wsb, false, true);
             if (ws_off != RangeAlloc::NONE) {
-                out_off = carve_locked(S, lk, out_bytes, false);
+                out_off = carve_locked(S, lk, out_bytes, false, true);
                 if (out_off == RangeAlloc::NONE) {
                     S->alloc.release(ws_off);
                     ws_off = RangeAlloc::NONE;
@@ -161,7 +172,7 @@ void run_spasgn(hp_server_s *S, hp_handle_t h, hipStream_t st, Pending p) {
     size_t x_off = RangeAlloc::NONE;
     if (s == HP_OK && info.exec_ws_bytes) {
         Lock lk(S->mu);
-        x_off = carve_locked(S, lk, info.exec_ws_bytes, true);
+        x_off = carve_locked(S, lk, info.exec_ws_bytes, true, true);
         if (x_off == RangeAlloc::NONE) s = HP_ERR_REJECTED;
     }
     if (s == HP_OK) {
@@ -201,7 +212,7 @@ std::vector<Pending> run_batch(hp_server_s *S, hp_handle_t h, hipStream_t st,
     std::vector<Pending> back;
     if (s == HP_OK && info.arena_bytes) {
         Lock lk(S->mu);
-        a_off = carve_locked(S, lk, info.arena_bytes, true);
+        a_off = carve_locked(S, lk, info.arena_bytes, true, n == 1);
         if (a_off == RangeAlloc::NONE) {
             if (n > 1) {
                 // give the requests back to run one at a time
@@ -278,9 +289,9 @@ void run_solo(hp_server_s *S, hp_handle_t h, hipStream_t st, Pending &p, size_t 
     if (s == HP_OK) {
         const size_t col_bytes = RangeAlloc::round((size_t)C.nnz * 4);
         Lock lk(S->mu);
-        out_off = carve_locked(S, lk, rp_bytes + col_bytes + (size_t)C.nnz * vs, true);
+        out_off = carve_locked(S, lk, rp_bytes + col_bytes + (size_t)C.nnz * vs, true, true);
         if (out_off != RangeAlloc::NONE && info.exec_ws_bytes) {
-            x_off = carve_locked(S, lk, info.exec_ws_bytes, true);
+            x_off = carve_locked(S, lk, info.exec_ws_bytes, true, true);
             if (x_off == RangeAlloc::NONE) {
                 S->alloc.release(out_off);
                 out_off = RangeAlloc::NONE;
@@ -372,7 +383,7 @@ void worker_main(hp_server_s *S) {
                     for (size_t k = 0; k < B.size(); k++) tmp[k] = B[k].r;
                     if (hp_batch_workspace(S->ctl, tmp.data(), (int)tmp.size(), &wsb) != HP_OK) wsb = 0;
                 }
-                ws_off = carve_locked(S, lk, wsb, false);
+                ws_off = carve_locked(S, lk, wsb, false, B.size() == 1);
                 if (ws_off == RangeAlloc::NONE) {
                     if (B.size() > 1) {
                         for (auto it = B.rbegin(); it != B.rend(); ++it) {
@@ -422,6 +433,7 @@ extern "C" hp_status_t hp_server_create(hp_server_t *out, int device, void *pool
     if (S->cfg.max_inflight <= 0) S->cfg.max_inflight = 4;
     if (S->cfg.max_inflight > 16) S->cfg.max_inflight = 16;
     if (S->cfg.max_batch <= 0) S->cfg.max_batch = 256;
+    if (S->cfg.release_wait_ms == 0) S->cfg.release_wait_ms = 1000;
     if (hp_create(&S->ctl, device) != HP_OK) {
         delete S;
         return HP_ERR_HIP;
@@ -450,7 +462,10 @@ extern "C" hp_status_t hp_server_submit(hp_server_t S, const hp_request_t *req, 
         s = hp_batch_workspace(S->ctl, &r, 1, &bytes);   // validates the request
     }
     if (s != HP_OK) return s;
-    Pending p{S->next_id++, r, now_ns(), false};
+    // a request over a large matrix fills the GPU by itself and runs faster
+    // through the plain calls than through the batched stage launches
+    const bool big = r.kind != HP_REQ_SPASGN && r.A.nnz > BATCH_MAX_NNZ;
+    Pending p{S->next_id++, r, now_ns(), big};
     *id = p.id;
     S->pending.push_back(p);
     S->submitted++;

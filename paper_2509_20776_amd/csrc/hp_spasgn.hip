@@ -786,6 +786,8 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
     Carve c(ws);
     AsgLayout L = asg_layout(c, m, n, A->nnz, fused, sym);
     hipStream_t s = h->stream;
+    if (hp_status_t v = validate_input(h, A, L.hdr, "spasgn plan: A")) return v;
+    if (hp_status_t v = validate_input(h, B, L.hdr, "spasgn plan: B")) return v;
     stage_begin(h);
     hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, scan_tiles(m));
     if (e == hipSuccess) e = launch_fill_words(s, L.rowinv, (size_t)m, 0xFFFFFFFFu);

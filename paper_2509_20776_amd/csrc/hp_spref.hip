@@ -236,6 +236,8 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     SprefLayout L = spref_layout(c, n, nI, nJ, A->nnz);
     const size_t st = scan_tiles(nI);
     hipStream_t s = h->stream;
+    if (!dcsc)
+        if (hp_status_t v = validate_input(h, A, L.hdr, "spref plan: A")) return v;
     stage_begin(h);
     hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, 3 * st);
     if (e == hipSuccess) e = launch_clear_words(s, L.zero, L.nzero);

@@ -72,7 +72,8 @@ class hp_batch_info_t(ctypes.Structure):
 
 
 class hp_server_config_t(ctypes.Structure):
-    _fields_ = [("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+    _fields_ = [("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("release_wait_ms", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class hp_completion_t(ctypes.Structure):
@@ -121,6 +122,7 @@ hp_batch_plan = _sig("hp_batch_plan", [_P, _REQP, ctypes.c_int, _P, _SZ, _BINFOP
 hp_batch_exec = _sig("hp_batch_exec", [_P, _REQP, ctypes.c_int, _P, _SZ, _BINFOP, _P, _SZ])
 hp_validate_workspace = _sig("hp_validate_workspace", [_P, _CSRP, ctypes.POINTER(_SZ)])
 hp_validate_csr = _sig("hp_validate_csr", [_P, _CSRP, _P, _SZ])
+hp_set_validate = _sig("hp_set_validate", [_P, ctypes.c_int])
 hp_spasgn_workspace = _sig("hp_spasgn_workspace", [_P, _CSRP, _CSRP, ctypes.POINTER(_SZ)])
 hp_spasgn_plan = _sig("hp_spasgn_plan", [_P, _CSRP, _CSRP, _P, _P, ctypes.c_int, _CSRP, _P, _SZ, _INFOP])
 hp_spasgn_exec = _sig("hp_spasgn_exec", [_P, _CSRP, _CSRP, _P, _P, ctypes.c_int, _CSRP, _P, _SZ, _INFOP,
@@ -267,6 +269,10 @@ class Handle:
 
     def _alloc(self, nbytes):
         return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def set_validate(self, on: bool):
+        """Plans check their CSR inputs first (hp_set_validate)."""
+        self.check(hp_set_validate(self.h, 1 if on else 0))
 
     def validate(self, A):
         """Raise HPError unless A is canonical CSR (hp_validate_csr)."""
@@ -507,9 +513,9 @@ KINDS = {"spref": 0, "permute": 1, "spasgn": 2}
 
 
 class Batch:
-    """Many spref / permute requests planned and executed together
-    (hp_batch_plan / hp_batch_exec).  Each request is a dict with
-    kind="spref" (A, I, J) or kind="permute" (A, p, q=None)."""
+    """Many requests planned and executed together (hp_batch_plan /
+    hp_batch_exec).  Each request is a dict with kind="spref" (A, I, J),
+    kind="permute" (A, p, q=None) or kind="spasgn" (A, B, I, J, op)."""
 
     def __init__(self, handle: "Handle", requests):
         self.hd = handle
@@ -523,6 +529,11 @@ class Batch:
             if r["kind"] == "spref":
                 rq.I, rq.J = _idx(r["I"]), _idx(r["J"])
                 rq.nI, rq.nJ = int(r["I"].numel()), int(r["J"].numel())
+            elif r["kind"] == "spasgn":
+                rq.B = to_csr_t(r["B"])
+                rq.I, rq.J = _idx(r["I"]), _idx(r["J"])
+                rq.nI, rq.nJ = int(r["I"].numel()), int(r["J"].numel())
+                rq.op = Handle._op(r.get("op", "second"))
             else:
                 rq.p, rq.q = _idx(r["p"]), _idx(r.get("q"))
         self.ws = None
@@ -586,10 +597,11 @@ class Server:
     submit(kind, A, ...) -> id; poll() -> list of completion dicts with the
     result as CSR views into the pool (valid until release(id))."""
 
-    def __init__(self, pool_bytes: int, device: int = 0, max_inflight: int = 4, max_batch: int = 256):
+    def __init__(self, pool_bytes: int, device: int = 0, max_inflight: int = 4, max_batch: int = 256,
+                 release_wait_ms: int = 0):
         torch.cuda.set_device(device)
         self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=f"cuda:{device}")
-        cfg = hp_server_config_t(max_inflight, max_batch)
+        cfg = hp_server_config_t(max_inflight, max_batch, release_wait_ms, 0)
         h = _P()
         code = hp_server_create(ctypes.byref(h), device, _dptr(self.pool), pool_bytes, ctypes.byref(cfg))
         if code != 0:

@@ -162,3 +162,62 @@ def test_batched_long_rows_wide(hp):
     got = b.results()
     for k, r in enumerate(reqs):
         assert_same(np_csr(got[k]), np_csr(_plain(hp, r)), f"request {k} ({r['kind']})")
+
+
+def test_batched_with_assignment_requests(hp):
+    """Assignment requests (all three operators) batched with extractions and
+    permutations: every result equals its plain call and the oracle; a
+    failing assignment (repeated index) is isolated; the replayed exec graph
+    rewrites the same bytes."""
+    _say("batched: assignment requests among extractions and permutations")
+    pool = [synth.rmat(s, 8, 21, f"ba{s}", symmetric=True, ptr_dtype=torch.int64, val_dtype=torch.float64,
+                       device="cuda") for s in (9, 11)]
+    pool.append(mixed_csr(22, 700, 900, [0, 1, 4, 30, 300, 2500], torch.int64, torch.float64))
+    reqs = []
+    for t in range(12):
+        A = pool[t % len(pool)]
+        nI, nJ = max(1, A.nrows // (5 + t)), max(1, A.ncols // (4 + t))
+        I = synth.subset(synth.stream_key(23, "I", t), A.nrows, nI, device="cuda")
+        J = synth.subset(synth.stream_key(23, "J", t), A.ncols, nJ, device="cuda")
+        if t % 3 == 0:
+            B = synth.bernoulli_block(nI, nJ, 0.05, 24, f"bB{t}", ptr_dtype=torch.int64, val_dtype=torch.float64,
+                                      device="cuda")
+            reqs.append(dict(kind="spasgn", A=A, B=B, I=I, J=J, op=["second", "plus", "replace"][(t // 3) % 3]))
+        elif t % 3 == 1:
+            reqs.append(dict(kind="spref", A=A, I=I, J=J))
+        else:
+            reqs.append(dict(kind="permute", A=A, p=synth.randperm(synth.stream_key(23, "p", t), A.nrows, "cuda"),
+                             q=synth.randperm(synth.stream_key(23, "q", t), A.ncols, "cuda")))
+    A = pool[0]
+    bad_I = torch.tensor([1, 1], dtype=torch.int32, device="cuda")
+    Bb = synth.bernoulli_block(2, 3, 0.5, 25, "bBad", ptr_dtype=torch.int64, val_dtype=torch.float64, device="cuda")
+    reqs.append(dict(kind="spasgn", A=A, B=Bb, I=bad_I, J=torch.arange(3, dtype=torch.int32, device="cuda"),
+                     op="second"))
+    b = hp.Batch(hp.handle(0), reqs)
+    st = b.plan()
+    assert st[:-1] == [0] * (len(reqs) - 1) and st[-1] == 4, st          # HP_ERR_DUPLICATE_INDEX
+    b.exec()
+    got = b.results()
+    torch.cuda.synchronize()
+    assert got[-1] is None
+    for k, r in enumerate(reqs[:-1]):
+        if r["kind"] == "spasgn":
+            plain = hp.spasgn(r["A"], r["B"], r["I"], r["J"], r["op"])
+            exp = oracle.spasgn(r["A"], r["B"], r["I"], r["J"], r["op"])
+        elif r["kind"] == "spref":
+            plain = hp.spref(r["A"], r["I"], r["J"])
+            exp = oracle.spref_map(r["A"], r["I"], r["J"])
+        else:
+            plain = hp.permute(r["A"], r["p"], r["q"])
+            exp = oracle.permute_map(r["A"], r["p"], r["q"])
+        assert_same(np_csr(got[k]), np_csr(plain), f"request {k} ({r['kind']}) vs plain")
+        assert_same(np_csr(got[k]), exp, f"request {k} ({r['kind']}) vs oracle")
+    first = [np_csr(c) if c is not None else None for c in got]
+    for c in got:
+        if c is not None:
+            c.col.fill_(-7)
+            c.val.fill_(-1.0)
+    b.exec()
+    again = b.results()
+    for k in range(len(reqs) - 1):
+        assert_same(np_csr(again[k]), first[k], f"replay {k}")

@@ -164,3 +164,41 @@ def test_served_rejects_invalid_at_submit(hp):
     (c,) = srv.poll()
     assert c["id"] == rid and c["status"] == 3
     srv.close()
+
+
+def test_served_inputs_written_asynchronously(hp):
+    """Inputs still being written on the caller's stream when they are
+    submitted: each request carries an event of that stream and the worker
+    waits for it, so the results equal the same requests run alone.  No
+    global synchronisation between writing the inputs and submitting."""
+    _say("served: inputs written by queued work, submitted at once")
+    A = synth.rmat(12, 16, 11, "srv-async", symmetric=True, device="cuda")
+    busy = torch.randn(4096, 4096, device="cuda")
+    srv = hp.Server(256 << 20, max_inflight=4, max_batch=8)
+    subs = {}
+    torch.cuda.synchronize()
+    for t in range(16):
+        busy = busy @ busy * 1e-3          # keeps the stream busy before the copies below
+        B = synth.CSR(A.nrows, A.ncols, torch.empty_like(A.rowptr).fill_(-1), torch.empty_like(A.col).fill_(-1),
+                      torch.empty_like(A.val).fill_(float("nan")))
+        B.rowptr.copy_(A.rowptr)
+        B.col.copy_(A.col)
+        B.val.copy_(A.val)
+        perm = torch.randperm(A.nrows, device="cuda").to(torch.int32)
+        if t % 2:
+            I = perm[: A.nrows // 3]
+            subs[srv.submit("spref", B, I=I, J=I)] = ("spref", I)
+        else:
+            subs[srv.submit("permute", B, p=perm, q=None)] = ("permute", perm)
+    srv.drain()
+    got = {}
+    while len(got) < len(subs):
+        for c in srv.poll():
+            got[c["id"]] = c
+    for rid, c in got.items():
+        assert c["status"] == 0, c["status"]
+        kind, x = subs[rid]
+        alone = hp.spref(A, x, x) if kind == "spref" else hp.permute(A, x)
+        assert_same(np_csr(c["C"]), np_csr(alone), f"request {rid} ({kind})")
+        srv.release(rid)
+    srv.close()

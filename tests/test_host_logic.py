@@ -168,3 +168,53 @@ def test_bounded_wait(tmp_path, flags):
     """)
     out = _run_c(tmp_path, src, lang="c++", flags=flags)
     assert out.startswith("OK"), out
+
+
+@pytest.mark.parametrize("flags", [(), tuple(SANITIZE)], ids=["plain", "asan-ubsan"])
+def test_tuner_cache_file(tmp_path, flags):
+    """hp_tunecache.hpp: the batched form's tuner choices round-trip through
+    the cache file; later lines override earlier ones, malformed lines are
+    skipped, keys with blanks are refused, the path follows HP_TUNE_CACHE and
+    then XDG_CACHE_HOME, and a missing file reads as empty."""
+    cache = tmp_path / "sub" / "tune.txt"
+    src = textwrap.dedent(r"""
+        #include <cstdio>
+        #include <cstdlib>
+        #include <string>
+        #include "hp_tunecache.hpp"
+        using namespace hp;
+        #define CHECK(c) do { if (!(c)) { printf("FAIL line %d: %s\n", __LINE__, #c); return 1; } } while (0)
+        int main(int argc, char **argv) {
+            const std::string path = argv[1];
+            CHECK(tune_cache_load(path).empty());
+            CHECK(tune_cache_store(path, "batch/cu256/plan/p0/v0/t2^10", 512));
+            CHECK(tune_cache_store(path, "batch/cu256/exec/p0/v0/t2^12", 1024));
+            CHECK(tune_cache_store(path, "batch/cu256/plan/p0/v0/t2^10", 256));
+            CHECK(!tune_cache_store(path, "bad key", 3));
+            CHECK(!tune_cache_store(path, "k", 0));
+            FILE *f = fopen(path.c_str(), "a");
+            fputs("garbage\n\n   \nnot_a_number x\n", f);
+            fclose(f);
+            auto m = tune_cache_load(path);
+            CHECK(m.size() == 2);
+            CHECK(m["batch/cu256/plan/p0/v0/t2^10"] == 256);
+            CHECK(m["batch/cu256/exec/p0/v0/t2^12"] == 1024);
+            setenv("HP_TUNE_CACHE", "/x/y.txt", 1);
+            CHECK(tune_cache_path() == "/x/y.txt");
+            setenv("HP_TUNE_CACHE", "", 1);
+            CHECK(tune_cache_path().empty());
+            CHECK(tune_cache_load(tune_cache_path()).empty() && !tune_cache_store(tune_cache_path(), "k", 1));
+            unsetenv("HP_TUNE_CACHE");
+            setenv("XDG_CACHE_HOME", "/c", 1);
+            CHECK(tune_cache_path() == "/c/hipperm/batch_tune.txt");
+            puts("OK");
+            return 0;
+        }
+    """)
+    f = tmp_path / "t.cpp"
+    f.write_text(src)
+    exe = tmp_path / "t"
+    subprocess.run(["g++", "-std=c++17", "-O1", *flags, "-I", CSRC, str(f), "-o", str(exe)], check=True,
+                   capture_output=True, text=True)
+    r = subprocess.run([str(exe), str(cache)], capture_output=True, text=True)
+    assert r.returncode == 0 and r.stdout.startswith("OK"), r.stdout + r.stderr
