@@ -239,7 +239,7 @@ __device__ __forceinline__ void step_mult(const int32_t (&c)[SR_U], const bool (
 // Gather side of the hit masks: the slots' hit bits come from the count
 // pass's words w[0..SR_U), so only the hits look anything up (their J
 // position; a negative one heads the chain of a repeated column).
-__device__ __forceinline__ void hits_from_mask(const uint64_t (&w)[SR_U], const int32_t (&raw)[SR_U],
+__device__ __forceinline__ void hits_from_mask(const uint64_t *__restrict__ w, const int32_t (&raw)[SR_U],
                                                int64_t n, const int32_t *__restrict__ jpos,
                                                const int32_t *__restrict__ Dn, int32_t (&c)[SR_U],
                                                int32_t (&jv)[SR_U], int (&mm)[SR_U]) {
@@ -556,12 +556,6 @@ __device__ inline void spref_gather_tile(
         // a slice boundary needs its hit count carried: `cur` is the row of
         // the previous slice's last lane and `carry` its hits so far.
         int carry = 0, cur = INT32_MIN;
-        uint64_t hwn[SR_U];
-        if (E > 0) {
-            const uint64_t *h0 = hmS + gw * SR_STEPS * SR_U;
-#pragma unroll
-            for (int u = 0; u < SR_U; u++) hwn[u] = h0[u];
-        }
         for (int e0 = 0; e0 < E; e0 += SR_BW) {
             int64_t k[SR_U];
             int32_t c[SR_U];
@@ -576,24 +570,13 @@ __device__ inline void spref_gather_tile(
                 rr[u] = ok[u] ? r : -1 - l;   // distinct per idle lane: never joins a segment
                 k[u] = g.rs[r] + (ec - g.start[r]);
             }
-            // this step's hit words (loaded one step ahead), then the next
-            // step's; only the hits load their column and value
-            uint64_t hw[SR_U];
-#pragma unroll
-            for (int u = 0; u < SR_U; u++) hw[u] = hwn[u];
-            if (e0 + SR_BW < E) {
-                const uint64_t *nx = hmS + (gw * SR_STEPS + e0 / SR_BW + 1) * SR_U;
-#pragma unroll
-                for (int u = 0; u < SR_U; u++) hwn[u] = nx[u];
-            }
             int32_t raw[SR_U];
             VT v[SR_U];
+            const uint64_t *hw = hmS + (gw * SR_STEPS + e0 / SR_BW) * SR_U;
 #pragma unroll
-            for (int u = 0; u < SR_U; u++) {
-                const bool hit = (hw[u] >> l) & 1ull;
-                raw[u] = hit ? __builtin_nontemporal_load(&acol[k[u]]) : 0;
-                v[u] = hit ? __builtin_nontemporal_load(&aval[k[u]]) : VT(0);
-            }
+            for (int u = 0; u < SR_U; u++) raw[u] = __builtin_nontemporal_load(&acol[k[u]]);
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) v[u] = __builtin_nontemporal_load(&aval[k[u]]);
             int32_t jv[SR_U];
             hits_from_mask(hw, raw, n, jpos, Dn, c, jv, mm);
 #pragma unroll
@@ -664,21 +647,17 @@ __device__ inline void spref_gather_tile(
         bool ok[SR_U];
         int32_t raw[SR_U];
         VT v[SR_U];
-        uint64_t hw[SR_U];
-#pragma unroll
-        for (int u = 0; u < SR_U; u++) hw[u] = use_mask ? hmB[q * SR_U + u] : ~0ull;
 #pragma unroll
         for (int u = 0; u < SR_U; u++) {
             const int64_t kk = b + u * WAVE + l;
             ok[u] = kk < e;
             const int64_t kc = base + (ok[u] ? kk : e - 1);
-            const bool load = (hw[u] >> l) & 1ull;   // with masks, only the hits
-            raw[u] = load ? __builtin_nontemporal_load(&acol[kc]) : 0;
-            v[u] = load ? __builtin_nontemporal_load(&aval[kc]) : VT(0);
+            raw[u] = __builtin_nontemporal_load(&acol[kc]);
+            v[u] = __builtin_nontemporal_load(&aval[kc]);
         }
         int32_t jv[SR_U];
         if (use_mask) {
-            hits_from_mask(hw, raw, n, jpos, Dn, c, jv, mm);
+            hits_from_mask(hmB + q * SR_U, raw, n, jpos, Dn, c, jv, mm);
         } else {
 #pragma unroll
             for (int u = 0; u < SR_U; u++) c[u] = (int32_t)clampc(raw[u], n);
