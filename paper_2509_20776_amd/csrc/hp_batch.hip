@@ -9,7 +9,9 @@
 //                3-7 class sorts (thread, wave, block, bucket split, bucket)
 //   permute plan 0 clear, fill -1  1 scatter inverses + counts  2 check
 //                3 rowptr scan (+ classes)
-//          exec  0 copy rowptr  1 short rows  3-7 class sorts (pull from A)
+//          exec  0 copy rowptr  1 short rows (pull)
+//                3-7 class sorts (pull from A)
+//                (columns looked up in qinv as rows are read)
 // Phases are grouped into stages (stage_of): a stage only holds phases
 // whose inputs were written by earlier stages, so one launch per stage runs
 // the tiles of every request of the batch, and stream order between the
@@ -18,7 +20,8 @@
 // persistent and take tiles from an atomic ticket in queue order, so the
 // tiles of one scan start in order and its look-back only waits on tiles
 // that are already running (the same argument as the plain scan kernel).
-// The exec half is captured once as a hipGraph and replayed.
+// The exec half is captured once as a hipGraph and replayed.  Each stage
+// runs a kernel compiled for that stage's phases alone (in_stage).
 #include "hp_internal.hpp"
 #include "hp_scan.hpp"
 #include "hp_segsort.hpp"
@@ -48,12 +51,12 @@ constexpr int CLEAR_PER_TILE = 4096;   // words cleared / copied per tile
 
 // Stage of each phase, per half and request kind (-1: phase not used).
 //   spref plan: {0} {1,2} {3,5} {4} {6} {7}; exec: {0} {1} {2..6} {7}
-//   permute plan: {0} {1} {2} {3};  exec: {0,1} {3..6} {7}
+//   permute plan: {0} {1} {2} {3};  exec: {0} {1,3..6} {7}
 // Phase 7 of exec (ranking long rows through a 128 KB LDS bitmap) is the
 // only content of exec stage RANK_STAGE, which runs its own kernel.
 constexpr int8_t STAGE_OF[2][2][NPH] = {
     {{0, 1, 1, 2, 3, 2, 4, 5}, {0, 1, 2, 3, -1, -1, -1, -1}},
-    {{0, 1, 2, 2, 2, 2, 2, 3}, {0, 0, -1, 1, 1, 1, 1, 3}},
+    {{0, 1, 2, 2, 2, 2, 2, 3}, {0, 1, -1, 1, 1, 1, 1, 3}},
 };
 constexpr int RANK_STAGE = 3;
 
@@ -125,40 +128,59 @@ __device__ inline void copy_rowptr_tile(int64_t tile, const PT *src, PT *dst, in
 }
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-template <typename PT, typename VT>
-__device__ void run_tile(int half, int phase, int64_t tile, const ReqDev &r, BatchSmem &sm) {
+// Whether phase ph of a request of kind k (0 extraction, 1 permutation) runs
+// in stage st of half h: each stage kernel is compiled with only its own
+// phases, so its register use (and hence occupancy) is that of its own
+// tiles, not of the heaviest tile of the whole batch.
+constexpr bool in_stage(int h, int st, int k, int ph) { return STAGE_OF[h][k][ph] == st; }
+#define HP_PHASE(k, ph) case ph: if constexpr (in_stage(HALF, STAGE, k, ph))
+
+template <typename PT, typename VT, int HALF, int STAGE>
+__device__ void perm_exec_phase(int phase, int64_t tile, const ReqDev &r, BatchSmem &sm, const PT *crow, int64_t cap,
+                                const uint64_t *goff, int32_t *tk, VT *tv, uint32_t *bst);
+
+template <typename PT, typename VT, int HALF, int STAGE>
+__device__ void run_tile(int phase, int64_t tile, const ReqDev &r, BatchSmem &sm) {
     uint64_t *goff = reinterpret_cast<uint64_t *>(r.lists + NBINS * (r.kind == HP_REQ_SPREF ? r.nI : r.m));
     const int64_t cap = r.kind == HP_REQ_SPREF ? r.nI : r.m;
-    if (half == 0) {
+    if constexpr (HALF == 0) {
         if (r.kind == HP_REQ_SPREF) {
             switch (phase) {
-                case 0:
+                HP_PHASE(0, 0) {
                     clear_tile(tile, r.zero, r.nzero);
                     if (tile == 0 && threadIdx.x == 0 && r.nrows_out == 0) ((PT *)r.crow_tmp)[0] = 0;
-                    break;
-                case 1: spref::spref_jscatter_tile(tile, r.J, r.nJ, r.n, r.mark, r.jpos, r.nm, r.hdr); break;
-                case 2:
+                }
+                break;
+                HP_PHASE(0, 1) { spref::spref_jscatter_tile(tile, r.J, r.nJ, r.n, r.mark, r.jpos, r.nm, r.hdr); }
+                break;
+                HP_PHASE(0, 2) {
                     spref::spref_rows_tile<PT>(tile, (const PT *)r.arow, r.I, r.nI, r.m, r.rs, r.rl, r.ch, r.big,
                                                r.hdr);
-                    break;
-                case 3: spref::spref_jpack_tile(tile, r.J, r.nJ, r.n, r.mark, r.bm, r.nw, r.jpos, r.Dn, r.dm); break;
-                case 4: spref::spref_jlink_tile(tile, r.J, r.nJ, r.jpos, r.Dn, r.bm, r.dm, r.b2, r.nw); break;
-                case 5:
+                }
+                break;
+                HP_PHASE(0, 3) { spref::spref_jpack_tile(tile, r.J, r.nJ, r.n, r.mark, r.bm, r.nw, r.jpos, r.Dn, r.dm); }
+                break;
+                HP_PHASE(0, 4) { spref::spref_jlink_tile(tile, r.J, r.nJ, r.jpos, r.Dn, r.bm, r.dm, r.b2, r.nw); }
+                break;
+                HP_PHASE(0, 5) {
                     scan_counts_tile<int64_t>(tile, sm.scan, r.ch, r.cp, r.nI, r.hdr, 0, r.tiles0, 0, nullptr, 0,
                                               nullptr, nullptr, nullptr);
-                    break;
-                case 6:
+                }
+                break;
+                HP_PHASE(0, 6) {
                     spref::spref_count_tile(tile, r.nbw, sm.gc, r.acol, r.n, r.rs, r.rl, r.cp, r.nI, r.b2, r.jpos,
                                             r.Dn, r.cnt, r.hmS, r.hmB, r.capb, r.hdr);
-                    break;
-                case 7:
+                }
+                break;
+                HP_PHASE(0, 7) {
                     scan_counts_tile<PT>(tile, sm.scan, r.cnt, (PT *)r.crow_tmp, r.nI, r.hdr, 1, r.tiles1, 3,
                                          r.lists, cap, goff, r.big, r.nm);
-                    break;
+                }
+                break;
             }
         } else {
             switch (phase) {
-                case 0: {
+                HP_PHASE(1, 0) {
                     const int64_t nct = cdiv(r.nzero, CLEAR_PER_TILE);
                     if (tile < nct) {
                         clear_tile(tile, r.zero, r.nzero);
@@ -166,90 +188,119 @@ __device__ void run_tile(int half, int phase, int64_t tile, const ReqDev &r, Bat
                     } else {
                         fill_tile(tile - nct, r.fill, r.nfill);
                     }
-                    break;
                 }
-                case 1:
+                break;
+                HP_PHASE(1, 1) {
                     perm::perm_prepare_tile<PT>(tile, (const PT *)r.arow, r.p, r.sym ? nullptr : r.q, r.m, r.n,
                                                 r.pinv, r.qinv, r.cnt, r.hdr);
-                    break;
-                case 2: perm::perm_check_tile(tile, r.m, r.n, r.pinv, r.qinv, !r.sym, r.hdr); break;
-                case 3:
+                }
+                break;
+                HP_PHASE(1, 2) { perm::perm_check_tile(tile, r.m, r.n, r.pinv, r.qinv, !r.sym, r.hdr); }
+                break;
+                HP_PHASE(1, 3) {
                     scan_counts_tile<PT>(tile, sm.scan, r.cnt, (PT *)r.crow_tmp, r.m, r.hdr, 0, r.tiles0, 1, r.lists,
                                          cap, goff, nullptr, nullptr);
-                    break;
+                }
+                break;
             }
         }
         return;
-    }
-    // exec half
-    const PT *crow = (const PT *)r.crow_tmp;
-    int32_t *tk = (int32_t *)r.tmp;
-    char *tp = (char *)r.tmp + ((r.glob_elems * sizeof(int32_t) + 255) & ~uint64_t(255));
-    VT *tv = (VT *)tp;
-    uint32_t *bst = (uint32_t *)(tp + ((r.glob_elems * sizeof(VT) + 255) & ~uint64_t(255)));
-    if (r.kind == HP_REQ_SPREF) {
-        LoadInPlace<PT, VT> ld{crow, r.ccol, (const VT *)r.cval};
-        switch (phase) {
-            case 0: {
-                const int64_t nct = cdiv(r.nI, CLEAR_PER_TILE);
-                if (tile < nct) clear_tile(tile, (uint32_t *)r.cursor, r.nI);
-                else copy_rowptr_tile<PT>(tile - nct, crow, (PT *)r.crow, r.nrows_out + 1);
+    } else {
+        // exec half
+        const PT *crow = (const PT *)r.crow_tmp;
+        int32_t *tk = (int32_t *)r.tmp;
+        char *tp = (char *)r.tmp + ((r.glob_elems * sizeof(int32_t) + 255) & ~uint64_t(255));
+        VT *tv = (VT *)tp;
+        uint32_t *bst = (uint32_t *)(tp + ((r.glob_elems * sizeof(VT) + 255) & ~uint64_t(255)));
+        if (r.kind == HP_REQ_SPREF) {
+            LoadInPlace<PT, VT> ld{crow, r.ccol, (const VT *)r.cval};
+            switch (phase) {
+                HP_PHASE(0, 0) {
+                    const int64_t nct = cdiv(r.nI, CLEAR_PER_TILE);
+                    if (tile < nct) clear_tile(tile, (uint32_t *)r.cursor, r.nI);
+                    else copy_rowptr_tile<PT>(tile - nct, crow, (PT *)r.crow, r.nrows_out + 1);
+                }
+                break;
+                HP_PHASE(0, 1) {
+                    spref::spref_gather_tile<PT, VT>(tile, r.nbw, sm.gs, r.acol, (const VT *)r.aval, r.n, r.rs, r.rl,
+                                                     r.cp, r.nI, r.b2, r.jpos, r.Dn, crow, r.ccol, (VT *)r.cval,
+                                                     r.cursor, r.hmS, r.hmB, r.capb, !r.monotone, r.gflag, r.hdr);
+                }
+                break;
+                HP_PHASE(0, 2) {
+                    sort_small_tile<PT, VT>(tile, sm.wave, crow, r.ccol, (VT *)r.cval, r.nI, ld, r.hdr, r.gflag,
+                                            r.big);
+                }
+                break;
+                HP_PHASE(0, 3) {
+                    seg_thread_tile<PT, VT>(tile, crow, r.ccol, (VT *)r.cval, r.lists + BIN_THREAD * cap,
+                                            r.cls[BIN_THREAD], ld, 0, r.hdr);
+                }
+                break;
+                HP_PHASE(0, 4) {
+                    seg_wave_tile<PT, VT>(tile, sm.wave, crow, r.ccol, (VT *)r.cval, r.lists + BIN_WAVE * cap,
+                                          r.cls[BIN_WAVE], ld, 0, r.hdr);
+                }
+                break;
+                HP_PHASE(0, 5) {
+                    seg_bitonic_tile<PT, VT, decltype(ld), 256, BITONIC_EMAX>(
+                        tile, sm.block, crow, r.ccol, (VT *)r.cval, r.lists + BIN_BLOCK * cap, r.cls[BIN_BLOCK], ld,
+                        bitonic_narrow(r.ncols_out), r.hdr);
+                }
+                break;
+                HP_PHASE(0, 6) {
+                    seg_bucket_tile<PT, VT>(tile, sm.bucket, crow, r.lists + BIN_GLOBAL * cap, goff,
+                                            r.cls[BIN_GLOBAL], ld, r.nb, tk, tv, bst, r.hdr);
+                }
                 break;
             }
-            case 1:
-                spref::spref_gather_tile<PT, VT>(tile, r.nbw, sm.gs, r.acol, (const VT *)r.aval, r.n, r.rs, r.rl, r.cp,
-                                                 r.nI, r.b2, r.jpos, r.Dn, crow, r.ccol, (VT *)r.cval, r.cursor,
-                                                 r.hmS, r.hmB, r.capb, !r.monotone, r.gflag, r.hdr);
-                break;
-            case 2:
-                sort_small_tile<PT, VT>(tile, sm.wave, crow, r.ccol, (VT *)r.cval, r.nI, ld, r.hdr, r.gflag, r.big);
-                break;
-            case 3:
-                seg_thread_tile<PT, VT>(tile, crow, r.ccol, (VT *)r.cval, r.lists + BIN_THREAD * cap, r.cls[BIN_THREAD],
-                                        ld, 0, r.hdr);
-                break;
-            case 4:
-                seg_wave_tile<PT, VT>(tile, sm.wave, crow, r.ccol, (VT *)r.cval, r.lists + BIN_WAVE * cap,
-                                      r.cls[BIN_WAVE], ld, 0, r.hdr);
-                break;
-            case 5:
-                seg_bitonic_tile<PT, VT, decltype(ld), 256, BITONIC_EMAX>(
-                    tile, sm.block, crow, r.ccol, (VT *)r.cval, r.lists + BIN_BLOCK * cap, r.cls[BIN_BLOCK], ld,
-                    bitonic_narrow(r.ncols_out), r.hdr);
-                break;
-            case 6:
-                seg_bucket_tile<PT, VT>(tile, sm.bucket, crow, r.lists + BIN_GLOBAL * cap, goff, r.cls[BIN_GLOBAL], ld,
-                                        r.nb, tk, tv, bst, r.hdr);
-                break;
-        }
-    } else {
-        perm::LoadPerm<PT, VT> ld{(const PT *)r.arow, r.acol, (const VT *)r.aval, r.p, r.qinv, r.n};
-        switch (phase) {
-            case 0: copy_rowptr_tile<PT>(tile, crow, (PT *)r.crow, r.nrows_out + 1); break;
-            case 1:
-                perm::perm_fill_short_tile<PT, VT>(tile, (const PT *)r.arow, r.acol, (const VT *)r.aval, r.pinv, r.qinv,
-                                                   crow, r.ccol, (VT *)r.cval, r.m, r.n, r.hdr);
-                break;
-            case 3:
-                seg_thread_tile<PT, VT>(tile, crow, r.ccol, (VT *)r.cval, r.lists + BIN_THREAD * cap, r.cls[BIN_THREAD],
-                                        ld, 0, r.hdr);
-                break;
-            case 4:
-                seg_wave_tile<PT, VT>(tile, sm.wave, crow, r.ccol, (VT *)r.cval, r.lists + BIN_WAVE * cap,
-                                      r.cls[BIN_WAVE], ld, 0, r.hdr);
-                break;
-            case 5:
-                seg_bitonic_tile<PT, VT, decltype(ld), 256, BITONIC_EMAX>(
-                    tile, sm.block, crow, r.ccol, (VT *)r.cval, r.lists + BIN_BLOCK * cap, r.cls[BIN_BLOCK], ld,
-                    bitonic_narrow(r.ncols_out), r.hdr);
-                break;
-            case 6:
-                seg_bucket_tile<PT, VT>(tile, sm.bucket, crow, r.lists + BIN_GLOBAL * cap, goff, r.cls[BIN_GLOBAL], ld,
-                                        r.nb, tk, tv, bst, r.hdr);
-                break;
+        } else {
+            perm_exec_phase<PT, VT, HALF, STAGE>(phase, tile, r, sm, crow, cap, goff, tk, tv, bst);
         }
     }
 }
+
+// Exec phases 0-6 of a permutation request: output row i is row p[i] of A
+// with its columns looked up in qinv on the way (a pass that renames all
+// columns first, as the plain call may do, measured slower here: its tiles
+// add to every batch's queue, while most batched matrices keep the bulk of
+// their entries in the long rows that the class sorts pull).
+template <typename PT, typename VT, int HALF, int STAGE>
+__device__ void perm_exec_phase(int phase, int64_t tile, const ReqDev &r, BatchSmem &sm, const PT *crow, int64_t cap,
+                                const uint64_t *goff, int32_t *tk, VT *tv, uint32_t *bst) {
+    perm::LoadPerm<PT, VT> ld{(const PT *)r.arow, r.acol, (const VT *)r.aval, r.p, r.qinv, r.n};
+    switch (phase) {
+        HP_PHASE(1, 0) { copy_rowptr_tile<PT>(tile, crow, (PT *)r.crow, r.nrows_out + 1); }
+        break;
+        HP_PHASE(1, 1) {
+            perm::perm_pull_short_tile<PT, VT>(tile, (const PT *)r.arow, nullptr, (const VT *)r.aval, r.p, crow,
+                                               r.ccol, (VT *)r.cval, r.m, r.hdr, r.acol, r.qinv, r.n);
+        }
+        break;
+        HP_PHASE(1, 3) {
+            seg_thread_tile<PT, VT>(tile, crow, r.ccol, (VT *)r.cval, r.lists + BIN_THREAD * cap, r.cls[BIN_THREAD],
+                                    ld, 0, r.hdr);
+        }
+        break;
+        HP_PHASE(1, 4) {
+            seg_wave_tile<PT, VT>(tile, sm.wave, crow, r.ccol, (VT *)r.cval, r.lists + BIN_WAVE * cap,
+                                  r.cls[BIN_WAVE], ld, 0, r.hdr);
+        }
+        break;
+        HP_PHASE(1, 5) {
+            seg_bitonic_tile<PT, VT, decltype(ld), 256, BITONIC_EMAX>(
+                tile, sm.block, crow, r.ccol, (VT *)r.cval, r.lists + BIN_BLOCK * cap, r.cls[BIN_BLOCK], ld,
+                bitonic_narrow(r.ncols_out), r.hdr);
+        }
+        break;
+        HP_PHASE(1, 6) {
+            seg_bucket_tile<PT, VT>(tile, sm.bucket, crow, r.lists + BIN_GLOBAL * cap, goff, r.cls[BIN_GLOBAL], ld,
+                                    r.nb, tk, tv, bst, r.hdr);
+        }
+        break;
+    }
+}
+#undef HP_PHASE
 
 // Exec phase 7: rank one bucket of a long row (RANK_THREADS threads).
 template <typename PT, typename VT>
@@ -281,8 +332,8 @@ __global__ void k_batch_reset(uint32_t *ticket, int nticket, DevHdr *hdrs, int64
 
 // One stage: persistent workgroups take tickets until the stage's tiles run
 // out.  q holds the stage's (request, phase) entries in queue order.
-template <typename PT, typename VT>
-__global__ __launch_bounds__(256) void k_batch_stage(int half, const QEntry *__restrict__ q, int nq, int64_t total,
+template <typename PT, typename VT, int HALF, int STAGE>
+__global__ __launch_bounds__(256) void k_batch_stage(const QEntry *__restrict__ q, int nq, int64_t total,
                                                     const ReqDev *__restrict__ reqs, uint32_t *ticket) {
     __shared__ __align__(16) BatchSmem sm;
     __shared__ int64_t s_t;
@@ -306,7 +357,7 @@ __global__ __launch_bounds__(256) void k_batch_stage(int half, const QEntry *__r
         const int64_t t = s_t;
         if (t >= total) break;
         const QEntry e = q[s_e];
-        run_tile<PT, VT>(half, e.phase, t - e.first, reqs[e.req], sm);
+        run_tile<PT, VT, HALF, STAGE>(e.phase, t - e.first, reqs[e.req], sm);
         __syncthreads();   // LDS and s_t are reused by the next tile
     }
 }
@@ -566,6 +617,37 @@ void build_stages(int half, const hp_request_t *reqs, const std::vector<std::arr
     S.off[NST] = (int)S.q.size();
 }
 
+// Stages that have a compiled stage kernel (launch_stage below): plan
+// stages 0-5, exec stages 0-2 (exec stage RANK_STAGE has its own kernel).
+constexpr bool stage_compiled(int h, int st) { return h == 0 ? st < NST : st < RANK_STAGE; }
+constexpr bool stages_covered() {
+    for (int h = 0; h < 2; h++)
+        for (int k = 0; k < 2; k++)
+            for (int ph = 0; ph < NPH; ph++) {
+                const int st = STAGE_OF[h][k][ph];
+                if (st >= 0 && !stage_compiled(h, st) && !(h == 1 && st == RANK_STAGE)) return false;
+            }
+    return true;
+}
+static_assert(stages_covered(), "every stage of the table needs a stage kernel");
+
+// The stage kernel compiled for (half, stage); false if there is none.
+template <typename PT, typename VT>
+bool launch_stage(hipStream_t s, int half, int st, int grid, const QEntry *q, int nq, int64_t tot, const ReqDev *reqs,
+                  uint32_t *tk) {
+#define HP_STAGE(H, ST)                                                                                      \
+    case H * NST + ST:                                                                                       \
+        static_assert(stage_compiled(H, ST), "stage list");                                                  \
+        hipLaunchKernelGGL((k_batch_stage<PT, VT, H, ST>), dim3(grid), dim3(256), 0, s, q, nq, tot, reqs, tk); \
+        return true;
+    switch (half * NST + st) {
+        HP_STAGE(0, 0) HP_STAGE(0, 1) HP_STAGE(0, 2) HP_STAGE(0, 3) HP_STAGE(0, 4) HP_STAGE(0, 5)
+        HP_STAGE(1, 0) HP_STAGE(1, 1) HP_STAGE(1, 2)
+        default: return false;
+    }
+#undef HP_STAGE
+}
+
 template <typename PT, typename VT>
 hipError_t launch_half(hp_handle_t h, int half, const Global &g, int n, const Stages &S, int grid) {
     hipStream_t s = h->stream;
@@ -580,9 +662,9 @@ hipError_t launch_half(hp_handle_t h, int half, const Global &g, int n, const St
             hipLaunchKernelGGL((k_batch_rank_stage<PT, VT>), dim3((int)std::min<int64_t>(tot, num_cus(h))),
                                dim3(RANK_THREADS), 0, s, g.queue + S.off[st], S.off[st + 1] - S.off[st], tot,
                                g.reqs, tk + st);
-        else
-            hipLaunchKernelGGL((k_batch_stage<PT, VT>), dim3(gr), dim3(256), 0, s, half, g.queue + S.off[st],
-                               S.off[st + 1] - S.off[st], tot, g.reqs, tk + st);
+        else if (!launch_stage<PT, VT>(s, half, st, gr, g.queue + S.off[st], S.off[st + 1] - S.off[st], tot, g.reqs,
+                                       tk + st))
+            return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -115,11 +115,15 @@ __device__ inline void perm_colmap_tile(int64_t bid, const int32_t *__restrict__
 }
 
 // Output rows of at most 4 entries, one lane per output row i (in order).
+// colq == nullptr: the columns are renamed here, cmap[col[k]] (used when
+// short rows hold few of the entries, so the renaming pass is not run).
 template <typename PT, typename VT>
 __device__ inline void perm_pull_short_tile(int64_t bid, const PT *__restrict__ arow, const int32_t *__restrict__ colq,
                                             const VT *__restrict__ aval, const int32_t *__restrict__ p,
                                             const PT *__restrict__ crow, int32_t *__restrict__ ccol,
-                                            VT *__restrict__ cval, int64_t m, const DevHdr *hdr) {
+                                            VT *__restrict__ cval, int64_t m, const DevHdr *hdr,
+                                            const int32_t *__restrict__ acol = nullptr,
+                                            const int32_t *__restrict__ cmap = nullptr, int64_t n = 0) {
     if (hdr->err) return;
     const int64_t i = bid * 256 + threadIdx.x;
     if (i >= m) return;
@@ -136,11 +140,20 @@ __device__ inline void perm_pull_short_tile(int64_t bid, const PT *__restrict__ 
         k[u] = INT32_MAX;
         v[u] = VT(0);
         if (u < len) {
-            k[u] = colq[s + u];
+            k[u] = colq ? colq[s + u] : cmap[clampc(acol[s + u], n)];
             v[u] = aval[s + u];
         }
     }
     sort_store_regs<4, VT>(k, v, len, false, ccol + d, cval + d);
+}
+
+// Rename the columns in a pass of their own when output rows of at most 4
+// entries hold at least half of them (the pull fill of those rows then
+// reads each row's renamed columns in one place); otherwise the fill and
+// the class sorts look each column up in qinv as they go (LoadPerm), and
+// the pass would only add its traffic.
+__host__ __device__ inline bool perm_use_colq(int64_t nnz, int64_t long_entries) {
+    return nnz > 0 && 2 * (nnz - long_entries) >= nnz;
 }
 
 // Longer output rows: the class sorts pull row p[i] with its columns

@@ -57,13 +57,23 @@ template <typename PT, typename VT>
 __global__ __launch_bounds__(256) void k_perm_pull_short(const PT *__restrict__ arow, const int32_t *__restrict__ colq,
                                                         const VT *__restrict__ aval, const int32_t *__restrict__ p,
                                                         const PT *__restrict__ crow, int32_t *__restrict__ ccol,
-                                                        VT *__restrict__ cval, int64_t m, const DevHdr *hdr) {
-    perm_pull_short_tile<PT, VT>(blockIdx.x, arow, colq, aval, p, crow, ccol, cval, m, hdr);
+                                                        VT *__restrict__ cval, int64_t m, const DevHdr *hdr,
+                                                        const int32_t *__restrict__ acol,
+                                                        const int32_t *__restrict__ cmap, int64_t n) {
+    perm_pull_short_tile<PT, VT>(blockIdx.x, arow, colq, aval, p, crow, ccol, cval, m, hdr, acol, cmap, n);
 }
 
-// Exec workspace: the class sorts' temporaries, then the renamed columns.
-size_t perm_xws_bytes(size_t seg_bytes, int64_t nnz) {
-    return ((seg_bytes + 255) & ~size_t(255)) + (((size_t)nnz * 4 + 255) & ~size_t(255));
+// Entries in output rows of more than 4 entries (the class sorts' rows).
+int64_t long_entries(const hp_plan_info_t *info) {
+    int64_t e = 0;
+    for (int b = 0; b < NBINS; b++) e += info->class_elems[b];
+    return e;
+}
+
+// Exec workspace: the class sorts' temporaries, then the renamed columns
+// when they are used.
+size_t perm_xws_bytes(size_t seg_bytes, int64_t nnz, bool colq) {
+    return ((seg_bytes + 255) & ~size_t(255)) + (colq ? (((size_t)nnz * 4 + 255) & ~size_t(255)) : 0);
 }
 
 hp_status_t perm_check_args(hp_handle_t h, const hp_csr_t *A, const int32_t *p, const int32_t *q,
@@ -137,7 +147,7 @@ hp_status_t perm_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
             info->class_elems[b] = (int64_t)H.bin_elems[b];
         }
         info->exec_ws_bytes = perm_xws_bytes(seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], H.bin_cnt[BIN_GLOBAL], vs, n),
-                                             A->nnz);
+                                             A->nnz, perm_use_colq(A->nnz, long_entries(info)));
     }
     return HP_OK;
 }
@@ -172,10 +182,11 @@ hp_status_t perm_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
     stage_begin(h);
     const size_t seg_bytes = seg_tmp_bytes((uint64_t)info->class_elems[BIN_GLOBAL], (uint64_t)info->rows_sorted[BIN_GLOBAL],
                                            vs, n);
-    if (info->exec_ws_bytes < perm_xws_bytes(seg_bytes, A->nnz))
+    const bool use_colq = perm_use_colq(A->nnz, long_entries(info));
+    if (info->exec_ws_bytes < perm_xws_bytes(seg_bytes, A->nnz, use_colq))
         return fail(h, HP_ERR_INVALID_ARG, "info is not from hp_permute_plan of this matrix");
-    int32_t *colq = (int32_t *)((char *)xws + ((seg_bytes + 255) & ~size_t(255)));
-    if (A->nnz > 0) {
+    int32_t *colq = use_colq ? (int32_t *)((char *)xws + ((seg_bytes + 255) & ~size_t(255))) : nullptr;
+    if (use_colq) {
         hipLaunchKernelGGL(k_perm_colmap, dim3((unsigned)((A->nnz + 1023) / 1024)), dim3(256), 0, s, A->col, A->nnz,
                            n, L.qinv, colq);
         stage_mark(h, "perm.colmap");
@@ -183,15 +194,23 @@ hp_status_t perm_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
     if (m > 0) {
         hipLaunchKernelGGL((k_perm_pull_short<PT, VT>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
                            (const PT *)A->rowptr, colq, (const VT *)A->val, p, (const PT *)C->rowptr, C->col,
-                           (VT *)C->val, m, L.hdr);
+                           (VT *)C->val, m, L.hdr, A->col, L.qinv, n);
         stage_mark(h, "perm.fill_short");
     }
     uint32_t cnt[NBINS];
     for (int b = 0; b < NBINS; b++) cnt[b] = (uint32_t)info->rows_sorted[b];
-    LoadPermMapped<PT, VT> ld{(const PT *)A->rowptr, colq, (const VT *)A->val, p, m};
-    hipError_t e = launch_seg_classes<PT, VT, LoadPermMapped<PT, VT>>(
-        s, (const PT *)C->rowptr, C->col, (VT *)C->val, L.lists, m, cnt, ld, sorted != 0, n, false, xws,
-        (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);
+    hipError_t e;
+    if (use_colq) {
+        LoadPermMapped<PT, VT> ld{(const PT *)A->rowptr, colq, (const VT *)A->val, p, m};
+        e = launch_seg_classes<PT, VT, LoadPermMapped<PT, VT>>(
+            s, (const PT *)C->rowptr, C->col, (VT *)C->val, L.lists, m, cnt, ld, sorted != 0, n, false, xws,
+            (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);
+    } else {
+        LoadPerm<PT, VT> ld{(const PT *)A->rowptr, A->col, (const VT *)A->val, p, L.qinv, n};
+        e = launch_seg_classes<PT, VT, LoadPerm<PT, VT>>(
+            s, (const PT *)C->rowptr, C->col, (VT *)C->val, L.lists, m, cnt, ld, sorted != 0, n, false, xws,
+            (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);
+    }
     stage_mark(h, "perm.fill_long");
     stage_end(h);
     return hip_check(h, e == hipSuccess ? hipGetLastError() : e, "permute exec");
