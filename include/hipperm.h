@@ -119,7 +119,8 @@ typedef struct {
     int32_t op;               /* which operation produced it (internal check)       */
     int64_t rows_sorted[4];   /* output rows per sort class: <=16, <=64, <=4096, >  */
     int64_t class_elems[4];   /* entries per sort class                             */
-    int64_t aux[4];           /* operation-specific counts                          */
+    int64_t aux[4];           /* operation-specific counts (permute: aux[0] is the
+                                 smallest exec workspace exec accepts)              */
 } hp_plan_info_t;
 
 typedef struct hp_handle_s *hp_handle_t;
@@ -164,6 +165,13 @@ hp_status_t hp_validate_csr(hp_handle_t h, const hp_csr_t *A, void *ws, size_t w
  * [0, n), or NULL for the symmetric form P A P^T (requires m == n).
  * C: caller sets nrows=m, ncols=n, ptr_type/val_type equal to A's and
  * rowptr (m+1 entries); plan writes rowptr and nnz (= nnz(A)).
+ * Exec workspace: info->exec_ws_bytes is the workspace of the fastest form;
+ * when rows of at most 4 entries hold at least half of the entries it
+ * includes one fixed slot per row of A (32 bytes for 4-byte values, 64 for
+ * 8-byte ones) into which exec first packs those rows.  info->aux[0] is the
+ * smallest exec workspace exec accepts: given less than exec_ws_bytes (but
+ * at least aux[0]) bytes, exec runs without the slots; the result is the
+ * same.  The workspace may start at any address.
  * Errors: INDEX_RANGE, NOT_PERMUTATION, SHAPE, WORKSPACE, ALIAS. */
 hp_status_t hp_permute_workspace(hp_handle_t h, const hp_csr_t *A, size_t *bytes);
 hp_status_t hp_permute_plan(hp_handle_t h, const hp_csr_t *A, const int32_t *p, const int32_t *q,
@@ -185,10 +193,12 @@ hp_status_t hp_permute_exec(hp_handle_t h, const hp_csr_t *A, const int32_t *p, 
  * C->val must hold nnz(A) entries (a permutation keeps nnz); plan writes
  * C->rowptr and C->nnz, exec C->col and C->val.
  * Limit: the plan workspace (hp_permute_workspace: about 36 bytes per row
- * of a square matrix) and the exec workspace (4 bytes per stored entry,
- * plus temporaries for rows longer than 2048 entries) must fit the array
- * together, e.g. 1M rows with 6M entries; otherwise HP_ERR_WORKSPACE (when
- * only the exec part does not fit, C->rowptr has already been written).
+ * of a square matrix) and the smallest exec workspace (info->aux[0] of the
+ * plan: temporaries for rows longer than 2048 entries only) must fit the
+ * array together, e.g. 1M rows with rows of up to 2048 entries; otherwise
+ * HP_ERR_WORKSPACE (when only the exec part does not fit, C->rowptr has
+ * already been written).  The exec runs with the row slots of
+ * hp_permute_exec when the array holds them too.
  * Stage timing must be off (HP_ERR_INVALID_ARG).
  * Every call on one device shares that device's array, which keeps the
  * last call's contents; each call clears what it needs cleared (status

@@ -262,9 +262,9 @@ __device__ void run_tile(int phase, int64_t tile, const ReqDev &r, BatchSmem &sm
 
 // Exec phases 0-6 of a permutation request: output row i is row p[i] of A
 // with its columns looked up in qinv on the way (a pass that renames all
-// columns first, as the plain call may do, measured slower here: its tiles
-// add to every batch's queue, while most batched matrices keep the bulk of
-// their entries in the long rows that the class sorts pull).
+// columns first measured slower here: its tiles add to every batch's
+// queue, while most batched matrices keep the bulk of their entries in the
+// long rows that the class sorts pull).
 template <typename PT, typename VT, int HALF, int STAGE>
 __device__ void perm_exec_phase(int phase, int64_t tile, const ReqDev &r, BatchSmem &sm, const PT *crow, int64_t cap,
                                 const uint64_t *goff, int32_t *tk, VT *tv, uint32_t *bst) {
@@ -273,8 +273,8 @@ __device__ void perm_exec_phase(int phase, int64_t tile, const ReqDev &r, BatchS
         HP_PHASE(1, 0) { copy_rowptr_tile<PT>(tile, crow, (PT *)r.crow, r.nrows_out + 1); }
         break;
         HP_PHASE(1, 1) {
-            perm::perm_pull_short_tile<PT, VT>(tile, (const PT *)r.arow, nullptr, (const VT *)r.aval, r.p, crow,
-                                               r.ccol, (VT *)r.cval, r.m, r.hdr, r.acol, r.qinv, r.n);
+            perm::perm_pull_short_tile<PT, VT>(tile, (const PT *)r.arow, r.acol, (const VT *)r.aval, r.p, r.qinv,
+                                               r.n, crow, r.ccol, (VT *)r.cval, r.m, r.hdr);
         }
         break;
         HP_PHASE(1, 3) {

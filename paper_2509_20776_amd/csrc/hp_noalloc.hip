@@ -79,7 +79,9 @@ extern "C" hp_status_t hp_permute_noalloc(hp_handle_t h, const hp_csr_t *A, cons
     hp_plan_info_t info{};
     st = hp_permute_plan(h, A, p, q, C, ws, plan_bytes, &info);
     if (st) return st;
-    const size_t xbytes = info.exec_ws_bytes;
+    // the exec workspace with the row slots when the array holds it, else
+    // the smallest one exec accepts (info.aux[0], without them)
+    const size_t xbytes = plan_bytes + info.exec_ws_bytes <= SCRATCH_BYTES ? info.exec_ws_bytes : (size_t)info.aux[0];
     if (plan_bytes + xbytes > SCRATCH_BYTES)
         return fail(h, HP_ERR_WORKSPACE, "permute_noalloc: rows longer than the block sort need " +
                                              std::to_string(xbytes) + " more bytes of scratch than the fixed " +

@@ -42,36 +42,6 @@ __device__ inline void perm_check_tile(int64_t bid, int64_t m, int64_t n, const 
     if (bad) atomicOr(&hdr->err, E_NOTPERM);   // error path only
 }
 
-// Rows of at most 4 entries: one lane per SOURCE row r, streamed in order
-// (coalesced reads of A, local reads of qinv for banded matrices), written
-// to output row pinv[r] after an in-register sort of the mapped columns.
-// Longer rows go through the class kernels (pull from A).
-template <typename PT, typename VT>
-__device__ inline void perm_fill_short_tile(
-    int64_t bid, const PT *__restrict__ arow, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
-    const int32_t *__restrict__ pinv, const int32_t *__restrict__ cmap, const PT *__restrict__ crow,
-    int32_t *__restrict__ ccol, VT *__restrict__ cval, int64_t m, int64_t n, const DevHdr *hdr) {
-    if (hdr->err) return;
-    const int64_t r = bid * 256 + threadIdx.x;
-    if (r >= m) return;
-    const int64_t s = arow[r];
-    const int len = (int)(arow[r + 1] - s);
-    if (len == 0 || len > 4) return;
-    const int64_t d = crow[pinv[r]];
-    int32_t k[4];
-    VT v[4];
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        k[i] = INT32_MAX;
-        v[i] = VT(0);
-        if (i < len) {
-            k[i] = cmap[clampc(acol[s + i], n)];
-            v[i] = aval[s + i];
-        }
-    }
-    sort_store_regs<4, VT>(k, v, len, false, ccol + d, cval + d);
-}
-
 // Longer rows: output row i is row p[i] of A with columns mapped (pull).
 template <typename PT, typename VT>
 struct LoadPerm {
@@ -88,42 +58,20 @@ struct LoadPerm {
     }
 };
 
-// ---- pull fill of the plain permutation ---------------------------------------
-// Output row i is row p[i] of A with every column c renamed qinv[c].  The
-// renaming is done once for all stored entries by a streaming pass (colq,
-// in A's storage order: coalesced reads of the columns, and for banded
-// matrices local reads of qinv), so the fill itself reads each source row
-// once, at a random place, and writes the output rows in order: random
-// reads and coalesced writes, instead of the random partial-line writes of
-// a push to row pinv[r].
+// ---- pull fill --------------------------------------------------------------
+// Output row i is row p[i] of A with every column c renamed qinv[c]: the
+// fill reads each source row at a random place and writes the output rows
+// in order (random reads and coalesced writes, instead of the random
+// partial-line writes of a push to row pinv[r]).
 
-// colq[k] = cmap[col[k]] for the 1024 entries k of tile bid.
-__device__ inline void perm_colmap_tile(int64_t bid, const int32_t *__restrict__ acol, int64_t nnz, int64_t n,
-                                        const int32_t *__restrict__ cmap, int32_t *__restrict__ colq) {
-    const int64_t b = bid * 1024 + threadIdx.x;
-    int32_t c[4];
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-        const int64_t k = b + u * 256;
-        c[u] = k < nnz ? acol[k] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-        const int64_t k = b + u * 256;
-        if (k < nnz) colq[k] = cmap[clampc(c[u], n)];
-    }
-}
-
-// Output rows of at most 4 entries, one lane per output row i (in order).
-// colq == nullptr: the columns are renamed here, cmap[col[k]] (used when
-// short rows hold few of the entries, so the renaming pass is not run).
+// Output rows of at most 4 entries, one lane per output row i (in order),
+// columns renamed on the way.
 template <typename PT, typename VT>
-__device__ inline void perm_pull_short_tile(int64_t bid, const PT *__restrict__ arow, const int32_t *__restrict__ colq,
+__device__ inline void perm_pull_short_tile(int64_t bid, const PT *__restrict__ arow, const int32_t *__restrict__ acol,
                                             const VT *__restrict__ aval, const int32_t *__restrict__ p,
-                                            const PT *__restrict__ crow, int32_t *__restrict__ ccol,
-                                            VT *__restrict__ cval, int64_t m, const DevHdr *hdr,
-                                            const int32_t *__restrict__ acol = nullptr,
-                                            const int32_t *__restrict__ cmap = nullptr, int64_t n = 0) {
+                                            const int32_t *__restrict__ cmap, int64_t n, const PT *__restrict__ crow,
+                                            int32_t *__restrict__ ccol, VT *__restrict__ cval, int64_t m,
+                                            const DevHdr *hdr) {
     if (hdr->err) return;
     const int64_t i = bid * 256 + threadIdx.x;
     if (i >= m) return;
@@ -140,40 +88,92 @@ __device__ inline void perm_pull_short_tile(int64_t bid, const PT *__restrict__ 
         k[u] = INT32_MAX;
         v[u] = VT(0);
         if (u < len) {
-            k[u] = colq ? colq[s + u] : cmap[clampc(acol[s + u], n)];
+            k[u] = cmap[clampc(acol[s + u], n)];
             v[u] = aval[s + u];
         }
     }
     sort_store_regs<4, VT>(k, v, len, false, ccol + d, cval + d);
 }
 
-// Rename the columns in a pass of their own when output rows of at most 4
-// entries hold at least half of them (the pull fill of those rows then
-// reads each row's renamed columns in one place); otherwise the fill and
-// the class sorts look each column up in qinv as they go (LoadPerm), and
-// the pass would only add its traffic.
-__host__ __device__ inline bool perm_use_colq(int64_t nnz, int64_t long_entries) {
+// Row slots: when rows of at most 4 entries hold most of the entries, a
+// streaming pass first packs each such source row r, renamed and sorted,
+// into a fixed slot of its own (4 column ids, then 4 values: 32 bytes for
+// 4-byte values, 64 for 8-byte ones, aligned to the slot size).  The fill
+// of output row i then reads one aligned slot, slot p[i], instead of the
+// row bounds, columns and values of row p[i] in three places: one random
+// line per row instead of about three, for a sequential pass over A.
+template <typename VT>
+constexpr int perm_slot_bytes() { return sizeof(VT) == 8 ? 64 : 32; }
+
+__host__ __device__ inline bool perm_use_slots(int64_t nnz, int64_t long_entries) {
     return nnz > 0 && 2 * (nnz - long_entries) >= nnz;
 }
 
-// Longer output rows: the class sorts pull row p[i] with its columns
-// already renamed in colq.
+// Pack source rows bid*256 .. +255 (one lane each) into their slots.
 template <typename PT, typename VT>
-struct LoadPermMapped {
-    const PT *arow;
-    const int32_t *colq;
-    const VT *aval;
-    const int32_t *p;
-    int64_t m;
-    __device__ __forceinline__ int64_t base(int64_t row) const {
-        const int32_t pr = p[row];
-        return arow[(uint32_t)pr < (uint64_t)m ? (int64_t)pr : 0];
+__device__ inline void perm_pack_tile(int64_t bid, const PT *__restrict__ arow, const int32_t *__restrict__ acol,
+                                      const VT *__restrict__ aval, const int32_t *__restrict__ cmap, int64_t n,
+                                      int64_t m, char *__restrict__ slots) {
+    const int64_t r = bid * 256 + threadIdx.x;
+    if (r >= m) return;
+    const int64_t s = arow[r];
+    const int len = (int)(arow[r + 1] - s);
+    if (len == 0 || len > 4) return;
+    int32_t k[4];
+    VT v[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        k[u] = INT32_MAX;
+        v[u] = VT(0);
+        if (u < len) {
+            k[u] = cmap[clampc(acol[s + u], n)];
+            v[u] = aval[s + u];
+        }
     }
-    __device__ __forceinline__ void get(int64_t b, int64_t k, int32_t &kk, VT &vv) const {
-        kk = colq[b + k];
-        vv = aval[b + k];
+    bitonic_regs<4, VT>(k, v);
+    char *slot = slots + r * perm_slot_bytes<VT>();
+    *reinterpret_cast<uint4 *>(slot) = make_uint4((uint32_t)k[0], (uint32_t)k[1], (uint32_t)k[2], (uint32_t)k[3]);
+    if constexpr (sizeof(VT) == 8) {
+        reinterpret_cast<ulonglong2 *>(slot)[1] = make_ulonglong2(v[0], v[1]);
+        reinterpret_cast<ulonglong2 *>(slot)[2] = make_ulonglong2(v[2], v[3]);
+    } else {
+        reinterpret_cast<uint4 *>(slot)[1] = make_uint4(v[0], v[1], v[2], v[3]);
     }
-};
+}
+
+// Output rows bid*256 .. +255 of at most 4 entries (one lane each), copied
+// from slot p[i]; the row's length is that of output row i.
+template <typename PT, typename VT>
+__device__ inline void perm_slot_fill_tile(int64_t bid, const int32_t *__restrict__ p, const char *__restrict__ slots,
+                                           const PT *__restrict__ crow, int32_t *__restrict__ ccol,
+                                           VT *__restrict__ cval, int64_t m, const DevHdr *hdr) {
+    if (hdr->err) return;
+    const int64_t i = bid * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int64_t d = crow[i];
+    const int len = (int)(crow[i + 1] - d);
+    if (len == 0 || len > 4) return;
+    const int32_t pr = p[i];
+    const int64_t src = (uint32_t)pr < (uint64_t)m ? (int64_t)pr : 0;   // p was checked by the plan
+    const char *slot = slots + src * perm_slot_bytes<VT>();
+    const uint4 kk = *reinterpret_cast<const uint4 *>(slot);
+    VT v[4];
+    if constexpr (sizeof(VT) == 8) {
+        const ulonglong2 a = reinterpret_cast<const ulonglong2 *>(slot)[1];
+        const ulonglong2 b = reinterpret_cast<const ulonglong2 *>(slot)[2];
+        v[0] = a.x, v[1] = a.y, v[2] = b.x, v[3] = b.y;
+    } else {
+        const uint4 a = reinterpret_cast<const uint4 *>(slot)[1];
+        v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w;
+    }
+    const int32_t k[4] = {(int32_t)kk.x, (int32_t)kk.y, (int32_t)kk.z, (int32_t)kk.w};
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+        if (u < len) {
+            ccol[d + u] = k[u];
+            cval[d + u] = v[u];
+        }
+}
 
 }  // namespace perm
 }  // namespace hp

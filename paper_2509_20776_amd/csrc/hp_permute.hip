@@ -9,9 +9,13 @@
 //          k_perm_prepare  scatter pinv, qinv; per-output-row counts; range
 //          k_perm_check    no slot left at -1 (every value occurs once)
 //          scan            rowptr of C + row classes by length
-//   exec : k_perm_fill_short  rows of <= 4 entries, streamed in source
-//                             order (push), sorted in registers
-//          class kernels       longer rows gathered from A (pull) and sorted
+//   exec : k_perm_pack       rows of <= 4 entries renamed, sorted and packed
+//                            into fixed slots (a sequential pass over A;
+//                            only when such rows hold most entries)
+//          k_perm_slot_fill  output rows of <= 4 entries copied from slot
+//                            p[i] (or k_perm_pull_short: read from row p[i]
+//                            of A, renamed and sorted in registers)
+//          class kernels     longer rows gathered from A (pull) and sorted
 #include "hp_internal.hpp"
 #include "hp_segsort.hpp"
 #include "hp_perm_tiles.hpp"
@@ -49,18 +53,25 @@ __global__ __launch_bounds__(256) void k_perm_check(int64_t m, int64_t n, const 
                                                    const int32_t *__restrict__ qinv, bool general, DevHdr *hdr) {
     perm_check_tile(blockIdx.x, m, n, pinv, qinv, general, hdr);
 }
-__global__ __launch_bounds__(256) void k_perm_colmap(const int32_t *__restrict__ acol, int64_t nnz, int64_t n,
-                                                    const int32_t *__restrict__ cmap, int32_t *__restrict__ colq) {
-    perm_colmap_tile(blockIdx.x, acol, nnz, n, cmap, colq);
+template <typename PT, typename VT>
+__global__ __launch_bounds__(256) void k_perm_pack(const PT *__restrict__ arow, const int32_t *__restrict__ acol,
+                                                  const VT *__restrict__ aval, const int32_t *__restrict__ cmap,
+                                                  int64_t n, int64_t m, char *__restrict__ slots) {
+    perm_pack_tile<PT, VT>(blockIdx.x, arow, acol, aval, cmap, n, m, slots);
 }
 template <typename PT, typename VT>
-__global__ __launch_bounds__(256) void k_perm_pull_short(const PT *__restrict__ arow, const int32_t *__restrict__ colq,
+__global__ __launch_bounds__(256) void k_perm_slot_fill(const int32_t *__restrict__ p, const char *__restrict__ slots,
+                                                       const PT *__restrict__ crow, int32_t *__restrict__ ccol,
+                                                       VT *__restrict__ cval, int64_t m, const DevHdr *hdr) {
+    perm_slot_fill_tile<PT, VT>(blockIdx.x, p, slots, crow, ccol, cval, m, hdr);
+}
+template <typename PT, typename VT>
+__global__ __launch_bounds__(256) void k_perm_pull_short(const PT *__restrict__ arow, const int32_t *__restrict__ acol,
                                                         const VT *__restrict__ aval, const int32_t *__restrict__ p,
+                                                        const int32_t *__restrict__ cmap, int64_t n,
                                                         const PT *__restrict__ crow, int32_t *__restrict__ ccol,
-                                                        VT *__restrict__ cval, int64_t m, const DevHdr *hdr,
-                                                        const int32_t *__restrict__ acol,
-                                                        const int32_t *__restrict__ cmap, int64_t n) {
-    perm_pull_short_tile<PT, VT>(blockIdx.x, arow, colq, aval, p, crow, ccol, cval, m, hdr, acol, cmap, n);
+                                                        VT *__restrict__ cval, int64_t m, const DevHdr *hdr) {
+    perm_pull_short_tile<PT, VT>(blockIdx.x, arow, acol, aval, p, cmap, n, crow, ccol, cval, m, hdr);
 }
 
 // Entries in output rows of more than 4 entries (the class sorts' rows).
@@ -70,10 +81,12 @@ int64_t long_entries(const hp_plan_info_t *info) {
     return e;
 }
 
-// Exec workspace: the class sorts' temporaries, then the renamed columns
-// when they are used.
-size_t perm_xws_bytes(size_t seg_bytes, int64_t nnz, bool colq) {
-    return ((seg_bytes + 255) & ~size_t(255)) + (colq ? (((size_t)nnz * 4 + 255) & ~size_t(255)) : 0);
+// Exec workspace: the class sorts' temporaries, then the row slots when
+// they are used (m slots of slot_bytes, from the first 256-byte boundary
+// after the temporaries, wherever the caller's workspace starts).
+size_t perm_xws_bytes(size_t seg_bytes, int64_t m, int slot_bytes) {
+    const size_t seg = (seg_bytes + 255) & ~size_t(255);
+    return slot_bytes ? seg + 256 + (((size_t)m * slot_bytes + 255) & ~size_t(255)) : seg;
 }
 
 hp_status_t perm_check_args(hp_handle_t h, const hp_csr_t *A, const int32_t *p, const int32_t *q,
@@ -146,8 +159,13 @@ hp_status_t perm_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
             info->rows_sorted[b] = H.bin_cnt[b];
             info->class_elems[b] = (int64_t)H.bin_elems[b];
         }
-        info->exec_ws_bytes = perm_xws_bytes(seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], H.bin_cnt[BIN_GLOBAL], vs, n),
-                                             A->nnz, perm_use_colq(A->nnz, long_entries(info)));
+        // exec_ws_bytes: with the row slots when they pay; aux[0]: the
+        // smallest exec workspace, without them
+        const size_t seg = seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], H.bin_cnt[BIN_GLOBAL], vs, n);
+        const int sb = vs == 8 ? perm_slot_bytes<uint64_t>() : perm_slot_bytes<uint32_t>();
+        info->aux[0] = (int64_t)perm_xws_bytes(seg, m, 0);
+        info->exec_ws_bytes = perm_use_slots(A->nnz, long_entries(info)) ? perm_xws_bytes(seg, m, sb)
+                                                                          : (size_t)info->aux[0];
     }
     return HP_OK;
 }
@@ -162,7 +180,7 @@ hp_status_t perm_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
     perm_layout(need, m, n, sym);
     if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "permute workspace too small");
     if (!info || info->op != 1) return fail(h, HP_ERR_INVALID_ARG, "info is not from hp_permute_plan");
-    if (xws_bytes < info->exec_ws_bytes || (info->exec_ws_bytes && !xws))
+    if (info->aux[0] < 0 || xws_bytes < (size_t)info->aux[0] || (info->aux[0] && !xws))
         return fail(h, HP_ERR_WORKSPACE, "permute exec workspace too small");
     if (C->nnz != A->nnz) return fail(h, HP_ERR_INVALID_ARG, "C->nnz must equal nnz(A) (set by plan)");
     if (C->nnz > 0 && (!C->col || !C->val)) return fail(h, HP_ERR_INVALID_ARG, "C->col/val is NULL");
@@ -182,35 +200,32 @@ hp_status_t perm_exec_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
     stage_begin(h);
     const size_t seg_bytes = seg_tmp_bytes((uint64_t)info->class_elems[BIN_GLOBAL], (uint64_t)info->rows_sorted[BIN_GLOBAL],
                                            vs, n);
-    const bool use_colq = perm_use_colq(A->nnz, long_entries(info));
-    if (info->exec_ws_bytes < perm_xws_bytes(seg_bytes, A->nnz, use_colq))
+    if ((size_t)info->aux[0] != perm_xws_bytes(seg_bytes, m, 0))
         return fail(h, HP_ERR_INVALID_ARG, "info is not from hp_permute_plan of this matrix");
-    int32_t *colq = use_colq ? (int32_t *)((char *)xws + ((seg_bytes + 255) & ~size_t(255))) : nullptr;
-    if (use_colq) {
-        hipLaunchKernelGGL(k_perm_colmap, dim3((unsigned)((A->nnz + 1023) / 1024)), dim3(256), 0, s, A->col, A->nnz,
-                           n, L.qinv, colq);
-        stage_mark(h, "perm.colmap");
-    }
-    if (m > 0) {
-        hipLaunchKernelGGL((k_perm_pull_short<PT, VT>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
-                           (const PT *)A->rowptr, colq, (const VT *)A->val, p, (const PT *)C->rowptr, C->col,
-                           (VT *)C->val, m, L.hdr, A->col, L.qinv, n);
+    // the row slots when they pay and the workspace holds them
+    const int sb = perm_slot_bytes<VT>();
+    const bool slots = perm_use_slots(A->nnz, long_entries(info)) && xws_bytes >= perm_xws_bytes(seg_bytes, m, sb);
+    const unsigned grid = (unsigned)((m + 255) / 256);
+    if (m > 0 && slots) {
+        const uintptr_t at = (uintptr_t)xws + ((seg_bytes + 255) & ~size_t(255));
+        char *sl = (char *)((at + 255) & ~uintptr_t(255));
+        hipLaunchKernelGGL((k_perm_pack<PT, VT>), dim3(grid), dim3(256), 0, s, (const PT *)A->rowptr, A->col,
+                           (const VT *)A->val, L.qinv, n, m, sl);
+        stage_mark(h, "perm.pack");
+        hipLaunchKernelGGL((k_perm_slot_fill<PT, VT>), dim3(grid), dim3(256), 0, s, p, (const char *)sl,
+                           (const PT *)C->rowptr, C->col, (VT *)C->val, m, L.hdr);
+        stage_mark(h, "perm.fill_short");
+    } else if (m > 0) {
+        hipLaunchKernelGGL((k_perm_pull_short<PT, VT>), dim3(grid), dim3(256), 0, s, (const PT *)A->rowptr, A->col,
+                           (const VT *)A->val, p, L.qinv, n, (const PT *)C->rowptr, C->col, (VT *)C->val, m, L.hdr);
         stage_mark(h, "perm.fill_short");
     }
     uint32_t cnt[NBINS];
     for (int b = 0; b < NBINS; b++) cnt[b] = (uint32_t)info->rows_sorted[b];
-    hipError_t e;
-    if (use_colq) {
-        LoadPermMapped<PT, VT> ld{(const PT *)A->rowptr, colq, (const VT *)A->val, p, m};
-        e = launch_seg_classes<PT, VT, LoadPermMapped<PT, VT>>(
-            s, (const PT *)C->rowptr, C->col, (VT *)C->val, L.lists, m, cnt, ld, sorted != 0, n, false, xws,
-            (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);
-    } else {
-        LoadPerm<PT, VT> ld{(const PT *)A->rowptr, A->col, (const VT *)A->val, p, L.qinv, n};
-        e = launch_seg_classes<PT, VT, LoadPerm<PT, VT>>(
-            s, (const PT *)C->rowptr, C->col, (VT *)C->val, L.lists, m, cnt, ld, sorted != 0, n, false, xws,
-            (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);
-    }
+    LoadPerm<PT, VT> ld{(const PT *)A->rowptr, A->col, (const VT *)A->val, p, L.qinv, n};
+    hipError_t e = launch_seg_classes<PT, VT, LoadPerm<PT, VT>>(
+        s, (const PT *)C->rowptr, C->col, (VT *)C->val, L.lists, m, cnt, ld, sorted != 0, n, false, xws,
+        (uint64_t)info->class_elems[BIN_GLOBAL], L.hdr, true);
     stage_mark(h, "perm.fill_long");
     stage_end(h);
     return hip_check(h, e == hipSuccess ? hipGetLastError() : e, "permute exec");

@@ -303,10 +303,14 @@ class Handle:
         return C, ws, info
 
     def permute_exec(self, A, p, q, C, ws, info, xws=None):
+        """Exec of a permute plan.  Without `xws` one of info.exec_ws_bytes
+        is allocated; a caller's `xws` goes to the library as it is (it
+        needs at least info.aux[0] bytes: the row-slot form runs when it
+        holds info.exec_ws_bytes)."""
         self._stream()
         Ac = to_csr_t(A)
         Cc = to_csr_t(C)
-        if info.exec_ws_bytes and (xws is None or xws.numel() < info.exec_ws_bytes):
+        if xws is None and info.exec_ws_bytes:
             xws = self._alloc(info.exec_ws_bytes)
         self.check(hp_permute_exec(self.h, ctypes.byref(Ac), _idx(p), _idx(q), ctypes.byref(Cc),
                                    _dptr(ws), ws.numel(), ctypes.byref(info),

@@ -44,6 +44,55 @@ def test_all_row_classes(hp, ptr, vdt):
     assert_same(np_csr(C2), np_csr(C), "repeat run identical")
 
 
+SHORT = [0, 1, 2, 3, 4, 1, 2, 3, 4, 4, 4, 0, 7, 20]   # rows of <= 4 entries hold most entries
+
+
+@pytest.mark.parametrize("ptr", [torch.int32, torch.int64])
+@pytest.mark.parametrize("vdt", [torch.float32, torch.float64])
+def test_row_slots_and_inline_fill_agree(hp, ptr, vdt):
+    """When rows of at most 4 entries hold most entries, the plan asks for
+    the row-slot workspace (exec_ws_bytes above aux[0]); exec with it, with
+    it at an address off the 256-byte grid, and with only aux[0] bytes (the
+    form without slots) all equal the oracle; below aux[0] is refused."""
+    h = hp.Handle(0)
+    m, n = 5000, 3000
+    A = mixed_csr(11, m, n, SHORT, ptr, vdt)
+    p = synth.randperm(12, m, "cuda")
+    q = synth.randperm(13, n, "cuda")
+    ref = oracle.permute(A, p, q)
+    C, ws, info = h.permute_plan(A, p, q)
+    assert info.exec_ws_bytes > info.aux[0] >= 0
+    assert_same(np_csr(h.permute_exec(A, p, q, C, ws, info)), ref, "row slots")
+    big = torch.empty(info.exec_ws_bytes + 4, dtype=torch.uint8, device="cuda")
+    C, ws, info = h.permute_plan(A, p, q)
+    assert_same(np_csr(h.permute_exec(A, p, q, C, ws, info, xws=big[4:])), ref, "row slots, offset workspace")
+    C, ws, info = h.permute_plan(A, p, q)
+    small = torch.empty(max(info.aux[0], 1), dtype=torch.uint8, device="cuda")[: info.aux[0]]
+    assert_same(np_csr(h.permute_exec(A, p, q, C, ws, info, xws=small if info.aux[0] else None)), ref,
+                "no row slots")
+    if info.aux[0] > 0:
+        with pytest.raises(hp.HPError) as e:
+            h.permute_exec(A, p, q, C, ws, info, xws=small[:-1])
+        assert e.value.name == "HP_ERR_WORKSPACE"
+    h.close()
+
+
+def test_row_slots_symmetric_and_noalloc(hp):
+    """Symmetric P A P^T through the row slots, and the entry point that
+    allocates nothing on the same matrix (it takes the slot form when its
+    array holds it)."""
+    h = hp.Handle(0)
+    m = 6000
+    A = mixed_csr(21, m, m, SHORT, torch.int64, torch.float64)
+    p = synth.randperm(22, m, "cuda")
+    ref = oracle.permute(A, p)
+    C, ws, info = h.permute_plan(A, p)
+    assert info.exec_ws_bytes > info.aux[0]
+    assert_same(np_csr(h.permute_exec(A, p, None, C, ws, info)), ref, "P A P^T, row slots")
+    assert_same(np_csr(h.permute_noalloc(A, p)), ref, "P A P^T, no-alloc")
+    h.close()
+
+
 def test_identity_column_map(hp):
     A = mixed_csr(4, 300, 5000, LENGTHS)
     p = synth.randperm(8, 300, "cuda")
