@@ -192,7 +192,7 @@ hp_status_t hp_permute_exec(hp_handle_t h, const hp_csr_t *A, const int32_t *p, 
  * A, p, q: as hp_permute_plan.  C: as hp_permute_plan, and C->col and
  * C->val must hold nnz(A) entries (a permutation keeps nnz); plan writes
  * C->rowptr and C->nnz, exec C->col and C->val.
- * Limit: the plan workspace (hp_permute_workspace: about 36 bytes per row
+ * Limit: the plan workspace (hp_permute_workspace: about 33 bytes per row
  * of a square matrix) and the smallest exec workspace (info->aux[0] of the
  * plan: temporaries for rows longer than 2048 entries only) must fit the
  * array together, e.g. 1M rows with rows of up to 2048 entries; otherwise

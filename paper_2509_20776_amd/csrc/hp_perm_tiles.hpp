@@ -8,10 +8,13 @@
 namespace hp {
 namespace perm {
 
+// pmark (optional): when the inverse of p itself is not needed (the pull
+// fill of a general permutation only reads p and qinv), every value r of p
+// just sets byte pmark[r] instead of pinv[r] = t: a quarter of the bytes.
 template <typename PT>
 __device__ inline void perm_prepare_tile(int64_t bid, const PT *__restrict__ arow, const int32_t *__restrict__ p,
                                          const int32_t *__restrict__ q, int64_t m, int64_t n, int32_t *pinv,
-                                         int32_t *qinv, int32_t *cnt, DevHdr *hdr) {
+                                         int32_t *qinv, int32_t *cnt, DevHdr *hdr, uint8_t *pmark = nullptr) {
     const int64_t t = bid * 256 + threadIdx.x;
     if (t < m) {
         const int32_t r = p[t];
@@ -19,7 +22,8 @@ __device__ inline void perm_prepare_tile(int64_t bid, const PT *__restrict__ aro
             atomicOr(&hdr->err, E_RANGE);     // error path only
             cnt[t] = 0;
         } else {
-            pinv[r] = (int32_t)t;
+            if (pmark) pmark[r] = 1;
+            else pinv[r] = (int32_t)t;
             cnt[t] = (int32_t)(arow[r + 1] - arow[r]);
         }
     }
@@ -30,14 +34,16 @@ __device__ inline void perm_prepare_tile(int64_t bid, const PT *__restrict__ aro
     }
 }
 
-// pinv and qinv start filled with -1 and every in-range value of p (q) has
-// been scattered: a slot left at -1 means some value is missing, hence
-// (m values in m slots) another is repeated.  Sequential reads only.
+// pinv and qinv start filled with -1 (pmark with 0) and every in-range
+// value of p (q) has been scattered: a slot left at -1 (0) means some value
+// is missing, hence (m values in m slots) another is repeated.  Sequential
+// reads only.
 __device__ inline void perm_check_tile(int64_t bid, int64_t m, int64_t n, const int32_t *__restrict__ pinv,
-                                       const int32_t *__restrict__ qinv, bool general, DevHdr *hdr) {
+                                       const int32_t *__restrict__ qinv, bool general, DevHdr *hdr,
+                                       const uint8_t *__restrict__ pmark = nullptr) {
     const int64_t t = bid * 256 + threadIdx.x;
     bool bad = false;
-    if (t < m) bad |= pinv[t] < 0;
+    if (t < m) bad |= pmark ? pmark[t] == 0 : pinv[t] < 0;
     if (general && t < n) bad |= qinv[t] < 0;
     if (bad) atomicOr(&hdr->err, E_NOTPERM);   // error path only
 }
@@ -109,15 +115,36 @@ __host__ __device__ inline bool perm_use_slots(int64_t nnz, int64_t long_entries
     return nnz > 0 && 2 * (nnz - long_entries) >= nnz;
 }
 
-// Pack source rows bid*256 .. +255 (one lane each) into their slots.
+// Entries of one wavefront's 64 rows staged through LDS by the pack when
+// they are at most this many (rows of about 4 entries): the wavefront then
+// reads them 64-wide in storage order, and each lane takes its row from LDS.
+constexpr int PACK_STAGE = 256;
+
+// Pack source rows bid*256 .. +255 (one lane each) into their slots; lk/lv
+// hold PACK_STAGE entries per wavefront of the block.  The slot is written
+// whole (unused entries as INT32_MAX / 0) so that its lines are full writes.
 template <typename PT, typename VT>
 __device__ inline void perm_pack_tile(int64_t bid, const PT *__restrict__ arow, const int32_t *__restrict__ acol,
                                       const VT *__restrict__ aval, const int32_t *__restrict__ cmap, int64_t n,
-                                      int64_t m, char *__restrict__ slots) {
-    const int64_t r = bid * 256 + threadIdx.x;
-    if (r >= m) return;
-    const int64_t s = arow[r];
-    const int len = (int)(arow[r + 1] - s);
+                                      int64_t m, char *__restrict__ slots, int32_t *lk, VT *lv) {
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    const int64_t r0 = bid * 256 + (int64_t)w * WAVE;
+    if (r0 >= m) return;   // the whole wavefront
+    const int64_t r = r0 + l;
+    const int64_t rend = r0 + WAVE < m ? r0 + WAVE : m;
+    const int64_t s0 = arow[r0], s1 = arow[rend];
+    const int64_t s = r < m ? (int64_t)arow[r] : s1;
+    const int len = r < m ? (int)(arow[r + 1] - s) : 0;
+    const bool staged = s1 - s0 <= PACK_STAGE;
+    int32_t *wk = lk + w * PACK_STAGE;
+    VT *wv = lv + w * PACK_STAGE;
+    if (staged) {
+        for (int64_t k = s0 + l; k < s1; k += WAVE) {
+            wk[k - s0] = cmap[clampc(acol[k], n)];
+            wv[k - s0] = aval[k];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
     if (len == 0 || len > 4) return;
     int32_t k[4];
     VT v[4];
@@ -126,8 +153,13 @@ __device__ inline void perm_pack_tile(int64_t bid, const PT *__restrict__ arow, 
         k[u] = INT32_MAX;
         v[u] = VT(0);
         if (u < len) {
-            k[u] = cmap[clampc(acol[s + u], n)];
-            v[u] = aval[s + u];
+            if (staged) {
+                k[u] = wk[s - s0 + u];
+                v[u] = wv[s - s0 + u];
+            } else {
+                k[u] = cmap[clampc(acol[s + u], n)];
+                v[u] = aval[s + u];
+            }
         }
     }
     bitonic_regs<4, VT>(k, v);
@@ -136,6 +168,7 @@ __device__ inline void perm_pack_tile(int64_t bid, const PT *__restrict__ arow, 
     if constexpr (sizeof(VT) == 8) {
         reinterpret_cast<ulonglong2 *>(slot)[1] = make_ulonglong2(v[0], v[1]);
         reinterpret_cast<ulonglong2 *>(slot)[2] = make_ulonglong2(v[2], v[3]);
+        reinterpret_cast<ulonglong2 *>(slot)[3] = make_ulonglong2(0, 0);
     } else {
         reinterpret_cast<uint4 *>(slot)[1] = make_uint4(v[0], v[1], v[2], v[3]);
     }

@@ -25,10 +25,13 @@ using namespace hp::perm;
 
 namespace {
 
+// The symmetric form renames columns with pinv itself; the general form
+// needs only qinv, and marks the values of p in bytes (pmark) for the check.
 struct PermLayout {
     DevHdr *hdr;
     uint64_t *tiles;
     int32_t *pinv, *qinv, *cnt;
+    uint8_t *pmark;
     uint32_t *lists;
 };
 
@@ -36,7 +39,8 @@ PermLayout perm_layout(Carve &c, int64_t m, int64_t n, bool sym) {
     PermLayout L;
     L.hdr = c.take<DevHdr>(1);
     L.tiles = c.take<uint64_t>(scan_tiles(m));
-    L.pinv = c.take<int32_t>(m);
+    L.pinv = sym ? c.take<int32_t>(m) : nullptr;
+    L.pmark = sym ? nullptr : reinterpret_cast<uint8_t *>(c.take<uint32_t>((m + 3) / 4));
     L.qinv = sym ? L.pinv : c.take<int32_t>(n);
     L.cnt = c.take<int32_t>(m);
     L.lists = c.take<uint32_t>(seg_list_words(m));
@@ -46,18 +50,22 @@ PermLayout perm_layout(Carve &c, int64_t m, int64_t n, bool sym) {
 template <typename PT>
 __global__ __launch_bounds__(256) void k_perm_prepare(const PT *__restrict__ arow, const int32_t *__restrict__ p,
                                                      const int32_t *__restrict__ q, int64_t m, int64_t n,
-                                                     int32_t *pinv, int32_t *qinv, int32_t *cnt, DevHdr *hdr) {
-    perm_prepare_tile<PT>(blockIdx.x, arow, p, q, m, n, pinv, qinv, cnt, hdr);
+                                                     int32_t *pinv, int32_t *qinv, int32_t *cnt, DevHdr *hdr,
+                                                     uint8_t *pmark) {
+    perm_prepare_tile<PT>(blockIdx.x, arow, p, q, m, n, pinv, qinv, cnt, hdr, pmark);
 }
 __global__ __launch_bounds__(256) void k_perm_check(int64_t m, int64_t n, const int32_t *__restrict__ pinv,
-                                                   const int32_t *__restrict__ qinv, bool general, DevHdr *hdr) {
-    perm_check_tile(blockIdx.x, m, n, pinv, qinv, general, hdr);
+                                                   const int32_t *__restrict__ qinv, bool general, DevHdr *hdr,
+                                                   const uint8_t *__restrict__ pmark) {
+    perm_check_tile(blockIdx.x, m, n, pinv, qinv, general, hdr, pmark);
 }
 template <typename PT, typename VT>
 __global__ __launch_bounds__(256) void k_perm_pack(const PT *__restrict__ arow, const int32_t *__restrict__ acol,
                                                   const VT *__restrict__ aval, const int32_t *__restrict__ cmap,
                                                   int64_t n, int64_t m, char *__restrict__ slots) {
-    perm_pack_tile<PT, VT>(blockIdx.x, arow, acol, aval, cmap, n, m, slots);
+    __shared__ int32_t lk[4 * PACK_STAGE];
+    __shared__ VT lv[4 * PACK_STAGE];
+    perm_pack_tile<PT, VT>(blockIdx.x, arow, acol, aval, cmap, n, m, slots, lk, lv);
 }
 template <typename PT, typename VT>
 __global__ __launch_bounds__(256) void k_perm_slot_fill(const int32_t *__restrict__ p, const char *__restrict__ slots,
@@ -127,15 +135,16 @@ hp_status_t perm_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
     if (hp_status_t v = validate_input(h, A, L.hdr, "permute plan: A")) return v;
     stage_begin(h);
     hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, scan_tiles(m));
-    if (e == hipSuccess) e = launch_fill_words(s, L.pinv, (size_t)m, 0xFFFFFFFFu);
+    if (e == hipSuccess) e = sym ? launch_fill_words(s, L.pinv, (size_t)m, 0xFFFFFFFFu)
+                                 : launch_fill_words(s, L.pmark, (size_t)(m + 3) / 4, 0u);
     if (e == hipSuccess && !sym) e = launch_fill_words(s, L.qinv, (size_t)n, 0xFFFFFFFFu);
     const int64_t hi = m > n ? m : n;
     const int grid = (int)std::max<int64_t>(1, (hi + 255) / 256);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_perm_prepare<PT>, dim3(grid), dim3(256), 0, s, (const PT *)A->rowptr, p, q,
-                           m, n, L.pinv, L.qinv, L.cnt, L.hdr);
+                           m, n, L.pinv, L.qinv, L.cnt, L.hdr, L.pmark);
         stage_mark(h, "perm.prepare");
-        hipLaunchKernelGGL(k_perm_check, dim3(grid), dim3(256), 0, s, m, n, L.pinv, L.qinv, !sym, L.hdr);
+        hipLaunchKernelGGL(k_perm_check, dim3(grid), dim3(256), 0, s, m, n, L.pinv, L.qinv, !sym, L.hdr, L.pmark);
         stage_mark(h, "perm.check");
         e = hipGetLastError();
     }

@@ -76,7 +76,7 @@ def test_noalloc_equals_plan_exec_two_calls(hp):
 
 def test_noalloc_rejects_inputs_beyond_the_scratch(hp):
     h = hp.handle(0)
-    m = 1 << 21
+    m = 1 << 22
     _say(f"no-alloc permute: {m} rows exceed the fixed scratch array")
     A = synth.CSR(m, m, torch.zeros(m + 1, dtype=torch.int32, device="cuda"),
                   torch.zeros(0, dtype=torch.int32, device="cuda"), torch.zeros(0, dtype=torch.float32, device="cuda"))
