@@ -6,7 +6,9 @@
 // paper's two-pass count / prefix / scatter becomes count -> scan -> fill,
 // with the Build-step sort folded into the fill:
 //   plan : fill -1      pinv, qinv
-//          k_perm_prepare  scatter pinv, qinv; per-output-row counts; range
+//          k_perm_prepare  scatter pinv (marks of p); per-output-row counts;
+//                          range of p
+//          k_perm_qinv     scatter qinv; range of q
 //          k_perm_check    no slot left at -1 (every value occurs once)
 //          scan            rowptr of C + row classes by length
 //   exec : k_perm_pack       rows of <= 4 entries renamed, sorted and packed
@@ -53,6 +55,10 @@ __global__ __launch_bounds__(256) void k_perm_prepare(const PT *__restrict__ aro
                                                      int32_t *pinv, int32_t *qinv, int32_t *cnt, DevHdr *hdr,
                                                      uint8_t *pmark) {
     perm_prepare_tile<PT>(blockIdx.x, arow, p, q, m, n, pinv, qinv, cnt, hdr, pmark);
+}
+__global__ __launch_bounds__(256) void k_perm_qinv(const int32_t *__restrict__ q, int64_t n, int32_t *qinv,
+                                                  DevHdr *hdr) {
+    perm_qinv_tile(blockIdx.x, q, n, qinv, hdr);
 }
 __global__ __launch_bounds__(256) void k_perm_check(int64_t m, int64_t n, const int32_t *__restrict__ pinv,
                                                    const int32_t *__restrict__ qinv, bool general, DevHdr *hdr,
@@ -141,8 +147,11 @@ hp_status_t perm_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
     const int64_t hi = m > n ? m : n;
     const int grid = (int)std::max<int64_t>(1, (hi + 255) / 256);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_perm_prepare<PT>, dim3(grid), dim3(256), 0, s, (const PT *)A->rowptr, p, q,
-                           m, n, L.pinv, L.qinv, L.cnt, L.hdr, L.pmark);
+        hipLaunchKernelGGL(k_perm_prepare<PT>, dim3((unsigned)std::max<int64_t>(1, (m + 255) / 256)), dim3(256), 0,
+                           s, (const PT *)A->rowptr, p, nullptr, m, n, L.pinv, L.qinv, L.cnt, L.hdr, L.pmark);
+        if (!sym)
+            hipLaunchKernelGGL(k_perm_qinv, dim3((unsigned)std::max<int64_t>(1, (n + 255) / 256)), dim3(256), 0, s,
+                               q, n, L.qinv, L.hdr);
         stage_mark(h, "perm.prepare");
         hipLaunchKernelGGL(k_perm_check, dim3(grid), dim3(256), 0, s, m, n, L.pinv, L.qinv, !sym, L.hdr, L.pmark);
         stage_mark(h, "perm.check");

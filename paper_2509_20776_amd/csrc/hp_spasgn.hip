@@ -116,6 +116,13 @@ __global__ __launch_bounds__(256) void k_fused_counts(const int32_t *__restrict_
     }
 }
 
+// qinv[q[j]] = j, a launch of its own (mixing this scatter with the row
+// gathers of k_fused_counts in one kernel is slower than the two apart).
+__global__ __launch_bounds__(256) void k_fused_qinv(const int32_t *__restrict__ q, int64_t n, int32_t *qinv,
+                                                   DevHdr *hdr) {
+    perm::perm_qinv_tile(blockIdx.x, q, n, qinv, hdr);
+}
+
 __global__ __launch_bounds__(256) void k_asg_inv(const int32_t *__restrict__ I, int64_t nI,
                                                 const int32_t *__restrict__ J, int64_t nJ, int64_t m,
                                                 int64_t n, int32_t *rowinv, int32_t *colinv,
@@ -823,8 +830,9 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
         const int64_t hi = std::max(m, n);
         if (nI > 0)
             hipLaunchKernelGGL(k_fused_mark, dim3(gridn(nI)), dim3(256), 0, s, I, nI, m, L.cnt, L.hdr);
-        hipLaunchKernelGGL(k_fused_counts, dim3(gridn(hi)), dim3(256), 0, s, p, sym ? nullptr : q, m, n, L.cnt,
-                           L.pinv, L.qinv, L.cnt_out, L.fflag, L.hdr);
+        hipLaunchKernelGGL(k_fused_counts, dim3(gridn(m)), dim3(256), 0, s, p, nullptr, m, n, L.cnt, L.pinv, L.qinv,
+                           L.cnt_out, L.fflag, L.hdr);
+        if (!sym) hipLaunchKernelGGL(k_fused_qinv, dim3(gridn(n)), dim3(256), 0, s, q, n, L.qinv, L.hdr);
         hipLaunchKernelGGL(k_fused_check, dim3(gridn(hi)), dim3(256), 0, s, m, n, L.pinv, L.qinv, !sym, L.hdr);
         // flagged output rows only: classification mode 4
         e = launch_scan_counts<PT>(s, L.cnt_out, (PT *)C->rowptr, m, L.hdr, 0, L.tiles, 4, L.lists, m, L.fflag);
