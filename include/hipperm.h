@@ -119,8 +119,9 @@ typedef struct {
     int32_t op;               /* which operation produced it (internal check)       */
     int64_t rows_sorted[4];   /* output rows per sort class: <=16, <=64, <=4096, >  */
     int64_t class_elems[4];   /* entries per sort class                             */
-    int64_t aux[4];           /* operation-specific counts (permute: aux[0] is the
-                                 smallest exec workspace exec accepts)              */
+    int64_t aux[4];           /* operation-specific counts (permute: aux[0], fused
+                                 assign-and-permute: aux[3] is the smallest exec
+                                 workspace exec accepts)                            */
 } hp_plan_info_t;
 
 typedef struct hp_handle_s *hp_handle_t;
@@ -265,15 +266,20 @@ hp_status_t hp_spasgn_exec(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, 
  * hp_spasgn) and permutes the result (as hp_permute):
  *   C[i, j] = X[p[i], q[j]],  X = A with A(I, J) = B under op.
  * The paper fuses the two by changing only where entries are sent; here the
- * merge of each source row writes straight to output row pinv[r] with its
- * columns mapped through qinv, and one sort pass orders every output row.
+ * merge of each row of I writes straight to output row pinv[r] with its
+ * columns mapped through qinv and a sort pass orders those rows, while the
+ * output rows outside I pull row p[i] of A (renamed, sorted in registers;
+ * rows of at most 4 entries from fixed row slots packed first, as in
+ * hp_permute_exec, when they hold at least half of the entries outside I).
  * The result is bit-identical to hp_spasgn followed by hp_permute.
  * I, J, op, B: as hp_spasgn.  p, q: as hp_permute (q NULL = symmetric form,
  * needs m == n; exec must get q NULL exactly when plan did).
  * C: caller sets nrows=m, ncols=n, types equal to A's, rowptr (m+1); plan
  * writes rowptr and nnz, exec writes col and val.  ws (size from
  * hp_spasgn_permute_workspace, independent of q) must be kept unchanged
- * from plan to exec; xws holds info->exec_ws_bytes.
+ * from plan to exec; xws holds info->exec_ws_bytes (with the row slots),
+ * or at least info->aux[3] bytes (then exec runs without them; the result
+ * is the same); it may start at any address.
  * Errors: INDEX_RANGE, DUPLICATE_INDEX, NOT_PERMUTATION, SHAPE, OVERFLOW,
  * WORKSPACE, ALIAS. */
 hp_status_t hp_spasgn_permute_workspace(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B,

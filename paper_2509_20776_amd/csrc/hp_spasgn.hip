@@ -33,12 +33,15 @@ constexpr int AS_WCAP = 256;   // A + B entries one wavefront resolves in LDS
 constexpr int64_t ASG_LONG = 512;
 constexpr int64_t ASG_HUGE = 65536;
 
+constexpr int FSUM_SLOTS = 64;   // spread partial sums of k_fused_counts (one 64-byte line each)
+
 struct AsgLayout {
     DevHdr *hdr;
     uint64_t *tiles;
     int32_t *rowinv, *colinv, *cnt;
     int32_t *pinv, *qinv, *cnt_out;   // fused assign-and-permute only
     uint8_t *fflag;                   // fused: 2 merged row, 1 copied row the sort pass pulls, 0 done
+    unsigned long long *fsum;         // fused: spread partial sums of the counts pass
     uint8_t *force;
     uint32_t *lists;
     int32_t *llist;        // rows of B whose A row is too long for the one-thread count
@@ -53,6 +56,7 @@ AsgLayout asg_layout(Carve &c, int64_t m, int64_t n, int64_t nnzA, bool fused = 
     AsgLayout L;
     L.pinv = L.qinv = L.cnt_out = nullptr;
     L.fflag = nullptr;
+    L.fsum = nullptr;
     L.hdr = c.take<DevHdr>(1);
     L.tiles = c.take<uint64_t>(scan_tiles(m));
     L.rowinv = c.take<int32_t>(m + 1);
@@ -69,6 +73,7 @@ AsgLayout asg_layout(Carve &c, int64_t m, int64_t n, int64_t nnzA, bool fused = 
         L.qinv = c.take<int32_t>(n + 1);
         L.cnt_out = c.take<int32_t>(m + 1);
         L.fflag = c.take<uint8_t>(m + 16);
+        L.fsum = c.take<unsigned long long>(FSUM_SLOTS * 2 * 8);
         if (sym) L.qinv = L.pinv;
     }
     return L;
@@ -93,12 +98,14 @@ __global__ __launch_bounds__(256) void k_fused_check(int64_t m, int64_t n, const
 // inverse permutations (pinv[p[i]] = i, qinv[q[i]] = i) and take the row's
 // count.  The sort pass orders the merged rows (rows of I, flag 2) in place
 // and fills rows outside I longer than THREAD_MAX (flag 1) straight from A;
-// shorter rows outside I are sorted by the copy itself.
+// shorter rows outside I (flag 0) are pulled by k_fused_fill_short.
 __global__ __launch_bounds__(256) void k_fused_counts(const int32_t *__restrict__ p, const int32_t *__restrict__ q,
                                                      int64_t m, int64_t n, const int32_t *__restrict__ cnt,
                                                      int32_t *pinv, int32_t *qinv, int32_t *cnt_out,
-                                                     uint8_t *fflag, DevHdr *hdr) {
+                                                     uint8_t *fflag, unsigned long long *fsum, DevHdr *hdr) {
+    __shared__ uint64_t s_part[2][256 / WAVE];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    uint64_t rest = 0, shrt = 0;
     if (i < m) {
         const int32_t r = p[i];
         const bool ok = r >= 0 && r < m;
@@ -107,12 +114,49 @@ __global__ __launch_bounds__(256) void k_fused_counts(const int32_t *__restrict_
         const uint32_t c = ok ? (uint32_t)cnt[r] : 0u;
         const int32_t len = (int32_t)(c & 0x7FFFFFFFu);
         cnt_out[i] = len;
-        fflag[i] = (c >> 31) ? 2 : (len > (int32_t)THREAD_MAX ? 1 : 0);
+        const uint8_t f = (c >> 31) ? 2 : (len > (int32_t)THREAD_MAX ? 1 : 0);
+        fflag[i] = f;
+        if (f != 2) rest = (uint64_t)len;
+        if (f == 0 && len <= 4) shrt = (uint64_t)len;
+    }
+    // entries of the rows outside I and of those with at most 4 entries
+    // (whether the exec's row slots pay): one partial per workgroup, added
+    // into one of FSUM_SLOTS spread slots (a single counter for every
+    // workgroup would serialise them), summed by k_fused_sum
+    rest = wave_sum(rest);
+    shrt = wave_sum(shrt);
+    const int w = threadIdx.x / WAVE;
+    if (lane_id() == 0) {
+        s_part[0][w] = rest;
+        s_part[1][w] = shrt;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        uint64_t t = 0;
+        for (int k = 0; k < 256 / WAVE; k++) t += s_part[threadIdx.x][k];
+        if (t) atomicAdd(&fsum[((blockIdx.x % FSUM_SLOTS) * 2 + threadIdx.x) * 8], (unsigned long long)t);
     }
     if (q && i < n) {
         const int32_t c = q[i];
         if (c < 0 || c >= n) atomicOr(&hdr->err, E_RANGE);
         else qinv[c] = (int32_t)i;
+    }
+}
+
+// hdr->aux[0] and aux[1]: the sums of the spread partials of k_fused_counts
+// (one wavefront).
+__global__ __launch_bounds__(64) void k_fused_sum(const unsigned long long *__restrict__ fsum, DevHdr *hdr) {
+    const int l = threadIdx.x;
+    uint64_t a = 0, b = 0;
+    if (l < FSUM_SLOTS) {
+        a = fsum[(l * 2 + 0) * 8];
+        b = fsum[(l * 2 + 1) * 8];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (l == 0) {
+        hdr->aux[0] = a;
+        hdr->aux[1] = b;
     }
 }
 
@@ -684,6 +728,45 @@ __global__ __launch_bounds__(256) void k_asg_copy_rest(const PT *__restrict__ ar
     }
 }
 
+// Fused form: rows of at most 4 entries renamed, sorted and packed into
+// their row slots (rows of I too; their slots are never read).
+template <typename PT, typename VT>
+__global__ __launch_bounds__(256) void k_fused_pack(const PT *__restrict__ arow, const int32_t *__restrict__ acol,
+                                                   const VT *__restrict__ aval, const int32_t *__restrict__ qinv,
+                                                   int64_t n, int64_t m, char *__restrict__ slots) {
+    __shared__ int32_t lk[4 * perm::PACK_STAGE];
+    __shared__ VT lv[4 * perm::PACK_STAGE];
+    perm::perm_pack_tile<PT, VT>(blockIdx.x, arow, acol, aval, qinv, n, m, slots, lk, lv);
+}
+
+// Fused form, output rows outside I of at most THREAD_MAX entries (flag 0),
+// one lane per output row i in order: row p[i] of A, columns renamed by
+// qinv and sorted, from its row slot (perm_pack_tile, rows of at most 4
+// entries) when slots are given, else straight from A.
+template <typename PT, typename VT>
+__global__ __launch_bounds__(256) void k_fused_fill_short(const int32_t *__restrict__ p,
+                                                         const uint8_t *__restrict__ fflag,
+                                                         const PT *__restrict__ arow, const int32_t *__restrict__ acol,
+                                                         const VT *__restrict__ aval, const int32_t *__restrict__ qinv,
+                                                         int64_t n, const char *__restrict__ slots,
+                                                         const PT *__restrict__ crow, int32_t *ccol, VT *cval,
+                                                         int64_t m, const DevHdr *hdr) {
+    if (hdr->err) return;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m || fflag[i] != 0) return;
+    const int64_t d = crow[i];
+    const int len = (int)(crow[i + 1] - d);
+    if (len == 0) return;
+    if (slots && len <= 4) {
+        perm::perm_slot_fill_tile<PT, VT>(blockIdx.x, p, slots, crow, ccol, cval, m, hdr);
+        return;
+    }
+    const int32_t pr = p[i];
+    const int64_t r = (uint32_t)pr < (uint64_t)m ? (int64_t)pr : 0;   // p was checked by the plan
+    lane_sort_row<VT>(LoadMapped<VT>{acol, aval, OutMap{nullptr, qinv, n}}, (int64_t)arow[r], len, false, ccol + d,
+                      cval + d);
+}
+
 // Rows outside I longer than ASG_LONG, coalesced reads and writes: a
 // workgroup per row of the rlong list, then every workgroup together on each
 // row of the rhuge list.
@@ -768,6 +851,13 @@ hp_status_t asg_check_args(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, 
 
 inline int gridn(int64_t n, int per = 256) { return (int)std::max<int64_t>(1, (n + per - 1) / per); }
 
+// Fused exec workspace with row slots: the sort temporaries, then m slots
+// from the first 256-byte boundary after them, wherever the workspace starts.
+size_t fused_xws_bytes(size_t seg_bytes, int64_t m, int vs) {
+    const size_t sb = vs == 8 ? perm::perm_slot_bytes<uint64_t>() : perm::perm_slot_bytes<uint32_t>();
+    return ((seg_bytes + 255) & ~size_t(255)) + 256 + (((size_t)m * sb + 255) & ~size_t(255));
+}
+
 // Plan of the assignment; with fused, also of the permutation of its result
 // (C = P (A (+) B') Q^T, p non-null, q null for the symmetric form).
 template <typename PT, typename VT>
@@ -830,8 +920,10 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
         const int64_t hi = std::max(m, n);
         if (nI > 0)
             hipLaunchKernelGGL(k_fused_mark, dim3(gridn(nI)), dim3(256), 0, s, I, nI, m, L.cnt, L.hdr);
+        launch_clear_words(s, L.fsum, FSUM_SLOTS * 2 * 8 * 2);
         hipLaunchKernelGGL(k_fused_counts, dim3(gridn(m)), dim3(256), 0, s, p, nullptr, m, n, L.cnt, L.pinv, L.qinv,
-                           L.cnt_out, L.fflag, L.hdr);
+                           L.cnt_out, L.fflag, L.fsum, L.hdr);
+        hipLaunchKernelGGL(k_fused_sum, dim3(1), dim3(64), 0, s, (const unsigned long long *)L.fsum, L.hdr);
         if (!sym) hipLaunchKernelGGL(k_fused_qinv, dim3(gridn(n)), dim3(256), 0, s, q, n, L.qinv, L.hdr);
         hipLaunchKernelGGL(k_fused_check, dim3(gridn(hi)), dim3(256), 0, s, m, n, L.pinv, L.qinv, !sym, L.hdr);
         // flagged output rows only: classification mode 4
@@ -860,6 +952,12 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
         info->aux[1] = (H.flags & F_NOT_RANGE) ? 0 : 1;   // J contiguous
         info->aux[2] = sym ? 1 : 0;
         info->exec_ws_bytes = seg_tmp_bytes(H.bin_elems[BIN_GLOBAL], H.bin_cnt[BIN_GLOBAL], vs, n);
+        // fused: aux[3] the smallest exec workspace; exec_ws_bytes adds the
+        // row slots when rows outside I of at most 4 entries hold at least
+        // half of the entries outside I
+        info->aux[3] = (int64_t)info->exec_ws_bytes;
+        if (fused && H.aux[1] > 0 && 2 * H.aux[1] >= H.aux[0])
+            info->exec_ws_bytes = fused_xws_bytes(info->exec_ws_bytes, m, (int)vs);
     }
     return HP_OK;
 }
@@ -880,8 +978,8 @@ hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
                           : "info is not from hp_spasgn_plan with this operator");
     if (fused && info->aux[2] != (q ? 0 : 1))
         return fail(h, HP_ERR_INVALID_ARG, "q differs in nullness from the plan");
-    if (xws_bytes < info->exec_ws_bytes || (info->exec_ws_bytes && !xws))
-        return fail(h, HP_ERR_WORKSPACE, "spasgn exec workspace too small");
+    const size_t xmin = fused ? (size_t)info->aux[3] : info->exec_ws_bytes;
+    if (xws_bytes < xmin || (xmin && !xws)) return fail(h, HP_ERR_WORKSPACE, "spasgn exec workspace too small");
     if (C->nnz != info->nnz_out) return fail(h, HP_ERR_INVALID_ARG, "C->nnz differs from the plan");
     if (C->nnz > 0 && (!C->col || !C->val)) return fail(h, HP_ERR_INVALID_ARG, "C->col/val is NULL");
     const size_t vs = sizeof(VT), ps = sizeof(PT);
@@ -899,11 +997,20 @@ hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
     const OutMap om{L.pinv, L.qinv, n};   // null maps for the plain assignment
     hipStream_t s = h->stream;
     stage_begin(h);
-    if (fused)
-        hipLaunchKernelGGL((k_asg_copy_rest<PT, VT, true>), dim3(gridn(m)), dim3(256), 0, s, (const PT *)A->rowptr,
-                           A->col, (const VT *)A->val, m, L.rowinv, (const PT *)C->rowptr, C->col, (VT *)C->val,
-                           L.hdr, om);
-    else
+    if (fused) {
+        // row slots when the plan asked for them and the workspace holds them
+        const bool slots = info->exec_ws_bytes > xmin && xws_bytes >= info->exec_ws_bytes;
+        char *sl = nullptr;
+        if (slots) {
+            const uintptr_t at = (uintptr_t)xws + ((xmin + 255) & ~size_t(255));
+            sl = (char *)((at + 255) & ~uintptr_t(255));
+            hipLaunchKernelGGL((k_fused_pack<PT, VT>), dim3(gridn(m)), dim3(256), 0, s, (const PT *)A->rowptr,
+                               A->col, (const VT *)A->val, L.qinv, n, m, sl);
+        }
+        hipLaunchKernelGGL((k_fused_fill_short<PT, VT>), dim3(gridn(m)), dim3(256), 0, s, p, L.fflag,
+                           (const PT *)A->rowptr, A->col, (const VT *)A->val, L.qinv, n, (const char *)sl,
+                           (const PT *)C->rowptr, C->col, (VT *)C->val, m, L.hdr);
+    } else
         hipLaunchKernelGGL((k_asg_copy_rest<PT, VT>), dim3(gridn(m)), dim3(256), 0, s, (const PT *)A->rowptr,
                            A->col, (const VT *)A->val, m, L.rowinv, (const PT *)C->rowptr, C->col, (VT *)C->val,
                            L.hdr, om);

@@ -497,9 +497,13 @@ class Handle:
         return C, ws, info
 
     def spasgn_permute_exec(self, A, B, I, J, p, q, C, ws, info, op="second", xws=None):
+        """Exec of a fused plan.  Without `xws` one of info.exec_ws_bytes is
+        allocated; a caller's `xws` goes to the library as it is (at least
+        info.aux[3] bytes; the row-slot form runs when it holds
+        info.exec_ws_bytes)."""
         self._stream()
         Ac, Bc, Cc = to_csr_t(A), to_csr_t(B), to_csr_t(C)
-        if info.exec_ws_bytes and (xws is None or xws.numel() < info.exec_ws_bytes):
+        if xws is None and info.exec_ws_bytes:
             xws = self._alloc(info.exec_ws_bytes)
         self.check(hp_spasgn_permute_exec(self.h, ctypes.byref(Ac), ctypes.byref(Bc), _idx(I), _idx(J),
                                           self._op(op), _idx(p), _idx(q), ctypes.byref(Cc), _dptr(ws),

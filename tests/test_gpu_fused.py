@@ -46,6 +46,52 @@ def _check(hp, A, B, I, J, p, q, op, what, with_oracle=True):
     return C
 
 
+SHORT = [0, 1, 2, 3, 4, 1, 2, 3, 4, 4, 4, 0, 7, 20]   # rows of <= 4 entries hold most entries
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("ptr,vdt", [(torch.int32, torch.float32), (torch.int64, torch.float64)])
+def test_short_rows_slots_and_pull_agree(hp, op, ptr, vdt):
+    """Rows outside I of at most 4 entries holding most entries: the plan
+    asks for row slots (exec_ws_bytes above aux[3]); exec with them, with
+    them at an address off the 256-byte grid, and with only aux[3] bytes
+    (rows pulled straight from A) all equal the separate calls and the
+    oracle; below aux[3] is refused."""
+    _say(f"fused: short rows, op {op}, ptr {ptr}, val {vdt}")
+    h = hp.Handle(0)
+    m, n = 4000, 3000
+    A = mixed_csr(31, m, n, SHORT, ptr, vdt)
+    rng = np.random.default_rng(32)
+    I = _t(rng.choice(m, 400, replace=False))
+    J = _t(rng.choice(n, 300, replace=False))
+    B = synth.bernoulli_block(400, 300, 0.02, 33, "fsb", ptr, vdt, "cuda")
+    p = synth.randperm(34, m, "cuda")
+    q = synth.randperm(35, n, "cuda")
+    ref = np_csr(h.permute(h.spasgn(A, B, I, J, op), p, q))
+    assert_same(ref, _oracle(A, B, I, J, p, q, op), "separate vs oracle")
+    C, ws, info = h.spasgn_permute_plan(A, B, I, J, p, q, op)
+    assert info.exec_ws_bytes > info.aux[3] >= 0
+    assert_same(np_csr(h.spasgn_permute_exec(A, B, I, J, p, q, C, ws, info, op)), ref, "row slots")
+    C, ws, info = h.spasgn_permute_plan(A, B, I, J, p, q, op)
+    big = torch.empty(info.exec_ws_bytes + 4, dtype=torch.uint8, device="cuda")
+    assert_same(np_csr(h.spasgn_permute_exec(A, B, I, J, p, q, C, ws, info, op, xws=big[4:])), ref,
+                "row slots, offset workspace")
+    C, ws, info = h.spasgn_permute_plan(A, B, I, J, p, q, op)
+    small = torch.empty(max(info.aux[3], 1), dtype=torch.uint8, device="cuda")[: info.aux[3]]
+    assert_same(np_csr(h.spasgn_permute_exec(A, B, I, J, p, q, C, ws, info, op,
+                                             xws=small if info.aux[3] else None)), ref, "pulled from A")
+    if info.aux[3] > 0:
+        with pytest.raises(hp.HPError) as e:
+            h.spasgn_permute_exec(A, B, I, J, p, q, C, ws, info, op, xws=small[:-1])
+        assert e.value.name == "HP_ERR_WORKSPACE"
+    # symmetric form through the slots
+    As = mixed_csr(36, m, m, SHORT, ptr, vdt)
+    Js = _t(rng.choice(m, 300, replace=False))
+    refs = np_csr(h.permute(h.spasgn(As, B, I, Js, op), p))
+    assert_same(np_csr(h.spasgn_permute(As, B, I, Js, p, None, op)), refs, "symmetric, row slots")
+    h.close()
+
+
 @pytest.mark.parametrize("op", OPS)
 @pytest.mark.parametrize("ptr,vdt", [(torch.int32, torch.float32), (torch.int64, torch.float64)])
 def test_rmat_random(hp, op, ptr, vdt):
