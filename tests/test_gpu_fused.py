@@ -88,7 +88,9 @@ def test_short_rows_slots_and_pull_agree(hp, op, ptr, vdt):
     As = mixed_csr(36, m, m, SHORT, ptr, vdt)
     Js = _t(rng.choice(m, 300, replace=False))
     refs = np_csr(h.permute(h.spasgn(As, B, I, Js, op), p))
-    assert_same(np_csr(h.spasgn_permute(As, B, I, Js, p, None, op)), refs, "symmetric, row slots")
+    orefs = _oracle(As, B, I, Js, p, None, op)
+    assert_same(refs, orefs, "symmetric, separate vs oracle")
+    assert_same(np_csr(h.spasgn_permute(As, B, I, Js, p, None, op)), orefs, "symmetric, row slots")
     h.close()
 
 

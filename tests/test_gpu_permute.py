@@ -77,13 +77,15 @@ def test_row_slots_and_inline_fill_agree(hp, ptr, vdt):
     h.close()
 
 
-def test_row_slots_symmetric_and_noalloc(hp):
+@pytest.mark.parametrize("ptr", [torch.int32, torch.int64])
+@pytest.mark.parametrize("vdt", [torch.float32, torch.float64])
+def test_row_slots_symmetric_and_noalloc(hp, ptr, vdt):
     """Symmetric P A P^T through the row slots, and the entry point that
     allocates nothing on the same matrix (it takes the slot form when its
     array holds it)."""
     h = hp.Handle(0)
     m = 6000
-    A = mixed_csr(21, m, m, SHORT, torch.int64, torch.float64)
+    A = mixed_csr(21, m, m, SHORT, ptr, vdt)
     p = synth.randperm(22, m, "cuda")
     ref = oracle.permute(A, p)
     C, ws, info = h.permute_plan(A, p)
