@@ -331,16 +331,19 @@ __global__ void k_batch_reset(uint32_t *ticket, int nticket, DevHdr *hdrs, int64
 }
 
 // One stage: persistent workgroups take tickets until the stage's tiles run
-// out.  q holds the stage's (request, phase) entries in queue order.
+// out.  q holds the stage's (request, phase) entries in queue order.  A
+// ticket is `per` consecutive tiles, run in order (so the tiles of a scan
+// still start in increasing order), which divides the ticket atomics and
+// the searches for the tile's queue entry by `per`.
 template <typename PT, typename VT, int HALF, int STAGE>
 __global__ __launch_bounds__(256) void k_batch_stage(const QEntry *__restrict__ q, int nq, int64_t total,
-                                                    const ReqDev *__restrict__ reqs, uint32_t *ticket) {
+                                                    const ReqDev *__restrict__ reqs, uint32_t *ticket, int per) {
     __shared__ __align__(16) BatchSmem sm;
     __shared__ int64_t s_t;
     __shared__ int32_t s_e;
     for (;;) {
         if (threadIdx.x == 0) {
-            const int64_t t = atomicAdd(ticket, 1u);
+            const int64_t t = (int64_t)atomicAdd(ticket, (uint32_t)per);
             int lo = 0;
             if (t < total) {
                 int hi = nq;   // last entry with first <= t
@@ -354,11 +357,16 @@ __global__ __launch_bounds__(256) void k_batch_stage(const QEntry *__restrict__ 
             s_e = lo;
         }
         __syncthreads();
-        const int64_t t = s_t;
-        if (t >= total) break;
-        const QEntry e = q[s_e];
-        run_tile<PT, VT, HALF, STAGE>(e.phase, t - e.first, reqs[e.req], sm);
-        __syncthreads();   // LDS and s_t are reused by the next tile
+        const int64_t t0 = s_t;
+        if (t0 >= total) break;
+        int e = s_e;
+        const int64_t t1 = t0 + per < total ? t0 + per : total;
+        for (int64_t t = t0; t < t1; t++) {
+            while (e + 1 < nq && q[e + 1].first <= t) e++;
+            const QEntry qe = q[e];
+            run_tile<PT, VT, HALF, STAGE>(qe.phase, t - qe.first, reqs[qe.req], sm);
+            __syncthreads();   // LDS and s_t are reused by the next tile
+        }
     }
 }
 
@@ -633,12 +641,12 @@ static_assert(stages_covered(), "every stage of the table needs a stage kernel")
 
 // The stage kernel compiled for (half, stage); false if there is none.
 template <typename PT, typename VT>
-bool launch_stage(hipStream_t s, int half, int st, int grid, const QEntry *q, int nq, int64_t tot, const ReqDev *reqs,
-                  uint32_t *tk) {
+bool launch_stage(hipStream_t s, int half, int st, int grid, int per, const QEntry *q, int nq, int64_t tot,
+                  const ReqDev *reqs, uint32_t *tk) {
 #define HP_STAGE(H, ST)                                                                                      \
     case H * NST + ST:                                                                                       \
         static_assert(stage_compiled(H, ST), "stage list");                                                  \
-        hipLaunchKernelGGL((k_batch_stage<PT, VT, H, ST>), dim3(grid), dim3(256), 0, s, q, nq, tot, reqs, tk); \
+        hipLaunchKernelGGL((k_batch_stage<PT, VT, H, ST>), dim3(grid), dim3(256), 0, s, q, nq, tot, reqs, tk, per); \
         return true;
     switch (half * NST + st) {
         HP_STAGE(0, 0) HP_STAGE(0, 1) HP_STAGE(0, 2) HP_STAGE(0, 3) HP_STAGE(0, 4) HP_STAGE(0, 5)
@@ -648,8 +656,17 @@ bool launch_stage(hipStream_t s, int half, int st, int grid, const QEntry *q, in
 #undef HP_STAGE
 }
 
+// Launch shape of a half: persistent workgroups per stage and tiles per
+// ticket (the autotuner's two knobs).  Encoded in one int for the tuner
+// cache and the graph key: grid in the low 20 bits, tiles per ticket above.
+struct Shape {
+    int grid, per;
+    int code() const { return grid | (per << 20); }
+    static Shape of(int code) { return Shape{code & 0xFFFFF, (code >> 20) > 0 ? code >> 20 : 1}; }
+};
+
 template <typename PT, typename VT>
-hipError_t launch_half(hp_handle_t h, int half, const Global &g, int n, const Stages &S, int grid) {
+hipError_t launch_half(hp_handle_t h, int half, const Global &g, int n, const Stages &S, Shape shape) {
     hipStream_t s = h->stream;
     const int64_t hw = half == 0 ? (int64_t)n * (int64_t)(sizeof(DevHdr) / 4) : 0;
     uint32_t *tk = g.ticket + half * NST;
@@ -657,32 +674,34 @@ hipError_t launch_half(hp_handle_t h, int half, const Global &g, int n, const St
     for (int st = 0; st < NST; st++) {
         const int64_t tot = S.total[st];
         if (tot <= 0) continue;
-        const int gr = (int)std::min<int64_t>(tot, grid);
+        const int gr = (int)std::min<int64_t>((tot + shape.per - 1) / shape.per, shape.grid);
         if (half == 1 && st == RANK_STAGE)   // one 1024-thread workgroup per CU at most
             hipLaunchKernelGGL((k_batch_rank_stage<PT, VT>), dim3((int)std::min<int64_t>(tot, num_cus(h))),
                                dim3(RANK_THREADS), 0, s, g.queue + S.off[st], S.off[st + 1] - S.off[st], tot,
                                g.reqs, tk + st);
-        else if (!launch_stage<PT, VT>(s, half, st, gr, g.queue + S.off[st], S.off[st + 1] - S.off[st], tot, g.reqs,
-                                       tk + st))
+        else if (!launch_stage<PT, VT>(s, half, st, gr, shape.per, g.queue + S.off[st], S.off[st + 1] - S.off[st],
+                                       tot, g.reqs, tk + st))
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-// Time one half at a few persistent grid sizes and keep the fastest per size
-// class (both halves are idempotent: every run starts from cleared state and
-// rewrites the same outputs).  Each candidate runs TUNE_SAMPLES times and
-// counts with its median.  Choices persist in the tuner cache file
-// (hp_tunecache.hpp), loaded on first use, so a size class is timed once per
-// machine.
+// Time one half at a few launch shapes (persistent grid x tiles per ticket)
+// and keep the fastest per size class (both halves are idempotent: every
+// run starts from cleared state and rewrites the same outputs).  Each
+// candidate runs TUNE_SAMPLES times and counts with its median.  Choices
+// persist in the tuner cache file (hp_tunecache.hpp), loaded on first use,
+// so a size class is timed once per machine.
 constexpr int TUNE_SAMPLES = 3;
+constexpr int DEFAULT_PER = 4;   // tiles per ticket without tuning
 bool g_cache_loaded = false;
 
 template <typename PT, typename VT>
-int tune_grid(hp_handle_t h, int half, const Global &g, int n, const Stages &S, const std::string &key,
-              bool tune) {
+Shape tune_shape(hp_handle_t h, int half, const Global &g, int n, const Stages &S, const std::string &key,
+                 bool tune) {
     const int cus = num_cus(h);
-    if (!tune) return 2 * cus;
+    const Shape fixed{2 * cus, DEFAULT_PER};
+    if (!tune) return fixed;
     const std::string path = tune_cache_path();
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -691,17 +710,19 @@ int tune_grid(hp_handle_t h, int half, const Global &g, int n, const Stages &S, 
             g_cache_loaded = true;
         }
         auto it = g_tuned.find(key);
-        if (it != g_tuned.end()) return it->second;
+        if (it != g_tuned.end()) return Shape::of(it->second);
     }
-    const int cand[4] = {cus, 2 * cus, 4 * cus, 8 * cus};
-    int best = cand[1];
+    std::vector<Shape> cand;
+    for (int gm : {1, 2, 4, 8})
+        for (int per : {1, 4, 16}) cand.push_back(Shape{gm * cus, per});
+    Shape best = fixed;
     if (getenv("HP_NO_TUNE")) return best;
     float best_ms = 1e30f;
     bool ok = true;
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
-    for (int c : cand) {
+    for (const Shape &c : cand) {
         float t[TUNE_SAMPLES];
         for (int r = 0; r < TUNE_SAMPLES && ok; r++) {
             hipEventRecord(e0, h->stream);
@@ -722,8 +743,8 @@ int tune_grid(hp_handle_t h, int half, const Global &g, int n, const Stages &S, 
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     std::lock_guard<std::mutex> lk(g_mu);
-    g_tuned[key] = best;
-    if (ok) tune_cache_store(path, key, best);
+    g_tuned[key] = best.code();
+    if (ok) tune_cache_store(path, key, best.code());
     return best;
 }
 
@@ -733,7 +754,7 @@ std::string size_class(hp_handle_t h, const char *half, int32_t pt, int32_t vt, 
     int lg = 0;
     while ((int64_t(1) << lg) < total) lg++;
     char buf[96];
-    snprintf(buf, sizeof buf, "batch/cu%d/%s/p%d/v%d/t2^%d", num_cus(h), half, pt, vt, lg);
+    snprintf(buf, sizeof buf, "batch2/cu%d/%s/p%d/v%d/t2^%d", num_cus(h), half, pt, vt, lg);
     return buf;
 }
 
@@ -812,9 +833,9 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
         e = hipMemcpyAsync(g.queue, S.q.data(), sizeof(QEntry) * S.q.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_check(h, e, "batch plan upload");
     const std::string key = size_class(h, "plan", reqs[0].A.ptr_type, reqs[0].A.val_type, total);
-    const int grid = tune_grid<PT, VT>(h, 0, g, n, S, key, !(info && (info->flags & HP_BATCH_NO_TUNE)));
+    const Shape shape = tune_shape<PT, VT>(h, 0, g, n, S, key, !(info && (info->flags & HP_BATCH_NO_TUNE)));
     stage_begin(h);
-    e = launch_half<PT, VT>(h, 0, g, n, S, grid);
+    e = launch_half<PT, VT>(h, 0, g, n, S, shape);
     stage_mark(h, "batch.plan");
     BatchState *bsp;
     {
@@ -924,7 +945,7 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
         info->arena_bytes = arena + 256;
         info->nnz_total = nnz_total;
         info->failed = failed;
-        info->grid_plan = grid;
+        info->grid_plan = shape.grid;
         info->tiles_plan = total;
     }
     return HP_OK;
@@ -974,11 +995,11 @@ hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
         e = hipMemcpyAsync(g.queue, S.q.data(), sizeof(QEntry) * S.q.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_check(h, e, "batch exec upload");
     const std::string key = size_class(h, "exec", reqs[0].A.ptr_type, reqs[0].A.val_type, total);
-    const int grid = tune_grid<PT, VT>(h, 1, g, n, S, key, !(info->flags & HP_BATCH_NO_TUNE));
+    const Shape shape = tune_shape<PT, VT>(h, 1, g, n, S, key, !(info->flags & HP_BATCH_NO_TUNE));
     // exec runs from a captured graph, replayed for any batch with the same
     // workspace, arena, grid and stage shapes (queue and request records are
     // uploaded before every launch)
-    GraphKey gk{ws, arena, grid, (int)(ps * 16 + vs), {}, {}, {}};
+    GraphKey gk{ws, arena, shape.code(), (int)(ps * 16 + vs), {}, {}, {}};
     std::copy(S.total, S.total + NST, gk.total.begin());
     std::copy(S.off, S.off + NST + 1, gk.off.begin());
     for (int k = 0; k < n; k++) {
@@ -990,14 +1011,14 @@ hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
     }
     stage_begin(h);
     if (info->flags & HP_BATCH_NO_GRAPH) {
-        e = launch_half<PT, VT>(h, 1, g, n, S, grid);
+        e = launch_half<PT, VT>(h, 1, g, n, S, shape);
         if (e == hipSuccess) {
             if (hp_status_t as = run_assignments(h, reqs, n, devs, bs.asg)) return as;
         }
         stage_mark(h, "batch.exec");
         if (e != hipSuccess) return hip_check(h, e, "batch exec");
         info->tiles_exec = total;
-        info->grid_exec = grid;
+        info->grid_exec = shape.grid;
         return HP_OK;
     }
     GraphEntry *gep;
@@ -1025,7 +1046,7 @@ hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
             h->stream = cs;
             e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                hipError_t le = launch_half<PT, VT>(h, 1, g, n, S, grid);
+                hipError_t le = launch_half<PT, VT>(h, 1, g, n, S, shape);
                 const hp_status_t as = le == hipSuccess ? run_assignments(h, reqs, n, devs, bs.asg) : HP_OK;
                 e = hipStreamEndCapture(cs, &ge.g);
                 if (e == hipSuccess) e = le;
@@ -1045,7 +1066,7 @@ hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
     if (e != hipSuccess) return hip_check(h, e, "batch exec");
     if (info) {
         info->tiles_exec = total;
-        info->grid_exec = grid;
+        info->grid_exec = shape.grid;
     }
     return HP_OK;
 }
