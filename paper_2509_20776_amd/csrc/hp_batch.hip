@@ -713,8 +713,8 @@ Shape tune_shape(hp_handle_t h, int half, const Global &g, int n, const Stages &
         if (it != g_tuned.end()) return Shape::of(it->second);
     }
     std::vector<Shape> cand;
-    for (int gm : {1, 2, 4, 8})
-        for (int per : {1, 4, 16}) cand.push_back(Shape{gm * cus, per});
+    for (int gm : {1, 2, 4, 8, 16})
+        for (int per : {1, 4, 16, 64}) cand.push_back(Shape{gm * cus, per});
     Shape best = fixed;
     if (getenv("HP_NO_TUNE")) return best;
     float best_ms = 1e30f;
