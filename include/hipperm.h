@@ -365,10 +365,10 @@ typedef struct {
     size_t arena_bytes;    /* arena the exec call needs                            */
     int64_t nnz_total;     /* sum of the requests' output nnz                       */
     int32_t failed;        /* requests whose plan status is not HP_OK               */
-    int32_t grid_plan;     /* persistent workgroups per plan stage (autotuned)     */
+    int32_t grid_plan;     /* largest persistent grid of the plan stages (tuned)   */
     int64_t tiles_plan;    /* tiles over all plan stages                            */
     int64_t tiles_exec;    /* tiles over all exec stages (set by exec)              */
-    int32_t grid_exec;     /* persistent workgroups per exec stage (set by exec)    */
+    int32_t grid_exec;     /* largest persistent grid of the exec stages (by exec) */
     int32_t flags;         /* in: HP_BATCH_NO_GRAPH, HP_BATCH_NO_TUNE               */
 } hp_batch_info_t;
 

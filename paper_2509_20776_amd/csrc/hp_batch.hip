@@ -527,13 +527,14 @@ struct BatchState {
 std::map<hp_handle_t, BatchState> g_state;        // last plan per handle
 struct GraphKey {
     const void *ws, *arena;
-    int grid, pv;
+    std::array<int, NST> shape;   // launch shape code per stage
+    int pv;
     std::array<int64_t, NST> total;
     std::array<int, NST + 1> off;
     std::vector<int64_t> asg;    // shapes of the assignment requests' launches
     bool operator<(const GraphKey &o) const {
-        return std::tie(ws, arena, grid, pv, total, off, asg) <
-               std::tie(o.ws, o.arena, o.grid, o.pv, o.total, o.off, o.asg);
+        return std::tie(ws, arena, shape, pv, total, off, asg) <
+               std::tie(o.ws, o.arena, o.shape, o.pv, o.total, o.off, o.asg);
     }
 };
 struct GraphEntry {
@@ -665,43 +666,63 @@ struct Shape {
     static Shape of(int code) { return Shape{code & 0xFFFFF, (code >> 20) > 0 ? code >> 20 : 1}; }
 };
 
+using Shapes = std::array<Shape, NST>;   // one launch shape per stage of a half
+
+int max_grid(const Shapes &s) {
+    int g = 0;
+    for (const Shape &x : s) g = std::max(g, x.grid);
+    return g;
+}
+
+// ev (tuning only): NST + 1 events, ev[st] recorded before stage st is
+// launched (or skipped) and ev[NST] after the last.
 template <typename PT, typename VT>
-hipError_t launch_half(hp_handle_t h, int half, const Global &g, int n, const Stages &S, Shape shape) {
+hipError_t launch_half(hp_handle_t h, int half, const Global &g, int n, const Stages &S, const Shapes &shape,
+                       hipEvent_t *ev = nullptr) {
     hipStream_t s = h->stream;
     const int64_t hw = half == 0 ? (int64_t)n * (int64_t)(sizeof(DevHdr) / 4) : 0;
     uint32_t *tk = g.ticket + half * NST;
     hipLaunchKernelGGL(k_batch_reset, dim3(half == 0 ? 64 : 1), dim3(256), 0, s, tk, NST, g.hdrs, hw);
     for (int st = 0; st < NST; st++) {
+        if (ev) hipEventRecord(ev[st], s);
         const int64_t tot = S.total[st];
         if (tot <= 0) continue;
-        const int gr = (int)std::min<int64_t>((tot + shape.per - 1) / shape.per, shape.grid);
+        const Shape &sh = shape[st];
+        const int gr = (int)std::min<int64_t>((tot + sh.per - 1) / sh.per, sh.grid);
         if (half == 1 && st == RANK_STAGE)   // one 1024-thread workgroup per CU at most
             hipLaunchKernelGGL((k_batch_rank_stage<PT, VT>), dim3((int)std::min<int64_t>(tot, num_cus(h))),
                                dim3(RANK_THREADS), 0, s, g.queue + S.off[st], S.off[st + 1] - S.off[st], tot,
                                g.reqs, tk + st);
-        else if (!launch_stage<PT, VT>(s, half, st, gr, shape.per, g.queue + S.off[st], S.off[st + 1] - S.off[st],
+        else if (!launch_stage<PT, VT>(s, half, st, gr, sh.per, g.queue + S.off[st], S.off[st + 1] - S.off[st],
                                        tot, g.reqs, tk + st))
             return hipErrorInvalidValue;
     }
+    if (ev) hipEventRecord(ev[NST], s);
     return hipGetLastError();
 }
 
 // Time one half at a few launch shapes (persistent grid x tiles per ticket)
-// and keep the fastest per size class (both halves are idempotent: every
-// run starts from cleared state and rewrites the same outputs).  Each
-// candidate runs TUNE_SAMPLES times and counts with its median.  Choices
-// persist in the tuner cache file (hp_tunecache.hpp), loaded on first use,
-// so a size class is timed once per machine.
+// and keep, for every stage, the shape under which that stage ran fastest
+// (stages are separate launches, so each is timed between events and
+// chosen on its own: a scan stage wants one tile per ticket, a streaming
+// stage many).  Both halves are idempotent: every run starts from cleared
+// state and rewrites the same outputs.  Each candidate runs TUNE_SAMPLES
+// times and counts with its median.  Choices persist in the tuner cache
+// file (hp_tunecache.hpp, one entry per stage), loaded on first use, so a
+// size class is timed once per machine.
 constexpr int TUNE_SAMPLES = 3;
 constexpr int DEFAULT_PER = 4;   // tiles per ticket without tuning
 bool g_cache_loaded = false;
 
+std::string stage_key(const std::string &key, int st) { return key + "/s" + std::to_string(st); }
+
 template <typename PT, typename VT>
-Shape tune_shape(hp_handle_t h, int half, const Global &g, int n, const Stages &S, const std::string &key,
-                 bool tune) {
+Shapes tune_shape(hp_handle_t h, int half, const Global &g, int n, const Stages &S, const std::string &key,
+                  bool tune) {
     const int cus = num_cus(h);
-    const Shape fixed{2 * cus, DEFAULT_PER};
-    if (!tune) return fixed;
+    Shapes best;
+    best.fill(Shape{2 * cus, DEFAULT_PER});
+    if (!tune || getenv("HP_NO_TUNE")) return best;
     const std::string path = tune_cache_path();
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -709,42 +730,51 @@ Shape tune_shape(hp_handle_t h, int half, const Global &g, int n, const Stages &
             for (auto &kv : tune_cache_load(path)) g_tuned.emplace(kv.first, kv.second);
             g_cache_loaded = true;
         }
-        auto it = g_tuned.find(key);
-        if (it != g_tuned.end()) return Shape::of(it->second);
+        bool all = true;
+        Shapes got = best;
+        for (int st = 0; st < NST && all; st++) {
+            auto it = g_tuned.find(stage_key(key, st));
+            if (it == g_tuned.end()) all = false;
+            else got[st] = Shape::of(it->second);
+        }
+        if (all) return got;
     }
     std::vector<Shape> cand;
     for (int gm : {1, 2, 4, 8, 16})
         for (int per : {1, 4, 16, 64}) cand.push_back(Shape{gm * cus, per});
-    Shape best = fixed;
-    if (getenv("HP_NO_TUNE")) return best;
-    float best_ms = 1e30f;
+    std::array<float, NST> best_ms;
+    best_ms.fill(1e30f);
     bool ok = true;
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    hipEvent_t ev[NST + 1];
+    for (auto &e : ev) hipEventCreate(&e);
     for (const Shape &c : cand) {
-        float t[TUNE_SAMPLES];
+        Shapes all;
+        all.fill(c);
+        float t[NST][TUNE_SAMPLES];
         for (int r = 0; r < TUNE_SAMPLES && ok; r++) {
-            hipEventRecord(e0, h->stream);
-            launch_half<PT, VT>(h, half, g, n, S, c);
-            hipEventRecord(e1, h->stream);
-            if (wait_event(h, e1, "batch tuner") != HP_OK) ok = false;
-            t[r] = 0;
-            hipEventElapsedTime(&t[r], e0, e1);
+            launch_half<PT, VT>(h, half, g, n, S, all, ev);
+            if (wait_event(h, ev[NST], "batch tuner") != HP_OK) ok = false;
+            for (int st = 0; st < NST; st++) {
+                t[st][r] = 0;
+                hipEventElapsedTime(&t[st][r], ev[st], ev[st + 1]);
+            }
         }
         if (!ok) break;
-        std::sort(t, t + TUNE_SAMPLES);
-        const float med = t[TUNE_SAMPLES / 2];
-        if (med < best_ms) {
-            best_ms = med;
-            best = c;
+        for (int st = 0; st < NST; st++) {
+            std::sort(t[st], t[st] + TUNE_SAMPLES);
+            const float med = t[st][TUNE_SAMPLES / 2];
+            if (med < best_ms[st]) {
+                best_ms[st] = med;
+                best[st] = c;
+            }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    for (auto &e : ev) hipEventDestroy(e);
     std::lock_guard<std::mutex> lk(g_mu);
-    g_tuned[key] = best.code();
-    if (ok) tune_cache_store(path, key, best.code());
+    for (int st = 0; st < NST; st++) {
+        g_tuned[stage_key(key, st)] = best[st].code();
+        if (ok) tune_cache_store(path, stage_key(key, st), best[st].code());
+    }
     return best;
 }
 
@@ -833,7 +863,7 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
         e = hipMemcpyAsync(g.queue, S.q.data(), sizeof(QEntry) * S.q.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_check(h, e, "batch plan upload");
     const std::string key = size_class(h, "plan", reqs[0].A.ptr_type, reqs[0].A.val_type, total);
-    const Shape shape = tune_shape<PT, VT>(h, 0, g, n, S, key, !(info && (info->flags & HP_BATCH_NO_TUNE)));
+    const Shapes shape = tune_shape<PT, VT>(h, 0, g, n, S, key, !(info && (info->flags & HP_BATCH_NO_TUNE)));
     stage_begin(h);
     e = launch_half<PT, VT>(h, 0, g, n, S, shape);
     stage_mark(h, "batch.plan");
@@ -945,7 +975,7 @@ hp_status_t batch_plan_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
         info->arena_bytes = arena + 256;
         info->nnz_total = nnz_total;
         info->failed = failed;
-        info->grid_plan = shape.grid;
+        info->grid_plan = max_grid(shape);
         info->tiles_plan = total;
     }
     return HP_OK;
@@ -995,11 +1025,12 @@ hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
         e = hipMemcpyAsync(g.queue, S.q.data(), sizeof(QEntry) * S.q.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_check(h, e, "batch exec upload");
     const std::string key = size_class(h, "exec", reqs[0].A.ptr_type, reqs[0].A.val_type, total);
-    const Shape shape = tune_shape<PT, VT>(h, 1, g, n, S, key, !(info->flags & HP_BATCH_NO_TUNE));
+    const Shapes shape = tune_shape<PT, VT>(h, 1, g, n, S, key, !(info->flags & HP_BATCH_NO_TUNE));
     // exec runs from a captured graph, replayed for any batch with the same
     // workspace, arena, grid and stage shapes (queue and request records are
     // uploaded before every launch)
-    GraphKey gk{ws, arena, shape.code(), (int)(ps * 16 + vs), {}, {}, {}};
+    GraphKey gk{ws, arena, {}, (int)(ps * 16 + vs), {}, {}, {}};
+    for (int st = 0; st < NST; st++) gk.shape[st] = shape[st].code();
     std::copy(S.total, S.total + NST, gk.total.begin());
     std::copy(S.off, S.off + NST + 1, gk.off.begin());
     for (int k = 0; k < n; k++) {
@@ -1018,7 +1049,7 @@ hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
         stage_mark(h, "batch.exec");
         if (e != hipSuccess) return hip_check(h, e, "batch exec");
         info->tiles_exec = total;
-        info->grid_exec = shape.grid;
+        info->grid_exec = max_grid(shape);
         return HP_OK;
     }
     GraphEntry *gep;
@@ -1066,7 +1097,7 @@ hp_status_t batch_exec_t(hp_handle_t h, hp_request_t *reqs, int n, void *ws, siz
     if (e != hipSuccess) return hip_check(h, e, "batch exec");
     if (info) {
         info->tiles_exec = total;
-        info->grid_exec = shape.grid;
+        info->grid_exec = max_grid(shape);
     }
     return HP_OK;
 }
