@@ -139,24 +139,67 @@ __global__ __launch_bounds__(256) void k_dcsc_buckets(const int32_t *__restrict_
 }
 
 // Bucket index of a doubly compressed matrix with m row ids and nzc stored
-// rows: about four stored rows per bucket, so a lookup is one bucket read
-// and a short search; the index takes O(nzc) memory, never O(m).
+// rows: two to four stored rows per bucket on average, and per bucket a
+// 64-byte record (DcscRec) when the bucket spans at most 256 ids, so a
+// lookup is one line (buckets of more than DX_REC rows, about 1% of them at
+// those averages, go through the bucket bounds and a short search); the
+// index takes O(nzc) memory, never O(m).
 struct DcscPlan {
     int shift = 0;
     int64_t nb = 1;
+    bool rec = false;
     size_t bytes = 0;
 };
 DcscPlan dcsc_plan(int64_t m, int64_t nzc) {
     DcscPlan d;
-    const int64_t target = std::max<int64_t>(1, nzc / 4);
+    const int64_t target = std::max<int64_t>(1, nzc / 2);
     while (((m + (int64_t(1) << d.shift) - 1) >> d.shift) > target) d.shift++;
     d.nb = std::max<int64_t>(1, (m + (int64_t(1) << d.shift) - 1) >> d.shift);
+    d.rec = d.shift <= 8;   // ids within a bucket fit the record's bytes
     Carve c(nullptr);
     c.take<int32_t>(d.nb + 1);
     c.take<int32_t>(d.nb + 1);
     c.take<uint64_t>(scan_tiles(d.nb));
+    if (d.rec) c.take<DcscRec>(d.nb);
     d.bytes = c.size();
     return d;
+}
+
+// Record of bucket b (one thread each): its stored rows' row pointers as
+// offsets from the first, their ids' low bits and their count; DX_REC_OVER
+// for a bucket of more rows, offsets past 32 bits or ids outside the bucket.
+template <typename PT>
+__global__ __launch_bounds__(256) void k_dcsc_rec(const int32_t *__restrict__ jc, const PT *__restrict__ colptr,
+                                                 const int32_t *__restrict__ bstart, int64_t nb, int shift,
+                                                 DcscRec *rec) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int64_t lo = bstart[b], cnt = (int64_t)bstart[b + 1] - lo;
+    uint32_t wd[16] = {};
+    DcscRec rc;
+    __builtin_memcpy(&rc, wd, sizeof(DcscRec));
+    rc.cnt = DX_REC_OVER;
+    if (cnt >= 0 && cnt <= DX_REC) {
+        bool ok = true;
+        rc.base = cnt > 0 ? (int64_t)colptr[lo] : 0;
+        for (int t = 0; t <= (int)cnt && cnt > 0; t++) {
+            const int64_t d = (int64_t)colptr[lo + t] - rc.base;
+            ok &= d >= 0 && d <= (int64_t)UINT32_MAX;
+            rc.off[t] = (uint32_t)d;
+        }
+        for (int t = 0; t < (int)cnt; t++) {
+            const int64_t id = (int64_t)jc[lo + t] - (b << shift);
+            ok &= id >= 0 && id < 256;
+            rc.lid[t] = (uint8_t)id;
+        }
+        if (ok) rc.cnt = (uint32_t)cnt;
+    }
+    __builtin_memcpy(wd, &rc, sizeof(DcscRec));
+    uint4 *q = reinterpret_cast<uint4 *>(rec + b);
+    q[0] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+    q[1] = make_uint4(wd[4], wd[5], wd[6], wd[7]);
+    q[2] = make_uint4(wd[8], wd[9], wd[10], wd[11]);
+    q[3] = make_uint4(wd[12], wd[13], wd[14], wd[15]);
 }
 __global__ __launch_bounds__(SR_BLOCK) void k_spref_count(
     const int32_t *__restrict__ acol, int64_t n, const int64_t *__restrict__ rs,
@@ -241,7 +284,7 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
     stage_begin(h);
     hipError_t e = launch_init_hdr(s, L.hdr, L.tiles, 3 * st);
     if (e == hipSuccess) e = launch_clear_words(s, L.zero, L.nzero);
-    DcscIndex dx{nullptr, 0, nullptr, 0};
+    DcscIndex dx{nullptr, 0, nullptr, 0, nullptr};
     if (dcsc && e == hipSuccess) {
         Carve cx((char *)ws + base);
         int32_t *bcnt = cx.take<int32_t>(dp.nb + 1);
@@ -253,7 +296,14 @@ hp_status_t spref_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *I, int
             hipLaunchKernelGGL(k_dcsc_buckets, dim3(grid1(nzc)), dim3(256), 0, s, jc, nzc, m, dp.shift, bcnt);
         if (e == hipSuccess)
             e = launch_scan_counts<int32_t>(s, bcnt, bstart, dp.nb, L.hdr, 2, btiles, 0, nullptr, 0);
-        dx = DcscIndex{jc, nzc, bstart, dp.shift};
+        DcscRec *rec = nullptr;
+        if (e == hipSuccess && dp.rec) {
+            rec = cx.take<DcscRec>(dp.nb);
+            hipLaunchKernelGGL(k_dcsc_rec<PT>, dim3(grid1(dp.nb)), dim3(256), 0, s, jc, (const PT *)A->rowptr, bstart,
+                               dp.nb, dp.shift, rec);
+            e = hipGetLastError();
+        }
+        dx = DcscIndex{jc, nzc, bstart, dp.shift, rec};
     }
     stage_mark(h, "spref.init");
     if (e == hipSuccess) {

@@ -107,11 +107,27 @@ __device__ inline void spref_jlink_tile(int64_t bid, const int32_t *__restrict__
 // plain row pointers.
 constexpr int DX_PROBE = 8;   // bucket sizes looked up without a search
 
+// rec (optional): one 64-byte record per bucket, so that the lookup of a
+// bucket of at most DX_REC stored rows is one aligned line: the bucket's
+// first row pointer, the row pointers of its rows (and the end) as 32-bit
+// offsets from it, their ids' low bits and their count (DX_REC_OVER: look
+// the bucket up through bstart instead).
+constexpr int DX_REC = 8;
+constexpr uint32_t DX_REC_OVER = 0xFFu;
+struct alignas(64) DcscRec {
+    int64_t base;                  // row pointer of the bucket's first stored row
+    uint32_t off[DX_REC + 1];      // row pointers of its stored rows and the end, minus base
+    uint8_t lid[DX_REC];           // their ids minus the bucket's first id
+    uint32_t cnt;                  // stored rows, or DX_REC_OVER
+};
+static_assert(sizeof(DcscRec) == 64, "a bucket record is one aligned 64-byte line");
+
 struct DcscIndex {
     const int32_t *jc;
     int64_t nzc;
     const int32_t *bstart;
     int shift;
+    const DcscRec *rec;
 };
 
 // sflag (optional): 1 for a selected row with 1..SR_LB entries, else 0.
@@ -122,7 +138,7 @@ struct DcscIndex {
 template <typename PT>
 __device__ inline void spref_rows_tile(int64_t bid, const PT *__restrict__ arow, const int32_t *__restrict__ I,
                                        int64_t nI, int64_t m, int64_t *rs, int32_t *rl, int32_t *ch, uint8_t *big,
-                                       DevHdr *hdr, DcscIndex dx = DcscIndex{nullptr, 0, nullptr, 0},
+                                       DevHdr *hdr, DcscIndex dx = DcscIndex{nullptr, 0, nullptr, 0, nullptr},
                                        int32_t *sflag = nullptr) {
     const int64_t i = bid * 256 + threadIdx.x;
     if (i >= nI) return;
@@ -134,8 +150,29 @@ __device__ inline void spref_rows_tile(int64_t bid, const PT *__restrict__ arow,
         const int32_t *jc = dx.jc;
         const int64_t nzc = dx.nzc;
         const int64_t b = r >> dx.shift;
-        int64_t lo = dx.bstart[b], hi = dx.bstart[b + 1];
-        if (hi - lo <= DX_PROBE) {
+        bool done = false;
+        if (dx.rec) {
+            // the bucket's record: one line, no dependent load
+            const uint4 *q = reinterpret_cast<const uint4 *>(dx.rec + b);
+            const uint4 w0 = q[0], w1 = q[1], w2 = q[2], w3 = q[3];
+            const uint32_t wd[16] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w,
+                                     w2.x, w2.y, w2.z, w2.w, w3.x, w3.y, w3.z, w3.w};
+            DcscRec rc;
+            __builtin_memcpy(&rc, wd, sizeof(DcscRec));
+            if (rc.cnt != DX_REC_OVER) {
+                const uint32_t want = (uint32_t)(r - (b << dx.shift));
+#pragma unroll
+                for (int t = 0; t < DX_REC; t++)
+                    if ((uint32_t)t < rc.cnt && rc.lid[t] == want) {
+                        s = rc.base + rc.off[t];
+                        len = (int64_t)rc.off[t + 1] - (int64_t)rc.off[t];
+                    }
+                done = true;
+            }
+        }
+        int64_t lo = done ? 0 : dx.bstart[b], hi = done ? 0 : dx.bstart[b + 1];
+        if (done) {
+        } else if (hi - lo <= DX_PROBE) {
             // a bucket of at most DX_PROBE stored rows: their ids and row
             // pointers are loaded together (both follow from the bucket
             // bounds), so the lookup is two rounds of memory latency
