@@ -373,7 +373,7 @@ typedef struct {
 } hp_batch_info_t;
 
 #define HP_BATCH_NO_GRAPH 1   /* launch exec directly instead of a captured graph   */
-#define HP_BATCH_NO_TUNE 2    /* fixed grid (2 workgroups per CU), no timing runs    */
+#define HP_BATCH_NO_TUNE 2    /* fixed launch shapes, no timing runs               */
 
 /* Workspace for a batch (tables, counters and rowptrs of every request). */
 hp_status_t hp_batch_workspace(hp_handle_t h, const hp_request_t *reqs, int n, size_t *bytes);

@@ -714,7 +714,10 @@ hipError_t launch_half(hp_handle_t h, int half, const Global &g, int n, const St
 // file (hp_tunecache.hpp, one entry per stage), loaded on first use, so a
 // size class is timed once per machine.
 constexpr int TUNE_SAMPLES = 3;
-constexpr int DEFAULT_PER = 4;   // tiles per ticket without tuning
+// Tiles per ticket without tuning (4 workgroups per CU), per half and
+// stage: what the tuner picked for the 512-request batch (one for the
+// stages holding the rowptr and chunk scans).
+constexpr int DEFAULT_PER[2][NST] = {{16, 4, 4, 1, 1, 1}, {4, 16, 16, 1, 1, 1}};
 bool g_cache_loaded = false;
 
 std::string stage_key(const std::string &key, int st) { return key + "/s" + std::to_string(st); }
@@ -724,7 +727,7 @@ Shapes tune_shape(hp_handle_t h, int half, const Global &g, int n, const Stages 
                   bool tune) {
     const int cus = num_cus(h);
     Shapes best;
-    best.fill(Shape{2 * cus, DEFAULT_PER});
+    for (int st = 0; st < NST; st++) best[st] = Shape{4 * cus, DEFAULT_PER[half][st]};
     if (!tune || getenv("HP_NO_TUNE")) return best;
     const std::string path = tune_cache_path();
     {
