@@ -383,7 +383,9 @@ __device__ void asg_row_I(
         }
         return;
     }
-    if (La + Lb <= AS_WCAP) {
+    // fused form (exec): the sort pass orders the row, so it is written in
+    // any order, straight from memory as for a long row
+    if (La + Lb <= AS_WCAP && (COUNT || om.cmap == nullptr)) {
         for (int x = l; x < La; x += WAVE) sm.a[x] = acol[as + x];
         for (int x = l; x < Lb; x += WAVE) {
             const int32_t cb = bcol[bs + x];
@@ -462,9 +464,10 @@ __device__ void asg_row_I(
         return;
     }
 
-    // Long row: resolve collisions against the rows in global memory, write
-    // surviving A entries then B' entries, and leave the order to the
-    // segmented sort (force flag set by the count pass).
+    // Long row (or any row of the fused form): resolve collisions against
+    // the rows in global memory, write surviving A entries then B' entries,
+    // and leave the order to the segmented sort (force flag set by the
+    // count pass; every merged row of the fused form is sorted).
     const int32_t *ac = acol + as;
     const int32_t *bc = bcol + bs;
     int nak = 0;
@@ -595,7 +598,10 @@ __global__ __launch_bounds__(256) void k_asg_merge_I(
         bad |= t + 1 < Lb && bk[q] >= nxt;
     }
     const bool inc = ((ballot(bad) >> (g * AS_G)) & 0xffffull) == 0;
-    const bool mine = small && inc;
+    // fused form: the sort pass orders every merged row, so any placement
+    // works and the mapped columns need not increase
+    const bool fused = om.cmap != nullptr;
+    const bool mine = small && (inc || fused);
     const bool lng = valid && !mine && x == 0;
     const uint64_t lm = ballot(lng);
     if (lm) {
@@ -626,6 +632,23 @@ __global__ __launch_bounds__(256) void k_asg_merge_I(
     }
     if (!mine) return;
     const int64_t d = crow[om.row(r)];
+    if (fused) {
+        // B' entries in B's order, then the kept A entries in A's order
+#pragma unroll
+        for (int q = 0; q < AS_G; q++) {
+            const int64_t t = q * AS_G + x;
+            if (t < Lb) {
+                ccol[d + t] = om.col(bk[q]);
+                cval[d + t] = bv[q];
+            }
+        }
+        if (x < La && ((kept >> x) & 1u)) {
+            const int64_t pos = d + Lb + __popc(kept & ((1u << x) - 1u));
+            ccol[pos] = om.col(ak);
+            cval[pos] = av;
+        }
+        return;
+    }
     // B' entries, each shifted by the kept A entries with smaller columns
     int below[AS_G];
 #pragma unroll
