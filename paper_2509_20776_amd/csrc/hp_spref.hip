@@ -175,33 +175,37 @@ __global__ __launch_bounds__(256) void k_dcsc_rec(const int32_t *__restrict__ jc
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= nb) return;
     const int64_t lo = bstart[b], cnt = (int64_t)bstart[b + 1] - lo;
-    uint32_t wd[16] = {};
-    DcscRec rc;
-    __builtin_memcpy(&rc, wd, sizeof(DcscRec));
-    rc.cnt = DX_REC_OVER;
-    if (cnt >= 0 && cnt <= DX_REC) {
-        bool ok = true;
-        rc.base = cnt > 0 ? (int64_t)colptr[lo] : 0;
-        for (int t = 0; t <= (int)cnt && cnt > 0; t++) {
-            const int64_t d = (int64_t)colptr[lo + t] - rc.base;
-            ok &= d >= 0 && d <= (int64_t)UINT32_MAX;
-            rc.off[t] = (uint32_t)d;
-        }
-        for (int t = 0; t < (int)cnt; t++) {
-            const int64_t id = (int64_t)jc[lo + t] - (b << shift);
-            ok &= id >= 0 && id < 256;
-            rc.lid[t] = (uint8_t)id;
-        }
-        if (ok) rc.cnt = (uint32_t)cnt;
+    const bool fits = cnt >= 0 && cnt <= DX_REC;
+    // every slot loaded with a constant index (predicated), so nothing
+    // lands in scratch memory
+    const int64_t base = fits && cnt > 0 ? (int64_t)colptr[lo] : 0;
+    uint32_t off[DX_REC + 1], lid[DX_REC];
+    bool ok = fits;
+#pragma unroll
+    for (int t = 0; t <= DX_REC; t++) {
+        const int64_t d = (fits && t <= cnt && cnt > 0) ? (int64_t)colptr[lo + t] - base : 0;
+        ok &= d >= 0 && d <= (int64_t)UINT32_MAX;
+        off[t] = (uint32_t)d;
     }
-    __builtin_memcpy(wd, &rc, sizeof(DcscRec));
+#pragma unroll
+    for (int t = 0; t < DX_REC; t++) {
+        const int64_t id = (fits && t < cnt) ? (int64_t)jc[lo + t] - (b << shift) : 0;
+        ok &= id >= 0 && id < 256;
+        lid[t] = (uint32_t)id & 0xffu;
+    }
+    // the record's 16 words: base (2), off[0..8] (9), lid packed four to a
+    // word (2), cnt (1), two unused (the layout of DcscRec)
+    static_assert(offsetof(DcscRec, off) == 8 && offsetof(DcscRec, lid) == 44 && offsetof(DcscRec, cnt) == 52,
+                  "record layout");
+    const uint32_t l0 = lid[0] | (lid[1] << 8) | (lid[2] << 16) | (lid[3] << 24);
+    const uint32_t l1 = lid[4] | (lid[5] << 8) | (lid[6] << 16) | (lid[7] << 24);
+    const uint32_t c = ok ? (uint32_t)cnt : DX_REC_OVER;
     uint4 *q = reinterpret_cast<uint4 *>(rec + b);
-    q[0] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
-    q[1] = make_uint4(wd[4], wd[5], wd[6], wd[7]);
-    q[2] = make_uint4(wd[8], wd[9], wd[10], wd[11]);
-    q[3] = make_uint4(wd[12], wd[13], wd[14], wd[15]);
-}
-__global__ __launch_bounds__(SR_BLOCK) void k_spref_count(
+    q[0] = make_uint4((uint32_t)base, (uint32_t)((uint64_t)base >> 32), off[0], off[1]);
+    q[1] = make_uint4(off[2], off[3], off[4], off[5]);
+    q[2] = make_uint4(off[6], off[7], off[8], l0);
+    q[3] = make_uint4(l1, c, 0u, 0u);
+}__global__ __launch_bounds__(SR_BLOCK) void k_spref_count(
     const int32_t *__restrict__ acol, int64_t n, const int64_t *__restrict__ rs,
     const int32_t *__restrict__ rl, const int64_t *__restrict__ cp, int64_t nI, int64_t ngb,
     const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos, const int32_t *__restrict__ Dn,
