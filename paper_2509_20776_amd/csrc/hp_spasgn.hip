@@ -26,6 +26,11 @@ using namespace hp;
 namespace {
 
 constexpr int AS_WCAP = 256;   // A + B entries one wavefront resolves in LDS
+// Rows of I whose mapped B columns do not increase (J out of order) are
+// placed by counting, O(L) per entry, only up to this many A + B entries;
+// longer ones are written unsorted and ordered by the class sorts (the
+// count pass flags them).
+constexpr int64_t AS_RANK_MAX = 64;
 // Rows outside I longer than ASG_LONG are not copied by the wavefront that
 // owns their 64-row group (hub rows at neighbouring ids would serialise on
 // it) but by a workgroup of their own, and rows longer than ASG_HUGE by
@@ -246,10 +251,12 @@ template <typename PT>
 __global__ __launch_bounds__(256) void k_asg_count_I(const PT *__restrict__ arow, const int32_t *__restrict__ acol,
                                                     const PT *__restrict__ brow, const int32_t *__restrict__ bcol,
                                                     const int32_t *__restrict__ I, int64_t nI,
+                                                    const int32_t *__restrict__ J, int64_t nJ,
                                                     const int32_t *__restrict__ colinv, int64_t n, int op,
                                                     int32_t *cnt, uint8_t *force, int32_t *llist, uint32_t *lcount,
                                                     const DevHdr *hdr) {
     if (hdr->err) return;
+    const bool jrange = !(ld_agent(&hdr->flags) & F_NOT_RANGE);   // set by the table pass
     const int l = lane_id(), g = l / AS_G, x = l % AS_G;
     const int64_t i = (int64_t)blockIdx.x * (256 / AS_G) + (threadIdx.x / WAVE) * (WAVE / AS_G) + g;
     const bool valid = i < nI;
@@ -290,9 +297,26 @@ __global__ __launch_bounds__(256) void k_asg_count_I(const PT *__restrict__ arow
         const bool kept = ja < 0 || (!replace && !ghit);
         nak += (small && a < La && kept) ? 1 : 0;
     }
+    // do the mapped B columns increase along the row (t order: q major,
+    // lane minor)?  Always when J is a range.
+    bool bad = false;
+    if (!jrange) {
+        int32_t bk[AS_G];
+#pragma unroll
+        for (int q = 0; q < AS_G; q++) bk[q] = bc[q] == INT32_MIN ? INT32_MAX : J[clampc(bc[q], nJ)];
+#pragma unroll
+        for (int q = 0; q < AS_G; q++) {
+            const int32_t nx_same = __shfl_down(bk[q], 1, AS_G);
+            const int32_t nx_wrap = q + 1 < AS_G ? __shfl(bk[q + 1], g * AS_G, WAVE) : INT32_MAX;
+            const int32_t nxt = x < AS_G - 1 ? nx_same : nx_wrap;
+            const int64_t t = q * AS_G + x;
+            bad |= t + 1 < Lb && bk[q] >= nxt;
+        }
+    }
+    const bool inc = ((ballot(bad) >> (g * AS_G)) & 0xffffull) == 0;
     if (small && x == 0) {
         cnt[r] = (int32_t)(nak + Lb);
-        force[r] = La + Lb > AS_WCAP ? 1 : 0;
+        force[r] = (La + Lb > AS_WCAP || (!inc && La + Lb > AS_RANK_MAX)) ? 1 : 0;
     }
 }
 
@@ -363,7 +387,7 @@ __device__ void asg_row_I(
     const int64_t bs = brow[i], Lb = brow[i + 1] - bs;
     const bool replace = op == HP_OP_REPLACE, plus = op == HP_OP_PLUS;
 
-    if (COUNT && La * 16 <= Lb) {
+    if (COUNT && La * 16 <= Lb && La + Lb > AS_WCAP) {
         // few A entries against a long B row: binary-search B in memory
         // instead of staging it (the count pass then reads little of B)
         const int32_t *bc = bcol + bs;
@@ -390,7 +414,7 @@ __device__ void asg_row_I(
         for (int x = l; x < Lb; x += WAVE) {
             const int32_t cb = bcol[bs + x];
             sm.b[x] = cb;
-            if (!COUNT) sm.k[x] = J[clampc(cb, nJ)];
+            sm.k[x] = J[clampc(cb, nJ)];
         }
         __builtin_amdgcn_wave_barrier();
         // surviving A entries, compacted in A order
@@ -406,68 +430,73 @@ __device__ void asg_row_I(
             if (!COUNT && kept) sm.ak[nak + __popcll(msk & lanemask_lt())] = sm.a[a];
             nak += __popcll(msk);
         }
-        if (COUNT) {
-            if (l == 0) {
-                cnt[r] = (int32_t)(nak + Lb);
-                force[r] = 0;
-            }
-            return;
-        }
-        __builtin_amdgcn_wave_barrier();
         bool inc = true;
         for (int t0 = 0; t0 + 1 < Lb; t0 += WAVE) {
             const int t = t0 + l;
             const bool bad = t + 1 < Lb && sm.k[t] >= sm.k[t + 1];
             inc = inc && ballot(bad) == 0;
         }
-        const int64_t d = crow[om.row(r)];
-        const int L = nak + (int)Lb;
-        if (!inc) {
-            for (int x = l; x < nak; x += WAVE) sm.o[x] = sm.ak[x];
-            for (int x = l; x < Lb; x += WAVE) sm.o[nak + x] = sm.k[x];
-            __builtin_amdgcn_wave_barrier();
-        }
-        // surviving A entries
-        int rank = 0;
-        for (int a0 = 0; a0 < La; a0 += WAVE) {
-            const int a = a0 + l;
-            bool kept = false;
-            int32_t key = 0;
-            if (a < La) {
-                key = sm.a[a];
-                const int32_t jb = colinv[clampc(key, n)];
-                kept = replace ? jb < 0 : (jb < 0 || find_n(sm.b, Lb, jb) < 0);
+        // a long row out of J's order is left to the class sorts
+        const bool unsorted = !inc && La + Lb > AS_RANK_MAX;
+        if (COUNT) {
+            if (l == 0) {
+                cnt[r] = (int32_t)(nak + Lb);
+                force[r] = unsorted ? 1 : 0;
             }
-            const uint64_t msk = ballot(kept);
-            if (kept) {
-                const int own = rank + __popcll(msk & lanemask_lt());
-                int pos;
-                if (inc) pos = own + lower_bound_n(sm.k, Lb, key);
-                else pos = count_less(sm.o, L, key);
+            return;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (!unsorted) {
+            const int64_t d = crow[om.row(r)];
+            const int L = nak + (int)Lb;
+            if (!inc) {
+                for (int x = l; x < nak; x += WAVE) sm.o[x] = sm.ak[x];
+                for (int x = l; x < Lb; x += WAVE) sm.o[nak + x] = sm.k[x];
+                __builtin_amdgcn_wave_barrier();
+            }
+            // surviving A entries
+            int rank = 0;
+            for (int a0 = 0; a0 < La; a0 += WAVE) {
+                const int a = a0 + l;
+                bool kept = false;
+                int32_t key = 0;
+                if (a < La) {
+                    key = sm.a[a];
+                    const int32_t jb = colinv[clampc(key, n)];
+                    kept = replace ? jb < 0 : (jb < 0 || find_n(sm.b, Lb, jb) < 0);
+                }
+                const uint64_t msk = ballot(kept);
+                if (kept) {
+                    const int own = rank + __popcll(msk & lanemask_lt());
+                    int pos;
+                    if (inc) pos = own + lower_bound_n(sm.k, Lb, key);
+                    else pos = count_less(sm.o, L, key);
+                    ccol[d + pos] = om.col(key);
+                    cval[d + pos] = aval[as + a];
+                }
+                rank += __popcll(msk);
+            }
+            // B' entries (values combined with A's where both exist for PLUS)
+            for (int t = l; t < Lb; t += WAVE) {
+                const int32_t key = sm.k[t];
+                VT v = bval[bs + t];
+                if (plus) {
+                    const int64_t p = find_n(sm.a, La, key);
+                    if (p >= 0) v = vadd(aval[as + p], v);
+                }
+                const int pos = inc ? t + lower_bound_n(sm.ak, nak, key) : count_less(sm.o, L, key);
                 ccol[d + pos] = om.col(key);
-                cval[d + pos] = aval[as + a];
+                cval[d + pos] = v;
             }
-            rank += __popcll(msk);
+            return;
         }
-        // B' entries (values combined with A's where both exist for PLUS)
-        for (int t = l; t < Lb; t += WAVE) {
-            const int32_t key = sm.k[t];
-            VT v = bval[bs + t];
-            if (plus) {
-                const int64_t p = find_n(sm.a, La, key);
-                if (p >= 0) v = vadd(aval[as + p], v);
-            }
-            const int pos = inc ? t + lower_bound_n(sm.ak, nak, key) : count_less(sm.o, L, key);
-            ccol[d + pos] = om.col(key);
-            cval[d + pos] = v;
-        }
-        return;
     }
 
-    // Long row (or any row of the fused form): resolve collisions against
-    // the rows in global memory, write surviving A entries then B' entries,
-    // and leave the order to the segmented sort (force flag set by the
-    // count pass; every merged row of the fused form is sorted).
+    // Long row, a row out of J's order longer than AS_RANK_MAX, or any row
+    // of the fused form: resolve collisions against the rows in global
+    // memory, write surviving A entries then B' entries, and leave the order
+    // to the segmented sort (force flag set by the count pass; every merged
+    // row of the fused form is sorted).
     const int32_t *ac = acol + as;
     const int32_t *bc = bcol + bs;
     int nak = 0;
@@ -927,9 +956,9 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
         hipLaunchKernelGGL(k_asg_count_rest<PT>, dim3(gridn(m)), dim3(256), 0, s, (const PT *)A->rowptr, m,
                            L.rowinv, L.cnt, L.force, L.rlong, L.rhuge, L.lcount + 1, L.hdr);
         if (nI > 0) {
-            hipLaunchKernelGGL(k_asg_count_I<PT>, dim3(gridn(nI, 256 / AS_G)), dim3(256), 0, s, (const PT *)A->rowptr, A->col,
-                               (const PT *)B->rowptr, B->col, I, nI, L.colinv, n, (int)op, L.cnt, L.force, L.llist,
-                               L.lcount, L.hdr);
+            hipLaunchKernelGGL(k_asg_count_I<PT>, dim3(gridn(nI, 256 / AS_G)), dim3(256), 0, s,
+                               (const PT *)A->rowptr, A->col, (const PT *)B->rowptr, B->col, I, nI, J, nJ, L.colinv,
+                               n, (int)op, L.cnt, L.force, L.llist, L.lcount, L.hdr);
             hipLaunchKernelGGL((k_asg_rows_list<PT, VT, true>), dim3((unsigned)std::min<int64_t>(gridn(nI, 4), 1024)),
                                dim3(256), 0, s, (const PT *)A->rowptr, A->col, (const VT *)A->val,
                                (const PT *)B->rowptr, B->col, (const VT *)B->val, I, J, nJ, L.colinv, n, (int)op,

@@ -52,6 +52,28 @@ def test_rmat_random_index_sets(hp, op, ptr, vdt):
 
 
 @pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("ptr,vdt", [(torch.int32, torch.float32), (torch.int64, torch.float64)])
+def test_rows_of_I_out_of_J_order(hp, op, ptr, vdt):
+    """J unsorted, so the mapped B columns of a row of I do not increase:
+    rows of up to 64 A + B entries are placed by counting, longer ones up to
+    256 are written unsorted and ordered by the class sorts, longer still go
+    the long-row way; also through the fused form."""
+    m, n = 900, 2000
+    A = mixed_csr(81, m, n, [0, 3, 12, 16, 40, 90, 150, 230, 400], ptr, vdt)
+    rng = np.random.default_rng(82)
+    nI, nJ = 300, 1200
+    I = _t(rng.choice(m, nI, replace=False))
+    J = _t(rng.choice(n, nJ, replace=False))                         # unsorted
+    B = mixed_csr(83, nI, nJ, [0, 2, 10, 30, 60, 120, 200, 250], ptr, vdt)
+    ref = oracle.spasgn(A, B, I, J, op)
+    assert_same(np_csr(hp.spasgn(A, B, I, J, op)), ref, f"J out of order, {op}")
+    p = synth.randperm(84, m, "cuda")
+    q = synth.randperm(85, n, "cuda")
+    Cf = np_csr(hp.spasgn_permute(A, B, I, J, p, q, op))
+    assert_same(Cf, oracle.permute((m, n) + tuple(ref), p, q), f"fused, J out of order, {op}")
+
+
+@pytest.mark.parametrize("op", OPS)
 def test_long_rows_fallback(hp, op):
     m, n = 300, 6000
     A = mixed_csr(31, m, n, [0, 3, 100, 250, 700, 5000])
