@@ -327,10 +327,12 @@ hp_status_t hp_block_nnz(hp_handle_t h, const hp_csr_t *A, int32_t gr, int32_t g
  * workgroups, followed by one readback of all output sizes.  The exec half
  * (fill and row sort of every request) is a second sequence of stage
  * launches, captured once in a hipGraph and replayed for any later batch
- * with the same workspace, arena, grid and stage shapes.  Stream order
- * between the stages is the only inter-tile dependency.  The number of
- * persistent workgroups is picked per size class by timing candidates the
- * first time the class is seen (the halves are idempotent).  Assignment
+ * with the same workspace, arena, launch shapes and stage shapes.  Stream
+ * order between the stages is the only inter-tile dependency.  Each stage's
+ * launch shape (persistent workgroups, and consecutive tiles a workgroup
+ * takes per ticket) is picked per size class by timing candidates the
+ * first time the class is seen (the halves are idempotent; choices persist
+ * in a cache file: HP_TUNE_CACHE, else ~/.cache/hipperm).  Assignment
  * requests (streaming merges of whole matrices) run the assignment's own
  * plan and exec kernels on the same stream, inside the same captured graph
  * for exec; their row pointers and plan tables live in the batch workspace.
