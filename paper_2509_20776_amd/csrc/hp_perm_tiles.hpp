@@ -153,9 +153,25 @@ __device__ inline void perm_pack_tile(int64_t bid, const PT *__restrict__ arow, 
     int32_t *wk = lk + w * PACK_STAGE;
     VT *wv = lv + w * PACK_STAGE;
     if (staged) {
-        for (int64_t k = s0 + l; k < s1; k += WAVE) {
-            wk[k - s0] = cmap[clampc(acol[k], n)];
-            wv[k - s0] = aval[k];
+        // all column and value loads of the wavefront in one round, then all
+        // renaming lookups in a second (a loop over the entries would make
+        // each lookup wait on its own column load)
+        static_assert(PACK_STAGE % WAVE == 0, "whole 64-wide rows of staged entries");
+        int32_t ck[PACK_STAGE / WAVE];
+        VT cv[PACK_STAGE / WAVE];
+#pragma unroll
+        for (int u = 0; u < PACK_STAGE / WAVE; u++) {
+            const int64_t k = s0 + u * WAVE + l;
+            ck[u] = k < s1 ? acol[k] : 0;
+            cv[u] = k < s1 ? aval[k] : VT(0);
+        }
+#pragma unroll
+        for (int u = 0; u < PACK_STAGE / WAVE; u++) {
+            const int64_t k = s0 + u * WAVE + l;
+            if (k < s1) {
+                wk[k - s0] = cmap[clampc(ck[u], n)];
+                wv[k - s0] = cv[u];
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
