@@ -304,8 +304,9 @@ size_t scan_tiles(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) 
 constexpr int64_t SCAN_ONEPASS_TILES = 256;
 
 // Four wavefronts per SIMD (at most 128 VGPRs): left alone the compiler
-// keeps all 16 staged values of a lane in flight and drops to two.
-template <typename PT>
+// keeps all 16 staged values of a lane in flight and drops to two.  CLS
+// false: the plain scan (no class lists), a smaller kernel.
+template <typename PT, bool CLS>
 __global__ __launch_bounds__(SCAN_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_scan_counts(
     const int32_t *__restrict__ cnt, PT *__restrict__ out, int64_t n, DevHdr *hdr, int slot,
     uint64_t *tile_state, int classify, uint32_t *lists, int64_t cap, uint64_t *goff,
@@ -314,8 +315,8 @@ __global__ __launch_bounds__(SCAN_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
     __shared__ uint32_t s_tile;
     if (threadIdx.x == 0) s_tile = atomicAdd(&hdr->ticket[slot], 1u);
     __syncthreads();
-    scan_counts_tile<PT>(s_tile, sm, cnt, out, n, hdr, slot, tile_state, classify, lists, cap, goff, force,
-                         nmslots);
+    scan_counts_tile<PT, CLS>(s_tile, sm, cnt, out, n, hdr, slot, tile_state, classify, lists, cap, goff, force,
+                              nmslots);
 }
 
 // Three-pass form for long scans: tile sums, one workgroup scanning them,
@@ -333,14 +334,14 @@ __global__ __launch_bounds__(PSCAN_BLOCK) void k_scan_partials(uint64_t *partial
     scan_partials_block(s_wave, partial, ntiles);
 }
 
-template <typename PT>
+template <typename PT, bool CLS>
 __global__ __launch_bounds__(SCAN_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_scan_down(
     const int32_t *__restrict__ cnt, PT *__restrict__ out, int64_t n, DevHdr *hdr, int slot,
     const uint64_t *__restrict__ prefix, int classify, uint32_t *lists, int64_t cap, uint64_t *goff,
     const uint8_t *__restrict__ force, const uint32_t *__restrict__ nmslots) {
     __shared__ ScanSmem sm;
-    scan_counts_tile<PT>(blockIdx.x, sm, cnt, out, n, hdr, slot, nullptr, classify, lists, cap, goff, force,
-                         nmslots, prefix);
+    scan_counts_tile<PT, CLS>(blockIdx.x, sm, cnt, out, n, hdr, slot, nullptr, classify, lists, cap, goff, force,
+                              nmslots, prefix);
 }
 
 template <typename PT>
@@ -365,12 +366,14 @@ hipError_t launch_scan_counts(hipStream_t s, const int32_t *cnt, PT *out, int64_
         // tile_state (scan_tiles(n) words) holds the tile sums, then prefixes
         hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, cnt, n, tile_state);
         hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(PSCAN_BLOCK), 0, s, tile_state, tiles);
-        hipLaunchKernelGGL(k_scan_down<PT>, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, cnt, out, n, hdr, slot,
-                           (const uint64_t *)tile_state, classify, bin_lists, bin_cap, goff, force, nmslots);
+        auto down = classify ? k_scan_down<PT, true> : k_scan_down<PT, false>;
+        hipLaunchKernelGGL(down, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, cnt, out, n, hdr, slot, (const uint64_t *)tile_state, classify,
+                           bin_lists, bin_cap, goff, force, nmslots);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_scan_counts<PT>, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, cnt, out, n,
-                       hdr, slot, tile_state, classify, bin_lists, bin_cap, goff, force, nmslots);
+    auto one = classify ? k_scan_counts<PT, true> : k_scan_counts<PT, false>;
+    hipLaunchKernelGGL(one, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, cnt, out, n, hdr, slot, tile_state, classify, bin_lists, bin_cap, goff,
+                       force, nmslots);
     return hipGetLastError();
 }
 

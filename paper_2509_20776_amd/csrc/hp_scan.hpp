@@ -60,16 +60,20 @@ struct ScanSmem {
     uint32_t bc[NBINS], bbase[NBINS];
     unsigned long long ge, gbase;
     int all;
-    uint64_t stage[SCAN_BLOCK / WAVE][SCAN_STAGE];
+    // 32-bit words: the counts on the way in, the outputs on the way out
+    // (a 64-bit output in two rounds, low then high words), so a block
+    // holds 17 KB of LDS
+    uint32_t stage[SCAN_BLOCK / WAVE][SCAN_STAGE];
 };
 
 // One tile of the exclusive scan of n int32 counts into out (PT, n+1
 // entries).  Single pass (tile_prefix == nullptr): tiles must be started in
 // increasing order (the caller's ticket) so that a tile only waits on
 // running tiles.  Second pass of the three-pass form: tile_prefix[tile] is
-// the tile's exclusive prefix, and no tile waits.
-template <typename PT>
-__device__ void scan_counts_tile(int64_t tile, ScanSmem &sm, const int32_t *__restrict__ cnt,
+// the tile's exclusive prefix, and no tile waits.  CLS false: classify is
+// 0 and the class-list code is left out of the kernel.
+template <typename PT, bool CLS = true>
+__device__ __forceinline__ void scan_counts_tile(int64_t tile, ScanSmem &sm, const int32_t *__restrict__ cnt,
                                  PT *__restrict__ out, int64_t n, DevHdr *hdr, int slot,
                                  uint64_t *tile_state, int classify, uint32_t *lists, int64_t cap,
                                  uint64_t *goff, const uint8_t *__restrict__ force,
@@ -96,7 +100,7 @@ __device__ void scan_counts_tile(int64_t tile, ScanSmem &sm, const int32_t *__re
     // stores go 64-wide in index order through the wavefront's staging area.
     const int w = threadIdx.x / WAVE, l = lane_id();
     const int64_t seg = tile * SCAN_TILE + (int64_t)w * SCAN_SEG;
-    uint32_t *st32 = reinterpret_cast<uint32_t *>(sm.stage[w]);
+    uint32_t *st32 = sm.stage[w];
     const int rowb = l + (l >> 4), lanb = 17 * l;
     if (seg + SCAN_SEG <= n) {
         const int32_t *src = cnt + seg + l;
@@ -163,23 +167,32 @@ __device__ void scan_counts_tile(int64_t tile, ScanSmem &sm, const int32_t *__re
     }
     __syncthreads();
     {
-        uint64_t *st64 = sm.stage[w];
-        uint64_t run = s_excl + texcl;
+        // the outputs' 32-bit words, transposed through LDS and stored
+        // 64-wide in index order: all of an int32 output, or the low then
+        // the high words of an int64 one
+        const uint64_t run0 = s_excl + texcl;
+        uint32_t *dst32 = reinterpret_cast<uint32_t *>(out);
+        constexpr int NW = sizeof(PT) / 4;
 #pragma unroll
-        for (int k = 0; k < SCAN_ITEMS; k++) {
-            st64[lanb + k] = run;
-            run += (uint32_t)v[k];
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (seg + SCAN_SEG <= n) {
-            PT *dst = out + seg + l;
+        for (int hw = 0; hw < NW; hw++) {
+            uint64_t run = run0;
 #pragma unroll
-            for (int k = 0; k < SCAN_ITEMS; k++) dst[k * WAVE] = (PT)st64[rowb + 68 * k];
-        } else {
             for (int k = 0; k < SCAN_ITEMS; k++) {
-                const int64_t idx = seg + k * WAVE + l;
-                if (idx < n) out[idx] = (PT)st64[rowb + 68 * k];
+                st32[lanb + k] = (uint32_t)(run >> (32 * hw));
+                run += (uint32_t)v[k];
             }
+            __builtin_amdgcn_wave_barrier();
+            if (seg + SCAN_SEG <= n) {
+                uint32_t *dst = dst32 + (seg + l) * NW + hw;
+#pragma unroll
+                for (int k = 0; k < SCAN_ITEMS; k++) dst[k * WAVE * NW] = st32[rowb + 68 * k];
+            } else {
+                for (int k = 0; k < SCAN_ITEMS; k++) {
+                    const int64_t idx = seg + k * WAVE + l;
+                    if (idx < n) dst32[idx * NW + hw] = st32[rowb + 68 * k];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();   // the reads above before the next round's writes
         }
     }
     const int64_t last_base = (n - 1) / SCAN_TILE;
@@ -190,26 +203,32 @@ __device__ void scan_counts_tile(int64_t tile, ScanSmem &sm, const int32_t *__re
         if (sizeof(PT) == 4 && total > (uint64_t)INT32_MAX) raise_err(hdr, E_OVERFLOW);
         if (classify == 3 && s_all) atomicOr(&hdr->flags, F_NOT_MONOTONE);
     }
-    if (classify) {
-        // block-aggregated append to the class lists: LDS offsets, then a
-        // handful of global atomics per tile
+    if (CLS && classify) {
+        // block-aggregated append to the class lists: each lane counts its
+        // 16 rows per class, takes one LDS offset per class (and one for
+        // the GLOBAL entries), the block one global offset per class; then
+        // the lane recomputes its rows' classes and appends them in order
+        // (no per-row offsets kept in registers)
         const bool all = s_all != 0;
-        int bin[SCAN_ITEMS];
-        uint32_t off[SCAN_ITEMS];
-        unsigned long long eoff[SCAN_ITEMS];
+        uint32_t flags = 0;   // bit k: force[base + k] (modes 3 and 4)
+        if (classify == 3 || classify == 4) {
+#pragma unroll
+            for (int k = 0; k < SCAN_ITEMS; k++)
+                if (base + k < n && force[base + k] != 0) flags |= 1u << k;
+        }
+        uint32_t lc[NBINS] = {0, 0, 0, 0};
+        unsigned long long lge = 0;
 #pragma unroll
         for (int k = 0; k < SCAN_ITEMS; k++) {
-            const int64_t idx = base + k;
-            const bool valid = idx < n;
-            const bool fl = (classify == 3 || classify == 4) && valid ? force[idx] != 0 : false;
-            bin[k] = valid ? class_of(v[k], classify, all, fl) : -1;
-            off[k] = 0;
-            eoff[k] = 0;
-            if (bin[k] >= 0) {
-                off[k] = atomicAdd(&s_bc[bin[k]], 1u);
-                if (bin[k] == BIN_GLOBAL) eoff[k] = atomicAdd(&s_ge, (unsigned long long)(uint32_t)v[k]);
-            }
+            const int b = base + k < n ? class_of(v[k], classify, all, (flags >> k) & 1u) : -1;
+#pragma unroll
+            for (int q = 0; q < NBINS; q++) lc[q] += b == q ? 1u : 0u;
+            if (b == BIN_GLOBAL) lge += (uint32_t)v[k];
         }
+        uint32_t lb[NBINS];
+#pragma unroll
+        for (int q = 0; q < NBINS; q++) lb[q] = lc[q] ? atomicAdd(&s_bc[q], lc[q]) : 0u;
+        unsigned long long ge = lge ? atomicAdd(&s_ge, lge) : 0ull;
         __syncthreads();
         if (threadIdx.x < NBINS && s_bc[threadIdx.x])
             s_bbase[threadIdx.x] = atomicAdd(&hdr->bin_cnt[threadIdx.x], s_bc[threadIdx.x]);
@@ -218,12 +237,18 @@ __device__ void scan_counts_tile(int64_t tile, ScanSmem &sm, const int32_t *__re
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < SCAN_ITEMS; k++) {
-            if (bin[k] < 0) continue;
-            const uint32_t pos = s_bbase[bin[k]] + off[k];
+            const int b = base + k < n ? class_of(v[k], classify, all, (flags >> k) & 1u) : -1;
+            if (b < 0) continue;
+            uint32_t slot = 0;
+#pragma unroll
+            for (int q = 0; q < NBINS; q++)
+                if (b == q) slot = lb[q]++;
+            const uint32_t pos = s_bbase[b] + slot;
             if (pos < cap) {
-                lists[(int64_t)bin[k] * cap + pos] = (uint32_t)(base + k);
-                if (bin[k] == BIN_GLOBAL) goff[pos] = s_gbase + eoff[k];
+                lists[(int64_t)b * cap + pos] = (uint32_t)(base + k);
+                if (b == BIN_GLOBAL) goff[pos] = s_gbase + ge;
             }
+            if (b == BIN_GLOBAL) ge += (uint32_t)v[k];
         }
     }
     __syncthreads();
