@@ -213,8 +213,8 @@ __global__ __launch_bounds__(256) void k_dcsc_rec(const int32_t *__restrict__ jc
     const uint64_t *nshort) {
     __shared__ GroupCore gs[SR_BLOCK / WAVE];
     (void)ngb;
-    spref_count_tile(blockIdx.x, SR_BIGBLOCKS, gs, acol, n, rs, rl, cp, nI, b2, jpos, Dn, cnt, hmS, hmB, capb, hdr,
-                     srows, nshort);
+    spref_count_tile<true>(blockIdx.x, SR_BIGBLOCKS, gs, acol, n, rs, rl, cp, nI, b2, jpos, Dn, cnt, hmS, hmB, capb,
+                           hdr, srows, nshort);
 }
 // Five wavefronts per SIMD (at most 96 VGPRs; the fp32 staging area keeps
 // five workgroups in LDS): the gather is bound by the latency of its

@@ -247,16 +247,12 @@ __device__ __forceinline__ int chain_len(int32_t v, const int32_t *Dn) {
     return k;
 }
 
-// Hit multiplicities of one step of SR_U slots (columns c, valid flags ok).
-// Every slot's word of the 2-bit map is loaded (one divergent access per
-// slot, all issued before any is used, so the loads of a step overlap); the
-// chain walk only runs for repeated columns.
-__device__ __forceinline__ void step_mult(const int32_t (&c)[SR_U], const bool (&ok)[SR_U],
-                                          const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos,
-                                          const int32_t *__restrict__ Dn, int (&mm)[SR_U]) {
-    uint32_t bw[SR_U];
-#pragma unroll
-    for (int u = 0; u < SR_U; u++) bw[u] = b2[c[u] >> 4];
+// Hit multiplicities of one step of SR_U slots (columns c, valid flags ok)
+// from their words bw of the 2-bit map; the chain walk only runs for
+// repeated columns.
+__device__ __forceinline__ void step_mult_words(const int32_t (&c)[SR_U], const bool (&ok)[SR_U],
+                                                const uint32_t (&bw)[SR_U], const int32_t *__restrict__ jpos,
+                                                const int32_t *__restrict__ Dn, int (&mm)[SR_U]) {
     bool dup[SR_U], any = false;
 #pragma unroll
     for (int u = 0; u < SR_U; u++) {
@@ -273,15 +269,25 @@ __device__ __forceinline__ void step_mult(const int32_t (&c)[SR_U], const bool (
     }
 }
 
+// The same with the words loaded here: every slot's word is loaded (one
+// divergent access per slot, all issued before any is used, so the loads
+// of a step overlap).
+__device__ __forceinline__ void step_mult(const int32_t (&c)[SR_U], const bool (&ok)[SR_U],
+                                          const uint32_t *__restrict__ b2, const int32_t *__restrict__ jpos,
+                                          const int32_t *__restrict__ Dn, int (&mm)[SR_U]) {
+    uint32_t bw[SR_U];
+#pragma unroll
+    for (int u = 0; u < SR_U; u++) bw[u] = b2[c[u] >> 4];
+    step_mult_words(c, ok, bw, jpos, Dn, mm);
+}
+
 // Gather side of the hit masks: the slots' hit bits come from the count
 // pass's words w[0..SR_U), so only the hits look anything up (their J
 // position; a negative one heads the chain of a repeated column).
-__device__ __forceinline__ void hits_from_mask(const uint64_t *__restrict__ w, const int32_t (&raw)[SR_U],
-                                               int64_t n, const int32_t *__restrict__ jpos,
-                                               const int32_t *__restrict__ Dn, int32_t (&c)[SR_U],
-                                               int32_t (&jv)[SR_U], int (&mm)[SR_U]) {
+__device__ __forceinline__ void hits_lookup(const uint64_t *__restrict__ w, const int32_t (&raw)[SR_U], int64_t n,
+                                            const int32_t *__restrict__ jpos, int32_t (&c)[SR_U],
+                                            int32_t (&jv)[SR_U], bool (&hit)[SR_U]) {
     const int l = lane_id();
-    bool hit[SR_U];
 #pragma unroll
     for (int u = 0; u < SR_U; u++) {
         hit[u] = (w[u] >> l) & 1ull;
@@ -289,6 +295,11 @@ __device__ __forceinline__ void hits_from_mask(const uint64_t *__restrict__ w, c
     }
 #pragma unroll
     for (int u = 0; u < SR_U; u++) jv[u] = hit[u] ? jpos[c[u]] : 0;
+}
+
+// Multiplicities of the hits once their J positions jv have arrived.
+__device__ __forceinline__ void hits_mult(const bool (&hit)[SR_U], const int32_t (&jv)[SR_U],
+                                          const int32_t *__restrict__ Dn, int (&mm)[SR_U]) {
     bool any = false;
 #pragma unroll
     for (int u = 0; u < SR_U; u++) {
@@ -300,6 +311,15 @@ __device__ __forceinline__ void hits_from_mask(const uint64_t *__restrict__ w, c
         for (int u = 0; u < SR_U; u++)
             if (hit[u] && jv[u] < 0) mm[u] = chain_len(jv[u], Dn);
     }
+}
+
+__device__ __forceinline__ void hits_from_mask(const uint64_t *__restrict__ w, const int32_t (&raw)[SR_U],
+                                               int64_t n, const int32_t *__restrict__ jpos,
+                                               const int32_t *__restrict__ Dn, int32_t (&c)[SR_U],
+                                               int32_t (&jv)[SR_U], int (&mm)[SR_U]) {
+    bool hit[SR_U];
+    hits_lookup(w, raw, n, jpos, c, jv, hit);
+    hits_mult(hit, jv, Dn, mm);
 }
 
 // Write the output entries of one hit whose jpos entry is x: one entry for a
@@ -426,7 +446,12 @@ __device__ __forceinline__ void stage_chain(int32_t x, VT v, int idx, int row, c
 // Tile bid of the count pass: bid < nbw are the long-row workers (a
 // contiguous range of chunks per wavefront), then one tile per 256 selected
 // rows (64 rows per wavefront, walked as one concatenation).  Every step
-// issues its column loads together, then its bitmap loads together.
+// issues its column loads together, then its bitmap loads together.  PIPE
+// (the plain kernel): each step's column loads are issued one step ahead, a
+// software pipeline (R-MAT scale-22 extraction: 146 -> 142 us); the batched
+// kernel, which holds the other stages' code too, keeps the plain loop (the
+// pipeline took its count stage from 89 to 180 VGPRs).
+template <bool PIPE = false>
 __device__ inline void spref_count_tile(
     int64_t bid, int64_t nbw, GroupCore *gs, const int32_t *__restrict__ acol, int64_t n,
     const int64_t *__restrict__ rs, const int32_t *__restrict__ rl, const int64_t *__restrict__ cp, int64_t nI,
@@ -456,26 +481,46 @@ __device__ inline void spref_count_tile(
         g.start[l] = incl - len;
         g.cnt[l] = 0;
         __builtin_amdgcn_wave_barrier();
-        for (int e0 = 0; e0 < E; e0 += SR_BW) {
+        // Software pipeline: the column loads of the next step go out after
+        // this step's bitmap loads and before their words are used, so a
+        // step waits on one round of loads instead of two.
+        // Carried between steps: the raw columns and the slots' rows, four
+        // 6-bit rows to a word.
+        static_assert(SR_U % 4 == 0, "rows packed four to a word");
+        uint32_t rrp[SR_U / 4];
+        int32_t raw[SR_U];
+        auto issue = [&](int e0) {
             int64_t k[SR_U];
-            int32_t c[SR_U];
-            int rr[SR_U], mm[SR_U];
-            bool ok[SR_U];
+#pragma unroll
+            for (int u = 0; u < SR_U / 4; u++) rrp[u] = 0;
 #pragma unroll
             for (int u = 0; u < SR_U; u++) {
                 const int e = e0 + u * WAVE + l;
-                ok[u] = e < E;
-                const int ec = ok[u] ? e : E - 1;
+                const int ec = e < E ? e : E - 1;
                 const int r = row_of(g.start, ec);
-                rr[u] = r;
+                rrp[u / 4] |= (uint32_t)r << (8 * (u % 4));
                 k[u] = g.rs[r] + (ec - g.start[r]);
             }
-            int32_t raw[SR_U];
 #pragma unroll
             for (int u = 0; u < SR_U; u++) raw[u] = __builtin_nontemporal_load(&acol[k[u]]);
+        };
+        if (PIPE && E > 0) issue(0);
+        for (int e0 = 0; e0 < E; e0 += SR_BW) {
+            if (!PIPE) issue(e0);
+            int32_t c[SR_U];
+            int rc[SR_U], mm[SR_U];
+            bool okc[SR_U];
+            uint32_t bw[SR_U];
 #pragma unroll
-            for (int u = 0; u < SR_U; u++) c[u] = (int32_t)clampc(raw[u], n);
-            step_mult(c, ok, b2, jpos, Dn, mm);
+            for (int u = 0; u < SR_U; u++) {
+                c[u] = (int32_t)clampc(raw[u], n);
+                rc[u] = (int)((rrp[u / 4] >> (8 * (u % 4))) & 0xFFu);
+                okc[u] = e0 + u * WAVE + l < E;
+            }
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) bw[u] = b2[c[u] >> 4];
+            if (PIPE && e0 + SR_BW < E) issue(e0 + SR_BW);
+            step_mult_words(c, okc, bw, jpos, Dn, mm);
             uint64_t hm = 0;
 #pragma unroll
             for (int u = 0; u < SR_U; u++) {
@@ -485,14 +530,14 @@ __device__ inline void spref_count_tile(
             if (l < SR_U) hmS[(gw * SR_STEPS + e0 / SR_BW) * SR_U + l] = hm;
 #pragma unroll
             for (int u = 0; u < SR_U; u++)
-                if (mm[u]) atomicAdd(&g.cnt[rr[u]], mm[u]);
+                if (mm[u]) atomicAdd(&g.cnt[rc[u]], mm[u]);
         }
         __builtin_amdgcn_wave_barrier();
         if (small) cnt[i] = g.cnt[l];
         return;
     }
     // big-row chunks: every wavefront takes a contiguous range of chunks
-    // (these workgroups come first)
+    // (these workgroups come first); pipelined like the short rows
     const int64_t nbig = cp[nI];
     int64_t q0, q1;
     chunk_range(nbig, bid * 4 + w, nbw * 4, q0, q1);
@@ -500,7 +545,9 @@ __device__ inline void spref_count_tile(
     int64_t row = wave_search_le(cp, nI + 1, q0);
     int64_t rbeg = cp[row], rend = cp[row + 1], base = rs[row];
     int64_t rlen = rl[row];
-    for (int64_t q = q0; q < q1; q++) {
+    int32_t raw[SR_U];
+    int nq = 0;   // entries of the chunk whose columns are in raw
+    auto issue = [&](int64_t q) {
         if (q >= rend) {
             row = next_chunk_row(cp, nI, row, q);
             rbeg = cp[row];
@@ -509,20 +556,32 @@ __device__ inline void spref_count_tile(
             rlen = rl[row];
         }
         const int64_t b = (q - rbeg) * SR_BW;
-        const int64_t e = min(b + SR_BW, rlen);
-        int32_t c[SR_U];
-        int mm[SR_U];
-        bool ok[SR_U];
-        int32_t raw[SR_U];
+        nq = (int)(min(b + SR_BW, rlen) - b);
+        const int64_t kb = base + b;
 #pragma unroll
         for (int u = 0; u < SR_U; u++) {
-            const int64_t kk = b + u * WAVE + l;
-            ok[u] = kk < e;
-            raw[u] = __builtin_nontemporal_load(&acol[base + (ok[u] ? kk : e - 1)]);
+            const int kk = u * WAVE + l;
+            raw[u] = __builtin_nontemporal_load(&acol[kb + (kk < nq ? kk : nq - 1)]);
+        }
+    };
+    if (PIPE) issue(q0);
+    for (int64_t q = q0; q < q1; q++) {
+        if (!PIPE) issue(q);
+        const int64_t crow_q = row;   // the row of chunk q
+        const int nc = nq;
+        int32_t c[SR_U];
+        int mm[SR_U];
+        bool okc[SR_U];
+        uint32_t bw[SR_U];
+#pragma unroll
+        for (int u = 0; u < SR_U; u++) {
+            c[u] = (int32_t)clampc(raw[u], n);
+            okc[u] = u * WAVE + l < nc;
         }
 #pragma unroll
-        for (int u = 0; u < SR_U; u++) c[u] = (int32_t)clampc(raw[u], n);
-        step_mult(c, ok, b2, jpos, Dn, mm);
+        for (int u = 0; u < SR_U; u++) bw[u] = b2[c[u] >> 4];
+        if (PIPE && q + 1 < q1) issue(q + 1);
+        step_mult_words(c, okc, bw, jpos, Dn, mm);
         if (nbig <= capb) {
             uint64_t hm = 0;
 #pragma unroll
@@ -536,7 +595,7 @@ __device__ inline void spref_count_tile(
 #pragma unroll
         for (int u = 0; u < SR_U; u++) sum += mm[u];
         sum = wave_sum(sum);
-        if (l == 0 && sum) atomicAdd(&cnt[row], sum);
+        if (l == 0 && sum) atomicAdd(&cnt[crow_q], sum);
     }
 }
 
@@ -593,29 +652,47 @@ __device__ inline void spref_gather_tile(
         // a slice boundary needs its hit count carried: `cur` is the row of
         // the previous slice's last lane and `carry` its hits so far.
         int carry = 0, cur = INT32_MIN;
-        for (int e0 = 0; e0 < E; e0 += SR_BW) {
+        // The slots' rows are kept four 6-bit rows to a word (82 VGPRs
+        // instead of 90).  Issuing the next step's column and value loads
+        // before this step's J positions are used (a software pipeline, as
+        // in the count pass) needed 116 VGPRs and took the gather from 187
+        // to 204 us at four wavefronts per SIMD.
+        uint32_t rrp[SR_U / 4];
+        int32_t raw[SR_U];
+        VT v[SR_U];
+        auto issue = [&](int e0) {
             int64_t k[SR_U];
-            int32_t c[SR_U];
-            int rr[SR_U], mm[SR_U];
-            bool ok[SR_U];
+#pragma unroll
+            for (int u = 0; u < SR_U / 4; u++) rrp[u] = 0;
 #pragma unroll
             for (int u = 0; u < SR_U; u++) {
                 const int e = e0 + u * WAVE + l;
-                ok[u] = e < E;
-                const int ec = ok[u] ? e : E - 1;
+                const int ec = e < E ? e : E - 1;
                 const int r = row_of(g.start, ec);
-                rr[u] = ok[u] ? r : -1 - l;   // distinct per idle lane: never joins a segment
+                rrp[u / 4] |= (uint32_t)r << (8 * (u % 4));
                 k[u] = g.rs[r] + (ec - g.start[r]);
             }
-            int32_t raw[SR_U];
-            VT v[SR_U];
-            const uint64_t *hw = hmS + (gw * SR_STEPS + e0 / SR_BW) * SR_U;
 #pragma unroll
             for (int u = 0; u < SR_U; u++) raw[u] = __builtin_nontemporal_load(&acol[k[u]]);
 #pragma unroll
             for (int u = 0; u < SR_U; u++) v[u] = __builtin_nontemporal_load(&aval[k[u]]);
-            int32_t jv[SR_U];
-            hits_from_mask(hw, raw, n, jpos, Dn, c, jv, mm);
+        };
+        for (int e0 = 0; e0 < E; e0 += SR_BW) {
+            issue(e0);
+            int32_t c[SR_U], jv[SR_U];
+            int rr[SR_U], mm[SR_U];
+            bool hit[SR_U];
+            VT vc[SR_U];
+#pragma unroll
+            for (int u = 0; u < SR_U; u++) {
+                const bool ok = e0 + u * WAVE + l < E;
+                const int r = (int)((rrp[u / 4] >> (8 * (u % 4))) & 0xFFu);
+                rr[u] = ok ? r : -1 - l;   // distinct per idle lane: never joins a segment
+                vc[u] = v[u];
+            }
+            const uint64_t *hw = hmS + (gw * SR_STEPS + e0 / SR_BW) * SR_U;
+            hits_lookup(hw, raw, n, jpos, c, jv, hit);
+            hits_mult(hit, jv, Dn, mm);
 #pragma unroll
             for (int u = 0; u < SR_U; u++) {
                 const int r = rr[u];
@@ -630,8 +707,8 @@ __device__ inline void spref_gather_tile(
                 const int pos = mine ? ex - base_ex : carry + ex;
                 if (mm[u] && pos + mm[u] <= g.scnt[r]) {   // within the planned count
                     const int so = g.soff[r];
-                    if (so >= 0) stage_chain<VT>(jv[u], v[u], so + pos, r, Dn, g);
-                    else emit_chain<VT>(jv[u], v[u], g.crow[r] + pos, Dn, ccol, cval);
+                    if (so >= 0) stage_chain<VT>(jv[u], vc[u], so + pos, r, Dn, g);
+                    else emit_chain<VT>(jv[u], vc[u], g.crow[r] + pos, Dn, ccol, cval);
                 }
                 carry = __builtin_amdgcn_readlane(pos + mm[u], WAVE - 1);
                 cur = __builtin_amdgcn_readlane(r, WAVE - 1);
@@ -667,7 +744,10 @@ __device__ inline void spref_gather_tile(
     int64_t row = wave_search_le(cp, nI + 1, q0);
     int64_t rbeg = cp[row], rend = cp[row + 1], base = rs[row];
     int64_t rlen = rl[row], orow = (int64_t)crow[row], oend = (int64_t)crow[row + 1];
-    for (int64_t q = q0; q < q1; q++) {
+    int32_t raw[SR_U];
+    VT v[SR_U];
+    int nq = 0;   // entries of the chunk whose columns and values are in raw, v
+    auto issue = [&](int64_t q) {
         if (q >= rend) {
             row = next_chunk_row(cp, nI, row, q);
             rbeg = cp[row];
@@ -678,23 +758,33 @@ __device__ inline void spref_gather_tile(
             oend = (int64_t)crow[row + 1];
         }
         const int64_t b = (q - rbeg) * SR_BW;
-        const int64_t e = min(b + SR_BW, rlen);
-        int32_t c[SR_U];
-        int mm[SR_U];
-        bool ok[SR_U];
-        int32_t raw[SR_U];
-        VT v[SR_U];
+        nq = (int)(min(b + SR_BW, rlen) - b);
+        const int64_t kb = base + b;
 #pragma unroll
         for (int u = 0; u < SR_U; u++) {
-            const int64_t kk = b + u * WAVE + l;
-            ok[u] = kk < e;
-            const int64_t kc = base + (ok[u] ? kk : e - 1);
+            const int kk = u * WAVE + l;
+            const int64_t kc = kb + (kk < nq ? kk : nq - 1);
             raw[u] = __builtin_nontemporal_load(&acol[kc]);
             v[u] = __builtin_nontemporal_load(&aval[kc]);
         }
-        int32_t jv[SR_U];
+    };
+    for (int64_t q = q0; q < q1; q++) {
+        issue(q);
+        const int64_t row_q = row, orow_q = orow, oend_q = oend;   // chunk q's row
+        const int nc = nq;
+        int32_t c[SR_U], jv[SR_U];
+        int mm[SR_U];
+        bool ok[SR_U];
+        VT vc[SR_U];
+#pragma unroll
+        for (int u = 0; u < SR_U; u++) {
+            ok[u] = u * WAVE + l < nc;
+            vc[u] = v[u];
+        }
         if (use_mask) {
-            hits_from_mask(hmB + q * SR_U, raw, n, jpos, Dn, c, jv, mm);
+            bool hit[SR_U];
+            hits_lookup(hmB + q * SR_U, raw, n, jpos, c, jv, hit);
+            hits_mult(hit, jv, Dn, mm);
         } else {
 #pragma unroll
             for (int u = 0; u < SR_U; u++) c[u] = (int32_t)clampc(raw[u], n);
@@ -711,12 +801,12 @@ __device__ inline void spref_gather_tile(
             run += __shfl(inc, WAVE - 1, WAVE);
         }
         int32_t cb = 0;
-        if (l == 0 && run) cb = atomicAdd(&cursor[row], run);
+        if (l == 0 && run) cb = atomicAdd(&cursor[row_q], run);
         cb = __shfl(cb, 0, WAVE);
-        const int64_t ob = orow + cb;
+        const int64_t ob = orow_q + cb;
 #pragma unroll
         for (int u = 0; u < SR_U; u++)
-            if (mm[u] && ob + ex[u] + mm[u] <= oend) emit_chain<VT>(jv[u], v[u], ob + ex[u], Dn, ccol, cval);
+            if (mm[u] && ob + ex[u] + mm[u] <= oend_q) emit_chain<VT>(jv[u], vc[u], ob + ex[u], Dn, ccol, cval);
     }
 }
 

@@ -161,6 +161,33 @@ def test_long_rows_over_2pow20_columns(hp):
     assert_same(np_csr(C), oracle.permute(A, p, q), "permute")
 
 
+def test_wide_general_permutation(hp):
+    """A general permutation over more than 2^22 columns: the whole output
+    against the oracle, and both error paths of q at that width (a repeated
+    value, values out of range on either side)."""
+    n = (1 << 22) + 40_961
+    A = mixed_csr(84, 40, n, [0, 1, 7, 900, 5000, 30000], torch.int32, torch.float32)
+    p = synth.randperm(85, A.nrows, "cuda")
+    q = synth.randperm(86, n, "cuda")
+    C = hp.permute(A, p, q)
+    torch.cuda.synchronize()
+    assert_same(np_csr(C), oracle.permute(A, p, q), "permute")
+    bad = q.clone()
+    bad[n - 1] = bad[17]
+    with pytest.raises(hp.HPError) as e:
+        hp.permute(A, p, bad)
+    assert e.value.name == "HP_ERR_NOT_PERMUTATION"
+    bad = q.clone()
+    bad[1 << 21] = n
+    with pytest.raises(hp.HPError) as e:
+        hp.permute(A, p, bad)
+    assert e.value.name == "HP_ERR_INDEX_RANGE"
+    bad[1 << 21] = -5
+    with pytest.raises(hp.HPError) as e:
+        hp.permute(A, p, bad)
+    assert e.value.name == "HP_ERR_INDEX_RANGE"
+
+
 @pytest.mark.parametrize("ptr,vdt", [(torch.int32, torch.float32), (torch.int64, torch.float64)])
 def test_large_random_graph_both_widths(hp, ptr, vdt):
     """Just over 2^20 rows of a random graph (0-10 entries a row): the whole
