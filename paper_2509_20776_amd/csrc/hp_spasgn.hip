@@ -577,7 +577,7 @@ __global__ __launch_bounds__(256) void k_asg_rows_list(
 // its rank among the kept ones + (B' entries below it); collisions drop
 // the A entry (PLUS adds its value to B's first).  Other rows go to llist.
 template <typename PT, typename VT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_asg_merge_I(
+__global__ __launch_bounds__(256) void k_asg_merge_I(
     const PT *__restrict__ arow, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
     const PT *__restrict__ brow, const int32_t *__restrict__ bcol, const VT *__restrict__ bval,
     const int32_t *__restrict__ I, int64_t nI, const int32_t *__restrict__ J, int64_t nJ,
