@@ -713,6 +713,147 @@ __global__ __launch_bounds__(256) void k_asg_merge_I(
     }
 }
 
+// Lane a's value, for a wave-uniform a (32- or 64-bit).
+template <typename T>
+__device__ __forceinline__ T read_lane(T x, int a) {
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t u = (uint64_t)x;
+        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, a);
+        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), a);
+        return (T)(((uint64_t)hi << 32) | lo);
+    } else {
+        return (T)__builtin_amdgcn_readlane((uint32_t)x, a);
+    }
+}
+
+// The same merge for long B rows (taken when B averages more than WAVE
+// entries a row): one wavefront per row of I, four rows per workgroup, B's
+// row in AS_MQ 64-wide slices of registers (each load 64 consecutive
+// entries) and A's row one entry per lane, so the collision tests and the
+// placement counts are ballots and the row's values wave-uniform.  About
+// 40 VGPRs (eight wavefronts a SIMD) where the 16-lane merge needs 155.
+// Rows with more than WAVE A entries or AS_MQ * WAVE B entries, or (plain
+// form) mapped B columns out of order, go to llist.
+constexpr int AS_MQ = 4;
+template <typename PT, typename VT>
+__global__ __launch_bounds__(256) void k_asg_merge_row(
+    const PT *__restrict__ arow, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
+    const PT *__restrict__ brow, const int32_t *__restrict__ bcol, const VT *__restrict__ bval,
+    const int32_t *__restrict__ I, int64_t nI, const int32_t *__restrict__ J, int64_t nJ,
+    const int32_t *__restrict__ colinv, int64_t n, int op, const PT *__restrict__ crow, int32_t *ccol, VT *cval,
+    int32_t *llist, uint32_t *lcount, int jrange, const DevHdr *hdr, OutMap om = OutMap{nullptr, nullptr, 0}) {
+    if (hdr->err) return;
+    const int l = lane_id();
+    const int64_t i = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
+    if (i >= nI) return;   // the whole wavefront
+    const int32_t j0 = nJ > 0 ? J[0] : 0;
+    const int64_t r = I[i];
+    const int64_t as = arow[r], La = arow[r + 1] - as;
+    const int64_t bs = brow[i], Lb = brow[i + 1] - bs;
+    const bool small = La <= WAVE && Lb <= AS_MQ * WAVE;
+    int32_t bc[AS_MQ], bk[AS_MQ];
+    VT bv[AS_MQ];
+#pragma unroll
+    for (int q = 0; q < AS_MQ; q++) {
+        const int64_t t = q * WAVE + l;
+        const bool in = small && t < Lb;
+        bc[q] = in ? bcol[bs + t] : INT32_MIN;
+        bv[q] = in ? bval[bs + t] : VT(0);
+    }
+#pragma unroll
+    for (int q = 0; q < AS_MQ; q++)
+        bk[q] = bc[q] == INT32_MIN ? INT32_MAX : (jrange ? j0 + (int32_t)clampc(bc[q], nJ) : J[clampc(bc[q], nJ)]);
+    int32_t ak = INT32_MAX, jb = -1;
+    VT av = VT(0);
+    if (small && l < La) {
+        ak = acol[as + l];
+        av = aval[as + l];
+        jb = colinv[clampc(ak, n)];
+    }
+    // mapped columns increasing along the row (t = q * WAVE + lane)?
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < AS_MQ; q++) {
+        const int32_t nx_same = __shfl_down(bk[q], 1, WAVE);
+        const int32_t nx_wrap = q + 1 < AS_MQ ? __shfl(bk[q + 1], 0, WAVE) : INT32_MAX;
+        const int32_t nxt = l < WAVE - 1 ? nx_same : nx_wrap;
+        const int64_t t = q * WAVE + l;
+        bad |= t + 1 < Lb && bk[q] >= nxt;
+    }
+    const bool inc = ballot(bad) == 0;
+    const bool fused = om.cmap != nullptr;
+    if (!(small && (inc || fused))) {
+        if (l == 0) llist[atomicAdd(lcount, 1u)] = (int32_t)i;   // rare: the one-wavefront merge
+        return;
+    }
+    const bool replace = op == HP_OP_REPLACE, plus = op == HP_OP_PLUS;
+    const int na = (int)La;
+    uint64_t kept = 0;   // bit a: A entry a survives (wave-uniform)
+    for (int a = 0; a < na; a++) {
+        const int32_t ja = read_lane(jb, a);
+        const VT va = read_lane(av, a);
+        bool hit = false;
+#pragma unroll
+        for (int q = 0; q < AS_MQ; q++) {
+            const bool h = ja >= 0 && bc[q] == ja;
+            hit |= h;
+            if (h && plus) bv[q] = vadd(va, bv[q]);
+        }
+        const bool ghit = ballot(hit) != 0;
+        if (ja < 0 || (!replace && !ghit)) kept |= 1ull << a;
+    }
+    const int64_t d = crow[om.row(r)];
+    const bool mykept = l < na && ((kept >> l) & 1ull);
+    if (fused) {
+        // B' entries in B's order, then the kept A entries in A's order
+#pragma unroll
+        for (int q = 0; q < AS_MQ; q++) {
+            const int64_t t = q * WAVE + l;
+            if (t < Lb) {
+                ccol[d + t] = om.col(bk[q]);
+                cval[d + t] = bv[q];
+            }
+        }
+        if (mykept) {
+            const int64_t pos = d + Lb + __popcll(kept & lanemask_lt());
+            ccol[pos] = om.col(ak);
+            cval[pos] = av;
+        }
+        return;
+    }
+    // B' entries, each shifted by the kept A entries with smaller columns;
+    // a kept A entry goes to its rank among the kept ones plus the B'
+    // entries below it
+    int below[AS_MQ];
+#pragma unroll
+    for (int q = 0; q < AS_MQ; q++) below[q] = 0;
+    int cntb_mine = 0;
+    for (int a = 0; a < na; a++) {
+        if (!((kept >> a) & 1ull)) continue;   // uniform
+        const int32_t ka = read_lane(ak, a);
+        int cb = 0;
+#pragma unroll
+        for (int q = 0; q < AS_MQ; q++) {
+            below[q] += ka < bk[q];
+            cb += __popcll(ballot(bk[q] < ka));
+        }
+        if (l == a) cntb_mine = cb;
+    }
+#pragma unroll
+    for (int q = 0; q < AS_MQ; q++) {
+        const int64_t t = q * WAVE + l;
+        if (t < Lb) {
+            ccol[d + t + below[q]] = om.col(bk[q]);
+            cval[d + t + below[q]] = bv[q];
+        }
+    }
+    if (mykept) {
+        const int64_t pos = d + __popcll(kept & lanemask_lt()) + cntb_mine;
+        ccol[pos] = om.col(ak);
+        cval[pos] = av;
+    }
+}
+
 // Entry k of a row of A with its column mapped (fused form).
 template <typename VT>
 struct LoadMapped {
@@ -1073,10 +1214,16 @@ hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
     stage_mark(h, "asgn.copy");
     if (nI > 0) {
         launch_clear_words(s, L.lcount, 1);
-        hipLaunchKernelGGL((k_asg_merge_I<PT, VT>), dim3(gridn(nI, 256 / AS_G)), dim3(256), 0, s,
-                           (const PT *)A->rowptr, A->col, (const VT *)A->val, (const PT *)B->rowptr, B->col,
-                           (const VT *)B->val, I, nI, J, nJ, L.colinv, n, (int)op, (const PT *)C->rowptr, C->col,
-                           (VT *)C->val, L.llist, L.lcount, (int)info->aux[1], L.hdr, om);
+        if (B->nnz > (int64_t)WAVE * nI)   // long B rows: one wavefront per row
+            hipLaunchKernelGGL((k_asg_merge_row<PT, VT>), dim3(gridn(nI, 256 / WAVE)), dim3(256), 0, s,
+                               (const PT *)A->rowptr, A->col, (const VT *)A->val, (const PT *)B->rowptr, B->col,
+                               (const VT *)B->val, I, nI, J, nJ, L.colinv, n, (int)op, (const PT *)C->rowptr, C->col,
+                               (VT *)C->val, L.llist, L.lcount, (int)info->aux[1], L.hdr, om);
+        else
+            hipLaunchKernelGGL((k_asg_merge_I<PT, VT>), dim3(gridn(nI, 256 / AS_G)), dim3(256), 0, s,
+                               (const PT *)A->rowptr, A->col, (const VT *)A->val, (const PT *)B->rowptr, B->col,
+                               (const VT *)B->val, I, nI, J, nJ, L.colinv, n, (int)op, (const PT *)C->rowptr, C->col,
+                               (VT *)C->val, L.llist, L.lcount, (int)info->aux[1], L.hdr, om);
         hipLaunchKernelGGL((k_asg_rows_list<PT, VT, false>), dim3((unsigned)std::min<int64_t>(gridn(nI, 4), 1024)),
                            dim3(256), 0, s, (const PT *)A->rowptr, A->col, (const VT *)A->val, (const PT *)B->rowptr,
                            B->col, (const VT *)B->val, I, J, nJ, L.colinv, n, (int)op, (const PT *)C->rowptr, C->col,

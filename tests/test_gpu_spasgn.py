@@ -74,6 +74,32 @@ def test_rows_of_I_out_of_J_order(hp, op, ptr, vdt):
 
 
 @pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("ptr,vdt", [(torch.int32, torch.float32), (torch.int64, torch.float64)])
+def test_long_B_rows_one_wavefront_a_row(hp, op, ptr, vdt):
+    """B rows averaging over 64 entries take the one-wavefront-a-row merge:
+    A rows of up to 64 entries and B rows of up to 256 merged in registers,
+    longer ones through the one-wavefront merge in LDS; J sorted (merged in
+    place), a contiguous range (no lookup of J), and unsorted; also fused."""
+    m, n = 1000, 3000
+    A = mixed_csr(91, m, n, [0, 1, 5, 40, 63, 64, 65, 120], ptr, vdt)
+    rng = np.random.default_rng(92)
+    nI, nJ = 400, 1500
+    I = _t(rng.choice(m, nI, replace=False))
+    Js = _t(np.sort(rng.choice(n, nJ, replace=False)))
+    Jr = _t(np.arange(700, 700 + nJ))
+    Ju = _t(rng.choice(n, nJ, replace=False))
+    B = mixed_csr(93, nI, nJ, [0, 1, 63, 64, 65, 128, 200, 255, 256, 257], ptr, vdt)
+    assert B.nnz > 64 * nI
+    p = synth.randperm(94, m, "cuda")
+    q = synth.randperm(95, n, "cuda")
+    for J, name in ((Js, "sorted J"), (Jr, "J a range"), (Ju, "unsorted J")):
+        ref = oracle.spasgn(A, B, I, J, op)
+        assert_same(np_csr(hp.spasgn(A, B, I, J, op)), ref, f"{name}, {op}")
+        Cf = np_csr(hp.spasgn_permute(A, B, I, J, p, q, op))
+        assert_same(Cf, oracle.permute((m, n) + tuple(ref), p, q), f"fused, {name}, {op}")
+
+
+@pytest.mark.parametrize("op", OPS)
 def test_long_rows_fallback(hp, op):
     m, n = 300, 6000
     A = mixed_csr(31, m, n, [0, 3, 100, 250, 700, 5000])
