@@ -101,16 +101,21 @@ __device__ inline void perm_pull_short_tile(int64_t bid, const PT *__restrict__ 
     const int len = (int)(arow[src + 1] - s);
     if (len == 0 || len > 4) return;
     const int64_t d = crow[i];
-    int32_t k[4];
+    // clamped indexes (len >= 1): the four loads, then the four lookups, go
+    // out together
+    int32_t c[4], k[4];
     VT v[4];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-        k[u] = INT32_MAX;
-        v[u] = VT(0);
-        if (u < len) {
-            k[u] = cmap[clampc(acol[s + u], n)];
-            v[u] = aval[s + u];
-        }
+        const int64_t e = s + (u < len ? u : len - 1);
+        c[u] = acol[e];
+        v[u] = aval[e];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int32_t mk = cmap[clampc(c[u], n)];
+        k[u] = u < len ? mk : INT32_MAX;
+        if (u >= len) v[u] = VT(0);
     }
     sort_store_regs<4, VT>(k, v, len, false, ccol + d, cval + d);
 }
@@ -165,11 +170,16 @@ __device__ inline void perm_pack_tile(int64_t bid, const PT *__restrict__ arow, 
             ck[u] = k < s1 ? acol[k] : 0;
             cv[u] = k < s1 ? aval[k] : VT(0);
         }
+        // every lane looks up (idle lanes column 0, one shared line), so
+        // the lookups are issued together rather than one branch at a time
+        int32_t mk[PACK_STAGE / WAVE];
+#pragma unroll
+        for (int u = 0; u < PACK_STAGE / WAVE; u++) mk[u] = cmap[clampc(ck[u], n)];
 #pragma unroll
         for (int u = 0; u < PACK_STAGE / WAVE; u++) {
             const int64_t k = s0 + u * WAVE + l;
             if (k < s1) {
-                wk[k - s0] = cmap[clampc(ck[u], n)];
+                wk[k - s0] = mk[u];
                 wv[k - s0] = cv[u];
             }
         }
@@ -178,18 +188,27 @@ __device__ inline void perm_pack_tile(int64_t bid, const PT *__restrict__ arow, 
     if (len == 0 || len > 4) return;
     int32_t k[4];
     VT v[4];
+    if (staged) {
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
-        k[u] = INT32_MAX;
-        v[u] = VT(0);
-        if (u < len) {
-            if (staged) {
-                k[u] = wk[s - s0 + u];
-                v[u] = wv[s - s0 + u];
-            } else {
-                k[u] = cmap[clampc(acol[s + u], n)];
-                v[u] = aval[s + u];
-            }
+        for (int u = 0; u < 4; u++) {
+            k[u] = u < len ? wk[s - s0 + u] : INT32_MAX;
+            v[u] = u < len ? wv[s - s0 + u] : VT(0);
+        }
+    } else {
+        // clamped indexes (len >= 1): the loads and lookups of the four
+        // entries go out together
+        int32_t c[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int64_t e = s + (u < len ? u : len - 1);
+            c[u] = acol[e];
+            v[u] = aval[e];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int32_t mk = cmap[clampc(c[u], n)];
+            k[u] = u < len ? mk : INT32_MAX;
+            if (u >= len) v[u] = VT(0);
         }
     }
     bitonic_regs<4, VT>(k, v);

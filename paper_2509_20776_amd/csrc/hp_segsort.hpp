@@ -58,7 +58,7 @@ __device__ __forceinline__ void bitonic_regs(int32_t (&k)[N], VT (&v)[N]) {
             }
 }
 
-// Sort up to N (4 or 16) elements held by one lane and store the first len.
+// Sort up to N (4, 8 or 16) elements held by one lane and store the first len.
 template <int N, typename VT>
 __device__ __forceinline__ void sort_store_regs(int32_t (&k)[N], VT (&v)[N], int len, bool sorted,
                                                 int32_t *okey, VT *oval) {
@@ -71,31 +71,33 @@ __device__ __forceinline__ void sort_store_regs(int32_t (&k)[N], VT (&v)[N], int
         }
 }
 
-// One lane sorts one row of <= 16 entries read through the loader.
+// One lane sorts one row of <= N entries read through the loader.  The
+// entry indexes are clamped to the row (len >= 1), so every load, and every
+// lookup a renaming loader makes, is issued without waiting on the one
+// before (loads under a per-entry branch went out one at a time).
+template <int N, typename VT, typename LD>
+__device__ __forceinline__ void lane_sort_n(const LD &ld, int64_t sb, int len, bool sorted, int32_t *okey,
+                                            VT *oval) {
+    int32_t k[N];
+    VT v[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) ld.get(sb, i < len ? i : len - 1, k[i], v[i]);
+#pragma unroll
+    for (int i = 0; i < N; i++)
+        if (i >= len) {
+            k[i] = INT32_MAX;
+            v[i] = VT(0);
+        }
+    sort_store_regs<N, VT>(k, v, len, sorted, okey, oval);
+}
+
 template <typename VT, typename LD>
 __device__ __forceinline__ void lane_sort_row(const LD &ld, int64_t sb, int len, bool sorted,
                                               int32_t *okey, VT *oval) {
-    if (len <= 4) {
-        int32_t k[4];
-        VT v[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            k[i] = INT32_MAX;
-            v[i] = VT(0);
-            if (i < len) ld.get(sb, i, k[i], v[i]);
-        }
-        sort_store_regs<4, VT>(k, v, len, sorted, okey, oval);
-        return;
-    }
-    int32_t k[16];
-    VT v[16];
-#pragma unroll
-    for (int i = 0; i < 16; i++) {
-        k[i] = INT32_MAX;
-        v[i] = VT(0);
-        if (i < len) ld.get(sb, i, k[i], v[i]);
-    }
-    sort_store_regs<16, VT>(k, v, len, sorted, okey, oval);
+    if (len <= 0) return;
+    if (len <= 4) lane_sort_n<4, VT>(ld, sb, len, sorted, okey, oval);
+    else if (len <= 8) lane_sort_n<8, VT>(ld, sb, len, sorted, okey, oval);
+    else lane_sort_n<16, VT>(ld, sb, len, sorted, okey, oval);
 }
 
 // Value held by lane l ^ d (d a power of two below 64; every lane of the

@@ -662,18 +662,23 @@ __global__ __launch_bounds__(256) void k_asg_merge_I(
     if (!mine) return;
     const int64_t d = crow[om.row(r)];
     if (fused) {
-        // B' entries in B's order, then the kept A entries in A's order
+        // B' entries in B's order, then the kept A entries in A's order; the
+        // column lookups all go out together (idle lanes look up column 0)
+#pragma unroll
+        for (int q = 0; q < AS_G; q++) bk[q] = om.col(q * AS_G + x < Lb ? bk[q] : 0);
+        const bool mk = x < La && ((kept >> x) & 1u);
+        const int32_t ma = om.col(mk ? ak : 0);
 #pragma unroll
         for (int q = 0; q < AS_G; q++) {
             const int64_t t = q * AS_G + x;
             if (t < Lb) {
-                ccol[d + t] = om.col(bk[q]);
+                ccol[d + t] = bk[q];
                 cval[d + t] = bv[q];
             }
         }
-        if (x < La && ((kept >> x) & 1u)) {
+        if (mk) {
             const int64_t pos = d + Lb + __popc(kept & ((1u << x) - 1u));
-            ccol[pos] = om.col(ak);
+            ccol[pos] = ma;
             cval[pos] = av;
         }
         return;
@@ -805,18 +810,23 @@ __global__ __launch_bounds__(256) void k_asg_merge_row(
     const int64_t d = crow[om.row(r)];
     const bool mykept = l < na && ((kept >> l) & 1ull);
     if (fused) {
-        // B' entries in B's order, then the kept A entries in A's order
+        // B' entries in B's order, then the kept A entries in A's order; the
+        // column lookups all go out together (idle lanes look up column 0)
+        int32_t mc[AS_MQ];
+#pragma unroll
+        for (int q = 0; q < AS_MQ; q++) mc[q] = om.col(q * WAVE + l < Lb ? bk[q] : 0);
+        const int32_t ma = om.col(mykept ? ak : 0);
 #pragma unroll
         for (int q = 0; q < AS_MQ; q++) {
             const int64_t t = q * WAVE + l;
             if (t < Lb) {
-                ccol[d + t] = om.col(bk[q]);
+                ccol[d + t] = mc[q];
                 cval[d + t] = bv[q];
             }
         }
         if (mykept) {
             const int64_t pos = d + Lb + __popcll(kept & lanemask_lt());
-            ccol[pos] = om.col(ak);
+            ccol[pos] = ma;
             cval[pos] = av;
         }
         return;
