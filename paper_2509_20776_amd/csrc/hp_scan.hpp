@@ -210,11 +210,15 @@ __device__ __forceinline__ void scan_counts_tile(int64_t tile, ScanSmem &sm, con
         // the lane recomputes its rows' classes and appends them in order
         // (no per-row offsets kept in registers)
         const bool all = s_all != 0;
-        uint32_t flags = 0;   // bit k: force[base + k] (modes 3 and 4)
+        // bit k: row base + k flagged, force[base + k] != 0 in mode 3, 1 or 2
+        // in mode 4 (3 marks a merged row its merge already sorted)
+        uint32_t flags = 0;
         if (classify == 3 || classify == 4) {
 #pragma unroll
-            for (int k = 0; k < SCAN_ITEMS; k++)
-                if (base + k < n && force[base + k] != 0) flags |= 1u << k;
+            for (int k = 0; k < SCAN_ITEMS; k++) {
+                const uint32_t f = base + k < n ? force[base + k] : 0u;
+                if (classify == 3 ? f != 0 : (f == 1 || f == 2)) flags |= 1u << k;
+            }
         }
         uint32_t lc[NBINS] = {0, 0, 0, 0};
         unsigned long long lge = 0;

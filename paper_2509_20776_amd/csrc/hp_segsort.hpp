@@ -200,6 +200,10 @@ __device__ __forceinline__ void wave_sort_packed(const int32_t (&mk)[4], const V
     __builtin_amdgcn_wave_barrier();
 }
 
+template <typename VT>
+__device__ __forceinline__ void wave_sort_regs(const int32_t (&mk)[4], const VT (&mv)[4], int len, int32_t *okey,
+                                               VT *oval, int32_t *s_k, VT *s_v);
+
 // One wavefront sorts one row of <= 256 entries (up to 4 per lane).  Keys
 // below 2^24 go through the packed bitonic network; otherwise every key's
 // rank is the number of smaller keys, read 16 at a time from LDS.
@@ -227,6 +231,16 @@ __device__ __forceinline__ void wave_sort_row(const LD &ld, int64_t sb, int len,
         }
         return;
     }
+    wave_sort_regs<VT>(mk, mv, len, okey, oval, s_k, s_v);
+}
+
+// The sorting part of wave_sort_row, on a row already in registers (entry
+// e = q * WAVE + lane in mk[q], mv[q], padding INT32_MAX); s_k and s_v are
+// the wavefront's staging area (free on entry).
+template <typename VT>
+__device__ __forceinline__ void wave_sort_regs(const int32_t (&mk)[4], const VT (&mv)[4], int len, int32_t *okey,
+                                               VT *oval, int32_t *s_k, VT *s_v) {
+    const int l = lane_id();
     bool wide = false;
 #pragma unroll
     for (int q = 0; q < 4; q++) wide |= q * WAVE + l < len && (uint32_t)mk[q] >= (1u << 24);

@@ -39,6 +39,10 @@ constexpr int64_t ASG_LONG = 512;
 constexpr int64_t ASG_HUGE = 65536;
 
 constexpr int FSUM_SLOTS = 64;   // spread partial sums of k_fused_counts (one 64-byte line each)
+// The one-wavefront-a-row merge (k_asg_merge_row) holds B's row in AS_MQ
+// 64-wide register slices; in the fused form it also sorts the merged row
+// when it has at most AS_MQ * WAVE entries.
+constexpr int AS_MQ = 4;
 
 struct AsgLayout {
     DevHdr *hdr;
@@ -85,13 +89,24 @@ AsgLayout asg_layout(Carve &c, int64_t m, int64_t n, int64_t nnzA, bool fused = 
 }
 
 // Fused form, after the counts: the rows of I get the top bit of their
-// count (the sort pass must order them whatever their length).
+// count (the sort pass must order them whatever their length), and
+// selfs[r] = 1 when the exec's merge sorts the row itself: selfsort (the
+// one-wavefront-a-row merge runs) and at most WAVE A entries and AS_MQ *
+// WAVE entries after the merge, the rows that merge keeps in registers.
+// selfs is the count pass's force array, which the fused form has no
+// other use for.
+template <typename PT>
 __global__ __launch_bounds__(256) void k_fused_mark(const int32_t *__restrict__ I, int64_t nI, int64_t m,
-                                                   int32_t *cnt, const DevHdr *hdr) {
+                                                   const PT *__restrict__ arow, int32_t *cnt, uint8_t *selfs,
+                                                   int selfsort, const DevHdr *hdr) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= nI || hdr->err) return;
     const int32_t r = I[t];
-    if (r >= 0 && r < m) cnt[r] = (int32_t)((uint32_t)cnt[r] | 0x80000000u);
+    if (r >= 0 && r < m) {
+        const int32_t c = cnt[r];
+        cnt[r] = (int32_t)((uint32_t)c | 0x80000000u);
+        selfs[r] = (selfsort && (int64_t)(arow[r + 1] - arow[r]) <= WAVE && c <= AS_MQ * WAVE) ? 1 : 0;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_fused_check(int64_t m, int64_t n, const int32_t *__restrict__ pinv,
@@ -103,11 +118,13 @@ __global__ __launch_bounds__(256) void k_fused_check(int64_t m, int64_t n, const
 // inverse permutations (pinv[p[i]] = i, qinv[q[i]] = i) and take the row's
 // count.  The sort pass orders the merged rows (rows of I, flag 2) in place
 // and fills rows outside I longer than THREAD_MAX (flag 1) straight from A;
-// shorter rows outside I (flag 0) are pulled by k_fused_fill_short.
+// shorter rows outside I (flag 0) are pulled by k_fused_fill_short; merged
+// rows the merge sorts itself (flag 3) are left alone.
 __global__ __launch_bounds__(256) void k_fused_counts(const int32_t *__restrict__ p, const int32_t *__restrict__ q,
                                                      int64_t m, int64_t n, const int32_t *__restrict__ cnt,
-                                                     int32_t *pinv, int32_t *qinv, int32_t *cnt_out,
-                                                     uint8_t *fflag, unsigned long long *fsum, DevHdr *hdr) {
+                                                     const uint8_t *__restrict__ selfs, int32_t *pinv,
+                                                     int32_t *qinv, int32_t *cnt_out, uint8_t *fflag,
+                                                     unsigned long long *fsum, DevHdr *hdr) {
     __shared__ uint64_t s_part[2][256 / WAVE];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     uint64_t rest = 0, shrt = 0;
@@ -119,9 +136,9 @@ __global__ __launch_bounds__(256) void k_fused_counts(const int32_t *__restrict_
         const uint32_t c = ok ? (uint32_t)cnt[r] : 0u;
         const int32_t len = (int32_t)(c & 0x7FFFFFFFu);
         cnt_out[i] = len;
-        const uint8_t f = (c >> 31) ? 2 : (len > (int32_t)THREAD_MAX ? 1 : 0);
+        const uint8_t f = (c >> 31) ? (selfs[r] ? 3 : 2) : (len > (int32_t)THREAD_MAX ? 1 : 0);
         fflag[i] = f;
-        if (f != 2) rest = (uint64_t)len;
+        if (f < 2) rest = (uint64_t)len;
         if (f == 0 && len <= 4) shrt = (uint64_t)len;
     }
     // entries of the rows outside I and of those with at most 4 entries
@@ -739,7 +756,6 @@ __device__ __forceinline__ T read_lane(T x, int a) {
 // 40 VGPRs (eight wavefronts a SIMD) where the 16-lane merge needs 155.
 // Rows with more than WAVE A entries or AS_MQ * WAVE B entries, or (plain
 // form) mapped B columns out of order, go to llist.
-constexpr int AS_MQ = 4;
 template <typename PT, typename VT>
 __global__ __launch_bounds__(256) void k_asg_merge_row(
     const PT *__restrict__ arow, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
@@ -747,6 +763,7 @@ __global__ __launch_bounds__(256) void k_asg_merge_row(
     const int32_t *__restrict__ I, int64_t nI, const int32_t *__restrict__ J, int64_t nJ,
     const int32_t *__restrict__ colinv, int64_t n, int op, const PT *__restrict__ crow, int32_t *ccol, VT *cval,
     int32_t *llist, uint32_t *lcount, int jrange, const DevHdr *hdr, OutMap om = OutMap{nullptr, nullptr, 0}) {
+    __shared__ __align__(16) SegSmemWave sm;   // the fused form's row sort
     if (hdr->err) return;
     const int l = lane_id();
     const int64_t i = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
@@ -816,6 +833,39 @@ __global__ __launch_bounds__(256) void k_asg_merge_row(
 #pragma unroll
         for (int q = 0; q < AS_MQ; q++) mc[q] = om.col(q * WAVE + l < Lb ? bk[q] : 0);
         const int32_t ma = om.col(mykept ? ak : 0);
+        const int nout = (int)Lb + __popcll(kept);
+        if (nout <= AS_MQ * WAVE) {
+            // the whole merged row fits this wavefront's sort (the plan
+            // flagged it 3, so the sort pass leaves it alone): stage it in
+            // LDS in merged order, take it back four entries a lane, sort
+            int32_t *s_k = sm.k[threadIdx.x / WAVE];
+            VT *s_v = reinterpret_cast<VT *>(sm.v[threadIdx.x / WAVE]);
+#pragma unroll
+            for (int q = 0; q < AS_MQ; q++) {
+                const int t = q * WAVE + l;
+                if (t < Lb) {
+                    s_k[t] = mc[q];
+                    s_v[t] = bv[q];
+                }
+            }
+            if (mykept) {
+                const int pos = (int)Lb + __popcll(kept & lanemask_lt());
+                s_k[pos] = ma;
+                s_v[pos] = av;
+            }
+            __builtin_amdgcn_wave_barrier();
+            int32_t mk[AS_MQ];
+            VT mv[AS_MQ];
+#pragma unroll
+            for (int q = 0; q < AS_MQ; q++) {
+                const int e = q * WAVE + l;
+                mk[q] = e < nout ? s_k[e] : INT32_MAX;
+                mv[q] = e < nout ? s_v[e] : VT(0);
+            }
+            __builtin_amdgcn_wave_barrier();
+            wave_sort_regs<VT>(mk, mv, nout, ccol + d, cval + d, s_k, s_v);
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < AS_MQ; q++) {
             const int64_t t = q * WAVE + l;
@@ -1122,9 +1172,11 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
     if (e == hipSuccess && fused) {
         const int64_t hi = std::max(m, n);
         if (nI > 0)
-            hipLaunchKernelGGL(k_fused_mark, dim3(gridn(nI)), dim3(256), 0, s, I, nI, m, L.cnt, L.hdr);
+            hipLaunchKernelGGL(k_fused_mark<PT>, dim3(gridn(nI)), dim3(256), 0, s, I, nI, m, (const PT *)A->rowptr,
+                               L.cnt, L.force, (int)(B->nnz > (int64_t)WAVE * nI), L.hdr);
         launch_clear_words(s, L.fsum, FSUM_SLOTS * 2 * 8 * 2);
-        hipLaunchKernelGGL(k_fused_counts, dim3(gridn(m)), dim3(256), 0, s, p, nullptr, m, n, L.cnt, L.pinv, L.qinv,
+        hipLaunchKernelGGL(k_fused_counts, dim3(gridn(m)), dim3(256), 0, s, p, nullptr, m, n, L.cnt,
+                           (const uint8_t *)L.force, L.pinv, L.qinv,
                            L.cnt_out, L.fflag, L.fsum, L.hdr);
         hipLaunchKernelGGL(k_fused_sum, dim3(1), dim3(64), 0, s, (const unsigned long long *)L.fsum, L.hdr);
         if (!sym) hipLaunchKernelGGL(k_fused_qinv, dim3(gridn(n)), dim3(256), 0, s, q, n, L.qinv, L.hdr);
