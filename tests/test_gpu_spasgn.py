@@ -99,6 +99,26 @@ def test_long_B_rows_one_wavefront_a_row(hp, op, ptr, vdt):
         assert_same(Cf, oracle.permute((m, n) + tuple(ref), p, q), f"fused, {name}, {op}")
 
 
+def test_fused_row_sort_wide_columns(hp):
+    """The fused merge's own row sort with mapped columns at or above 2^24
+    (the wavefront sort ranks by counting instead of packing key and
+    position): more than 2^24 columns, long B rows, whole output against
+    the oracle."""
+    m, n = 300, (1 << 24) + 5000
+    A = mixed_csr(97, m, n, [0, 2, 9, 40], torch.int64, torch.float64)
+    rng = np.random.default_rng(98)
+    nI, nJ = 120, 30000
+    I = _t(rng.choice(m, nI, replace=False))
+    J = _t(rng.choice(n, nJ, replace=False))
+    B = mixed_csr(99, nI, nJ, [0, 70, 130, 200, 256], torch.int64, torch.float64)
+    assert B.nnz > 64 * nI
+    p = synth.randperm(100, m, "cuda")
+    q = synth.randperm(101, n, "cuda")
+    ref = oracle.spasgn(A, B, I, J, "second")
+    Cf = np_csr(hp.spasgn_permute(A, B, I, J, p, q, "second"))
+    assert_same(Cf, oracle.permute((m, n) + tuple(ref), p, q), "fused, wide columns")
+
+
 @pytest.mark.parametrize("op", OPS)
 def test_long_rows_fallback(hp, op):
     m, n = 300, 6000
