@@ -295,21 +295,31 @@ __global__ __launch_bounds__(256) void k_asg_count_I(const PT *__restrict__ arow
         base = __shfl(base, 0, WAVE);
         if (lng) llist[base + __popcll(lm & lanemask_lt())] = (int32_t)i;
     }
+    // B's columns: for the collision test, and (J not a range) to check
+    // their mapped order; REPLACE over a range of J needs neither
+    const bool replace = op == HP_OP_REPLACE;
+    const bool needb = !replace || !jrange;
     int32_t bc[AS_G];
 #pragma unroll
     for (int q = 0; q < AS_G; q++) {
         const int64_t t = q * AS_G + x;
-        bc[q] = small && t < Lb ? bcol[bs + t] : INT32_MIN;
+        bc[q] = needb && small && t < Lb ? bcol[bs + t] : INT32_MIN;
     }
     int32_t jb = -1;
     if (small && x < La) jb = colinv[clampc(acol[as + x], n)];
-    const bool replace = op == HP_OP_REPLACE;
+    // the loop stops at the longest A row among the wavefront's four rows;
+    // REPLACE keeps exactly the A entries outside J, whatever B holds
+    int amax = small ? (int)La : 0;
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) amax = max(amax, __shfl_xor(amax, off, WAVE));
     int nak = 0;
-    for (int a = 0; a < AS_G; a++) {
+    for (int a = 0; a < amax; a++) {
         const int32_t ja = __shfl(jb, g * AS_G + a, WAVE);
         bool hit = false;
+        if (!replace) {
 #pragma unroll
-        for (int q = 0; q < AS_G; q++) hit |= bc[q] == ja;
+            for (int q = 0; q < AS_G; q++) hit |= bc[q] == ja;
+        }
         const bool ghit = ((ballot(hit) >> (g * AS_G)) & 0xffffull) != 0;
         const bool kept = ja < 0 || (!replace && !ghit);
         nak += (small && a < La && kept) ? 1 : 0;
