@@ -54,6 +54,13 @@ def test_helpers(env):
     for gr, gc in [(8, 8), (1, 1), (3, 5), (64, 64)]:
         got = h.block_nnz(A, gr, gc).cpu().numpy()
         assert np.array_equal(got, _block_counts(A, gr, gc)), (gr, gc)
+    # more grid rows than matrix rows (empty grid rows), and a matrix of
+    # several entry chunks per wavefront with empty rows
+    from tests._gpu import mixed_csr
+    for Am, gr, gc in [(mixed_csr(3, 5, 40, [0, 7, 40]), 8, 3),
+                       (mixed_csr(4, 3000, 500, [0, 0, 1, 90, 300], torch.int64), 7, 9)]:
+        got = h.block_nnz(Am, gr, gc).cpu().numpy()
+        assert np.array_equal(got, _block_counts(Am, gr, gc)), (gr, gc)
     with pytest.raises(hp.HPError):
         h.block_nnz(A, 65, 64)
 
