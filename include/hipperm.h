@@ -250,6 +250,8 @@ hp_status_t hp_spref_dcsc_exec(hp_handle_t h, const hp_dcsc_t *A, const int32_t 
 /* I, J: distinct indices (Sec. 2.3) of lengths B->nrows and B->ncols.
  * A and B share ptr_type and val_type.  C: caller sets nrows=m, ncols=n,
  * types equal to A's, rowptr (m+1).
+ * The workspace size depends on A's shape and nnz and on nnz(B) (B must be
+ * given; its arrays are not read).
  * Errors: INDEX_RANGE, DUPLICATE_INDEX, SHAPE, OVERFLOW, WORKSPACE, ALIAS. */
 hp_status_t hp_spasgn_workspace(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B,
                                 size_t *bytes);

@@ -54,14 +54,25 @@ struct AsgLayout {
     uint8_t *force;
     uint32_t *lists;
     int32_t *llist;        // rows of B whose A row is too long for the one-thread count
-    uint32_t *lcount;      // [0]: llist entries, [1]: rlong entries, [2]: rhuge entries
+    uint32_t *lcount;      // [0]: llist entries, [1]: rlong entries, [2]: rhuge entries, [3]: hlist entries
+    int32_t *hlist;        // rows of I with more than AS_HUGE A + B entries (the whole grid each)
+    uint32_t *hcur;        // exec: placement cursor of the kept A entries of each hlist row
+    int64_t hcap;
     int32_t *rlong;        // rows outside I of ASG_LONG+1..ASG_HUGE entries (a workgroup each)
     int32_t *rhuge;        // rows outside I longer than ASG_HUGE (the whole grid each)
 };
 
 // The fused form always reserves qinv, so its workspace size does not depend
 // on q; the symmetric form (q null) then uses pinv for both maps.
-AsgLayout asg_layout(Carve &c, int64_t m, int64_t n, int64_t nnzA, bool fused = false, bool sym = false) {
+// Rows of I with more than AS_HUGE A + B entries are merged (and counted) by
+// every workgroup together instead of one wavefront: a single wavefront
+// walking a hub row's tens of thousands of entries, each with a binary
+// search of the other row, was the tail of the whole pass.  At most
+// (nnz(A) + nnz(B)) / AS_HUGE rows qualify.
+constexpr int64_t AS_HUGE = 4096;
+
+AsgLayout asg_layout(Carve &c, int64_t m, int64_t n, int64_t nnzA, int64_t nnzB, bool fused = false,
+                     bool sym = false) {
     AsgLayout L;
     L.pinv = L.qinv = L.cnt_out = nullptr;
     L.fflag = nullptr;
@@ -77,6 +88,9 @@ AsgLayout asg_layout(Carve &c, int64_t m, int64_t n, int64_t nnzA, bool fused = 
     L.lcount = c.take<uint32_t>(64);
     L.rlong = c.take<int32_t>(std::min<int64_t>(m, nnzA / ASG_LONG) + 1);
     L.rhuge = c.take<int32_t>(std::min<int64_t>(m, nnzA / ASG_HUGE) + 1);
+    L.hcap = std::min<int64_t>(m, (nnzA + nnzB) / AS_HUGE) + 1;
+    L.hlist = c.take<int32_t>(L.hcap);
+    L.hcur = c.take<uint32_t>(L.hcap);
     if (fused) {
         L.pinv = c.take<int32_t>(m + 1);
         L.qinv = c.take<int32_t>(n + 1);
@@ -407,12 +421,25 @@ __device__ void asg_row_I(
     const VT *__restrict__ aval, const PT *__restrict__ brow, const int32_t *__restrict__ bcol,
     const VT *__restrict__ bval, const int32_t *__restrict__ I, const int32_t *__restrict__ J, int64_t nJ,
     const int32_t *__restrict__ colinv, int64_t n, int op, const PT *__restrict__ crow, int32_t *ccol,
-    VT *cval, int32_t *cnt, uint8_t *force, OutMap om = OutMap{nullptr, nullptr, 0}) {
+    VT *cval, int32_t *cnt, uint8_t *force, OutMap om = OutMap{nullptr, nullptr, 0}, int32_t *hlist = nullptr,
+    uint32_t *hcount = nullptr) {
     const int l = lane_id();
     const int64_t r = I[i];
     const int64_t as = arow[r], La = arow[r + 1] - as;
     const int64_t bs = brow[i], Lb = brow[i + 1] - bs;
     const bool replace = op == HP_OP_REPLACE, plus = op == HP_OP_PLUS;
+    if (hlist && La + Lb > AS_HUGE) {
+        // left to k_asg_rows_huge (every workgroup on the row); the count
+        // starts at B's entries, the kept A entries are added there
+        if (l == 0) {
+            hlist[atomicAdd(hcount, 1u)] = (int32_t)i;
+            if (COUNT) {
+                cnt[r] = (int32_t)Lb;
+                force[r] = 1;
+            }
+        }
+        return;
+    }
 
     if (COUNT && La * 16 <= Lb && La + Lb > AS_WCAP) {
         // few A entries against a long B row: binary-search B in memory
@@ -587,14 +614,85 @@ __global__ __launch_bounds__(256) void k_asg_rows_list(
     const int32_t *__restrict__ I, const int32_t *__restrict__ J, int64_t nJ,
     const int32_t *__restrict__ colinv, int64_t n, int op, const PT *__restrict__ crow, int32_t *ccol,
     VT *cval, int32_t *cnt, uint8_t *force, const int32_t *__restrict__ llist, const uint32_t *__restrict__ lcount,
-    const DevHdr *hdr, OutMap om = OutMap{nullptr, nullptr, 0}) {
+    const DevHdr *hdr, OutMap om = OutMap{nullptr, nullptr, 0}, int32_t *hlist = nullptr,
+    uint32_t *hcount = nullptr) {
     __shared__ __align__(16) RowSmem sm_all[4];
     if (hdr->err) return;
     const int w = threadIdx.x / WAVE;
     const uint32_t nl = *lcount;
     for (uint32_t t = blockIdx.x * 4 + w; t < nl; t += gridDim.x * 4)
         asg_row_I<PT, VT, COUNT>(llist[t], sm_all[w], arow, acol, aval, brow, bcol, bval, I, J, nJ, colinv, n, op,
-                                 crow, ccol, cval, cnt, force, om);
+                                 crow, ccol, cval, cnt, force, om, hlist, hcount);
+}
+
+// Rows of hlist (more than AS_HUGE A + B entries), one after another, each
+// spread over every wavefront of the grid: A's entries are tested against
+// B's row by binary search as in the long-row path, kept ones counted into
+// cnt[r] (COUNT) or placed through the row's cursor hcur[h] in any order
+// (the row is sorted afterwards, its force flag set); B' entries go after
+// the kept A entries, at their own offset.  Wave-uniform loop bounds keep
+// every lane in the ballots.
+template <typename PT, typename VT, bool COUNT>
+__global__ __launch_bounds__(256) void k_asg_rows_huge(
+    const PT *__restrict__ arow, const int32_t *__restrict__ acol, const VT *__restrict__ aval,
+    const PT *__restrict__ brow, const int32_t *__restrict__ bcol, const VT *__restrict__ bval,
+    const int32_t *__restrict__ I, const int32_t *__restrict__ J, int64_t nJ,
+    const int32_t *__restrict__ colinv, int64_t n, int op, const PT *__restrict__ crow, int32_t *ccol,
+    VT *cval, int32_t *cnt, const int32_t *__restrict__ hlist, const uint32_t *__restrict__ hcount,
+    uint32_t *hcur, const DevHdr *hdr, OutMap om = OutMap{nullptr, nullptr, 0}) {
+    if (hdr->err) return;
+    const int l = lane_id();
+    const int64_t gw = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
+    const int64_t nw = (int64_t)gridDim.x * (256 / WAVE);
+    const bool replace = op == HP_OP_REPLACE, plus = op == HP_OP_PLUS;
+    const uint32_t nh = *hcount;
+    for (uint32_t h = 0; h < nh; h++) {
+        const int64_t i = hlist[h];
+        const int64_t r = I[i];
+        const int64_t as = arow[r], La = arow[r + 1] - as;
+        const int64_t bs = brow[i], Lb = brow[i + 1] - bs;
+        const int32_t *ac = acol + as;
+        const int32_t *bc = bcol + bs;
+        int64_t d = 0, nak = 0;
+        if (!COUNT) {
+            const int64_t orow = om.row(r);
+            d = (int64_t)crow[orow];
+            nak = (int64_t)crow[orow + 1] - d - Lb;   // kept A entries, from the plan's count
+        }
+        for (int64_t a0 = gw * WAVE; a0 < La; a0 += nw * WAVE) {
+            const int64_t a = a0 + l;
+            bool kept = false;
+            if (a < La) {
+                const int32_t jb = colinv[clampc(ac[a], n)];
+                kept = replace ? jb < 0 : (jb < 0 || find_n(bc, Lb, jb) < 0);
+            }
+            const uint64_t msk = ballot(kept);
+            if (!msk) continue;
+            if (COUNT) {
+                if (l == 0) atomicAdd(&cnt[r], (int32_t)__popcll(msk));
+            } else {
+                uint32_t base = 0;
+                if (l == 0) base = atomicAdd(&hcur[h], (uint32_t)__popcll(msk));
+                base = __shfl(base, 0, WAVE);
+                const int64_t pos = base + __popcll(msk & lanemask_lt());
+                if (kept && pos < nak) {   // within the planned count
+                    ccol[d + pos] = om.col(ac[a]);
+                    cval[d + pos] = aval[as + a];
+                }
+            }
+        }
+        if (COUNT) continue;
+        for (int64_t t = gw * WAVE + l; t < Lb; t += nw * WAVE) {
+            const int32_t key = J[clampc(bc[t], nJ)];
+            VT v = bval[bs + t];
+            if (plus) {
+                const int64_t p = find_n(ac, La, key);
+                if (p >= 0) v = vadd(aval[as + p], v);
+            }
+            ccol[d + nak + t] = om.col(key);
+            cval[d + nak + t] = v;
+        }
+    }
 }
 
 // Merge pass, 16 lanes per row of B as in the count: the group holds B's
@@ -1131,7 +1229,7 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
     const int64_t m = A->nrows, n = A->ncols, nI = B->nrows, nJ = B->ncols;
     const bool sym = fused && q == nullptr;
     Carve need(nullptr);
-    asg_layout(need, m, n, A->nnz, fused, sym);
+    asg_layout(need, m, n, A->nnz, B->nnz, fused, sym);
     if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "spasgn plan workspace too small");
     const size_t ps = sizeof(PT), vs = sizeof(VT);
     const void *ins[] = {A->rowptr, A->col, A->val, B->rowptr, B->col, B->val, I, J, p, q};
@@ -1144,7 +1242,7 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
     if (overlaps(C->rowptr, (m + 1) * ps, ws, ws_bytes))
         return fail(h, HP_ERR_ALIAS, "C->rowptr overlaps the workspace");
     Carve c(ws);
-    AsgLayout L = asg_layout(c, m, n, A->nnz, fused, sym);
+    AsgLayout L = asg_layout(c, m, n, A->nnz, B->nnz, fused, sym);
     hipStream_t s = h->stream;
     if (hp_status_t v = validate_input(h, A, L.hdr, "spasgn plan: A")) return v;
     if (hp_status_t v = validate_input(h, B, L.hdr, "spasgn plan: B")) return v;
@@ -1163,7 +1261,7 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
         hipLaunchKernelGGL(k_asg_dup, dim3(gridn(hi)), dim3(256), 0, s, I, nI, J, nJ, m, n, L.rowinv,
                            L.colinv, L.hdr);
         stage_mark(h, "asgn.tables");
-        e = launch_clear_words(s, L.lcount, 3);
+        e = launch_clear_words(s, L.lcount, 4);   // llist, rlong, rhuge and hlist counts
         hipLaunchKernelGGL(k_asg_count_rest<PT>, dim3(gridn(m)), dim3(256), 0, s, (const PT *)A->rowptr, m,
                            L.rowinv, L.cnt, L.force, L.rlong, L.rhuge, L.lcount + 1, L.hdr);
         if (nI > 0) {
@@ -1174,7 +1272,12 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
                                dim3(256), 0, s, (const PT *)A->rowptr, A->col, (const VT *)A->val,
                                (const PT *)B->rowptr, B->col, (const VT *)B->val, I, J, nJ, L.colinv, n, (int)op,
                                (const PT *)nullptr, (int32_t *)nullptr, (VT *)nullptr, L.cnt, L.force, L.llist,
-                               L.lcount, L.hdr);
+                               L.lcount, L.hdr, OutMap{nullptr, nullptr, 0}, L.hlist, L.lcount + 3);
+            hipLaunchKernelGGL((k_asg_rows_huge<PT, VT, true>), dim3(1024), dim3(256), 0, s, (const PT *)A->rowptr,
+                               A->col, (const VT *)A->val, (const PT *)B->rowptr, B->col, (const VT *)B->val, I, J,
+                               nJ, L.colinv, n, (int)op, (const PT *)nullptr, (int32_t *)nullptr, (VT *)nullptr,
+                               L.cnt, (const int32_t *)L.hlist, (const uint32_t *)(L.lcount + 3), L.hcur, L.hdr,
+                               OutMap{nullptr, nullptr, 0});
         }
         stage_mark(h, "asgn.count");
         e = hipGetLastError();
@@ -1235,7 +1338,7 @@ hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
     const int64_t m = A->nrows, n = A->ncols, nI = B->nrows, nJ = B->ncols;
     const bool sym = fused && q == nullptr;
     Carve need(nullptr);
-    asg_layout(need, m, n, A->nnz, fused, sym);
+    asg_layout(need, m, n, A->nnz, B->nnz, fused, sym);
     if (!ws || ws_bytes < need.size()) return fail(h, HP_ERR_WORKSPACE, "spasgn workspace too small");
     if (!info || info->op != (fused ? 4 : 3) || info->aux[0] != (int64_t)op)
         return fail(h, HP_ERR_INVALID_ARG,
@@ -1258,7 +1361,7 @@ hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
             overlaps(C->val, (size_t)C->nnz * vs, ins[k], insz[k]))
             return fail(h, HP_ERR_ALIAS, "C->col/val overlaps an input or workspace");
     Carve c(ws);
-    AsgLayout L = asg_layout(c, m, n, A->nnz, fused, sym);
+    AsgLayout L = asg_layout(c, m, n, A->nnz, B->nnz, fused, sym);
     const OutMap om{L.pinv, L.qinv, n};   // null maps for the plain assignment
     hipStream_t s = h->stream;
     stage_begin(h);
@@ -1285,7 +1388,9 @@ hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
                            (VT *)C->val, L.hdr, om);
     stage_mark(h, "asgn.copy");
     if (nI > 0) {
-        launch_clear_words(s, L.lcount, 1);
+        launch_clear_words(s, L.lcount, 1);       // llist (rlong/rhuge counts stay from the plan)
+        launch_clear_words(s, L.lcount + 3, 1);   // hlist
+        launch_clear_words(s, L.hcur, (size_t)L.hcap);
         if (B->nnz > (int64_t)WAVE * nI)   // long B rows: one wavefront per row
             hipLaunchKernelGGL((k_asg_merge_row<PT, VT>), dim3(gridn(nI, 256 / WAVE)), dim3(256), 0, s,
                                (const PT *)A->rowptr, A->col, (const VT *)A->val, (const PT *)B->rowptr, B->col,
@@ -1299,7 +1404,11 @@ hp_status_t asg_exec_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
         hipLaunchKernelGGL((k_asg_rows_list<PT, VT, false>), dim3((unsigned)std::min<int64_t>(gridn(nI, 4), 1024)),
                            dim3(256), 0, s, (const PT *)A->rowptr, A->col, (const VT *)A->val, (const PT *)B->rowptr,
                            B->col, (const VT *)B->val, I, J, nJ, L.colinv, n, (int)op, (const PT *)C->rowptr, C->col,
-                           (VT *)C->val, L.cnt, L.force, L.llist, L.lcount, L.hdr, om);
+                           (VT *)C->val, L.cnt, L.force, L.llist, L.lcount, L.hdr, om, L.hlist, L.lcount + 3);
+        hipLaunchKernelGGL((k_asg_rows_huge<PT, VT, false>), dim3(1024), dim3(256), 0, s, (const PT *)A->rowptr,
+                           A->col, (const VT *)A->val, (const PT *)B->rowptr, B->col, (const VT *)B->val, I, J, nJ,
+                           L.colinv, n, (int)op, (const PT *)C->rowptr, C->col, (VT *)C->val, L.cnt,
+                           (const int32_t *)L.hlist, (const uint32_t *)(L.lcount + 3), L.hcur, L.hdr, om);
     }
     stage_mark(h, "asgn.merge");
     hipError_t e = hipGetLastError();
@@ -1332,9 +1441,9 @@ extern "C" hp_status_t hp_spasgn_workspace(hp_handle_t h, const hp_csr_t *A, con
     if (!h || !bytes) return HP_ERR_INVALID_ARG;
     hp_status_t st = check_csr_args(h, A, "A");
     if (st) return st;
-    (void)B;
+    if (!B) return fail(h, HP_ERR_INVALID_ARG, "B is NULL (the workspace depends on nnz(B))");
     Carve c(nullptr);
-    asg_layout(c, A->nrows, A->ncols, A->nnz);
+    asg_layout(c, A->nrows, A->ncols, A->nnz, B->nnz);
     *bytes = c.size();
     return HP_OK;
 }
@@ -1383,9 +1492,9 @@ extern "C" hp_status_t hp_spasgn_permute_workspace(hp_handle_t h, const hp_csr_t
     if (!h || !bytes) return HP_ERR_INVALID_ARG;
     hp_status_t st = check_csr_args(h, A, "A");
     if (st) return st;
-    (void)B;
+    if (!B) return fail(h, HP_ERR_INVALID_ARG, "B is NULL (the workspace depends on nnz(B))");
     Carve c(nullptr);
-    asg_layout(c, A->nrows, A->ncols, A->nnz, true, false);
+    asg_layout(c, A->nrows, A->ncols, A->nnz, B->nnz, true, false);
     *bytes = c.size();
     return HP_OK;
 }

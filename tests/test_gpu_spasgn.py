@@ -122,6 +122,28 @@ def test_fused_row_sort_wide_columns(hp):
 
 
 @pytest.mark.parametrize("op", OPS)
+def test_huge_rows_whole_grid(hp, op):
+    """Rows of I with more than 4096 A + B entries are counted and merged by
+    every workgroup together: huge A rows against short B rows and the
+    reverse, several huge rows in one call, sorted and unsorted J, plain and
+    fused, whole output against the oracle."""
+    m, n = 60, 20000
+    A = mixed_csr(111, m, n, [0, 5, 6000, 9000, 40], torch.int64, torch.float64)
+    rng = np.random.default_rng(112)
+    nI, nJ = 30, 15000
+    I = _t(rng.choice(m, nI, replace=False))
+    p = synth.randperm(113, m, "cuda")
+    q = synth.randperm(114, n, "cuda")
+    for J, name in ((_t(rng.choice(n, nJ, replace=False)), "unsorted J"),
+                    (_t(np.sort(rng.choice(n, nJ, replace=False))), "sorted J")):
+        B = mixed_csr(115, nI, nJ, [0, 3, 5000, 8000, 100], torch.int64, torch.float64)
+        ref = oracle.spasgn(A, B, I, J, op)
+        assert_same(np_csr(hp.spasgn(A, B, I, J, op)), ref, f"{name}, {op}")
+        Cf = np_csr(hp.spasgn_permute(A, B, I, J, p, q, op))
+        assert_same(Cf, oracle.permute((m, n) + tuple(ref), p, q), f"fused, {name}, {op}")
+
+
+@pytest.mark.parametrize("op", OPS)
 def test_long_rows_fallback(hp, op):
     m, n = 300, 6000
     A = mixed_csr(31, m, n, [0, 3, 100, 250, 700, 5000])
