@@ -695,11 +695,22 @@ __device__ void seg_bucket_tile(int64_t bid, SegSmemBucket &sm, const PT *__rest
     VT *yv = tval + goff[t];
     for (int i = threadIdx.x; i <= nb; i += 256) s_h[i] = 0;
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < len; i += 256) {
-        int32_t kk;
-        VT vv;
-        ld.get(sb, i, kk, vv);
-        atomicAdd(&s_h[(uint32_t)kk >> BKT_SHIFT], 1u);
+    // BKT_U entries per thread and round, their loads (and a renaming
+    // loader's lookups) issued together: indexes are clamped to the row
+    // (len >= 1) and the extra lanes masked afterwards.  One entry per round
+    // left a hub row of 67K entries at two dependent loads per 256 entries.
+    constexpr int BKT_U = 8;
+    for (int64_t i0 = 0; i0 < len; i0 += 256 * BKT_U) {
+        int32_t kk[BKT_U];
+        VT vv[BKT_U];
+#pragma unroll
+        for (int u = 0; u < BKT_U; u++) {
+            const int64_t i = i0 + u * 256 + threadIdx.x;
+            ld.get(sb, i < len ? i : len - 1, kk[u], vv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < BKT_U; u++)
+            if (i0 + u * 256 + threadIdx.x < len) atomicAdd(&s_h[(uint32_t)kk[u] >> BKT_SHIFT], 1u);
     }
     __syncthreads();
     // exclusive scan of the histogram, 256 threads over nb+1 counters
@@ -721,13 +732,21 @@ __device__ void seg_bucket_tile(int64_t bid, SegSmemBucket &sm, const PT *__rest
         }
     }
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < len; i += 256) {
-        int32_t kk;
-        VT vv;
-        ld.get(sb, i, kk, vv);
-        const uint32_t pos = atomicAdd(&s_h[(uint32_t)kk >> BKT_SHIFT], 1u);
-        yk[pos] = kk;
-        yv[pos] = vv;
+    for (int64_t i0 = 0; i0 < len; i0 += 256 * BKT_U) {
+        int32_t kk[BKT_U];
+        VT vv[BKT_U];
+#pragma unroll
+        for (int u = 0; u < BKT_U; u++) {
+            const int64_t i = i0 + u * 256 + threadIdx.x;
+            ld.get(sb, i < len ? i : len - 1, kk[u], vv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < BKT_U; u++) {
+            if (i0 + u * 256 + threadIdx.x >= len) continue;
+            const uint32_t pos = atomicAdd(&s_h[(uint32_t)kk[u] >> BKT_SHIFT], 1u);
+            yk[pos] = kk[u];
+            yv[pos] = vv[u];
+        }
     }
     __syncthreads();
 }
