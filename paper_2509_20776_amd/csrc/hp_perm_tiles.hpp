@@ -223,20 +223,11 @@ __device__ inline void perm_pack_tile(int64_t bid, const PT *__restrict__ arow, 
     }
 }
 
-// Output rows bid*256 .. +255 of at most 4 entries (one lane each), copied
-// from slot p[i]; the row's length is that of output row i.
-template <typename PT, typename VT>
-__device__ inline void perm_slot_fill_tile(int64_t bid, const int32_t *__restrict__ p, const char *__restrict__ slots,
-                                           const PT *__restrict__ crow, int32_t *__restrict__ ccol,
-                                           VT *__restrict__ cval, int64_t m, const DevHdr *hdr) {
-    if (hdr->err) return;
-    const int64_t i = bid * 256 + threadIdx.x;
-    if (i >= m) return;
-    const int64_t d = crow[i];
-    const int len = (int)(crow[i + 1] - d);
-    if (len == 0 || len > 4) return;
-    const int32_t pr = p[i];
-    const int64_t src = (uint32_t)pr < (uint64_t)m ? (int64_t)pr : 0;   // p was checked by the plan
+// Copy the first len (1..4) entries of the row slot of source row src to
+// output position d.
+template <typename VT>
+__device__ __forceinline__ void perm_slot_copy(const char *__restrict__ slots, int64_t src, int len, int64_t d,
+                                               int32_t *__restrict__ ccol, VT *__restrict__ cval) {
     const char *slot = slots + src * perm_slot_bytes<VT>();
     const uint4 kk = *reinterpret_cast<const uint4 *>(slot);
     VT v[4];
@@ -255,6 +246,25 @@ __device__ inline void perm_slot_fill_tile(int64_t bid, const int32_t *__restric
             ccol[d + u] = k[u];
             cval[d + u] = v[u];
         }
+}
+
+// Output rows bid*256 .. +255 of at most 4 entries (one lane each), copied
+// from slot p[i]; the row's length is that of output row i.
+template <typename PT, typename VT>
+__device__ inline void perm_slot_fill_tile(int64_t bid, const int32_t *__restrict__ p, const char *__restrict__ slots,
+                                           const PT *__restrict__ crow, int32_t *__restrict__ ccol,
+                                           VT *__restrict__ cval, int64_t m, const DevHdr *hdr) {
+    if (hdr->err) return;
+    const int64_t i = bid * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int64_t d = crow[i];
+    const int len = (int)(crow[i + 1] - d);
+    if (len == 0 || len > 4) return;
+    // (loading p[i] together with the row bounds, ahead of this branch, did
+    // not speed the fill up: it is bound by the random slot reads)
+    const int32_t pr = p[i];
+    const int64_t src = (uint32_t)pr < (uint64_t)m ? (int64_t)pr : 0;   // p was checked by the plan
+    perm_slot_copy<VT>(slots, src, len, d, ccol, cval);
 }
 
 }  // namespace perm

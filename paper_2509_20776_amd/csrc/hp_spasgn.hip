@@ -1114,16 +1114,22 @@ __global__ __launch_bounds__(256) void k_fused_fill_short(const int32_t *__restr
                                                          int64_t m, const DevHdr *hdr) {
     if (hdr->err) return;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= m || fflag[i] != 0) return;
+    if (i >= m) return;
+    // the flag, the row bounds and p[i] in one round of loads (the asm
+    // keeps the compiler from sinking each load below the branch before it)
+    const uint8_t f = fflag[i];
     const int64_t d = crow[i];
-    const int len = (int)(crow[i + 1] - d);
+    const int64_t e = crow[i + 1];
+    const int32_t pr = p[i];
+    asm volatile("" ::"v"(d), "v"(e), "v"(pr));
+    if (f != 0) return;
+    const int len = (int)(e - d);
     if (len == 0) return;
+    const int64_t r = (uint32_t)pr < (uint64_t)m ? (int64_t)pr : 0;   // p was checked by the plan
     if (slots && len <= 4) {
-        perm::perm_slot_fill_tile<PT, VT>(blockIdx.x, p, slots, crow, ccol, cval, m, hdr);
+        perm::perm_slot_copy<VT>(slots, r, len, d, ccol, cval);
         return;
     }
-    const int32_t pr = p[i];
-    const int64_t r = (uint32_t)pr < (uint64_t)m ? (int64_t)pr : 0;   // p was checked by the plan
     lane_sort_row<VT>(LoadMapped<VT>{acol, aval, OutMap{nullptr, qinv, n}}, (int64_t)arow[r], len, false, ccol + d,
                       cval + d);
 }
