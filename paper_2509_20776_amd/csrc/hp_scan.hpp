@@ -220,39 +220,44 @@ __device__ __forceinline__ void scan_counts_tile(int64_t tile, ScanSmem &sm, con
                 if (classify == 3 ? f != 0 : (f == 1 || f == 2)) flags |= 1u << k;
             }
         }
-        uint32_t lc[NBINS] = {0, 0, 0, 0};
-        unsigned long long lge = 0;
+        // modes that classify flagged rows only: a tile without one skips the
+        // appends (its barriers included: the test is block-wide)
+        const bool only_flagged = classify == 4 || (classify == 3 && !all);
+        if (!(only_flagged && !__syncthreads_or(flags != 0))) {
+            uint32_t lc[NBINS] = {0, 0, 0, 0};
+            unsigned long long lge = 0;
 #pragma unroll
-        for (int k = 0; k < SCAN_ITEMS; k++) {
-            const int b = base + k < n ? class_of(v[k], classify, all, (flags >> k) & 1u) : -1;
+            for (int k = 0; k < SCAN_ITEMS; k++) {
+                const int b = base + k < n ? class_of(v[k], classify, all, (flags >> k) & 1u) : -1;
 #pragma unroll
-            for (int q = 0; q < NBINS; q++) lc[q] += b == q ? 1u : 0u;
-            if (b == BIN_GLOBAL) lge += (uint32_t)v[k];
-        }
-        uint32_t lb[NBINS];
-#pragma unroll
-        for (int q = 0; q < NBINS; q++) lb[q] = lc[q] ? atomicAdd(&s_bc[q], lc[q]) : 0u;
-        unsigned long long ge = lge ? atomicAdd(&s_ge, lge) : 0ull;
-        __syncthreads();
-        if (threadIdx.x < NBINS && s_bc[threadIdx.x])
-            s_bbase[threadIdx.x] = atomicAdd(&hdr->bin_cnt[threadIdx.x], s_bc[threadIdx.x]);
-        if (threadIdx.x == NBINS && s_ge)
-            s_gbase = atomicAdd((unsigned long long *)&hdr->bin_elems[BIN_GLOBAL], s_ge);
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < SCAN_ITEMS; k++) {
-            const int b = base + k < n ? class_of(v[k], classify, all, (flags >> k) & 1u) : -1;
-            if (b < 0) continue;
-            uint32_t slot = 0;
-#pragma unroll
-            for (int q = 0; q < NBINS; q++)
-                if (b == q) slot = lb[q]++;
-            const uint32_t pos = s_bbase[b] + slot;
-            if (pos < cap) {
-                lists[(int64_t)b * cap + pos] = (uint32_t)(base + k);
-                if (b == BIN_GLOBAL) goff[pos] = s_gbase + ge;
+                for (int q = 0; q < NBINS; q++) lc[q] += b == q ? 1u : 0u;
+                if (b == BIN_GLOBAL) lge += (uint32_t)v[k];
             }
-            if (b == BIN_GLOBAL) ge += (uint32_t)v[k];
+            uint32_t lb[NBINS];
+#pragma unroll
+            for (int q = 0; q < NBINS; q++) lb[q] = lc[q] ? atomicAdd(&s_bc[q], lc[q]) : 0u;
+            unsigned long long ge = lge ? atomicAdd(&s_ge, lge) : 0ull;
+            __syncthreads();
+            if (threadIdx.x < NBINS && s_bc[threadIdx.x])
+                s_bbase[threadIdx.x] = atomicAdd(&hdr->bin_cnt[threadIdx.x], s_bc[threadIdx.x]);
+            if (threadIdx.x == NBINS && s_ge)
+                s_gbase = atomicAdd((unsigned long long *)&hdr->bin_elems[BIN_GLOBAL], s_ge);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < SCAN_ITEMS; k++) {
+                const int b = base + k < n ? class_of(v[k], classify, all, (flags >> k) & 1u) : -1;
+                if (b < 0) continue;
+                uint32_t slot = 0;
+#pragma unroll
+                for (int q = 0; q < NBINS; q++)
+                    if (b == q) slot = lb[q]++;
+                const uint32_t pos = s_bbase[b] + slot;
+                if (pos < cap) {
+                    lists[(int64_t)b * cap + pos] = (uint32_t)(base + k);
+                    if (b == BIN_GLOBAL) goff[pos] = s_gbase + ge;
+                }
+                if (b == BIN_GLOBAL) ge += (uint32_t)v[k];
+            }
         }
     }
     __syncthreads();
