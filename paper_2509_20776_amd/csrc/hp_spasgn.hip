@@ -1149,9 +1149,28 @@ __global__ __launch_bounds__(256) void k_asg_copy_long(const PT *__restrict__ ar
         const int64_t r = rlong[i];
         const int64_t a = arow[r], len = arow[r + 1] - a;
         const int64_t d = crow[om.row(r)];
-        for (int64_t e = threadIdx.x; e < len; e += blockDim.x) {
-            ccol[d + e] = om.col(acol[a + e]);
-            cval[d + e] = aval[a + e];
+        // eight entries a thread per round, the loads (and lookups) issued
+        // together (len > ASG_LONG >= 1)
+        for (int64_t e0 = 0; e0 < len; e0 += 8 * 256) {
+            int32_t kc[8];
+            VT kv[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int64_t e = e0 + u * 256 + threadIdx.x;
+                const int64_t ec = e < len ? e : len - 1;
+                kc[u] = acol[a + ec];
+                kv[u] = aval[a + ec];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) kc[u] = om.col(kc[u]);
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int64_t e = e0 + u * 256 + threadIdx.x;
+                if (e < len) {
+                    ccol[d + e] = kc[u];
+                    cval[d + e] = kv[u];
+                }
+            }
         }
     }
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
