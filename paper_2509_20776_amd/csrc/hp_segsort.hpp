@@ -451,16 +451,24 @@ __device__ __forceinline__ void bitonic_row(const LD &ld, int64_t sb, int len, i
     VT *sv = reinterpret_cast<VT *>(sm.v);
     constexpr W PMASK = (W(1) << PB) - 1;
     W x[E];
+    {
+        // clamped entry indexes (len >= 1): the E loads, and a renaming
+        // loader's lookups, go out together instead of one branch at a time
+        int32_t kk[E];
+        VT vv[E];
 #pragma unroll
-    for (int q = 0; q < E; q++) {
-        const int i = q * T + t;
-        x[q] = ~W(0);
-        if (i < len) {
-            int32_t kk;
-            VT vv;
-            ld.get(sb, i, kk, vv);
-            x[q] = ((W)(uint32_t)kk << PB) | (W)i;
-            sv[i] = vv;
+        for (int q = 0; q < E; q++) {
+            const int i = q * T + t;
+            ld.get(sb, i < len ? i : len - 1, kk[q], vv[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < E; q++) {
+            const int i = q * T + t;
+            x[q] = ~W(0);
+            if (i < len) {
+                x[q] = ((W)(uint32_t)kk[q] << PB) | (W)i;
+                sv[i] = vv[q];
+            }
         }
     }
     bitonic_block<T, E, W>(x, reinterpret_cast<W *>(sm.x));
