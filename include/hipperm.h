@@ -269,7 +269,9 @@ hp_status_t hp_spasgn_exec(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, 
  *   C[i, j] = X[p[i], q[j]],  X = A with A(I, J) = B under op.
  * The paper fuses the two by changing only where entries are sent; here the
  * merge of each row of I writes straight to output row pinv[r] with its
- * columns mapped through qinv and a sort pass orders those rows, while the
+ * columns mapped through qinv and a sort pass orders those rows (when B's
+ * rows average over 64 entries, the merge sorts a row of at most 256
+ * entries itself), while the
  * output rows outside I pull row p[i] of A (renamed, sorted in registers;
  * rows of at most 4 entries from fixed row slots packed first, as in
  * hp_permute_exec, when they hold at least half of the entries outside I).
@@ -278,7 +280,8 @@ hp_status_t hp_spasgn_exec(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, 
  * needs m == n; exec must get q NULL exactly when plan did).
  * C: caller sets nrows=m, ncols=n, types equal to A's, rowptr (m+1); plan
  * writes rowptr and nnz, exec writes col and val.  ws (size from
- * hp_spasgn_permute_workspace, independent of q) must be kept unchanged
+ * hp_spasgn_permute_workspace, independent of q; like hp_spasgn_workspace
+ * it needs B for nnz(B)) must be kept unchanged
  * from plan to exec; xws holds info->exec_ws_bytes (with the row slots),
  * or at least info->aux[3] bytes (then exec runs without them; the result
  * is the same); it may start at any address.
