@@ -176,6 +176,28 @@ def test_empty_and_errors(hp):
     assert ex.value.name == "HP_ERR_SHAPE"
 
 
+def test_workspace_depends_on_B(hp):
+    """The assignment workspaces grow with nnz(B) (the list of rows of I with
+    more than 4096 A + B entries) and refuse a NULL B."""
+    import ctypes
+    from paper_2509_20776_amd import hipperm as H
+    h = H.handle(0)
+    A = mixed_csr(121, 5000, 60, [0, 3, 9])
+    Ac = H.to_csr_t(A)
+    sizes = []
+    for nnzb in (0, 1 << 24):
+        Bc = H.to_csr_t(mixed_csr(122, 5, 6, [0, 1]))
+        Bc.nnz = nnzb   # only the count is read
+        for fn in (H.hp_spasgn_workspace, H.hp_spasgn_permute_workspace):
+            need = ctypes.c_size_t(0)
+            assert fn(h.h, ctypes.byref(Ac), ctypes.byref(Bc), ctypes.byref(need)) == 0
+            sizes.append(need.value)
+    assert sizes[2] > sizes[0] and sizes[3] > sizes[1]
+    for fn in (H.hp_spasgn_workspace, H.hp_spasgn_permute_workspace):
+        need = ctypes.c_size_t(0)
+        assert fn(h.h, ctypes.byref(Ac), None, ctypes.byref(need)) != 0
+
+
 def test_streaming_round_trip(hp):
     """80% of the edges plus four 5% parts assigned back gives A again."""
     A = synth.rmat(11, 8, 9, "rt", symmetric=False, device="cuda")
