@@ -62,6 +62,42 @@ __device__ inline void perm_check_tile(int64_t bid, int64_t m, int64_t n, const 
     if (bad) atomicOr(&hdr->err, E_NOTPERM);   // error path only
 }
 
+// perm_check_tile with four slots a thread and vector loads (the plain
+// kernels: ceil(max(m, n) / 1024) workgroups of 256); the tables start on
+// 256-byte boundaries (pmark is allocated in 32-bit words).
+__device__ __forceinline__ bool any_neg4(const int32_t *__restrict__ a, int64_t t, int64_t len) {
+    if (t + 4 <= len) {
+        const int4 v = *reinterpret_cast<const int4 *>(a + t);
+        return (v.x | v.y | v.z | v.w) < 0;
+    }
+    bool bad = false;
+    for (int k = 0; k < 4; k++)
+        if (t + k < len) bad |= a[t + k] < 0;
+    return bad;
+}
+
+__device__ inline void perm_check4_tile(int64_t bid, int64_t m, int64_t n, const int32_t *__restrict__ pinv,
+                                        const int32_t *__restrict__ qinv, bool general, DevHdr *hdr,
+                                        const uint8_t *__restrict__ pmark = nullptr) {
+    const int64_t t = (bid * 256 + threadIdx.x) * 4;
+    bool bad = false;
+    if (t < m) {
+        if (pmark) {
+            if (t + 4 <= m) {
+                const uint32_t w = *reinterpret_cast<const uint32_t *>(pmark + t);
+                bad |= ((w - 0x01010101u) & ~w & 0x80808080u) != 0;   // a zero byte
+            } else {
+                for (int k = 0; k < 4; k++)
+                    if (t + k < m) bad |= pmark[t + k] == 0;
+            }
+        } else {
+            bad |= any_neg4(pinv, t, m);
+        }
+    }
+    if (general && t < n) bad |= any_neg4(qinv, t, n);
+    if (bad) atomicOr(&hdr->err, E_NOTPERM);   // error path only
+}
+
 // Longer rows: output row i is row p[i] of A with columns mapped (pull).
 template <typename PT, typename VT>
 struct LoadPerm {

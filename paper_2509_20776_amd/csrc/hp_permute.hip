@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_perm_qinv(const int32_t *__restrict__ q
 __global__ __launch_bounds__(256) void k_perm_check(int64_t m, int64_t n, const int32_t *__restrict__ pinv,
                                                    const int32_t *__restrict__ qinv, bool general, DevHdr *hdr,
                                                    const uint8_t *__restrict__ pmark) {
-    perm_check_tile(blockIdx.x, m, n, pinv, qinv, general, hdr, pmark);
+    perm_check4_tile(blockIdx.x, m, n, pinv, qinv, general, hdr, pmark);
 }
 template <typename PT, typename VT>
 __global__ __launch_bounds__(256) void k_perm_pack(const PT *__restrict__ arow, const int32_t *__restrict__ acol,
@@ -145,7 +145,6 @@ hp_status_t perm_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
                                  : launch_fill_words(s, L.pmark, (size_t)(m + 3) / 4, 0u);
     if (e == hipSuccess && !sym) e = launch_fill_words(s, L.qinv, (size_t)n, 0xFFFFFFFFu);
     const int64_t hi = m > n ? m : n;
-    const int grid = (int)std::max<int64_t>(1, (hi + 255) / 256);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_perm_prepare<PT>, dim3((unsigned)std::max<int64_t>(1, (m + 255) / 256)), dim3(256), 0,
                            s, (const PT *)A->rowptr, p, nullptr, m, n, L.pinv, L.qinv, L.cnt, L.hdr, L.pmark);
@@ -153,7 +152,8 @@ hp_status_t perm_plan_t(hp_handle_t h, const hp_csr_t *A, const int32_t *p, cons
             hipLaunchKernelGGL(k_perm_qinv, dim3((unsigned)std::max<int64_t>(1, (n + 255) / 256)), dim3(256), 0, s,
                                q, n, L.qinv, L.hdr);
         stage_mark(h, "perm.prepare");
-        hipLaunchKernelGGL(k_perm_check, dim3(grid), dim3(256), 0, s, m, n, L.pinv, L.qinv, !sym, L.hdr, L.pmark);
+        hipLaunchKernelGGL(k_perm_check, dim3((unsigned)std::max<int64_t>(1, (hi + 1023) / 1024)), dim3(256), 0, s, m,
+                           n, L.pinv, L.qinv, !sym, L.hdr, L.pmark);
         stage_mark(h, "perm.check");
         e = hipGetLastError();
     }

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_fused_mark(const int32_t *__restrict__ 
 
 __global__ __launch_bounds__(256) void k_fused_check(int64_t m, int64_t n, const int32_t *__restrict__ pinv,
                                                     const int32_t *__restrict__ qinv, bool general, DevHdr *hdr) {
-    perm::perm_check_tile(blockIdx.x, m, n, pinv, qinv, general, hdr);
+    perm::perm_check4_tile(blockIdx.x, m, n, pinv, qinv, general, hdr);
 }
 
 // Output row i holds row p[i] of the assignment result: scatter the
@@ -1318,7 +1318,7 @@ hp_status_t asg_plan_t(hp_handle_t h, const hp_csr_t *A, const hp_csr_t *B, cons
                            L.cnt_out, L.fflag, L.fsum, L.hdr);
         hipLaunchKernelGGL(k_fused_sum, dim3(1), dim3(64), 0, s, (const unsigned long long *)L.fsum, L.hdr);
         if (!sym) hipLaunchKernelGGL(k_fused_qinv, dim3(gridn(n)), dim3(256), 0, s, q, n, L.qinv, L.hdr);
-        hipLaunchKernelGGL(k_fused_check, dim3(gridn(hi)), dim3(256), 0, s, m, n, L.pinv, L.qinv, !sym, L.hdr);
+        hipLaunchKernelGGL(k_fused_check, dim3(gridn(hi, 1024)), dim3(256), 0, s, m, n, L.pinv, L.qinv, !sym, L.hdr);
         // flagged output rows only: classification mode 4
         e = launch_scan_counts<PT>(s, L.cnt_out, (PT *)C->rowptr, m, L.hdr, 0, L.tiles, 4, L.lists, m, L.fflag);
         stage_mark(h, "asgn.scan");
